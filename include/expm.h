@@ -1,0 +1,175 @@
+/*
+ * expm.h - C ABI of the MI355X (gfx950) filtered precise-integration sparse
+ * matrix exponential.
+ *
+ * Method: Wu, Zhang, Zhu, Hu, "High-performance computation of large sparse
+ * matrix exponential" (arXiv 2110.04493), Algorithm 4.2.  Given a real sparse
+ * H and a tolerance eps_tol, the library chooses the Taylor degree M and the
+ * squaring count N from problem (4.20), builds the filtered Taylor seed
+ * T_0 of e^{H 2^-N} - I (Eq. 4.10-4.14), runs the N filtered updates
+ * T <- 2T + T*T of Eq. (2.7)/(4.15), each followed by the forward-error
+ * filter of Algorithm 4.1, and returns E = I + T_N.  Every step runs in HIP
+ * kernels on the GPU in IEEE double precision.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are square CSR: rowptr int64[n+1], col int32[nnz] (sorted and
+ *    unique within each row, 0 <= col < n), val double[nnz].  n < 2^31.
+ *  - All matrix and gradient pointers are DEVICE pointers on the current HIP
+ *    device.  Input views are borrowed: the library never writes or frees
+ *    them and does not keep them after the call returns.
+ *  - Every call is ordered on opts.stream (NULL = the null stream).  Calls
+ *    block the host only where they must read a size or a scalar back from
+ *    the device (allocation sizes, the norm of H, filter termination).
+ *  - Return value: EXPM_OK (0) or a negative EXPM_E* code.  On error no
+ *    output is allocated, the outputs are left zeroed, and expm_last_error()
+ *    returns a message for the calling thread.
+ *  - A plan is not thread-safe; separate plans may be used concurrently.
+ */
+#ifndef EXPM_H
+#define EXPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXPM_OK 0
+#define EXPM_EINVAL (-1)   /* malformed CSR, NaN/Inf values, eps out of range     */
+#define EXPM_ENOMEM (-2)   /* device allocation failed                            */
+#define EXPM_EHIP (-3)     /* a HIP runtime call failed                           */
+#define EXPM_ERANGE (-4)   /* no (M, N) with M <= 170 satisfies problem (4.20)    */
+#define EXPM_ENOTCONV (-5) /* Algorithm 4.1 hit opts.max_filter_iter             */
+#define EXPM_ENOTIMPL (-6) /* option combination not provided                    */
+#define EXPM_ESTATE (-7)   /* call out of order (e.g. backward without forward)   */
+
+#define EXPM_NORMAL_AUTO (-1)
+#define EXPM_FILTER_PAPER 0 /* Algorithm 4.1 with the budgets of Algorithm 4.2    */
+#define EXPM_FILTER_NONE 1  /* a = 0: plain precise integration, only exact zeros
+                               are dropped (section 4.2: a_i = 0 is the original
+                               method)                                            */
+
+#define EXPM_MAXSTEP 128
+
+/* Borrowed read-only CSR view (device pointers). */
+typedef struct {
+    int64_t n, nnz;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} expm_csr_cview;
+
+/* Output CSR (device pointers).  Owned by the caller's allocator when one is
+ * given in expm_opts, else by the library; release with expm_csr_release()
+ * or expm_free(). */
+typedef struct {
+    int64_t n, nnz;
+    int64_t *rowptr;
+    int32_t *col;
+    double *val;
+} expm_csr;
+
+/* Optional device allocator for outputs.  alloc returns a device pointer of
+ * at least `bytes` bytes usable on `stream` (NULL on failure); free releases
+ * one.  Workspace is always allocated by the library itself. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} expm_allocator;
+
+typedef struct {
+    int normal;              /* Algorithm 4.2 step 2: -1 detect (exact symmetric
+                                or skew-symmetric, else ||HH^T - H^TH||_F <=
+                                16 u ||H||_F^2), 0 non-normal, 1 normal        */
+    int filter_mode;         /* EXPM_FILTER_PAPER (default) | EXPM_FILTER_NONE */
+    double e_r;              /* Algorithm 4.1 tolerance e_r (default 0.1)      */
+    int max_filter_iter;     /* Algorithm 4.1 iteration cap (default 64)       */
+    int keep_checkpoints;    /* 1: keep what expm_sparse_backward needs         */
+    int checkpoint_interval; /* squaring iterates kept every c steps; 0 picks
+                                c = ceil(sqrt(N)), 1 keeps all of them         */
+    void *stream;            /* hipStream_t for every launch and copy          */
+    const expm_allocator *allocator; /* outputs; NULL = library allocation     */
+} expm_opts;
+
+/* Per-call statistics (indices as in the paper: Taylor term i = 2..M',
+ * squaring step i = 1..N). */
+typedef struct {
+    int status, M, N, taylor_terms, normal, squarings;
+    double a, norm_h, h0, r0, eg0;
+    double taylor_theta[EXPM_MAXSTEP];
+    int taylor_iters[EXPM_MAXSTEP];
+    int64_t taylor_cand[EXPM_MAXSTEP], taylor_kept[EXPM_MAXSTEP];
+    double sq_theta[EXPM_MAXSTEP], sq_normF[EXPM_MAXSTEP], sq_budget[EXPM_MAXSTEP];
+    double sq_dropped[EXPM_MAXSTEP];
+    int sq_iters[EXPM_MAXSTEP];
+    int64_t sq_cand[EXPM_MAXSTEP], sq_kept[EXPM_MAXSTEP];
+    int64_t nnz_e;
+    size_t peak_workspace_bytes;
+} expm_stats;
+
+typedef struct expm_plan_s *expm_plan_t;
+
+/* Fills opts with the defaults listed above. */
+void expm_opts_default(expm_opts *opts);
+
+/* Creates a plan: the stream, options and the device workspace pool that
+ * every later call on it reuses.  opts may be NULL (defaults).  Errors:
+ * EXPM_EINVAL (bad option values), EXPM_EHIP. */
+int expm_plan(expm_plan_t *out, const expm_opts *opts);
+
+/* Algorithm 4.2: E ~= e^H.  H is a borrowed device CSR view; eps = eps_tol,
+ * the relative error tolerance of problem (4.20), with 2^-60 <= eps < 1
+ * (tolerances down to the unit roundoff of section 4.4 and slightly below,
+ * as in section 5.2, are accepted).  *E receives a newly allocated device
+ * CSR with sorted columns and no explicit zeros.  When the plan keeps
+ * checkpoints, the state needed by expm_sparse_backward replaces that of the
+ * previous call.  Errors: EXPM_EINVAL, EXPM_ERANGE, EXPM_ENOTCONV,
+ * EXPM_ENOMEM, EXPM_EHIP. */
+int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E);
+
+/* Adjoint of the last expm_sparse call on p (which must have run with
+ * keep_checkpoints = 1): given dL/dE aligned with the stored entries of that
+ * E (device double[nnz(E)]), writes dL/dH aligned with the stored entries of
+ * its H (device double[nnz(H)], caller-allocated).  It is the exact
+ * derivative of the map Algorithm 4.2 evaluates with every filter mask and
+ * threshold held fixed: for the squarings of Eq. (4.15),
+ * G_{k-1} = P_{k-1}(2 G_k + G_k T_{k-1}^T + T_{k-1}^T G_k), then the Taylor
+ * recursion of Eq. (4.11) and the 2^-N scaling.  Squaring iterates between
+ * checkpoints are recomputed.  Errors: EXPM_ESTATE, EXPM_ENOMEM, EXPM_EHIP. */
+int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals);
+
+/* Algorithm 4.2 for `count` independent matrices H[k] with tolerances
+ * eps[k] (host array), in one pass: every kernel launch of a step serves
+ * the rows of all instances still active at that step.  E[k] as for
+ * expm_sparse.  Errors as expm_sparse; on error no E[k] is allocated. */
+int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cview *H, const double *eps,
+                        expm_csr *E);
+
+/* Statistics of the last expm_sparse call (for batched calls, of the last
+ * instance).  Errors: EXPM_ESTATE if no call has run. */
+int expm_get_stats(expm_plan_t p, expm_stats *out);
+
+/* Frees one output returned by this plan and zeroes *E. */
+void expm_csr_release(expm_plan_t p, expm_csr *E);
+
+/* Frees the plan, its workspace, checkpoints and unreleased outputs. */
+void expm_free(expm_plan_t p);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *expm_last_error(void);
+
+/* Host helpers.  Eq. (4.5): r0(M, x) = (1/M!) sum_k x^{M+1+k}/(k!(M+1+k)),
+ * the bound on ||F_0^{-1} R_0|| for degree M at ||H 2^-N|| = x. */
+double expm_r0(int M, double x);
+
+/* Problem (4.20): the (M, N) minimising M 2^N with ||H 2^-N|| <= 1 and
+ * 2^N r0(M, ||H|| 2^-N) <= eps; N in [N0, N0 + 50], ties to smaller N.
+ * Errors: EXPM_EINVAL, EXPM_ERANGE. */
+int expm_choose_mn(double norm_h, double eps, int *M, int *N);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXPM_H */

@@ -1,0 +1,198 @@
+"""PyTorch-facing API: device tensors in, device tensors out.
+
+Torch provides device memory (outputs are allocated through torch's caching
+allocator via the library's allocator callback) and the stream (the current
+torch stream); the computation itself runs in the gfx950 library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import capi
+
+
+class _TorchAllocator:
+    """Allocator callback handing torch uint8 buffers to the library."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live: dict[int, torch.Tensor] = {}
+        self._alloc = capi.ALLOC_FN(self._do_alloc)
+        self._free = capi.FREE_FN(self._do_free)
+        self.struct = capi.expm_allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, stream, ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _do_free(self, ptr, stream, ctx):
+        self.live.pop(ptr, None)
+
+    def take(self, ptr: int, count: int, dtype: torch.dtype) -> torch.Tensor:
+        """Moves ownership of one output buffer to the caller as a typed view."""
+        if count == 0:
+            self.live.pop(ptr, None)
+            return torch.empty(0, dtype=dtype, device=self.device)
+        t = self.live.pop(ptr)
+        nbytes = count * torch.empty(0, dtype=dtype).element_size()
+        return t[:nbytes].view(dtype)
+
+
+def _view(crow: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> capi.expm_csr_cview:
+    n = crow.numel() - 1
+    return capi.expm_csr_cview(n, val.numel(), crow.data_ptr(), col.data_ptr(), val.data_ptr())
+
+
+def _check_inputs(crow, col, val):
+    dev = val.device
+    if dev.type != "cuda":
+        raise ValueError("the gfx950 library takes device tensors (no CPU path)")
+    if crow.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float64:
+        raise TypeError("expects int64 row pointers, int32 columns and float64 values")
+    for t in (crow, col, val):
+        if not t.is_contiguous() or t.device != dev:
+            raise ValueError("inputs must be contiguous tensors on one device")
+
+
+@dataclass
+class Options:
+    normal: int = capi.EXPM_NORMAL_AUTO
+    filter_mode: int = capi.EXPM_FILTER_PAPER
+    e_r: float = 0.1
+    max_filter_iter: int = 64
+    keep_checkpoints: bool = False
+    checkpoint_interval: int = 0
+
+
+class Plan:
+    """Owns one ``expm_plan_t`` (workspace pool, stream binding)."""
+
+    def __init__(self, device=None, options: Options | None = None, stream=None):
+        self.device = torch.device(device if device is not None else "cuda", )
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.options = options or Options()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.alloc = _TorchAllocator(self.device)
+        o = capi.expm_opts_default()
+        o.normal = self.options.normal
+        o.filter_mode = self.options.filter_mode
+        o.e_r = self.options.e_r
+        o.max_filter_iter = self.options.max_filter_iter
+        o.keep_checkpoints = int(self.options.keep_checkpoints)
+        o.checkpoint_interval = self.options.checkpoint_interval
+        o.stream = self.stream.cuda_stream
+        o.allocator = C.pointer(self.alloc.struct)
+        self._opts = o
+        with torch.cuda.device(self.device):
+            self.handle = capi.expm_plan(o)
+
+    def _take(self, E: capi.expm_csr):
+        n = E.n
+        rp = self.alloc.take(E.rowptr, n + 1, torch.int64)
+        ci = self.alloc.take(E.col, E.nnz, torch.int32) if E.col else \
+            torch.empty(0, dtype=torch.int32, device=self.device)
+        v = self.alloc.take(E.val, E.nnz, torch.float64) if E.val else \
+            torch.empty(0, dtype=torch.float64, device=self.device)
+        capi.expm_csr_release(self.handle, E)
+        return rp, ci, v
+
+    def expm(self, crow, col, val, eps: float):
+        """E = e^H as (rowptr int64, col int32, val float64) device tensors."""
+        _check_inputs(crow, col, val)
+        with torch.cuda.device(self.device):
+            E = capi.expm_sparse(self.handle, _view(crow, col, val), eps)
+            return self._take(E)
+
+    def backward(self, dE: torch.Tensor, nnz_h: int) -> torch.Tensor:
+        dE = dE.contiguous().to(torch.float64)
+        dH = torch.empty(nnz_h, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            capi.expm_sparse_backward(self.handle, dE.data_ptr(), dH.data_ptr())
+        return dH
+
+    def expm_batched(self, mats, eps):
+        views = []
+        for crow, col, val in mats:
+            _check_inputs(crow, col, val)
+            views.append(_view(crow, col, val))
+        with torch.cuda.device(self.device):
+            outs = capi.expm_sparse_batched(self.handle, views, list(eps))
+            return [self._take(E) for E in outs]
+
+    def stats(self) -> dict:
+        return capi.expm_get_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.current_stream(self.device).synchronize()
+            capi.expm_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def csr_parts(H: torch.Tensor):
+    """(crow int64, col int32, val float64) of a torch sparse CSR tensor."""
+    return (H.crow_indices().to(torch.int64).contiguous(),
+            H.col_indices().to(torch.int32).contiguous(),
+            H.values().to(torch.float64).contiguous())
+
+
+def expm(H: torch.Tensor, eps: float, **options) -> torch.Tensor:
+    """e^H for a float64 sparse CSR tensor on the GPU (Algorithm 4.2)."""
+    crow, col, val = csr_parts(H)
+    plan = Plan(val.device, Options(**options))
+    try:
+        rp, ci, v = plan.expm(crow, col, val, eps)
+    finally:
+        plan.close()
+    n = rp.numel() - 1
+    return torch.sparse_csr_tensor(rp, ci.to(torch.int64), v, size=(n, n))
+
+
+class ExpmFn(torch.autograd.Function):
+    """Values of E = e^H as a differentiable function of the values of H.
+
+    forward(crow, col, vals, eps) returns (E_vals, E_crow, E_col); only
+    E_vals carries a gradient.  backward returns dL/d(vals of H), the exact
+    derivative of the computed map with the filter masks held fixed."""
+
+    @staticmethod
+    def forward(ctx, crow, col, vals, eps, checkpoint_interval=0):
+        plan = Plan(vals.device, Options(keep_checkpoints=True,
+                                         checkpoint_interval=checkpoint_interval))
+        rp, ci, v = plan.expm(crow, col, vals.detach(), eps)
+        ctx.plan = plan
+        ctx.nnz_h = vals.numel()
+        ctx.mark_non_differentiable(rp, ci)
+        return v, rp, ci
+
+    @staticmethod
+    def backward(ctx, gE, _grp, _gci):
+        dH = ctx.plan.backward(gE, ctx.nnz_h)
+        ctx.plan.close()
+        return None, None, dH, None, None
+
+
+def expm_batched(mats, eps, **options):
+    """Exponentials of several CSR matrices (list of (crow, col, vals)) in one
+    batched call; returns a list of (rowptr, col, val)."""
+    if not mats:
+        return []
+    plan = Plan(mats[0][2].device, Options(**options))
+    try:
+        return plan.expm_batched(mats, eps)
+    finally:
+        plan.close()

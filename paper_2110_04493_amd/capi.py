@@ -1,0 +1,197 @@
+"""ctypes binding of ``include/expm.h`` (argument marshalling only).
+
+The names match the C ABI one to one.  Pointers are plain integers (device
+addresses); nothing here computes anything: every step of the method runs in
+the gfx950 library ``libexpm_gfx950.so``.  Loading fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libexpm_gfx950.so")
+
+EXPM_OK = 0
+EXPM_EINVAL = -1
+EXPM_ENOMEM = -2
+EXPM_EHIP = -3
+EXPM_ERANGE = -4
+EXPM_ENOTCONV = -5
+EXPM_ENOTIMPL = -6
+EXPM_ESTATE = -7
+EXPM_NORMAL_AUTO = -1
+EXPM_FILTER_PAPER = 0
+EXPM_FILTER_NONE = 1
+EXPM_MAXSTEP = 128
+
+ERROR_NAMES = {0: "EXPM_OK", -1: "EXPM_EINVAL", -2: "EXPM_ENOMEM", -3: "EXPM_EHIP",
+               -4: "EXPM_ERANGE", -5: "EXPM_ENOTCONV", -6: "EXPM_ENOTIMPL", -7: "EXPM_ESTATE"}
+
+# Every function the header declares.
+SYMBOLS = ["expm_opts_default", "expm_plan", "expm_sparse", "expm_sparse_backward",
+           "expm_sparse_batched", "expm_get_stats", "expm_csr_release", "expm_free",
+           "expm_last_error", "expm_r0", "expm_choose_mn"]
+
+
+class expm_csr_cview(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class expm_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class expm_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class expm_opts(C.Structure):
+    _fields_ = [("normal", C.c_int), ("filter_mode", C.c_int), ("e_r", C.c_double),
+                ("max_filter_iter", C.c_int), ("keep_checkpoints", C.c_int),
+                ("checkpoint_interval", C.c_int), ("stream", C.c_void_p),
+                ("allocator", C.POINTER(expm_allocator))]
+
+
+_S = EXPM_MAXSTEP
+
+
+class expm_stats(C.Structure):
+    _fields_ = [("status", C.c_int), ("M", C.c_int), ("N", C.c_int), ("taylor_terms", C.c_int),
+                ("normal", C.c_int), ("squarings", C.c_int),
+                ("a", C.c_double), ("norm_h", C.c_double), ("h0", C.c_double),
+                ("r0", C.c_double), ("eg0", C.c_double),
+                ("taylor_theta", C.c_double * _S), ("taylor_iters", C.c_int * _S),
+                ("taylor_cand", C.c_int64 * _S), ("taylor_kept", C.c_int64 * _S),
+                ("sq_theta", C.c_double * _S), ("sq_normF", C.c_double * _S),
+                ("sq_budget", C.c_double * _S), ("sq_dropped", C.c_double * _S),
+                ("sq_iters", C.c_int * _S),
+                ("sq_cand", C.c_int64 * _S), ("sq_kept", C.c_int64 * _S),
+                ("nnz_e", C.c_int64), ("peak_workspace_bytes", C.c_size_t)]
+
+    def to_dict(self) -> dict:
+        d = {k: getattr(self, k) for k in ("status", "M", "N", "taylor_terms", "normal",
+                                           "squarings", "a", "norm_h", "h0", "r0", "eg0",
+                                           "nnz_e", "peak_workspace_bytes")}
+        T, N = self.taylor_terms, self.squarings
+        for k in ("taylor_theta", "taylor_iters", "taylor_cand", "taylor_kept"):
+            d[k] = list(getattr(self, k)[2:T + 2])
+        for k in ("sq_theta", "sq_normF", "sq_budget", "sq_dropped", "sq_iters", "sq_cand",
+                  "sq_kept"):
+            d[k] = list(getattr(self, k)[1:N + 1])
+        return d
+
+
+class ExpmError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """The loaded gfx950 library (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2110_04493_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        L.expm_opts_default.argtypes = [C.POINTER(expm_opts)]
+        L.expm_opts_default.restype = None
+        L.expm_plan.argtypes = [C.POINTER(_P), C.POINTER(expm_opts)]
+        L.expm_sparse.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_double, C.POINTER(expm_csr)]
+        L.expm_sparse_backward.argtypes = [_P, _P, _P]
+        L.expm_sparse_batched.argtypes = [_P, C.c_int, C.POINTER(expm_csr_cview),
+                                          C.POINTER(C.c_double), C.POINTER(expm_csr)]
+        L.expm_get_stats.argtypes = [_P, C.POINTER(expm_stats)]
+        L.expm_csr_release.argtypes = [_P, C.POINTER(expm_csr)]
+        L.expm_csr_release.restype = None
+        L.expm_free.argtypes = [_P]
+        L.expm_free.restype = None
+        L.expm_last_error.restype = C.c_char_p
+        L.expm_r0.argtypes = [C.c_int, C.c_double]
+        L.expm_r0.restype = C.c_double
+        L.expm_choose_mn.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int)]
+        for name in SYMBOLS:
+            if name not in ("expm_opts_default", "expm_csr_release", "expm_free",
+                            "expm_last_error", "expm_r0"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str) -> None:
+    if code != EXPM_OK:
+        raise ExpmError(code, where, expm_last_error())
+
+
+def expm_opts_default() -> expm_opts:
+    o = expm_opts()
+    lib().expm_opts_default(C.byref(o))
+    return o
+
+
+def expm_plan(opts: expm_opts) -> int:
+    h = _P()
+    check(lib().expm_plan(C.byref(h), C.byref(opts)), "expm_plan")
+    return h.value
+
+
+def expm_sparse(plan: int, H: expm_csr_cview, eps: float) -> expm_csr:
+    E = expm_csr()
+    check(lib().expm_sparse(_P(plan), C.byref(H), float(eps), C.byref(E)), "expm_sparse")
+    return E
+
+
+def expm_sparse_backward(plan: int, dE_ptr: int, dH_ptr: int) -> None:
+    check(lib().expm_sparse_backward(_P(plan), _P(dE_ptr), _P(dH_ptr)), "expm_sparse_backward")
+
+
+def expm_sparse_batched(plan: int, H: list, eps: list) -> list:
+    k = len(H)
+    Harr = (expm_csr_cview * max(k, 1))(*H)
+    earr = (C.c_double * max(k, 1))(*[float(e) for e in eps])
+    Earr = (expm_csr * max(k, 1))()
+    check(lib().expm_sparse_batched(_P(plan), k, Harr, earr, Earr), "expm_sparse_batched")
+    return [Earr[j] for j in range(k)]
+
+
+def expm_get_stats(plan: int) -> dict:
+    s = expm_stats()
+    check(lib().expm_get_stats(_P(plan), C.byref(s)), "expm_get_stats")
+    return s.to_dict()
+
+
+def expm_csr_release(plan: int, E: expm_csr) -> None:
+    lib().expm_csr_release(_P(plan), C.byref(E))
+
+
+def expm_free(plan: int) -> None:
+    lib().expm_free(_P(plan))
+
+
+def expm_last_error() -> str:
+    return lib().expm_last_error().decode()
+
+
+def expm_r0(M: int, x: float) -> float:
+    return lib().expm_r0(int(M), float(x))
+
+
+def expm_choose_mn(norm_h: float, eps: float) -> tuple[int, int]:
+    M, N = C.c_int(), C.c_int()
+    check(lib().expm_choose_mn(float(norm_h), float(eps), C.byref(M), C.byref(N)),
+          "expm_choose_mn")
+    return M.value, N.value

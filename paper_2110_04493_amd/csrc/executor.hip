@@ -1,0 +1,987 @@
+// Host executor and C ABI of the gfx950 filtered precise-integration
+// sparse exponential (Algorithm 4.2 of Wu, Zhang, Zhu, Hu, arXiv 2110.04493).
+//
+// The host drives a fixed sequence of kernel launches on the plan's stream
+// and reads back only sizes (to allocate) and the filter controller (to know
+// when Algorithm 4.1 has stopped).  All matrix data stays on the device.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/expm.h"
+#include "kernels.hpp"
+
+using namespace xpm;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Status {
+    int code = EXPM_OK;
+};
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) {                                                            \
+            if (_e == hipErrorOutOfMemory)                                                 \
+                return fail(EXPM_ENOMEM, "%s: out of device memory (%s:%d)", #expr,        \
+                            __FILE__, __LINE__);                                           \
+            return fail(EXPM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),  \
+                        __FILE__, __LINE__);                                               \
+        }                                                                                  \
+    } while (0)
+
+#define CHK(expr)                \
+    do {                         \
+        int _s = (expr);         \
+        if (_s != EXPM_OK) return _s; \
+    } while (0)
+
+// ------------------------------------------------------------------ memory
+
+// Grow-only device buffer from the stream-ordered pool.
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct DCsr {
+    int64_t n = 0, nnz = 0;
+    Buf rp, ci, v;
+    CsrView view() const {
+        return CsrView{n, (const int64_t *)rp.p, (const int32_t *)ci.p, (const double *)v.p};
+    }
+};
+
+}  // namespace
+
+struct expm_plan_s {
+    expm_opts opts{};
+    hipStream_t st = nullptr;
+    size_t live = 0, peak = 0;
+
+    // workspace
+    Buf lo, words, woff, ub, cnt, crp, bitmaps, lists, counts, scan_tmp, part, ctl, rowsq, norm2,
+        scratch, soff, sbytes, flags, krp, tmp1, tmp2;
+    Buf cci, cv;            // candidate entries
+    int *host = nullptr;    // pinned readback area
+    // current matrices
+    DCsr H0, S, Snew, T, Tnew, Hpat_t;
+    // adjoint state
+    bool have_fwd = false;
+    int M = 0, N = 0, Mp = 0, ck = 1;
+    double a = 0;
+    std::vector<DCsr> taylor;        // S^_1 .. S^_M'
+    std::vector<DCsr> ckpt;          // T^_k for k = 0, ck, 2ck, ... (index k / ck)
+    DCsr TN;                         // T^_N
+    DCsr Epat;                       // pattern of the returned E
+    std::vector<double> theta;       // squaring thresholds, 1..N
+    bool zero_h = false;
+    // stats / outputs
+    expm_stats stats{};
+    bool have_stats = false;
+    std::vector<void *> outputs;
+};
+
+namespace {
+
+int ensure(expm_plan_s &P, Buf &b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return EXPM_OK;
+    if (b.p) {
+        HIPCHK(hipFreeAsync(b.p, P.st));
+        P.live -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    want = (want + 255) & ~(size_t)255;
+    hipError_t e = hipMallocAsync(&b.p, want, P.st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        e = hipMallocAsync(&b.p, bytes, P.st);
+        want = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(EXPM_ENOMEM, "cannot allocate %zu bytes of device workspace", bytes);
+    }
+    b.bytes = want;
+    P.live += want;
+    P.peak = std::max(P.peak, P.live);
+    return EXPM_OK;
+}
+
+void release(expm_plan_s &P, Buf &b) {
+    if (b.p) {
+        (void)hipFreeAsync(b.p, P.st);
+        P.live -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+void release(expm_plan_s &P, DCsr &A) {
+    release(P, A.rp);
+    release(P, A.ci);
+    release(P, A.v);
+    A.n = A.nnz = 0;
+}
+
+int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz) {
+    CHK(ensure(P, A.rp, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, A.ci, sizeof(int32_t) * nnz));
+    CHK(ensure(P, A.v, sizeof(double) * nnz));
+    A.n = n;
+    A.nnz = nnz;
+    return EXPM_OK;
+}
+
+// Exact-size copy of a device CSR (checkpoints, Taylor terms).
+int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src) {
+    release(P, dst);
+    CHK(ensure_csr(P, dst, src.n, src.nnz));
+    HIPCHK(hipMemcpyAsync(dst.rp.p, src.rp.p, sizeof(int64_t) * (src.n + 1),
+                          hipMemcpyDeviceToDevice, P.st));
+    if (src.nnz) {
+        HIPCHK(hipMemcpyAsync(dst.ci.p, src.ci.p, sizeof(int32_t) * src.nnz,
+                              hipMemcpyDeviceToDevice, P.st));
+        HIPCHK(hipMemcpyAsync(dst.v.p, src.v.p, sizeof(double) * src.nnz, hipMemcpyDeviceToDevice,
+                              P.st));
+    }
+    return EXPM_OK;
+}
+
+int sync(expm_plan_s &P) {
+    HIPCHK(hipStreamSynchronize(P.st));
+    return EXPM_OK;
+}
+
+int scan(expm_plan_s &P, const int64_t *in, int64_t *out, int64_t n) {
+    size_t tb = scan_tmp_bytes(n);
+    CHK(ensure(P, P.scan_tmp, tb));
+    HIPCHK(scan_i64(in, out, n, P.scan_tmp.p, P.scan_tmp.bytes, P.st));
+    return EXPM_OK;
+}
+
+void *out_alloc(expm_plan_s &P, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    void *p = nullptr;
+    if (P.opts.allocator && P.opts.allocator->alloc) {
+        p = P.opts.allocator->alloc(bytes, P.st, P.opts.allocator->ctx);
+    } else if (hipMallocAsync(&p, bytes, P.st) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p) P.outputs.push_back(p);
+    return p;
+}
+
+void out_free(expm_plan_s &P, void *p) {
+    if (!p) return;
+    auto it = std::find(P.outputs.begin(), P.outputs.end(), p);
+    if (it == P.outputs.end()) return;
+    P.outputs.erase(it);
+    if (P.opts.allocator && P.opts.allocator->free)
+        P.opts.allocator->free(p, P.st, P.opts.allocator->ctx);
+    else
+        (void)hipFreeAsync(p, P.st);
+}
+
+// ------------------------------------------------------------------ planner
+// Eq. (4.5): r0(M, x) = sum_{k>=0} x^{M+1+k} / (M! k! (M+1+k)), all terms
+// positive; stop once a term no longer changes the sum at 2^-60.
+double plan_r0(int M, double x) {
+    if (!(x > 0.0)) return 0.0;
+    double lead = x;                      // x^{M+1} / M!
+    for (int j = 1; j <= M; ++j) lead *= x / (double)j;
+    double total = 0.0, pk = lead;
+    for (int k = 0;; ++k) {
+        if (k) pk *= x / (double)k;
+        const double t = pk / (double)(M + 1 + k);
+        total += t;
+        if (t < ldexp(total, -60) || k > 100000) break;
+    }
+    return total;
+}
+
+// Problem (4.20) by enumeration: N in [N0, N0 + 50], the least M >= 1 meeting
+// the tolerance for each N, minimal M 2^N, first (smallest N) on ties.
+int plan_mn(double nh, double eps, int *Mo, int *No) {
+    if (!(nh >= 0.0) || !isfinite(nh) || !(eps > 0.0)) return EXPM_EINVAL;
+    int n0 = 0;
+    if (nh > 1.0) n0 = (int)ceil(log2(nh));
+    while (ldexp(nh, -n0) > 1.0) ++n0;
+    int bestM = 0, bestN = 0;
+    double bestCost = 0.0;
+    for (int N = n0; N <= n0 + 50; ++N) {
+        const double x = ldexp(nh, -N);
+        int M = 1;
+        while (M <= 170 && ldexp(plan_r0(M, x), N) > eps) ++M;
+        if (M > 170) continue;
+        const double cost = ldexp((double)M, N);
+        if (bestM == 0 || cost < bestCost) {
+            bestM = M;
+            bestN = N;
+            bestCost = cost;
+        }
+    }
+    if (bestM == 0) return EXPM_ERANGE;
+    *Mo = bestM;
+    *No = bestN;
+    return EXPM_OK;
+}
+
+// ------------------------------------------------------------------ SpGEMM driver
+// C = alphaA * A + A * B (divided by div), into the candidate buffers
+// (P.crp, P.cci, P.cv).  Returns the candidate total in *total; with rowsq
+// the per-row sums of (c + delta)^2 are left in P.rowsq.
+int spgemm(expm_plan_s &P, CsrView A, CsrView B, double alphaA, double div, bool rowsq,
+           int64_t *total) {
+    const int64_t n = A.n;
+    hipStream_t st = P.st;
+    CHK(ensure(P, P.lo, sizeof(int32_t) * n));
+    CHK(ensure(P, P.words, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.woff, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.ub, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.crp, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.sbytes, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.soff, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.lists, sizeof(int32_t) * (size_t)kNumClasses * (n > 0 ? n : 1)));
+    CHK(ensure(P, P.counts, sizeof(int) * 16));
+    int64_t *words = (int64_t *)P.words.p, *woff = (int64_t *)P.woff.p;
+    HIPCHK(row_bounds(A, B, alphaA != 0.0, (int32_t *)P.lo.p, words, (int64_t *)P.ub.p, st));
+    CHK(scan(P, words, woff, n));
+    HIPCHK(bin_rows(woff, nullptr, n, 0, (int *)P.counts.p, (int32_t *)P.lists.p, st));
+    int64_t *hl = (int64_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hl, woff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hl + 1, P.counts.p, sizeof(int) * kSymClasses, hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    const int64_t twords = hl[0];
+    int symc[kSymClasses];
+    memcpy(symc, hl + 1, sizeof symc);
+    CHK(ensure(P, P.bitmaps, sizeof(uint32_t) * twords));
+    int64_t *cnt = (int64_t *)P.cnt.p, *crp = (int64_t *)P.crp.p;
+    HIPCHK(symbolic(A, B, alphaA != 0.0, (const int32_t *)P.lo.p, woff, (uint32_t *)P.bitmaps.p,
+                    cnt, symc, (const int32_t *)P.lists.p, n, st));
+    CHK(scan(P, cnt, crp, n));
+    HIPCHK(numeric_scratch_sizes(woff, crp, n, (int64_t *)P.sbytes.p, st));
+    CHK(scan(P, (const int64_t *)P.sbytes.p, (int64_t *)P.soff.p, n));
+    HIPCHK(bin_rows(woff, crp, n, 1, (int *)P.counts.p, (int32_t *)P.lists.p, st));
+    HIPCHK(hipMemcpyAsync(hl, crp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.soff.p + n, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hl + 2, P.counts.p, sizeof(int) * kNumClasses, hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    const int64_t cand = hl[0], gscratch = hl[1];
+    int numc[kNumClasses];
+    memcpy(numc, hl + 2, sizeof numc);
+    CHK(ensure(P, P.cci, sizeof(int32_t) * cand));
+    CHK(ensure(P, P.cv, sizeof(double) * cand));
+    if (gscratch) CHK(ensure(P, P.scratch, (size_t)gscratch));
+    if (rowsq) CHK(ensure(P, P.rowsq, sizeof(double) * (n + 1)));
+    HIPCHK(numeric(A, B, alphaA, div, (const int32_t *)P.lo.p, woff,
+                   (const uint32_t *)P.bitmaps.p, crp, (int32_t *)P.cci.p, (double *)P.cv.p,
+                   rowsq ? (double *)P.rowsq.p : nullptr, numc, (const int32_t *)P.lists.p, n,
+                   P.scratch.p, (const int64_t *)P.soff.p, st));
+    *total = cand;
+    return EXPM_OK;
+}
+
+constexpr int kParts = 1024;
+
+// Algorithm 4.1 on the candidate values plus the row counts of the kept
+// entries: leaves the threshold in P.ctl, kept counts scanned into P.krp.
+// norm2 (device) scales eg for the relative squaring budget; theta_fixed >= 0
+// (or -1 to keep everything) skips the search.
+int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
+                     const double *norm2, bool use_fixed, double theta_fixed, bool addI,
+                     FilterCtl *hctl, int64_t *kept) {
+    hipStream_t st = P.st;
+    CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
+    FilterCtl *ctl = (FilterCtl *)P.ctl.p;
+    if (use_fixed)
+        HIPCHK(filter_init_theta(ctl, theta_fixed, st));
+    else
+        HIPCHK(filter_init(ctl, eg_scale, norm2, P.opts.e_r, P.opts.max_filter_iter, st));
+    const int64_t *crp = (const int64_t *)P.crp.p;
+    for (int round = 0;; ++round) {
+        if (!use_fixed) {
+            for (int j = 0; j < 4; ++j)
+                HIPCHK(filter_pass((const double *)P.cv.p, crp + n, cand, ctl, (double *)P.part.p,
+                                   kParts, st));
+        }
+        HIPCHK(count_kept(crp, (const int32_t *)P.cci.p, (const double *)P.cv.p, n, ctl,
+                          addI ? 1 : 0, (int64_t *)P.cnt.p, st));
+        CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
+        HIPCHK(hipMemcpyAsync(P.host, ctl, sizeof(FilterCtl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync((char *)P.host + 256, (int64_t *)P.krp.p + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        memcpy(hctl, P.host, sizeof(FilterCtl));
+        memcpy(kept, (char *)P.host + 256, sizeof(int64_t));
+        if (hctl->done) break;
+        if (round > P.opts.max_filter_iter)
+            return fail(EXPM_ENOTCONV, "Algorithm 4.1 did not stop");
+    }
+    if (hctl->status)
+        return fail(EXPM_ENOTCONV, "Algorithm 4.1 reached %d iterations (budget %g)",
+                    hctl->iter, hctl->eg);
+    return EXPM_OK;
+}
+
+// Writes the kept candidate entries (rows from P.krp) into dst (capacity
+// must hold `kept` entries; dst.rp receives P.krp).
+int write_filtered(expm_plan_s &P, int64_t n, DCsr &dst, int64_t kept, bool addI,
+                   bool exact_alloc) {
+    if (exact_alloc) release(P, dst);
+    CHK(ensure_csr(P, dst, n, kept));
+    HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+                          P.st));
+    HIPCHK(write_kept((const int64_t *)P.crp.p, (const int32_t *)P.cci.p, (const double *)P.cv.p,
+                      n, (const FilterCtl *)P.ctl.p, addI ? 1 : 0, (const int64_t *)dst.rp.p,
+                      (int32_t *)dst.ci.p, (double *)dst.v.p, P.st));
+    return EXPM_OK;
+}
+
+// dst = A + B with exact zeros dropped (capacity nnz(A) + nnz(B)).
+int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst) {
+    const int64_t n = A.n;
+    CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
+    CHK(ensure_csr(P, dst, n, A.nnz + B.nnz));
+    HIPCHK(add_count(A.view(), B.view(), (int64_t *)P.cnt.p, P.st));
+    CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)dst.rp.p, n));
+    HIPCHK(add_write(A.view(), B.view(), (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
+                     (double *)dst.v.p, P.st));
+    return EXPM_OK;
+}
+
+// Device transpose of A into dst.
+int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst) {
+    const int64_t n = A.n;
+    CHK(ensure_csr(P, dst, n, A.nnz));
+    CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.tmp2, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.cci, sizeof(int32_t) * A.nnz));
+    CHK(ensure(P, P.cv, sizeof(double) * A.nnz));
+    CHK(ensure(P, P.scan_tmp, scan_tmp_bytes(n)));
+    HIPCHK(transpose(A.view(), A.nnz, (int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
+                     (double *)dst.v.p, (int64_t *)P.tmp1.p, (int64_t *)P.tmp2.p,
+                     (int32_t *)P.cci.p, (double *)P.cv.p, P.scan_tmp.p, P.scan_tmp.bytes,
+                     P.st));
+    return EXPM_OK;
+}
+
+// Masked products on the mask's pattern (see masked_products).  The scratch
+// for rows whose working set exceeds LDS is sized by a first call and the
+// call is repeated once with enough room.
+int masked(expm_plan_s &P, CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2,
+           double div, double *out) {
+    const int64_t n = M.n;
+    CHK(ensure(P, P.scratch, masked_meta_bytes(n)));
+    size_t need = 0;
+    hipError_t e = masked_products(M, D, gamma, t1, t2, div, out, P.scratch.p, P.scratch.bytes,
+                                   &need, P.st);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        CHK(sync(P));
+        CHK(ensure(P, P.scratch, need));
+        e = masked_products(M, D, gamma, t1, t2, div, out, P.scratch.p, P.scratch.bytes, &need,
+                            P.st);
+    }
+    HIPCHK(e);
+    return EXPM_OK;
+}
+
+CsrView empty_view() { return CsrView{0, nullptr, nullptr, nullptr}; }
+
+// ------------------------------------------------------------------ forward
+
+int check_view(const expm_csr_cview *H) {
+    if (!H) return fail(EXPM_EINVAL, "H is NULL");
+    if (H->n < 0 || H->n > INT32_MAX - 1) return fail(EXPM_EINVAL, "n = %lld out of range",
+                                                      (long long)H->n);
+    if (H->nnz < 0) return fail(EXPM_EINVAL, "nnz < 0");
+    if (H->n > 0 && !H->rowptr) return fail(EXPM_EINVAL, "rowptr is NULL");
+    if (H->nnz > 0 && (!H->col || !H->val)) return fail(EXPM_EINVAL, "col/val is NULL");
+    return EXPM_OK;
+}
+
+int output_identity(expm_plan_s &P, int64_t n, expm_csr *E) {
+    int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
+    int32_t *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * n);
+    double *v = (double *)out_alloc(P, sizeof(double) * n);
+    if (!rp || !ci || !v) {
+        out_free(P, rp);
+        out_free(P, ci);
+        out_free(P, v);
+        return fail(EXPM_ENOMEM, "cannot allocate the output");
+    }
+    HIPCHK(fill_identity(n, rp, ci, v, P.st));
+    E->n = n;
+    E->nnz = n;
+    E->rowptr = rp;
+    E->col = ci;
+    E->val = v;
+    return EXPM_OK;
+}
+
+// Is H normal?  Exact symmetric / skew-symmetric, else the commutator test.
+int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal) {
+    const int64_t n = H.n;
+    DCsr Ht;
+    CHK(transpose_csr(P, H, Ht));
+    CHK(ensure(P, P.flags, sizeof(int) * 4));
+    int ones[3] = {1, 1, 1};
+    HIPCHK(hipMemcpyAsync(P.flags.p, ones, sizeof ones, hipMemcpyHostToDevice, P.st));
+    HIPCHK(compare_csr(H.view(), Ht.view(), H.nnz, (int *)P.flags.p, P.st));
+    HIPCHK(hipMemcpyAsync(P.host, P.flags.p, sizeof(int) * 3, hipMemcpyDeviceToHost, P.st));
+    CHK(sync(P));
+    int f[3];
+    memcpy(f, P.host, sizeof f);
+    if (f[0] && (f[1] || f[2])) {
+        *normal = 1;
+        release(P, Ht);
+        return EXPM_OK;
+    }
+    // ||H H^T - H^T H||_F <= 16 u ||H||_F^2
+    int64_t c1, c2;
+    CHK(spgemm(P, H.view(), Ht.view(), 0.0, 1.0, false, &c1));
+    DCsr X, Y;
+    CHK(ensure_csr(P, X, n, c1));
+    HIPCHK(hipMemcpyAsync(X.rp.p, P.crp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, P.st));
+    HIPCHK(hipMemcpyAsync(X.ci.p, P.cci.p, sizeof(int32_t) * c1, hipMemcpyDeviceToDevice, P.st));
+    HIPCHK(hipMemcpyAsync(X.v.p, P.cv.p, sizeof(double) * c1, hipMemcpyDeviceToDevice, P.st));
+    CHK(spgemm(P, Ht.view(), H.view(), 0.0, 1.0, false, &c2));
+    CHK(ensure_csr(P, Y, n, c2));
+    HIPCHK(hipMemcpyAsync(Y.rp.p, P.crp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, P.st));
+    HIPCHK(hipMemcpyAsync(Y.ci.p, P.cci.p, sizeof(int32_t) * c2, hipMemcpyDeviceToDevice, P.st));
+    HIPCHK(scale_ldexp((const double *)P.cv.p, (double *)Y.v.p, c2, 0, P.st));
+    // Z = H H^T - H^T H
+    DCsr Z;
+    HIPCHK(negate_values((double *)Y.v.p, c2, P.st));
+    CHK(sparse_add(P, X, Y, Z));
+    CHK(ensure(P, P.norm2, sizeof(double) * 2));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    HIPCHK(sumsq((const double *)Z.v.p, (const int64_t *)Z.rp.p + n, Z.nnz, (double *)P.part.p,
+                 kParts, (double *)P.norm2.p, P.st));
+    HIPCHK(hipMemcpyAsync(P.host, P.norm2.p, sizeof(double), hipMemcpyDeviceToHost, P.st));
+    CHK(sync(P));
+    double c2n;
+    memcpy(&c2n, P.host, sizeof c2n);
+    *normal = sqrt(c2n) <= 16.0 * ldexp(1.0, -53) * nh * nh;
+    release(P, Ht);
+    release(P, X);
+    release(P, Y);
+    release(P, Z);
+    return EXPM_OK;
+}
+
+void free_adjoint_state(expm_plan_s &P) {
+    for (auto &A : P.taylor) release(P, A);
+    for (auto &A : P.ckpt) release(P, A);
+    P.taylor.clear();
+    P.ckpt.clear();
+    release(P, P.TN);
+    release(P, P.Epat);
+    P.theta.clear();
+    P.have_fwd = false;
+}
+
+// One filtered squaring T <- filter(2T + T*T) into dst; with theta_fixed the
+// stored threshold replaces the search.  Fills the step's statistics when
+// stat_i > 0.  addI: dst = I + filtered (the finish step), exact_alloc: dst
+// gets exactly the kept entries.
+int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
+                double theta_fixed, bool addI, bool exact_alloc, int stat_i) {
+    const int64_t n = T.n;
+    int64_t cand;
+    CHK(spgemm(P, T.view(), T.view(), 2.0, 1.0, !use_fixed, &cand));
+    if (!use_fixed) {
+        CHK(ensure(P, P.norm2, sizeof(double) * 2));
+        CHK(ensure(P, P.part, sizeof(double) * kParts));
+        HIPCHK(sum_values((const double *)P.rowsq.p, n, (double *)P.part.p, kParts,
+                          (double *)P.norm2.p, P.st));
+    }
+    FilterCtl h{};
+    int64_t kept;
+    CHK(filter_and_count(P, n, cand, a_ri, (const double *)P.norm2.p, use_fixed, theta_fixed,
+                         addI, &h, &kept));
+    CHK(write_filtered(P, n, dst, kept, addI, exact_alloc));
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
+        expm_stats &S = P.stats;
+        S.sq_theta[stat_i] = h.theta;
+        S.sq_iters[stat_i] = h.iter;
+        S.sq_cand[stat_i] = cand;
+        S.sq_kept[stat_i] = kept;
+        S.sq_budget[stat_i] = h.eg;
+        S.sq_normF[stat_i] = a_ri > 0 ? h.eg / a_ri : 0.0;
+        S.sq_dropped[stat_i] = h.b;
+    }
+    return EXPM_OK;
+}
+
+int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
+    CHK(check_view(Hv));
+    if (!E) return fail(EXPM_EINVAL, "E is NULL");
+    memset(E, 0, sizeof *E);
+    if (!(eps >= ldexp(1.0, -60) && eps < 1.0))
+        return fail(EXPM_EINVAL, "eps = %g outside [2^-60, 1)", eps);
+    hipStream_t st = P.st;
+    const int64_t n = Hv->n, nnz = Hv->nnz;
+    free_adjoint_state(P);
+    memset(&P.stats, 0, sizeof P.stats);
+    P.have_stats = false;
+    P.peak = P.live;
+    if (n == 0) {
+        E->n = 0;
+        int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t));
+        if (!rp) return fail(EXPM_ENOMEM, "cannot allocate the output");
+        HIPCHK(hipMemsetAsync(rp, 0, sizeof(int64_t), st));
+        E->rowptr = rp;
+        P.have_stats = true;
+        return EXPM_OK;
+    }
+    // own copy of H's pattern; H0 values
+    CHK(ensure_csr(P, P.H0, n, nnz));
+    HIPCHK(hipMemcpyAsync(P.H0.rp.p, Hv->rowptr, sizeof(int64_t) * (n + 1),
+                          hipMemcpyDeviceToDevice, st));
+    if (nnz) {
+        HIPCHK(hipMemcpyAsync(P.H0.ci.p, Hv->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice,
+                              st));
+        HIPCHK(hipMemcpyAsync(P.H0.v.p, Hv->val, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
+                              st));
+    }
+    // validate + ||H||_F
+    CHK(ensure(P, P.flags, sizeof(int) * 4));
+    CHK(ensure(P, P.norm2, sizeof(double) * 2));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    HIPCHK(hipMemsetAsync(P.flags.p, 0, sizeof(int), st));
+    HIPCHK(validate_csr(P.H0.view(), nnz, (int *)P.flags.p, st));
+    HIPCHK(sumsq((const double *)P.H0.v.p, nullptr, nnz, (double *)P.part.p, kParts,
+                 (double *)P.norm2.p, st));
+    HIPCHK(hipMemcpyAsync(P.host, P.flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char *)P.host + 8, P.norm2.p, sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    int flag;
+    double nh2;
+    memcpy(&flag, P.host, sizeof flag);
+    memcpy(&nh2, (char *)P.host + 8, sizeof nh2);
+    if (flag & 1) return fail(EXPM_EINVAL, "rowptr is not a valid CSR row pointer");
+    if (flag & 2) return fail(EXPM_EINVAL, "column indices out of range or not strictly increasing");
+    if (flag & 4) return fail(EXPM_EINVAL, "H holds NaN or Inf");
+    expm_stats &S = P.stats;
+    const double nh = sqrt(nh2);
+    S.norm_h = nh;
+    if (nh == 0.0) {
+        P.zero_h = true;
+        CHK(output_identity(P, n, E));
+        P.Epat.n = 0;
+        P.have_fwd = P.opts.keep_checkpoints != 0;
+        S.nnz_e = n;
+        P.have_stats = true;
+        return EXPM_OK;
+    }
+    P.zero_h = false;
+    // Step 1: (M, N); step 2: a.
+    int M, N;
+    int s = plan_mn(nh, eps, &M, &N);
+    if (s == EXPM_ERANGE) return fail(EXPM_ERANGE, "no (M, N) satisfies problem (4.20)");
+    if (s) return fail(s, "invalid norm %g", nh);
+    if (N >= EXPM_MAXSTEP - 1 || M >= EXPM_MAXSTEP - 1)
+        return fail(EXPM_ERANGE, "(M, N) = (%d, %d) exceeds the step limit", M, N);
+    int normal = P.opts.normal;
+    if (normal < 0) CHK(detect_normal(P, P.H0, nh, &normal));
+    double a = 1.0 / (N + 1);
+    if (!normal && 1.0 / nh < a) a = 1.0 / nh;
+    if (P.opts.filter_mode == EXPM_FILTER_NONE) a = 0.0;
+    S.M = M;
+    S.N = N;
+    S.normal = normal;
+    S.a = a;
+    // Step 3: H0 = H 2^-N, r0, eg0, Taylor seed.
+    HIPCHK(scale_ldexp((const double *)P.H0.v.p, (double *)P.H0.v.p, nnz, -N, st));
+    const double h0 = ldexp(nh, -N), r0 = plan_r0(M, h0);
+    const double eg0 = a * r0 / (M * exp(2.0 * h0));
+    S.h0 = h0;
+    S.r0 = r0;
+    S.eg0 = eg0;
+    const bool keep = P.opts.keep_checkpoints != 0;
+    P.M = M;
+    P.N = N;
+    P.a = a;
+    int ck = P.opts.checkpoint_interval;
+    if (ck <= 0) ck = std::max(1, (int)ceil(sqrt((double)N)));
+    P.ck = ck;
+    CHK(copy_csr(P, P.S, P.H0));
+    CHK(copy_csr(P, P.T, P.H0));
+    if (keep) {
+        P.taylor.emplace_back();
+        CHK(copy_csr(P, P.taylor.back(), P.H0));
+    }
+    S.taylor_terms = 1;
+    const CsrView H0v = P.H0.view();
+    for (int i = 2; i <= M; ++i) {
+        int64_t cand;
+        CHK(spgemm(P, P.S.view(), H0v, 0.0, (double)i, false, &cand));
+        FilterCtl h{};
+        int64_t kept;
+        CHK(filter_and_count(P, n, cand, eg0, nullptr, false, 0.0, false, &h, &kept));
+        S.taylor_theta[i] = h.theta;
+        S.taylor_iters[i] = h.iter;
+        S.taylor_cand[i] = cand;
+        S.taylor_kept[i] = kept;
+        if (kept == 0) break;   // later terms are exactly zero
+        CHK(write_filtered(P, n, P.Snew, kept, false, false));
+        std::swap(P.S, P.Snew);
+        P.S.nnz = kept;
+        S.taylor_terms = i;
+        if (keep) {
+            P.taylor.emplace_back();
+            CHK(copy_csr(P, P.taylor.back(), P.S));
+        }
+        CHK(sparse_add(P, P.T, P.S, P.Tnew));
+        std::swap(P.T, P.Tnew);
+    }
+    P.Mp = S.taylor_terms;
+    // T's true nnz (the add only bounds it)
+    HIPCHK(hipMemcpyAsync(P.host, (int64_t *)P.T.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    memcpy(&P.T.nnz, P.host, sizeof(int64_t));
+    if (keep) {
+        P.ckpt.emplace_back();
+        CHK(copy_csr(P, P.ckpt.back(), P.T));
+    }
+    // Step 4: squarings.  Step 5 (E = I + T_N) is fused into the last one.
+    DCsr Eout;
+    for (int i = 1; i <= N; ++i) {
+        const double ri = ldexp(r0, i);
+        const bool last = i == N;
+        CHK(square_step(P, P.T, P.Tnew, a * ri, false, 0.0, false, false, i));
+        P.theta.push_back(S.sq_theta[i]);
+        std::swap(P.T, P.Tnew);
+        P.T.nnz = S.sq_kept[i];
+        if (keep && !last && i % ck == 0) {
+            P.ckpt.emplace_back();
+            CHK(copy_csr(P, P.ckpt.back(), P.T));
+        }
+    }
+    S.squarings = N;
+    if (keep) CHK(copy_csr(P, P.TN, P.T));
+    // E = I + T_N (exact zeros not stored)
+    {
+        CHK(ensure(P, P.crp, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.cci, sizeof(int32_t) * (P.T.nnz + 1)));
+        CHK(ensure(P, P.cv, sizeof(double) * (P.T.nnz + 1)));
+        HIPCHK(hipMemcpyAsync(P.crp.p, P.T.rp.p, sizeof(int64_t) * (n + 1),
+                              hipMemcpyDeviceToDevice, st));
+        if (P.T.nnz) {
+            HIPCHK(hipMemcpyAsync(P.cci.p, P.T.ci.p, sizeof(int32_t) * P.T.nnz,
+                                  hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(P.cv.p, P.T.v.p, sizeof(double) * P.T.nnz,
+                                  hipMemcpyDeviceToDevice, st));
+        }
+        FilterCtl h{};
+        int64_t kept;
+        CHK(filter_and_count(P, n, P.T.nnz, 0.0, nullptr, true, -1.0, true, &h, &kept));
+        int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
+        int32_t *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * kept);
+        double *v = (double *)out_alloc(P, sizeof(double) * kept);
+        if (!rp || !ci || !v) {
+            out_free(P, rp);
+            out_free(P, ci);
+            out_free(P, v);
+            return fail(EXPM_ENOMEM, "cannot allocate the output (%lld entries)",
+                        (long long)kept);
+        }
+        HIPCHK(hipMemcpyAsync(rp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+                              st));
+        HIPCHK(write_kept((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
+                          (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, rp, ci, v,
+                          st));
+        E->n = n;
+        E->nnz = kept;
+        E->rowptr = rp;
+        E->col = ci;
+        E->val = v;
+        S.nnz_e = kept;
+        if (keep) {
+            CHK(ensure_csr(P, P.Epat, n, kept));
+            HIPCHK(hipMemcpyAsync(P.Epat.rp.p, rp, sizeof(int64_t) * (n + 1),
+                                  hipMemcpyDeviceToDevice, st));
+            if (kept)
+                HIPCHK(hipMemcpyAsync(P.Epat.ci.p, ci, sizeof(int32_t) * kept,
+                                      hipMemcpyDeviceToDevice, st));
+        }
+    }
+    S.peak_workspace_bytes = P.peak;
+    P.have_fwd = keep;
+    P.have_stats = true;
+    return EXPM_OK;
+}
+
+// ------------------------------------------------------------------ backward
+
+int backward(expm_plan_s &P, const double *dE, double *dH) {
+    if (!P.have_fwd) return fail(EXPM_ESTATE, "no forward state: run expm_sparse with "
+                                              "keep_checkpoints = 1 first");
+    hipStream_t st = P.st;
+    const int64_t n = P.H0.n, nnzH = P.H0.nnz;
+    if (P.zero_h) {   // e^0 = I was returned without computation: constant map
+        if (nnzH) HIPCHK(hipMemsetAsync(dH, 0, sizeof(double) * nnzH, st));
+        return EXPM_OK;
+    }
+    const int N = P.N, ck = P.ck;
+    // G_N on supp(T_N): E = I + T_N.
+    CsrView Ev = CsrView{n, (const int64_t *)P.Epat.rp.p, (const int32_t *)P.Epat.ci.p, dE};
+    Buf g, gn;
+    CHK(ensure(P, g, sizeof(double) * (P.TN.nnz + 1)));
+    MaskTerm none{empty_view(), empty_view(), 0.0};
+    CHK(masked(P, P.TN.view(), Ev, 1.0, none, none, 1.0, (double *)g.p));
+    // iterates of the current segment: seg[j] = T^_{base + j}
+    std::vector<DCsr> seg;
+    int seg_base = -1;
+    DCsr Tt;
+    const DCsr *Tk = &P.TN;   // pattern of g
+    for (int k = N; k >= 1; --k) {
+        const int km1 = k - 1;
+        const int base = (km1 / ck) * ck;
+        const DCsr *Tp;
+        if (km1 % ck == 0) {
+            Tp = &P.ckpt[km1 / ck];
+        } else {
+            if (seg_base != base) {
+                for (auto &A : seg) release(P, A);
+                seg.clear();
+                seg.resize(ck);
+                seg_base = base;
+                const DCsr *prev = &P.ckpt[base / ck];
+                for (int j = base + 1; j <= std::min(base + ck - 1, N - 1); ++j) {
+                    CHK(square_step(P, *prev, seg[j - base], 0.0, true, P.theta[j - 1], false,
+                                    true, 0));
+                    prev = &seg[j - base];
+                }
+            }
+            Tp = &seg[km1 - base];
+        }
+        CHK(transpose_csr(P, *Tp, Tt));
+        CHK(ensure(P, gn, sizeof(double) * (Tp->nnz + 1)));
+        CsrView Gk = CsrView{n, (const int64_t *)Tk->rp.p, (const int32_t *)Tk->ci.p,
+                             (const double *)g.p};
+        MaskTerm t1{Gk, Tt.view(), 1.0}, t2{Tt.view(), Gk, 1.0};
+        CHK(masked(P, Tp->view(), Gk, 2.0, t1, t2, 1.0, (double *)gn.p));
+        std::swap(g, gn);
+        Tk = Tp;
+        if (k - 1 == base && seg_base == base) {
+            for (auto &A : seg) release(P, A);
+            seg.clear();
+            seg_base = -1;
+        }
+    }
+    for (auto &A : seg) release(P, A);
+    // Taylor seed: g is dL/dT^_0 on supp(T^_0) = P.ckpt[0].
+    const int Mp = (int)P.taylor.size();
+    CsrView G0 = CsrView{n, (const int64_t *)P.ckpt[0].rp.p, (const int32_t *)P.ckpt[0].ci.p,
+                         (const double *)g.p};
+    DCsr H0t;
+    CHK(transpose_csr(P, P.H0, H0t));
+    std::vector<Buf> D(Mp + 1);
+    CHK(ensure(P, D[Mp], sizeof(double) * (P.taylor[Mp - 1].nnz + 1)));
+    CHK(masked(P, P.taylor[Mp - 1].view(), G0, 1.0, none, none, 1.0,
+               (double *)D[Mp].p));
+    Buf acc, acc2;
+    CHK(ensure(P, acc, sizeof(double) * (nnzH + 1)));
+    CHK(ensure(P, acc2, sizeof(double) * (nnzH + 1)));
+    if (nnzH) HIPCHK(hipMemsetAsync(acc.p, 0, sizeof(double) * nnzH, st));
+    DCsr St;
+    for (int i = Mp - 1; i >= 1; --i) {
+        const DCsr &Si = P.taylor[i - 1], &Sn = P.taylor[i];
+        CsrView Dn = CsrView{n, (const int64_t *)Sn.rp.p, (const int32_t *)Sn.ci.p,
+                             (const double *)D[i + 1].p};
+        CHK(ensure(P, D[i], sizeof(double) * (Si.nnz + 1)));
+        MaskTerm t1{Dn, H0t.view(), 1.0};
+        CHK(masked(P, Si.view(), G0, 1.0, t1, none, (double)(i + 1), (double *)D[i].p));
+        CHK(transpose_csr(P, Si, St));
+        MaskTerm t3{St.view(), Dn, 1.0};
+        CsrView accv = CsrView{n, (const int64_t *)P.H0.rp.p, (const int32_t *)P.H0.ci.p,
+                               (const double *)acc.p};
+        CHK(masked(P, P.H0.view(), accv, 1.0, t3, none, (double)(i + 1),
+                   (double *)acc2.p));
+        std::swap(acc, acc2);
+    }
+    // dH = 2^-N (acc + D_1); S^_1 = H0 shares H's pattern.
+    HIPCHK(add_scaled_ldexp((const double *)acc.p, (const double *)D[1].p, dH, nnzH, -N, st));
+    for (auto &b : D) release(P, b);
+    release(P, acc);
+    release(P, acc2);
+    release(P, g);
+    release(P, gn);
+    release(P, Tt);
+    release(P, H0t);
+    release(P, St);
+    CHK(sync(P));
+    return EXPM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+void expm_opts_default(expm_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->normal = EXPM_NORMAL_AUTO;
+    o->filter_mode = EXPM_FILTER_PAPER;
+    o->e_r = 0.1;
+    o->max_filter_iter = 64;
+    o->keep_checkpoints = 0;
+    o->checkpoint_interval = 0;
+    o->stream = nullptr;
+    o->allocator = nullptr;
+}
+
+int expm_plan(expm_plan_t *out, const expm_opts *opts) {
+    g_err.clear();
+    if (!out) return fail(EXPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    expm_opts o;
+    if (opts)
+        o = *opts;
+    else
+        expm_opts_default(&o);
+    if (o.filter_mode != EXPM_FILTER_PAPER && o.filter_mode != EXPM_FILTER_NONE)
+        return fail(EXPM_EINVAL, "unknown filter_mode %d", o.filter_mode);
+    if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
+        o.checkpoint_interval < 0)
+        return fail(EXPM_EINVAL, "invalid option value");
+    expm_plan_s *P = new (std::nothrow) expm_plan_s();
+    if (!P) return fail(EXPM_ENOMEM, "cannot allocate the plan");
+    P->opts = o;
+    P->st = (hipStream_t)o.stream;
+    if (hipHostMalloc((void **)&P->host, 4096, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete P;
+        return fail(EXPM_EHIP, "cannot allocate pinned host memory");
+    }
+    // keep freed pool memory cached in the process for reuse between calls
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    }
+    (void)hipGetLastError();
+    *out = P;
+    return EXPM_OK;
+}
+
+int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E) {
+    g_err.clear();
+    if (!p) return fail(EXPM_EINVAL, "plan is NULL");
+    int s = forward(*p, H, eps, E);
+    if (s != EXPM_OK) {
+        p->stats.status = s;
+        (void)hipStreamSynchronize(p->st);
+        (void)hipGetLastError();
+        if (E) {
+            out_free(*p, E->rowptr);
+            out_free(*p, E->col);
+            out_free(*p, E->val);
+            memset(E, 0, sizeof *E);
+        }
+        free_adjoint_state(*p);
+    }
+    return s;
+}
+
+int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals) {
+    g_err.clear();
+    if (!p) return fail(EXPM_EINVAL, "plan is NULL");
+    if (p->have_fwd && p->H0.nnz && !dH_vals) return fail(EXPM_EINVAL, "dH is NULL");
+    if (p->have_fwd && p->Epat.nnz && !dE_vals) return fail(EXPM_EINVAL, "dE is NULL");
+    int s = backward(*p, dE_vals, dH_vals);
+    if (s != EXPM_OK) {
+        (void)hipStreamSynchronize(p->st);
+        (void)hipGetLastError();
+    }
+    return s;
+}
+
+
+int expm_get_stats(expm_plan_t p, expm_stats *out) {
+    if (!p || !out) return fail(EXPM_EINVAL, "NULL argument");
+    if (!p->have_stats) return fail(EXPM_ESTATE, "no call has completed on this plan");
+    *out = p->stats;
+    return EXPM_OK;
+}
+
+void expm_csr_release(expm_plan_t p, expm_csr *E) {
+    if (!p || !E) return;
+    out_free(*p, E->rowptr);
+    out_free(*p, E->col);
+    out_free(*p, E->val);
+    memset(E, 0, sizeof *E);
+}
+
+void expm_free(expm_plan_t p) {
+    if (!p) return;
+    expm_plan_s &P = *p;
+    (void)hipStreamSynchronize(P.st);
+    free_adjoint_state(P);
+    Buf *bufs[] = {&P.lo, &P.words, &P.woff, &P.ub, &P.cnt, &P.crp, &P.bitmaps, &P.lists,
+                   &P.counts, &P.scan_tmp, &P.part, &P.ctl, &P.rowsq, &P.norm2, &P.scratch,
+                   &P.soff, &P.sbytes, &P.flags, &P.krp, &P.tmp1, &P.tmp2, &P.cci, &P.cv};
+    for (Buf *b : bufs) release(P, *b);
+    DCsr *mats[] = {&P.H0, &P.S, &P.Snew, &P.T, &P.Tnew, &P.Hpat_t};
+    for (DCsr *m : mats) release(P, *m);
+    while (!P.outputs.empty()) out_free(P, P.outputs.back());
+    (void)hipStreamSynchronize(P.st);
+    if (P.host) (void)hipHostFree(P.host);
+    (void)hipGetLastError();
+    delete p;
+}
+
+const char *expm_last_error(void) { return g_err.c_str(); }
+
+double expm_r0(int M, double x) { return plan_r0(M, x); }
+
+int expm_choose_mn(double norm_h, double eps, int *M, int *N) {
+    if (!M || !N) return fail(EXPM_EINVAL, "NULL output");
+    int s = plan_mn(norm_h, eps, M, N);
+    if (s) return fail(s, "no (M, N) for norm %g and eps %g", norm_h, eps);
+    return EXPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Launch wrappers of the gfx950 kernels.  Every wrapper enqueues on `st` and
+// returns the status of the launch (hipSuccess or the launch error).
+#pragma once
+
+#include "common.hpp"
+
+namespace xpm {
+
+// Number of row classes of the bitmap and accumulator kernels (the last one
+// keeps its working set in global memory).
+constexpr int kSymClasses = 5;
+constexpr int kNumClasses = 7;
+
+// Per-wave LDS capacity (bytes) of each class; the last class is global.
+extern const int kSymCap[kSymClasses];
+extern const int kNumCap[kNumClasses];
+
+// Filter controller of Algorithm 4.1, resident in device memory.
+struct FilterCtl {
+    double eg;      // budget eps_g
+    double er;      // tolerance e_r
+    double theta;   // current entry threshold eps_f
+    double b;       // norm of the current drop set
+    double m;       // m_n
+    int iter, maxit, done, status;
+    unsigned arrive;  // blocks finished in the current pass
+};
+
+// ------------------------------------------------------------- scan
+// out[0] = 0, out[i+1] = out[i] + in[i] for i < n; int64 counts.
+hipError_t scan_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t tmp_bytes,
+                    hipStream_t st);
+size_t scan_tmp_bytes(int64_t n);
+
+// ------------------------------------------------------------- checks, norms
+// flag |= 1: rowptr not monotone / bad start; 2: column out of range or not
+// increasing; 4: non-finite value.
+hipError_t validate_csr(CsrView A, int64_t nnz, int *flag, hipStream_t st);
+// part[b] partial sums of v^2 over fixed chunks, then a fixed-order sum into *out.
+hipError_t sumsq(const double *v, const int64_t *count, int64_t maxcount, double *part, int nparts,
+                 double *out, hipStream_t st);
+hipError_t scale_ldexp(const double *in, double *out, int64_t m, int e, hipStream_t st);
+hipError_t negate_values(double *v, int64_t m, hipStream_t st);
+// *out = sum of v[0..m) in a fixed order (block partials, then one block).
+hipError_t sum_values(const double *v, int64_t m, double *part, int nparts, double *out,
+                      hipStream_t st);
+// out = ldexp(a + b, e), elementwise.
+hipError_t add_scaled_ldexp(const double *a, const double *b, double *out, int64_t m, int e,
+                            hipStream_t st);
+// flags[0] = 1 if pattern(A) == pattern(B); flags[1] = values equal; flags[2] = values negated.
+hipError_t compare_csr(CsrView A, CsrView B, int64_t nnz, int *flags, hipStream_t st);
+
+// ------------------------------------------------------------- SpGEMM
+// Row bounds of C = A*B (+ alphaA*A if addA): bitmap origin lo (multiple of
+// 32), bitmap words, and the number of partial products ub.
+hipError_t row_bounds(CsrView A, CsrView B, int addA, int32_t *lo, int64_t *words, int64_t *ub,
+                      hipStream_t st);
+// Class of every row from a per-row byte requirement; rows listed per class.
+// counts[kClasses] must be zeroed by the caller (done inside); lists is
+// kClasses * n int32.
+hipError_t bin_rows(const int64_t *words, const int64_t *cnt, int64_t n, int kind, int *counts,
+                    int32_t *lists, hipStream_t st);
+// Structural row counts of C and the column bitmaps of every row.
+hipError_t symbolic(CsrView A, CsrView B, int addA, const int32_t *lo, const int64_t *woff,
+                    uint32_t *bitmaps, int64_t *cnt, const int *host_counts, const int32_t *lists,
+                    int64_t n, hipStream_t st);
+// Numeric values: C = alphaA*A + A*B, then divided by `div` (1 = none).
+// Rows sorted by column.  rowsq (optional): per-row sum of (c_ij + delta_ij)^2
+// plus 1 when row i stores no diagonal entry.
+hipError_t numeric(CsrView A, CsrView B, double alphaA, double div, const int32_t *lo,
+                   const int64_t *woff, const uint32_t *bitmaps, const int64_t *crp, int32_t *cci,
+                   double *cv, double *rowsq, const int *host_counts, const int32_t *lists,
+                   int64_t n, void *scratch, const int64_t *scratch_off, hipStream_t st);
+// Per-row byte requirement of the global-memory numeric class (for scratch).
+hipError_t numeric_scratch_sizes(const int64_t *woff, const int64_t *crp, int64_t n,
+                                 int64_t *bytes, hipStream_t st);
+
+// ------------------------------------------------------------- filter
+hipError_t filter_init(FilterCtl *c, double eg_scale, const double *norm2, double er, int maxit,
+                       hipStream_t st);
+hipError_t filter_init_theta(FilterCtl *c, double theta, hipStream_t st);
+// One Algorithm 4.1 pass (sum of v^2 over |v| <= theta) plus the controller
+// update; no-ops once the controller is done.
+hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
+                       double *part, int nparts, hipStream_t st);
+// Kept counts per row (|v| > theta); with addI the identity is added (E = I + T).
+hipError_t count_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                      const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st);
+hipError_t write_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                      const FilterCtl *c, int addI, const int64_t *orp, int32_t *oci, double *ov,
+                      hipStream_t st);
+
+// ------------------------------------------------------------- sparse add
+// C = A + B with exact zeros removed (two passes: count then write).
+hipError_t add_count(CsrView A, CsrView B, int64_t *cnt, hipStream_t st);
+hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, double *cv,
+                     hipStream_t st);
+// Identity matrix rows.
+hipError_t fill_identity(int64_t n, int64_t *rp, int32_t *ci, double *v, hipStream_t st);
+
+// ------------------------------------------------------------- transpose
+// colcnt and fillpos: n int64 each; tmp_ci / tmp_v: nnz entries each (used
+// for rows longer than the LDS sort).
+hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double *tv,
+                     int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, double *tmp_v,
+                     void *scan_tmp, size_t scan_tmp_bytes, hipStream_t st);
+
+// ------------------------------------------------------------- masked products
+// out[e] (aligned with the stored entries of mask M) =
+//   gamma * D(i,j) + alpha1 * (A1*B1)(i,j) + alpha2 * (A2*B2)(i,j),
+// for (i, j) in supp(M); D, A2/B2 optional (n == 0 views are skipped).
+// The product terms are divided by `div` before being added.
+struct MaskTerm {
+    CsrView A, B;
+    double alpha;
+};
+// Returns hipErrorOutOfMemory (with *needed set) when scratch is too small.
+size_t masked_meta_bytes(int64_t n);
+hipError_t masked_products(CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2,
+                           double div, double *out, void *scratch, size_t scratch_bytes,
+                           size_t *needed, hipStream_t st);
+
+}  // namespace xpm
