@@ -1,0 +1,185 @@
+"""Benchmark: filtered precise-integration expm, forward + adjoint, on one GPU.
+
+One step = one pass of the whole hot path on the 2D heat-conduction
+workload (300 x 300 five-point grid, n = 90,000, lognormal(0, 0.5)
+conductances, H = -tau L with ||H||_1 = 50, eps_tol = 1e-12): planning,
+Taylor seed, N filtered squarings, E = I + T_N, then the adjoint of
+L = sum(G .* E) (G: 2% dense, N(0,1), a counter-based synthetic matrix).
+Inputs are resident on the device before timing starts.
+
+Prints one JSON line.  `value` is the wall time of one step in seconds
+(lower is better).  `roofline` covers the dominant kernel, the numeric pass
+of the squaring products, timed with HIP events on the library's stream
+inside the timed steps.  `cpu_baseline` times the CPU oracle on a bounded
+sample of the same workload family.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "expm wall time + squaring-SpGEMM HBM GB/s (% roofline) at n=90k; fwd+adjoint"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
+RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--side", type=int, default=300, help="grid side (300 -> n = 90,000)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-side", type=int, default=150)
+    ap.add_argument("--forward-only", action="store_true")
+    return ap.parse_args()
+
+
+def numeric_roofline(stats: dict, n: int):
+    """Algorithmic work of the numeric SpGEMM pass over all squaring steps.
+    Per step i: flops = 2 * (partial products of T*T) + 2 * nnz(T_{i-1})
+    (the 2T term); bytes = 12 * nnz(T_{i-1}) + 8 * (n + 1) (input CSR read
+    once) + 12 * cand_i (candidate CSR written once)."""
+    fl = by = t = 0.0
+    per = []
+    for i in range(stats["N"]):
+        fma, nin, cand = stats["sq_fma"][i], stats["sq_in"][i], stats["sq_cand"][i]
+        f = 2.0 * fma + 2.0 * nin
+        b = 12.0 * nin + 8.0 * (n + 1) + 12.0 * cand
+        ms = stats["t_num_ms"][i]
+        fl += f
+        by += b
+        t += ms
+        per.append({"step": i + 1, "ms": round(ms, 4), "gbps": round(b / (ms * 1e6), 1),
+                    "tflops": round(f / (ms * 1e9), 3), "cand": cand,
+                    "kept": stats["sq_kept"][i]})
+    return fl, by, t, per
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus N > 1 is not "
+                                   "supported (see the multi-GPU design notes)"}))
+        sys.exit(2)
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+
+    torch.cuda.set_device(0)
+    H, eps = W.config2(args.side)
+    n = H.n
+    crow = torch.from_numpy(H.rowptr).cuda()
+    col = torch.from_numpy(H.col).cuda()
+    val = torch.from_numpy(H.val).cuda()
+    plan = api.Plan("cuda", api.Options(keep_checkpoints=not args.forward_only, profile=True))
+    dE = None
+
+    def step():
+        nonlocal dE
+        rp, ci, v = plan.expm(crow, col, val, eps)
+        if not args.forward_only:
+            if dE is None or dE.numel() != v.numel():
+                # synthetic loss weights on E's support (built once, outside timing)
+                rows = np.repeat(np.arange(n), np.diff(rp.cpu().numpy()))
+                g = W.loss_weights(rows, ci.cpu().numpy(), n, density=0.02)
+                dE = torch.from_numpy(g).cuda()
+            plan.backward(dE, val.numel())
+        return v.numel()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times, fwd_ms, bwd_ms, stats = [], [], [], None
+    t_all0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nnz_e = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        stats = plan.stats()
+        fwd_ms.append(stats["t_total_ms"])
+        bwd_ms.append(stats["t_backward_ms"] if not args.forward_only else 0.0)
+    t_all = time.perf_counter() - t_all0
+    plan.close()
+    sec = t_all / args.steps
+
+    fl, by, tnum, per = numeric_roofline(stats, n)
+    tflops = fl / (tnum * 1e9)
+    gbps = by / (tnum * 1e6)
+    bound = "alu" if fl / by > RIDGE else "hbm"
+    if bound == "alu":
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
+                "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(gbps / PEAK_HBM_GBS, 4), "traffic": None}
+    t_bound = max(by / (PEAK_HBM_GBS * 1e9), fl / (PEAK_FP64_TFLOPS * 1e12)) * 1e3
+    out = {
+        "metric": METRIC, "value": round(sec, 5), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D 5-point grid Laplacian {args.side}x{args.side} (n={n}), "
+                               "lognormal(0,0.5) conductances, H=-tau*L with ||H||_1=50, "
+                               "eps_tol=1e-12; forward expm"
+                               + ("" if args.forward_only else
+                                  " + adjoint of sum(G.*E), G 2% N(0,1)"),
+                   "n": n, "nnz_h": int(H.nnz), "nnz_e": int(nnz_e), "M": stats["M"],
+                   "N": stats["N"], "parallelism": "single GPU"},
+        "forward_ms": round(float(np.median(fwd_ms)), 3),
+        "adjoint_ms": round(float(np.median(bwd_ms)), 3),
+        "roofline": roof,
+        "squaring_spgemm": {"kernel": "k_numeric", "ms": round(tnum, 3),
+                            "algorithmic_GB": round(by / 1e9, 3),
+                            "algorithmic_GFLOP": round(fl / 1e9, 2),
+                            "hbm_gbps": round(gbps, 1), "hbm_frac": round(gbps / PEAK_HBM_GBS, 4),
+                            "fp64_tflops": round(tflops, 3),
+                            "roofline_frac": round(t_bound / tnum, 4),
+                            "per_step": per},
+        "phase_ms": {"symbolic": round(sum(stats["t_sym_ms"]), 3),
+                     "numeric": round(tnum, 3),
+                     "filter": round(sum(stats["t_filter_ms"]), 3),
+                     "taylor": round(stats["t_taylor_ms"], 3)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, n)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, n_full):
+    """The oracle on a bounded sample: the same workload family on a
+    side x side grid (default 150 -> n = 22,500), forward + adjoint, scaled
+    linearly in the number of rows to the benchmark's n."""
+    import oracle
+    from paper_2110_04493_amd import workloads as W
+    H, eps = W.config2(args.cpu_sample_side)
+    t0 = time.perf_counter()
+    run = oracle.Run(H.rowptr, H.col, H.val, eps, keep=not args.forward_only)
+    res = run.result()
+    if not args.forward_only:
+        rows = np.repeat(np.arange(H.n), np.diff(res.rowptr))
+        run.backward(W.loss_weights(rows, res.col, H.n, density=0.02))
+    dt = time.perf_counter() - t0
+    run.close()
+    scale = n_full / H.n
+    return {"value": round(dt * scale, 3), "unit": "s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"oracle forward{'' if args.forward_only else ' + adjoint'} on the "
+                      f"{args.cpu_sample_side}x{args.cpu_sample_side} grid of the same family "
+                      f"(n={H.n}, M={res.stats['M']}, N={res.stats['N']}) took {dt:.2f} s; "
+                      f"scaled x{scale:.1f} (linear in rows) to n={n_full}"}
+
+
+if __name__ == "__main__":
+    main()

@@ -91,6 +91,10 @@ typedef struct {
                                 c = ceil(sqrt(N)), 1 keeps all of them         */
     void *stream;            /* hipStream_t for every launch and copy          */
     const expm_allocator *allocator; /* outputs; NULL = library allocation     */
+    int profile;             /* 1: time the kernel phases of every squaring
+                                step with HIP events on `stream` and count
+                                the algorithmic work (fields t_* and sq_fma,
+                                sq_in of expm_stats); 0 (default): off        */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',
@@ -107,6 +111,14 @@ typedef struct {
     int64_t sq_cand[EXPM_MAXSTEP], sq_kept[EXPM_MAXSTEP];
     int64_t nnz_e;
     size_t peak_workspace_bytes;
+    /* with opts.profile: per squaring step i, the partial products of
+     * T*T (sq_fma), the stored entries of the input iterate (sq_in), and the
+     * device time in ms of the symbolic, numeric and filter+compaction
+     * phases; t_taylor_ms is the whole Taylor phase, t_backward_ms the last
+     * expm_sparse_backward call. */
+    int64_t sq_fma[EXPM_MAXSTEP], sq_in[EXPM_MAXSTEP];
+    double t_sym_ms[EXPM_MAXSTEP], t_num_ms[EXPM_MAXSTEP], t_filter_ms[EXPM_MAXSTEP];
+    double t_taylor_ms, t_backward_ms, t_total_ms;
 } expm_stats;
 
 typedef struct expm_plan_s *expm_plan_t;

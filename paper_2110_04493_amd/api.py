@@ -69,6 +69,7 @@ class Options:
     max_filter_iter: int = 64
     keep_checkpoints: bool = False
     checkpoint_interval: int = 0
+    profile: bool = False
 
 
 class Plan:
@@ -90,6 +91,7 @@ class Plan:
         o.checkpoint_interval = self.options.checkpoint_interval
         o.stream = self.stream.cuda_stream
         o.allocator = C.pointer(self.alloc.struct)
+        o.profile = int(self.options.profile)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)

@@ -57,7 +57,7 @@ class expm_opts(C.Structure):
     _fields_ = [("normal", C.c_int), ("filter_mode", C.c_int), ("e_r", C.c_double),
                 ("max_filter_iter", C.c_int), ("keep_checkpoints", C.c_int),
                 ("checkpoint_interval", C.c_int), ("stream", C.c_void_p),
-                ("allocator", C.POINTER(expm_allocator))]
+                ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int)]
 
 
 _S = EXPM_MAXSTEP
@@ -74,17 +74,23 @@ class expm_stats(C.Structure):
                 ("sq_budget", C.c_double * _S), ("sq_dropped", C.c_double * _S),
                 ("sq_iters", C.c_int * _S),
                 ("sq_cand", C.c_int64 * _S), ("sq_kept", C.c_int64 * _S),
-                ("nnz_e", C.c_int64), ("peak_workspace_bytes", C.c_size_t)]
+                ("nnz_e", C.c_int64), ("peak_workspace_bytes", C.c_size_t),
+                ("sq_fma", C.c_int64 * _S), ("sq_in", C.c_int64 * _S),
+                ("t_sym_ms", C.c_double * _S), ("t_num_ms", C.c_double * _S),
+                ("t_filter_ms", C.c_double * _S),
+                ("t_taylor_ms", C.c_double), ("t_backward_ms", C.c_double),
+                ("t_total_ms", C.c_double)]
 
     def to_dict(self) -> dict:
         d = {k: getattr(self, k) for k in ("status", "M", "N", "taylor_terms", "normal",
                                            "squarings", "a", "norm_h", "h0", "r0", "eg0",
-                                           "nnz_e", "peak_workspace_bytes")}
+                                           "nnz_e", "peak_workspace_bytes", "t_taylor_ms",
+                                           "t_backward_ms", "t_total_ms")}
         T, N = self.taylor_terms, self.squarings
         for k in ("taylor_theta", "taylor_iters", "taylor_cand", "taylor_kept"):
             d[k] = list(getattr(self, k)[2:T + 2])
         for k in ("sq_theta", "sq_normF", "sq_budget", "sq_dropped", "sq_iters", "sq_cand",
-                  "sq_kept"):
+                  "sq_kept", "sq_fma", "sq_in", "t_sym_ms", "t_num_ms", "t_filter_ms"):
             d[k] = list(getattr(self, k)[1:N + 1])
         return d
 

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -22,9 +23,10 @@ namespace {
 
 thread_local std::string g_err;
 
-struct Status {
-    int code = EXPM_OK;
-};
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+        .count();
+}
 
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...) {
@@ -99,6 +101,10 @@ struct expm_plan_s {
     expm_stats stats{};
     bool have_stats = false;
     std::vector<void *> outputs;
+    // profiling: events around the phases of the last sparse product
+    hipEvent_t ev[8] = {};
+    bool have_events = false;
+    int64_t last_fma = 0;
 };
 
 namespace {
@@ -256,7 +262,7 @@ int plan_mn(double nh, double eps, int *Mo, int *No) {
 // C = alphaA * A + A * B (divided by div), into the candidate buffers
 // (P.crp, P.cci, P.cv).  Returns the candidate total in *total; with rowsq
 // the per-row sums of (c + delta)^2 are left in P.rowsq.
-int spgemm(expm_plan_s &P, CsrView A, CsrView B, double alphaA, double div, bool rowsq,
+int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, double div, bool rowsq,
            int64_t *total) {
     const int64_t n = A.n;
     hipStream_t st = P.st;
@@ -271,6 +277,8 @@ int spgemm(expm_plan_s &P, CsrView A, CsrView B, double alphaA, double div, bool
     CHK(ensure(P, P.lists, sizeof(int32_t) * (size_t)kNumClasses * (n > 0 ? n : 1)));
     CHK(ensure(P, P.counts, sizeof(int) * 16));
     int64_t *words = (int64_t *)P.words.p, *woff = (int64_t *)P.woff.p;
+    const bool prof = P.opts.profile && P.have_events;
+    if (prof) HIPCHK(hipEventRecord(P.ev[0], st));
     HIPCHK(row_bounds(A, B, alphaA != 0.0, (int32_t *)P.lo.p, words, (int64_t *)P.ub.p, st));
     CHK(scan(P, words, woff, n));
     HIPCHK(bin_rows(woff, nullptr, n, 0, (int *)P.counts.p, (int32_t *)P.lists.p, st));
@@ -290,6 +298,13 @@ int spgemm(expm_plan_s &P, CsrView A, CsrView B, double alphaA, double div, bool
     HIPCHK(numeric_scratch_sizes(woff, crp, n, (int64_t *)P.sbytes.p, st));
     CHK(scan(P, (const int64_t *)P.sbytes.p, (int64_t *)P.soff.p, n));
     HIPCHK(bin_rows(woff, crp, n, 1, (int *)P.counts.p, (int32_t *)P.lists.p, st));
+    if (prof) {
+        // partial products = sum of ub minus the rows of the alphaA*A term
+        CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
+        CHK(scan(P, (const int64_t *)P.ub.p, (int64_t *)P.tmp1.p, n));
+        HIPCHK(hipMemcpyAsync(hl + 8, (int64_t *)P.tmp1.p + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipMemcpyAsync(hl, crp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.soff.p + n, sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
@@ -303,10 +318,17 @@ int spgemm(expm_plan_s &P, CsrView A, CsrView B, double alphaA, double div, bool
     CHK(ensure(P, P.cv, sizeof(double) * cand));
     if (gscratch) CHK(ensure(P, P.scratch, (size_t)gscratch));
     if (rowsq) CHK(ensure(P, P.rowsq, sizeof(double) * (n + 1)));
+    if (prof) {
+        int64_t ubt;
+        memcpy(&ubt, hl + 8, sizeof ubt);
+        P.last_fma = alphaA != 0.0 ? ubt - nnzA : ubt;
+        HIPCHK(hipEventRecord(P.ev[1], st));
+    }
     HIPCHK(numeric(A, B, alphaA, div, (const int32_t *)P.lo.p, woff,
                    (const uint32_t *)P.bitmaps.p, crp, (int32_t *)P.cci.p, (double *)P.cv.p,
                    rowsq ? (double *)P.rowsq.p : nullptr, numc, (const int32_t *)P.lists.p, n,
                    P.scratch.p, (const int64_t *)P.soff.p, st));
+    if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     *total = cand;
     return EXPM_OK;
 }
@@ -472,13 +494,13 @@ int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal) {
     }
     // ||H H^T - H^T H||_F <= 16 u ||H||_F^2
     int64_t c1, c2;
-    CHK(spgemm(P, H.view(), Ht.view(), 0.0, 1.0, false, &c1));
+    CHK(spgemm(P, H.view(), H.nnz, Ht.view(), 0.0, 1.0, false, &c1));
     DCsr X, Y;
     CHK(ensure_csr(P, X, n, c1));
     HIPCHK(hipMemcpyAsync(X.rp.p, P.crp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, P.st));
     HIPCHK(hipMemcpyAsync(X.ci.p, P.cci.p, sizeof(int32_t) * c1, hipMemcpyDeviceToDevice, P.st));
     HIPCHK(hipMemcpyAsync(X.v.p, P.cv.p, sizeof(double) * c1, hipMemcpyDeviceToDevice, P.st));
-    CHK(spgemm(P, Ht.view(), H.view(), 0.0, 1.0, false, &c2));
+    CHK(spgemm(P, Ht.view(), Ht.nnz, H.view(), 0.0, 1.0, false, &c2));
     CHK(ensure_csr(P, Y, n, c2));
     HIPCHK(hipMemcpyAsync(Y.rp.p, P.crp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, P.st));
     HIPCHK(hipMemcpyAsync(Y.ci.p, P.cci.p, sizeof(int32_t) * c2, hipMemcpyDeviceToDevice, P.st));
@@ -522,7 +544,7 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
                 double theta_fixed, bool addI, bool exact_alloc, int stat_i) {
     const int64_t n = T.n;
     int64_t cand;
-    CHK(spgemm(P, T.view(), T.view(), 2.0, 1.0, !use_fixed, &cand));
+    CHK(spgemm(P, T.view(), T.nnz, T.view(), 2.0, 1.0, !use_fixed, &cand));
     if (!use_fixed) {
         CHK(ensure(P, P.norm2, sizeof(double) * 2));
         CHK(ensure(P, P.part, sizeof(double) * kParts));
@@ -534,6 +556,19 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
     CHK(filter_and_count(P, n, cand, a_ri, (const double *)P.norm2.p, use_fixed, theta_fixed,
                          addI, &h, &kept));
     CHK(write_filtered(P, n, dst, kept, addI, exact_alloc));
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP && P.opts.profile && P.have_events) {
+        HIPCHK(hipEventRecord(P.ev[3], P.st));
+        HIPCHK(hipEventSynchronize(P.ev[3]));
+        float t0, t1, t2;
+        HIPCHK(hipEventElapsedTime(&t0, P.ev[0], P.ev[1]));
+        HIPCHK(hipEventElapsedTime(&t1, P.ev[1], P.ev[2]));
+        HIPCHK(hipEventElapsedTime(&t2, P.ev[2], P.ev[3]));
+        P.stats.t_sym_ms[stat_i] = t0;
+        P.stats.t_num_ms[stat_i] = t1;
+        P.stats.t_filter_ms[stat_i] = t2;
+        P.stats.sq_fma[stat_i] = P.last_fma;
+        P.stats.sq_in[stat_i] = T.nnz;
+    }
     if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
         expm_stats &S = P.stats;
         S.sq_theta[stat_i] = h.theta;
@@ -626,6 +661,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     S.N = N;
     S.normal = normal;
     S.a = a;
+    const auto t_taylor0 = std::chrono::steady_clock::now();
     // Step 3: H0 = H 2^-N, r0, eg0, Taylor seed.
     HIPCHK(scale_ldexp((const double *)P.H0.v.p, (double *)P.H0.v.p, nnz, -N, st));
     const double h0 = ldexp(nh, -N), r0 = plan_r0(M, h0);
@@ -650,7 +686,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     const CsrView H0v = P.H0.view();
     for (int i = 2; i <= M; ++i) {
         int64_t cand;
-        CHK(spgemm(P, P.S.view(), H0v, 0.0, (double)i, false, &cand));
+        CHK(spgemm(P, P.S.view(), P.S.nnz, H0v, 0.0, (double)i, false, &cand));
         FilterCtl h{};
         int64_t kept;
         CHK(filter_and_count(P, n, cand, eg0, nullptr, false, 0.0, false, &h, &kept));
@@ -671,6 +707,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         std::swap(P.T, P.Tnew);
     }
     P.Mp = S.taylor_terms;
+    S.t_taylor_ms = ms_since(t_taylor0);
     // T's true nnz (the add only bounds it)
     HIPCHK(hipMemcpyAsync(P.host, (int64_t *)P.T.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
@@ -903,6 +940,12 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
         }
     }
     (void)hipGetLastError();
+    if (o.profile) {
+        P->have_events = true;
+        for (hipEvent_t &e : P->ev)
+            if (hipEventCreate(&e) != hipSuccess) P->have_events = false;
+        (void)hipGetLastError();
+    }
     *out = P;
     return EXPM_OK;
 }
@@ -910,7 +953,12 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
 int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E) {
     g_err.clear();
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
+    const auto t0 = std::chrono::steady_clock::now();
     int s = forward(*p, H, eps, E);
+    if (s == EXPM_OK) {
+        (void)hipStreamSynchronize(p->st);
+        p->stats.t_total_ms = ms_since(t0);
+    }
     if (s != EXPM_OK) {
         p->stats.status = s;
         (void)hipStreamSynchronize(p->st);
@@ -931,7 +979,9 @@ int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals) 
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
     if (p->have_fwd && p->H0.nnz && !dH_vals) return fail(EXPM_EINVAL, "dH is NULL");
     if (p->have_fwd && p->Epat.nnz && !dE_vals) return fail(EXPM_EINVAL, "dE is NULL");
+    const auto t0 = std::chrono::steady_clock::now();
     int s = backward(*p, dE_vals, dH_vals);
+    if (s == EXPM_OK) p->stats.t_backward_ms = ms_since(t0);
     if (s != EXPM_OK) {
         (void)hipStreamSynchronize(p->st);
         (void)hipGetLastError();
@@ -968,6 +1018,8 @@ void expm_free(expm_plan_t p) {
     for (DCsr *m : mats) release(P, *m);
     while (!P.outputs.empty()) out_free(P, P.outputs.back());
     (void)hipStreamSynchronize(P.st);
+    if (P.have_events)
+        for (hipEvent_t &e : P.ev) (void)hipEventDestroy(e);
     if (P.host) (void)hipHostFree(P.host);
     (void)hipGetLastError();
     delete p;
