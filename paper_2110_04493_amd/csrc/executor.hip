@@ -14,12 +14,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/expm.h"
-#include "kernels.hpp"
+#include "plan.hpp"
 
 using namespace xpm;
+using namespace xpm::host;
 
-namespace {
+namespace xpm {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -39,75 +40,13 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIPCHK(expr)                                                                       \
-    do {                                                                                   \
-        hipError_t _e = (expr);                                                            \
-        if (_e != hipSuccess) {                                                            \
-            if (_e == hipErrorOutOfMemory)                                                 \
-                return fail(EXPM_ENOMEM, "%s: out of device memory (%s:%d)", #expr,        \
-                            __FILE__, __LINE__);                                           \
-            return fail(EXPM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),  \
-                        __FILE__, __LINE__);                                               \
-        }                                                                                  \
-    } while (0)
 
-#define CHK(expr)                \
-    do {                         \
-        int _s = (expr);         \
-        if (_s != EXPM_OK) return _s; \
-    } while (0)
+}  // namespace host
+}  // namespace xpm
 
-// ------------------------------------------------------------------ memory
 
-// Grow-only device buffer from the stream-ordered pool.
-struct Buf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct DCsr {
-    int64_t n = 0, nnz = 0;
-    Buf rp, ci, v;
-    CsrView view() const {
-        return CsrView{n, (const int64_t *)rp.p, (const int32_t *)ci.p, (const double *)v.p};
-    }
-};
-
-}  // namespace
-
-struct expm_plan_s {
-    expm_opts opts{};
-    hipStream_t st = nullptr;
-    size_t live = 0, peak = 0;
-
-    // workspace
-    Buf lo, words, woff, ub, cnt, crp, bitmaps, lists, counts, scan_tmp, part, ctl, rowsq, norm2,
-        scratch, soff, sbytes, flags, krp, tmp1, tmp2;
-    Buf cci, cv;            // candidate entries
-    int *host = nullptr;    // pinned readback area
-    // current matrices
-    DCsr H0, S, Snew, T, Tnew, Hpat_t;
-    // adjoint state
-    bool have_fwd = false;
-    int M = 0, N = 0, Mp = 0, ck = 1;
-    double a = 0;
-    std::vector<DCsr> taylor;        // S^_1 .. S^_M'
-    std::vector<DCsr> ckpt;          // T^_k for k = 0, ck, 2ck, ... (index k / ck)
-    DCsr TN;                         // T^_N
-    DCsr Epat;                       // pattern of the returned E
-    std::vector<double> theta;       // squaring thresholds, 1..N
-    bool zero_h = false;
-    // stats / outputs
-    expm_stats stats{};
-    bool have_stats = false;
-    std::vector<void *> outputs;
-    // profiling: events around the phases of the last sparse product
-    hipEvent_t ev[8] = {};
-    bool have_events = false;
-    int64_t last_fma = 0;
-};
-
-namespace {
+namespace xpm {
+namespace host {
 
 int ensure(expm_plan_s &P, Buf &b, size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -333,7 +272,6 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
     return EXPM_OK;
 }
 
-constexpr int kParts = 1024;
 
 // Algorithm 4.1 on the candidate values plus the row counts of the kept
 // entries: leaves the threshold in P.ctl, kept counts scanned into P.krp.
@@ -888,7 +826,8 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     return EXPM_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace xpm
 
 // ====================================================================== C ABI
 

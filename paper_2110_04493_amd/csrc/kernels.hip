@@ -1,57 +1,13 @@
-// gfx950 kernels of the filtered precise-integration sparse exponential.
-//
-// Sparse products use row-wise Gustavson (one wavefront per output row) in
-// two passes.  The symbolic pass marks the output columns of a row in a bit
-// map spanning [lo, hi] of the columns the row can reach; the bit maps are
-// kept.  The numeric pass turns a bit map into a perfect hash: the rank of a
-// column (prefix popcount) is its position in the sorted output row, so
-// partial products are accumulated into a compact LDS array that is already
-// in column order and no sort is needed.  A wave consumes the left factor's
-// row in storage order and spreads one right-factor row over its lanes at a
-// time; within one instruction all columns differ, so accumulation is
-// race-free without atomics and bitwise reproducible.
-//
-// Rows are binned by their working-set size; each bin runs with the number
-// of waves per block that keeps one block within 64 KB of LDS, and rows too
-// large for LDS run the same code on global scratch.
+// gfx950 kernels of the filtered precise-integration sparse exponential:
+// scans, reductions, checks, the device side of Algorithm 4.1 (filter
+// passes and controller), compaction with the identity insert of
+// Algorithm 4.2 step 5, sparse addition and transposition.  The sparse
+// products themselves are in spgemm.hip.
 #include "kernels.hpp"
 
 #include <math.h>
 
 namespace xpm {
-
-const int kSymCap[kSymClasses] = {1024, 4096, 16384, 65536, 0};
-static const int kSymWpb[kSymClasses] = {8, 8, 4, 1, 4};
-const int kNumCap[kNumClasses] = {2048, 4096, 8192, 16384, 32768, 65536, 0};
-static const int kNumWpb[kNumClasses] = {8, 8, 8, 4, 2, 1, 4};
-
-// Orders this wave's earlier LDS accesses before its later ones (LDS
-// instructions of one wave execute in order; this stops the compiler from
-// moving accesses across the phase boundary).
-__device__ __forceinline__ void wave_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Phase boundary for working sets in global memory: waits for and publishes
-// every outstanding access of the wave.
-template <bool kGlobal>
-__device__ __forceinline__ void phase_fence() {
-    if (kGlobal) __threadfence();
-    wave_fence();
-}
-
-// Accumulate into the working set: plain read-modify-write in LDS (lanes of
-// one instruction always hold distinct slots), device atomics in global.
-template <bool kGlobal>
-__device__ __forceinline__ void acc_add(double *p, double x) {
-    if (kGlobal)
-        atomicAdd(p, x);
-    else
-        *p += x;
-}
-
-__device__ __forceinline__ int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
 // ============================================================== scan
 // Three-phase exclusive scan: per-block sums, a scan of the block sums in
@@ -279,312 +235,6 @@ hipError_t compare_csr(CsrView A, CsrView B, int64_t nnz, int *flags, hipStream_
     return hipGetLastError();
 }
 
-// ============================================================== SpGEMM: bounds
-
-__global__ void k_row_bounds(CsrView A, CsrView B, int addA, int32_t *lo, int64_t *words,
-                             int64_t *ub) {
-    int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (i >= A.n) return;
-    int mn = INT32_MAX, mx = -1;
-    long long s = 0;
-    int64_t b = A.rp[i], e = A.rp[i + 1];
-    for (int64_t p = b + lane_id(); p < e; p += kWave) {
-        int k = A.ci[p];
-        int64_t q0 = B.rp[k], q1 = B.rp[k + 1];
-        if (q1 > q0) {
-            mn = min(mn, B.ci[q0]);
-            mx = max(mx, B.ci[q1 - 1]);
-            s += q1 - q0;
-        }
-    }
-    if (addA && e > b && lane_id() == 0) {
-        mn = min(mn, A.ci[b]);
-        mx = max(mx, A.ci[e - 1]);
-        s += e - b;
-    }
-    mn = wave_min(mn);
-    mx = wave_max(mx);
-    s = wave_sum_ll(s);
-    if (lane_id() == 0) {
-        if (mx < 0) {
-            lo[i] = 0;
-            words[i] = 0;
-        } else {
-            int l = mn & ~31;
-            lo[i] = l;
-            words[i] = ((mx - l) >> 5) + 1;
-        }
-        ub[i] = s;
-    }
-}
-
-hipError_t row_bounds(CsrView A, CsrView B, int addA, int32_t *lo, int64_t *words, int64_t *ub,
-                      hipStream_t st) {
-    if (A.n == 0) return hipSuccess;
-    int wpb = 4;
-    hipLaunchKernelGGL(k_row_bounds, dim3((A.n + wpb - 1) / wpb), dim3(wpb * kWave), 0, st, A, B,
-                       addA, lo, words, ub);
-    return hipGetLastError();
-}
-
-// ============================================================== binning
-// kind 0: symbolic (bit map bytes), 1: numeric (accumulator + stage + bit
-// map with prefix counts), 2: masked product (accumulator + bit map/prefix).
-__device__ __forceinline__ int64_t row_bytes(int kind, int64_t W, int64_t c) {
-    if (kind == 0) return 4 * W;
-    if (kind == 1) return align8(12 * c) + 8 * W;
-    return 8 * c + 8 * W;
-}
-
-struct Caps {
-    int cap[8];
-    int ncls;
-};
-
-__global__ void k_bin(const int64_t *woff, const int64_t *crp, int64_t n, int kind, Caps caps,
-                      int *counts, int32_t *lists) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t W = woff[i + 1] - woff[i];
-    int64_t c = crp ? crp[i + 1] - crp[i] : 0;
-    int64_t bytes = row_bytes(kind, W, c);
-    int cls = caps.ncls - 1;
-    for (int j = 0; j < caps.ncls - 1; j++)
-        if (bytes <= caps.cap[j]) {
-            cls = j;
-            break;
-        }
-    int pos = atomicAdd(&counts[cls], 1);
-    lists[(int64_t)cls * n + pos] = (int32_t)i;
-}
-
-hipError_t bin_rows(const int64_t *woff, const int64_t *crp, int64_t n, int kind, int *counts,
-                    int32_t *lists, hipStream_t st) {
-    Caps caps;
-    caps.ncls = kind == 0 ? kSymClasses : kNumClasses;
-    for (int j = 0; j < caps.ncls; j++) caps.cap[j] = kind == 0 ? kSymCap[j] : kNumCap[j];
-    hipError_t e = hipMemsetAsync(counts, 0, sizeof(int) * caps.ncls, st);
-    if (e != hipSuccess) return e;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin, dim3((n + 255) / 256), dim3(256), 0, st, woff, crp, n, kind, caps,
-                       counts, lists);
-    return hipGetLastError();
-}
-
-// ============================================================== SpGEMM: symbolic
-
-template <bool kGlobal>
-__global__ __launch_bounds__(512) void k_symbolic(CsrView A, CsrView B, int addA,
-                                                  const int32_t *__restrict__ lo,
-                                                  const int64_t *__restrict__ woff,
-                                                  uint32_t *__restrict__ bitmaps,
-                                                  int64_t *__restrict__ cnt,
-                                                  const int32_t *__restrict__ list, int nlist,
-                                                  int wpb, int cap_words) {
-    extern __shared__ uint32_t smem_u32[];
-    int wave = threadIdx.x / kWave, lane = lane_id();
-    int64_t idx = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb + wave;
-    if (idx >= nlist) return;
-    int64_t i = list[idx];
-    int64_t w0 = woff[i], W = woff[i + 1] - w0;
-    if (W == 0) {
-        if (lane == 0) cnt[i] = 0;
-        return;
-    }
-    uint32_t *bm = kGlobal ? bitmaps + w0 : smem_u32 + (int64_t)wave * cap_words;
-    for (int64_t w = lane; w < W; w += kWave) bm[w] = 0;
-    phase_fence<kGlobal>();
-    const int base = lo[i];
-    int64_t b = A.rp[i], e = A.rp[i + 1];
-    if (addA) {
-        for (int64_t p = b + lane; p < e; p += kWave) {
-            int d = A.ci[p] - base;
-            atomicOr(&bm[d >> 5], 1u << (d & 31));
-        }
-    }
-    for (int64_t p = b; p < e; p++) {
-        int k = A.ci[p];
-        int64_t q1 = B.rp[k + 1];
-        for (int64_t q = B.rp[k] + lane; q < q1; q += kWave) {
-            int d = B.ci[q] - base;
-            atomicOr(&bm[d >> 5], 1u << (d & 31));
-        }
-    }
-    phase_fence<kGlobal>();
-    long long s = 0;
-    for (int64_t w = lane; w < W; w += kWave) {
-        uint32_t x = bm[w];
-        s += __popc(x);
-        if (!kGlobal) bitmaps[w0 + w] = x;
-    }
-    s = wave_sum_ll(s);
-    if (lane == 0) cnt[i] = s;
-}
-
-hipError_t symbolic(CsrView A, CsrView B, int addA, const int32_t *lo, const int64_t *woff,
-                    uint32_t *bitmaps, int64_t *cnt, const int *host_counts,
-                    const int32_t *lists, int64_t n, hipStream_t st) {
-    for (int c = 0; c < kSymClasses; c++) {
-        int m = host_counts[c];
-        if (m == 0) continue;
-        int wpb = kSymWpb[c];
-        dim3 grid((m + wpb - 1) / wpb), block(wpb * kWave);
-        const int32_t *list = lists + (int64_t)c * n;
-        if (kSymCap[c] > 0) {
-            int capw = kSymCap[c] / 4;
-            hipLaunchKernelGGL(k_symbolic<false>, grid, block, (size_t)wpb * kSymCap[c], st, A, B,
-                               addA, lo, woff, bitmaps, cnt, list, m, wpb, capw);
-        } else {
-            hipLaunchKernelGGL(k_symbolic<true>, grid, block, 0, st, A, B, addA, lo, woff,
-                               bitmaps, cnt, list, m, wpb, 0);
-        }
-    }
-    return hipGetLastError();
-}
-
-// ============================================================== SpGEMM: numeric
-
-// Loads a row's bit map and forms (word, exclusive popcount prefix) pairs.
-__device__ __forceinline__ void load_rank_table(const uint32_t *__restrict__ src, int64_t W,
-                                                uint2 *bp) {
-    unsigned carry = 0;
-    for (int64_t w0 = 0; w0 < W; w0 += kWave) {
-        int64_t w = w0 + lane_id();
-        uint32_t x = w < W ? src[w] : 0u;
-        unsigned pc = __popc(x);
-        unsigned inc = wave_incl_scan(pc);
-        if (w < W) bp[w] = make_uint2(x, carry + inc - pc);
-        carry += __shfl(inc, kWave - 1);
-    }
-}
-
-__device__ __forceinline__ unsigned rank_of(const uint2 *bp, int d) {
-    uint2 e = bp[d >> 5];
-    return e.y + __popc(e.x & ((1u << (d & 31)) - 1u));
-}
-
-template <bool kGlobal>
-__global__ __launch_bounds__(512) void k_numeric(
-    CsrView A, CsrView B, double alphaA, double div, const int32_t *__restrict__ lo,
-    const int64_t *__restrict__ woff, const uint32_t *__restrict__ bitmaps,
-    const int64_t *__restrict__ crp, int32_t *__restrict__ cci, double *__restrict__ cv,
-    double *__restrict__ rowsq, const int32_t *__restrict__ list, int nlist, int wpb,
-    int cap_bytes, char *__restrict__ scratch, const int64_t *__restrict__ scratch_off) {
-    extern __shared__ double smem_f64[];
-    int wave = threadIdx.x / kWave, lane = lane_id();
-    int64_t idx = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb + wave;
-    if (idx >= nlist) return;
-    const int64_t i = list[idx];
-    const int64_t w0 = woff[i], W = woff[i + 1] - w0;
-    const int64_t o = crp[i], c = crp[i + 1] - o;
-    if (c == 0) {
-        if (rowsq && lane == 0) rowsq[i] = 1.0;
-        return;
-    }
-    char *mem = kGlobal ? scratch + scratch_off[i]
-                        : (char *)smem_f64 + (int64_t)wave * cap_bytes;
-    double *acc = (double *)mem;
-    int32_t *stage = (int32_t *)(mem + 8 * c);
-    uint2 *bp = (uint2 *)(mem + align8(12 * c));
-    const int base = lo[i];
-
-    load_rank_table(bitmaps + w0, W, bp);
-    phase_fence<kGlobal>();
-    for (int64_t w = lane; w < W; w += kWave) {
-        uint2 e = bp[w];
-        unsigned x = e.x, r = e.y;
-        while (x) {
-            int bit = __ffs(x) - 1;
-            x &= x - 1;
-            stage[r] = base + 32 * (int)w + bit;
-            acc[r] = 0.0;
-            r++;
-        }
-    }
-    phase_fence<kGlobal>();
-    const int64_t b = A.rp[i], e = A.rp[i + 1];
-    if (alphaA != 0.0) {
-        for (int64_t p = b + lane; p < e; p += kWave) {
-            unsigned r = rank_of(bp, A.ci[p] - base);
-            acc_add<kGlobal>(&acc[r], alphaA * A.v[p]);
-        }
-        phase_fence<kGlobal>();
-    }
-    for (int64_t p = b; p < e; p++) {
-        const int k = A.ci[p];
-        const double a = A.v[p];
-        const int64_t q1 = B.rp[k + 1];
-        for (int64_t q = B.rp[k] + lane; q < q1; q += kWave) {
-            unsigned r = rank_of(bp, B.ci[q] - base);
-            if (kGlobal)
-                atomicAdd(&acc[r], a * B.v[q]);
-            else
-                acc[r] = fma(a, B.v[q], acc[r]);
-        }
-    }
-    phase_fence<kGlobal>();
-    double s = 0.0;
-    bool diag = false;
-    for (int64_t t = lane; t < c; t += kWave) {
-        int col = stage[t];
-        double val = acc[t];
-        if (div != 1.0) val = val / div;
-        cci[o + t] = col;
-        cv[o + t] = val;
-        if (rowsq) {
-            double f = col == i ? val + 1.0 : val;
-            diag |= col == i;
-            s = fma(f, f, s);
-        }
-    }
-    if (rowsq) {
-        s = wave_sum(s);
-        bool any = __ballot(diag) != 0;
-        if (lane == 0) rowsq[i] = any ? s : s + 1.0;
-    }
-}
-
-__global__ void k_numeric_scratch(const int64_t *woff, const int64_t *crp, int64_t n,
-                                  int64_t *bytes) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t W = woff[i + 1] - woff[i], c = crp[i + 1] - crp[i];
-    int64_t need = align8(12 * c) + 8 * W;
-    int64_t small = need <= kNumCap[kNumClasses - 2];
-    bytes[i] = small ? 0 : (need + 255) & ~int64_t(255);
-}
-
-hipError_t numeric_scratch_sizes(const int64_t *woff, const int64_t *crp, int64_t n,
-                                 int64_t *bytes, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_numeric_scratch, dim3((n + 255) / 256), dim3(256), 0, st, woff, crp, n,
-                       bytes);
-    return hipGetLastError();
-}
-
-hipError_t numeric(CsrView A, CsrView B, double alphaA, double div, const int32_t *lo,
-                   const int64_t *woff, const uint32_t *bitmaps, const int64_t *crp, int32_t *cci,
-                   double *cv, double *rowsq, const int *host_counts, const int32_t *lists,
-                   int64_t n, void *scratch, const int64_t *scratch_off, hipStream_t st) {
-    for (int c = 0; c < kNumClasses; c++) {
-        int m = host_counts[c];
-        if (m == 0) continue;
-        int wpb = kNumWpb[c];
-        dim3 grid((m + wpb - 1) / wpb), block(wpb * kWave);
-        const int32_t *list = lists + (int64_t)c * n;
-        if (kNumCap[c] > 0) {
-            hipLaunchKernelGGL(k_numeric<false>, grid, block, (size_t)wpb * kNumCap[c], st, A, B,
-                               alphaA, div, lo, woff, bitmaps, crp, cci, cv, rowsq, list, m, wpb,
-                               kNumCap[c], (char *)nullptr, (const int64_t *)nullptr);
-        } else {
-            hipLaunchKernelGGL(k_numeric<true>, grid, block, 0, st, A, B, alphaA, div, lo, woff,
-                               bitmaps, crp, cci, cv, rowsq, list, m, wpb, 0, (char *)scratch,
-                               scratch_off);
-        }
-    }
-    return hipGetLastError();
-}
-
 // ============================================================== filter (Algorithm 4.1)
 
 __global__ void k_filter_init(FilterCtl *c, double eg_scale, const double *norm2, double er,
@@ -693,9 +343,15 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 // Per row: entries kept (|v| > theta); with addI the diagonal becomes 1 + v
 // (dropped if exactly 0) or is inserted as 1.
 __global__ void k_count_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
-                             const FilterCtl *c, int addI, int64_t *cnt) {
+                             const FilterCtl *c, int addI, int64_t *cnt,
+                             const int32_t *row_inst, const int *inst_addI) {
     int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (i >= n) return;
+    if (row_inst) {
+        const int k = row_inst[i];
+        c += k;
+        addI = inst_addI ? inst_addI[k] : addI;
+    }
     const double theta = c->theta;
     long long k = 0;
     int dstate = 0;   // 0 absent/dropped, 1 kept, 2 kept but 1 + v == 0
@@ -712,9 +368,14 @@ __global__ void k_count_kept(const int64_t *crp, const int32_t *cci, const doubl
 
 __global__ void k_write_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
                              const FilterCtl *c, int addI, const int64_t *orp, int32_t *oci,
-                             double *ov) {
+                             double *ov, const int32_t *row_inst, const int *inst_addI) {
     int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (i >= n) return;
+    if (row_inst) {
+        const int k = row_inst[i];
+        c += k;
+        addI = inst_addI ? inst_addI[k] : addI;
+    }
     const double theta = c->theta;
     const int64_t b = crp[i], e = crp[i + 1];
     // diagonal state (see k_count_kept)
@@ -776,21 +437,22 @@ __global__ void k_write_kept(const int64_t *crp, const int32_t *cci, const doubl
 }
 
 hipError_t count_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
-                      const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st) {
+                      const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st,
+                      const int32_t *row_inst, const int *inst_addI) {
     if (n == 0) return hipSuccess;
     int wpb = 4;
     hipLaunchKernelGGL(k_count_kept, dim3((n + wpb - 1) / wpb), dim3(wpb * kWave), 0, st, crp,
-                       cci, cv, n, c, addI, cnt);
+                       cci, cv, n, c, addI, cnt, row_inst, inst_addI);
     return hipGetLastError();
 }
 
 hipError_t write_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
                       const FilterCtl *c, int addI, const int64_t *orp, int32_t *oci, double *ov,
-                      hipStream_t st) {
+                      hipStream_t st, const int32_t *row_inst, const int *inst_addI) {
     if (n == 0) return hipSuccess;
     int wpb = 4;
     hipLaunchKernelGGL(k_write_kept, dim3((n + wpb - 1) / wpb), dim3(wpb * kWave), 0, st, crp,
-                       cci, cv, n, c, addI, orp, oci, ov);
+                       cci, cv, n, c, addI, orp, oci, ov, row_inst, inst_addI);
     return hipGetLastError();
 }
 
@@ -959,201 +621,6 @@ hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double 
     hipLaunchKernelGGL(k_colfill, g, b, 0, st, A, fillpos, tci, tv);
     hipLaunchKernelGGL(k_sort_rows, dim3(n), dim3(kSortBlock), 0, st, trp, n, tci, tv, tmp_ci,
                        tmp_v);
-    return hipGetLastError();
-}
-
-// ============================================================== masked products
-// One wave per mask row; the mask row's columns form the rank table, partial
-// products whose column is not in the mask are skipped.
-
-template <bool kGlobal>
-__global__ __launch_bounds__(512) void k_masked(
-    CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2, double div,
-    double *__restrict__ out, const int32_t *__restrict__ list, int nlist, int wpb,
-    int cap_bytes, char *__restrict__ scratch, const int64_t *__restrict__ scratch_off) {
-    extern __shared__ double smem_f64[];
-    int wave = threadIdx.x / kWave, lane = lane_id();
-    int64_t idx = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb + wave;
-    if (idx >= nlist) return;
-    const int64_t i = list[idx];
-    const int64_t o = M.rp[i], c = M.rp[i + 1] - o;
-    if (c == 0) return;
-    const int lo = M.ci[o] & ~31;
-    const int64_t W = ((M.ci[o + c - 1] - lo) >> 5) + 1;
-    char *mem = kGlobal ? scratch + scratch_off[i] : (char *)smem_f64 + (int64_t)wave * cap_bytes;
-    double *acc = (double *)mem;
-    uint2 *bp = (uint2 *)(mem + 8 * c);
-    for (int64_t w = lane; w < W; w += kWave) bp[w] = make_uint2(0u, 0u);
-    for (int64_t t = lane; t < c; t += kWave) acc[t] = 0.0;
-    phase_fence<kGlobal>();
-    for (int64_t t = lane; t < c; t += kWave) {
-        int d = M.ci[o + t] - lo;
-        atomicOr(&bp[d >> 5].x, 1u << (d & 31));
-    }
-    phase_fence<kGlobal>();
-    {   // prefix counts
-        unsigned carry = 0;
-        for (int64_t w0 = 0; w0 < W; w0 += kWave) {
-            int64_t w = w0 + lane;
-            uint32_t x = w < W ? bp[w].x : 0u;
-            unsigned pc = __popc(x);
-            unsigned inc = wave_incl_scan(pc);
-            if (w < W) bp[w].y = carry + inc - pc;
-            carry += __shfl(inc, kWave - 1);
-        }
-    }
-    phase_fence<kGlobal>();
-    const int hi = lo + 32 * (int)W;
-    const MaskTerm ts[2] = {t1, t2};
-    for (int u = 0; u < 2; u++) {
-        const MaskTerm &t = ts[u];
-        if (t.A.n == 0 || t.alpha == 0.0) continue;
-        const int64_t b = t.A.rp[i], e = t.A.rp[i + 1];
-        for (int64_t p = b; p < e; p++) {
-            const int k = t.A.ci[p];
-            const double a = t.alpha * t.A.v[p];
-            const int64_t q1 = t.B.rp[k + 1];
-            for (int64_t q = t.B.rp[k] + lane; q < q1; q += kWave) {
-                int col = t.B.ci[q];
-                if (col < lo || col >= hi) continue;
-                int d = col - lo;
-                uint2 e2 = bp[d >> 5];
-                unsigned bit = 1u << (d & 31);
-                if (!(e2.x & bit)) continue;
-                unsigned r = e2.y + __popc(e2.x & (bit - 1u));
-                if (kGlobal)
-                    atomicAdd(&acc[r], a * t.B.v[q]);
-                else
-                    acc[r] = fma(a, t.B.v[q], acc[r]);
-            }
-        }
-    }
-    phase_fence<kGlobal>();
-    if (D.n != 0 && gamma != 0.0) {
-        // direct term, added after the products are divided by div
-        for (int64_t s = lane; s < c; s += kWave) {
-            double val = acc[s];
-            if (div != 1.0) val = val / div;
-            acc[s] = val;
-        }
-        phase_fence<kGlobal>();
-        const int64_t b = D.rp[i], e = D.rp[i + 1];
-        for (int64_t p = b + lane; p < e; p += kWave) {
-            int col = D.ci[p];
-            if (col < lo || col >= hi) continue;
-            int d = col - lo;
-            uint2 e2 = bp[d >> 5];
-            unsigned bit = 1u << (d & 31);
-            if (!(e2.x & bit)) continue;
-            unsigned r = e2.y + __popc(e2.x & (bit - 1u));
-            acc_add<kGlobal>(&acc[r], gamma * D.v[p]);
-        }
-        phase_fence<kGlobal>();
-        for (int64_t s = lane; s < c; s += kWave) out[o + s] = acc[s];
-    } else {
-        for (int64_t s = lane; s < c; s += kWave) {
-            double val = acc[s];
-            if (div != 1.0) val = val / div;
-            out[o + s] = val;
-        }
-    }
-}
-
-__global__ void k_masked_bytes(CsrView M, int64_t *woff_like, int64_t *cnt_like) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M.n) return;
-    int64_t o = M.rp[i], c = M.rp[i + 1] - o;
-    int64_t W = c ? ((M.ci[o + c - 1] - (M.ci[o] & ~31)) >> 5) + 1 : 0;
-    woff_like[i] = W;
-    cnt_like[i] = c;
-}
-
-__global__ void k_masked_scratch(const int64_t *W, const int64_t *C, int64_t n, int64_t *bytes) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t need = 8 * C[i] + 8 * W[i];
-    bytes[i] = need <= kNumCap[kNumClasses - 2] ? 0 : (need + 255) & ~int64_t(255);
-}
-
-__global__ void k_bin_direct(const int64_t *W, const int64_t *C, int64_t n, Caps caps,
-                             int *counts, int32_t *lists) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t bytes = 8 * C[i] + 8 * W[i];
-    int cls = caps.ncls - 1;
-    for (int j = 0; j < caps.ncls - 1; j++)
-        if (bytes <= caps.cap[j]) {
-            cls = j;
-            break;
-        }
-    int pos = atomicAdd(&counts[cls], 1);
-    lists[(int64_t)cls * n + pos] = (int32_t)i;
-}
-
-// scratch layout (bytes): W[n] int64 | C[n] int64 | sb[n+1] int64 | off[n+1] int64 |
-// counts[8] int | lists[kNumClasses*n] int32 | scan tmp | global rows' memory
-size_t masked_meta_bytes(int64_t n) {
-    size_t b = sizeof(int64_t) * (4 * (size_t)n + 2) + 8 * sizeof(int) +
-               sizeof(int32_t) * (size_t)kNumClasses * n;
-    b = (b + 255) & ~(size_t)255;
-    b += (scan_tmp_bytes(n) + 255) & ~(size_t)255;
-    return b + 256;
-}
-
-hipError_t masked_products(CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2,
-                           double div, double *out, void *scratch, size_t scratch_bytes,
-                           size_t *needed, hipStream_t st) {
-    const int64_t n = M.n;
-    if (n == 0) return hipSuccess;
-    char *s = (char *)scratch;
-    if (masked_meta_bytes(n) > scratch_bytes) {
-        if (needed) *needed = masked_meta_bytes(n);
-        return hipErrorOutOfMemory;
-    }
-    int64_t *W = (int64_t *)s;
-    int64_t *C = W + n;
-    int64_t *sb = C + n;
-    int64_t *off = sb + n + 1;
-    int *counts = (int *)(off + n + 1);
-    int32_t *lists = (int32_t *)(counts + 8);
-    char *scan_tmp = (char *)(lists + (int64_t)kNumClasses * n);
-    scan_tmp = (char *)(((uintptr_t)scan_tmp + 255) & ~(uintptr_t)255);
-    char *glob = scan_tmp + ((scan_tmp_bytes(n) + 255) & ~(size_t)255);
-    size_t used = (size_t)(glob - s);
-    if (used > scratch_bytes) return hipErrorInvalidValue;
-    dim3 g((n + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_masked_bytes, g, b, 0, st, M, W, C);
-    hipLaunchKernelGGL(k_masked_scratch, g, b, 0, st, W, C, n, sb);
-    hipError_t e = scan_i64(sb, off, n, scan_tmp, scan_tmp_bytes(n), st);
-    if (e != hipSuccess) return e;
-    Caps caps;
-    caps.ncls = kNumClasses;
-    for (int j = 0; j < kNumClasses; j++) caps.cap[j] = kNumCap[j];
-    e = hipMemsetAsync(counts, 0, sizeof(int) * 8, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_direct, g, b, 0, st, W, C, n, caps, counts, lists);
-    int hc[8];
-    int64_t gbytes = 0;
-    e = hipMemcpyAsync(hc, counts, sizeof(int) * kNumClasses, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&gbytes, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    if (needed) *needed = used + (size_t)gbytes;
-    if (used + (size_t)gbytes > scratch_bytes) return hipErrorOutOfMemory;
-    for (int c = 0; c < kNumClasses; c++) {
-        int m = hc[c];
-        if (m == 0) continue;
-        int wpb = kNumWpb[c];
-        dim3 grid((m + wpb - 1) / wpb), block(wpb * kWave);
-        const int32_t *list = lists + (int64_t)c * n;
-        if (kNumCap[c] > 0)
-            hipLaunchKernelGGL(k_masked<false>, grid, block, (size_t)wpb * kNumCap[c], st, M, D,
-                               gamma, t1, t2, div, out, list, m, wpb, kNumCap[c], (char *)nullptr,
-                               (const int64_t *)nullptr);
-        else
-            hipLaunchKernelGGL(k_masked<true>, grid, block, 0, st, M, D, gamma, t1, t2, div, out,
-                               list, m, wpb, 0, glob, off);
-    }
     return hipGetLastError();
 }
 

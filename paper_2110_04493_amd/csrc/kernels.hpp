@@ -9,7 +9,7 @@ namespace xpm {
 // Number of row classes of the bitmap and accumulator kernels (the last one
 // keeps its working set in global memory).
 constexpr int kSymClasses = 5;
-constexpr int kNumClasses = 7;
+constexpr int kNumClasses = 9;
 
 // Per-wave LDS capacity (bytes) of each class; the last class is global.
 extern const int kSymCap[kSymClasses];
@@ -84,11 +84,52 @@ hipError_t filter_init_theta(FilterCtl *c, double theta, hipStream_t st);
 hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
                        double *part, int nparts, hipStream_t st);
 // Kept counts per row (|v| > theta); with addI the identity is added (E = I + T).
+// With row_inst, row i uses controller c[row_inst[i]] and (if inst_addI is
+// given) inst_addI[row_inst[i]] in place of addI.
 hipError_t count_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
-                      const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st);
+                      const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st,
+                      const int32_t *row_inst = nullptr, const int *inst_addI = nullptr);
 hipError_t write_kept(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
                       const FilterCtl *c, int addI, const int64_t *orp, int32_t *oci, double *ov,
-                      hipStream_t st);
+                      hipStream_t st, const int32_t *row_inst = nullptr,
+                      const int *inst_addI = nullptr);
+
+// ------------------------------------------------------------- batched
+// Instance k of a block-diagonal stack owns rows [row_off[k], row_off[k+1]).
+hipError_t fill_row_inst(const int64_t *row_off, int count, int64_t n, int32_t *row_inst,
+                         hipStream_t st);
+// Per-instance controller set-up: mode[k] 0 = search with budget
+// eg_scale[k] * sqrt(norm2[k]) (norm2 may be NULL: budget eg_scale[k]),
+// 1 = keep everything, 2 = drop everything.
+hipError_t filter_init_batched(FilterCtl *c, int count, const double *eg_scale,
+                               const double *norm2, const int *mode, double er, int maxit,
+                               hipStream_t st);
+// One Algorithm 4.1 pass for every instance whose controller is not done;
+// instance k's candidate values are cv[crp[row_off[k]] .. crp[row_off[k+1]]).
+hipError_t filter_pass_batched(const double *cv, const int64_t *crp, const int64_t *row_off,
+                               int count, FilterCtl *c, double *part, int blocks_per_inst,
+                               hipStream_t st);
+// out[k] = sum of v over rows [row_off[k], row_off[k+1]) (fixed order).
+hipError_t segment_sums(const double *v, const int64_t *row_off, int count, double *out,
+                        hipStream_t st);
+// out[k] = rp[row_off[k]] for k = 0..count.
+hipError_t gather_offsets(const int64_t *rp, const int64_t *row_off, int count, int64_t *out,
+                          hipStream_t st);
+// Stacks instance CSRs (descriptor table on the device) into one
+// block-diagonal CSR; values scaled by 2^-shift[k].
+struct InstDesc {
+    const int64_t *rp;
+    const int32_t *ci;
+    const double *v;
+    int64_t n, row_off, nnz_off;
+    int shift;
+};
+hipError_t stack_instances(const InstDesc *desc, int count, const int64_t *row_off, int64_t n,
+                           int64_t *rp, int32_t *ci, double *v, hipStream_t st);
+// Copies rows [r0, r0 + m) of a CSR into a standalone CSR with columns
+// shifted by -r0.
+hipError_t extract_block(const int64_t *rp, const int32_t *ci, const double *v, int64_t r0,
+                         int64_t m, int64_t *orp, int32_t *oci, double *ov, hipStream_t st);
 
 // ------------------------------------------------------------- sparse add
 // C = A + B with exact zeros removed (two passes: count then write).

