@@ -1,0 +1,531 @@
+// Squaring product on 16 x 16 dense tiles with FP64 matrix cores (gfx950).
+//
+// Once the filtered iterate's band has filled in, T_{i-1} is held as
+// block-sparse rows of dense 16 x 16 tiles and T~ = 2T + T*T is formed tile by
+// tile with v_mfma_f64_16x16x4f64: C_IJ = (2 I) T_IJ + sum_K T_IK T_KJ, four
+// matrix instructions per tile product.  The candidate stays in tile form for
+// the filter (Algorithm 4.1 runs on the flat tile values; padding and
+// structural zeros add nothing to any sum), and the compaction writes the kept
+// entries straight back to CSR.
+//
+// Lane layouts of v_mfma_f64_16x16x4f64 (one double per lane for A and B,
+// four for the accumulator): A(i, k) comes from lane i + 16k, B(k, j) from
+// lane j + 16k, and the result (i, j) lands in lane j + 16 (i mod 4), register
+// i / 4.  Tiles are stored so that each lane's four operands of a 16-deep
+// product are 32 contiguous bytes:
+//   A layout: (r, c) at ((c mod 4) 16 + r) 4 + c / 4
+//   B layout: (r, c) at ((r mod 4) 16 + c) 4 + r / 4   (= accumulator layout)
+//
+// Block rows carry a bit map of their block columns (origin a multiple of
+// 32 block columns) with prefix counts, so the tile of block column J is
+// found in O(1) by rank, as in the scalar product.
+#include <stdlib.h>
+
+#include "kernels.hpp"
+
+namespace xpm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 16;
+constexpr int kTileElems = kTile * kTile;
+
+__device__ __forceinline__ int offA(int r, int c) { return (((c & 3) << 4) + r) * 4 + (c >> 2); }
+__device__ __forceinline__ int offB(int r, int c) { return (((r & 3) << 4) + c) * 4 + (r >> 2); }
+
+__device__ __forceinline__ void wfence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ----------------------------------------------------------------- T -> tiles
+
+// Per block row: origin (block column, multiple of 32) and bit-map words.
+__global__ void k_bsr_bounds(CsrView T, int64_t nb, int32_t *lo, int64_t *words) {
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= nb) return;
+    const int64_t r0 = I * kTile, r1 = min<int64_t>(r0 + kTile, T.n);
+    int mn = INT32_MAX, mx = -1;
+    for (int64_t i = r0; i < r1; ++i) {
+        const int64_t b = T.rp[i], e = T.rp[i + 1];
+        if (e > b && lane_id() == 0) {
+            mn = min(mn, T.ci[b] >> 4);
+            mx = max(mx, T.ci[e - 1] >> 4);
+        }
+    }
+    if (lane_id() == 0) {
+        if (mx < 0) {
+            lo[I] = 0;
+            words[I] = 0;
+        } else {
+            const int l = mn & ~31;
+            lo[I] = l;
+            words[I] = ((mx - l) >> 5) + 1;
+        }
+    }
+}
+
+// Bit map of the block columns of each block row, as (word, prefix) pairs,
+// and the tile count.  The bit map is built in LDS (at most n / 512 words).
+__global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const int32_t *lo,
+                                                   const int64_t *woff, uint2 *rt, int64_t *cnt) {
+    extern __shared__ uint32_t bm[];
+    const int64_t I = blockIdx.x;
+    if (I >= nb) return;
+    const int lane = lane_id();
+    const int64_t w0 = woff[I], W = woff[I + 1] - w0;
+    if (W == 0) {
+        if (lane == 0) cnt[I] = 0;
+        return;
+    }
+    for (int64_t w = lane; w < W; w += kWave) bm[w] = 0;
+    wfence();
+    const int base = lo[I];
+    const int64_t r1 = min<int64_t>(I * kTile + kTile, T.n);
+    for (int64_t i = I * kTile; i < r1; ++i)
+        for (int64_t p = T.rp[i] + lane; p < T.rp[i + 1]; p += kWave) {
+            const int d = (T.ci[p] >> 4) - base;
+            atomicOr(&bm[d >> 5], 1u << (d & 31));
+        }
+    wfence();
+    unsigned carry = 0;
+    for (int64_t b0 = 0; b0 < W; b0 += kWave) {
+        const int64_t w = b0 + lane;
+        const uint32_t x = w < W ? bm[w] : 0u;
+        const unsigned pc = __popc(x);
+        const unsigned inc = wave_incl_scan(pc);
+        if (w < W) rt[w0 + w] = make_uint2(x, carry + inc - pc);
+        carry += __shfl(inc, kWave - 1);
+    }
+    if (lane == 0) cnt[I] = carry;
+}
+
+// Tile index of block column J in block row K, or -1.
+__device__ __forceinline__ int64_t tile_of(const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                                           const int64_t *tb, int64_t K, int J) {
+    const int d = J - lo[K];
+    const int64_t w0 = woff[K];
+    if (d < 0 || (d >> 5) >= woff[K + 1] - w0) return -1;
+    const uint2 e = rt[w0 + (d >> 5)];
+    const uint32_t bit = 1u << (d & 31);
+    if (!(e.x & bit)) return -1;
+    return tb[K] + e.y + __popc(e.x & (bit - 1u));
+}
+
+// Scatters the entries of T into the zeroed tiles, in both operand layouts.
+__global__ void k_bsr_fill(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff,
+                           const uint2 *rt, const int64_t *tb, double *tA, double *tB) {
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= nb) return;
+    const int64_t r1 = min<int64_t>(I * kTile + kTile, T.n);
+    for (int64_t i = I * kTile; i < r1; ++i) {
+        const int r = (int)(i & 15);
+        for (int64_t p = T.rp[i] + lane_id(); p < T.rp[i + 1]; p += kWave) {
+            const int j = T.ci[p];
+            const int64_t t = tile_of(lo, woff, rt, tb, I, j >> 4);
+            const double v = T.v[p];
+            tA[t * kTileElems + offA(r, j & 15)] = v;
+            tB[t * kTileElems + offB(r, j & 15)] = v;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- C pattern
+
+// Block-column range of C's block row I: the union of T's block rows K for
+// the block columns K of block row I (and block row I itself, the 2T term).
+__global__ void k_bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff,
+                              const uint2 *rt, const int64_t *tb, int32_t *clo,
+                              int64_t *cwords) {
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= nb) return;
+    const int lane = lane_id();
+    const int64_t W = woff[I + 1] - woff[I];
+    int mn = INT32_MAX, mx = -1;
+    if (W > 0) {
+        mn = lo[I];
+        mx = lo[I] + 32 * (int)W - 1;
+    }
+    // every set bit of block row I names a block row K
+    for (int64_t w = lane; w < W; w += kWave) {
+        uint32_t x = rt[woff[I] + w].x;
+        while (x) {
+            const int K = lo[I] + 32 * (int)w + __ffs(x) - 1;
+            x &= x - 1;
+            const int64_t WK = woff[K + 1] - woff[K];
+            if (WK > 0) {
+                mn = min(mn, lo[K]);
+                mx = max(mx, lo[K] + 32 * (int)WK - 1);
+            }
+        }
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        if (mx < 0) {
+            clo[I] = 0;
+            cwords[I] = 0;
+        } else {
+            clo[I] = mn;
+            cwords[I] = ((mx - mn) >> 5) + 1;
+        }
+    }
+}
+
+// C's block-row bit maps (word-aligned ORs of T's bit maps) and tile counts;
+// with ccols != NULL also the sorted block-column list of every C block row.
+__global__ __launch_bounds__(64) void k_bsr_cpattern(int64_t nb, const int32_t *lo,
+                                                     const int64_t *woff, const uint2 *rt,
+                                                     const int32_t *clo, const int64_t *cwoff,
+                                                     int64_t *ccnt, const int64_t *ctb,
+                                                     int32_t *ccols) {
+    extern __shared__ uint32_t bm[];
+    const int64_t I = blockIdx.x;
+    if (I >= nb) return;
+    const int lane = lane_id();
+    const int64_t CW = cwoff[I + 1] - cwoff[I];
+    if (CW == 0) {
+        if (lane == 0 && !ccols) ccnt[I] = 0;
+        return;
+    }
+    for (int64_t w = lane; w < CW; w += kWave) bm[w] = 0;
+    wfence();
+    const int cbase = clo[I];
+    auto or_row = [&](int64_t K) {
+        const int64_t WK = woff[K + 1] - woff[K];
+        const int sh = (lo[K] - cbase) >> 5;   // both origins are multiples of 32
+        for (int64_t w = lane; w < WK; w += kWave) {
+            const uint32_t x = rt[woff[K] + w].x;
+            if (x) atomicOr(&bm[sh + w], x);
+        }
+    };
+    or_row(I);
+    const int64_t W = woff[I + 1] - woff[I];
+    for (int64_t w = 0; w < W; ++w) {
+        uint32_t x = rt[woff[I] + w].x;
+        while (x) {
+            const int K = lo[I] + 32 * (int)w + __ffs(x) - 1;
+            x &= x - 1;
+            or_row(K);
+        }
+    }
+    wfence();
+    unsigned carry = 0;
+    for (int64_t b0 = 0; b0 < CW; b0 += kWave) {
+        const int64_t w = b0 + lane;
+        uint32_t x = w < CW ? bm[w] : 0u;
+        const unsigned pc = __popc(x);
+        const unsigned inc = wave_incl_scan(pc);
+        if (ccols && w < CW) {
+            unsigned r = carry + inc - pc;
+            while (x) {
+                ccols[ctb[I] + r] = cbase + 32 * (int)w + __ffs(x) - 1;
+                x &= x - 1;
+                ++r;
+            }
+        }
+        carry += __shfl(inc, kWave - 1);
+    }
+    if (lane == 0 && !ccols) ccnt[I] = carry;
+}
+
+__global__ void k_bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, int group) {
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nb) gcnt[I] = (ccnt[I] + group - 1) / group;
+}
+
+// ----------------------------------------------------------------- product
+
+// One wave per work item (block row I, group of up to kGroup consecutive
+// tiles of C's block row I).  For every block column K of T's block row I
+// (ascending) the tiles T_KJ of the group's block columns are found by rank;
+// when at least one exists, T_IK is loaded once (A layout) and each T_KJ
+// (B layout) is multiplied in with four 16x16x4 instructions.
+template <int kGroup>
+__global__ __launch_bounds__(256) void k_bsr_numeric(
+    int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
+    const uint2 *__restrict__ rt, const int64_t *__restrict__ tb, const double *__restrict__ tA,
+    const double *__restrict__ tB, const int64_t *__restrict__ gofs,
+    const int64_t *__restrict__ ctb, const int64_t *__restrict__ ccnt,
+    const int32_t *__restrict__ ccols, double *__restrict__ ctiles, int64_t nwork, int remap) {
+    const int lane = lane_id();
+    const unsigned blk = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int64_t w = (int64_t)blk * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (w >= nwork) return;
+    int64_t lo_i = 0, hi_i = nb - 1;   // last I with gofs[I] <= w
+    while (lo_i < hi_i) {
+        const int64_t mid = (lo_i + hi_i + 1) >> 1;
+        if (gofs[mid] <= w) lo_i = mid; else hi_i = mid - 1;
+    }
+    const int64_t I = lo_i;
+    const int64_t g0 = (w - gofs[I]) * kGroup;
+    const int ng = (int)min<int64_t>(kGroup, ccnt[I] - g0);
+    int J[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) J[t] = t < ng ? ccols[ctb[I] + g0 + t] : -1;
+    d4 acc[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    // 2 T_IJ = (2 I_16) T_IJ: lane l's A operand of slice kk is 2 on the
+    // diagonal (row l % 16 == column 4 kk + l / 16).
+    {
+        double two[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) two[kk] = (lane & 15) == 4 * kk + (lane >> 4) ? 2.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            if (t >= ng) break;
+            const int64_t tt = tile_of(lo, woff, rt, tb, I, J[t]);
+            if (tt < 0) continue;
+            const d4 b = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(two[kk], b[kk], acc[t], 0, 0, 0);
+        }
+    }
+    const int64_t W = woff[I + 1] - woff[I];
+    const int jlo = J[0], jhi = J[ng - 1];
+    for (int64_t ww = 0; ww < W; ++ww) {
+        uint32_t x = rt[woff[I] + ww].x;
+        while (x) {
+            const int K = lo[I] + 32 * (int)ww + __ffs(x) - 1;
+            x &= x - 1;
+            const int64_t WK = woff[K + 1] - woff[K];
+            if (WK == 0 || jhi < lo[K] || jlo >= lo[K] + 32 * (int)WK) continue;
+            int64_t tk[kGroup];
+            bool any = false;
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                tk[t] = t < ng ? tile_of(lo, woff, rt, tb, K, J[t]) : -1;
+                any = any || tk[t] >= 0;
+            }
+            if (!any) continue;
+            const int64_t ta = tb[I] + rt[woff[I] + ww].y + __popc(rt[woff[I] + ww].x & ((1u << (K - lo[I] - 32 * (int)ww)) - 1u));
+            const d4 a = *(const d4 *)(tA + ta * kTileElems + 4 * lane);
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                if (tk[t] < 0) continue;
+                const d4 b = *(const d4 *)(tB + tk[t] * kTileElems + 4 * lane);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t)
+        if (t < ng) *(d4 *)(ctiles + (ctb[I] + g0 + t) * kTileElems + 4 * lane) = acc[t];
+}
+
+// ----------------------------------------------------------------- norm, compaction
+
+// Per block row: sum over its candidate slots of (c_ij + delta_ij)^2 for the
+// rows below n, plus 1 for each such row whose diagonal slot is absent; and
+// the count of nonzero slots.
+__global__ void k_bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
+                           const int32_t *ccols, const double *ctiles, double *bsq,
+                           int64_t *bnz) {
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= nb) return;
+    const int lane = lane_id();
+    const int rows = (int)min<int64_t>(kTile, n - I * kTile);
+    double s = 0.0;
+    long long nz = 0;
+    bool diag = false;
+    for (int64_t t = 0; t < ccnt[I]; ++t) {
+        const int64_t tt = ctb[I] + t;
+        const bool dtile = ccols[tt] == (int)I;
+        diag |= dtile;
+        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
+        // lane holds (i, j) = (4 r + lane / 16, lane % 16), r = 0..3
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * r + (lane >> 4), j = lane & 15;
+            if (i >= rows) continue;
+            const double f = dtile && i == j ? v[r] + 1.0 : v[r];
+            s = fma(f, f, s);
+            nz += v[r] != 0.0;
+        }
+    }
+    s = wave_sum(s);
+    nz = wave_sum_ll(nz);
+    if (lane == 0) {
+        bsq[I] = diag ? s : s + rows;
+        bnz[I] = nz;
+    }
+}
+
+// Kept entries (|v| > theta, column < n) of row i = 16 I + r: the lanes take
+// four tiles at a time, sixteen columns each, so entries come in column order.
+__global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
+                            const int32_t *ccols, const double *ctiles, const FilterCtl *c,
+                            int64_t *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const int lane = lane_id();
+    const int64_t I = i >> 4;
+    const int r = (int)(i & 15);
+    const double theta = c->theta;
+    long long k = 0;
+    for (int64_t t0 = 0; t0 < ccnt[I]; t0 += 4) {
+        const int64_t t = t0 + (lane >> 4);
+        if (t < ccnt[I]) {
+            const int64_t tt = ctb[I] + t;
+            const int col = 16 * ccols[tt] + (lane & 15);
+            const double v = ctiles[tt * kTileElems + offB(r, lane & 15)];
+            k += col < n && fabs(v) > theta;
+        }
+    }
+    k = wave_sum_ll(k);
+    if (lane == 0) cnt[i] = k;
+}
+
+__global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
+                            const int32_t *ccols, const double *ctiles, const FilterCtl *c,
+                            const int64_t *orp, int32_t *oci, double *ov) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const int lane = lane_id();
+    const int64_t I = i >> 4;
+    const int r = (int)(i & 15);
+    const double theta = c->theta;
+    int64_t out = orp[i];
+    for (int64_t t0 = 0; t0 < ccnt[I]; t0 += 4) {
+        const int64_t t = t0 + (lane >> 4);
+        bool keep = false;
+        int col = 0;
+        double v = 0.0;
+        if (t < ccnt[I]) {
+            const int64_t tt = ctb[I] + t;
+            col = 16 * ccols[tt] + (lane & 15);
+            v = ctiles[tt * kTileElems + offB(r, lane & 15)];
+            keep = col < n && fabs(v) > theta;
+        }
+        const unsigned long long km = __ballot(keep);
+        if (keep) {
+            const int64_t my = out + __popcll(km & ((1ull << lane) - 1ull));
+            oci[my] = col;
+            ov[my] = v;
+        }
+        out += __popcll(km);
+    }
+}
+
+// ----------------------------------------------------------------- host wrappers
+
+size_t bsr_lds_words(int64_t n) { return (size_t)((n + 15) / 16 + 31) / 32 + 2; }
+
+hipError_t bsr_bounds(CsrView T, int64_t nb, int32_t *lo, int64_t *words, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_bounds, dim3((nb + 3) / 4), dim3(256), 0, st, T, nb, lo, words);
+    return hipGetLastError();
+}
+
+hipError_t bsr_bitmap(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, uint2 *rt,
+                      int64_t *cnt, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_bitmap, dim3(nb), dim3(64), bsr_lds_words(T.n) * 4, st, T, nb, lo,
+                       woff, rt, cnt);
+    return hipGetLastError();
+}
+
+hipError_t bsr_fill(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                    const int64_t *tb, double *tA, double *tB, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_fill, dim3((nb + 3) / 4), dim3(256), 0, st, T, nb, lo, woff, rt, tb,
+                       tA, tB);
+    return hipGetLastError();
+}
+
+hipError_t bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                       const int64_t *tb, int32_t *clo, int64_t *cwords, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_cbounds, dim3((nb + 3) / 4), dim3(256), 0, st, nb, lo, woff, rt, tb,
+                       clo, cwords);
+    return hipGetLastError();
+}
+
+hipError_t bsr_cpattern(int64_t n, int64_t nb, const int32_t *lo, const int64_t *woff,
+                        const uint2 *rt, const int32_t *clo, const int64_t *cwoff, int64_t *ccnt,
+                        const int64_t *ctb, int32_t *ccols, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_cpattern, dim3(nb), dim3(64), bsr_lds_words(n) * 4, st, nb, lo,
+                       woff, rt, clo, cwoff, ccnt, ctb, ccols);
+    return hipGetLastError();
+}
+
+// Output tiles per work item (4, 8 or 16; EXPM_BSR_GROUP) and the block
+// mapping of the product (default 0: hardware round-robin over the XCDs, so
+// the chip works on one band of block rows whose tiles stay in the shared
+// last-level cache; EXPM_BSR_REMAP=1: contiguous work-item ranges per XCD).
+// Measured on MI355X at n = 90,000: 4 tiles and round-robin are fastest
+// (larger groups reuse A tiles but lose occupancy).
+static int bsr_group() {
+    static const int g = [] {
+        const char *e = getenv("EXPM_BSR_GROUP");
+        const int v = e ? atoi(e) : 4;
+        return v == 8 || v == 16 ? v : 4;
+    }();
+    return g;
+}
+
+hipError_t bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_groups, dim3((nb + 255) / 256), dim3(256), 0, st, ccnt, nb, gcnt,
+                       bsr_group());
+    return hipGetLastError();
+}
+
+hipError_t bsr_numeric(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                       const int64_t *tb, const double *tA, const double *tB, const int64_t *gofs,
+                       const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                       double *ctiles, int64_t nwork, hipStream_t st) {
+    if (nwork == 0) return hipSuccess;
+    static const int remap = [] {
+        const char *e = getenv("EXPM_BSR_REMAP");
+        return e && e[0] == '1' ? 1 : 0;
+    }();
+    const dim3 grid((nwork + 3) / 4), block(256);
+    switch (bsr_group()) {
+    case 4:
+        hipLaunchKernelGGL(k_bsr_numeric<4>, grid, block, 0, st, nb, lo, woff, rt, tb, tA, tB,
+                           gofs, ctb, ccnt, ccols, ctiles, nwork, remap);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_bsr_numeric<16>, grid, block, 0, st, nb, lo, woff, rt, tb, tA, tB,
+                           gofs, ctb, ccnt, ccols, ctiles, nwork, remap);
+        break;
+    default:
+        hipLaunchKernelGGL(k_bsr_numeric<8>, grid, block, 0, st, nb, lo, woff, rt, tb, tA, tB,
+                           gofs, ctb, ccnt, ccols, ctiles, nwork, remap);
+    }
+    return hipGetLastError();
+}
+
+hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
+                    const int32_t *ccols, const double *ctiles, double *bsq, int64_t *bnz,
+                    hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_norm, dim3((nb + 3) / 4), dim3(256), 0, st, n, nb, ctb, ccnt, ccols,
+                       ctiles, bsq, bnz);
+    return hipGetLastError();
+}
+
+hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                     const double *ctiles, const FilterCtl *c, int64_t *cnt, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_count, dim3((n + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
+                       ctiles, c, cnt);
+    return hipGetLastError();
+}
+
+hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                     const double *ctiles, const FilterCtl *c, const int64_t *orp, int32_t *oci,
+                     double *ov, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_write, dim3((n + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
+                       ctiles, c, orp, oci, ov);
+    return hipGetLastError();
+}
+
+}  // namespace xpm

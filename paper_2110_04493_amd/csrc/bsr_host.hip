@@ -1,0 +1,194 @@
+// Host driver of the 16 x 16 tile squaring step (kernels in bsr.hip).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "plan.hpp"
+
+namespace xpm {
+namespace host {
+
+// Builds T's tile pattern; returns the tile count and T's fill (stored
+// entries over tile slots).  Leaves b_lo, b_woff, b_rt, b_tb filled.
+int bsr_pattern(expm_plan_s &P, const DCsr &T, int64_t *ntiles, double *fill) {
+    hipStream_t st = P.st;
+    const int64_t n = T.n, nb = (n + 15) / 16;
+    CHK(ensure(P, P.b_lo, sizeof(int32_t) * (nb + 1)));
+    CHK(ensure(P, P.b_words, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.b_woff, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.b_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.b_tb, sizeof(int64_t) * (nb + 1)));
+    HIPCHK(bsr_bounds(T.view(), nb, (int32_t *)P.b_lo.p, (int64_t *)P.b_words.p, st));
+    CHK(scan(P, (const int64_t *)P.b_words.p, (int64_t *)P.b_woff.p, nb));
+    int64_t *hl = (int64_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.b_woff.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    const int64_t words = hl[0];
+    CHK(ensure(P, P.b_rt, sizeof(uint2) * (words + 1)));
+    HIPCHK(bsr_bitmap(T.view(), nb, (const int32_t *)P.b_lo.p, (const int64_t *)P.b_woff.p,
+                      (uint2 *)P.b_rt.p, (int64_t *)P.b_cnt.p, st));
+    CHK(scan(P, (const int64_t *)P.b_cnt.p, (int64_t *)P.b_tb.p, nb));
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.b_tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    *ntiles = hl[0];
+    *fill = *ntiles ? (double)T.nnz / ((double)*ntiles * 256.0) : 0.0;
+    return EXPM_OK;
+}
+
+// One filtered squaring on tiles (T's pattern from bsr_pattern): fills the
+// candidate tiles, runs Algorithm 4.1 (or applies theta_fixed) and writes the
+// kept entries of T~ into dst as CSR.
+int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, double a_ri,
+                    bool use_fixed, double theta_fixed, bool exact_alloc, int stat_i) {
+    hipStream_t st = P.st;
+    const int64_t n = T.n, nb = (n + 15) / 16;
+    const bool prof = P.opts.profile && P.have_events && stat_i > 0;
+    int64_t *hl = (int64_t *)P.host;
+    if (prof) {
+        // algorithmic partial products of T*T (for the statistics only)
+        CHK(ensure(P, P.lo, sizeof(int32_t) * n));
+        CHK(ensure(P, P.words, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.ub, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
+        HIPCHK(row_bounds(T.view(), T.view(), 1, (int32_t *)P.lo.p, (int64_t *)P.words.p,
+                          (int64_t *)P.ub.p, st));
+        CHK(scan(P, (const int64_t *)P.ub.p, (int64_t *)P.tmp1.p, n));
+        HIPCHK(hipMemcpyAsync(hl + 16, (int64_t *)P.tmp1.p + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(P.ev[0], st));
+    }
+    // T's tiles in both operand layouts
+    const size_t tbytes = sizeof(double) * 256 * (size_t)(ntiles > 0 ? ntiles : 1);
+    CHK(ensure(P, P.b_tA, tbytes));
+    CHK(ensure(P, P.b_tB, tbytes));
+    HIPCHK(hipMemsetAsync(P.b_tA.p, 0, tbytes, st));
+    HIPCHK(hipMemsetAsync(P.b_tB.p, 0, tbytes, st));
+    HIPCHK(bsr_fill(T.view(), nb, (const int32_t *)P.b_lo.p, (const int64_t *)P.b_woff.p,
+                    (const uint2 *)P.b_rt.p, (const int64_t *)P.b_tb.p, (double *)P.b_tA.p,
+                    (double *)P.b_tB.p, st));
+    // C's tile pattern
+    CHK(ensure(P, P.c_lo, sizeof(int32_t) * (nb + 1)));
+    CHK(ensure(P, P.c_words, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.c_woff, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.c_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.c_tb, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.g_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.g_ofs, sizeof(int64_t) * (nb + 1)));
+    const int32_t *lo = (const int32_t *)P.b_lo.p;
+    const int64_t *woff = (const int64_t *)P.b_woff.p, *tb = (const int64_t *)P.b_tb.p;
+    const uint2 *rt = (const uint2 *)P.b_rt.p;
+    HIPCHK(bsr_cbounds(nb, lo, woff, rt, tb, (int32_t *)P.c_lo.p, (int64_t *)P.c_words.p, st));
+    CHK(scan(P, (const int64_t *)P.c_words.p, (int64_t *)P.c_woff.p, nb));
+    HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
+                        (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p, nullptr, nullptr, st));
+    CHK(scan(P, (const int64_t *)P.c_cnt.p, (int64_t *)P.c_tb.p, nb));
+    HIPCHK(bsr_groups((const int64_t *)P.c_cnt.p, nb, (int64_t *)P.g_cnt.p, st));
+    CHK(scan(P, (const int64_t *)P.g_cnt.p, (int64_t *)P.g_ofs.p, nb));
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.c_tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.g_ofs.p + nb, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    const int64_t ctiles = hl[0], nwork = hl[1];
+    CHK(ensure(P, P.c_cols, sizeof(int32_t) * (ctiles + 1)));
+    CHK(ensure(P, P.c_tiles, sizeof(double) * 256 * (size_t)(ctiles + 1)));
+    HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
+                        (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
+                        (const int64_t *)P.c_tb.p, (int32_t *)P.c_cols.p, st));
+    if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
+    HIPCHK(bsr_numeric(nb, lo, woff, rt, tb, (const double *)P.b_tA.p, (const double *)P.b_tB.p,
+                       (const int64_t *)P.g_ofs.p, (const int64_t *)P.c_tb.p,
+                       (const int64_t *)P.c_cnt.p, (const int32_t *)P.c_cols.p,
+                       (double *)P.c_tiles.p, nwork, st));
+    if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
+    // ||I + T~||_F and the nonzero candidate count
+    CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));
+    CHK(ensure(P, P.b_nz, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.b_total, sizeof(int64_t) * 2));
+    CHK(ensure(P, P.norm2, sizeof(double) * 2));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    CHK(ensure(P, P.tmp2, sizeof(int64_t) * (nb + 1)));
+    HIPCHK(bsr_norm(n, nb, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
+                    (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, (double *)P.b_sq.p,
+                    (int64_t *)P.b_nz.p, st));
+    if (!use_fixed)
+        HIPCHK(sum_values((const double *)P.b_sq.p, nb, (double *)P.part.p, kParts,
+                          (double *)P.norm2.p, st));
+    CHK(scan(P, (const int64_t *)P.b_nz.p, (int64_t *)P.tmp2.p, nb));
+    const int64_t slots = ctiles * 256;
+    hl[20] = slots;   // pinned staging; not touched again before the next sync
+    HIPCHK(hipMemcpyAsync(P.b_total.p, hl + 20, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // Algorithm 4.1 on the tile values, then the kept counts per row
+    CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
+    CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
+    FilterCtl *ctl = (FilterCtl *)P.ctl.p;
+    if (use_fixed)
+        HIPCHK(filter_init_theta(ctl, theta_fixed, st));
+    else
+        HIPCHK(filter_init(ctl, a_ri, (const double *)P.norm2.p, P.opts.e_r,
+                           P.opts.max_filter_iter, st));
+    FilterCtl h{};
+    int64_t kept = 0, cand_nz = 0;
+    for (int round = 0;; ++round) {
+        if (!use_fixed)
+            for (int j = 0; j < 4; ++j)
+                HIPCHK(filter_pass((const double *)P.c_tiles.p, (const int64_t *)P.b_total.p,
+                                   slots, ctl, (double *)P.part.p, kParts, st));
+        HIPCHK(bsr_count(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
+                         (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, ctl,
+                         (int64_t *)P.cnt.p, st));
+        CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
+        HIPCHK(hipMemcpyAsync(P.host, ctl, sizeof(FilterCtl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hl + 8, (int64_t *)P.krp.p + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hl + 9, (int64_t *)P.tmp2.p + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        memcpy(&h, P.host, sizeof h);
+        kept = hl[8];
+        cand_nz = hl[9];
+        if (h.done) break;
+        if (round > P.opts.max_filter_iter)
+            return fail(EXPM_ENOTCONV, "Algorithm 4.1 did not stop");
+    }
+    if (h.status)
+        return fail(EXPM_ENOTCONV, "Algorithm 4.1 reached %d iterations (budget %g)", h.iter,
+                    h.eg);
+    if (exact_alloc) release(P, dst);
+    CHK(ensure_csr(P, dst, n, kept));
+    HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+                          st));
+    HIPCHK(bsr_write(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
+                     (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, ctl,
+                     (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p, (double *)dst.v.p, st));
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
+        expm_stats &S = P.stats;
+        if (prof) {
+            HIPCHK(hipEventRecord(P.ev[3], st));
+            HIPCHK(hipEventSynchronize(P.ev[3]));
+            float t0, t1, t2;
+            HIPCHK(hipEventElapsedTime(&t0, P.ev[0], P.ev[1]));
+            HIPCHK(hipEventElapsedTime(&t1, P.ev[1], P.ev[2]));
+            HIPCHK(hipEventElapsedTime(&t2, P.ev[2], P.ev[3]));
+            S.t_sym_ms[stat_i] = t0;
+            S.t_num_ms[stat_i] = t1;
+            S.t_filter_ms[stat_i] = t2;
+            S.sq_fma[stat_i] = hl[16] - T.nnz;
+            S.sq_in[stat_i] = T.nnz;
+        }
+        S.sq_theta[stat_i] = h.theta;
+        S.sq_iters[stat_i] = h.iter;
+        S.sq_cand[stat_i] = cand_nz;
+        S.sq_kept[stat_i] = kept;
+        S.sq_budget[stat_i] = h.eg;
+        S.sq_normF[stat_i] = a_ri > 0 ? h.eg / a_ri : 0.0;
+        S.sq_dropped[stat_i] = h.b;
+    }
+    return EXPM_OK;
+}
+
+}  // namespace host
+}  // namespace xpm

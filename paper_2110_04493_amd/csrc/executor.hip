@@ -468,6 +468,7 @@ void free_adjoint_state(expm_plan_s &P) {
     for (auto &A : P.ckpt) release(P, A);
     P.taylor.clear();
     P.ckpt.clear();
+    P.sq_path.clear();
     release(P, P.TN);
     release(P, P.Epat);
     P.theta.clear();
@@ -479,8 +480,32 @@ void free_adjoint_state(expm_plan_s &P) {
 // stat_i > 0.  addI: dst = I + filtered (the finish step), exact_alloc: dst
 // gets exactly the kept entries.
 int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
-                double theta_fixed, bool addI, bool exact_alloc, int stat_i) {
+                double theta_fixed, bool addI, bool exact_alloc, int stat_i, int step) {
     const int64_t n = T.n;
+    // Tile or scalar product: decided once per squaring step from the tile
+    // fill of T and recorded, so that recomputation repeats the same path.
+    bool tiles = false;
+    int64_t ntiles = 0;
+    bool have_pattern = false;
+    if (step >= 1 && (int)P.sq_path.size() >= step) {
+        tiles = P.sq_path[step - 1] != 0;
+    } else {
+        if (!addI && P.bsr_min_fill <= 1.0 && (n + 15) / 16 <= 32 * 16384) {
+            double fill = 0.0;
+            CHK(bsr_pattern(P, T, &ntiles, &fill));
+            have_pattern = true;
+            tiles = ntiles > 0 && fill >= P.bsr_min_fill;
+        }
+        if (step >= 1) P.sq_path.push_back(tiles ? 1 : 0);
+    }
+    if (tiles) {
+        if (!have_pattern) {
+            double fill;
+            CHK(bsr_pattern(P, T, &ntiles, &fill));
+        }
+        return square_step_bsr(P, T, ntiles, dst, a_ri, use_fixed, theta_fixed, exact_alloc,
+                               stat_i);
+    }
     int64_t cand;
     CHK(spgemm(P, T.view(), T.nnz, T.view(), 2.0, 1.0, !use_fixed, &cand));
     if (!use_fixed) {
@@ -660,7 +685,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     for (int i = 1; i <= N; ++i) {
         const double ri = ldexp(r0, i);
         const bool last = i == N;
-        CHK(square_step(P, P.T, P.Tnew, a * ri, false, 0.0, false, false, i));
+        CHK(square_step(P, P.T, P.Tnew, a * ri, false, 0.0, false, false, i, i));
         P.theta.push_back(S.sq_theta[i]);
         std::swap(P.T, P.Tnew);
         P.T.nnz = S.sq_kept[i];
@@ -761,7 +786,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
                 const DCsr *prev = &P.ckpt[base / ck];
                 for (int j = base + 1; j <= std::min(base + ck - 1, N - 1); ++j) {
                     CHK(square_step(P, *prev, seg[j - base], 0.0, true, P.theta[j - 1], false,
-                                    true, 0));
+                                    true, 0, j));
                     prev = &seg[j - base];
                 }
             }
@@ -864,6 +889,7 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (!P) return fail(EXPM_ENOMEM, "cannot allocate the plan");
     P->opts = o;
     P->st = (hipStream_t)o.stream;
+    if (const char *f = getenv("EXPM_BSR_FILL")) P->bsr_min_fill = atof(f);
     if (hipHostMalloc((void **)&P->host, 4096, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete P;

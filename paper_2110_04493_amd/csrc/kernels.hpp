@@ -94,6 +94,33 @@ hipError_t write_kept(const int64_t *crp, const int32_t *cci, const double *cv, 
                       hipStream_t st, const int32_t *row_inst = nullptr,
                       const int *inst_addI = nullptr);
 
+// ------------------------------------------------------------- 16 x 16 tiles
+// (see bsr.hip).  nb = ceil(n / 16) block rows.
+size_t bsr_lds_words(int64_t n);
+hipError_t bsr_bounds(CsrView T, int64_t nb, int32_t *lo, int64_t *words, hipStream_t st);
+hipError_t bsr_bitmap(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, uint2 *rt,
+                      int64_t *cnt, hipStream_t st);
+hipError_t bsr_fill(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                    const int64_t *tb, double *tA, double *tB, hipStream_t st);
+hipError_t bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                       const int64_t *tb, int32_t *clo, int64_t *cwords, hipStream_t st);
+hipError_t bsr_cpattern(int64_t n, int64_t nb, const int32_t *lo, const int64_t *woff,
+                        const uint2 *rt, const int32_t *clo, const int64_t *cwoff, int64_t *ccnt,
+                        const int64_t *ctb, int32_t *ccols, hipStream_t st);
+hipError_t bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, hipStream_t st);
+hipError_t bsr_numeric(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                       const int64_t *tb, const double *tA, const double *tB, const int64_t *gofs,
+                       const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                       double *ctiles, int64_t nwork, hipStream_t st);
+hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
+                    const int32_t *ccols, const double *ctiles, double *bsq, int64_t *bnz,
+                    hipStream_t st);
+hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                     const double *ctiles, const FilterCtl *c, int64_t *cnt, hipStream_t st);
+hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                     const double *ctiles, const FilterCtl *c, const int64_t *orp, int32_t *oci,
+                     double *ov, hipStream_t st);
+
 // ------------------------------------------------------------- batched
 // Instance k of a block-diagonal stack owns rows [row_off[k], row_off[k+1]).
 hipError_t fill_row_inst(const int64_t *row_off, int count, int64_t n, int32_t *row_inst,

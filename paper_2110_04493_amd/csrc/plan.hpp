@@ -62,6 +62,15 @@ struct expm_plan_s {
     hipEvent_t ev[8] = {};
     bool have_events = false;
     int64_t last_fma = 0;
+    // 16 x 16 tile path of the squaring: T's tile pattern (origin, bit-map
+    // words, rank tables, tile bases), its tiles in both operand layouts, C's
+    // tile pattern, work items and the candidate tiles
+    xpm::host::Buf b_lo, b_words, b_woff, b_rt, b_cnt, b_tb, b_tA, b_tB, c_lo, c_words, c_woff,
+        c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz, b_total;
+    std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows
+    // tile fill of T from which the tile product is used; on MI355X at
+    // n = 90,000 the two paths cost the same at a fill of about 0.2
+    double bsr_min_fill = 0.2;
 };
 
 namespace xpm {
@@ -89,6 +98,9 @@ int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
 int check_view(const expm_csr_cview *H);
 void free_adjoint_state(expm_plan_s &P);
+int bsr_pattern(expm_plan_s &P, const DCsr &T, int64_t *ntiles, double *fill);
+int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, double a_ri,
+                    bool use_fixed, double theta_fixed, bool exact_alloc, int stat_i);
 
 }  // namespace host
 }  // namespace xpm
