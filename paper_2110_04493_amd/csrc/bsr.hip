@@ -21,22 +21,9 @@
 // found in O(1) by rank, as in the scalar product.
 #include <stdlib.h>
 
-#include "kernels.hpp"
+#include "bsr_common.hpp"
 
 namespace xpm {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int kTile = 16;
-constexpr int kTileElems = kTile * kTile;
-
-__device__ __forceinline__ int offA(int r, int c) { return (((c & 3) << 4) + r) * 4 + (c >> 2); }
-__device__ __forceinline__ int offB(int r, int c) { return (((r & 3) << 4) + c) * 4 + (r >> 2); }
-
-__device__ __forceinline__ void wfence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 // ----------------------------------------------------------------- T -> tiles
 
@@ -98,18 +85,6 @@ __global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const 
         carry += __shfl(inc, kWave - 1);
     }
     if (lane == 0) cnt[I] = carry;
-}
-
-// Tile index of block column J in block row K, or -1.
-__device__ __forceinline__ int64_t tile_of(const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                                           const int64_t *tb, int64_t K, int J) {
-    const int d = J - lo[K];
-    const int64_t w0 = woff[K];
-    if (d < 0 || (d >> 5) >= woff[K + 1] - w0) return -1;
-    const uint2 e = rt[w0 + (d >> 5)];
-    const uint32_t bit = 1u << (d & 31);
-    if (!(e.x & bit)) return -1;
-    return tb[K] + e.y + __popc(e.x & (bit - 1u));
 }
 
 // Scatters the entries of T into the zeroed tiles, in both operand layouts.

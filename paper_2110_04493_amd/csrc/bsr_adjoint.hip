@@ -1,0 +1,265 @@
+// Adjoint squaring step on 16 x 16 tiles (gfx950 FP64 matrix cores).
+//
+// For the squarings of Eq. (4.15) with frozen masks, the gradient moves back
+// one step as  G_{k-1} = P_{k-1}(2 G_k + G_k T^T + T^T G_k),  T = T_{k-1},
+// where P_{k-1} keeps the stored entries of T_{k-1}.  On tiles, for every
+// tile (I, J) of T's pattern:
+//   2 G_IJ                = (2 I_16) G_IJ                 (G_IJ, B layout)
+//   (G T^T)_IJ = sum_K G_IK (T_JK)^T                      (G_IK A layout, T_JK A layout
+//                                                          read as the B operand)
+//   (T^T G)_IJ = sum_K (T_KI)^T G_KJ                      (T_KI B layout read as the
+//                                                          A operand, G_KJ B layout)
+// then the mask keeps the slots where T_IJ is nonzero.  The K sums run over
+// G's block row I and over T's block column I (T^T's block row I, kept as a
+// sorted list), in ascending K, so the result is bitwise reproducible.
+#include "bsr_common.hpp"
+
+namespace xpm {
+
+// ----------------------------------------------------------------- T^T's block rows
+
+__global__ void k_bsr_colcount(int64_t nb, const int32_t *lo, const int64_t *woff,
+                               const uint2 *rt, int64_t *cnt) {
+    const int64_t K = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (K >= nb) return;
+    for (int64_t w = woff[K] + lane_id(); w < woff[K + 1]; w += kWave) {
+        uint32_t x = rt[w].x;
+        const int base = lo[K] + 32 * (int)(w - woff[K]);
+        while (x) {
+            const int J = base + __ffs(x) - 1;
+            x &= x - 1;
+            atomicAdd((unsigned long long *)&cnt[J], 1ull);
+        }
+    }
+}
+
+__global__ void k_bsr_colfill(int64_t nb, const int32_t *lo, const int64_t *woff,
+                              const uint2 *rt, const int64_t *tb, int64_t *fill, int32_t *uk,
+                              int64_t *ut) {
+    const int64_t K = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (K >= nb) return;
+    for (int64_t w = woff[K] + lane_id(); w < woff[K + 1]; w += kWave) {
+        const uint2 e = rt[w];
+        uint32_t x = e.x;
+        unsigned r = e.y;
+        const int base = lo[K] + 32 * (int)(w - woff[K]);
+        while (x) {
+            const int J = base + __ffs(x) - 1;
+            x &= x - 1;
+            const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&fill[J], 1ull);
+            uk[pos] = (int32_t)K;
+            ut[pos] = tb[K] + r;
+            ++r;
+        }
+    }
+}
+
+// Sorts each block column's list by K (ranks are distinct: one tile per
+// (K, J)), from the unsorted (uk, ut) into (ck, ct).
+__global__ void k_bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk, const int64_t *ut,
+                              int32_t *ck, int64_t *ct) {
+    const int64_t J = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (J >= nb) return;
+    const int64_t b = ptr[J], e = ptr[J + 1];
+    for (int64_t p = b + lane_id(); p < e; p += kWave) {
+        const int32_t k = uk[p];
+        int64_t r = 0;
+        for (int64_t q = b; q < e; ++q) r += uk[q] < k;
+        ck[b + r] = k;
+        ct[b + r] = ut[p];
+    }
+}
+
+// ----------------------------------------------------------------- adjoint tiles
+
+// One wave per work item: a block row I of T and up to kGroup of its tiles.
+template <int kGroup>
+__global__ __launch_bounds__(256) void k_bsr_adjoint(
+    int64_t nb,
+    // T = T_{k-1}: pattern and tiles
+    const int32_t *__restrict__ tlo, const int64_t *__restrict__ twoff,
+    const uint2 *__restrict__ trt, const int64_t *__restrict__ ttb,
+    const double *__restrict__ tA, const double *__restrict__ tB,
+    // G on T_k's pattern
+    const int32_t *__restrict__ glo, const int64_t *__restrict__ gwoff,
+    const uint2 *__restrict__ grt, const int64_t *__restrict__ gtb,
+    const double *__restrict__ gA, const double *__restrict__ gB,
+    // T's block columns (T^T's block rows), sorted by K
+    const int64_t *__restrict__ cptr, const int32_t *__restrict__ ck,
+    const int64_t *__restrict__ ct,
+    const int64_t *__restrict__ gofs, double *__restrict__ out, int64_t nwork) {
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (w >= nwork) return;
+    int64_t a0 = 0, a1 = nb - 1;   // last I with gofs[I] <= w
+    while (a0 < a1) {
+        const int64_t mid = (a0 + a1 + 1) >> 1;
+        if (gofs[mid] <= w) a0 = mid; else a1 = mid - 1;
+    }
+    const int64_t I = a0;
+    const int64_t t0 = (w - gofs[I]) * kGroup;             // first tile (rank in block row I)
+    const int64_t cntI = ttb[I + 1] - ttb[I];
+    const int ng = (int)min<int64_t>(kGroup, cntI - t0);
+    // block columns J of the group: the t0-th .. set bits of T's block row I
+    int J[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) J[t] = (int)I;   // valid block index until found
+    {
+        int found = 0;
+        const int64_t W = twoff[I + 1] - twoff[I];
+        for (int64_t ww = 0; ww < W && found < ng; ++ww) {
+            const uint2 e = trt[twoff[I] + ww];
+            uint32_t x = e.x;
+            unsigned r = e.y;
+            while (x && found < ng) {
+                const int bit = __ffs(x) - 1;
+                x &= x - 1;
+                if ((int64_t)r >= t0) J[found++] = tlo[I] + 32 * (int)ww + bit;
+                ++r;
+            }
+        }
+    }
+    d4 acc[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const d4 two = two_identity_a(lane);
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        if (t >= ng) break;
+        const int64_t tg = tile_of(glo, gwoff, grt, gtb, I, J[t]);
+        if (tg >= 0) acc[t] = mfma16(two, *(const d4 *)(gB + tg * kTileElems + 4 * lane), acc[t]);
+    }
+    // (G T^T)_IJ = sum over K in G's block row I of G_IK (T_JK)^T
+    {
+        const int64_t W = gwoff[I + 1] - gwoff[I];
+        for (int64_t ww = 0; ww < W; ++ww) {
+            const uint2 e = grt[gwoff[I] + ww];
+            uint32_t x = e.x;
+            unsigned r = e.y;
+            while (x) {
+                const int K = glo[I] + 32 * (int)ww + __ffs(x) - 1;
+                x &= x - 1;
+                const int64_t tgk = gtb[I] + r;
+                ++r;
+                int64_t tj[kGroup];
+                bool any = false;
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t) {
+                    tj[t] = t < ng ? tile_of(tlo, twoff, trt, ttb, J[t], K) : -1;
+                    any = any || tj[t] >= 0;
+                }
+                if (!any) continue;
+                const d4 a = *(const d4 *)(gA + tgk * kTileElems + 4 * lane);
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t)
+                    if (tj[t] >= 0)
+                        acc[t] = mfma16(a, *(const d4 *)(tA + tj[t] * kTileElems + 4 * lane),
+                                        acc[t]);
+            }
+        }
+    }
+    // (T^T G)_IJ = sum over K in T's block column I of (T_KI)^T G_KJ
+    for (int64_t p = cptr[I]; p < cptr[I + 1]; ++p) {
+        const int K = ck[p];
+        int64_t tg[kGroup];
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            tg[t] = t < ng ? tile_of(glo, gwoff, grt, gtb, K, J[t]) : -1;
+            any = any || tg[t] >= 0;
+        }
+        if (!any) continue;
+        const d4 a = *(const d4 *)(tB + ct[p] * kTileElems + 4 * lane);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t)
+            if (tg[t] >= 0)
+                acc[t] = mfma16(a, *(const d4 *)(gB + tg[t] * kTileElems + 4 * lane), acc[t]);
+    }
+    // mask by T's stored entries (T_IJ in the B layout = accumulator layout)
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        if (t >= ng) break;
+        const int64_t tt = ttb[I] + t0 + t;
+        const d4 m = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
+        d4 o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = m[r] != 0.0 ? acc[t][r] : 0.0;
+        *(d4 *)(out + tt * kTileElems + 4 * lane) = o;
+    }
+}
+
+// Values of the output tiles at T's stored entries (CSR order).
+__global__ void k_bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                             const int64_t *tb, const double *tiles, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= T.n) return;
+    const int64_t I = i >> 4;
+    const int r = (int)(i & 15);
+    for (int64_t p = T.rp[i] + lane_id(); p < T.rp[i + 1]; p += kWave) {
+        const int j = T.ci[p];
+        const int64_t t = tile_of(lo, woff, rt, tb, I, j >> 4);
+        out[p] = tiles[t * kTileElems + offB(r, j & 15)];
+    }
+}
+
+// Work items of four tiles per block row, from the tile bases tb.
+__global__ void k_bsr_groups4(const int64_t *tb, int64_t nb, int64_t *gcnt) {
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nb) gcnt[I] = (tb[I + 1] - tb[I] + 3) / 4;
+}
+
+// ----------------------------------------------------------------- wrappers
+
+hipError_t bsr_groups4(const int64_t *tb, int64_t nb, int64_t *gcnt, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_groups4, dim3((nb + 255) / 256), dim3(256), 0, st, tb, nb, gcnt);
+    return hipGetLastError();
+}
+
+hipError_t bsr_colcount(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                        int64_t *cnt, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_colcount, dim3((nb + 3) / 4), dim3(256), 0, st, nb, lo, woff, rt,
+                       cnt);
+    return hipGetLastError();
+}
+
+hipError_t bsr_colfill(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                       const int64_t *tb, int64_t *fill, int32_t *uk, int64_t *ut,
+                       hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_colfill, dim3((nb + 3) / 4), dim3(256), 0, st, nb, lo, woff, rt, tb,
+                       fill, uk, ut);
+    return hipGetLastError();
+}
+
+hipError_t bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk, const int64_t *ut,
+                       int32_t *ck, int64_t *ct, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_colsort, dim3((nb + 3) / 4), dim3(256), 0, st, ptr, nb, uk, ut, ck,
+                       ct);
+    return hipGetLastError();
+}
+
+hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, const uint2 *trt,
+                       const int64_t *ttb, const double *tA, const double *tB, const int32_t *glo,
+                       const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
+                       const double *gA, const double *gB, const int64_t *cptr,
+                       const int32_t *ck, const int64_t *ct, const int64_t *gofs, double *out,
+                       int64_t nwork, hipStream_t st) {
+    if (nwork == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_adjoint<4>, dim3((nwork + 3) / 4), dim3(256), 0, st, nb, tlo, twoff,
+                       trt, ttb, tA, tB, glo, gwoff, grt, gtb, gA, gB, cptr, ck, ct, gofs, out,
+                       nwork);
+    return hipGetLastError();
+}
+
+hipError_t bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                      const int64_t *tb, const double *tiles, double *out, hipStream_t st) {
+    if (T.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_gather, dim3((T.n + 3) / 4), dim3(256), 0, st, T, lo, woff, rt, tb,
+                       tiles, out);
+    return hipGetLastError();
+}
+
+}  // namespace xpm

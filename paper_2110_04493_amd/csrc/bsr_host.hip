@@ -1,4 +1,5 @@
-// Host driver of the 16 x 16 tile squaring step (kernels in bsr.hip).
+// Host drivers of the 16 x 16 tile squaring step and its adjoint (kernels in
+// bsr.hip and bsr_adjoint.hip).
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -8,42 +9,63 @@
 namespace xpm {
 namespace host {
 
-// Builds T's tile pattern; returns the tile count and T's fill (stored
-// entries over tile slots).  Leaves b_lo, b_woff, b_rt, b_tb filled.
-int bsr_pattern(expm_plan_s &P, const DCsr &T, int64_t *ntiles, double *fill) {
+void release(expm_plan_s &P, TileSet &ts) {
+    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt, &ts.cnt, &ts.tb, &ts.tA, &ts.tB};
+    for (Buf *b : all) release(P, *b);
+    ts.nb = ts.ntiles = 0;
+}
+
+// Tile pattern of T (origin, bit maps with prefix counts, tile bases) and
+// T's fill: stored entries over tile slots.
+int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill) {
     hipStream_t st = P.st;
     const int64_t n = T.n, nb = (n + 15) / 16;
-    CHK(ensure(P, P.b_lo, sizeof(int32_t) * (nb + 1)));
-    CHK(ensure(P, P.b_words, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.b_woff, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.b_cnt, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.b_tb, sizeof(int64_t) * (nb + 1)));
-    HIPCHK(bsr_bounds(T.view(), nb, (int32_t *)P.b_lo.p, (int64_t *)P.b_words.p, st));
-    CHK(scan(P, (const int64_t *)P.b_words.p, (int64_t *)P.b_woff.p, nb));
+    ts.nb = nb;
+    CHK(ensure(P, ts.lo, sizeof(int32_t) * (nb + 1)));
+    CHK(ensure(P, ts.words, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, ts.woff, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, ts.cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, ts.tb, sizeof(int64_t) * (nb + 1)));
+    HIPCHK(bsr_bounds(T, nb, (int32_t *)ts.lo.p, (int64_t *)ts.words.p, st));
+    CHK(scan(P, (const int64_t *)ts.words.p, (int64_t *)ts.woff.p, nb));
     int64_t *hl = (int64_t *)P.host;
-    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.b_woff.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)ts.woff.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
     CHK(sync(P));
     const int64_t words = hl[0];
-    CHK(ensure(P, P.b_rt, sizeof(uint2) * (words + 1)));
-    HIPCHK(bsr_bitmap(T.view(), nb, (const int32_t *)P.b_lo.p, (const int64_t *)P.b_woff.p,
-                      (uint2 *)P.b_rt.p, (int64_t *)P.b_cnt.p, st));
-    CHK(scan(P, (const int64_t *)P.b_cnt.p, (int64_t *)P.b_tb.p, nb));
-    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.b_tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+    CHK(ensure(P, ts.rt, sizeof(uint2) * (words + 1)));
+    HIPCHK(bsr_bitmap(T, nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
+                      (uint2 *)ts.rt.p, (int64_t *)ts.cnt.p, st));
+    CHK(scan(P, (const int64_t *)ts.cnt.p, (int64_t *)ts.tb.p, nb));
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)ts.tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
     CHK(sync(P));
-    *ntiles = hl[0];
-    *fill = *ntiles ? (double)T.nnz / ((double)*ntiles * 256.0) : 0.0;
+    ts.ntiles = hl[0];
+    *fill = ts.ntiles ? (double)nnz / ((double)ts.ntiles * 256.0) : 0.0;
     return EXPM_OK;
 }
 
-// One filtered squaring on tiles (T's pattern from bsr_pattern): fills the
+// T's values into zeroed tiles of the pattern, in both operand layouts.
+int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts) {
+    const size_t tbytes = sizeof(double) * 256 * (size_t)(ts.ntiles > 0 ? ts.ntiles : 1);
+    CHK(ensure(P, ts.tA, tbytes));
+    CHK(ensure(P, ts.tB, tbytes));
+    HIPCHK(hipMemsetAsync(ts.tA.p, 0, tbytes, P.st));
+    HIPCHK(hipMemsetAsync(ts.tB.p, 0, tbytes, P.st));
+    HIPCHK(bsr_fill(T, ts.nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
+                    (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (double *)ts.tA.p,
+                    (double *)ts.tB.p, P.st));
+    return EXPM_OK;
+}
+
+// One filtered squaring on tiles (T's pattern already in P.tsT): fills the
 // candidate tiles, runs Algorithm 4.1 (or applies theta_fixed) and writes the
 // kept entries of T~ into dst as CSR.
-int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, double a_ri,
-                    bool use_fixed, double theta_fixed, bool exact_alloc, int stat_i) {
+int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
+                    double theta_fixed, bool exact_alloc, int stat_i) {
     hipStream_t st = P.st;
-    const int64_t n = T.n, nb = (n + 15) / 16;
+    TileSet &ts = P.tsT;
+    const int64_t n = T.n, nb = ts.nb;
     const bool prof = P.opts.profile && P.have_events && stat_i > 0;
     int64_t *hl = (int64_t *)P.host;
     if (prof) {
@@ -59,15 +81,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, do
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(P.ev[0], st));
     }
-    // T's tiles in both operand layouts
-    const size_t tbytes = sizeof(double) * 256 * (size_t)(ntiles > 0 ? ntiles : 1);
-    CHK(ensure(P, P.b_tA, tbytes));
-    CHK(ensure(P, P.b_tB, tbytes));
-    HIPCHK(hipMemsetAsync(P.b_tA.p, 0, tbytes, st));
-    HIPCHK(hipMemsetAsync(P.b_tB.p, 0, tbytes, st));
-    HIPCHK(bsr_fill(T.view(), nb, (const int32_t *)P.b_lo.p, (const int64_t *)P.b_woff.p,
-                    (const uint2 *)P.b_rt.p, (const int64_t *)P.b_tb.p, (double *)P.b_tA.p,
-                    (double *)P.b_tB.p, st));
+    CHK(bsr_tiles(P, T.view(), ts));
     // C's tile pattern
     CHK(ensure(P, P.c_lo, sizeof(int32_t) * (nb + 1)));
     CHK(ensure(P, P.c_words, sizeof(int64_t) * (nb + 1)));
@@ -76,9 +90,9 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, do
     CHK(ensure(P, P.c_tb, sizeof(int64_t) * (nb + 1)));
     CHK(ensure(P, P.g_cnt, sizeof(int64_t) * (nb + 1)));
     CHK(ensure(P, P.g_ofs, sizeof(int64_t) * (nb + 1)));
-    const int32_t *lo = (const int32_t *)P.b_lo.p;
-    const int64_t *woff = (const int64_t *)P.b_woff.p, *tb = (const int64_t *)P.b_tb.p;
-    const uint2 *rt = (const uint2 *)P.b_rt.p;
+    const int32_t *lo = (const int32_t *)ts.lo.p;
+    const int64_t *woff = (const int64_t *)ts.woff.p, *tb = (const int64_t *)ts.tb.p;
+    const uint2 *rt = (const uint2 *)ts.rt.p;
     HIPCHK(bsr_cbounds(nb, lo, woff, rt, tb, (int32_t *)P.c_lo.p, (int64_t *)P.c_words.p, st));
     CHK(scan(P, (const int64_t *)P.c_words.p, (int64_t *)P.c_woff.p, nb));
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
@@ -98,7 +112,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, do
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
                         (const int64_t *)P.c_tb.p, (int32_t *)P.c_cols.p, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
-    HIPCHK(bsr_numeric(nb, lo, woff, rt, tb, (const double *)P.b_tA.p, (const double *)P.b_tB.p,
+    HIPCHK(bsr_numeric(nb, lo, woff, rt, tb, (const double *)ts.tA.p, (const double *)ts.tB.p,
                        (const int64_t *)P.g_ofs.p, (const int64_t *)P.c_tb.p,
                        (const int64_t *)P.c_cnt.p, (const int32_t *)P.c_cols.p,
                        (double *)P.c_tiles.p, nwork, st));
@@ -187,6 +201,60 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, do
         S.sq_normF[stat_i] = a_ri > 0 ? h.eg / a_ri : 0.0;
         S.sq_dropped[stat_i] = h.b;
     }
+    return EXPM_OK;
+}
+
+// Adjoint squaring step on tiles.  Tp's pattern must already be in P.tsT
+// (bsr_pattern); G's pattern is that of Tk.
+int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
+                     double *out) {
+    hipStream_t st = P.st;
+    TileSet &T = P.tsT, &G = P.tsG;
+    const int64_t nb = T.nb;
+    CHK(bsr_tiles(P, Tp.view(), T));
+    const CsrView Gv{Tk.n, (const int64_t *)Tk.rp.p, (const int32_t *)Tk.ci.p, g};
+    double fg;
+    CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));
+    CHK(bsr_tiles(P, Gv, G));
+    // T's block columns as sorted lists (T^T's block rows)
+    CHK(ensure(P, P.tc_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.tc_ptr, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.tc_fill, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.tc_k, sizeof(int32_t) * 2 * (T.ntiles + 1)));
+    CHK(ensure(P, P.tc_t, sizeof(int64_t) * 2 * (T.ntiles + 1)));
+    int32_t *uk = (int32_t *)P.tc_k.p, *ck = uk + (T.ntiles + 1);
+    int64_t *ut = (int64_t *)P.tc_t.p, *ct = ut + (T.ntiles + 1);
+    HIPCHK(hipMemsetAsync(P.tc_cnt.p, 0, sizeof(int64_t) * (nb + 1), st));
+    HIPCHK(bsr_colcount(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
+                        (const uint2 *)T.rt.p, (int64_t *)P.tc_cnt.p, st));
+    CHK(scan(P, (const int64_t *)P.tc_cnt.p, (int64_t *)P.tc_ptr.p, nb));
+    HIPCHK(hipMemcpyAsync(P.tc_fill.p, P.tc_ptr.p, sizeof(int64_t) * nb, hipMemcpyDeviceToDevice,
+                          st));
+    HIPCHK(bsr_colfill(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
+                       (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (int64_t *)P.tc_fill.p,
+                       uk, ut, st));
+    HIPCHK(bsr_colsort((const int64_t *)P.tc_ptr.p, nb, uk, ut, ck, ct, st));
+    // work items: four output tiles of one block row of T each
+    CHK(ensure(P, P.g_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.g_ofs, sizeof(int64_t) * (nb + 1)));
+    HIPCHK(bsr_groups4((const int64_t *)T.tb.p, nb, (int64_t *)P.g_cnt.p, st));
+    CHK(scan(P, (const int64_t *)P.g_cnt.p, (int64_t *)P.g_ofs.p, nb));
+    int64_t *hl = (int64_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.g_ofs.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    const int64_t nwork = hl[0];
+    CHK(ensure(P, P.adj_tiles, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
+    HIPCHK(bsr_adjoint(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
+                       (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (const double *)T.tA.p,
+                       (const double *)T.tB.p, (const int32_t *)G.lo.p,
+                       (const int64_t *)G.woff.p, (const uint2 *)G.rt.p,
+                       (const int64_t *)G.tb.p, (const double *)G.tA.p,
+                       (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
+                       (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p, nwork, st));
+    HIPCHK(bsr_gather(Tp.view(), (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
+                      (const uint2 *)T.rt.p, (const int64_t *)T.tb.p,
+                      (const double *)P.adj_tiles.p, out, st));
     return EXPM_OK;
 }
 

@@ -479,32 +479,36 @@ void free_adjoint_state(expm_plan_s &P) {
 // stored threshold replaces the search.  Fills the step's statistics when
 // stat_i > 0.  addI: dst = I + filtered (the finish step), exact_alloc: dst
 // gets exactly the kept entries.
+// Tiles need a block-row bit map in LDS (at most n / 512 words) and are
+// switched off entirely by a fill threshold above 1.
+bool tiles_allowed(const expm_plan_s &P, int64_t n) {
+    return P.bsr_min_fill <= 1.0 && bsr_lds_words(n) * 4 <= 65536;
+}
+
 int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
                 double theta_fixed, bool addI, bool exact_alloc, int stat_i, int step) {
     const int64_t n = T.n;
     // Tile or scalar product: decided once per squaring step from the tile
     // fill of T and recorded, so that recomputation repeats the same path.
     bool tiles = false;
-    int64_t ntiles = 0;
     bool have_pattern = false;
     if (step >= 1 && (int)P.sq_path.size() >= step) {
         tiles = P.sq_path[step - 1] != 0;
     } else {
-        if (!addI && P.bsr_min_fill <= 1.0 && (n + 15) / 16 <= 32 * 16384) {
+        if (!addI && tiles_allowed(P, n)) {
             double fill = 0.0;
-            CHK(bsr_pattern(P, T, &ntiles, &fill));
+            CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill));
             have_pattern = true;
-            tiles = ntiles > 0 && fill >= P.bsr_min_fill;
+            tiles = P.tsT.ntiles > 0 && fill >= P.bsr_min_fill;
         }
         if (step >= 1) P.sq_path.push_back(tiles ? 1 : 0);
     }
     if (tiles) {
         if (!have_pattern) {
             double fill;
-            CHK(bsr_pattern(P, T, &ntiles, &fill));
+            CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill));
         }
-        return square_step_bsr(P, T, ntiles, dst, a_ri, use_fixed, theta_fixed, exact_alloc,
-                               stat_i);
+        return square_step_bsr(P, T, dst, a_ri, use_fixed, theta_fixed, exact_alloc, stat_i);
     }
     int64_t cand;
     CHK(spgemm(P, T.view(), T.nnz, T.view(), 2.0, 1.0, !use_fixed, &cand));
@@ -792,12 +796,23 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             }
             Tp = &seg[km1 - base];
         }
-        CHK(transpose_csr(P, *Tp, Tt));
         CHK(ensure(P, gn, sizeof(double) * (Tp->nnz + 1)));
-        CsrView Gk = CsrView{n, (const int64_t *)Tk->rp.p, (const int32_t *)Tk->ci.p,
-                             (const double *)g.p};
-        MaskTerm t1{Gk, Tt.view(), 1.0}, t2{Tt.view(), Gk, 1.0};
-        CHK(masked(P, Tp->view(), Gk, 2.0, t1, t2, 1.0, (double *)gn.p));
+        // tiles when T_{k-1}'s tile fill is high enough, as in the forward
+        bool tiles = false;
+        if (tiles_allowed(P, n)) {
+            double fill = 0.0;
+            CHK(bsr_pattern(P, Tp->view(), Tp->nnz, P.tsT, &fill));
+            tiles = P.tsT.ntiles > 0 && fill >= P.bsr_min_fill;
+        }
+        if (tiles) {
+            CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p));
+        } else {
+            CHK(transpose_csr(P, *Tp, Tt));
+            CsrView Gk = CsrView{n, (const int64_t *)Tk->rp.p, (const int32_t *)Tk->ci.p,
+                                 (const double *)g.p};
+            MaskTerm t1{Gk, Tt.view(), 1.0}, t2{Tt.view(), Gk, 1.0};
+            CHK(masked(P, Tp->view(), Gk, 2.0, t1, t2, 1.0, (double *)gn.p));
+        }
         std::swap(g, gn);
         Tk = Tp;
         if (k - 1 == base && seg_base == base) {
@@ -979,6 +994,12 @@ void expm_free(expm_plan_t p) {
                    &P.counts, &P.scan_tmp, &P.part, &P.ctl, &P.rowsq, &P.norm2, &P.scratch,
                    &P.soff, &P.sbytes, &P.flags, &P.krp, &P.tmp1, &P.tmp2, &P.cci, &P.cv};
     for (Buf *b : bufs) release(P, *b);
+    Buf *tbufs[] = {&P.c_lo, &P.c_words, &P.c_woff, &P.c_cnt, &P.c_tb, &P.c_cols, &P.c_tiles,
+                    &P.g_cnt, &P.g_ofs, &P.b_sq, &P.b_nz, &P.b_total, &P.tc_cnt, &P.tc_ptr,
+                    &P.tc_fill, &P.tc_k, &P.tc_t, &P.adj_tiles};
+    for (Buf *b : tbufs) release(P, *b);
+    release(P, P.tsT);
+    release(P, P.tsG);
     DCsr *mats[] = {&P.H0, &P.S, &P.Snew, &P.T, &P.Tnew, &P.Hpat_t};
     for (DCsr *m : mats) release(P, *m);
     while (!P.outputs.empty()) out_free(P, P.outputs.back());

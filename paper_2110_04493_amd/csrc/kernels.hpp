@@ -121,6 +121,24 @@ hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
                      const double *ctiles, const FilterCtl *c, const int64_t *orp, int32_t *oci,
                      double *ov, hipStream_t st);
 
+// adjoint on tiles (bsr_adjoint.hip)
+hipError_t bsr_colcount(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                        int64_t *cnt, hipStream_t st);
+hipError_t bsr_colfill(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                       const int64_t *tb, int64_t *fill, int32_t *uk, int64_t *ut,
+                       hipStream_t st);
+hipError_t bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk, const int64_t *ut,
+                       int32_t *ck, int64_t *ct, hipStream_t st);
+hipError_t bsr_groups4(const int64_t *tb, int64_t nb, int64_t *gcnt, hipStream_t st);
+hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, const uint2 *trt,
+                       const int64_t *ttb, const double *tA, const double *tB, const int32_t *glo,
+                       const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
+                       const double *gA, const double *gB, const int64_t *cptr,
+                       const int32_t *ck, const int64_t *ct, const int64_t *gofs, double *out,
+                       int64_t nwork, hipStream_t st);
+hipError_t bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                      const int64_t *tb, const double *tiles, double *out, hipStream_t st);
+
 // ------------------------------------------------------------- batched
 // Instance k of a block-diagonal stack owns rows [row_off[k], row_off[k+1]).
 hipError_t fill_row_inst(const int64_t *row_off, int count, int64_t n, int32_t *row_inst,

@@ -28,6 +28,14 @@ struct DCsr {
     }
 };
 
+// A matrix held as 16 x 16 tiles: per block row the origin (block column,
+// multiple of 32), bit-map words with prefix counts (rank table) and the
+// base tile index; the tiles in the A and B operand layouts.
+struct TileSet {
+    Buf lo, words, woff, rt, cnt, tb, tA, tB;
+    int64_t nb = 0, ntiles = 0;
+};
+
 
 }  // namespace host
 }  // namespace xpm
@@ -65,8 +73,11 @@ struct expm_plan_s {
     // 16 x 16 tile path of the squaring: T's tile pattern (origin, bit-map
     // words, rank tables, tile bases), its tiles in both operand layouts, C's
     // tile pattern, work items and the candidate tiles
-    xpm::host::Buf b_lo, b_words, b_woff, b_rt, b_cnt, b_tb, b_tA, b_tB, c_lo, c_words, c_woff,
-        c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz, b_total;
+    xpm::host::TileSet tsT, tsG;
+    xpm::host::Buf c_lo, c_words, c_woff, c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz,
+        b_total;
+    // block-column lists of T (the block rows of T^T) for the adjoint
+    xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles;
     std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows
     // tile fill of T from which the tile product is used; on MI355X at
     // n = 90,000 the two paths cost the same at a fill of about 0.2
@@ -98,9 +109,15 @@ int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
 int check_view(const expm_csr_cview *H);
 void free_adjoint_state(expm_plan_s &P);
-int bsr_pattern(expm_plan_s &P, const DCsr &T, int64_t *ntiles, double *fill);
-int square_step_bsr(expm_plan_s &P, const DCsr &T, int64_t ntiles, DCsr &dst, double a_ri,
-                    bool use_fixed, double theta_fixed, bool exact_alloc, int stat_i);
+int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill);
+int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts);
+int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
+                    double theta_fixed, bool exact_alloc, int stat_i);
+// One adjoint step on tiles: out (aligned with Tp's entries) =
+// P_Tp(2 G + G Tp^T + Tp^T G), with G given on the pattern of Tk.
+int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
+                     double *out);
+void release(expm_plan_s &P, TileSet &ts);
 
 }  // namespace host
 }  // namespace xpm

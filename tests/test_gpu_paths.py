@@ -1,0 +1,54 @@
+"""Both squaring paths (16x16 tiles on matrix cores, scalar rows) forced on
+their own, forward and adjoint, against the oracle; tile and scalar results
+agree with each other to the parity bar.  EXPM_BSR_FILL is read when a plan
+is created: 0 takes tiles at every squaring step, 2 never."""
+import numpy as np
+import pytest
+
+from paper_2110_04493_amd import workloads as W
+from _helpers import compare, final_theta, run_gpu, run_oracle
+from test_gpu_adjoint import gpu_grad, oracle_grad
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def cases():
+    rng = np.random.default_rng(11)
+    L = W.grid_laplacian(33, 29, rng)                    # n not a multiple of 16
+    yield "grid", L.scaled(-30.0 / W.norm1(L)), 1e-12
+    yield "tridiag", W.tridiag(1000, 1.0, -2.0, 1.0, 10.0), 1e-14
+    yield "general", W.random_sparse(150, 0.03, 3, kind="general", scale=1.2), 1e-12
+    yield "adjacency", W.config4_instance(1, nmin=100, nmax=300)[0], 1e-12
+
+
+@pytest.mark.parametrize("fill", ["0", "2"])
+@pytest.mark.parametrize("name,H,eps", list(cases()), ids=[c[0] for c in cases()])
+def test_forward_paths(monkeypatch, fill, name, H, eps):
+    monkeypatch.setenv("EXPM_BSR_FILL", fill)
+    Eg, sg = run_gpu(H, eps)
+    Eo, so = run_oracle(H, eps)
+    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
+    print(f"[{name} fill={fill}] relF={rel:.2e} only={og},{oo}", flush=True)
+    assert rel <= TOL and ok
+    assert (sg["M"], sg["N"]) == (so["M"], so["N"])
+
+
+@pytest.mark.parametrize("fill", ["0", "2"])
+@pytest.mark.parametrize("name,H,eps", list(cases()), ids=[c[0] for c in cases()])
+def test_adjoint_paths(monkeypatch, fill, name, H, eps):
+    monkeypatch.setenv("EXPM_BSR_FILL", fill)
+    dg, _ = gpu_grad(H, eps, density=0.2, checkpoint_interval=2)
+    do, _ = oracle_grad(H, eps, density=0.2)
+    rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+    print(f"[{name} fill={fill}] adjoint rel={rel:.2e}", flush=True)
+    assert rel <= TOL
+
+
+def test_tiles_deterministic(monkeypatch):
+    monkeypatch.setenv("EXPM_BSR_FILL", "0")
+    H, eps = W.config5(40)
+    E1, _ = run_gpu(H, eps)
+    E2, _ = run_gpu(H, eps)
+    assert np.array_equal(E1.col, E2.col)
+    assert np.array_equal(E1.val.view(np.uint64), E2.val.view(np.uint64))
