@@ -41,7 +41,57 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=150)
     ap.add_argument("--forward-only", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (the "
+                         "reference kernel for scaling HBM counter readings) and exit")
     return ap.parse_args()
+
+
+TILE_SOURCES = ("paper_2110_04493_amd/csrc/bsr.hip", "paper_2110_04493_amd/csrc/bsr_common.hpp")
+TRAFFIC_FILE = "profiles/k_bsr_numeric_grid300_traffic.md"
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TILE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the tile product from the committed counter
+    summary, or None when it is absent or the kernel source has changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes: int):
+    """A plain copy kernel of known size: torch's elementwise kernel for
+    dst = src * 1 reads and writes nbytes each."""
+    import torch
+    n = nbytes // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}), flush=True)
 
 
 def numeric_roofline(stats: dict, n: int):
@@ -61,6 +111,7 @@ def numeric_roofline(stats: dict, n: int):
         t += ms
         per.append({"step": i + 1, "ms": round(ms, 4), "gbps": round(b / (ms * 1e6), 1),
                     "tflops": round(f / (ms * 1e9), 3), "cand": cand,
+                    "path": "tiles" if stats["sq_tiles"][i] else "rows",
                     "kept": stats["sq_kept"][i]})
     return fl, by, t, per
 
@@ -71,6 +122,9 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus N > 1 is not "
                                    "supported (see the multi-GPU design notes)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import torch
     from paper_2110_04493_amd import api, workloads as W
 
@@ -99,6 +153,7 @@ def main():
         step()
     torch.cuda.synchronize()
     times, fwd_ms, bwd_ms, stats = [], [], [], None
+    tl = {"launches": 0, "ms": 0.0, "flops": 0.0, "adj_launches": 0, "adj_ms": 0.0}
     t_all0 = time.perf_counter()
     for _ in range(args.steps):
         torch.cuda.synchronize()
@@ -109,6 +164,11 @@ def main():
         stats = plan.stats()
         fwd_ms.append(stats["t_total_ms"])
         bwd_ms.append(stats["t_backward_ms"] if not args.forward_only else 0.0)
+        tl["launches"] += stats["tile_launches"]
+        tl["ms"] += stats["tile_ms"]
+        tl["flops"] += stats["tile_flops"]
+        tl["adj_launches"] += stats["adj_tile_launches"]
+        tl["adj_ms"] += stats["adj_tile_ms"]
     t_all = time.perf_counter() - t_all0
     plan.close()
     sec = t_all / args.steps
@@ -116,14 +176,25 @@ def main():
     fl, by, tnum, per = numeric_roofline(stats, n)
     tflops = fl / (tnum * 1e9)
     gbps = by / (tnum * 1e6)
-    bound = "alu" if fl / by > RIDGE else "hbm"
-    if bound == "alu":
-        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
-                "traffic": None}
+    if tl["launches"]:
+        # dominant kernel: the tile squaring product on FP64 matrix cores
+        avg_ms = tl["ms"] / tl["launches"]
+        fl_launch = tl["flops"] / tl["launches"]
+        ach = fl_launch / (avg_ms * 1e9)
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                "traffic": measured_traffic(), "kernel": "k_bsr_numeric",
+                "launches": tl["launches"], "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_flop_per_launch": round(fl_launch)}
     else:
-        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(gbps / PEAK_HBM_GBS, 4), "traffic": None}
+        bound = "alu" if fl / by > RIDGE else "hbm"
+        if bound == "alu":
+            roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP64_TFLOPS, 4)}
+        else:
+            roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(gbps / PEAK_HBM_GBS, 4)}
+        roof.update({"traffic": None, "kernel": "k_numeric"})
     t_bound = max(by / (PEAK_HBM_GBS * 1e9), fl / (PEAK_FP64_TFLOPS * 1e12)) * 1e3
     out = {
         "metric": METRIC, "value": round(sec, 5), "unit": "s", "n_gpus": 1,
@@ -140,7 +211,10 @@ def main():
         "forward_ms": round(float(np.median(fwd_ms)), 3),
         "adjoint_ms": round(float(np.median(bwd_ms)), 3),
         "roofline": roof,
-        "squaring_spgemm": {"kernel": "k_numeric", "ms": round(tnum, 3),
+        "adjoint_tile_kernel": {"kernel": "k_bsr_adjoint", "launches": tl["adj_launches"],
+                                "ms": round(tl["adj_ms"] / max(args.steps, 1), 3)},
+        "squaring_spgemm": {"kernel": "numeric pass (k_numeric rows / k_bsr_numeric tiles)",
+                            "ms": round(tnum, 3),
                             "algorithmic_GB": round(by / 1e9, 3),
                             "algorithmic_GFLOP": round(fl / 1e9, 2),
                             "hbm_gbps": round(gbps, 1), "hbm_frac": round(gbps / PEAK_HBM_GBS, 4),

@@ -119,6 +119,19 @@ typedef struct {
     int64_t sq_fma[EXPM_MAXSTEP], sq_in[EXPM_MAXSTEP];
     double t_sym_ms[EXPM_MAXSTEP], t_num_ms[EXPM_MAXSTEP], t_filter_ms[EXPM_MAXSTEP];
     double t_taylor_ms, t_backward_ms, t_total_ms;
+    /* with opts.profile, summed over every launch of the 16x16 tile squaring
+     * product since the last expm_sparse began (its forward steps, then the
+     * recomputation inside expm_sparse_backward): launches, device time in ms
+     * (events on the plan's stream around each launch), and algorithmic
+     * flops, 2 per partial product of T*T plus 2 per stored entry of T (the
+     * 2T term), zero padding of the tiles not counted.  adj_tile_* covers
+     * the tile kernel of the adjoint step the same way (time only). */
+    int64_t tile_launches;
+    double tile_ms, tile_flops;
+    int64_t adj_tile_launches;
+    double adj_tile_ms;
+    /* per squaring step: 1 if its product ran on 16x16 tiles, 0 on rows */
+    int sq_tiles[EXPM_MAXSTEP];
 } expm_stats;
 
 typedef struct expm_plan_s *expm_plan_t;

@@ -79,18 +79,24 @@ class expm_stats(C.Structure):
                 ("t_sym_ms", C.c_double * _S), ("t_num_ms", C.c_double * _S),
                 ("t_filter_ms", C.c_double * _S),
                 ("t_taylor_ms", C.c_double), ("t_backward_ms", C.c_double),
-                ("t_total_ms", C.c_double)]
+                ("t_total_ms", C.c_double),
+                ("tile_launches", C.c_int64), ("tile_ms", C.c_double),
+                ("tile_flops", C.c_double), ("adj_tile_launches", C.c_int64),
+                ("adj_tile_ms", C.c_double), ("sq_tiles", C.c_int * _S)]
 
     def to_dict(self) -> dict:
         d = {k: getattr(self, k) for k in ("status", "M", "N", "taylor_terms", "normal",
                                            "squarings", "a", "norm_h", "h0", "r0", "eg0",
                                            "nnz_e", "peak_workspace_bytes", "t_taylor_ms",
-                                           "t_backward_ms", "t_total_ms")}
+                                           "t_backward_ms", "t_total_ms", "tile_launches",
+                                           "tile_ms", "tile_flops", "adj_tile_launches",
+                                           "adj_tile_ms")}
         T, N = self.taylor_terms, self.squarings
         for k in ("taylor_theta", "taylor_iters", "taylor_cand", "taylor_kept"):
             d[k] = list(getattr(self, k)[2:T + 2])
         for k in ("sq_theta", "sq_normF", "sq_budget", "sq_dropped", "sq_iters", "sq_cand",
-                  "sq_kept", "sq_fma", "sq_in", "t_sym_ms", "t_num_ms", "t_filter_ms"):
+                  "sq_kept", "sq_fma", "sq_in", "t_sym_ms", "t_num_ms", "t_filter_ms",
+                  "sq_tiles"):
             d[k] = list(getattr(self, k)[1:N + 1])
         return d
 

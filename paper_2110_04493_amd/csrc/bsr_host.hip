@@ -66,7 +66,9 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     hipStream_t st = P.st;
     TileSet &ts = P.tsT;
     const int64_t n = T.n, nb = ts.nb;
-    const bool prof = P.opts.profile && P.have_events && stat_i > 0;
+    // profiling covers every launch (recomputation too); the per-step
+    // statistics only the forward steps (stat_i > 0)
+    const bool prof = P.opts.profile && P.have_events;
     int64_t *hl = (int64_t *)P.host;
     if (prof) {
         // algorithmic partial products of T*T (for the statistics only)
@@ -178,21 +180,27 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     HIPCHK(bsr_write(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
                      (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, ctl,
                      (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p, (double *)dst.v.p, st));
-    if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
-        expm_stats &S = P.stats;
-        if (prof) {
-            HIPCHK(hipEventRecord(P.ev[3], st));
-            HIPCHK(hipEventSynchronize(P.ev[3]));
-            float t0, t1, t2;
-            HIPCHK(hipEventElapsedTime(&t0, P.ev[0], P.ev[1]));
-            HIPCHK(hipEventElapsedTime(&t1, P.ev[1], P.ev[2]));
-            HIPCHK(hipEventElapsedTime(&t2, P.ev[2], P.ev[3]));
+    expm_stats &S = P.stats;
+    if (prof) {
+        HIPCHK(hipEventRecord(P.ev[3], st));
+        HIPCHK(hipEventSynchronize(P.ev[3]));
+        float t0, t1, t2;
+        HIPCHK(hipEventElapsedTime(&t0, P.ev[0], P.ev[1]));
+        HIPCHK(hipEventElapsedTime(&t1, P.ev[1], P.ev[2]));
+        HIPCHK(hipEventElapsedTime(&t2, P.ev[2], P.ev[3]));
+        const int64_t fma = hl[16] - T.nnz;
+        S.tile_launches += 1;
+        S.tile_ms += t1;
+        S.tile_flops += 2.0 * (double)fma + 2.0 * (double)T.nnz;
+        if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
             S.t_sym_ms[stat_i] = t0;
             S.t_num_ms[stat_i] = t1;
             S.t_filter_ms[stat_i] = t2;
-            S.sq_fma[stat_i] = hl[16] - T.nnz;
+            S.sq_fma[stat_i] = fma;
             S.sq_in[stat_i] = T.nnz;
         }
+    }
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
         S.sq_theta[stat_i] = h.theta;
         S.sq_iters[stat_i] = h.iter;
         S.sq_cand[stat_i] = cand_nz;
@@ -245,6 +253,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     CHK(sync(P));
     const int64_t nwork = hl[0];
     CHK(ensure(P, P.adj_tiles, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
+    const bool prof = P.opts.profile && P.have_events;
+    if (prof) HIPCHK(hipEventRecord(P.ev[4], st));
     HIPCHK(bsr_adjoint(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
                        (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (const double *)T.tA.p,
                        (const double *)T.tB.p, (const int32_t *)G.lo.p,
@@ -252,6 +262,14 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const int64_t *)G.tb.p, (const double *)G.tA.p,
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
                        (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p, nwork, st));
+    if (prof) {
+        HIPCHK(hipEventRecord(P.ev[5], st));
+        HIPCHK(hipEventSynchronize(P.ev[5]));
+        float t;
+        HIPCHK(hipEventElapsedTime(&t, P.ev[4], P.ev[5]));
+        P.stats.adj_tile_launches += 1;
+        P.stats.adj_tile_ms += t;
+    }
     HIPCHK(bsr_gather(Tp.view(), (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
                       (const uint2 *)T.rt.p, (const int64_t *)T.tb.p,
                       (const double *)P.adj_tiles.p, out, st));

@@ -503,6 +503,7 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
         }
         if (step >= 1) P.sq_path.push_back(tiles ? 1 : 0);
     }
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP) P.stats.sq_tiles[stat_i] = tiles ? 1 : 0;
     if (tiles) {
         if (!have_pattern) {
             double fill;

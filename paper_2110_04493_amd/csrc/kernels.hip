@@ -220,18 +220,34 @@ hipError_t add_scaled_ldexp(const double *a, const double *b, double *out, int64
 }
 
 __global__ void k_compare(CsrView A, CsrView B, int64_t nnz, int *flags) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j <= A.n && A.rp[j] != B.rp[j]) atomicAnd(&flags[0], 0);
-    if (j < nnz) {
-        if (A.ci[j] != B.ci[j]) atomicAnd(&flags[0], 0);
-        if (A.v[j] != B.v[j]) atomicAnd(&flags[1], 0);
-        if (A.v[j] != -B.v[j]) atomicAnd(&flags[2], 0);
+    // Grid-stride; each wave clears a flag with one atomic, and only when
+    // one of its lanes found a mismatch.
+    bool pat = false, eq = true, neg = true;
+    const int64_t m = nnz > A.n + 1 ? nnz : A.n + 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+        if (j <= A.n && A.rp[j] != B.rp[j]) pat = true;
+        if (j < nnz) {
+            if (A.ci[j] != B.ci[j]) pat = true;
+            const double a = A.v[j], b = B.v[j];
+            if (a != b) eq = false;
+            if (a != -b) neg = false;
+        }
+    }
+    const unsigned long long bp = __ballot(pat), be = __ballot(!eq), bn = __ballot(!neg);
+    if (lane_id() == 0) {
+        if (bp) atomicAnd(&flags[0], 0);
+        if (be) atomicAnd(&flags[1], 0);
+        if (bn) atomicAnd(&flags[2], 0);
     }
 }
 
 hipError_t compare_csr(CsrView A, CsrView B, int64_t nnz, int *flags, hipStream_t st) {
     int64_t m = nnz > A.n + 1 ? nnz : A.n + 1;
-    hipLaunchKernelGGL(k_compare, dim3((m + 255) / 256), dim3(256), 0, st, A, B, nnz, flags);
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_compare, dim3((unsigned)blocks), dim3(256), 0, st, A, B, nnz, flags);
     return hipGetLastError();
 }
 

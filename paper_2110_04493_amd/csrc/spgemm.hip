@@ -166,25 +166,41 @@ static Caps make_caps(int kind) {
     return caps;
 }
 
-__device__ __forceinline__ void bin_one(int64_t i, int64_t n, int64_t bytes, const Caps &caps,
-                                        int *counts, int32_t *lists) {
+// Appends row i to its class list.  All lanes of the wave call it (valid =
+// the lane has a row); the lanes of one class share a single atomic, so the
+// handful of class counters see one update per class per wave.
+__device__ __forceinline__ void bin_one(int64_t i, bool valid, int64_t n, int64_t bytes,
+                                        const Caps &caps, int *counts, int32_t *lists) {
     int cls = caps.ncls - 1;
     for (int j = 0; j < caps.ncls - 1; j++)
         if (bytes <= caps.cap[j]) {
             cls = j;
             break;
         }
-    int pos = atomicAdd(&counts[cls], 1);
-    lists[(int64_t)cls * n + pos] = (int32_t)i;
+    if (!valid) cls = -1;
+    const unsigned long long lt = (1ull << lane_id()) - 1ull;
+    for (int c = 0; c < caps.ncls; ++c) {
+        const unsigned long long m = __ballot(cls == c);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&counts[c], __popcll(m));
+        base = __shfl(base, leader);
+        if (cls == c) lists[(int64_t)c * n + base + __popcll(m & lt)] = (int32_t)i;
+    }
 }
 
 __global__ void k_bin(const int64_t *woff, const int64_t *crp, int64_t n, int kind, Caps caps,
                       int *counts, int32_t *lists) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t W = woff[i + 1] - woff[i];
-    int64_t c = crp ? crp[i + 1] - crp[i] : 0;
-    bin_one(i, n, row_bytes(kind, W, c), caps, counts, lists);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    int64_t bytes = 0;
+    if (valid) {
+        const int64_t W = woff[i + 1] - woff[i];
+        const int64_t c = crp ? crp[i + 1] - crp[i] : 0;
+        bytes = row_bytes(kind, W, c);
+    }
+    bin_one(i, valid, n, bytes, caps, counts, lists);
 }
 
 hipError_t bin_rows(const int64_t *woff, const int64_t *crp, int64_t n, int kind, int *counts,
@@ -544,13 +560,16 @@ __global__ __launch_bounds__(512) void k_masked(
 }
 
 __global__ void k_masked_bin(CsrView M, Caps caps, int *counts, int32_t *lists, int64_t *sb) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M.n) return;
-    const int64_t o = M.rp[i], c = M.rp[i + 1] - o;
-    const int64_t W = c ? ((M.ci[o + c - 1] - (M.ci[o] & ~31)) >> 5) + 1 : 0;
-    const int64_t bytes = row_bytes(1, W, c);
-    bin_one(i, M.n, bytes, caps, counts, lists);
-    sb[i] = bytes <= kNumCap[kNumClasses - 2] ? 0 : (bytes + 255) & ~int64_t(255);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < M.n;
+    int64_t bytes = 0;
+    if (valid) {
+        const int64_t o = M.rp[i], c = M.rp[i + 1] - o;
+        const int64_t W = c ? ((M.ci[o + c - 1] - (M.ci[o] & ~31)) >> 5) + 1 : 0;
+        bytes = row_bytes(1, W, c);
+    }
+    bin_one(i, valid, M.n, bytes, caps, counts, lists);
+    if (valid) sb[i] = bytes <= kNumCap[kNumClasses - 2] ? 0 : (bytes + 255) & ~int64_t(255);
 }
 
 // scratch layout: sb[n+1] int64 | off[n+1] int64 | counts[16] int |
