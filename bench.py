@@ -60,10 +60,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(flop_per_launch: float):
     """HBM bytes per launch of the tile product from the committed counter
-    summary, or None when it is absent or the kernel source has changed since
-    the counters were taken."""
+    summary, or None when it is absent, the kernel source has changed since
+    the counters were taken, or the launches do different work (the summary's
+    algorithmic flops per launch differ from this run's by more than 1%)."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -76,6 +77,9 @@ def measured_traffic():
     if kv.get("kernel_source_sha256") != kernel_source_digest():
         return None
     try:
+        ref = float(kv["algorithmic_flop_per_launch"])
+        if abs(ref - flop_per_launch) > 0.01 * ref:
+            return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -183,7 +187,7 @@ def main():
         ach = fl_launch / (avg_ms * 1e9)
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
-                "traffic": measured_traffic(), "kernel": "k_bsr_numeric",
+                "traffic": measured_traffic(fl_launch), "kernel": "k_bsr_numeric",
                 "launches": tl["launches"], "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_flop_per_launch": round(fl_launch)}
     else:

@@ -95,6 +95,14 @@ typedef struct {
                                 step with HIP events on `stream` and count
                                 the algorithmic work (fields t_* and sq_fma,
                                 sq_in of expm_stats); 0 (default): off        */
+    int reorder;             /* locality reordering: the rows and columns of H
+                                are permuted symmetrically (2D cells from graph
+                                distances) before the method runs and E is
+                                permuted back, so that band tiles of the late
+                                squarings are fuller.  Results are those of
+                                the unpermuted method up to rounding order.
+                                -1 (default) on for n >= 4096 when the tile
+                                product can run, 0 off, 1 on                  */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',

@@ -70,6 +70,7 @@ class Options:
     keep_checkpoints: bool = False
     checkpoint_interval: int = 0
     profile: bool = False
+    reorder: int = -1
 
 
 class Plan:
@@ -92,6 +93,7 @@ class Plan:
         o.stream = self.stream.cuda_stream
         o.allocator = C.pointer(self.alloc.struct)
         o.profile = int(self.options.profile)
+        o.reorder = int(self.options.reorder)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)

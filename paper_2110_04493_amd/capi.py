@@ -57,7 +57,8 @@ class expm_opts(C.Structure):
     _fields_ = [("normal", C.c_int), ("filter_mode", C.c_int), ("e_r", C.c_double),
                 ("max_filter_iter", C.c_int), ("keep_checkpoints", C.c_int),
                 ("checkpoint_interval", C.c_int), ("stream", C.c_void_p),
-                ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int)]
+                ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int),
+                ("reorder", C.c_int)]
 
 
 _S = EXPM_MAXSTEP

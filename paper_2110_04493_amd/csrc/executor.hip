@@ -561,6 +561,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     free_adjoint_state(P);
     memset(&P.stats, 0, sizeof P.stats);
     P.have_stats = false;
+    P.perm_active = false;
     P.peak = P.live;
     if (n == 0) {
         E->n = 0;
@@ -629,6 +630,25 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     S.N = N;
     S.normal = normal;
     S.a = a;
+    const bool keep = P.opts.keep_checkpoints != 0;
+    // Locality reordering: H' = P H P^T replaces H; E is permuted back below.
+    {
+        const int ro = P.opts.reorder;
+        if (ro == 1 || (ro < 0 && n >= 4096 && tiles_allowed(P, n)))
+            CHK(compute_reorder(P, P.H0.view(), &P.perm_active));
+        if (P.perm_active) {
+            CHK(ensure_csr(P, P.Hp, n, nnz));
+            int64_t *hm = nullptr;
+            if (keep) {
+                CHK(ensure(P, P.hmap, sizeof(int64_t) * (nnz + 1)));
+                hm = (int64_t *)P.hmap.p;
+            }
+            CHK(permute_csr(P, P.H0.view(), nnz, (const int32_t *)P.order.p,
+                            (const int32_t *)P.newidx.p, (int64_t *)P.Hp.rp.p,
+                            (int32_t *)P.Hp.ci.p, (double *)P.Hp.v.p, hm));
+            std::swap(P.H0, P.Hp);
+        }
+    }
     const auto t_taylor0 = std::chrono::steady_clock::now();
     // Step 3: H0 = H 2^-N, r0, eg0, Taylor seed.
     HIPCHK(scale_ldexp((const double *)P.H0.v.p, (double *)P.H0.v.p, nnz, -N, st));
@@ -637,7 +657,6 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     S.h0 = h0;
     S.r0 = r0;
     S.eg0 = eg0;
-    const bool keep = P.opts.keep_checkpoints != 0;
     P.M = M;
     P.N = N;
     P.a = a;
@@ -727,11 +746,30 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
             return fail(EXPM_ENOMEM, "cannot allocate the output (%lld entries)",
                         (long long)kept);
         }
-        HIPCHK(hipMemcpyAsync(rp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+        // with reordering E' = I + T'_N goes to workspace and is permuted back
+        int64_t *erp = rp;
+        int32_t *eci = ci;
+        double *ev = v;
+        if (P.perm_active) {
+            CHK(ensure_csr(P, P.Eperm, n, kept));
+            erp = (int64_t *)P.Eperm.rp.p;
+            eci = (int32_t *)P.Eperm.ci.p;
+            ev = (double *)P.Eperm.v.p;
+        }
+        HIPCHK(hipMemcpyAsync(erp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
                               st));
         HIPCHK(write_kept((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
-                          (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, rp, ci, v,
+                          (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, erp, eci, ev,
                           st));
+        if (P.perm_active) {
+            int64_t *em = nullptr;
+            if (keep) {
+                CHK(ensure(P, P.emap, sizeof(int64_t) * (kept + 1)));
+                em = (int64_t *)P.emap.p;
+            }
+            CHK(permute_csr(P, P.Eperm.view(), kept, (const int32_t *)P.newidx.p,
+                            (const int32_t *)P.order.p, rp, ci, v, em));
+        }
         E->n = n;
         E->nnz = kept;
         E->rowptr = rp;
@@ -740,10 +778,10 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         S.nnz_e = kept;
         if (keep) {
             CHK(ensure_csr(P, P.Epat, n, kept));
-            HIPCHK(hipMemcpyAsync(P.Epat.rp.p, rp, sizeof(int64_t) * (n + 1),
+            HIPCHK(hipMemcpyAsync(P.Epat.rp.p, erp, sizeof(int64_t) * (n + 1),
                                   hipMemcpyDeviceToDevice, st));
             if (kept)
-                HIPCHK(hipMemcpyAsync(P.Epat.ci.p, ci, sizeof(int32_t) * kept,
+                HIPCHK(hipMemcpyAsync(P.Epat.ci.p, eci, sizeof(int32_t) * kept,
                                       hipMemcpyDeviceToDevice, st));
         }
     }
@@ -765,9 +803,16 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         return EXPM_OK;
     }
     const int N = P.N, ck = P.ck;
-    // G_N on supp(T_N): E = I + T_N.
-    CsrView Ev = CsrView{n, (const int64_t *)P.Epat.rp.p, (const int32_t *)P.Epat.ci.p, dE};
-    Buf g, gn;
+    // G_N on supp(T_N): E = I + T_N.  With reordering dE is first moved onto
+    // the entries of E' (the pattern kept in Epat).
+    Buf g, gn, dEp, dHp;
+    const double *dEu = dE;
+    if (P.perm_active) {
+        CHK(ensure(P, dEp, sizeof(double) * (P.Epat.nnz + 1)));
+        CHK(scatter_map(P, dE, (const int64_t *)P.emap.p, P.Epat.nnz, (double *)dEp.p));
+        dEu = (const double *)dEp.p;
+    }
+    CsrView Ev = CsrView{n, (const int64_t *)P.Epat.rp.p, (const int32_t *)P.Epat.ci.p, dEu};
     CHK(ensure(P, g, sizeof(double) * (P.TN.nnz + 1)));
     MaskTerm none{empty_view(), empty_view(), 0.0};
     CHK(masked(P, P.TN.view(), Ev, 1.0, none, none, 1.0, (double *)g.p));
@@ -853,13 +898,24 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
                    (double *)acc2.p));
         std::swap(acc, acc2);
     }
-    // dH = 2^-N (acc + D_1); S^_1 = H0 shares H's pattern.
-    HIPCHK(add_scaled_ldexp((const double *)acc.p, (const double *)D[1].p, dH, nnzH, -N, st));
+    // dH = 2^-N (acc + D_1); S^_1 = H0 shares H's pattern (H' with reordering,
+    // whose entries hmap sends back to H's).
+    if (P.perm_active) {
+        CHK(ensure(P, dHp, sizeof(double) * (nnzH + 1)));
+        HIPCHK(add_scaled_ldexp((const double *)acc.p, (const double *)D[1].p,
+                                (double *)dHp.p, nnzH, -N, st));
+        CHK(scatter_map(P, (const double *)dHp.p, (const int64_t *)P.hmap.p, nnzH, dH));
+    } else {
+        HIPCHK(add_scaled_ldexp((const double *)acc.p, (const double *)D[1].p, dH, nnzH, -N,
+                                st));
+    }
     for (auto &b : D) release(P, b);
     release(P, acc);
     release(P, acc2);
     release(P, g);
     release(P, gn);
+    release(P, dEp);
+    release(P, dHp);
     release(P, Tt);
     release(P, H0t);
     release(P, St);
@@ -885,6 +941,7 @@ void expm_opts_default(expm_opts *o) {
     o->checkpoint_interval = 0;
     o->stream = nullptr;
     o->allocator = nullptr;
+    o->reorder = -1;
 }
 
 int expm_plan(expm_plan_t *out, const expm_opts *opts) {
@@ -899,7 +956,7 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.filter_mode != EXPM_FILTER_PAPER && o.filter_mode != EXPM_FILTER_NONE)
         return fail(EXPM_EINVAL, "unknown filter_mode %d", o.filter_mode);
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
-        o.checkpoint_interval < 0)
+        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1)
         return fail(EXPM_EINVAL, "invalid option value");
     expm_plan_s *P = new (std::nothrow) expm_plan_s();
     if (!P) return fail(EXPM_ENOMEM, "cannot allocate the plan");

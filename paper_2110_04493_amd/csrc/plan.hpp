@@ -79,6 +79,13 @@ struct expm_plan_s {
     // block-column lists of T (the block rows of T^T) for the adjoint
     xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles;
     std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows
+    // locality reordering: order (new -> old), newidx (old -> new); H' = P H P^T
+    // replaces H0 and E = P^T E' P; hmap / emap give, for each entry of H' / of
+    // the returned E, the index of the matching entry of H / of E'
+    bool perm_active = false;
+    xpm::host::Buf order, newidx, hmap, emap, ro_rb, ro_d0, ro_d1, ro_d3, ro_q0, ro_q1, ro_cell,
+        ro_cnt, ro_off, ro_pcnt, ro_pw, ro_pofs, ro_gbits;
+    xpm::host::DCsr Hp, Eperm;
     // tile fill of T from which the tile product is used; on MI355X at
     // n = 90,000 the two paths cost the same at a fill of about 0.2
     double bsr_min_fill = 0.2;
@@ -118,6 +125,10 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
                      double *out);
 void release(expm_plan_s &P, TileSet &ts);
+int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
+int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
+                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap);
+int scatter_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst);
 
 }  // namespace host
 }  // namespace xpm

@@ -1,0 +1,366 @@
+// Locality reordering: a symmetric permutation P applied as H' = P H P^T
+// before the method runs, and E = P^T E' P after it.
+//
+// Every step of Algorithm 4.2 commutes with a symmetric permutation: the
+// products, the Frobenius norms and the filter of Algorithm 4.1 (an entry is
+// kept by its magnitude against a global threshold) give the permuted result
+// up to the order of floating-point sums.  The permutation only changes which
+// rows share a 16 x 16 tile.  In natural order a 2D grid puts 16 consecutive
+// nodes on one grid line, so a tile row touches the whole band of every
+// neighbouring line; grouping nodes into compact 2D cells roughly halves the
+// tiles per block row and the matrix-core work of the late squarings.
+//
+// The cells come from graph distances alone, with no coordinates: breadth-
+// first distances d1, d3 from two far-apart nodes (u1, found from node 0,
+// and u3, the node farthest from both u1 and the node u2 farthest from u1)
+// act as two coordinates, and nodes are grouped by (d1 / 4, d3 / 8) and
+// ordered by cell, then by index.  Graphs without such structure (small
+// diameter, so very full cells) keep their order.
+#include <string.h>
+
+#include "plan.hpp"
+
+namespace xpm {
+
+constexpr int kBfsThreads = 1024;
+constexpr int kCellMax = 256;      // largest cell the ordering accepts
+constexpr int kPermLdsWords = 4096;
+
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__device__ __forceinline__ long long wave_max_ll(long long x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const long long y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Breadth-first distances from *srcp over G's out-edges, in one workgroup
+// (level-synchronous; the frontier of a mesh is small).  dist must hold -1.
+// Nodes not reached get (largest distance + 1).  Writes res[0] = the node
+// maximising dist (or min(dist, other) when other is given), smallest index
+// on ties, and res[1] = the largest distance.
+__global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *srcp,
+                                                     int32_t *dist, int32_t *q0, int32_t *q1,
+                                                     const int32_t *other, int32_t *res) {
+    __shared__ int s_next, s_size;
+    __shared__ long long s_best[kBfsThreads / kWave];
+    __shared__ int s_unreached;
+    const int tid = threadIdx.x;
+    const int64_t n = G.n;
+    if (tid == 0) {
+        const int src = *srcp;
+        atomicExch(&dist[src], 0);
+        q0[0] = src;
+        s_size = 1;
+        s_next = 0;
+        s_unreached = 0;
+    }
+    __syncthreads();
+    int level = 0;
+    int32_t *cur = q0, *nxt = q1;
+    for (;;) {
+        const int size = s_size;
+        if (size == 0) break;
+        for (int i = tid; i < size; i += kBfsThreads) {
+            const int v = cur[i];
+            for (int64_t p = G.rp[v]; p < G.rp[v + 1]; ++p) {
+                const int u = G.ci[p];
+                // a stale -1 only costs a failed compare-and-swap
+                if (dist[u] == -1 && atomicCAS(&dist[u], -1, level + 1) == -1)
+                    nxt[atomicAdd(&s_next, 1)] = u;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_size = s_next;
+            s_next = 0;
+        }
+        __syncthreads();
+        int32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        ++level;
+    }
+    // level - 1 is the largest distance reached
+    long long best = -1;
+    for (int64_t v = tid; v < n; v += kBfsThreads) {
+        int d = __hip_atomic_load(&dist[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (d < 0) {
+            d = level;
+            dist[v] = d;
+            s_unreached = 1;
+        }
+        const int key = other ? min(d, other[v]) : d;
+        const long long pk = ((long long)key << 32) | (long long)(0x7fffffff - (int)v);
+        best = pk > best ? pk : best;
+    }
+    best = wave_max_ll(best);
+    if (lane_id() == 0) s_best[tid / kWave] = best;
+    __syncthreads();
+    if (tid == 0) {
+        long long b = s_best[0];
+        for (int w = 1; w < kBfsThreads / kWave; ++w) b = s_best[w] > b ? s_best[w] : b;
+        res[0] = 0x7fffffff - (int)(b & 0xffffffffll);
+        res[1] = s_unreached ? level : level - 1;
+    }
+}
+
+// Cell of every node and the cell populations.
+__global__ void k_cell_count(int64_t n, const int32_t *d1, const int32_t *d3, int64_t kb,
+                             int64_t *cell, int64_t *cnt) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t c = (int64_t)(d1[v] / 4) * kb + d3[v] / 8;
+    cell[v] = c;
+    atomicAdd((unsigned long long *)&cnt[c], 1ull);
+}
+
+__global__ void k_max_i64(const int64_t *a, int64_t n, int32_t *out) {
+    __shared__ long long s[256 / kWave];
+    long long m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = a[i] > m ? a[i] : m;
+    m = wave_max_ll(m);
+    if (lane_id() == 0) s[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long b = s[0];
+        for (int w = 1; w < 256 / kWave; ++w) b = s[w] > b ? s[w] : b;
+        atomicMax(out, (int)(b < 0x7fffffff ? b : 0x7fffffff));
+    }
+}
+
+__global__ void k_cell_scatter(int64_t n, const int64_t *cell, const int64_t *coff,
+                               int64_t *cfill, int32_t *tmp) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t c = cell[v];
+    const int64_t pos = coff[c] + (int64_t)atomicAdd((unsigned long long *)&cfill[c], 1ull);
+    tmp[pos] = (int32_t)v;
+}
+
+// One wave per cell: members in ascending node index (rank by counting).
+__global__ void k_cell_sort(int64_t ncell, const int64_t *coff, const int32_t *tmp,
+                            int32_t *order, int32_t *newidx) {
+    const int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (c >= ncell) return;
+    const int64_t o = coff[c];
+    const int k = (int)(coff[c + 1] - o);
+    for (int j = lane_id(); j < k; j += kWave) {
+        const int32_t x = tmp[o + j];
+        int r = 0;
+        for (int i = 0; i < k; ++i) r += tmp[o + i] < x;
+        order[o + r] = x;
+        newidx[x] = (int32_t)(o + r);
+    }
+}
+
+// Permuted rows: output row r is input row src_row[r] with its columns
+// mapped through colmap.  Per output row: its length and, when its column
+// window is wider than the LDS bit map, the number of global words.
+__global__ void k_perm_words(CsrView X, const int32_t *src_row, const int32_t *colmap,
+                             int64_t *cnt, int64_t *gwords) {
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (r >= X.n) return;
+    const int32_t s = src_row[r];
+    const int64_t b = X.rp[s], e = X.rp[s + 1];
+    int mn = INT32_MAX, mx = -1;
+    for (int64_t p = b + lane_id(); p < e; p += kWave) {
+        const int c = colmap[X.ci[p]];
+        mn = min(mn, c);
+        mx = max(mx, c);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane_id() == 0) {
+        cnt[r] = e - b;
+        const int64_t W = mx < 0 ? 0 : (((int64_t)mx - (mn & ~31)) >> 5) + 1;
+        gwords[r] = W > kPermLdsWords ? W : 0;
+    }
+}
+
+// One wave per output row.  The mapped columns are marked in a bit map over
+// the row's window; the rank of a column (prefix count + bits below it) is
+// its position in the sorted output row.  emap (optional) receives, for
+// every output entry, the index of its input entry.
+__global__ __launch_bounds__(64) void k_perm_rows(CsrView X, const int32_t *src_row,
+                                                  const int32_t *colmap, const int64_t *orp,
+                                                  int32_t *oci, double *ov, int64_t *emap,
+                                                  const int64_t *gofs, uint2 *gbits) {
+    __shared__ uint2 lbits[kPermLdsWords];
+    const int64_t r = blockIdx.x;
+    if (r >= X.n) return;
+    const int lane = lane_id();
+    const int32_t s = src_row[r];
+    const int64_t b = X.rp[s], e = X.rp[s + 1];
+    if (e == b) return;
+    int mn = INT32_MAX, mx = -1;
+    for (int64_t p = b + lane; p < e; p += kWave) {
+        const int c = colmap[X.ci[p]];
+        mn = min(mn, c);
+        mx = max(mx, c);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    const int lo = mn & ~31;
+    const int64_t W = (((int64_t)mx - lo) >> 5) + 1;
+    // The bit map lives in LDS, or for very wide windows in this row's slice
+    // of global scratch; every access goes through device-coherent atomics so
+    // that the global case never reads a stale cache line.
+    uint32_t *bits = W > kPermLdsWords ? (uint32_t *)(gbits + gofs[r]) : (uint32_t *)lbits;
+    auto ld = [](uint32_t *a) {
+        return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto st = [](uint32_t *a, uint32_t v) {
+        __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    for (int64_t w = lane; w < W; w += kWave) {
+        st(&bits[2 * w], 0u);
+        st(&bits[2 * w + 1], 0u);
+    }
+    __syncthreads();
+    for (int64_t p = b + lane; p < e; p += kWave) {
+        const int d = colmap[X.ci[p]] - lo;
+        atomicOr(&bits[2 * (d >> 5)], 1u << (d & 31));
+    }
+    __syncthreads();
+    unsigned carry = 0;
+    for (int64_t w0 = 0; w0 < W; w0 += kWave) {
+        const int64_t w = w0 + lane;
+        const unsigned pc = w < W ? __popc(ld(&bits[2 * w])) : 0u;
+        const unsigned inc = wave_incl_scan(pc);
+        if (w < W) st(&bits[2 * w + 1], carry + inc - pc);
+        carry += __shfl(inc, kWave - 1);
+    }
+    __syncthreads();
+    const int64_t ob = orp[r];
+    for (int64_t p = b + lane; p < e; p += kWave) {
+        const int c = colmap[X.ci[p]];
+        const int d = c - lo;
+        const uint32_t wx = ld(&bits[2 * (d >> 5)]), wy = ld(&bits[2 * (d >> 5) + 1]);
+        const int64_t q = ob + wy + __popc(wx & ((1u << (d & 31)) - 1u));
+        oci[q] = c;
+        ov[q] = X.v[p];
+        if (emap) emap[q] = p;
+    }
+}
+
+__global__ void k_scatter_map(const double *src, const int64_t *map, int64_t m, double *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) dst[map[i]] = src[i];
+}
+
+static unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+namespace host {
+
+// Computes the cell ordering of G's pattern into P.order (new -> old) and
+// P.newidx (old -> new); *active = false when the graph has no usable 2D
+// structure (then nothing is permuted).
+int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
+    hipStream_t st = P.st;
+    const int64_t n = G.n;
+    *active = false;
+    if (n < 2) return EXPM_OK;
+    CHK(ensure(P, P.ro_rb, sizeof(int32_t) * 16));
+    CHK(ensure(P, P.ro_d0, sizeof(int32_t) * n));
+    CHK(ensure(P, P.ro_d1, sizeof(int32_t) * n));
+    CHK(ensure(P, P.ro_d3, sizeof(int32_t) * n));
+    CHK(ensure(P, P.ro_q0, sizeof(int32_t) * n));
+    CHK(ensure(P, P.ro_q1, sizeof(int32_t) * n));
+    int32_t *rb = (int32_t *)P.ro_rb.p, *d0 = (int32_t *)P.ro_d0.p, *d1 = (int32_t *)P.ro_d1.p,
+            *d3 = (int32_t *)P.ro_d3.p, *q0 = (int32_t *)P.ro_q0.p, *q1 = (int32_t *)P.ro_q1.p;
+    HIPCHK(hipMemsetAsync(rb, 0, sizeof(int32_t) * 16, st));
+    auto bfs = [&](const int32_t *srcp, int32_t *dist, const int32_t *other, int32_t *res) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, dist, n, -1);
+        hipLaunchKernelGGL(k_bfs, dim3(1), dim3(kBfsThreads), 0, st, G, srcp, dist, q0, q1, other,
+                           res);
+        return hipGetLastError();
+    };
+    // rb: [0] node 0 | [1..2] u1, max d0 | [3..4] u2, max d1 | [5..6] u3 | [7..8] -, max d3
+    HIPCHK(bfs(rb + 0, d0, nullptr, rb + 1));
+    HIPCHK(bfs(rb + 1, d1, nullptr, rb + 3));
+    HIPCHK(bfs(rb + 3, d0, d1, rb + 5));
+    HIPCHK(bfs(rb + 5, d3, nullptr, rb + 7));
+    int32_t *hb = (int32_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hb, rb, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    const int64_t maxd1 = hb[4], maxd3 = hb[8];
+    const int64_t kb = maxd3 / 8 + 1, ncell = (maxd1 / 4 + 1) * kb;
+    if (ncell > 4 * n + 1024) return EXPM_OK;   // path-like: the natural order is kept
+    CHK(ensure(P, P.ro_cell, sizeof(int64_t) * n));
+    CHK(ensure(P, P.ro_cnt, sizeof(int64_t) * (ncell + 1)));
+    CHK(ensure(P, P.ro_off, sizeof(int64_t) * (ncell + 1)));
+    int64_t *cell = (int64_t *)P.ro_cell.p, *cnt = (int64_t *)P.ro_cnt.p,
+            *off = (int64_t *)P.ro_off.p;
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (ncell + 1), st));
+    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d1, d3, kb,
+                       cell, cnt);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_max_i64, dim3(blocks_for(ncell, 256) < 1024 ? blocks_for(ncell, 256)
+                                                                       : 1024),
+                       dim3(256), 0, st, cnt, ncell, rb + 9);
+    HIPCHK(hipGetLastError());
+    CHK(scan(P, cnt, off, ncell));
+    HIPCHK(hipMemcpyAsync(hb + 9, rb + 9, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    if (hb[9] > kCellMax) return EXPM_OK;       // no 2D structure: keep the order
+    CHK(ensure(P, P.order, sizeof(int32_t) * n));
+    CHK(ensure(P, P.newidx, sizeof(int32_t) * n));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (ncell + 1), st));
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, cell, off,
+                       cnt, q0);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(ncell, 4)), dim3(256), 0, st, ncell, off,
+                       q0, (int32_t *)P.order.p, (int32_t *)P.newidx.p);
+    HIPCHK(hipGetLastError());
+    *active = true;
+    return EXPM_OK;
+}
+
+// Output CSR (orp, oci, ov; caller-allocated, nnz entries) whose row r is
+// row src_row[r] of X with columns mapped by colmap, sorted.
+int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
+                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap) {
+    hipStream_t st = P.st;
+    const int64_t n = X.n;
+    CHK(ensure(P, P.ro_pcnt, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.ro_pw, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.ro_pofs, sizeof(int64_t) * (n + 1)));
+    int64_t *pc = (int64_t *)P.ro_pcnt.p, *pw = (int64_t *)P.ro_pw.p,
+            *pofs = (int64_t *)P.ro_pofs.p;
+    hipLaunchKernelGGL(k_perm_words, dim3(blocks_for(n, 4)), dim3(256), 0, st, X, src_row, colmap,
+                       pc, pw);
+    HIPCHK(hipGetLastError());
+    CHK(scan(P, pc, orp, n));
+    CHK(scan(P, pw, pofs, n));
+    int64_t *hl = (int64_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hl, pofs + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    const int64_t gw = hl[0];
+    CHK(ensure(P, P.ro_gbits, sizeof(uint2) * (gw + 1)));
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_perm_rows, dim3((unsigned)n), dim3(64), 0, st, X, src_row, colmap,
+                           orp, oci, ov, emap, pofs, (uint2 *)P.ro_gbits.p);
+        HIPCHK(hipGetLastError());
+    }
+    return EXPM_OK;
+}
+
+int scatter_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst) {
+    if (m <= 0) return EXPM_OK;
+    hipLaunchKernelGGL(k_scatter_map, dim3(blocks_for(m, 256)), dim3(256), 0, P.st, src, map, m,
+                       dst);
+    HIPCHK(hipGetLastError());
+    return EXPM_OK;
+}
+
+}  // namespace host
+}  // namespace xpm

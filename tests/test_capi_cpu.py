@@ -33,8 +33,8 @@ def test_library_exports_every_symbol():
 
 def test_defaults():
     o = capi.expm_opts_default()
-    assert (o.normal, o.filter_mode, o.e_r, o.max_filter_iter, o.keep_checkpoints) == \
-        (-1, 0, 0.1, 64, 0)
+    assert (o.normal, o.filter_mode, o.e_r, o.max_filter_iter, o.keep_checkpoints,
+            o.reorder) == (-1, 0, 0.1, 64, 0, -1)
     assert capi.expm_last_error() == ""
 
 

@@ -1,7 +1,7 @@
 """Both squaring paths (16x16 tiles on matrix cores, scalar rows) forced on
-their own, forward and adjoint, against the oracle; tile and scalar results
-agree with each other to the parity bar.  EXPM_BSR_FILL is read when a plan
-is created: 0 takes tiles at every squaring step, 2 never."""
+their own, with and without the locality reordering, forward and adjoint,
+against the oracle.  EXPM_BSR_FILL is read when a plan is created: 0 takes
+tiles at every squaring step, 2 never."""
 import numpy as np
 import pytest
 
@@ -20,35 +20,65 @@ def cases():
     yield "tridiag", W.tridiag(1000, 1.0, -2.0, 1.0, 10.0), 1e-14
     yield "general", W.random_sparse(150, 0.03, 3, kind="general", scale=1.2), 1e-12
     yield "adjacency", W.config4_instance(1, nmin=100, nmax=300)[0], 1e-12
+    yield "disconnected", disconnected(), 1e-12
 
 
+def disconnected():
+    """Two components of different shape plus isolated nodes (empty rows)."""
+    rng = np.random.default_rng(12)
+    A = W.grid_laplacian(20, 23, rng).scaled(-0.4)
+    B = W.tridiag(300, 1.0, -2.0, 1.0, 3.0)
+    n = A.n + B.n + 5
+    r = np.concatenate([A.rows(), B.rows() + A.n])
+    c = np.concatenate([A.col.astype(np.int64), B.col.astype(np.int64) + A.n])
+    v = np.concatenate([A.val, B.val])
+    return W.csr_from_coo(n, r, c, v)
+
+
+@pytest.mark.parametrize("reorder", [0, 1])
 @pytest.mark.parametrize("fill", ["0", "2"])
 @pytest.mark.parametrize("name,H,eps", list(cases()), ids=[c[0] for c in cases()])
-def test_forward_paths(monkeypatch, fill, name, H, eps):
+def test_forward_paths(monkeypatch, fill, reorder, name, H, eps):
     monkeypatch.setenv("EXPM_BSR_FILL", fill)
-    Eg, sg = run_gpu(H, eps)
+    print(f"[{name} fill={fill} reorder={reorder}] n={H.n}", flush=True)
+    Eg, sg = run_gpu(H, eps, reorder=reorder)
     Eo, so = run_oracle(H, eps)
     rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
-    print(f"[{name} fill={fill}] relF={rel:.2e} only={og},{oo}", flush=True)
+    print(f"[{name} fill={fill} reorder={reorder}] relF={rel:.2e} only={og},{oo}", flush=True)
     assert rel <= TOL and ok
     assert (sg["M"], sg["N"]) == (so["M"], so["N"])
 
 
+@pytest.mark.parametrize("reorder", [0, 1])
 @pytest.mark.parametrize("fill", ["0", "2"])
 @pytest.mark.parametrize("name,H,eps", list(cases()), ids=[c[0] for c in cases()])
-def test_adjoint_paths(monkeypatch, fill, name, H, eps):
+def test_adjoint_paths(monkeypatch, fill, reorder, name, H, eps):
     monkeypatch.setenv("EXPM_BSR_FILL", fill)
-    dg, _ = gpu_grad(H, eps, density=0.2, checkpoint_interval=2)
+    print(f"[{name} fill={fill} reorder={reorder}] adjoint n={H.n}", flush=True)
+    dg, _ = gpu_grad(H, eps, density=0.2, checkpoint_interval=2, reorder=reorder)
     do, _ = oracle_grad(H, eps, density=0.2)
     rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
-    print(f"[{name} fill={fill}] adjoint rel={rel:.2e}", flush=True)
+    print(f"[{name} fill={fill} reorder={reorder}] adjoint rel={rel:.2e}", flush=True)
     assert rel <= TOL
 
 
-def test_tiles_deterministic(monkeypatch):
+@pytest.mark.parametrize("reorder", [0, 1])
+def test_tiles_deterministic(monkeypatch, reorder):
     monkeypatch.setenv("EXPM_BSR_FILL", "0")
     H, eps = W.config5(40)
-    E1, _ = run_gpu(H, eps)
-    E2, _ = run_gpu(H, eps)
+    E1, _ = run_gpu(H, eps, reorder=reorder)
+    E2, _ = run_gpu(H, eps, reorder=reorder)
     assert np.array_equal(E1.col, E2.col)
     assert np.array_equal(E1.val.view(np.uint64), E2.val.view(np.uint64))
+
+
+def test_reorder_matches_natural_order():
+    """The permuted run returns the same E as the natural-order run up to
+    rounding order (entries that flip across the threshold aside)."""
+    H, eps = W.config5(60)
+    Ea, sa = run_gpu(H, eps, reorder=0)
+    Eb, sb = run_gpu(H, eps, reorder=1)
+    rel, ok, og, oo = compare(Eb, Ea, sa["sq_theta"][-1])
+    print(f"[reorder vs natural] relF={rel:.2e} only={og},{oo}", flush=True)
+    assert rel <= 1e-13 and ok
+    assert (sa["M"], sa["N"]) == (sb["M"], sb["N"])
