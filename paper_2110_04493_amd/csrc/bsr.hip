@@ -25,6 +25,9 @@
 
 namespace xpm {
 
+constexpr int kPanel = 4;        // block rows per panel (one wave each)
+constexpr int kPanelGroup = 4;   // output tiles per wave
+
 // ----------------------------------------------------------------- T -> tiles
 
 // Per block row: origin (block column, multiple of 32) and bit-map words.
@@ -85,6 +88,24 @@ __global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const 
         carry += __shfl(inc, kWave - 1);
     }
     if (lane == 0) cnt[I] = carry;
+}
+
+// Block column of every tile, in tile order (block rows in order, columns
+// ascending within a block row).
+__global__ void k_bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                            const int64_t *tb, int32_t *tcols) {
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= nb) return;
+    const int64_t w0 = woff[I], W = woff[I + 1] - w0;
+    for (int64_t w = lane_id(); w < W; w += kWave) {
+        const uint2 e = rt[w0 + w];
+        uint32_t x = e.x;
+        int64_t q = tb[I] + e.y;
+        while (x) {
+            tcols[q++] = lo[I] + 32 * (int)w + __ffs(x) - 1;
+            x &= x - 1;
+        }
+    }
 }
 
 // Scatters the entries of T into the zeroed tiles, in both operand layouts.
@@ -148,12 +169,13 @@ __global__ void k_bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff
 }
 
 // C's block-row bit maps (word-aligned ORs of T's bit maps) and tile counts;
-// with ccols != NULL also the sorted block-column list of every C block row.
+// with ccols != NULL also the sorted block-column list of every C block row
+// and C's rank table crt (word, prefix count), as T's rt.
 __global__ __launch_bounds__(64) void k_bsr_cpattern(int64_t nb, const int32_t *lo,
                                                      const int64_t *woff, const uint2 *rt,
                                                      const int32_t *clo, const int64_t *cwoff,
                                                      int64_t *ccnt, const int64_t *ctb,
-                                                     int32_t *ccols) {
+                                                     int32_t *ccols, uint2 *crt) {
     extern __shared__ uint32_t bm[];
     const int64_t I = blockIdx.x;
     if (I >= nb) return;
@@ -193,6 +215,7 @@ __global__ __launch_bounds__(64) void k_bsr_cpattern(int64_t nb, const int32_t *
         const unsigned inc = wave_incl_scan(pc);
         if (ccols && w < CW) {
             unsigned r = carry + inc - pc;
+            crt[cwoff[I] + w] = make_uint2(x, r);
             while (x) {
                 ccols[ctb[I] + r] = cbase + 32 * (int)w + __ffs(x) - 1;
                 x &= x - 1;
@@ -290,6 +313,214 @@ __global__ __launch_bounds__(256) void k_bsr_numeric(
 #pragma unroll
     for (int t = 0; t < kGroup; ++t)
         if (t < ng) *(d4 *)(ctiles + (ctb[I] + g0 + t) * kTileElems + 4 * lane) = acc[t];
+}
+
+// ----------------------------------------------------------------- panels
+//
+// A panel is kPanel consecutive block rows of C.  Its four waves (one block
+// row each) take the same kPanelGroup block columns from the union of the
+// panel's C patterns, so for every K they read the same B tiles T_KJ close
+// together in time and share them through the CU's caches; each wave reads
+// its own A tiles.  Output tiles absent from a row's C pattern receive no
+// product and are not written.
+
+// Panel origin (block column, multiple of 32) and bit-map words.
+__global__ void k_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cwoff,
+                               int32_t *plo, int64_t *pwords) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (nb + kPanel - 1) / kPanel;
+    if (p >= np) return;
+    int mn = INT32_MAX, mx = -1;
+    for (int64_t I = p * kPanel; I < min<int64_t>(p * kPanel + kPanel, nb); ++I) {
+        const int64_t CW = cwoff[I + 1] - cwoff[I];
+        if (CW > 0) {
+            mn = min(mn, clo[I]);
+            mx = max(mx, clo[I] + 32 * (int)CW - 1);
+        }
+    }
+    if (mx < 0) {
+        plo[p] = 0;
+        pwords[p] = 0;
+    } else {
+        plo[p] = mn;
+        pwords[p] = ((mx - mn) >> 5) + 1;
+    }
+}
+
+// Union of the C block-column lists of a panel: counts (pcols == NULL) or
+// the sorted list at pofs[p].
+__global__ __launch_bounds__(64) void k_panel_cols(int64_t nb, const int32_t *clo,
+                                                   const int64_t *cwoff, const uint2 *crt,
+                                                   const int32_t *plo, const int64_t *pwoff,
+                                                   int64_t *pcnt, const int64_t *pofs,
+                                                   int32_t *pcols) {
+    extern __shared__ uint32_t bm[];
+    const int64_t p = blockIdx.x;
+    const int lane = lane_id();
+    const int64_t PW = pwoff[p + 1] - pwoff[p];
+    if (PW == 0) {
+        if (lane == 0 && !pcols) pcnt[p] = 0;
+        return;
+    }
+    for (int64_t w = lane; w < PW; w += kWave) bm[w] = 0;
+    wfence();
+    for (int64_t I = p * kPanel; I < min<int64_t>(p * kPanel + kPanel, nb); ++I) {
+        const int64_t CW = cwoff[I + 1] - cwoff[I];
+        const int sh = (clo[I] - plo[p]) >> 5;
+        for (int64_t w = lane; w < CW; w += kWave) {
+            const uint32_t x = crt[cwoff[I] + w].x;
+            if (x) atomicOr(&bm[sh + w], x);
+        }
+    }
+    wfence();
+    const int base = plo[p];
+    unsigned carry = 0;
+    for (int64_t b0 = 0; b0 < PW; b0 += kWave) {
+        const int64_t w = b0 + lane;
+        uint32_t x = w < PW ? bm[w] : 0u;
+        const unsigned pc = __popc(x);
+        const unsigned inc = wave_incl_scan(pc);
+        if (pcols && w < PW) {
+            unsigned r = carry + inc - pc;
+            while (x) {
+                pcols[pofs[p] + r] = base + 32 * (int)w + __ffs(x) - 1;
+                x &= x - 1;
+                ++r;
+            }
+        }
+        carry += __shfl(inc, kWave - 1);
+    }
+    if (lane == 0 && !pcols) pcnt[p] = carry;
+}
+
+// One workgroup per work item (panel, group of kGroup panel columns); wave
+// w computes block row kPanel p + w.  C_IJ = (2 I) T_IJ + sum_K T_IK T_KJ
+// with K ascending over the tiles of T's block row I.  The lanes first find,
+// 64 values of K at a time, the tiles T_KJ of the group (one K per lane, all
+// lookups in flight together); the product loop then walks the K that have
+// at least one, reading their indices with readlane, and loads the operands
+// of the next K before issuing the matrix instructions of the current one.
+template <int kGroup>
+__global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
+    int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
+    const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
+    const int32_t *__restrict__ tcols, const double *__restrict__ tA,
+    const double *__restrict__ tB, const int64_t *__restrict__ pgofs, int64_t np,
+    const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
+    const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
+    const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
+    int64_t nwork, int remap) {
+    const int lane = lane_id();
+    const int64_t w = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    if (w >= nwork) return;
+    int64_t lo_p = 0, hi_p = np - 1;   // last panel with pgofs[p] <= w
+    while (lo_p < hi_p) {
+        const int64_t mid = (lo_p + hi_p + 1) >> 1;
+        if (pgofs[mid] <= w) lo_p = mid; else hi_p = mid - 1;
+    }
+    const int64_t p = lo_p;
+    const int64_t I = p * kPanel + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (I >= nb) return;
+    const int64_t g0 = (w - pgofs[p]) * kGroup;
+    const int ng = (int)min<int64_t>(kGroup, pofs[p + 1] - pofs[p] - g0);
+    int J[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) J[t] = t < ng ? pcols[pofs[p] + g0 + t] : -1;
+    d4 acc[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    {
+        const d4 two = two_identity_a(lane);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            if (t >= ng) break;
+            const int64_t tt = tile_of(lo, woff, rt, tb, I, J[t]);
+            if (tt < 0) continue;
+            const d4 b = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
+            acc[t] = mfma16(two, b, acc[t]);
+        }
+    }
+    const int64_t t0 = tb[I], nk = tb[I + 1] - t0;
+    const int jlo = J[0], jhi = J[ng - 1];
+    for (int64_t c0 = 0; c0 < nk; c0 += kWave) {
+        int ti[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) ti[t] = -1;
+        if (c0 + lane < nk) {
+            const int K = tcols[t0 + c0 + lane];
+            const int loK = lo[K];
+            const int64_t w0 = woff[K], WK = woff[K + 1] - w0;
+            if (WK > 0 && jhi >= loK && jlo < loK + 32 * (int)WK) {
+                const int64_t tbK = tb[K];
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t) {
+                    const int d = J[t] - loK;
+                    if (t < ng && d >= 0 && (d >> 5) < WK) {
+                        const uint2 e = rt[w0 + (d >> 5)];
+                        const uint32_t bit = 1u << (d & 31);
+                        if (e.x & bit) ti[t] = (int)(tbK + e.y + __popc(e.x & (bit - 1u)));
+                    }
+                }
+            }
+        }
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) any = any || ti[t] >= 0;
+        uint64_t m = __ballot(any);
+        if (!m) continue;
+        // operands of the current K; absent B tiles load a valid dummy tile
+        // (the A tile) so that every stage issues the same loads
+        int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        int64_t ta = t0 + c0 + l;
+        int bi[kGroup];
+        d4 a = *(const d4 *)(tA + ta * kTileElems + 4 * lane);
+        d4 b[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            bi[t] = __builtin_amdgcn_readlane(ti[t], l);
+            const int64_t src = bi[t] >= 0 ? bi[t] : ta;
+            b[t] = *(const d4 *)(tB + src * kTileElems + 4 * lane);
+        }
+        for (;;) {
+            const bool more = m != 0;
+            d4 a2 = a, b2[kGroup];
+            int bi2[kGroup];
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                b2[t] = b[t];
+                bi2[t] = -1;
+            }
+            if (more) {
+                l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                ta = t0 + c0 + l;
+                a2 = *(const d4 *)(tA + ta * kTileElems + 4 * lane);
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t) {
+                    bi2[t] = __builtin_amdgcn_readlane(ti[t], l);
+                    const int64_t src = bi2[t] >= 0 ? bi2[t] : ta;
+                    b2[t] = *(const d4 *)(tB + src * kTileElems + 4 * lane);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t)
+                if (bi[t] >= 0) acc[t] = mfma16(a, b[t], acc[t]);
+            if (!more) break;
+            a = a2;
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                b[t] = b2[t];
+                bi[t] = bi2[t];
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        if (t >= ng) break;
+        const int64_t ct = tile_of(clo, cwoff, crt, ctb, I, J[t]);
+        if (ct >= 0) *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
+    }
 }
 
 // ----------------------------------------------------------------- norm, compaction
@@ -422,10 +653,63 @@ hipError_t bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff, const
 
 hipError_t bsr_cpattern(int64_t n, int64_t nb, const int32_t *lo, const int64_t *woff,
                         const uint2 *rt, const int32_t *clo, const int64_t *cwoff, int64_t *ccnt,
-                        const int64_t *ctb, int32_t *ccols, hipStream_t st) {
+                        const int64_t *ctb, int32_t *ccols, uint2 *crt, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_cpattern, dim3(nb), dim3(64), bsr_lds_words(n) * 4, st, nb, lo,
-                       woff, rt, clo, cwoff, ccnt, ctb, ccols);
+                       woff, rt, clo, cwoff, ccnt, ctb, ccols, crt);
+    return hipGetLastError();
+}
+
+hipError_t bsr_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cwoff, int32_t *plo,
+                            int64_t *pwords, hipStream_t st) {
+    const int64_t np = (nb + kPanel - 1) / kPanel;
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_panel_bounds, dim3((np + 255) / 256), dim3(256), 0, st, nb, clo, cwoff,
+                       plo, pwords);
+    return hipGetLastError();
+}
+
+hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64_t *cwoff,
+                          const uint2 *crt, const int32_t *plo, const int64_t *pwoff,
+                          int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st) {
+    const int64_t np = (nb + kPanel - 1) / kPanel;
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_panel_cols, dim3((unsigned)np), dim3(64), bsr_lds_words(n) * 4, st, nb,
+                       clo, cwoff, crt, plo, pwoff, pcnt, pofs, pcols);
+    return hipGetLastError();
+}
+
+hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipStream_t st) {
+    const int64_t np = (nb + kPanel - 1) / kPanel;
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_groups, dim3((np + 255) / 256), dim3(256), 0, st, pcnt, np, gcnt,
+                       kPanelGroup);
+    return hipGetLastError();
+}
+
+hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                     const int64_t *tb, int32_t *tcols, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_tcols, dim3((nb + 3) / 4), dim3(256), 0, st, nb, lo, woff, rt, tb,
+                       tcols);
+    return hipGetLastError();
+}
+
+hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                             const int64_t *tb, const int32_t *tcols, const double *tA,
+                             const double *tB,
+                             const int64_t *pgofs, const int64_t *pofs, const int32_t *pcols,
+                             const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
+                             const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st) {
+    if (nwork == 0) return hipSuccess;
+    static const int remap = [] {
+        const char *e = getenv("EXPM_BSR_REMAP");
+        return e && e[0] == '1' ? 1 : 0;
+    }();
+    hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
+                       dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
+                       (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb, ctiles,
+                       nwork, remap);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ namespace xpm {
 namespace host {
 
 void release(expm_plan_s &P, TileSet &ts) {
-    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt, &ts.cnt, &ts.tb, &ts.tA, &ts.tB};
+    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt, &ts.cnt, &ts.tb, &ts.tA, &ts.tB, &ts.cols};
     for (Buf *b : all) release(P, *b);
     ts.nb = ts.ntiles = 0;
 }
@@ -41,6 +41,9 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
                           st));
     CHK(sync(P));
     ts.ntiles = hl[0];
+    CHK(ensure(P, ts.cols, sizeof(int32_t) * (ts.ntiles + 1)));
+    HIPCHK(bsr_tcols(nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
+                     (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (int32_t *)ts.cols.p, st));
     *fill = ts.ntiles ? (double)nnz / ((double)ts.ntiles * 256.0) : 0.0;
     return EXPM_OK;
 }
@@ -98,26 +101,74 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     HIPCHK(bsr_cbounds(nb, lo, woff, rt, tb, (int32_t *)P.c_lo.p, (int64_t *)P.c_words.p, st));
     CHK(scan(P, (const int64_t *)P.c_words.p, (int64_t *)P.c_woff.p, nb));
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
-                        (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p, nullptr, nullptr, st));
+                        (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p, nullptr, nullptr,
+                        nullptr, st));
     CHK(scan(P, (const int64_t *)P.c_cnt.p, (int64_t *)P.c_tb.p, nb));
-    HIPCHK(bsr_groups((const int64_t *)P.c_cnt.p, nb, (int64_t *)P.g_cnt.p, st));
-    CHK(scan(P, (const int64_t *)P.g_cnt.p, (int64_t *)P.g_ofs.p, nb));
+    const bool panels = P.bsr_panels;
+    if (!panels) {
+        HIPCHK(bsr_groups((const int64_t *)P.c_cnt.p, nb, (int64_t *)P.g_cnt.p, st));
+        CHK(scan(P, (const int64_t *)P.g_cnt.p, (int64_t *)P.g_ofs.p, nb));
+    }
     HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.c_tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
     HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.g_ofs.p + nb, sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hl + 2, (int64_t *)P.c_woff.p + nb, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, st));
     CHK(sync(P));
-    const int64_t ctiles = hl[0], nwork = hl[1];
+    const int64_t ctiles = hl[0], cwords = hl[2];
+    int64_t nwork = hl[1];
     CHK(ensure(P, P.c_cols, sizeof(int32_t) * (ctiles + 1)));
     CHK(ensure(P, P.c_tiles, sizeof(double) * 256 * (size_t)(ctiles + 1)));
+    CHK(ensure(P, P.c_rt, sizeof(uint2) * (cwords + 1)));
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
-                        (const int64_t *)P.c_tb.p, (int32_t *)P.c_cols.p, st));
+                        (const int64_t *)P.c_tb.p, (int32_t *)P.c_cols.p, (uint2 *)P.c_rt.p,
+                        st));
+    if (panels) {
+        // panels of four block rows and their shared column groups
+        const int64_t np = (nb + 3) / 4;
+        CHK(ensure(P, P.p_lo, sizeof(int32_t) * (np + 1)));
+        CHK(ensure(P, P.p_words, sizeof(int64_t) * (np + 1)));
+        CHK(ensure(P, P.p_woff, sizeof(int64_t) * (np + 1)));
+        CHK(ensure(P, P.p_cnt, sizeof(int64_t) * (np + 1)));
+        CHK(ensure(P, P.p_ofs, sizeof(int64_t) * (np + 1)));
+        CHK(ensure(P, P.p_gcnt, sizeof(int64_t) * (np + 1)));
+        CHK(ensure(P, P.p_gofs, sizeof(int64_t) * (np + 1)));
+        CHK(ensure(P, P.p_cols, sizeof(int32_t) * (ctiles + 1)));
+        const int32_t *clo = (const int32_t *)P.c_lo.p;
+        const int64_t *cwoff = (const int64_t *)P.c_woff.p;
+        HIPCHK(bsr_panel_bounds(nb, clo, cwoff, (int32_t *)P.p_lo.p, (int64_t *)P.p_words.p, st));
+        CHK(scan(P, (const int64_t *)P.p_words.p, (int64_t *)P.p_woff.p, np));
+        HIPCHK(bsr_panel_cols(n, nb, clo, cwoff, (const uint2 *)P.c_rt.p,
+                              (const int32_t *)P.p_lo.p, (const int64_t *)P.p_woff.p,
+                              (int64_t *)P.p_cnt.p, nullptr, nullptr, st));
+        CHK(scan(P, (const int64_t *)P.p_cnt.p, (int64_t *)P.p_ofs.p, np));
+        HIPCHK(bsr_panel_cols(n, nb, clo, cwoff, (const uint2 *)P.c_rt.p,
+                              (const int32_t *)P.p_lo.p, (const int64_t *)P.p_woff.p,
+                              (int64_t *)P.p_cnt.p, (const int64_t *)P.p_ofs.p,
+                              (int32_t *)P.p_cols.p, st));
+        HIPCHK(bsr_panel_groups((const int64_t *)P.p_cnt.p, nb, (int64_t *)P.p_gcnt.p, st));
+        CHK(scan(P, (const int64_t *)P.p_gcnt.p, (int64_t *)P.p_gofs.p, np));
+        HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.p_gofs.p + np, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        nwork = hl[1];
+    }
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
-    HIPCHK(bsr_numeric(nb, lo, woff, rt, tb, (const double *)ts.tA.p, (const double *)ts.tB.p,
-                       (const int64_t *)P.g_ofs.p, (const int64_t *)P.c_tb.p,
-                       (const int64_t *)P.c_cnt.p, (const int32_t *)P.c_cols.p,
-                       (double *)P.c_tiles.p, nwork, st));
+    if (panels)
+        HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
+                                 (const double *)ts.tA.p,
+                                 (const double *)ts.tB.p, (const int64_t *)P.p_gofs.p,
+                                 (const int64_t *)P.p_ofs.p, (const int32_t *)P.p_cols.p,
+                                 (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
+                                 (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
+                                 (double *)P.c_tiles.p, nwork, st));
+    else
+        HIPCHK(bsr_numeric(nb, lo, woff, rt, tb, (const double *)ts.tA.p,
+                           (const double *)ts.tB.p, (const int64_t *)P.g_ofs.p,
+                           (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
+                           (const int32_t *)P.c_cols.p, (double *)P.c_tiles.p, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     // ||I + T~||_F and the nonzero candidate count
     CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));

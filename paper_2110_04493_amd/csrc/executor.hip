@@ -963,6 +963,7 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     P->opts = o;
     P->st = (hipStream_t)o.stream;
     if (const char *f = getenv("EXPM_BSR_FILL")) P->bsr_min_fill = atof(f);
+    if (const char *f = getenv("EXPM_BSR_PANEL")) P->bsr_panels = f[0] != '0';
     if (hipHostMalloc((void **)&P->host, 4096, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete P;

@@ -106,7 +106,22 @@ hipError_t bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff, const
                        const int64_t *tb, int32_t *clo, int64_t *cwords, hipStream_t st);
 hipError_t bsr_cpattern(int64_t n, int64_t nb, const int32_t *lo, const int64_t *woff,
                         const uint2 *rt, const int32_t *clo, const int64_t *cwoff, int64_t *ccnt,
-                        const int64_t *ctb, int32_t *ccols, hipStream_t st);
+                        const int64_t *ctb, int32_t *ccols, uint2 *crt, hipStream_t st);
+// panels of 4 block rows sharing column groups (bsr.hip)
+hipError_t bsr_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cwoff, int32_t *plo,
+                            int64_t *pwords, hipStream_t st);
+hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64_t *cwoff,
+                          const uint2 *crt, const int32_t *plo, const int64_t *pwoff,
+                          int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st);
+hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipStream_t st);
+hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                     const int64_t *tb, int32_t *tcols, hipStream_t st);
+hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                             const int64_t *tb, const int32_t *tcols, const double *tA,
+                             const double *tB,
+                             const int64_t *pgofs, const int64_t *pofs, const int32_t *pcols,
+                             const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
+                             const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st);
 hipError_t bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, hipStream_t st);
 hipError_t bsr_numeric(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                        const int64_t *tb, const double *tA, const double *tB, const int64_t *gofs,

@@ -32,7 +32,7 @@ struct DCsr {
 // multiple of 32), bit-map words with prefix counts (rank table) and the
 // base tile index; the tiles in the A and B operand layouts.
 struct TileSet {
-    Buf lo, words, woff, rt, cnt, tb, tA, tB;
+    Buf lo, words, woff, rt, cnt, tb, tA, tB, cols;   // cols: block column of every tile
     int64_t nb = 0, ntiles = 0;
 };
 
@@ -75,7 +75,12 @@ struct expm_plan_s {
     // tile pattern, work items and the candidate tiles
     xpm::host::TileSet tsT, tsG;
     xpm::host::Buf c_lo, c_words, c_woff, c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz,
-        b_total;
+        b_total, c_rt;
+    // panels of four block rows for the product (p_*: origin, words, column
+    // counts and lists, work groups); EXPM_BSR_PANEL=0 uses one block row per
+    // work item instead
+    xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
+    bool bsr_panels = true;
     // block-column lists of T (the block rows of T^T) for the adjoint
     xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles;
     std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows
