@@ -442,79 +442,20 @@ __global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
     }
     const int64_t t0 = tb[I], nk = tb[I + 1] - t0;
     const int jlo = J[0], jhi = J[ng - 1];
-    for (int64_t c0 = 0; c0 < nk; c0 += kWave) {
-        int ti[kGroup];
+    auto item = [&](int64_t r, int &K, int &a) {
+        K = tcols[t0 + r];
+        a = (int)(t0 + r);
+    };
+    auto look = [&](int K, int (&ti)[kGroup]) {
+        const int loK = lo[K];
+        const int64_t w0 = woff[K], WK = woff[K + 1] - w0;
+        if (WK == 0 || jhi < loK || jlo >= loK + 32 * (int)WK) return;
+        const int64_t tbK = tb[K];
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t) ti[t] = -1;
-        if (c0 + lane < nk) {
-            const int K = tcols[t0 + c0 + lane];
-            const int loK = lo[K];
-            const int64_t w0 = woff[K], WK = woff[K + 1] - w0;
-            if (WK > 0 && jhi >= loK && jlo < loK + 32 * (int)WK) {
-                const int64_t tbK = tb[K];
-#pragma unroll
-                for (int t = 0; t < kGroup; ++t) {
-                    const int d = J[t] - loK;
-                    if (t < ng && d >= 0 && (d >> 5) < WK) {
-                        const uint2 e = rt[w0 + (d >> 5)];
-                        const uint32_t bit = 1u << (d & 31);
-                        if (e.x & bit) ti[t] = (int)(tbK + e.y + __popc(e.x & (bit - 1u)));
-                    }
-                }
-            }
-        }
-        bool any = false;
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t) any = any || ti[t] >= 0;
-        uint64_t m = __ballot(any);
-        if (!m) continue;
-        // operands of the current K; absent B tiles load a valid dummy tile
-        // (the A tile) so that every stage issues the same loads
-        int l = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        int64_t ta = t0 + c0 + l;
-        int bi[kGroup];
-        d4 a = *(const d4 *)(tA + ta * kTileElems + 4 * lane);
-        d4 b[kGroup];
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t) {
-            bi[t] = __builtin_amdgcn_readlane(ti[t], l);
-            const int64_t src = bi[t] >= 0 ? bi[t] : ta;
-            b[t] = *(const d4 *)(tB + src * kTileElems + 4 * lane);
-        }
-        for (;;) {
-            const bool more = m != 0;
-            d4 a2 = a, b2[kGroup];
-            int bi2[kGroup];
-#pragma unroll
-            for (int t = 0; t < kGroup; ++t) {
-                b2[t] = b[t];
-                bi2[t] = -1;
-            }
-            if (more) {
-                l = __ffsll((long long)m) - 1;
-                m &= m - 1;
-                ta = t0 + c0 + l;
-                a2 = *(const d4 *)(tA + ta * kTileElems + 4 * lane);
-#pragma unroll
-                for (int t = 0; t < kGroup; ++t) {
-                    bi2[t] = __builtin_amdgcn_readlane(ti[t], l);
-                    const int64_t src = bi2[t] >= 0 ? bi2[t] : ta;
-                    b2[t] = *(const d4 *)(tB + src * kTileElems + 4 * lane);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < kGroup; ++t)
-                if (bi[t] >= 0) acc[t] = mfma16(a, b[t], acc[t]);
-            if (!more) break;
-            a = a2;
-#pragma unroll
-            for (int t = 0; t < kGroup; ++t) {
-                b[t] = b2[t];
-                bi[t] = bi2[t];
-            }
-        }
-    }
+        for (int t = 0; t < kGroup; ++t)
+            if (t < ng) ti[t] = tile_in_row(loK, w0, WK, tbK, rt, J[t]);
+    };
+    pipe_products<kGroup>(nk, item, look, tA, tB, acc);
 #pragma unroll
     for (int t = 0; t < kGroup; ++t) {
         if (t >= ng) break;

@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
     // G on T_k's pattern
     const int32_t *__restrict__ glo, const int64_t *__restrict__ gwoff,
     const uint2 *__restrict__ grt, const int64_t *__restrict__ gtb,
-    const double *__restrict__ gA, const double *__restrict__ gB,
+    const int32_t *__restrict__ gcols, const double *__restrict__ gA,
+    const double *__restrict__ gB,
     // T's block columns (T^T's block rows), sorted by K
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ ck,
     const int64_t *__restrict__ ct,
@@ -131,49 +132,46 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
     }
     // (G T^T)_IJ = sum over K in G's block row I of G_IK (T_JK)^T
     {
-        const int64_t W = gwoff[I + 1] - gwoff[I];
-        for (int64_t ww = 0; ww < W; ++ww) {
-            const uint2 e = grt[gwoff[I] + ww];
-            uint32_t x = e.x;
-            unsigned r = e.y;
-            while (x) {
-                const int K = glo[I] + 32 * (int)ww + __ffs(x) - 1;
-                x &= x - 1;
-                const int64_t tgk = gtb[I] + r;
-                ++r;
-                int64_t tj[kGroup];
-                bool any = false;
-#pragma unroll
-                for (int t = 0; t < kGroup; ++t) {
-                    tj[t] = t < ng ? tile_of(tlo, twoff, trt, ttb, J[t], K) : -1;
-                    any = any || tj[t] >= 0;
-                }
-                if (!any) continue;
-                const d4 a = *(const d4 *)(gA + tgk * kTileElems + 4 * lane);
-#pragma unroll
-                for (int t = 0; t < kGroup; ++t)
-                    if (tj[t] >= 0)
-                        acc[t] = mfma16(a, *(const d4 *)(tA + tj[t] * kTileElems + 4 * lane),
-                                        acc[t]);
-            }
-        }
-    }
-    // (T^T G)_IJ = sum over K in T's block column I of (T_KI)^T G_KJ
-    for (int64_t p = cptr[I]; p < cptr[I + 1]; ++p) {
-        const int K = ck[p];
-        int64_t tg[kGroup];
-        bool any = false;
+        int loJ[kGroup], tbJ[kGroup];
+        int64_t w0J[kGroup], WJ[kGroup];
 #pragma unroll
         for (int t = 0; t < kGroup; ++t) {
-            tg[t] = t < ng ? tile_of(glo, gwoff, grt, gtb, K, J[t]) : -1;
-            any = any || tg[t] >= 0;
+            const int Jt = J[t];
+            loJ[t] = tlo[Jt];
+            w0J[t] = twoff[Jt];
+            WJ[t] = t < ng ? twoff[Jt + 1] - w0J[t] : 0;
+            tbJ[t] = (int)ttb[Jt];
         }
-        if (!any) continue;
-        const d4 a = *(const d4 *)(tB + ct[p] * kTileElems + 4 * lane);
+        const int64_t g0 = gtb[I];
+        auto item = [&](int64_t r, int &K, int &a) {
+            K = gcols[g0 + r];
+            a = (int)(g0 + r);
+        };
+        auto look = [&](int K, int (&ti)[kGroup]) {
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t)
-            if (tg[t] >= 0)
-                acc[t] = mfma16(a, *(const d4 *)(gB + tg[t] * kTileElems + 4 * lane), acc[t]);
+            for (int t = 0; t < kGroup; ++t)
+                ti[t] = tile_in_row(loJ[t], w0J[t], WJ[t], tbJ[t], trt, K);
+        };
+        pipe_products<kGroup>(gtb[I + 1] - g0, item, look, gA, tA, acc);
+    }
+    // (T^T G)_IJ = sum over K in T's block column I of (T_KI)^T G_KJ
+    {
+        const int64_t p0 = cptr[I];
+        const int jlo = J[0], jhi = J[ng - 1];
+        auto item = [&](int64_t r, int &K, int &a) {
+            K = ck[p0 + r];
+            a = (int)ct[p0 + r];
+        };
+        auto look = [&](int K, int (&ti)[kGroup]) {
+            const int loK = glo[K];
+            const int64_t w0 = gwoff[K], WK = gwoff[K + 1] - w0;
+            if (WK == 0 || jhi < loK || jlo >= loK + 32 * (int)WK) return;
+            const int64_t tbK = gtb[K];
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t)
+                if (t < ng) ti[t] = tile_in_row(loK, w0, WK, tbK, grt, J[t]);
+        };
+        pipe_products<kGroup>(cptr[I + 1] - p0, item, look, tB, gB, acc);
     }
     // mask by T's stored entries (T_IJ in the B layout = accumulator layout)
 #pragma unroll
@@ -244,13 +242,13 @@ hipError_t bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk, const 
 hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, const uint2 *trt,
                        const int64_t *ttb, const double *tA, const double *tB, const int32_t *glo,
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
-                       const double *gA, const double *gB, const int64_t *cptr,
-                       const int32_t *ck, const int64_t *ct, const int64_t *gofs, double *out,
-                       int64_t nwork, hipStream_t st) {
+                       const int32_t *gcols, const double *gA, const double *gB,
+                       const int64_t *cptr, const int32_t *ck, const int64_t *ct,
+                       const int64_t *gofs, double *out, int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_adjoint<4>, dim3((nwork + 3) / 4), dim3(256), 0, st, nb, tlo, twoff,
-                       trt, ttb, tA, tB, glo, gwoff, grt, gtb, gA, gB, cptr, ck, ct, gofs, out,
-                       nwork);
+                       trt, ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
+                       out, nwork);
     return hipGetLastError();
 }
 

@@ -58,4 +58,94 @@ __device__ __forceinline__ d4 two_identity_a(int lane) {
     return t;
 }
 
+// Accumulates acc[t] += sum over items r = 0 .. nr-1, in order, of
+// A(r) * B(r, t), 16 x 16 tile products on the matrix cores.  item(r, K, a)
+// gives item r's inner index K and its A-operand tile index a; look(K, ti)
+// sets ti[t] to the B-operand tile index for output t, leaving -1 where that
+// tile is absent.  The indices of 64 items are looked up at once (one item
+// per lane, all loads in flight together); the products then walk the items
+// with at least one B tile, reading their indices with readlane, and load the
+// operands of the next item before issuing the current item's instructions.
+// Absent B tiles load tile 0 of Bb (present whenever a product runs) so that
+// every stage issues the same loads.
+template <int kGroup, class Item, class Look>
+__device__ __forceinline__ void pipe_products(int64_t nr, Item item, Look look,
+                                              const double *__restrict__ Ab,
+                                              const double *__restrict__ Bb,
+                                              d4 (&acc)[kGroup]) {
+    const int lane = lane_id();
+    for (int64_t c0 = 0; c0 < nr; c0 += kWave) {
+        int ti[kGroup];
+        int ai = 0;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) ti[t] = -1;
+        if (c0 + lane < nr) {
+            int K;
+            item(c0 + lane, K, ai);
+            look(K, ti);
+        }
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) any = any || ti[t] >= 0;
+        uint64_t m = __ballot(any);
+        if (!m) continue;
+        int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        int64_t ta = __builtin_amdgcn_readlane(ai, l);
+        d4 a = *(const d4 *)(Ab + ta * kTileElems + 4 * lane);
+        int bi[kGroup];
+        d4 b[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            bi[t] = __builtin_amdgcn_readlane(ti[t], l);
+            const int64_t src = bi[t] >= 0 ? bi[t] : 0;
+            b[t] = *(const d4 *)(Bb + src * kTileElems + 4 * lane);
+        }
+        for (;;) {
+            const bool more = m != 0;
+            d4 a2 = a, b2[kGroup];
+            int bi2[kGroup];
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                b2[t] = b[t];
+                bi2[t] = -1;
+            }
+            if (more) {
+                l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                ta = __builtin_amdgcn_readlane(ai, l);
+                a2 = *(const d4 *)(Ab + ta * kTileElems + 4 * lane);
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t) {
+                    bi2[t] = __builtin_amdgcn_readlane(ti[t], l);
+                    const int64_t src = bi2[t] >= 0 ? bi2[t] : 0;
+                    b2[t] = *(const d4 *)(Bb + src * kTileElems + 4 * lane);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t)
+                if (bi[t] >= 0) acc[t] = mfma16(a, b[t], acc[t]);
+            if (!more) break;
+            a = a2;
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                b[t] = b2[t];
+                bi[t] = bi2[t];
+            }
+        }
+    }
+}
+
+// Tile index of block column J in a block row whose origin, bit-map words
+// and tile base are already loaded (as tile_of), or -1.
+__device__ __forceinline__ int tile_in_row(int loK, int64_t w0, int64_t WK, int64_t tbK,
+                                           const uint2 *rt, int J) {
+    const int d = J - loK;
+    if (d < 0 || (d >> 5) >= WK) return -1;
+    const uint2 e = rt[w0 + (d >> 5)];
+    const uint32_t bit = 1u << (d & 31);
+    if (!(e.x & bit)) return -1;
+    return (int)(tbK + e.y + __popc(e.x & (bit - 1u)));
+}
+
 }  // namespace xpm

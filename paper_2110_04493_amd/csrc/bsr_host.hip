@@ -310,7 +310,7 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (const double *)T.tA.p,
                        (const double *)T.tB.p, (const int32_t *)G.lo.p,
                        (const int64_t *)G.woff.p, (const uint2 *)G.rt.p,
-                       (const int64_t *)G.tb.p, (const double *)G.tA.p,
+                       (const int64_t *)G.tb.p, (const int32_t *)G.cols.p, (const double *)G.tA.p,
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
                        (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p, nwork, st));
     if (prof) {

@@ -499,7 +499,7 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
             double fill = 0.0;
             CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill));
             have_pattern = true;
-            tiles = P.tsT.ntiles > 0 && fill >= P.bsr_min_fill;
+            tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
         }
         if (step >= 1) P.sq_path.push_back(tiles ? 1 : 0);
     }
@@ -848,7 +848,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         if (tiles_allowed(P, n)) {
             double fill = 0.0;
             CHK(bsr_pattern(P, Tp->view(), Tp->nnz, P.tsT, &fill));
-            tiles = P.tsT.ntiles > 0 && fill >= P.bsr_min_fill;
+            tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
         }
         if (tiles) {
             CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p));

@@ -148,9 +148,9 @@ hipError_t bsr_groups4(const int64_t *tb, int64_t nb, int64_t *gcnt, hipStream_t
 hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, const uint2 *trt,
                        const int64_t *ttb, const double *tA, const double *tB, const int32_t *glo,
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
-                       const double *gA, const double *gB, const int64_t *cptr,
-                       const int32_t *ck, const int64_t *ct, const int64_t *gofs, double *out,
-                       int64_t nwork, hipStream_t st);
+                       const int32_t *gcols, const double *gA, const double *gB,
+                       const int64_t *cptr, const int32_t *ck, const int64_t *ct,
+                       const int64_t *gofs, double *out, int64_t nwork, hipStream_t st);
 hipError_t bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                       const int64_t *tb, const double *tiles, double *out, hipStream_t st);
 
