@@ -90,10 +90,10 @@ __global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const 
     if (lane == 0) cnt[I] = carry;
 }
 
-// Block column of every tile, in tile order (block rows in order, columns
-// ascending within a block row).
+// Block column and block row of every tile, in tile order (block rows in
+// order, columns ascending within a block row).
 __global__ void k_bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                            const int64_t *tb, int32_t *tcols) {
+                            const int64_t *tb, int32_t *tcols, int32_t *trows) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= nb) return;
     const int64_t w0 = woff[I], W = woff[I + 1] - w0;
@@ -102,28 +102,70 @@ __global__ void k_bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, 
         uint32_t x = e.x;
         int64_t q = tb[I] + e.y;
         while (x) {
+            trows[q] = (int32_t)I;
             tcols[q++] = lo[I] + 32 * (int)w + __ffs(x) - 1;
             x &= x - 1;
         }
     }
 }
 
-// Scatters the entries of T into the zeroed tiles, in both operand layouts.
-__global__ void k_bsr_fill(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff,
-                           const uint2 *rt, const int64_t *tb, double *tA, double *tB) {
-    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (I >= nb) return;
-    const int64_t r1 = min<int64_t>(I * kTile + kTile, T.n);
-    for (int64_t i = I * kTile; i < r1; ++i) {
-        const int r = (int)(i & 15);
-        for (int64_t p = T.rp[i] + lane_id(); p < T.rp[i + 1]; p += kWave) {
-            const int j = T.ci[p];
-            const int64_t t = tile_of(lo, woff, rt, tb, I, j >> 4);
+// Row segments: for every tile and each of its 16 rows, the first CSR entry
+// of that row inside the tile and the entry count, packed as
+// (position << 5) | count (0 for none; the table starts zeroed).
+__global__ void k_bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                          const int64_t *tb, int64_t *seg) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= T.n) return;
+    const int64_t I = i >> 4;
+    const int r = (int)(i & 15);
+    const int64_t b = T.rp[i], e = T.rp[i + 1];
+    for (int64_t p = b + lane_id(); p < e; p += kWave) {
+        const int J = T.ci[p] >> 4;
+        if (p > b && (T.ci[p - 1] >> 4) == J) continue;
+        int len = 1;
+        while (p + len < e && (T.ci[p + len] >> 4) == J) ++len;
+        const int64_t tt = tile_of(lo, woff, rt, tb, I, J);
+        seg[tt * kTile + r] = (p << 5) | len;
+    }
+}
+
+// One wave per tile: the tile is assembled in LDS in both operand layouts
+// from its row segments (16 lanes per row, consecutive entries) and written
+// out whole, 32 contiguous bytes per lane.
+__global__ __launch_bounds__(256) void k_bsr_assemble(CsrView T, int64_t ntiles,
+                                                      const int32_t *tcols, const int32_t *trows,
+                                                      const int64_t *seg, double *tA,
+                                                      double *tB) {
+    __shared__ double buf[4][2][kTileElems];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    const int64_t tt = (int64_t)blockIdx.x * 4 + wv;
+    if (tt >= ntiles) return;
+    double *bA = buf[wv][0], *bB = buf[wv][1];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        bA[4 * lane + q] = 0.0;
+        bB[4 * lane + q] = 0.0;
+    }
+    wfence();
+    const int64_t I = trows[tt];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int r = 4 * rr + (lane >> 4);
+        if (I * kTile + r >= T.n) continue;
+        const int64_t s = seg[tt * kTile + r];
+        const int j = lane & 15;
+        if (j < (int)(s & 31)) {
+            const int64_t p = (s >> 5) + j;
+            const int c = T.ci[p] & 15;
             const double v = T.v[p];
-            tA[t * kTileElems + offA(r, j & 15)] = v;
-            tB[t * kTileElems + offB(r, j & 15)] = v;
+            bA[offA(r, c)] = v;
+            bB[offB(r, c)] = v;
         }
     }
+    wfence();
+    *(d4 *)(tA + tt * kTileElems + 4 * lane) = *(const d4 *)(bA + 4 * lane);
+    *(d4 *)(tB + tt * kTileElems + 4 * lane) = *(const d4 *)(bB + 4 * lane);
+    (void)tcols;
 }
 
 // ----------------------------------------------------------------- C pattern
@@ -502,59 +544,78 @@ __global__ void k_bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int6
     }
 }
 
-// Kept entries (|v| > theta, column < n) of row i = 16 I + r: the lanes take
-// four tiles at a time, sixteen columns each, so entries come in column order.
+// Compaction of the candidate tiles.  One wave per block row I reads each
+// tile of the block row once (32 contiguous bytes per lane): lane l holds
+// column l % 16 of rows r = l / 16 + 4 k, k = 0..3 (the accumulator layout),
+// so the 16 lanes of group g = l / 16 see the full 16 columns of rows g,
+// g + 4, g + 8, g + 12.  An entry is kept when its row and column are below
+// n and |v| > theta; tiles run in ascending block column, so each row's kept
+// entries come out in column order.
+__device__ __forceinline__ bool bsr_keep(int64_t i, int col, int64_t n, double v, double theta) {
+    return i < n && col < n && fabs(v) > theta;
+}
+
 __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
                             const int32_t *ccols, const double *ctiles, const FilterCtl *c,
                             int64_t *cnt) {
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (i >= n) return;
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= (n + kTile - 1) / kTile) return;
     const int lane = lane_id();
-    const int64_t I = i >> 4;
-    const int r = (int)(i & 15);
+    const int g = lane >> 4;
     const double theta = c->theta;
-    long long k = 0;
-    for (int64_t t0 = 0; t0 < ccnt[I]; t0 += 4) {
-        const int64_t t = t0 + (lane >> 4);
-        if (t < ccnt[I]) {
-            const int64_t tt = ctb[I] + t;
-            const int col = 16 * ccols[tt] + (lane & 15);
-            const double v = ctiles[tt * kTileElems + offB(r, lane & 15)];
-            k += col < n && fabs(v) > theta;
+    int k4[4] = {0, 0, 0, 0};
+    const int64_t base = ctb[I], cntI = ccnt[I];
+    for (int64_t t = 0; t < cntI; ++t) {
+        const int64_t tt = base + t;
+        const int col = 16 * ccols[tt] + (lane & 15);
+        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) k4[k] += bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) k4[k] += __shfl_xor(k4[k], o);
+    if ((lane & 15) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = I * kTile + g + 4 * k;
+            if (i < n) cnt[i] = k4[k];
         }
     }
-    k = wave_sum_ll(k);
-    if (lane == 0) cnt[i] = k;
 }
 
 __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
                             const int32_t *ccols, const double *ctiles, const FilterCtl *c,
                             const int64_t *orp, int32_t *oci, double *ov) {
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (i >= n) return;
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= (n + kTile - 1) / kTile) return;
     const int lane = lane_id();
-    const int64_t I = i >> 4;
-    const int r = (int)(i & 15);
+    const int g = lane >> 4, cl = lane & 15;
     const double theta = c->theta;
-    int64_t out = orp[i];
-    for (int64_t t0 = 0; t0 < ccnt[I]; t0 += 4) {
-        const int64_t t = t0 + (lane >> 4);
-        bool keep = false;
-        int col = 0;
-        double v = 0.0;
-        if (t < ccnt[I]) {
-            const int64_t tt = ctb[I] + t;
-            col = 16 * ccols[tt] + (lane & 15);
-            v = ctiles[tt * kTileElems + offB(r, lane & 15)];
-            keep = col < n && fabs(v) > theta;
+    int64_t out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = I * kTile + g + 4 * k;
+        out[k] = i < n ? orp[i] : 0;
+    }
+    const int64_t base = ctb[I], cntI = ccnt[I];
+    const uint32_t below = (1u << cl) - 1u;
+    for (int64_t t = 0; t < cntI; ++t) {
+        const int64_t tt = base + t;
+        const int col = 16 * ccols[tt] + cl;
+        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool keep = bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+            const uint32_t gm = (uint32_t)(__ballot(keep) >> (16 * g)) & 0xffffu;
+            if (keep) {
+                const int64_t q = out[k] + __popc(gm & below);
+                oci[q] = col;
+                ov[q] = v[k];
+            }
+            out[k] += __popc(gm);
         }
-        const unsigned long long km = __ballot(keep);
-        if (keep) {
-            const int64_t my = out + __popcll(km & ((1ull << lane) - 1ull));
-            oci[my] = col;
-            ov[my] = v;
-        }
-        out += __popcll(km);
     }
 }
 
@@ -573,14 +634,6 @@ hipError_t bsr_bitmap(CsrView T, int64_t nb, const int32_t *lo, const int64_t *w
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_bitmap, dim3(nb), dim3(64), bsr_lds_words(T.n) * 4, st, T, nb, lo,
                        woff, rt, cnt);
-    return hipGetLastError();
-}
-
-hipError_t bsr_fill(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                    const int64_t *tb, double *tA, double *tB, hipStream_t st) {
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_fill, dim3((nb + 3) / 4), dim3(256), 0, st, T, nb, lo, woff, rt, tb,
-                       tA, tB);
     return hipGetLastError();
 }
 
@@ -629,10 +682,25 @@ hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipS
 }
 
 hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                     const int64_t *tb, int32_t *tcols, hipStream_t st) {
+                     const int64_t *tb, int32_t *tcols, int32_t *trows, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_tcols, dim3((nb + 3) / 4), dim3(256), 0, st, nb, lo, woff, rt, tb,
-                       tcols);
+                       tcols, trows);
+    return hipGetLastError();
+}
+
+hipError_t bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                   const int64_t *tb, int64_t *seg, hipStream_t st) {
+    if (T.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_seg, dim3((T.n + 3) / 4), dim3(256), 0, st, T, lo, woff, rt, tb, seg);
+    return hipGetLastError();
+}
+
+hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const int32_t *trows,
+                        const int64_t *seg, double *tA, double *tB, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_assemble, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, T,
+                       ntiles, tcols, trows, seg, tA, tB);
     return hipGetLastError();
 }
 
@@ -714,7 +782,8 @@ hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *cc
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const FilterCtl *c, int64_t *cnt, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_count, dim3((n + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
+    const int64_t nb = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_bsr_count, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
                        ctiles, c, cnt);
     return hipGetLastError();
 }
@@ -723,7 +792,8 @@ hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
                      const double *ctiles, const FilterCtl *c, const int64_t *orp, int32_t *oci,
                      double *ov, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_write, dim3((n + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
+    const int64_t nb = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_bsr_write, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
                        ctiles, c, orp, oci, ov);
     return hipGetLastError();
 }

@@ -10,7 +10,8 @@ namespace xpm {
 namespace host {
 
 void release(expm_plan_s &P, TileSet &ts) {
-    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt, &ts.cnt, &ts.tb, &ts.tA, &ts.tB, &ts.cols};
+    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt,   &ts.cnt,
+                  &ts.tb, &ts.tA,    &ts.tB,   &ts.cols, &ts.rows, &ts.seg};
     for (Buf *b : all) release(P, *b);
     ts.nb = ts.ntiles = 0;
 }
@@ -42,22 +43,26 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
     CHK(sync(P));
     ts.ntiles = hl[0];
     CHK(ensure(P, ts.cols, sizeof(int32_t) * (ts.ntiles + 1)));
+    CHK(ensure(P, ts.rows, sizeof(int32_t) * (ts.ntiles + 1)));
     HIPCHK(bsr_tcols(nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
-                     (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (int32_t *)ts.cols.p, st));
+                     (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (int32_t *)ts.cols.p,
+                     (int32_t *)ts.rows.p, st));
     *fill = ts.ntiles ? (double)nnz / ((double)ts.ntiles * 256.0) : 0.0;
     return EXPM_OK;
 }
 
-// T's values into zeroed tiles of the pattern, in both operand layouts.
+// T's values as tiles of the pattern, in both operand layouts: a table of
+// row segments, then every tile assembled whole.
 int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts) {
-    const size_t tbytes = sizeof(double) * 256 * (size_t)(ts.ntiles > 0 ? ts.ntiles : 1);
-    CHK(ensure(P, ts.tA, tbytes));
-    CHK(ensure(P, ts.tB, tbytes));
-    HIPCHK(hipMemsetAsync(ts.tA.p, 0, tbytes, P.st));
-    HIPCHK(hipMemsetAsync(ts.tB.p, 0, tbytes, P.st));
-    HIPCHK(bsr_fill(T, ts.nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
-                    (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (double *)ts.tA.p,
-                    (double *)ts.tB.p, P.st));
+    const size_t nt = (size_t)(ts.ntiles > 0 ? ts.ntiles : 1);
+    CHK(ensure(P, ts.tA, sizeof(double) * 256 * nt));
+    CHK(ensure(P, ts.tB, sizeof(double) * 256 * nt));
+    CHK(ensure(P, ts.seg, sizeof(int64_t) * 16 * nt));
+    HIPCHK(hipMemsetAsync(ts.seg.p, 0, sizeof(int64_t) * 16 * nt, P.st));
+    HIPCHK(bsr_seg(T, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
+                   (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (int64_t *)ts.seg.p, P.st));
+    HIPCHK(bsr_assemble(T, ts.ntiles, (const int32_t *)ts.cols.p, (const int32_t *)ts.rows.p,
+                        (const int64_t *)ts.seg.p, (double *)ts.tA.p, (double *)ts.tB.p, P.st));
     return EXPM_OK;
 }
 

@@ -100,8 +100,6 @@ size_t bsr_lds_words(int64_t n);
 hipError_t bsr_bounds(CsrView T, int64_t nb, int32_t *lo, int64_t *words, hipStream_t st);
 hipError_t bsr_bitmap(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, uint2 *rt,
                       int64_t *cnt, hipStream_t st);
-hipError_t bsr_fill(CsrView T, int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                    const int64_t *tb, double *tA, double *tB, hipStream_t st);
 hipError_t bsr_cbounds(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                        const int64_t *tb, int32_t *clo, int64_t *cwords, hipStream_t st);
 hipError_t bsr_cpattern(int64_t n, int64_t nb, const int32_t *lo, const int64_t *woff,
@@ -115,7 +113,11 @@ hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64
                           int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st);
 hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipStream_t st);
 hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                     const int64_t *tb, int32_t *tcols, hipStream_t st);
+                     const int64_t *tb, int32_t *tcols, int32_t *trows, hipStream_t st);
+hipError_t bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
+                   const int64_t *tb, int64_t *seg, hipStream_t st);
+hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const int32_t *trows,
+                        const int64_t *seg, double *tA, double *tB, hipStream_t st);
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
                              const double *tB,

@@ -32,7 +32,8 @@ struct DCsr {
 // multiple of 32), bit-map words with prefix counts (rank table) and the
 // base tile index; the tiles in the A and B operand layouts.
 struct TileSet {
-    Buf lo, words, woff, rt, cnt, tb, tA, tB, cols;   // cols: block column of every tile
+    Buf lo, words, woff, rt, cnt, tb, tA, tB, cols, rows, seg;   // cols / rows: block column
+                                                                 // and row of every tile
     int64_t nb = 0, ntiles = 0;
 };
 
