@@ -118,13 +118,37 @@ __global__ void k_bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, con
     if (i >= T.n) return;
     const int64_t I = i >> 4;
     const int r = (int)(i & 15);
+    const int lane = lane_id();
     const int64_t b = T.rp[i], e = T.rp[i + 1];
-    for (int64_t p = b + lane_id(); p < e; p += kWave) {
-        const int J = T.ci[p] >> 4;
-        if (p > b && (T.ci[p - 1] >> 4) == J) continue;
-        int len = 1;
-        while (p + len < e && (T.ci[p + len] >> 4) == J) ++len;
-        const int64_t tt = tile_of(lo, woff, rt, tb, I, J);
+    const int loI = lo[I];
+    const int64_t w0 = woff[I], tbI = tb[I];
+    const unsigned long long above = lane == kWave - 1 ? 0ull : ~0ull << (lane + 1);
+    for (int64_t c0 = b; c0 < e; c0 += kWave) {
+        // segment starts of this chunk by ballot; a start's length runs to the
+        // next start, or past the chunk end for the chunk's last segment
+        const int64_t p = c0 + lane;
+        const bool valid = p < e;
+        const int J = valid ? T.ci[p] >> 4 : INT32_MAX;
+        int Jprev = __shfl_up(J, 1);
+        if (lane == 0) Jprev = c0 > b ? T.ci[c0 - 1] >> 4 : -1;
+        const bool start = valid && J != Jprev;
+        const unsigned long long sm = __ballot(start);
+        if (!start) continue;
+        const unsigned long long nx = sm & above;
+        int64_t len;
+        if (nx) {
+            len = __ffsll((long long)nx) - 1 - lane;
+        } else {
+            int64_t q = min<int64_t>(e, c0 + kWave);
+            len = q - p;
+            while (q < e && (T.ci[q] >> 4) == J) {
+                ++len;
+                ++q;
+            }
+        }
+        const int d = J - loI;
+        const uint2 w = rt[w0 + (d >> 5)];
+        const int64_t tt = tbI + w.y + __popc(w.x & ((1u << (d & 31)) - 1u));
         seg[tt * kTile + r] = (p << 5) | len;
     }
 }
