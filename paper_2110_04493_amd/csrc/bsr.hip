@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) void k_bsr_numeric(
         }
     }
     const int64_t W = woff[I + 1] - woff[I];
-    const int jlo = J[0], jhi = J[ng - 1];
+    const int jlo = J[0], jhi = last_of(J, ng);
     for (int64_t ww = 0; ww < W; ++ww) {
         uint32_t x = rt[woff[I] + ww].x;
         while (x) {
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
         }
     }
     const int64_t t0 = tb[I], nk = tb[I + 1] - t0;
-    const int jlo = J[0], jhi = J[ng - 1];
+    const int jlo = J[0], jhi = last_of(J, ng);
     auto item = [&](int64_t r, int &K, int &a) {
         K = tcols[t0 + r];
         a = (int)(t0 + r);

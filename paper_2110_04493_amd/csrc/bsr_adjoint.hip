@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
     // (T^T G)_IJ = sum over K in T's block column I of (T_KI)^T G_KJ
     {
         const int64_t p0 = cptr[I];
-        const int jlo = J[0], jhi = J[ng - 1];
+        const int jlo = J[0], jhi = last_of(J, ng);
         auto item = [&](int64_t r, int &K, int &a) {
             K = ck[p0 + r];
             a = (int)ct[p0 + r];

@@ -41,6 +41,17 @@ __device__ __forceinline__ int64_t tile_of(const int32_t *lo, const int64_t *wof
     return tb[K] + e.y + __popc(e.x & (bit - 1u));
 }
 
+// a[n - 1] of a small register array without a dynamic index (which would
+// move the array to scratch memory); n >= 1.
+template <int kN>
+__device__ __forceinline__ int last_of(const int (&a)[kN], int n) {
+    int v = a[0];
+#pragma unroll
+    for (int t = 1; t < kN; ++t)
+        if (t < n) v = a[t];
+    return v;
+}
+
 // 16-deep product of one A-operand tile with one B-operand tile into acc.
 __device__ __forceinline__ d4 mfma16(const d4 &a, const d4 &b, d4 acc) {
 #pragma unroll
