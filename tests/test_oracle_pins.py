@@ -304,6 +304,26 @@ def test_grid_rows_sum_to_one():
     assert np.max(np.abs(D - D.T)) <= 2 * res.stats["sq_theta"][-1]
 
 
+def test_unit_grid_kronecker_closed_form():
+    """Config 3's reference: for a unit grid e^{-tL} is the Kronecker product
+    of two path exponentials (exact cosine eigenbasis).  The oracle on a small
+    unit grid with config 3's t and tolerance matches it to 10 eps, and the
+    closed form itself has unit row sums."""
+    from _closed_forms import path_laplacian_expm, unit_grid_expm_row
+    m, t, eps = 24, 0.5, 1e-10
+    L = W.grid_laplacian(m, m, None)
+    H = L.scaled(-t)
+    res = oracle.expm(H.rowptr, H.col, H.val, eps)
+    E = W.to_dense(W.Csr(H.n, res.rowptr, res.col, res.val))
+    P = path_laplacian_expm(m, t)
+    X = np.stack([unit_grid_expm_row(P, m, i) for i in range(m * m)])
+    assert np.max(np.abs(X.sum(axis=1) - 1.0)) <= 1e-13
+    assert np.linalg.norm(E - X) / np.linalg.norm(X) <= 10 * eps
+    # the closed form against a dense Pade exponential of the same L
+    Xp = sla.expm(-t * W.to_dense(L))
+    assert np.max(np.abs(Xp - X)) <= 1e-14
+
+
 def test_inverse_identity():
     """e^H e^{-H} = I for a moderate-norm nonsymmetric H."""
     A = W.random_sparse(80, 0.04, 11, scale=0.8)
