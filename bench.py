@@ -41,6 +41,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=150)
     ap.add_argument("--forward-only", action="store_true")
+    ap.add_argument("--workload", choices=["grid", "batched", "grad"], default="grid",
+                    help="grid: the headline 2D heat-conduction workload (default); batched: "
+                         "many uneven instances of the batched family in one call, timed "
+                         "against a per-matrix loop; grad: the differentiation workload "
+                         "(200 x 200 grid, forward + adjoint), timed against a forward-only "
+                         "loop")
+    ap.add_argument("--count", type=int, default=64, help="batched: number of instances")
+    ap.add_argument("--nmin", type=int, default=500, help="batched: smallest n")
+    ap.add_argument("--nmax", type=int, default=2000, help="batched: largest n")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (the "
                          "reference kernel for scaling HBM counter readings) and exit")
@@ -128,6 +137,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "grad":
+        bench_grad(args)
         return
     import torch
     from paper_2110_04493_amd import api, workloads as W
@@ -232,6 +247,91 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, n)
+    print(json.dumps(out), flush=True)
+
+
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def bench_batched(args):
+    """Instances j = 0 .. count-1 of the batched family (even j: unit grid,
+    tau ~ U[1, 20]; odd j: random adjacency, beta ~ U[0.1, 1]; eps 1e-12),
+    n ~ U[nmin, nmax].  One expm_sparse_batched call against a loop of
+    expm_sparse calls on the same plan options, both on resident inputs."""
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    torch.cuda.set_device(0)
+    inst = [W.config4_instance(j, nmin=args.nmin, nmax=args.nmax) for j in range(args.count)]
+    dev = [tuple(torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)) for H, _ in inst]
+    eps = [e for _, e in inst]
+    plan = api.Plan("cuda", api.Options())
+    tb, tl = [], []
+    for it in range(args.warmup + args.steps):
+        t_b, outs = _sync_time(lambda: plan.expm_batched(dev, eps))
+        nnz_b = sum(int(o[2].numel()) for o in outs)
+        del outs
+        t_l, outs = _sync_time(lambda: [plan.expm(*d, e) for d, e in zip(dev, eps)])
+        nnz_l = sum(int(o[2].numel()) for o in outs)
+        del outs
+        if it >= args.warmup:
+            tb.append(t_b)
+            tl.append(t_l)
+    plan.close()
+    assert nnz_b == nnz_l
+    sec = float(np.median(tb))
+    out = {"metric": "batched expm wall time (one call) vs per-matrix loop",
+           "value": round(sec, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.count} instances of the batched family, n in "
+                                  f"[{args.nmin}, {args.nmax}], half unit grids (tau in [1, 20]), "
+                                  "half random adjacency (beta in [0.1, 1]), eps 1e-12",
+                      "count": args.count, "sum_n": int(sum(H.n for H, _ in inst)),
+                      "nnz_e_total": nnz_b, "parallelism": "single GPU"},
+           "loop_s": round(float(np.median(tl)), 5),
+           "speedup_vs_loop": round(float(np.median(tl)) / sec, 3)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_grad(args):
+    """The differentiation workload: 200 x 200 grid, lognormal(0, 0.5)
+    conductances, H = -5 L / ||L||_1, eps 1e-12, loss sum(G .* E) with G 2%
+    N(0, 1); forward + adjoint against the forward alone."""
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    torch.cuda.set_device(0)
+    H, eps = W.config5(200)
+    crow, col, val = (torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val))
+    plan = api.Plan("cuda", api.Options(keep_checkpoints=True))
+    rp, ci, v = plan.expm(crow, col, val, eps)
+    rows = np.repeat(np.arange(H.n), np.diff(rp.cpu().numpy()))
+    dE = torch.from_numpy(W.loss_weights(rows, ci.cpu().numpy(), H.n, density=0.02)).cuda()
+    tf, tfb = [], []
+    for it in range(args.warmup + args.steps):
+        t1, _ = _sync_time(lambda: plan.expm(crow, col, val, eps))
+        t2, _ = _sync_time(lambda: plan.backward(dE, val.numel()))
+        if it >= args.warmup:
+            tf.append(t1)
+            tfb.append(t1 + t2)
+    st = plan.stats()
+    plan.close()
+    sec = float(np.median(tfb))
+    out = {"metric": "expm forward + adjoint wall time (differentiation workload)",
+           "value": round(sec, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "2D 5-point grid 200x200 (n=40000), lognormal(0,0.5), "
+                                  "H=-5L/||L||_1, eps 1e-12, loss sum(G.*E), G 2% N(0,1)",
+                      "n": H.n, "nnz_e": int(st["nnz_e"]), "M": st["M"], "N": st["N"],
+                      "parallelism": "single GPU"},
+           "forward_s": round(float(np.median(tf)), 5),
+           "adjoint_over_forward": round(sec / float(np.median(tf)) - 1.0, 3)}
     print(json.dumps(out), flush=True)
 
 

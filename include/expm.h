@@ -103,6 +103,10 @@ typedef struct {
                                 the unpermuted method up to rounding order.
                                 -1 (default) on for n >= 4096 when the tile
                                 product can run, 0 off, 1 on                  */
+    double tile_min_fill;    /* a squaring step (and its adjoint) runs on 16x16
+                                tiles when T's stored entries fill at least
+                                this fraction of its tiles: < 0 (default)
+                                picks 0.2, 0 always tiles, > 1 never          */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',

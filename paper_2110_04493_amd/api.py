@@ -71,6 +71,7 @@ class Options:
     checkpoint_interval: int = 0
     profile: bool = False
     reorder: int = -1
+    tile_min_fill: float = -1.0
 
 
 class Plan:
@@ -94,6 +95,7 @@ class Plan:
         o.allocator = C.pointer(self.alloc.struct)
         o.profile = int(self.options.profile)
         o.reorder = int(self.options.reorder)
+        o.tile_min_fill = float(self.options.tile_min_fill)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)

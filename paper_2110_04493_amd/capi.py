@@ -58,7 +58,7 @@ class expm_opts(C.Structure):
                 ("max_filter_iter", C.c_int), ("keep_checkpoints", C.c_int),
                 ("checkpoint_interval", C.c_int), ("stream", C.c_void_p),
                 ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int),
-                ("reorder", C.c_int)]
+                ("reorder", C.c_int), ("tile_min_fill", C.c_double)]
 
 
 _S = EXPM_MAXSTEP

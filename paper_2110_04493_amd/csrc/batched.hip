@@ -599,7 +599,18 @@ int batched(expm_plan_s &P, BatchBufs &B, int count, const expm_csr_cview *H, co
         CsrView Tv{R, (const int64_t *)P.T.rp.p, (const int32_t *)P.T.ci.p,
                    (const double *)P.T.v.p};
         int64_t cand;
-        CHK(spgemm(P, Tv, P.T.nnz, Tv, 2.0, 1.0, true, &cand));
+        // 16 x 16 tiles on the matrix cores once the stacked iterate fills
+        // its tiles (cross-instance slots are exact zeros and drop out)
+        bool tiles = false;
+        if (tiles_allowed(P, R)) {
+            double fill = 0.0;
+            CHK(bsr_pattern(P, Tv, P.T.nnz, P.tsT, &fill));
+            tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
+        }
+        if (tiles)
+            CHK(tile_candidates(P, Tv, &cand));
+        else
+            CHK(spgemm(P, Tv, P.T.nnz, Tv, 2.0, 1.0, true, &cand));
         HIPCHK(segment_sums((const double *)P.rowsq.p, (const int64_t *)B.rowoff.p, Ka,
                             (double *)B.norm2.p, st));
         for (int k = 0; k < Ka; ++k) {

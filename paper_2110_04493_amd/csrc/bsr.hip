@@ -643,6 +643,42 @@ __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
     }
 }
 
+// Per row i < n of the candidate: sum over the row's tile slots of
+// (c_ij + delta_ij)^2, plus 1 when the row's diagonal tile is absent (its
+// row's contribution to ||I + C||_F^2; padding slots hold zeros).
+__global__ void k_bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt,
+                            const int32_t *ccols, const double *ctiles, double *rowsq) {
+    const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (I >= (n + kTile - 1) / kTile) return;
+    const int lane = lane_id();
+    const int g = lane >> 4, cl = lane & 15;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    bool diag = false;
+    const int64_t base = ctb[I], cntI = ccnt[I];
+    for (int64_t t = 0; t < cntI; ++t) {
+        const int64_t tt = base + t;
+        const bool dtile = ccols[tt] == (int)I;
+        diag |= dtile;
+        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double f = dtile && g + 4 * k == cl ? v[k] + 1.0 : v[k];
+            s4[k] = fma(f, f, s4[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) s4[k] += __shfl_xor(s4[k], o);
+    if (cl == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = I * kTile + g + 4 * k;
+            if (i < n) rowsq[i] = diag ? s4[k] : s4[k] + 1.0;
+        }
+    }
+}
+
 // ----------------------------------------------------------------- host wrappers
 
 size_t bsr_lds_words(int64_t n) { return (size_t)((n + 15) / 16 + 31) / 32 + 2; }
@@ -800,6 +836,15 @@ hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *cc
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_norm, dim3((nb + 3) / 4), dim3(256), 0, st, n, nb, ctb, ccnt, ccols,
                        ctiles, bsq, bnz);
+    return hipGetLastError();
+}
+
+hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                     const double *ctiles, double *rowsq, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int64_t nb = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_bsr_rowsq, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
+                       ctiles, rowsq);
     return hipGetLastError();
 }
 

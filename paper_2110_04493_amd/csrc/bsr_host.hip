@@ -66,32 +66,16 @@ int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts) {
     return EXPM_OK;
 }
 
-// One filtered squaring on tiles (T's pattern already in P.tsT): fills the
-// candidate tiles, runs Algorithm 4.1 (or applies theta_fixed) and writes the
-// kept entries of T~ into dst as CSR.
-int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
-                    double theta_fixed, bool exact_alloc, int stat_i) {
+// C = 2T + T*T on tiles (T's pattern already in P.tsT): T's tiles, C's tile
+// pattern (rank table, panels) and the candidate tiles in P.c_tiles; the
+// product kernel is bracketed by events ev[1], ev[2] when prof.  *ctiles_out
+// receives the number of candidate tiles.
+int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
     hipStream_t st = P.st;
     TileSet &ts = P.tsT;
     const int64_t n = T.n, nb = ts.nb;
-    // profiling covers every launch (recomputation too); the per-step
-    // statistics only the forward steps (stat_i > 0)
-    const bool prof = P.opts.profile && P.have_events;
     int64_t *hl = (int64_t *)P.host;
-    if (prof) {
-        // algorithmic partial products of T*T (for the statistics only)
-        CHK(ensure(P, P.lo, sizeof(int32_t) * n));
-        CHK(ensure(P, P.words, sizeof(int64_t) * (n + 1)));
-        CHK(ensure(P, P.ub, sizeof(int64_t) * (n + 1)));
-        CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
-        HIPCHK(row_bounds(T.view(), T.view(), 1, (int32_t *)P.lo.p, (int64_t *)P.words.p,
-                          (int64_t *)P.ub.p, st));
-        CHK(scan(P, (const int64_t *)P.ub.p, (int64_t *)P.tmp1.p, n));
-        HIPCHK(hipMemcpyAsync(hl + 16, (int64_t *)P.tmp1.p + n, sizeof(int64_t),
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(P.ev[0], st));
-    }
-    CHK(bsr_tiles(P, T.view(), ts));
+    CHK(bsr_tiles(P, T, ts));
     // C's tile pattern
     CHK(ensure(P, P.c_lo, sizeof(int32_t) * (nb + 1)));
     CHK(ensure(P, P.c_words, sizeof(int64_t) * (nb + 1)));
@@ -175,6 +159,71 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                            (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
                            (const int32_t *)P.c_cols.p, (double *)P.c_tiles.p, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
+    *ctiles_out = ctiles;
+    return EXPM_OK;
+}
+
+// T~ = 2T + T*T on tiles, returned unfiltered as a CSR candidate in
+// P.crp / P.cci / P.cv (every nonzero slot, columns sorted) with the rows'
+// contributions to ||I + T~||_F^2 in P.rowsq: the same outputs as the
+// scalar product, for callers that filter rows with per-row thresholds
+// (the batched path).  T's pattern must already be in P.tsT.
+int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand) {
+    hipStream_t st = P.st;
+    const int64_t n = T.n;
+    int64_t ctiles = 0;
+    CHK(tile_product(P, T, false, &ctiles));
+    const int64_t *ctb = (const int64_t *)P.c_tb.p, *ccnt = (const int64_t *)P.c_cnt.p;
+    const int32_t *ccols = (const int32_t *)P.c_cols.p;
+    const double *ctl_tiles = (const double *)P.c_tiles.p;
+    CHK(ensure(P, P.rowsq, sizeof(double) * (n + 1)));
+    HIPCHK(bsr_rowsq(n, ctb, ccnt, ccols, ctl_tiles, (double *)P.rowsq.p, st));
+    CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
+    CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.crp, sizeof(int64_t) * (n + 1)));
+    FilterCtl *ctl = (FilterCtl *)P.ctl.p;
+    HIPCHK(filter_init_theta(ctl, 0.0, st));   // keep every nonzero slot
+    HIPCHK(bsr_count(n, ctb, ccnt, ccols, ctl_tiles, ctl, (int64_t *)P.cnt.p, st));
+    CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.crp.p, n));
+    int64_t *hl = (int64_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.crp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    *cand = hl[0];
+    CHK(ensure(P, P.cci, sizeof(int32_t) * (*cand + 1)));
+    CHK(ensure(P, P.cv, sizeof(double) * (*cand + 1)));
+    HIPCHK(bsr_write(n, ctb, ccnt, ccols, ctl_tiles, ctl, (const int64_t *)P.crp.p,
+                     (int32_t *)P.cci.p, (double *)P.cv.p, st));
+    return EXPM_OK;
+}
+
+// One filtered squaring on tiles (T's pattern already in P.tsT): fills the
+// candidate tiles, runs Algorithm 4.1 (or applies theta_fixed) and writes the
+// kept entries of T~ into dst as CSR.
+int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
+                    double theta_fixed, bool exact_alloc, int stat_i) {
+    hipStream_t st = P.st;
+    TileSet &ts = P.tsT;
+    const int64_t n = T.n, nb = ts.nb;
+    // profiling covers every launch (recomputation too); the per-step
+    // statistics only the forward steps (stat_i > 0)
+    const bool prof = P.opts.profile && P.have_events;
+    int64_t *hl = (int64_t *)P.host;
+    if (prof) {
+        // algorithmic partial products of T*T (for the statistics only)
+        CHK(ensure(P, P.lo, sizeof(int32_t) * n));
+        CHK(ensure(P, P.words, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.ub, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
+        HIPCHK(row_bounds(T.view(), T.view(), 1, (int32_t *)P.lo.p, (int64_t *)P.words.p,
+                          (int64_t *)P.ub.p, st));
+        CHK(scan(P, (const int64_t *)P.ub.p, (int64_t *)P.tmp1.p, n));
+        HIPCHK(hipMemcpyAsync(hl + 16, (int64_t *)P.tmp1.p + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(P.ev[0], st));
+    }
+    int64_t ctiles = 0;
+    CHK(tile_product(P, T.view(), prof, &ctiles));
     // ||I + T~||_F and the nonzero candidate count
     CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));
     CHK(ensure(P, P.b_nz, sizeof(int64_t) * (nb + 1)));

@@ -722,17 +722,11 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     if (keep) CHK(copy_csr(P, P.TN, P.T));
     // E = I + T_N (exact zeros not stored)
     {
-        CHK(ensure(P, P.crp, sizeof(int64_t) * (n + 1)));
-        CHK(ensure(P, P.cci, sizeof(int32_t) * (P.T.nnz + 1)));
-        CHK(ensure(P, P.cv, sizeof(double) * (P.T.nnz + 1)));
-        HIPCHK(hipMemcpyAsync(P.crp.p, P.T.rp.p, sizeof(int64_t) * (n + 1),
-                              hipMemcpyDeviceToDevice, st));
-        if (P.T.nnz) {
-            HIPCHK(hipMemcpyAsync(P.cci.p, P.T.ci.p, sizeof(int32_t) * P.T.nnz,
-                                  hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(P.cv.p, P.T.v.p, sizeof(double) * P.T.nnz,
-                                  hipMemcpyDeviceToDevice, st));
-        }
+        // T_N becomes the candidate of the compaction (buffers handed over,
+        // not copied; P.T is rebuilt by the next call)
+        std::swap(P.crp, P.T.rp);
+        std::swap(P.cci, P.T.ci);
+        std::swap(P.cv, P.T.v);
         FilterCtl h{};
         int64_t kept;
         CHK(filter_and_count(P, n, P.T.nnz, 0.0, nullptr, true, -1.0, true, &h, &kept));
@@ -942,6 +936,7 @@ void expm_opts_default(expm_opts *o) {
     o->stream = nullptr;
     o->allocator = nullptr;
     o->reorder = -1;
+    o->tile_min_fill = -1.0;
 }
 
 int expm_plan(expm_plan_t *out, const expm_opts *opts) {
@@ -956,13 +951,14 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.filter_mode != EXPM_FILTER_PAPER && o.filter_mode != EXPM_FILTER_NONE)
         return fail(EXPM_EINVAL, "unknown filter_mode %d", o.filter_mode);
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
-        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1)
+        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1 ||
+        !(o.tile_min_fill == o.tile_min_fill))
         return fail(EXPM_EINVAL, "invalid option value");
     expm_plan_s *P = new (std::nothrow) expm_plan_s();
     if (!P) return fail(EXPM_ENOMEM, "cannot allocate the plan");
     P->opts = o;
     P->st = (hipStream_t)o.stream;
-    if (const char *f = getenv("EXPM_BSR_FILL")) P->bsr_min_fill = atof(f);
+    if (o.tile_min_fill >= 0.0) P->bsr_min_fill = o.tile_min_fill;
     if (const char *f = getenv("EXPM_BSR_PANEL")) P->bsr_panels = f[0] != '0';
     if (hipHostMalloc((void **)&P->host, 4096, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();

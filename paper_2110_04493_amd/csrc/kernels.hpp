@@ -132,6 +132,8 @@ hipError_t bsr_numeric(int64_t nb, const int32_t *lo, const int64_t *woff, const
 hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                     const int32_t *ccols, const double *ctiles, double *bsq, int64_t *bnz,
                     hipStream_t st);
+hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                     const double *ctiles, double *rowsq, hipStream_t st);
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const FilterCtl *c, int64_t *cnt, hipStream_t st);
 hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,

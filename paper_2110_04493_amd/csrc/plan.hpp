@@ -92,8 +92,9 @@ struct expm_plan_s {
     xpm::host::Buf order, newidx, hmap, emap, ro_rb, ro_d0, ro_d1, ro_d3, ro_q0, ro_q1, ro_cell,
         ro_cnt, ro_off, ro_pcnt, ro_pw, ro_pofs, ro_gbits;
     xpm::host::DCsr Hp, Eperm;
-    // tile fill of T from which the tile product is used; on MI355X at
-    // n = 90,000 the two paths cost the same at a fill of about 0.2
+    // tile fill of T from which the tile product is used (opts.tile_min_fill;
+    // default 0.2, where the two paths cost about the same on MI355X at
+    // n = 90,000 in natural order)
     double bsr_min_fill = 0.2;
 };
 
@@ -124,6 +125,9 @@ int check_view(const expm_csr_cview *H);
 void free_adjoint_state(expm_plan_s &P);
 int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill);
 int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts);
+bool tiles_allowed(const expm_plan_s &P, int64_t n);
+int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out);
+int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand);
 int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
                     double theta_fixed, bool exact_alloc, int stat_i);
 // One adjoint step on tiles: out (aligned with Tp's entries) =

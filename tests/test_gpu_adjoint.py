@@ -40,8 +40,7 @@ def oracle_grad(H, eps, density=0.3, seed=5000, **kw):
 def check(H, eps, density=0.3, **opts):
     print(f"[adjoint] n={H.n} nnz={H.nnz} eps={eps} {opts}", flush=True)
     okw = {k: v for k, v in opts.items() if k in ("filter_mode", "normal")}
-    gopts = {k: v for k, v in opts.items() if k not in ("normal",) or True}
-    dg, sg = gpu_grad(H, eps, density, **gopts)
+    dg, sg = gpu_grad(H, eps, density, **opts)
     do, so = oracle_grad(H, eps, density, **okw)
     rel = np.linalg.norm(dg - do) / max(np.linalg.norm(do), 1e-300)
     print(f"  rel={rel:.3e} N={sg['N']} M={sg['M']} taylor={sg['taylor_terms']}", flush=True)

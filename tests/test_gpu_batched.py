@@ -25,8 +25,8 @@ def run_batched(mats, eps, **opts):
     return res, st
 
 
-def check_all(mats, eps, vs_single=True):
-    outs, _ = run_batched(mats, eps)
+def check_all(mats, eps, vs_single=True, **opts):
+    outs, _ = run_batched(mats, eps, **opts)
     for j, (H, Eb) in enumerate(zip(mats, outs)):
         Eo, so = run_oracle(H, eps[j])
         rel, ok, og, oo = compare(Eb, Eo, final_theta(so))
@@ -48,6 +48,20 @@ def test_batched_workload_family_small():
         mats.append(H)
         eps.append(e)
     check_all(mats, eps)
+
+
+@pytest.mark.parametrize("fill", [0.0, 2.0])
+def test_batched_product_paths(fill):
+    """The batched product on 16 x 16 tiles for every step (fill 0) and on
+    scalar rows only (fill 2); instance sizes not multiples of 16, so tiles
+    straddle instances."""
+    mats, eps = [], []
+    for j in range(6):
+        H, e = W.config4_instance(j, nmin=50, nmax=300)
+        mats.append(H)
+        eps.append(e)
+    print(f"[batched tile_min_fill={fill}] n={[H.n for H in mats]}", flush=True)
+    check_all(mats, eps, vs_single=False, tile_min_fill=fill)
 
 
 def test_batched_mixed_edge_cases():

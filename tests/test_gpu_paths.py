@@ -1,7 +1,7 @@
 """Both squaring paths (16x16 tiles on matrix cores, scalar rows) forced on
 their own, with and without the locality reordering, forward and adjoint,
-against the oracle.  EXPM_BSR_FILL is read when a plan is created: 0 takes
-tiles at every squaring step, 2 never."""
+against the oracle.  tile_min_fill = 0 takes tiles at every squaring step,
+2 never."""
 import numpy as np
 import pytest
 
@@ -38,10 +38,9 @@ def disconnected():
 @pytest.mark.parametrize("reorder", [0, 1])
 @pytest.mark.parametrize("fill", ["0", "2"])
 @pytest.mark.parametrize("name,H,eps", list(cases()), ids=[c[0] for c in cases()])
-def test_forward_paths(monkeypatch, fill, reorder, name, H, eps):
-    monkeypatch.setenv("EXPM_BSR_FILL", fill)
+def test_forward_paths(fill, reorder, name, H, eps):
     print(f"[{name} fill={fill} reorder={reorder}] n={H.n}", flush=True)
-    Eg, sg = run_gpu(H, eps, reorder=reorder)
+    Eg, sg = run_gpu(H, eps, reorder=reorder, tile_min_fill=float(fill))
     Eo, so = run_oracle(H, eps)
     rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
     print(f"[{name} fill={fill} reorder={reorder}] relF={rel:.2e} only={og},{oo}", flush=True)
@@ -52,10 +51,10 @@ def test_forward_paths(monkeypatch, fill, reorder, name, H, eps):
 @pytest.mark.parametrize("reorder", [0, 1])
 @pytest.mark.parametrize("fill", ["0", "2"])
 @pytest.mark.parametrize("name,H,eps", list(cases()), ids=[c[0] for c in cases()])
-def test_adjoint_paths(monkeypatch, fill, reorder, name, H, eps):
-    monkeypatch.setenv("EXPM_BSR_FILL", fill)
+def test_adjoint_paths(fill, reorder, name, H, eps):
     print(f"[{name} fill={fill} reorder={reorder}] adjoint n={H.n}", flush=True)
-    dg, _ = gpu_grad(H, eps, density=0.2, checkpoint_interval=2, reorder=reorder)
+    dg, _ = gpu_grad(H, eps, density=0.2, checkpoint_interval=2, reorder=reorder,
+                     tile_min_fill=float(fill))
     do, _ = oracle_grad(H, eps, density=0.2)
     rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
     print(f"[{name} fill={fill} reorder={reorder}] adjoint rel={rel:.2e}", flush=True)
@@ -63,11 +62,10 @@ def test_adjoint_paths(monkeypatch, fill, reorder, name, H, eps):
 
 
 @pytest.mark.parametrize("reorder", [0, 1])
-def test_tiles_deterministic(monkeypatch, reorder):
-    monkeypatch.setenv("EXPM_BSR_FILL", "0")
+def test_tiles_deterministic(reorder):
     H, eps = W.config5(40)
-    E1, _ = run_gpu(H, eps, reorder=reorder)
-    E2, _ = run_gpu(H, eps, reorder=reorder)
+    E1, _ = run_gpu(H, eps, reorder=reorder, tile_min_fill=0.0)
+    E2, _ = run_gpu(H, eps, reorder=reorder, tile_min_fill=0.0)
     assert np.array_equal(E1.col, E2.col)
     assert np.array_equal(E1.val.view(np.uint64), E2.val.view(np.uint64))
 
@@ -88,9 +86,8 @@ def test_reorder_matches_natural_order():
 def test_row_work_items(monkeypatch, name, H, eps):
     """The tile product with one block row per work item (instead of panels
     of four) gives the same parity."""
-    monkeypatch.setenv("EXPM_BSR_FILL", "0")
     monkeypatch.setenv("EXPM_BSR_PANEL", "0")
-    Eg, _ = run_gpu(H, eps, reorder=1)
+    Eg, _ = run_gpu(H, eps, reorder=1, tile_min_fill=0.0)
     Eo, so = run_oracle(H, eps)
     rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
     print(f"[{name} row work items] relF={rel:.2e} only={og},{oo}", flush=True)
