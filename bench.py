@@ -57,7 +57,7 @@ def parse():
 
 
 TILE_SOURCES = ("paper_2110_04493_amd/csrc/bsr.hip", "paper_2110_04493_amd/csrc/bsr_common.hpp")
-TRAFFIC_FILE = "profiles/k_bsr_numeric_grid300_traffic.md"
+TRAFFIC_FILE = "profiles/k_bsr_numeric_panel_grid300_traffic.md"
 
 
 def kernel_source_digest() -> str:
@@ -202,7 +202,7 @@ def main():
         ach = fl_launch / (avg_ms * 1e9)
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
-                "traffic": measured_traffic(fl_launch), "kernel": "k_bsr_numeric",
+                "traffic": measured_traffic(fl_launch), "kernel": "k_bsr_numeric_panel",
                 "launches": tl["launches"], "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_flop_per_launch": round(fl_launch)}
     else:
