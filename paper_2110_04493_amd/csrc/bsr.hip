@@ -471,14 +471,15 @@ __global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
     int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
     const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
     const int32_t *__restrict__ tcols, const double *__restrict__ tA,
-    const double *__restrict__ tB, const int64_t *__restrict__ pgofs, int64_t np,
+    const double *__restrict__ tB, const int64_t *__restrict__ pgofs,
+    const int64_t *__restrict__ nwork_dev, int64_t np,
     const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
-    int64_t nwork, int remap) {
+    int remap) {
     const int lane = lane_id();
     const int64_t w = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    if (w >= nwork) return;
+    if (w >= *nwork_dev) return;
     int64_t lo_p = 0, hi_p = np - 1;   // last panel with pgofs[p] <= w
     while (lo_p < hi_p) {
         const int64_t mid = (lo_p + hi_p + 1) >> 1;
@@ -766,8 +767,8 @@ hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const i
 
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
-                             const double *tB,
-                             const int64_t *pgofs, const int64_t *pofs, const int32_t *pcols,
+                             const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
+                             const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
@@ -777,8 +778,8 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
     }();
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
-                       (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb, ctiles,
-                       nwork, remap);
+                       nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
+                       ctiles, remap);
     return hipGetLastError();
 }
 

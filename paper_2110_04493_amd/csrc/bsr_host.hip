@@ -30,10 +30,16 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
     HIPCHK(bsr_bounds(T, nb, (int32_t *)ts.lo.p, (int64_t *)ts.words.p, st));
     CHK(scan(P, (const int64_t *)ts.words.p, (int64_t *)ts.woff.p, nb));
     int64_t *hl = (int64_t *)P.host;
-    HIPCHK(hipMemcpyAsync(hl, (int64_t *)ts.woff.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
-                          st));
-    CHK(sync(P));
-    const int64_t words = hl[0];
+    // a block row's bit map spans at most (nb + 31) / 32 + 1 words: when that
+    // bound is small the rank table is sized by it, saving a readback
+    const int64_t bound = nb * ((nb + 31) / 32 + 1);
+    int64_t words = bound;
+    if (bound * (int64_t)sizeof(uint2) > ((int64_t)64 << 20)) {
+        HIPCHK(hipMemcpyAsync(hl, (int64_t *)ts.woff.p + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        words = hl[0];
+    }
     CHK(ensure(P, ts.rt, sizeof(uint2) * (words + 1)));
     HIPCHK(bsr_bitmap(T, nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
                       (uint2 *)ts.rt.p, (int64_t *)ts.cnt.p, st));
@@ -139,16 +145,17 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
                               (int32_t *)P.p_cols.p, st));
         HIPCHK(bsr_panel_groups((const int64_t *)P.p_cnt.p, nb, (int64_t *)P.p_gcnt.p, st));
         CHK(scan(P, (const int64_t *)P.p_gcnt.p, (int64_t *)P.p_gofs.p, np));
-        HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.p_gofs.p + np, sizeof(int64_t),
-                              hipMemcpyDeviceToHost, st));
-        CHK(sync(P));
-        nwork = hl[1];
+        // launched on a bound of the work-item count (a panel's union holds
+        // at most the sum of its rows' tiles); the kernel reads the exact
+        // count, p_gofs[np], and surplus workgroups return at once
+        nwork = ctiles / 4 + np + 1;
     }
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
     if (panels)
         HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
                                  (const double *)ts.tA.p,
                                  (const double *)ts.tB.p, (const int64_t *)P.p_gofs.p,
+                                 (const int64_t *)P.p_gofs.p + (nb + 3) / 4,
                                  (const int64_t *)P.p_ofs.p, (const int32_t *)P.p_cols.p,
                                  (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
                                  (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,

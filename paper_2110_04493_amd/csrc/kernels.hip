@@ -78,6 +78,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const int64_t *in, in
     }
 }
 
+// Arrays of up to kScanSmall entries are scanned by one block in one launch
+// (tile by tile with a running carry): most scans here are over block rows
+// or panels, where the three launches would cost more than the work.
+constexpr int64_t kScanSmall = 16 * kScanTile;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_one(const int64_t *in, int64_t n,
+                                                         int64_t *out) {
+    long long carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += kScanTile) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * kScanItems;
+        long long v[kScanItems];
+        long long s = 0;
+        for (int j = 0; j < kScanItems; j++) {
+            const int64_t idx = base + j;
+            v[j] = idx < n ? in[idx] : 0;
+            s += v[j];
+        }
+        long long tot;
+        long long ex = block_excl_scan(s, &tot) + carry;
+        for (int j = 0; j < kScanItems; j++) {
+            const int64_t idx = base + j;
+            if (idx < n) out[idx] = ex;
+            ex += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 size_t scan_tmp_bytes(int64_t n) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     return (size_t)(nb + 1) * sizeof(int64_t);
@@ -90,6 +119,10 @@ hipError_t scan_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_
     int64_t *bsum = (int64_t *)tmp;
     if (n == 0) {
         return hipMemsetAsync(out, 0, sizeof(int64_t), st);
+    }
+    if (n <= kScanSmall) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanBlock), 0, st, in, n, out);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, in, n, bsum);
     hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(kScanBlock), 0, st, bsum, nb, out + n);

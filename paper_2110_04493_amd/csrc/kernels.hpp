@@ -120,8 +120,8 @@ hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const i
                         const int64_t *seg, double *tA, double *tB, hipStream_t st);
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
-                             const double *tB,
-                             const int64_t *pgofs, const int64_t *pofs, const int32_t *pcols,
+                             const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
+                             const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st);
 hipError_t bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, hipStream_t st);
