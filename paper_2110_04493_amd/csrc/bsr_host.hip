@@ -327,14 +327,14 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
 // Adjoint squaring step on tiles.  Tp's pattern must already be in P.tsT
 // (bsr_pattern); G's pattern is that of Tk.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out) {
+                     double *out, bool g_pattern_ready) {
     hipStream_t st = P.st;
     TileSet &T = P.tsT, &G = P.tsG;
     const int64_t nb = T.nb;
     CHK(bsr_tiles(P, Tp.view(), T));
     const CsrView Gv{Tk.n, (const int64_t *)Tk.rp.p, (const int32_t *)Tk.ci.p, g};
     double fg;
-    CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));
+    if (!g_pattern_ready) CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));
     CHK(bsr_tiles(P, Gv, G));
     // T's block columns as sorted lists (T^T's block rows)
     CHK(ensure(P, P.tc_cnt, sizeof(int64_t) * (nb + 1)));

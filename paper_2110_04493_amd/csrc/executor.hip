@@ -815,6 +815,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     int seg_base = -1;
     DCsr Tt;
     const DCsr *Tk = &P.TN;   // pattern of g
+    bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     for (int k = N; k >= 1; --k) {
         const int km1 = k - 1;
         const int base = (km1 / ck) * ck;
@@ -838,14 +839,15 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         }
         CHK(ensure(P, gn, sizeof(double) * (Tp->nnz + 1)));
         // tiles when T_{k-1}'s tile fill is high enough, as in the forward
-        bool tiles = false;
+        bool tiles = false, have_pattern = false;
         if (tiles_allowed(P, n)) {
             double fill = 0.0;
             CHK(bsr_pattern(P, Tp->view(), Tp->nnz, P.tsT, &fill));
+            have_pattern = true;
             tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
         }
         if (tiles) {
-            CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p));
+            CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p, g_ready));
         } else {
             CHK(transpose_csr(P, *Tp, Tt));
             CsrView Gk = CsrView{n, (const int64_t *)Tk->rp.p, (const int32_t *)Tk->ci.p,
@@ -855,6 +857,10 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         }
         std::swap(g, gn);
         Tk = Tp;
+        // T_{k-1}'s tile pattern is the pattern of the next step's gradient:
+        // keep it in tsG (recomputation below reuses tsT)
+        if (have_pattern) std::swap(P.tsT, P.tsG);
+        g_ready = have_pattern;
         if (k - 1 == base && seg_base == base) {
             for (auto &A : seg) release(P, A);
             seg.clear();

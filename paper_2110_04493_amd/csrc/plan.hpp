@@ -131,9 +131,10 @@ int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand);
 int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
                     double theta_fixed, bool exact_alloc, int stat_i);
 // One adjoint step on tiles: out (aligned with Tp's entries) =
-// P_Tp(2 G + G Tp^T + Tp^T G), with G given on the pattern of Tk.
+// P_Tp(2 G + G Tp^T + Tp^T G), with G given on the pattern of Tk.  Tp's tile
+// pattern must be in P.tsT; with g_pattern_ready, P.tsG already holds Tk's.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out);
+                     double *out, bool g_pattern_ready);
 void release(expm_plan_s &P, TileSet &ts);
 int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,

@@ -11,11 +11,11 @@
 // tiles per block row and the matrix-core work of the late squarings.
 //
 // The cells come from graph distances alone, with no coordinates: breadth-
-// first distances d1, d3 from two far-apart nodes (u1, found from node 0,
-// and u3, the node farthest from both u1 and the node u2 farthest from u1)
-// act as two coordinates, and nodes are grouped by (d1 / 4, d3 / 8) and
-// ordered by cell, then by index.  Graphs without such structure (small
-// diameter, so very full cells) keep their order.
+// first distances d1, d3 from two far-apart nodes (u1, the node farthest
+// from node 0, and u3, the node farthest from both node 0 and u1) act as two
+// coordinates, and nodes are grouped by (d1 / 4, d3 / 8) and ordered by
+// cell, then by index.  Graphs without such structure (small diameter, so
+// very full cells) keep their order.
 #include <string.h>
 
 #include "plan.hpp"
@@ -284,11 +284,11 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
                            res);
         return hipGetLastError();
     };
-    // rb: [0] node 0 | [1..2] u1, max d0 | [3..4] u2, max d1 | [5..6] u3 | [7..8] -, max d3
+    // rb: [0] node 0 | [1..2] u1, max d0 | [3..4] u3 = argmax min(d0, d1), max d1 |
+    //     [7..8] -, max d3
     HIPCHK(bfs(rb + 0, d0, nullptr, rb + 1));
-    HIPCHK(bfs(rb + 1, d1, nullptr, rb + 3));
-    HIPCHK(bfs(rb + 3, d0, d1, rb + 5));
-    HIPCHK(bfs(rb + 5, d3, nullptr, rb + 7));
+    HIPCHK(bfs(rb + 1, d1, d0, rb + 3));
+    HIPCHK(bfs(rb + 3, d3, nullptr, rb + 7));
     int32_t *hb = (int32_t *)P.host;
     HIPCHK(hipMemcpyAsync(hb, rb, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, st));
     CHK(sync(P));
