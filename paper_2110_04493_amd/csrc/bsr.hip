@@ -300,87 +300,6 @@ __global__ void k_bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, int
 
 // ----------------------------------------------------------------- product
 
-// One wave per work item (block row I, group of up to kGroup consecutive
-// tiles of C's block row I).  For every block column K of T's block row I
-// (ascending) the tiles T_KJ of the group's block columns are found by rank;
-// when at least one exists, T_IK is loaded once (A layout) and each T_KJ
-// (B layout) is multiplied in with four 16x16x4 instructions.
-template <int kGroup>
-__global__ __launch_bounds__(256) void k_bsr_numeric(
-    int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
-    const uint2 *__restrict__ rt, const int64_t *__restrict__ tb, const double *__restrict__ tA,
-    const double *__restrict__ tB, const int64_t *__restrict__ gofs,
-    const int64_t *__restrict__ ctb, const int64_t *__restrict__ ccnt,
-    const int32_t *__restrict__ ccols, double *__restrict__ ctiles, int64_t nwork, int remap) {
-    const int lane = lane_id();
-    const unsigned blk = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int64_t w = (int64_t)blk * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (w >= nwork) return;
-    int64_t lo_i = 0, hi_i = nb - 1;   // last I with gofs[I] <= w
-    while (lo_i < hi_i) {
-        const int64_t mid = (lo_i + hi_i + 1) >> 1;
-        if (gofs[mid] <= w) lo_i = mid; else hi_i = mid - 1;
-    }
-    const int64_t I = lo_i;
-    const int64_t g0 = (w - gofs[I]) * kGroup;
-    const int ng = (int)min<int64_t>(kGroup, ccnt[I] - g0);
-    int J[kGroup];
-#pragma unroll
-    for (int t = 0; t < kGroup; ++t) J[t] = t < ng ? ccols[ctb[I] + g0 + t] : -1;
-    d4 acc[kGroup];
-#pragma unroll
-    for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    // 2 T_IJ = (2 I_16) T_IJ: lane l's A operand of slice kk is 2 on the
-    // diagonal (row l % 16 == column 4 kk + l / 16).
-    {
-        double two[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) two[kk] = (lane & 15) == 4 * kk + (lane >> 4) ? 2.0 : 0.0;
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t) {
-            if (t >= ng) break;
-            const int64_t tt = tile_of(lo, woff, rt, tb, I, J[t]);
-            if (tt < 0) continue;
-            const d4 b = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(two[kk], b[kk], acc[t], 0, 0, 0);
-        }
-    }
-    const int64_t W = woff[I + 1] - woff[I];
-    const int jlo = J[0], jhi = last_of(J, ng);
-    for (int64_t ww = 0; ww < W; ++ww) {
-        uint32_t x = rt[woff[I] + ww].x;
-        while (x) {
-            const int K = lo[I] + 32 * (int)ww + __ffs(x) - 1;
-            x &= x - 1;
-            const int64_t WK = woff[K + 1] - woff[K];
-            if (WK == 0 || jhi < lo[K] || jlo >= lo[K] + 32 * (int)WK) continue;
-            int64_t tk[kGroup];
-            bool any = false;
-#pragma unroll
-            for (int t = 0; t < kGroup; ++t) {
-                tk[t] = t < ng ? tile_of(lo, woff, rt, tb, K, J[t]) : -1;
-                any = any || tk[t] >= 0;
-            }
-            if (!any) continue;
-            const int64_t ta = tb[I] + rt[woff[I] + ww].y + __popc(rt[woff[I] + ww].x & ((1u << (K - lo[I] - 32 * (int)ww)) - 1u));
-            const d4 a = *(const d4 *)(tA + ta * kTileElems + 4 * lane);
-#pragma unroll
-            for (int t = 0; t < kGroup; ++t) {
-                if (tk[t] < 0) continue;
-                const d4 b = *(const d4 *)(tB + tk[t] * kTileElems + 4 * lane);
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc[t], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < kGroup; ++t)
-        if (t < ng) *(d4 *)(ctiles + (ctb[I] + g0 + t) * kTileElems + 4 * lane) = acc[t];
-}
-
 // ----------------------------------------------------------------- panels
 //
 // A panel is kPanel consecutive block rows of C.  Its four waves (one block
@@ -475,10 +394,9 @@ __global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
     const int64_t *__restrict__ nwork_dev, int64_t np,
     const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
-    const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
-    int remap) {
+    const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles) {
     const int lane = lane_id();
-    const int64_t w = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
     int64_t lo_p = 0, hi_p = np - 1;   // last panel with pgofs[p] <= w
     while (lo_p < hi_p) {
@@ -772,62 +690,10 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
-    static const int remap = [] {
-        const char *e = getenv("EXPM_BSR_REMAP");
-        return e && e[0] == '1' ? 1 : 0;
-    }();
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, remap);
-    return hipGetLastError();
-}
-
-// Output tiles per work item (4, 8 or 16; EXPM_BSR_GROUP) and the block
-// mapping of the product (default 0: hardware round-robin over the XCDs, so
-// the chip works on one band of block rows whose tiles stay in the shared
-// last-level cache; EXPM_BSR_REMAP=1: contiguous work-item ranges per XCD).
-// Measured on MI355X at n = 90,000: 4 tiles and round-robin are fastest
-// (larger groups reuse A tiles but lose occupancy).
-static int bsr_group() {
-    static const int g = [] {
-        const char *e = getenv("EXPM_BSR_GROUP");
-        const int v = e ? atoi(e) : 4;
-        return v == 8 || v == 16 ? v : 4;
-    }();
-    return g;
-}
-
-hipError_t bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, hipStream_t st) {
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_groups, dim3((nb + 255) / 256), dim3(256), 0, st, ccnt, nb, gcnt,
-                       bsr_group());
-    return hipGetLastError();
-}
-
-hipError_t bsr_numeric(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                       const int64_t *tb, const double *tA, const double *tB, const int64_t *gofs,
-                       const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                       double *ctiles, int64_t nwork, hipStream_t st) {
-    if (nwork == 0) return hipSuccess;
-    static const int remap = [] {
-        const char *e = getenv("EXPM_BSR_REMAP");
-        return e && e[0] == '1' ? 1 : 0;
-    }();
-    const dim3 grid((nwork + 3) / 4), block(256);
-    switch (bsr_group()) {
-    case 4:
-        hipLaunchKernelGGL(k_bsr_numeric<4>, grid, block, 0, st, nb, lo, woff, rt, tb, tA, tB,
-                           gofs, ctb, ccnt, ccols, ctiles, nwork, remap);
-        break;
-    case 16:
-        hipLaunchKernelGGL(k_bsr_numeric<16>, grid, block, 0, st, nb, lo, woff, rt, tb, tA, tB,
-                           gofs, ctb, ccnt, ccols, ctiles, nwork, remap);
-        break;
-    default:
-        hipLaunchKernelGGL(k_bsr_numeric<8>, grid, block, 0, st, nb, lo, woff, rt, tb, tA, tB,
-                           gofs, ctb, ccnt, ccols, ctiles, nwork, remap);
-    }
+                       ctiles);
     return hipGetLastError();
 }
 

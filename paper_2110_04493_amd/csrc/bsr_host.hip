@@ -88,8 +88,6 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
     CHK(ensure(P, P.c_woff, sizeof(int64_t) * (nb + 1)));
     CHK(ensure(P, P.c_cnt, sizeof(int64_t) * (nb + 1)));
     CHK(ensure(P, P.c_tb, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.g_cnt, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.g_ofs, sizeof(int64_t) * (nb + 1)));
     const int32_t *lo = (const int32_t *)ts.lo.p;
     const int64_t *woff = (const int64_t *)ts.woff.p, *tb = (const int64_t *)ts.tb.p;
     const uint2 *rt = (const uint2 *)ts.rt.p;
@@ -99,20 +97,12 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p, nullptr, nullptr,
                         nullptr, st));
     CHK(scan(P, (const int64_t *)P.c_cnt.p, (int64_t *)P.c_tb.p, nb));
-    const bool panels = P.bsr_panels;
-    if (!panels) {
-        HIPCHK(bsr_groups((const int64_t *)P.c_cnt.p, nb, (int64_t *)P.g_cnt.p, st));
-        CHK(scan(P, (const int64_t *)P.g_cnt.p, (int64_t *)P.g_ofs.p, nb));
-    }
     HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.c_tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
-    HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.g_ofs.p + nb, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hl + 2, (int64_t *)P.c_woff.p + nb, sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
     CHK(sync(P));
     const int64_t ctiles = hl[0], cwords = hl[2];
-    int64_t nwork = hl[1];
     CHK(ensure(P, P.c_cols, sizeof(int32_t) * (ctiles + 1)));
     CHK(ensure(P, P.c_tiles, sizeof(double) * 256 * (size_t)(ctiles + 1)));
     CHK(ensure(P, P.c_rt, sizeof(uint2) * (cwords + 1)));
@@ -120,7 +110,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
                         (const int64_t *)P.c_tb.p, (int32_t *)P.c_cols.p, (uint2 *)P.c_rt.p,
                         st));
-    if (panels) {
+    {
         // panels of four block rows and their shared column groups
         const int64_t np = (nb + 3) / 4;
         CHK(ensure(P, P.p_lo, sizeof(int32_t) * (np + 1)));
@@ -148,23 +138,16 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
         // launched on a bound of the work-item count (a panel's union holds
         // at most the sum of its rows' tiles); the kernel reads the exact
         // count, p_gofs[np], and surplus workgroups return at once
-        nwork = ctiles / 4 + np + 1;
     }
+    const int64_t nwork = ctiles / 4 + (nb + 3) / 4 + 1;
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
-    if (panels)
-        HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
-                                 (const double *)ts.tA.p,
-                                 (const double *)ts.tB.p, (const int64_t *)P.p_gofs.p,
-                                 (const int64_t *)P.p_gofs.p + (nb + 3) / 4,
-                                 (const int64_t *)P.p_ofs.p, (const int32_t *)P.p_cols.p,
-                                 (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
-                                 (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
-                                 (double *)P.c_tiles.p, nwork, st));
-    else
-        HIPCHK(bsr_numeric(nb, lo, woff, rt, tb, (const double *)ts.tA.p,
-                           (const double *)ts.tB.p, (const int64_t *)P.g_ofs.p,
-                           (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
-                           (const int32_t *)P.c_cols.p, (double *)P.c_tiles.p, nwork, st));
+    HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
+                             (const double *)ts.tA.p, (const double *)ts.tB.p,
+                             (const int64_t *)P.p_gofs.p, (const int64_t *)P.p_gofs.p + (nb + 3) / 4,
+                             (const int64_t *)P.p_ofs.p, (const int32_t *)P.p_cols.p,
+                             (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
+                             (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
+                             (double *)P.c_tiles.p, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     *ctiles_out = ctiles;
     return EXPM_OK;

@@ -965,7 +965,6 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     P->opts = o;
     P->st = (hipStream_t)o.stream;
     if (o.tile_min_fill >= 0.0) P->bsr_min_fill = o.tile_min_fill;
-    if (const char *f = getenv("EXPM_BSR_PANEL")) P->bsr_panels = f[0] != '0';
     if (hipHostMalloc((void **)&P->host, 4096, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete P;

@@ -124,11 +124,6 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st);
-hipError_t bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, hipStream_t st);
-hipError_t bsr_numeric(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
-                       const int64_t *tb, const double *tA, const double *tB, const int64_t *gofs,
-                       const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                       double *ctiles, int64_t nwork, hipStream_t st);
 hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                     const int32_t *ccols, const double *ctiles, double *bsq, int64_t *bnz,
                     hipStream_t st);

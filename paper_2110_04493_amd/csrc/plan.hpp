@@ -78,10 +78,8 @@ struct expm_plan_s {
     xpm::host::Buf c_lo, c_words, c_woff, c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz,
         b_total, c_rt;
     // panels of four block rows for the product (p_*: origin, words, column
-    // counts and lists, work groups); EXPM_BSR_PANEL=0 uses one block row per
-    // work item instead
+    // counts and lists, work groups)
     xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
-    bool bsr_panels = true;
     // block-column lists of T (the block rows of T^T) for the adjoint
     xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles;
     std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows

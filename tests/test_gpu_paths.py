@@ -80,20 +80,3 @@ def test_reorder_matches_natural_order():
     print(f"[reorder vs natural] relF={rel:.2e} only={og},{oo}", flush=True)
     assert rel <= 1e-13 and ok
     assert (sa["M"], sa["N"]) == (sb["M"], sb["N"])
-
-
-@pytest.mark.parametrize("name,H,eps", list(cases())[:2], ids=[c[0] for c in cases()][:2])
-def test_row_work_items(monkeypatch, name, H, eps):
-    """The tile product with one block row per work item (instead of panels
-    of four) gives the same parity, forward and adjoint."""
-    monkeypatch.setenv("EXPM_BSR_PANEL", "0")
-    Eg, _ = run_gpu(H, eps, reorder=1, tile_min_fill=0.0)
-    Eo, so = run_oracle(H, eps)
-    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
-    print(f"[{name} row work items] relF={rel:.2e} only={og},{oo}", flush=True)
-    assert rel <= TOL and ok
-    dg, _ = gpu_grad(H, eps, density=0.2, checkpoint_interval=2, reorder=1, tile_min_fill=0.0)
-    do, _ = oracle_grad(H, eps, density=0.2)
-    rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
-    print(f"[{name} row work items] adjoint rel={rel:.2e}", flush=True)
-    assert rel <= TOL
