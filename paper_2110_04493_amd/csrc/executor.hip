@@ -468,6 +468,7 @@ void free_adjoint_state(expm_plan_s &P) {
     for (auto &A : P.ckpt) release(P, A);
     P.taylor.clear();
     P.ckpt.clear();
+    P.ckpt_at.clear();
     P.sq_path.clear();
     release(P, P.TN);
     release(P, P.Epat);
@@ -702,8 +703,13 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     memcpy(&P.T.nnz, P.host, sizeof(int64_t));
     if (keep) {
         P.ckpt.emplace_back();
+        P.ckpt_at.push_back(0);
         CHK(copy_csr(P, P.ckpt.back(), P.T));
     }
+    // Checkpoints every ck squarings, counted back from T_{N-1}: the
+    // iterates recomputed by the adjoint are then the cheaper early ones of
+    // each segment (the iterates grow with every squaring).
+    const int ck_off = N >= 1 ? (N - 1) % ck : 0;
     // Step 4: squarings.  Step 5 (E = I + T_N) is fused into the last one.
     DCsr Eout;
     for (int i = 1; i <= N; ++i) {
@@ -713,8 +719,9 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.theta.push_back(S.sq_theta[i]);
         std::swap(P.T, P.Tnew);
         P.T.nnz = S.sq_kept[i];
-        if (keep && !last && i % ck == 0) {
+        if (keep && !last && i >= ck_off && (i - ck_off) % ck == 0) {
             P.ckpt.emplace_back();
+            P.ckpt_at.push_back(i);
             CHK(copy_csr(P, P.ckpt.back(), P.T));
         }
     }
@@ -818,18 +825,23 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     for (int k = N; k >= 1; --k) {
         const int km1 = k - 1;
-        const int base = (km1 / ck) * ck;
+        // the segment holding T_{k-1}: from the last checkpoint at or below
+        // it up to the next checkpoint (or T_N)
+        int ci = 0;
+        while (ci + 1 < (int)P.ckpt_at.size() && P.ckpt_at[ci + 1] <= km1) ++ci;
+        const int base = P.ckpt_at[ci];
+        const int next = ci + 1 < (int)P.ckpt_at.size() ? P.ckpt_at[ci + 1] : N;
         const DCsr *Tp;
-        if (km1 % ck == 0) {
-            Tp = &P.ckpt[km1 / ck];
+        if (km1 == base) {
+            Tp = &P.ckpt[ci];
         } else {
             if (seg_base != base) {
                 for (auto &A : seg) release(P, A);
                 seg.clear();
-                seg.resize(ck);
+                seg.resize(next - base);
                 seg_base = base;
-                const DCsr *prev = &P.ckpt[base / ck];
-                for (int j = base + 1; j <= std::min(base + ck - 1, N - 1); ++j) {
+                const DCsr *prev = &P.ckpt[ci];
+                for (int j = base + 1; j <= std::min(next - 1, N - 1); ++j) {
                     CHK(square_step(P, *prev, seg[j - base], 0.0, true, P.theta[j - 1], false,
                                     true, 0, j));
                     prev = &seg[j - base];

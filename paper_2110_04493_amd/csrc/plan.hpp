@@ -58,7 +58,8 @@ struct expm_plan_s {
     int M = 0, N = 0, Mp = 0, ck = 1;
     double a = 0;
     std::vector<xpm::host::DCsr> taylor;        // S^_1 .. S^_M'
-    std::vector<xpm::host::DCsr> ckpt;          // T^_k for k = 0, ck, 2ck, ... (index k / ck)
+    std::vector<xpm::host::DCsr> ckpt;          // kept iterates T^_k, k = ckpt_at[j]
+    std::vector<int> ckpt_at;                   // 0, then every ck back from N - 1
     xpm::host::DCsr TN;                         // T^_N
     xpm::host::DCsr Epat;                       // pattern of the returned E
     std::vector<double> theta;       // squaring thresholds, 1..N
