@@ -194,8 +194,16 @@ __global__ __launch_bounds__(kRedBlock) void k_sum_parts(const double *part, int
     if (threadIdx.x == 0) *out = s;
 }
 
+// Partial-sum blocks for m values: about 16 values per thread, at most
+// nparts; a function of the size alone, so sums are reproducible.
+static int parts_for(int64_t m, int nparts) {
+    const int64_t want = (m + (int64_t)kRedBlock * 16 - 1) / ((int64_t)kRedBlock * 16);
+    return (int)(want < 1 ? 1 : want < nparts ? want : nparts);
+}
+
 hipError_t sumsq(const double *v, const int64_t *count, int64_t maxcount, double *part, int nparts,
                  double *out, hipStream_t st) {
+    nparts = parts_for(maxcount, nparts);
     hipLaunchKernelGGL(k_sumsq_part, dim3(nparts), dim3(kRedBlock), 0, st, v, count, maxcount,
                        part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kRedBlock), 0, st, part, nparts, out);
@@ -235,6 +243,7 @@ __global__ __launch_bounds__(kRedBlock) void k_sum_part(const double *v, int64_t
 
 hipError_t sum_values(const double *v, int64_t m, double *part, int nparts, double *out,
                       hipStream_t st) {
+    nparts = parts_for(m, nparts);
     hipLaunchKernelGGL(k_sum_part, dim3(nparts), dim3(kRedBlock), 0, st, v, m, part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kRedBlock), 0, st, part, nparts, out);
     return hipGetLastError();
@@ -378,6 +387,7 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass(const double *__restr
 
 hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
                        double *part, int nparts, hipStream_t st) {
+    nparts = parts_for(maxcount, nparts);
     hipLaunchKernelGGL(k_filter_pass, dim3(nparts), dim3(kRedBlock), 0, st, v, count, maxcount, c,
                        part);
     return hipGetLastError();

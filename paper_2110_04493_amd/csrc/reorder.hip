@@ -111,6 +111,93 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *s
     }
 }
 
+// The same breadth-first search with the visited set as a bit map in LDS
+// (an LDS atomicOr marks a node instead of a compare-and-swap in memory) and
+// the frontier queues in LDS; a frontier beyond kQCap nodes continues in
+// the global queues at the same positions.  For n <= kBfsLdsNodes.
+constexpr int kQCap = 4096;
+constexpr int64_t kBfsLdsNodes = 200000;   // bit map + queues stay under 64 KB
+
+__global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_t *srcp,
+                                                         int32_t *dist, int32_t *gq0,
+                                                         int32_t *gq1, const int32_t *other,
+                                                         int32_t *res) {
+    extern __shared__ uint32_t sm[];
+    __shared__ int s_next, s_size, s_unreached;
+    __shared__ long long s_best[kBfsThreads / kWave];
+    const int tid = threadIdx.x;
+    const int64_t n = G.n;
+    const int VW = (int)((n + 31) / 32);
+    uint32_t *vis = sm;
+    int32_t *lq0 = (int32_t *)(sm + VW), *lq1 = lq0 + kQCap;
+    for (int i = tid; i < VW; i += kBfsThreads) vis[i] = 0u;
+    __syncthreads();
+    if (tid == 0) {
+        const int src = *srcp;
+        vis[src >> 5] |= 1u << (src & 31);
+        dist[src] = 0;
+        lq0[0] = src;
+        s_size = 1;
+        s_next = 0;
+        s_unreached = 0;
+    }
+    __syncthreads();
+    int level = 0;
+    int32_t *lcur = lq0, *lnxt = lq1, *gcur = gq0, *gnxt = gq1;
+    for (;;) {
+        const int size = s_size;
+        if (size == 0) break;
+        for (int i = tid; i < size; i += kBfsThreads) {
+            const int v = i < kQCap ? lcur[i] : gcur[i];
+            for (int64_t p = G.rp[v]; p < G.rp[v + 1]; ++p) {
+                const int u = G.ci[p];
+                const uint32_t bit = 1u << (u & 31);
+                if (vis[u >> 5] & bit) continue;
+                if (atomicOr(&vis[u >> 5], bit) & bit) continue;
+                dist[u] = level + 1;
+                const int pos = atomicAdd(&s_next, 1);
+                if (pos < kQCap) lnxt[pos] = u; else gnxt[pos] = u;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_size = s_next;
+            s_next = 0;
+        }
+        __syncthreads();
+        int32_t *t = lcur;
+        lcur = lnxt;
+        lnxt = t;
+        t = gcur;
+        gcur = gnxt;
+        gnxt = t;
+        ++level;
+    }
+    long long best = -1;
+    for (int64_t v = tid; v < n; v += kBfsThreads) {
+        int d;
+        if (vis[v >> 5] & (1u << (v & 31))) {
+            d = __hip_atomic_load(&dist[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            d = level;
+            dist[v] = d;
+            s_unreached = 1;
+        }
+        const int key = other ? min(d, other[v]) : d;
+        const long long pk = ((long long)key << 32) | (long long)(0x7fffffff - (int)v);
+        best = pk > best ? pk : best;
+    }
+    best = wave_max_ll(best);
+    if (lane_id() == 0) s_best[tid / kWave] = best;
+    __syncthreads();
+    if (tid == 0) {
+        long long b = s_best[0];
+        for (int w = 1; w < kBfsThreads / kWave; ++w) b = s_best[w] > b ? s_best[w] : b;
+        res[0] = 0x7fffffff - (int)(b & 0xffffffffll);
+        res[1] = s_unreached ? level : level - 1;
+    }
+}
+
 // Cell of every node and the cell populations.
 __global__ void k_cell_count(int64_t n, const int32_t *d1, const int32_t *d3, int64_t kb,
                              int64_t *cell, int64_t *cnt) {
@@ -279,6 +366,12 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
             *d3 = (int32_t *)P.ro_d3.p, *q0 = (int32_t *)P.ro_q0.p, *q1 = (int32_t *)P.ro_q1.p;
     HIPCHK(hipMemsetAsync(rb, 0, sizeof(int32_t) * 16, st));
     auto bfs = [&](const int32_t *srcp, int32_t *dist, const int32_t *other, int32_t *res) {
+        if (n <= kBfsLdsNodes) {
+            const size_t lds = sizeof(uint32_t) * ((n + 31) / 32) + sizeof(int32_t) * 2 * kQCap;
+            hipLaunchKernelGGL(k_bfs_lds, dim3(1), dim3(kBfsThreads), lds, st, G, srcp, dist, q0,
+                               q1, other, res);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, dist, n, -1);
         hipLaunchKernelGGL(k_bfs, dim3(1), dim3(kBfsThreads), 0, st, G, srcp, dist, q0, q1, other,
                            res);
