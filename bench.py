@@ -125,6 +125,7 @@ def numeric_roofline(stats: dict, n: int):
         per.append({"step": i + 1, "ms": round(ms, 4), "gbps": round(b / (ms * 1e6), 1),
                     "tflops": round(f / (ms * 1e9), 3), "cand": cand,
                     "path": "tiles" if stats["sq_tiles"][i] else "rows",
+                    "tile_slots": 256 * stats["sq_tiles"][i],
                     "kept": stats["sq_kept"][i]})
     return fl, by, t, per
 

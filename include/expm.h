@@ -142,7 +142,8 @@ typedef struct {
     double tile_ms, tile_flops;
     int64_t adj_tile_launches;
     double adj_tile_ms;
-    /* per squaring step: 1 if its product ran on 16x16 tiles, 0 on rows */
+    /* per squaring step: the number of 16x16 candidate tiles its product
+       filled (capped at INT32_MAX), or 0 when it ran on scalar rows */
     int sq_tiles[EXPM_MAXSTEP];
 } expm_stats;
 

@@ -385,8 +385,11 @@ __global__ __launch_bounds__(64) void k_panel_cols(int64_t nb, const int32_t *cl
 // lookups in flight together); the product loop then walks the K that have
 // at least one, reading their indices with readlane, and loads the operands
 // of the next K before issuing the matrix instructions of the current one.
+// The kernel waits on memory far more than on the matrix cores, so it is
+// held to 128 registers: four waves per SIMD instead of two or three.
 template <int kGroup>
-__global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
+__global__ __launch_bounds__(kWave * kPanel)
+__attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
     const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
     const int32_t *__restrict__ tcols, const double *__restrict__ tA,
@@ -394,7 +397,8 @@ __global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
     const int64_t *__restrict__ nwork_dev, int64_t np,
     const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
-    const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles) {
+    const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
+    int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz) {
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
@@ -445,42 +449,58 @@ __global__ __launch_bounds__(kWave * kPanel) void k_bsr_numeric_panel(
     for (int t = 0; t < kGroup; ++t) {
         if (t >= ng) break;
         const int64_t ct = tile_of(clo, cwoff, crt, ctb, I, J[t]);
-        if (ct >= 0) *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
+        if (ct < 0) continue;
+        *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
+        if (!tsq) continue;
+        // the tile's share of ||I + C||_F^2 over the rows below n, and its
+        // nonzero slots; lane holds (i, j) = (4 r + lane / 16, lane % 16)
+        const int rows = (int)min<int64_t>(kTile, n - I * kTile);
+        const bool dtile = J[t] == (int)I;
+        double s = 0.0;
+        long long nz = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * r + (lane >> 4);
+            if (i >= rows) continue;
+            const double f = dtile && i == (lane & 15) ? acc[t][r] + 1.0 : acc[t][r];
+            s = fma(f, f, s);
+            nz += acc[t][r] != 0.0;
+        }
+        s = wave_sum(s);
+        nz = wave_sum_ll(nz);
+        if (lane == 0) {
+            tsq[ct] = s;
+            tnz[ct] = (int32_t)nz;
+        }
     }
 }
 
 // ----------------------------------------------------------------- norm, compaction
 
-// Per block row: sum over its candidate slots of (c_ij + delta_ij)^2 for the
-// rows below n, plus 1 for each such row whose diagonal slot is absent; and
-// the count of nonzero slots.
-__global__ void k_bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
-                           const int32_t *ccols, const double *ctiles, double *bsq,
-                           int64_t *bnz) {
+// Per block row, from the per-tile partials the product wrote: the sum over
+// its candidate slots of (c_ij + delta_ij)^2 for the rows below n, plus 1 for
+// each such row whose diagonal tile is absent; and the count of nonzero
+// slots.  Tiles are taken lane-strided in index order, then a fixed
+// butterfly, so the result is reproducible.
+__global__ void k_bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
+                                 const int32_t *ccols, const double *tsq, const int32_t *tnz,
+                                 double *bsq, int64_t *bnz) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= nb) return;
     const int lane = lane_id();
     const int rows = (int)min<int64_t>(kTile, n - I * kTile);
+    const int64_t b = ctb[I], e = b + ccnt[I];
     double s = 0.0;
     long long nz = 0;
     bool diag = false;
-    for (int64_t t = 0; t < ccnt[I]; ++t) {
-        const int64_t tt = ctb[I] + t;
-        const bool dtile = ccols[tt] == (int)I;
-        diag |= dtile;
-        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
-        // lane holds (i, j) = (4 r + lane / 16, lane % 16), r = 0..3
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = 4 * r + (lane >> 4), j = lane & 15;
-            if (i >= rows) continue;
-            const double f = dtile && i == j ? v[r] + 1.0 : v[r];
-            s = fma(f, f, s);
-            nz += v[r] != 0.0;
-        }
+    for (int64_t t = b + lane; t < e; t += kWave) {
+        s += tsq[t];
+        nz += tnz[t];
+        diag |= ccols[t] == (int)I;
     }
     s = wave_sum(s);
     nz = wave_sum_ll(nz);
+    diag = __ballot(diag) != 0ull;
     if (lane == 0) {
         bsq[I] = diag ? s : s + rows;
         bnz[I] = nz;
@@ -688,21 +708,22 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
-                             const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st) {
+                             const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
+                             int32_t *tnz, int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles);
+                       ctiles, n, tsq, tnz);
     return hipGetLastError();
 }
 
-hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
-                    const int32_t *ccols, const double *ctiles, double *bsq, int64_t *bnz,
-                    hipStream_t st) {
+hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
+                          const int32_t *ccols, const double *tsq, const int32_t *tnz,
+                          double *bsq, int64_t *bnz, hipStream_t st) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_norm, dim3((nb + 3) / 4), dim3(256), 0, st, n, nb, ctb, ccnt, ccols,
-                       ctiles, bsq, bnz);
+    hipLaunchKernelGGL(k_bsr_norm_tiles, dim3((nb + 3) / 4), dim3(256), 0, st, n, nb, ctb, ccnt,
+                       ccols, tsq, tnz, bsq, bnz);
     return hipGetLastError();
 }
 

@@ -74,9 +74,11 @@ int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts) {
 
 // C = 2T + T*T on tiles (T's pattern already in P.tsT): T's tiles, C's tile
 // pattern (rank table, panels) and the candidate tiles in P.c_tiles; the
-// product kernel is bracketed by events ev[1], ev[2] when prof.  *ctiles_out
-// receives the number of candidate tiles.
-int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
+// product kernel is bracketed by events ev[1], ev[2] when prof.  With
+// tile_norms the product also leaves each tile's share of ||I + T~||_F^2 and
+// its nonzero count in P.c_sq / P.c_nz.  *ctiles_out receives the number of
+// candidate tiles.
+int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out) {
     hipStream_t st = P.st;
     TileSet &ts = P.tsT;
     const int64_t n = T.n, nb = ts.nb;
@@ -106,6 +108,10 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
     CHK(ensure(P, P.c_cols, sizeof(int32_t) * (ctiles + 1)));
     CHK(ensure(P, P.c_tiles, sizeof(double) * 256 * (size_t)(ctiles + 1)));
     CHK(ensure(P, P.c_rt, sizeof(uint2) * (cwords + 1)));
+    if (tile_norms) {
+        CHK(ensure(P, P.c_sq, sizeof(double) * (ctiles + 1)));
+        CHK(ensure(P, P.c_nz, sizeof(int32_t) * (ctiles + 1)));
+    }
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
                         (const int64_t *)P.c_tb.p, (int32_t *)P.c_cols.p, (uint2 *)P.c_rt.p,
@@ -147,7 +153,9 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out) {
                              (const int64_t *)P.p_ofs.p, (const int32_t *)P.p_cols.p,
                              (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
                              (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
-                             (double *)P.c_tiles.p, nwork, st));
+                             (double *)P.c_tiles.p, n,
+                             tile_norms ? (double *)P.c_sq.p : nullptr,
+                             tile_norms ? (int32_t *)P.c_nz.p : nullptr, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     *ctiles_out = ctiles;
     return EXPM_OK;
@@ -162,7 +170,7 @@ int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand) {
     hipStream_t st = P.st;
     const int64_t n = T.n;
     int64_t ctiles = 0;
-    CHK(tile_product(P, T, false, &ctiles));
+    CHK(tile_product(P, T, false, false, &ctiles));
     const int64_t *ctb = (const int64_t *)P.c_tb.p, *ccnt = (const int64_t *)P.c_cnt.p;
     const int32_t *ccols = (const int32_t *)P.c_cols.p;
     const double *ctl_tiles = (const double *)P.c_tiles.p;
@@ -213,7 +221,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         HIPCHK(hipEventRecord(P.ev[0], st));
     }
     int64_t ctiles = 0;
-    CHK(tile_product(P, T.view(), prof, &ctiles));
+    CHK(tile_product(P, T.view(), prof, true, &ctiles));
     // ||I + T~||_F and the nonzero candidate count
     CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));
     CHK(ensure(P, P.b_nz, sizeof(int64_t) * (nb + 1)));
@@ -221,9 +229,10 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     CHK(ensure(P, P.norm2, sizeof(double) * 2));
     CHK(ensure(P, P.part, sizeof(double) * kParts));
     CHK(ensure(P, P.tmp2, sizeof(int64_t) * (nb + 1)));
-    HIPCHK(bsr_norm(n, nb, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
-                    (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, (double *)P.b_sq.p,
-                    (int64_t *)P.b_nz.p, st));
+    HIPCHK(bsr_norm_tiles(n, nb, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
+                          (const int32_t *)P.c_cols.p, (const double *)P.c_sq.p,
+                          (const int32_t *)P.c_nz.p, (double *)P.b_sq.p, (int64_t *)P.b_nz.p,
+                          st));
     if (!use_fixed)
         HIPCHK(sum_values((const double *)P.b_sq.p, nb, (double *)P.part.p, kParts,
                           (double *)P.norm2.p, st));
@@ -296,6 +305,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         }
     }
     if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
+        S.sq_tiles[stat_i] = (int)std::min<int64_t>(ctiles, INT32_MAX);
         S.sq_theta[stat_i] = h.theta;
         S.sq_iters[stat_i] = h.iter;
         S.sq_cand[stat_i] = cand_nz;

@@ -504,7 +504,7 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
         }
         if (step >= 1) P.sq_path.push_back(tiles ? 1 : 0);
     }
-    if (stat_i > 0 && stat_i < EXPM_MAXSTEP) P.stats.sq_tiles[stat_i] = tiles ? 1 : 0;
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP && !tiles) P.stats.sq_tiles[stat_i] = 0;
     if (tiles) {
         if (!have_pattern) {
             double fill;
@@ -1068,11 +1068,17 @@ void expm_free(expm_plan_t p) {
     for (Buf *b : bufs) release(P, *b);
     Buf *tbufs[] = {&P.c_lo, &P.c_words, &P.c_woff, &P.c_cnt, &P.c_tb, &P.c_cols, &P.c_tiles,
                     &P.g_cnt, &P.g_ofs, &P.b_sq, &P.b_nz, &P.b_total, &P.tc_cnt, &P.tc_ptr,
-                    &P.tc_fill, &P.tc_k, &P.tc_t, &P.adj_tiles};
+                    &P.tc_fill, &P.tc_k, &P.tc_t, &P.adj_tiles, &P.c_rt, &P.p_lo,
+                    &P.p_words, &P.p_woff, &P.p_cnt, &P.p_ofs, &P.p_gcnt, &P.p_gofs,
+                    &P.p_cols, &P.c_sq, &P.c_nz};
     for (Buf *b : tbufs) release(P, *b);
+    Buf *rbufs[] = {&P.order, &P.newidx, &P.hmap, &P.emap, &P.ro_rb, &P.ro_d0, &P.ro_d1,
+                    &P.ro_d3, &P.ro_q0, &P.ro_q1, &P.ro_cell, &P.ro_cnt, &P.ro_off,
+                    &P.ro_pcnt, &P.ro_pw, &P.ro_pofs, &P.ro_gbits};
+    for (Buf *b : rbufs) release(P, *b);
     release(P, P.tsT);
     release(P, P.tsG);
-    DCsr *mats[] = {&P.H0, &P.S, &P.Snew, &P.T, &P.Tnew, &P.Hpat_t};
+    DCsr *mats[] = {&P.H0, &P.S, &P.Snew, &P.T, &P.Tnew, &P.Hpat_t, &P.Hp, &P.Eperm};
     for (DCsr *m : mats) release(P, *m);
     while (!P.outputs.empty()) out_free(P, P.outputs.back());
     (void)hipStreamSynchronize(P.st);

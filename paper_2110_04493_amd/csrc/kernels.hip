@@ -599,64 +599,39 @@ __global__ void k_colfill(CsrView A, int64_t *fillpos, int32_t *tci, double *tv)
     }
 }
 
-constexpr int kSortBlock = 256;
-constexpr int kSortMax = 4096;
+// One wave per row: each entry of the unsorted row (uci, uv) goes to its rank
+// among the row's columns (distinct within a row) in (ci, v).  Keys of rows
+// up to kRankLds entries are staged in LDS; longer rows are ranked from
+// memory.
+constexpr int kRankLds = 1024;
 
-// Sorts each row segment by column: bitonic sort in LDS for rows up to
-// kSortMax entries, rank placement (O(len^2)) beyond.
-__global__ __launch_bounds__(kSortBlock) void k_sort_rows(const int64_t *rp, int64_t n,
-                                                          int32_t *ci, double *v,
-                                                          int32_t *tmp_ci, double *tmp_v) {
-    __shared__ int32_t key[kSortMax];
-    __shared__ double val[kSortMax];
-    int64_t i = blockIdx.x;
+__global__ __launch_bounds__(256) void k_rank_rows(const int64_t *rp, int64_t n,
+                                                   const int32_t *uci, const double *uv,
+                                                   int32_t *ci, double *v) {
+    __shared__ int32_t skey[4][kRankLds];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * 4 + wv;
     if (i >= n) return;
-    int64_t b = rp[i], len = rp[i + 1] - b;
-    if (len <= 1) return;
-    if (len <= kSortMax) {
-        int P = 1;
-        while (P < len) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += kSortBlock) {
-            key[t] = t < len ? ci[b + t] : INT32_MAX;
-            val[t] = t < len ? v[b + t] : 0.0;
-        }
-        __syncthreads();
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = threadIdx.x; t < P; t += kSortBlock) {
-                    int u = t ^ j;
-                    if (u > t) {
-                        bool up = (t & k) == 0;
-                        int32_t kt = key[t], ku = key[u];
-                        if ((kt > ku) == up) {
-                            key[t] = ku;
-                            key[u] = kt;
-                            double vt = val[t];
-                            val[t] = val[u];
-                            val[u] = vt;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (int t = threadIdx.x; t < len; t += kSortBlock) {
-            ci[b + t] = key[t];
-            v[b + t] = val[t];
+    const int64_t b = rp[i], len = rp[i + 1] - b;
+    if (len <= kRankLds) {
+        int32_t *k = skey[wv];
+        for (int64_t t = lane; t < len; t += kWave) k[t] = uci[b + t];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t t = lane; t < len; t += kWave) {
+            const int32_t x = k[t];
+            int64_t r = 0;
+            for (int64_t u = 0; u < len; ++u) r += k[u] < x;
+            ci[b + r] = x;
+            v[b + r] = uv[b + t];
         }
     } else {
-        for (int64_t t = threadIdx.x; t < len; t += kSortBlock) {
-            int32_t k0 = ci[b + t];
+        for (int64_t t = lane; t < len; t += kWave) {
+            const int32_t x = uci[b + t];
             int64_t r = 0;
-            for (int64_t u = 0; u < len; u++) r += ci[b + u] < k0;
-            tmp_ci[b + r] = k0;
-            tmp_v[b + r] = v[b + t];
-        }
-        __syncthreads();
-        __threadfence_block();
-        for (int64_t t = threadIdx.x; t < len; t += kSortBlock) {
-            ci[b + t] = tmp_ci[b + t];
-            v[b + t] = tmp_v[b + t];
+            for (int64_t u = 0; u < len; ++u) r += uci[b + u] < x;
+            ci[b + r] = x;
+            v[b + r] = uv[b + t];
         }
     }
 }
@@ -677,9 +652,10 @@ hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double 
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(fillpos, trp, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colfill, g, b, 0, st, A, fillpos, tci, tv);
-    hipLaunchKernelGGL(k_sort_rows, dim3(n), dim3(kSortBlock), 0, st, trp, n, tci, tv, tmp_ci,
-                       tmp_v);
+    // unsorted rows into the scratch arrays, then each entry to its rank
+    hipLaunchKernelGGL(k_colfill, g, b, 0, st, A, fillpos, tmp_ci, tmp_v);
+    hipLaunchKernelGGL(k_rank_rows, dim3((n + 3) / 4), dim3(256), 0, st, trp, n, tmp_ci, tmp_v,
+                       tci, tv);
     return hipGetLastError();
 }
 

@@ -123,10 +123,11 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
-                             const int64_t *ctb, double *ctiles, int64_t nwork, hipStream_t st);
-hipError_t bsr_norm(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
-                    const int32_t *ccols, const double *ctiles, double *bsq, int64_t *bnz,
-                    hipStream_t st);
+                             const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
+                             int32_t *tnz, int64_t nwork, hipStream_t st);
+hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
+                          const int32_t *ccols, const double *tsq, const int32_t *tnz,
+                          double *bsq, int64_t *bnz, hipStream_t st);
 hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, double *rowsq, hipStream_t st);
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,

@@ -78,6 +78,8 @@ struct expm_plan_s {
     xpm::host::TileSet tsT, tsG;
     xpm::host::Buf c_lo, c_words, c_woff, c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz,
         b_total, c_rt;
+    // per candidate tile: its share of ||I + T~||_F^2 and its nonzero slots
+    xpm::host::Buf c_sq, c_nz;
     // panels of four block rows for the product (p_*: origin, words, column
     // counts and lists, work groups)
     xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
@@ -125,7 +127,7 @@ void free_adjoint_state(expm_plan_s &P);
 int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill);
 int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts);
 bool tiles_allowed(const expm_plan_s &P, int64_t n);
-int tile_product(expm_plan_s &P, CsrView T, bool prof, int64_t *ctiles_out);
+int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out);
 int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand);
 int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
                     double theta_fixed, bool exact_alloc, int stat_i);
