@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
     // T's block columns (T^T's block rows), sorted by K
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ ck,
     const int64_t *__restrict__ ct,
-    const int64_t *__restrict__ gofs, double *__restrict__ out, int64_t nwork) {
+    const int64_t *__restrict__ gofs, double *__restrict__ out, double *__restrict__ outA,
+    int64_t nwork) {
     const int lane = lane_id();
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (w >= nwork) return;
@@ -183,6 +184,12 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
 #pragma unroll
         for (int r = 0; r < 4; ++r) o[r] = m[r] != 0.0 ? acc[t][r] : 0.0;
         *(d4 *)(out + tt * kTileElems + 4 * lane) = o;
+        if (!outA) continue;
+        // the same tile in the A operand layout: o[r] is entry (4 r + lane / 16,
+        // lane % 16)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            outA[tt * kTileElems + offA(4 * r + (lane >> 4), lane & 15)] = o[r];
     }
 }
 
@@ -244,11 +251,12 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
-                       const int64_t *gofs, double *out, int64_t nwork, hipStream_t st) {
+                       const int64_t *gofs, double *out, double *outA, int64_t nwork,
+                       hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_adjoint<4>, dim3((nwork + 3) / 4), dim3(256), 0, st, nb, tlo, twoff,
                        trt, ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
-                       out, nwork);
+                       out, outA, nwork);
     return hipGetLastError();
 }
 

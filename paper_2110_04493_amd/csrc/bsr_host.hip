@@ -320,7 +320,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
 // Adjoint squaring step on tiles.  Tp's pattern must already be in P.tsT
 // (bsr_pattern); G's pattern is that of Tk.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out, bool g_pattern_ready) {
+                     double *out, bool g_pattern_ready, bool g_tiles_ready) {
     hipStream_t st = P.st;
     TileSet &T = P.tsT, &G = P.tsG;
     const int64_t nb = T.nb;
@@ -328,7 +328,7 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     const CsrView Gv{Tk.n, (const int64_t *)Tk.rp.p, (const int32_t *)Tk.ci.p, g};
     double fg;
     if (!g_pattern_ready) CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));
-    CHK(bsr_tiles(P, Gv, G));
+    if (!(g_pattern_ready && g_tiles_ready)) CHK(bsr_tiles(P, Gv, G));
     // T's block columns as sorted lists (T^T's block rows)
     CHK(ensure(P, P.tc_cnt, sizeof(int64_t) * (nb + 1)));
     CHK(ensure(P, P.tc_ptr, sizeof(int64_t) * (nb + 1)));
@@ -358,6 +358,7 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     CHK(sync(P));
     const int64_t nwork = hl[0];
     CHK(ensure(P, P.adj_tiles, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
+    CHK(ensure(P, P.adj_tilesA, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
     const bool prof = P.opts.profile && P.have_events;
     if (prof) HIPCHK(hipEventRecord(P.ev[4], st));
     HIPCHK(bsr_adjoint(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
@@ -366,7 +367,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const int64_t *)G.woff.p, (const uint2 *)G.rt.p,
                        (const int64_t *)G.tb.p, (const int32_t *)G.cols.p, (const double *)G.tA.p,
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
-                       (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p, nwork, st));
+                       (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p,
+                       (double *)P.adj_tilesA.p, nwork, st));
     if (prof) {
         HIPCHK(hipEventRecord(P.ev[5], st));
         HIPCHK(hipEventSynchronize(P.ev[5]));

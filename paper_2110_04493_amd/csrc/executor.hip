@@ -823,6 +823,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     DCsr Tt;
     const DCsr *Tk = &P.TN;   // pattern of g
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
+    bool g_tiles = false;     // ... and g's values as tiles
     for (int k = N; k >= 1; --k) {
         const int km1 = k - 1;
         // the segment holding T_{k-1}: from the last checkpoint at or below
@@ -859,7 +860,8 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
         }
         if (tiles) {
-            CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p, g_ready));
+            CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p, g_ready,
+                                 g_tiles));
         } else {
             CHK(transpose_csr(P, *Tp, Tt));
             CsrView Gk = CsrView{n, (const int64_t *)Tk->rp.p, (const int32_t *)Tk->ci.p,
@@ -873,6 +875,13 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         // keep it in tsG (recomputation below reuses tsT)
         if (have_pattern) std::swap(P.tsT, P.tsG);
         g_ready = have_pattern;
+        // after a tile step the new gradient is already on T_{k-1}'s tiles:
+        // its tile buffers become G's, T_{k-1}'s values go to the spare pair
+        g_tiles = tiles;
+        if (tiles) {
+            std::swap(P.tsG.tB, P.adj_tiles);
+            std::swap(P.tsG.tA, P.adj_tilesA);
+        }
         if (k - 1 == base && seg_base == base) {
             for (auto &A : seg) release(P, A);
             seg.clear();
@@ -1068,7 +1077,7 @@ void expm_free(expm_plan_t p) {
     for (Buf *b : bufs) release(P, *b);
     Buf *tbufs[] = {&P.c_lo, &P.c_words, &P.c_woff, &P.c_cnt, &P.c_tb, &P.c_cols, &P.c_tiles,
                     &P.g_cnt, &P.g_ofs, &P.b_sq, &P.b_nz, &P.b_total, &P.tc_cnt, &P.tc_ptr,
-                    &P.tc_fill, &P.tc_k, &P.tc_t, &P.adj_tiles, &P.c_rt, &P.p_lo,
+                    &P.tc_fill, &P.tc_k, &P.tc_t, &P.adj_tiles, &P.adj_tilesA, &P.c_rt, &P.p_lo,
                     &P.p_words, &P.p_woff, &P.p_cnt, &P.p_ofs, &P.p_gcnt, &P.p_gofs,
                     &P.p_cols, &P.c_sq, &P.c_nz};
     for (Buf *b : tbufs) release(P, *b);

@@ -83,8 +83,9 @@ struct expm_plan_s {
     // panels of four block rows for the product (p_*: origin, words, column
     // counts and lists, work groups)
     xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
-    // block-column lists of T (the block rows of T^T) for the adjoint
-    xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles;
+    // block-column lists of T (the block rows of T^T) for the adjoint; the
+    // adjoint step's output tiles in the B and A operand layouts
+    xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles, adj_tilesA;
     std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows
     // locality reordering: order (new -> old), newidx (old -> new); H' = P H P^T
     // replaces H0 and E = P^T E' P; hmap / emap give, for each entry of H' / of
@@ -133,9 +134,11 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                     double theta_fixed, bool exact_alloc, int stat_i);
 // One adjoint step on tiles: out (aligned with Tp's entries) =
 // P_Tp(2 G + G Tp^T + Tp^T G), with G given on the pattern of Tk.  Tp's tile
-// pattern must be in P.tsT; with g_pattern_ready, P.tsG already holds Tk's.
+// pattern must be in P.tsT; with g_pattern_ready, P.tsG already holds Tk's,
+// and with g_tiles_ready also G's values as tiles.  The output is also left
+// as tiles on Tp's pattern in P.adj_tiles / P.adj_tilesA.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out, bool g_pattern_ready);
+                     double *out, bool g_pattern_ready, bool g_tiles_ready);
 void release(expm_plan_s &P, TileSet &ts);
 int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
