@@ -320,7 +320,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
 // Adjoint squaring step on tiles.  Tp's pattern must already be in P.tsT
 // (bsr_pattern); G's pattern is that of Tk.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out, bool g_pattern_ready, bool g_tiles_ready) {
+                     double *out, bool g_pattern_ready, bool g_tiles_ready, bool want_csr) {
     hipStream_t st = P.st;
     TileSet &T = P.tsT, &G = P.tsG;
     const int64_t nb = T.nb;
@@ -377,9 +377,14 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
         P.stats.adj_tile_launches += 1;
         P.stats.adj_tile_ms += t;
     }
-    HIPCHK(bsr_gather(Tp.view(), (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
-                      (const uint2 *)T.rt.p, (const int64_t *)T.tb.p,
-                      (const double *)P.adj_tiles.p, out, st));
+    if (want_csr) CHK(gather_tiles(P, Tp, T, (const double *)P.adj_tiles.p, out));
+    return EXPM_OK;
+}
+
+int gather_tiles(expm_plan_s &P, const DCsr &A, const TileSet &ts, const double *tiles,
+                 double *out) {
+    HIPCHK(bsr_gather(A.view(), (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
+                      (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, tiles, out, P.st));
     return EXPM_OK;
 }
 

@@ -824,6 +824,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     const DCsr *Tk = &P.TN;   // pattern of g
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     bool g_tiles = false;     // ... and g's values as tiles
+    bool g_stale = false;     // g's values only as tiles (P.tsG), not yet in g
     for (int k = N; k >= 1; --k) {
         const int km1 = k - 1;
         // the segment holding T_{k-1}: from the last checkpoint at or below
@@ -861,8 +862,10 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         }
         if (tiles) {
             CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p, g_ready,
-                                 g_tiles));
+                                 g_tiles, false));
         } else {
+            if (g_stale) CHK(gather_tiles(P, *Tk, P.tsG, (const double *)P.tsG.tB.p,
+                                          (double *)g.p));
             CHK(transpose_csr(P, *Tp, Tt));
             CsrView Gk = CsrView{n, (const int64_t *)Tk->rp.p, (const int32_t *)Tk->ci.p,
                                  (const double *)g.p};
@@ -878,6 +881,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         // after a tile step the new gradient is already on T_{k-1}'s tiles:
         // its tile buffers become G's, T_{k-1}'s values go to the spare pair
         g_tiles = tiles;
+        g_stale = tiles;
         if (tiles) {
             std::swap(P.tsG.tB, P.adj_tiles);
             std::swap(P.tsG.tA, P.adj_tilesA);
@@ -889,6 +893,8 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         }
     }
     for (auto &A : seg) release(P, A);
+    if (g_stale)
+        CHK(gather_tiles(P, *Tk, P.tsG, (const double *)P.tsG.tB.p, (double *)g.p));
     // Taylor seed: g is dL/dT^_0 on supp(T^_0) = P.ckpt[0].
     const int Mp = (int)P.taylor.size();
     CsrView G0 = CsrView{n, (const int64_t *)P.ckpt[0].rp.p, (const int32_t *)P.ckpt[0].ci.p,

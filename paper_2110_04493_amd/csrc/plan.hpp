@@ -135,10 +135,15 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
 // One adjoint step on tiles: out (aligned with Tp's entries) =
 // P_Tp(2 G + G Tp^T + Tp^T G), with G given on the pattern of Tk.  Tp's tile
 // pattern must be in P.tsT; with g_pattern_ready, P.tsG already holds Tk's,
-// and with g_tiles_ready also G's values as tiles.  The output is also left
-// as tiles on Tp's pattern in P.adj_tiles / P.adj_tilesA.
+// and with g_tiles_ready also G's values as tiles.  The output is left as
+// tiles on Tp's pattern in P.adj_tiles / P.adj_tilesA, and written to out
+// only with want_csr.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out, bool g_pattern_ready, bool g_tiles_ready);
+                     double *out, bool g_pattern_ready, bool g_tiles_ready, bool want_csr);
+// Values of A's stored entries (CSR order) from tiles in the B layout on A's
+// tile pattern ts.
+int gather_tiles(expm_plan_s &P, const DCsr &A, const TileSet &ts, const double *tiles,
+                 double *out);
 void release(expm_plan_s &P, TileSet &ts);
 int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,

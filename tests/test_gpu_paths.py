@@ -80,3 +80,25 @@ def test_reorder_matches_natural_order():
     print(f"[reorder vs natural] relF={rel:.2e} only={og},{oo}", flush=True)
     assert rel <= 1e-13 and ok
     assert (sa["M"], sa["N"]) == (sb["M"], sb["N"])
+
+
+@pytest.mark.parametrize("reorder", [0, 1])
+def test_adjoint_mixed_paths(reorder):
+    """Fill thresholds between the two paths: the late squaring steps run on
+    tiles and the early ones on scalar rows, so the adjoint hands its
+    gradient from the tile steps to the row steps."""
+    rng = np.random.default_rng(11)
+    L = W.grid_laplacian(33, 29, rng)
+    H, eps = L.scaled(-30.0 / W.norm1(L)), 1e-12
+    do, _ = oracle_grad(H, eps, density=0.2)
+    mixed = 0
+    for fill in (0.05, 0.1, 0.15, 0.2, 0.3, 0.45):
+        dg, st = gpu_grad(H, eps, density=0.2, checkpoint_interval=3, reorder=reorder,
+                          tile_min_fill=fill)
+        paths = [st["sq_tiles"][i] > 0 for i in range(st["N"])]
+        rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+        print(f"[mixed reorder={reorder} fill={fill}] tiles per step {paths} rel={rel:.2e}",
+              flush=True)
+        assert rel <= TOL
+        mixed += any(paths) and not all(paths)
+    assert mixed > 0
