@@ -93,8 +93,15 @@ typedef struct {
     const expm_allocator *allocator; /* outputs; NULL = library allocation     */
     int profile;             /* 1: time the kernel phases of every squaring
                                 step with HIP events on `stream` and count
-                                the algorithmic work (fields t_* and sq_fma,
-                                sq_in of expm_stats); 0 (default): off        */
+                                the algorithmic work (fields t_*, sq_fma,
+                                sq_in, tile_* and adj_tile_* of expm_stats);
+                                this waits for the device after every step.
+                                2: only an event pair around every launch of
+                                the tile product and the adjoint tile kernel,
+                                read once the call has synchronised (fields
+                                tile_launches, tile_ms, adj_tile_launches,
+                                adj_tile_ms; tile_flops stays 0).
+                                0 (default): off                              */
     int reorder;             /* locality reordering: the rows and columns of H
                                 are permuted symmetrically (2D cells from graph
                                 distances) before the method runs and E is
@@ -123,7 +130,7 @@ typedef struct {
     int64_t sq_cand[EXPM_MAXSTEP], sq_kept[EXPM_MAXSTEP];
     int64_t nnz_e;
     size_t peak_workspace_bytes;
-    /* with opts.profile: per squaring step i, the partial products of
+    /* with opts.profile == 1: per squaring step i, the partial products of
      * T*T (sq_fma), the stored entries of the input iterate (sq_in), and the
      * device time in ms of the symbolic, numeric and filter+compaction
      * phases; t_taylor_ms is the whole Taylor phase, t_backward_ms the last
@@ -131,13 +138,14 @@ typedef struct {
     int64_t sq_fma[EXPM_MAXSTEP], sq_in[EXPM_MAXSTEP];
     double t_sym_ms[EXPM_MAXSTEP], t_num_ms[EXPM_MAXSTEP], t_filter_ms[EXPM_MAXSTEP];
     double t_taylor_ms, t_backward_ms, t_total_ms;
-    /* with opts.profile, summed over every launch of the 16x16 tile squaring
-     * product since the last expm_sparse began (its forward steps, then the
-     * recomputation inside expm_sparse_backward): launches, device time in ms
-     * (events on the plan's stream around each launch), and algorithmic
-     * flops, 2 per partial product of T*T plus 2 per stored entry of T (the
-     * 2T term), zero padding of the tiles not counted.  adj_tile_* covers
-     * the tile kernel of the adjoint step the same way (time only). */
+    /* with opts.profile 1 or 2, summed over every launch of the 16x16 tile
+     * squaring product since the last expm_sparse began (its forward steps,
+     * then the recomputation inside expm_sparse_backward): launches, device
+     * time in ms (events on the plan's stream around each launch), and, with
+     * profile 1 only, algorithmic flops, 2 per partial product of T*T plus 2
+     * per stored entry of T (the 2T term), zero padding of the tiles not
+     * counted.  adj_tile_* covers the tile kernel of the adjoint step the
+     * same way (time only). */
     int64_t tile_launches;
     double tile_ms, tile_flops;
     int64_t adj_tile_launches;

@@ -69,7 +69,7 @@ class Options:
     max_filter_iter: int = 64
     keep_checkpoints: bool = False
     checkpoint_interval: int = 0
-    profile: bool = False
+    profile: int = 0           # 1: phase timers and work counts, 2: tile kernel timers only
     reorder: int = -1
     tile_min_fill: float = -1.0
 

@@ -686,8 +686,14 @@ extern "C" int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cvie
     using namespace xpm::host;
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
     BatchBufs B;
+    p->kt_used = 0;
+    p->kt_kind.clear();
     int s = batched(*p, B, count, H, eps, E);
     free_bufs(*p, B);
+    if (s == EXPM_OK && light_profile(*p)) {
+        (void)hipStreamSynchronize(p->st);
+        ktimer_collect(*p);
+    }
     if (s != EXPM_OK) {
         (void)hipStreamSynchronize(p->st);
         (void)hipGetLastError();

@@ -147,6 +147,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
     }
     const int64_t nwork = ctiles / 4 + (nb + 3) / 4 + 1;
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
+    if (light_profile(P)) CHK(ktimer_mark(P, 0));
     HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
                              (const double *)ts.tA.p, (const double *)ts.tB.p,
                              (const int64_t *)P.p_gofs.p, (const int64_t *)P.p_gofs.p + (nb + 3) / 4,
@@ -157,6 +158,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              tile_norms ? (double *)P.c_sq.p : nullptr,
                              tile_norms ? (int32_t *)P.c_nz.p : nullptr, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
+    if (light_profile(P)) CHK(ktimer_mark(P, 0));
     *ctiles_out = ctiles;
     return EXPM_OK;
 }
@@ -205,7 +207,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     const int64_t n = T.n, nb = ts.nb;
     // profiling covers every launch (recomputation too); the per-step
     // statistics only the forward steps (stat_i > 0)
-    const bool prof = P.opts.profile && P.have_events;
+    const bool prof = P.opts.profile == 1 && P.have_events;
     int64_t *hl = (int64_t *)P.host;
     if (prof) {
         // algorithmic partial products of T*T (for the statistics only)
@@ -359,8 +361,9 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     const int64_t nwork = hl[0];
     CHK(ensure(P, P.adj_tiles, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
     CHK(ensure(P, P.adj_tilesA, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
-    const bool prof = P.opts.profile && P.have_events;
+    const bool prof = P.opts.profile == 1 && P.have_events;
     if (prof) HIPCHK(hipEventRecord(P.ev[4], st));
+    if (light_profile(P)) CHK(ktimer_mark(P, 1));
     HIPCHK(bsr_adjoint(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
                        (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (const double *)T.tA.p,
                        (const double *)T.tB.p, (const int32_t *)G.lo.p,
@@ -369,6 +372,7 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
                        (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p,
                        (double *)P.adj_tilesA.p, nwork, st));
+    if (light_profile(P)) CHK(ktimer_mark(P, 1));
     if (prof) {
         HIPCHK(hipEventRecord(P.ev[5], st));
         HIPCHK(hipEventSynchronize(P.ev[5]));
@@ -379,6 +383,37 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     }
     if (want_csr) CHK(gather_tiles(P, Tp, T, (const double *)P.adj_tiles.p, out));
     return EXPM_OK;
+}
+
+bool light_profile(const expm_plan_s &P) { return P.opts.profile == 2 && P.have_events; }
+
+int ktimer_mark(expm_plan_s &P, int kind) {
+    if (P.kt_used == P.kt_ev.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        P.kt_ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(P.kt_ev[P.kt_used], P.st));
+    if (P.kt_used % 2 == 0) P.kt_kind.push_back((char)kind);
+    ++P.kt_used;
+    return EXPM_OK;
+}
+
+void ktimer_collect(expm_plan_s &P) {
+    for (size_t j = 0; j + 1 < P.kt_used; j += 2) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, P.kt_ev[j], P.kt_ev[j + 1]) != hipSuccess) continue;
+        if (P.kt_kind[j / 2] == 0) {
+            P.stats.tile_launches += 1;
+            P.stats.tile_ms += t;
+        } else {
+            P.stats.adj_tile_launches += 1;
+            P.stats.adj_tile_ms += t;
+        }
+    }
+    (void)hipGetLastError();
+    P.kt_used = 0;
+    P.kt_kind.clear();
 }
 
 int gather_tiles(expm_plan_s &P, const DCsr &A, const TileSet &ts, const double *tiles,

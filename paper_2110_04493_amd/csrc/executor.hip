@@ -216,7 +216,7 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
     CHK(ensure(P, P.lists, sizeof(int32_t) * (size_t)kNumClasses * (n > 0 ? n : 1)));
     CHK(ensure(P, P.counts, sizeof(int) * 16));
     int64_t *words = (int64_t *)P.words.p, *woff = (int64_t *)P.woff.p;
-    const bool prof = P.opts.profile && P.have_events;
+    const bool prof = P.opts.profile == 1 && P.have_events;
     if (prof) HIPCHK(hipEventRecord(P.ev[0], st));
     HIPCHK(row_bounds(A, B, alphaA != 0.0, (int32_t *)P.lo.p, words, (int64_t *)P.ub.p, st));
     CHK(scan(P, words, woff, n));
@@ -525,7 +525,7 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
     CHK(filter_and_count(P, n, cand, a_ri, (const double *)P.norm2.p, use_fixed, theta_fixed,
                          addI, &h, &kept));
     CHK(write_filtered(P, n, dst, kept, addI, exact_alloc));
-    if (stat_i > 0 && stat_i < EXPM_MAXSTEP && P.opts.profile && P.have_events) {
+    if (stat_i > 0 && stat_i < EXPM_MAXSTEP && P.opts.profile == 1 && P.have_events) {
         HIPCHK(hipEventRecord(P.ev[3], P.st));
         HIPCHK(hipEventSynchronize(P.ev[3]));
         float t0, t1, t2;
@@ -984,7 +984,8 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.filter_mode != EXPM_FILTER_PAPER && o.filter_mode != EXPM_FILTER_NONE)
         return fail(EXPM_EINVAL, "unknown filter_mode %d", o.filter_mode);
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
-        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1 ||
+        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1 || o.profile < 0 ||
+        o.profile > 2 ||
         !(o.tile_min_fill == o.tile_min_fill))
         return fail(EXPM_EINVAL, "invalid option value");
     expm_plan_s *P = new (std::nothrow) expm_plan_s();
@@ -1021,10 +1022,13 @@ int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E)
     g_err.clear();
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
     const auto t0 = std::chrono::steady_clock::now();
+    p->kt_used = 0;
+    p->kt_kind.clear();
     int s = forward(*p, H, eps, E);
     if (s == EXPM_OK) {
         (void)hipStreamSynchronize(p->st);
         p->stats.t_total_ms = ms_since(t0);
+        ktimer_collect(*p);
     }
     if (s != EXPM_OK) {
         p->stats.status = s;
@@ -1047,8 +1051,13 @@ int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals) 
     if (p->have_fwd && p->H0.nnz && !dH_vals) return fail(EXPM_EINVAL, "dH is NULL");
     if (p->have_fwd && p->Epat.nnz && !dE_vals) return fail(EXPM_EINVAL, "dE is NULL");
     const auto t0 = std::chrono::steady_clock::now();
+    p->kt_used = 0;
+    p->kt_kind.clear();
     int s = backward(*p, dE_vals, dH_vals);
-    if (s == EXPM_OK) p->stats.t_backward_ms = ms_since(t0);
+    if (s == EXPM_OK) {
+        p->stats.t_backward_ms = ms_since(t0);
+        ktimer_collect(*p);
+    }
     if (s != EXPM_OK) {
         (void)hipStreamSynchronize(p->st);
         (void)hipGetLastError();
@@ -1099,6 +1108,7 @@ void expm_free(expm_plan_t p) {
     (void)hipStreamSynchronize(P.st);
     if (P.have_events)
         for (hipEvent_t &e : P.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t &e : P.kt_ev) (void)hipEventDestroy(e);
     if (P.host) (void)hipHostFree(P.host);
     (void)hipGetLastError();
     delete p;

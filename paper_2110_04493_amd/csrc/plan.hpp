@@ -71,6 +71,11 @@ struct expm_plan_s {
     // profiling: events around the phases of the last sparse product
     hipEvent_t ev[8] = {};
     bool have_events = false;
+    // opts.profile == 2: an event pair around every tile product (kind 0) and
+    // adjoint tile (kind 1) launch, read once the call has synchronised
+    std::vector<hipEvent_t> kt_ev;
+    std::vector<char> kt_kind;
+    size_t kt_used = 0;
     int64_t last_fma = 0;
     // 16 x 16 tile path of the squaring: T's tile pattern (origin, bit-map
     // words, rank tables, tile bases), its tiles in both operand layouts, C's
@@ -145,6 +150,13 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
 int gather_tiles(expm_plan_s &P, const DCsr &A, const TileSet &ts, const double *tiles,
                  double *out);
 void release(expm_plan_s &P, TileSet &ts);
+// Kernel timers (opts.profile == 2): ktimer_mark records the next event of
+// the pool on the plan's stream (call it before and after one launch);
+// ktimer_collect, after the stream has synchronised, adds the measured pairs
+// to the tile statistics and empties the pool.
+bool light_profile(const expm_plan_s &P);
+int ktimer_mark(expm_plan_s &P, int kind);
+void ktimer_collect(expm_plan_s &P);
 int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
                 const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap);

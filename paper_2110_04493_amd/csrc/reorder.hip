@@ -24,7 +24,9 @@ namespace xpm {
 
 constexpr int kBfsThreads = 1024;
 constexpr int kCellMax = 256;      // largest cell the ordering accepts
-constexpr int kPermLdsWords = 4096;
+constexpr int kPermWaves = 4;        // output rows (waves) per workgroup
+constexpr int kPermLdsWords = 1024;  // bit-map words per wave in LDS
+constexpr int kPermCache = 16;       // mapped columns held per lane
 
 __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -273,51 +275,79 @@ __global__ void k_perm_words(CsrView X, const int32_t *src_row, const int32_t *c
     }
 }
 
-// One wave per output row.  The mapped columns are marked in a bit map over
-// the row's window; the rank of a column (prefix count + bits below it) is
-// its position in the sorted output row.  emap (optional) receives, for
-// every output entry, the index of its input entry.
-__global__ __launch_bounds__(64) void k_perm_rows(CsrView X, const int32_t *src_row,
-                                                  const int32_t *colmap, const int64_t *orp,
-                                                  int32_t *oci, double *ov, int64_t *emap,
-                                                  const int64_t *gofs, uint2 *gbits) {
-    __shared__ uint2 lbits[kPermLdsWords];
-    const int64_t r = blockIdx.x;
+// One wave per output row, kPermWaves rows per workgroup.  The mapped
+// columns are marked in a bit map over the row's window; the rank of a
+// column (prefix count + bits below it) is its position in the sorted output
+// row.  Rows of up to kWave * kPermCache entries keep their mapped columns
+// in registers between the passes.  emap (optional) receives, for every
+// output entry, the index of its input entry.
+__global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
+    CsrView X, const int32_t *src_row, const int32_t *colmap, const int64_t *orp, int32_t *oci,
+    double *ov, int64_t *emap, const int64_t *gofs, uint2 *gbits) {
+    __shared__ uint2 lbits[kPermWaves][kPermLdsWords];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    const int64_t r = (int64_t)blockIdx.x * kPermWaves + wv;
     if (r >= X.n) return;
-    const int lane = lane_id();
     const int32_t s = src_row[r];
     const int64_t b = X.rp[s], e = X.rp[s + 1];
     if (e == b) return;
+    const bool cached = e - b <= (int64_t)kWave * kPermCache;
+    int cc[kPermCache];
     int mn = INT32_MAX, mx = -1;
-    for (int64_t p = b + lane; p < e; p += kWave) {
-        const int c = colmap[X.ci[p]];
-        mn = min(mn, c);
-        mx = max(mx, c);
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kPermCache; ++j) {
+            const int64_t p = b + lane + (int64_t)kWave * j;
+            cc[j] = p < e ? colmap[X.ci[p]] : -1;
+            if (cc[j] >= 0) {
+                mn = min(mn, cc[j]);
+                mx = max(mx, cc[j]);
+            }
+        }
+    } else {
+        for (int64_t p = b + lane; p < e; p += kWave) {
+            const int c = colmap[X.ci[p]];
+            mn = min(mn, c);
+            mx = max(mx, c);
+        }
     }
     mn = wave_min(mn);
     mx = wave_max(mx);
     const int lo = mn & ~31;
     const int64_t W = (((int64_t)mx - lo) >> 5) + 1;
-    // The bit map lives in LDS, or for very wide windows in this row's slice
-    // of global scratch; every access goes through device-coherent atomics so
-    // that the global case never reads a stale cache line.
-    uint32_t *bits = W > kPermLdsWords ? (uint32_t *)(gbits + gofs[r]) : (uint32_t *)lbits;
+    // The bit map lives in this wave's slice of LDS, or for very wide windows
+    // in this row's slice of global scratch; every access goes through
+    // device-coherent atomics so that the global case never reads a stale
+    // cache line, and the wave's passes are separated by workgroup-scope
+    // fences (which wait for its own stores).
+    uint32_t *bits = W > kPermLdsWords ? (uint32_t *)(gbits + gofs[r]) : (uint32_t *)lbits[wv];
     auto ld = [](uint32_t *a) {
         return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     auto st = [](uint32_t *a, uint32_t v) {
         __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
+    auto pass_end = []() {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    };
     for (int64_t w = lane; w < W; w += kWave) {
         st(&bits[2 * w], 0u);
         st(&bits[2 * w + 1], 0u);
     }
-    __syncthreads();
-    for (int64_t p = b + lane; p < e; p += kWave) {
-        const int d = colmap[X.ci[p]] - lo;
+    pass_end();
+    auto mark = [&](int c) {
+        const int d = c - lo;
         atomicOr(&bits[2 * (d >> 5)], 1u << (d & 31));
+    };
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kPermCache; ++j)
+            if (cc[j] >= 0) mark(cc[j]);
+    } else {
+        for (int64_t p = b + lane; p < e; p += kWave) mark(colmap[X.ci[p]]);
     }
-    __syncthreads();
+    pass_end();
     unsigned carry = 0;
     for (int64_t w0 = 0; w0 < W; w0 += kWave) {
         const int64_t w = w0 + lane;
@@ -326,16 +356,22 @@ __global__ __launch_bounds__(64) void k_perm_rows(CsrView X, const int32_t *src_
         if (w < W) st(&bits[2 * w + 1], carry + inc - pc);
         carry += __shfl(inc, kWave - 1);
     }
-    __syncthreads();
+    pass_end();
     const int64_t ob = orp[r];
-    for (int64_t p = b + lane; p < e; p += kWave) {
-        const int c = colmap[X.ci[p]];
+    auto place = [&](int c, int64_t p) {
         const int d = c - lo;
         const uint32_t wx = ld(&bits[2 * (d >> 5)]), wy = ld(&bits[2 * (d >> 5) + 1]);
         const int64_t q = ob + wy + __popc(wx & ((1u << (d & 31)) - 1u));
         oci[q] = c;
         ov[q] = X.v[p];
         if (emap) emap[q] = p;
+    };
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kPermCache; ++j)
+            if (cc[j] >= 0) place(cc[j], b + lane + (int64_t)kWave * j);
+    } else {
+        for (int64_t p = b + lane; p < e; p += kWave) place(colmap[X.ci[p]], p);
     }
 }
 
@@ -440,8 +476,9 @@ int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
     const int64_t gw = hl[0];
     CHK(ensure(P, P.ro_gbits, sizeof(uint2) * (gw + 1)));
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_perm_rows, dim3((unsigned)n), dim3(64), 0, st, X, src_row, colmap,
-                           orp, oci, ov, emap, pofs, (uint2 *)P.ro_gbits.p);
+        hipLaunchKernelGGL(k_perm_rows, dim3((unsigned)((n + kPermWaves - 1) / kPermWaves)),
+                           dim3(kWave * kPermWaves), 0, st, X, src_row, colmap, orp, oci, ov,
+                           emap, pofs, (uint2 *)P.ro_gbits.p);
         HIPCHK(hipGetLastError());
     }
     return EXPM_OK;

@@ -60,3 +60,17 @@ def test_choose_mn_rejects_bad_input():
         capi.expm_choose_mn(float("nan"), 1e-12)
     assert e.value.code == capi.EXPM_EINVAL
     assert "norm" in capi.expm_last_error() or capi.expm_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("filter_mode", 7), ("e_r", -0.5),
+                                         ("max_filter_iter", 0), ("normal", 2),
+                                         ("checkpoint_interval", -1), ("reorder", 2),
+                                         ("profile", 3), ("profile", -1),
+                                         ("tile_min_fill", float("nan"))])
+def test_plan_rejects_invalid_options(field, value):
+    """Option validation runs before the plan touches the device."""
+    o = capi.expm_opts_default()
+    setattr(o, field, value)
+    with pytest.raises(capi.ExpmError) as e:
+        capi.expm_plan(o)
+    assert e.value.code == capi.EXPM_EINVAL
