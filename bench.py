@@ -11,10 +11,10 @@ Prints one JSON line.  `value` is the wall time of one step in seconds
 (lower is better).  `roofline` covers the dominant kernel, the tile product
 of the squarings: its launches are timed with HIP events on the library's
 stream inside the timed steps (profile mode 2: event pairs only, read after
-each call), and its algorithmic flops per launch come from one untimed pass
+each call), and its algorithmic flops per launch come from untimed passes
 before them with the full profile (profile mode 1, which counts the partial
 products of every step and waits for the device after each step; the
-per-step table and phase times come from that pass too).  `cpu_baseline`
+per-step table and phase times come from the second of those passes).  `cpu_baseline`
 times the CPU oracle on a bounded sample of the same workload family.
 """
 from __future__ import annotations
