@@ -672,6 +672,12 @@ hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64
     return hipGetLastError();
 }
 
+int64_t bsr_panel_work_bound(int64_t ctiles, int64_t nb) {
+    // a panel's union holds at most the sum of its rows' tiles, and each
+    // panel rounds up once
+    return ctiles / kPanelGroup + (nb + kPanel - 1) / kPanel + 1;
+}
+
 hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipStream_t st) {
     const int64_t np = (nb + kPanel - 1) / kPanel;
     if (np == 0) return hipSuccess;

@@ -145,7 +145,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         // at most the sum of its rows' tiles); the kernel reads the exact
         // count, p_gofs[np], and surplus workgroups return at once
     }
-    const int64_t nwork = ctiles / 4 + (nb + 3) / 4 + 1;
+    const int64_t nwork = bsr_panel_work_bound(ctiles, nb);
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,

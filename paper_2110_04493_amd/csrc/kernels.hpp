@@ -111,6 +111,7 @@ hipError_t bsr_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cwoff
 hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64_t *cwoff,
                           const uint2 *crt, const int32_t *plo, const int64_t *pwoff,
                           int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st);
+int64_t bsr_panel_work_bound(int64_t ctiles, int64_t nb);
 hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipStream_t st);
 hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                      const int64_t *tb, int32_t *tcols, int32_t *trows, hipStream_t st);
