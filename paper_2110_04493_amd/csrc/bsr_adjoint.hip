@@ -16,6 +16,8 @@
 
 namespace xpm {
 
+constexpr int kAdjGroup = 4;   // output tiles per wave (work item)
+
 // ----------------------------------------------------------------- T^T's block rows
 
 __global__ void k_bsr_colcount(int64_t nb, const int32_t *lo, const int64_t *woff,
@@ -210,7 +212,7 @@ __global__ void k_bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, 
 // Work items of four tiles per block row, from the tile bases tb.
 __global__ void k_bsr_groups4(const int64_t *tb, int64_t nb, int64_t *gcnt) {
     const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I < nb) gcnt[I] = (tb[I + 1] - tb[I] + 3) / 4;
+    if (I < nb) gcnt[I] = (tb[I + 1] - tb[I] + kAdjGroup - 1) / kAdjGroup;
 }
 
 // ----------------------------------------------------------------- wrappers
@@ -254,7 +256,7 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int64_t *gofs, double *out, double *outA, int64_t nwork,
                        hipStream_t st) {
     if (nwork == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_adjoint<4>, dim3((nwork + 3) / 4), dim3(256), 0, st, nb, tlo, twoff,
+    hipLaunchKernelGGL(k_bsr_adjoint<kAdjGroup>, dim3((nwork + 3) / 4), dim3(256), 0, st, nb, tlo, twoff,
                        trt, ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
                        out, outA, nwork);
     return hipGetLastError();
