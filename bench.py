@@ -130,7 +130,7 @@ def numeric_roofline(stats: dict, n: int):
                     "tflops": round(f / (ms * 1e9), 3), "cand": cand,
                     "path": "tiles" if stats["sq_tiles"][i] else "rows",
                     "tile_slots": 256 * stats["sq_tiles"][i],
-                    "kept": stats["sq_kept"][i]})
+                    "kept": stats["sq_kept"][i], "filter_iters": stats["sq_iters"][i]})
     return fl, by, t, per
 
 

@@ -398,7 +398,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
-    int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz) {
+    int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn) {
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
@@ -452,11 +452,12 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         if (ct < 0) continue;
         *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
         if (!tsq) continue;
-        // the tile's share of ||I + C||_F^2 over the rows below n, and its
-        // nonzero slots; lane holds (i, j) = (4 r + lane / 16, lane % 16)
+        // the tile's share of ||I + C||_F^2 over the rows below n, its
+        // nonzero slots and their smallest magnitude (slots outside the
+        // matrix hold zeros); lane holds (i, j) = (4 r + lane / 16, lane % 16)
         const int rows = (int)min<int64_t>(kTile, n - I * kTile);
         const bool dtile = J[t] == (int)I;
-        double s = 0.0;
+        double s = 0.0, mn = INFINITY;
         long long nz = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -465,12 +466,15 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
             const double f = dtile && i == (lane & 15) ? acc[t][r] + 1.0 : acc[t][r];
             s = fma(f, f, s);
             nz += acc[t][r] != 0.0;
+            if (acc[t][r] != 0.0) mn = fmin(mn, fabs(acc[t][r]));
         }
         s = wave_sum(s);
         nz = wave_sum_ll(nz);
+        mn = wave_min_f64(mn);
         if (lane == 0) {
             tsq[ct] = s;
             tnz[ct] = (int32_t)nz;
+            tmn[ct] = mn;
         }
     }
 }
@@ -715,12 +719,12 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
-                             int32_t *tnz, int64_t nwork, hipStream_t st) {
+                             int32_t *tnz, double *tmn, int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz);
+                       ctiles, n, tsq, tnz, tmn);
     return hipGetLastError();
 }
 

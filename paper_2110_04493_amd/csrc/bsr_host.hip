@@ -111,6 +111,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
     if (tile_norms) {
         CHK(ensure(P, P.c_sq, sizeof(double) * (ctiles + 1)));
         CHK(ensure(P, P.c_nz, sizeof(int32_t) * (ctiles + 1)));
+        CHK(ensure(P, P.c_mn, sizeof(double) * (ctiles + 1)));
     }
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
@@ -156,7 +157,8 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
                              (double *)P.c_tiles.p, n,
                              tile_norms ? (double *)P.c_sq.p : nullptr,
-                             tile_norms ? (int32_t *)P.c_nz.p : nullptr, nwork, st));
+                             tile_norms ? (int32_t *)P.c_nz.p : nullptr,
+                             tile_norms ? (double *)P.c_mn.p : nullptr, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     *ctiles_out = ctiles;
@@ -227,7 +229,6 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     // ||I + T~||_F and the nonzero candidate count
     CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));
     CHK(ensure(P, P.b_nz, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.b_total, sizeof(int64_t) * 2));
     CHK(ensure(P, P.norm2, sizeof(double) * 2));
     CHK(ensure(P, P.part, sizeof(double) * kParts));
     CHK(ensure(P, P.tmp2, sizeof(int64_t) * (nb + 1)));
@@ -239,9 +240,6 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         HIPCHK(sum_values((const double *)P.b_sq.p, nb, (double *)P.part.p, kParts,
                           (double *)P.norm2.p, st));
     CHK(scan(P, (const int64_t *)P.b_nz.p, (int64_t *)P.tmp2.p, nb));
-    const int64_t slots = ctiles * 256;
-    hl[20] = slots;   // pinned staging; not touched again before the next sync
-    HIPCHK(hipMemcpyAsync(P.b_total.p, hl + 20, sizeof(int64_t), hipMemcpyHostToDevice, st));
     // Algorithm 4.1 on the tile values, then the kept counts per row
     CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
     CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
@@ -257,8 +255,8 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     for (int round = 0;; ++round) {
         if (!use_fixed)
             for (int j = 0; j < 4; ++j)
-                HIPCHK(filter_pass((const double *)P.c_tiles.p, (const int64_t *)P.b_total.p,
-                                   slots, ctl, (double *)P.part.p, kParts, st));
+                HIPCHK(filter_pass_tiles((const double *)P.c_tiles.p, (const double *)P.c_mn.p,
+                                         ctiles, ctl, (double *)P.part.p, kParts, st));
         HIPCHK(bsr_count(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
                          (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, ctl,
                          (int64_t *)P.cnt.p, st));

@@ -336,11 +336,14 @@ hipError_t filter_init_theta(FilterCtl *c, double theta, hipStream_t st) {
     return hipGetLastError();
 }
 
-// One pass: b^2 = sum of v^2 over |v| <= theta (the entries still in the
-// drop vector b_n of Algorithm 4.1, since theta only decreases).  The last
-// block to finish sums the block partials in a fixed order and advances the
+// End of one pass: this block's partial s goes to part[]; the last block to
+// finish sums the block partials in a fixed order and advances the
 // controller: m = b / theta and the next theta = eps_g / m, or stop when
 // b <= eps_g (1 + e_r).
+__device__ void filter_pass_end(double s, double theta, FilterCtl *c, double *part);
+
+// One pass: b^2 = sum of v^2 over |v| <= theta (the entries still in the
+// drop vector b_n of Algorithm 4.1, since theta only decreases).
 __global__ __launch_bounds__(kRedBlock) void k_filter_pass(const double *__restrict__ v,
                                                            const int64_t *count,
                                                            int64_t maxcount, FilterCtl *c,
@@ -354,6 +357,33 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass(const double *__restr
         double x = v[j];
         if (fabs(x) <= theta) s = fma(x, x, s);
     }
+    filter_pass_end(s, theta, c, part);
+}
+
+// The pass over candidate tiles: one wave per tile (grid-stride), each lane
+// 32 contiguous bytes.
+__global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *__restrict__ tiles,
+                                                                 const double *__restrict__ tmin,
+                                                                 int64_t ntiles, FilterCtl *c,
+                                                                 double *part) {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    if (c->done) return;
+    const double theta = c->theta;
+    constexpr int wpb = kRedBlock / kWave;
+    const int lane = lane_id();
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; t < ntiles;
+         t += (int64_t)gridDim.x * wpb) {
+        if (tmin[t] > theta) continue;
+        const v4 x = *(const v4 *)(tiles + t * 256 + 4 * lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (fabs(x[r]) <= theta) s = fma(x[r], x[r], s);
+    }
+    filter_pass_end(s, theta, c, part);
+}
+
+__device__ void filter_pass_end(double s, double theta, FilterCtl *c, double *part) {
     s = block_sum(s);
     __shared__ unsigned ticket;
     if (threadIdx.x == 0) {
@@ -383,6 +413,14 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass(const double *__restr
             c->theta = c->eg / c->m;
         }
     }
+}
+
+hipError_t filter_pass_tiles(const double *tiles, const double *tmin, int64_t ntiles,
+                             FilterCtl *c, double *part, int nparts, hipStream_t st) {
+    nparts = parts_for(ntiles * 16, nparts);
+    hipLaunchKernelGGL(k_filter_pass_tiles, dim3(nparts), dim3(kRedBlock), 0, st, tiles, tmin,
+                       ntiles, c, part);
+    return hipGetLastError();
 }
 
 hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
