@@ -398,7 +398,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
-    int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn) {
+    int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
+    double *__restrict__ tmx, uint4 *__restrict__ trc) {
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
@@ -453,28 +454,40 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
         if (!tsq) continue;
         // the tile's share of ||I + C||_F^2 over the rows below n, its
-        // nonzero slots and their smallest magnitude (slots outside the
-        // matrix hold zeros); lane holds (i, j) = (4 r + lane / 16, lane % 16)
+        // nonzero slots, their smallest and largest magnitudes and the
+        // nonzeros of each of its 16 rows (slots outside the matrix hold
+        // zeros); lane holds (i, j) = (4 r + lane / 16, lane % 16)
         const int rows = (int)min<int64_t>(kTile, n - I * kTile);
         const bool dtile = J[t] == (int)I;
-        double s = 0.0, mn = INFINITY;
+        double s = 0.0, mn = INFINITY, mx = 0.0;
         long long nz = 0;
+        uint32_t rc[4] = {0u, 0u, 0u, 0u};   // byte i % 4 of word i / 4: row i
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 4 * r + (lane >> 4);
-            if (i >= rows) continue;
-            const double f = dtile && i == (lane & 15) ? acc[t][r] + 1.0 : acc[t][r];
-            s = fma(f, f, s);
-            nz += acc[t][r] != 0.0;
-            if (acc[t][r] != 0.0) mn = fmin(mn, fabs(acc[t][r]));
+            const bool in = i < rows;
+            const double v = in ? acc[t][r] : 0.0;
+            const double f = dtile && i == (lane & 15) ? v + 1.0 : v;
+            if (in) s = fma(f, f, s);
+            nz += v != 0.0;
+            if (v != 0.0) mn = fmin(mn, fabs(v));
+            mx = fmax(mx, fabs(v));
+            // rows 4 r .. 4 r + 3 are the four 16-lane groups of register r
+            const unsigned long long m = __ballot(v != 0.0);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                rc[r] |= (uint32_t)__popcll((m >> (16 * g)) & 0xffffull) << (8 * g);
         }
         s = wave_sum(s);
         nz = wave_sum_ll(nz);
         mn = wave_min_f64(mn);
+        mx = wave_max_f64(mx);
         if (lane == 0) {
             tsq[ct] = s;
             tnz[ct] = (int32_t)nz;
             tmn[ct] = mn;
+            tmx[ct] = mx;
+            trc[ct] = make_uint4(rc[0], rc[1], rc[2], rc[3]);
         }
     }
 }
@@ -522,8 +535,13 @@ __device__ __forceinline__ bool bsr_keep(int64_t i, int col, int64_t n, double v
     return i < n && col < n && fabs(v) > theta;
 }
 
+// With the per-tile summaries of the product (tmn, tmx: smallest nonzero and
+// largest magnitude, trc: nonzeros per row), a tile whose slots are all at
+// most theta is skipped, and one whose nonzeros all exceed theta is counted
+// from trc without reading it.
 __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
-                            const int32_t *ccols, const double *ctiles, const FilterCtl *c,
+                            const int32_t *ccols, const double *ctiles, const double *tmn,
+                            const double *tmx, const uint4 *trc, const FilterCtl *c,
                             int64_t *cnt) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= (n + kTile - 1) / kTile) return;
@@ -534,6 +552,18 @@ __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
     const int64_t base = ctb[I], cntI = ccnt[I];
     for (int64_t t = 0; t < cntI; ++t) {
         const int64_t tt = base + t;
+        if (tmx) {
+            if (tmx[tt] <= theta) continue;
+            if (tmn[tt] > theta) {
+                if ((lane & 15) == 0) {
+                    const uint4 q = trc[tt];
+                    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) k4[k] += (int)((w[k] >> (8 * g)) & 0xffu);
+                }
+                continue;
+            }
+        }
         const int col = 16 * ccols[tt] + (lane & 15);
         const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
 #pragma unroll
@@ -553,8 +583,8 @@ __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
 }
 
 __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
-                            const int32_t *ccols, const double *ctiles, const FilterCtl *c,
-                            const int64_t *orp, int32_t *oci, double *ov) {
+                            const int32_t *ccols, const double *ctiles, const double *tmx,
+                            const FilterCtl *c, const int64_t *orp, int32_t *oci, double *ov) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= (n + kTile - 1) / kTile) return;
     const int lane = lane_id();
@@ -570,6 +600,7 @@ __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
     const uint32_t below = (1u << cl) - 1u;
     for (int64_t t = 0; t < cntI; ++t) {
         const int64_t tt = base + t;
+        if (tmx && tmx[tt] <= theta) continue;   // nothing kept
         const int col = 16 * ccols[tt] + cl;
         const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
 #pragma unroll
@@ -719,12 +750,13 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
-                             int32_t *tnz, double *tmn, int64_t nwork, hipStream_t st) {
+                             int32_t *tnz, double *tmn, double *tmx, uint4 *trc,
+                             int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz, tmn);
+                       ctiles, n, tsq, tnz, tmn, tmx, trc);
     return hipGetLastError();
 }
 
@@ -747,21 +779,22 @@ hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
 }
 
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                     const double *ctiles, const FilterCtl *c, int64_t *cnt, hipStream_t st) {
+                     const double *ctiles, const double *tmn, const double *tmx,
+                     const uint4 *trc, const FilterCtl *c, int64_t *cnt, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int64_t nb = (n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_bsr_count, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
-                       ctiles, c, cnt);
+                       ctiles, tmn, tmx, trc, c, cnt);
     return hipGetLastError();
 }
 
 hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                     const double *ctiles, const FilterCtl *c, const int64_t *orp, int32_t *oci,
-                     double *ov, hipStream_t st) {
+                     const double *ctiles, const double *tmx, const FilterCtl *c,
+                     const int64_t *orp, int32_t *oci, double *ov, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int64_t nb = (n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_bsr_write, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
-                       ctiles, c, orp, oci, ov);
+                       ctiles, tmx, c, orp, oci, ov);
     return hipGetLastError();
 }
 

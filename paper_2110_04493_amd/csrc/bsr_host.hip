@@ -112,6 +112,8 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         CHK(ensure(P, P.c_sq, sizeof(double) * (ctiles + 1)));
         CHK(ensure(P, P.c_nz, sizeof(int32_t) * (ctiles + 1)));
         CHK(ensure(P, P.c_mn, sizeof(double) * (ctiles + 1)));
+        CHK(ensure(P, P.c_mx, sizeof(double) * (ctiles + 1)));
+        CHK(ensure(P, P.c_rc, sizeof(uint4) * (ctiles + 1)));
     }
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
@@ -158,7 +160,9 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              (double *)P.c_tiles.p, n,
                              tile_norms ? (double *)P.c_sq.p : nullptr,
                              tile_norms ? (int32_t *)P.c_nz.p : nullptr,
-                             tile_norms ? (double *)P.c_mn.p : nullptr, nwork, st));
+                             tile_norms ? (double *)P.c_mn.p : nullptr,
+                             tile_norms ? (double *)P.c_mx.p : nullptr,
+                             tile_norms ? (uint4 *)P.c_rc.p : nullptr, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     *ctiles_out = ctiles;
@@ -185,7 +189,8 @@ int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand) {
     CHK(ensure(P, P.crp, sizeof(int64_t) * (n + 1)));
     FilterCtl *ctl = (FilterCtl *)P.ctl.p;
     HIPCHK(filter_init_theta(ctl, 0.0, st));   // keep every nonzero slot
-    HIPCHK(bsr_count(n, ctb, ccnt, ccols, ctl_tiles, ctl, (int64_t *)P.cnt.p, st));
+    HIPCHK(bsr_count(n, ctb, ccnt, ccols, ctl_tiles, nullptr, nullptr, nullptr, ctl,
+                     (int64_t *)P.cnt.p, st));
     CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.crp.p, n));
     int64_t *hl = (int64_t *)P.host;
     HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.crp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -194,7 +199,7 @@ int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand) {
     *cand = hl[0];
     CHK(ensure(P, P.cci, sizeof(int32_t) * (*cand + 1)));
     CHK(ensure(P, P.cv, sizeof(double) * (*cand + 1)));
-    HIPCHK(bsr_write(n, ctb, ccnt, ccols, ctl_tiles, ctl, (const int64_t *)P.crp.p,
+    HIPCHK(bsr_write(n, ctb, ccnt, ccols, ctl_tiles, nullptr, ctl, (const int64_t *)P.crp.p,
                      (int32_t *)P.cci.p, (double *)P.cv.p, st));
     return EXPM_OK;
 }
@@ -258,8 +263,9 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                 HIPCHK(filter_pass_tiles((const double *)P.c_tiles.p, (const double *)P.c_mn.p,
                                          ctiles, ctl, (double *)P.part.p, kParts, st));
         HIPCHK(bsr_count(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
-                         (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, ctl,
-                         (int64_t *)P.cnt.p, st));
+                         (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,
+                         (const double *)P.c_mn.p, (const double *)P.c_mx.p,
+                         (const uint4 *)P.c_rc.p, ctl, (int64_t *)P.cnt.p, st));
         CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
         HIPCHK(hipMemcpyAsync(P.host, ctl, sizeof(FilterCtl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hl + 8, (int64_t *)P.krp.p + n, sizeof(int64_t),
@@ -282,8 +288,9 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
                           st));
     HIPCHK(bsr_write(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
-                     (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p, ctl,
-                     (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p, (double *)dst.v.p, st));
+                     (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,
+                     (const double *)P.c_mx.p, ctl, (const int64_t *)dst.rp.p,
+                     (int32_t *)dst.ci.p, (double *)dst.v.p, st));
     expm_stats &S = P.stats;
     if (prof) {
         HIPCHK(hipEventRecord(P.ev[3], st));

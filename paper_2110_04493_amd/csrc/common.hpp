@@ -35,6 +35,12 @@ __device__ __forceinline__ double wave_min_f64(double x) {
     return x;
 }
 
+__device__ __forceinline__ double wave_max_f64(double x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+
 __device__ __forceinline__ long long wave_sum_ll(long long x) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);

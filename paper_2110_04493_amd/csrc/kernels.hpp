@@ -130,17 +130,22 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
-                             int32_t *tnz, double *tmn, int64_t nwork, hipStream_t st);
+                             int32_t *tnz, double *tmn, double *tmx, uint4 *trc,
+                             int64_t nwork, hipStream_t st);
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
                           double *bsq, int64_t *bnz, hipStream_t st);
 hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, double *rowsq, hipStream_t st);
+// Compaction of the candidate tiles (kept: |v| > c->theta) into CSR: kept
+// counts per row, then the entries.  tmn / tmx / trc (may be NULL) are the
+// per-tile summaries the product leaves with its norm partials.
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                     const double *ctiles, const FilterCtl *c, int64_t *cnt, hipStream_t st);
+                     const double *ctiles, const double *tmn, const double *tmx,
+                     const uint4 *trc, const FilterCtl *c, int64_t *cnt, hipStream_t st);
 hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                     const double *ctiles, const FilterCtl *c, const int64_t *orp, int32_t *oci,
-                     double *ov, hipStream_t st);
+                     const double *ctiles, const double *tmx, const FilterCtl *c,
+                     const int64_t *orp, int32_t *oci, double *ov, hipStream_t st);
 
 // adjoint on tiles (bsr_adjoint.hip)
 hipError_t bsr_colcount(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,

@@ -83,9 +83,9 @@ struct expm_plan_s {
     xpm::host::TileSet tsT, tsG;
     xpm::host::Buf c_lo, c_words, c_woff, c_cnt, c_tb, c_cols, c_tiles, g_cnt, g_ofs, b_sq, b_nz,
         c_rt;
-    // per candidate tile: its share of ||I + T~||_F^2, its nonzero slots and
-    // their smallest magnitude
-    xpm::host::Buf c_sq, c_nz, c_mn;
+    // per candidate tile: its share of ||I + T~||_F^2, its nonzero slots,
+    // their smallest and largest magnitudes and the nonzeros of each row
+    xpm::host::Buf c_sq, c_nz, c_mn, c_mx, c_rc;
     // panels of four block rows for the product (p_*: origin, words, column
     // counts and lists, work groups)
     xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
