@@ -327,11 +327,12 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
 // Adjoint squaring step on tiles.  Tp's pattern must already be in P.tsT
 // (bsr_pattern); G's pattern is that of Tk.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out, bool g_pattern_ready, bool g_tiles_ready, bool want_csr) {
+                     double *out, bool g_pattern_ready, bool g_tiles_ready, bool want_csr,
+                     bool t_tiles_ready) {
     hipStream_t st = P.st;
     TileSet &T = P.tsT, &G = P.tsG;
     const int64_t nb = T.nb;
-    CHK(bsr_tiles(P, Tp.view(), T));
+    if (!t_tiles_ready) CHK(bsr_tiles(P, Tp.view(), T));
     const CsrView Gv{Tk.n, (const int64_t *)Tk.rp.p, (const int32_t *)Tk.ci.p, g};
     double fg;
     if (!g_pattern_ready) CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));

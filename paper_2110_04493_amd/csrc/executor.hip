@@ -560,6 +560,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     hipStream_t st = P.st;
     const int64_t n = Hv->n, nnz = Hv->nnz;
     free_adjoint_state(P);
+    P.fwd_ts_ok = false;
     memset(&P.stats, 0, sizeof P.stats);
     P.have_stats = false;
     P.perm_active = false;
@@ -727,6 +728,10 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     }
     S.squarings = N;
     if (keep) CHK(copy_csr(P, P.TN, P.T));
+    if (keep && N >= 1 && (int)P.sq_path.size() >= N && P.sq_path[N - 1]) {
+        std::swap(P.tsT, P.fwd_ts);   // the tiles of T_{N-1}, input of the last product
+        P.fwd_ts_ok = true;
+    }
     // E = I + T_N (exact zeros not stored)
     {
         // T_N becomes the candidate of the compaction (buffers handed over,
@@ -807,6 +812,14 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // G_N on supp(T_N): E = I + T_N.  With reordering dE is first moved onto
     // the entries of E' (the pattern kept in Epat).
     Buf g, gn, dEp, dHp;
+    DCsr Tt, H0t, St;
+    Buf acc, acc2;
+    std::vector<Buf> D;
+    auto free_locals = at_exit([&] {
+        for (Buf *b : {&g, &gn, &dEp, &dHp, &acc, &acc2}) release(P, *b);
+        for (DCsr *m : {&Tt, &H0t, &St}) release(P, *m);
+        for (auto &b : D) release(P, b);
+    });
     const double *dEu = dE;
     if (P.perm_active) {
         CHK(ensure(P, dEp, sizeof(double) * (P.Epat.nnz + 1)));
@@ -820,7 +833,14 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // iterates of the current segment: seg[j] = T^_{base + j}
     std::vector<DCsr> seg;
     int seg_base = -1;
-    DCsr Tt;
+    auto free_iterates = at_exit([&] {
+        for (auto &A : seg) release(P, A);
+    });
+    // T^_{N-1}'s tiles from the forward's last product serve the first
+    // adjoint step (the largest iterate).  The tile sets trade places and
+    // come back, so their buffers keep their sizes from call to call.
+    bool fwd_tiles = P.fwd_ts_ok && N >= 1;
+    P.fwd_ts_ok = false;
     const DCsr *Tk = &P.TN;   // pattern of g
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     bool g_tiles = false;     // ... and g's values as tiles
@@ -852,17 +872,23 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             Tp = &seg[km1 - base];
         }
         CHK(ensure(P, gn, sizeof(double) * (Tp->nnz + 1)));
-        // tiles when T_{k-1}'s tile fill is high enough, as in the forward
-        bool tiles = false, have_pattern = false;
-        if (tiles_allowed(P, n)) {
-            double fill = 0.0;
-            CHK(bsr_pattern(P, Tp->view(), Tp->nnz, P.tsT, &fill));
+        // tiles exactly where forward step k ran on tiles (the same test of
+        // T_{k-1}'s tile fill)
+        const bool tiles = (int)P.sq_path.size() >= k && P.sq_path[k - 1] != 0;
+        bool have_pattern = false, t_ready = false;
+        if (tiles) {
+            if (k == N && fwd_tiles) {
+                std::swap(P.tsT, P.fwd_ts);
+                t_ready = true;
+            } else {
+                double fill = 0.0;
+                CHK(bsr_pattern(P, Tp->view(), Tp->nnz, P.tsT, &fill));
+            }
             have_pattern = true;
-            tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
         }
         if (tiles) {
             CHK(adjoint_step_bsr(P, *Tp, *Tk, (const double *)g.p, (double *)gn.p, g_ready,
-                                 g_tiles, false));
+                                 g_tiles, false, t_ready));
         } else {
             if (g_stale) CHK(gather_tiles(P, *Tk, P.tsG, (const double *)P.tsG.tB.p,
                                           (double *)g.p));
@@ -899,17 +925,14 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     const int Mp = (int)P.taylor.size();
     CsrView G0 = CsrView{n, (const int64_t *)P.ckpt[0].rp.p, (const int32_t *)P.ckpt[0].ci.p,
                          (const double *)g.p};
-    DCsr H0t;
     CHK(transpose_csr(P, P.H0, H0t));
-    std::vector<Buf> D(Mp + 1);
+    D.resize(Mp + 1);
     CHK(ensure(P, D[Mp], sizeof(double) * (P.taylor[Mp - 1].nnz + 1)));
     CHK(masked(P, P.taylor[Mp - 1].view(), G0, 1.0, none, none, 1.0,
                (double *)D[Mp].p));
-    Buf acc, acc2;
     CHK(ensure(P, acc, sizeof(double) * (nnzH + 1)));
     CHK(ensure(P, acc2, sizeof(double) * (nnzH + 1)));
     if (nnzH) HIPCHK(hipMemsetAsync(acc.p, 0, sizeof(double) * nnzH, st));
-    DCsr St;
     for (int i = Mp - 1; i >= 1; --i) {
         const DCsr &Si = P.taylor[i - 1], &Sn = P.taylor[i];
         CsrView Dn = CsrView{n, (const int64_t *)Sn.rp.p, (const int32_t *)Sn.ci.p,
@@ -1102,6 +1125,7 @@ void expm_free(expm_plan_t p) {
     for (Buf *b : rbufs) release(P, *b);
     release(P, P.tsT);
     release(P, P.tsG);
+    release(P, P.fwd_ts);
     DCsr *mats[] = {&P.H0, &P.S, &P.Snew, &P.T, &P.Tnew, &P.Hpat_t, &P.Hp, &P.Eperm};
     for (DCsr *m : mats) release(P, *m);
     while (!P.outputs.empty()) out_free(P, P.outputs.back());

@@ -61,6 +61,10 @@ struct expm_plan_s {
     std::vector<xpm::host::DCsr> ckpt;          // kept iterates T^_k, k = ckpt_at[j]
     std::vector<int> ckpt_at;                   // 0, then every ck back from N - 1
     xpm::host::DCsr TN;                         // T^_N
+    // T^_{N-1} as tiles (pattern and both layouts) when the last squaring ran
+    // on tiles: the first adjoint step needs exactly these
+    xpm::host::TileSet fwd_ts;
+    bool fwd_ts_ok = false;
     xpm::host::DCsr Epat;                       // pattern of the returned E
     std::vector<double> theta;       // squaring thresholds, 1..N
     bool zero_h = false;
@@ -111,6 +115,18 @@ namespace host {
 
 constexpr int kParts = 1024;
 
+// Runs f when the enclosing scope ends: releases a function's local
+// workspace on its error returns too (release is idempotent).
+template <class F>
+struct AtExit {
+    F f;
+    ~AtExit() { f(); }
+};
+template <class F>
+AtExit<F> at_exit(F f) {
+    return AtExit<F>{f};
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0);
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int ensure(expm_plan_s &P, Buf &b, size_t bytes);
@@ -140,12 +156,14 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                     double theta_fixed, bool exact_alloc, int stat_i);
 // One adjoint step on tiles: out (aligned with Tp's entries) =
 // P_Tp(2 G + G Tp^T + Tp^T G), with G given on the pattern of Tk.  Tp's tile
-// pattern must be in P.tsT; with g_pattern_ready, P.tsG already holds Tk's,
+// pattern must be in P.tsT (with t_tiles_ready also its tiles, else they
+// are assembled here); with g_pattern_ready, P.tsG already holds Tk's,
 // and with g_tiles_ready also G's values as tiles.  The output is left as
 // tiles on Tp's pattern in P.adj_tiles / P.adj_tilesA, and written to out
 // only with want_csr.
 int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const double *g,
-                     double *out, bool g_pattern_ready, bool g_tiles_ready, bool want_csr);
+                     double *out, bool g_pattern_ready, bool g_tiles_ready, bool want_csr,
+                     bool t_tiles_ready);
 // Values of A's stored entries (CSR order) from tiles in the B layout on A's
 // tile pattern ts.
 int gather_tiles(expm_plan_s &P, const DCsr &A, const TileSet &ts, const double *tiles,
