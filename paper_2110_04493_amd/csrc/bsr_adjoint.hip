@@ -16,7 +16,8 @@
 
 namespace xpm {
 
-constexpr int kAdjGroup = 4;   // output tiles per wave (work item)
+constexpr int kAdjGroup = 4;      // output tiles per wave (work item)
+constexpr bool kAdjSplit = true;  // the step as two kernels (see k_bsr_adjoint)
 
 // ----------------------------------------------------------------- T^T's block rows
 
@@ -75,8 +76,11 @@ __global__ void k_bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk,
 // ----------------------------------------------------------------- adjoint tiles
 
 // One wave per work item: a block row I of T and up to kGroup of its tiles.
-template <int kGroup>
-__global__ __launch_bounds__(256) void k_bsr_adjoint(
+// kPart 0 computes the whole step; kPart 1 only 2 G + G T^T (unmasked, into
+// out) and kPart 2 adds T^T G to it, masks, and writes both layouts: the two
+// halves need fewer registers each, so more waves fit on a SIMD.
+template <int kGroup, int kPart>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bsr_adjoint(
     int64_t nb,
     // T = T_{k-1}: pattern and tiles
     const int32_t *__restrict__ tlo, const int64_t *__restrict__ twoff,
@@ -126,15 +130,25 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
     d4 acc[kGroup];
 #pragma unroll
     for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    const d4 two = two_identity_a(lane);
+    if constexpr (kPart == 2) {
 #pragma unroll
-    for (int t = 0; t < kGroup; ++t) {
-        if (t >= ng) break;
-        const int64_t tg = tile_of(glo, gwoff, grt, gtb, I, J[t]);
-        if (tg >= 0) acc[t] = mfma16(two, *(const d4 *)(gB + tg * kTileElems + 4 * lane), acc[t]);
+        for (int t = 0; t < kGroup; ++t) {
+            if (t >= ng) break;
+            acc[t] = *(const d4 *)(out + (ttb[I] + t0 + t) * kTileElems + 4 * lane);
+        }
+    }
+    if constexpr (kPart != 2) {
+        const d4 two = two_identity_a(lane);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            if (t >= ng) break;
+            const int64_t tg = tile_of(glo, gwoff, grt, gtb, I, J[t]);
+            if (tg >= 0)
+                acc[t] = mfma16(two, *(const d4 *)(gB + tg * kTileElems + 4 * lane), acc[t]);
+        }
     }
     // (G T^T)_IJ = sum over K in G's block row I of G_IK (T_JK)^T
-    {
+    if constexpr (kPart != 2) {
         int loJ[kGroup], tbJ[kGroup];
         int64_t w0J[kGroup], WJ[kGroup];
 #pragma unroll
@@ -156,6 +170,14 @@ __global__ __launch_bounds__(256) void k_bsr_adjoint(
                 ti[t] = tile_in_row(loJ[t], w0J[t], WJ[t], tbJ[t], trt, K);
         };
         pipe_products<kGroup>(gtb[I + 1] - g0, item, look, gA, tA, acc);
+    }
+    if constexpr (kPart == 1) {
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            if (t >= ng) break;
+            *(d4 *)(out + (ttb[I] + t0 + t) * kTileElems + 4 * lane) = acc[t];
+        }
+        return;
     }
     // (T^T G)_IJ = sum over K in T's block column I of (T_KI)^T G_KJ
     {
@@ -256,9 +278,19 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int64_t *gofs, double *out, double *outA, int64_t nwork,
                        hipStream_t st) {
     if (nwork == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_adjoint<kAdjGroup>, dim3((nwork + 3) / 4), dim3(256), 0, st, nb, tlo, twoff,
-                       trt, ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
-                       out, outA, nwork);
+    const dim3 grid((unsigned)((nwork + 3) / 4)), block(256);
+    if (kAdjSplit) {
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1>), grid, block, 0, st, nb, tlo, twoff, trt,
+                           ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
+                           out, outA, nwork);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2>), grid, block, 0, st, nb, tlo, twoff, trt,
+                           ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
+                           out, outA, nwork);
+    } else {
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 0>), grid, block, 0, st, nb, tlo, twoff, trt,
+                           ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
+                           out, outA, nwork);
+    }
     return hipGetLastError();
 }
 
