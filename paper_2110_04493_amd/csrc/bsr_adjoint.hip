@@ -82,10 +82,11 @@ __global__ void k_bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk,
 template <int kGroup, int kPart>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bsr_adjoint(
     int64_t nb,
-    // T = T_{k-1}: pattern and tiles
+    // T = T_{k-1}: pattern (with each tile's block column) and tiles
     const int32_t *__restrict__ tlo, const int64_t *__restrict__ twoff,
     const uint2 *__restrict__ trt, const int64_t *__restrict__ ttb,
-    const double *__restrict__ tA, const double *__restrict__ tB,
+    const int32_t *__restrict__ tcols, const double *__restrict__ tA,
+    const double *__restrict__ tB,
     // G on T_k's pattern
     const int32_t *__restrict__ glo, const int64_t *__restrict__ gwoff,
     const uint2 *__restrict__ grt, const int64_t *__restrict__ gtb,
@@ -108,25 +109,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t t0 = (w - gofs[I]) * kGroup;             // first tile (rank in block row I)
     const int64_t cntI = ttb[I + 1] - ttb[I];
     const int ng = (int)min<int64_t>(kGroup, cntI - t0);
-    // block columns J of the group: the t0-th .. set bits of T's block row I
+    // block columns J of the group: tiles t0 .. t0 + ng - 1 of T's block row I
+    // (past ng, a valid block index that is never used)
     int J[kGroup];
 #pragma unroll
-    for (int t = 0; t < kGroup; ++t) J[t] = (int)I;   // valid block index until found
-    {
-        int found = 0;
-        const int64_t W = twoff[I + 1] - twoff[I];
-        for (int64_t ww = 0; ww < W && found < ng; ++ww) {
-            const uint2 e = trt[twoff[I] + ww];
-            uint32_t x = e.x;
-            unsigned r = e.y;
-            while (x && found < ng) {
-                const int bit = __ffs(x) - 1;
-                x &= x - 1;
-                if ((int64_t)r >= t0) J[found++] = tlo[I] + 32 * (int)ww + bit;
-                ++r;
-            }
-        }
-    }
+    for (int t = 0; t < kGroup; ++t) J[t] = t < ng ? tcols[ttb[I] + t0 + t] : (int)I;
     d4 acc[kGroup];
 #pragma unroll
     for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -271,7 +258,8 @@ hipError_t bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk, const 
 }
 
 hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, const uint2 *trt,
-                       const int64_t *ttb, const double *tA, const double *tB, const int32_t *glo,
+                       const int64_t *ttb, const int32_t *tcols, const double *tA,
+                       const double *tB, const int32_t *glo,
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
@@ -279,18 +267,16 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     const dim3 grid((unsigned)((nwork + 3) / 4)), block(256);
+#define XPM_ADJ_ARGS                                                                           \
+    nb, tlo, twoff, trt, ttb, tcols, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, \
+        gofs, out, outA, nwork
     if (kAdjSplit) {
-        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1>), grid, block, 0, st, nb, tlo, twoff, trt,
-                           ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
-                           out, outA, nwork);
-        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2>), grid, block, 0, st, nb, tlo, twoff, trt,
-                           ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
-                           out, outA, nwork);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1>), grid, block, 0, st, XPM_ADJ_ARGS);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2>), grid, block, 0, st, XPM_ADJ_ARGS);
     } else {
-        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 0>), grid, block, 0, st, nb, tlo, twoff, trt,
-                           ttb, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, gofs,
-                           out, outA, nwork);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 0>), grid, block, 0, st, XPM_ADJ_ARGS);
     }
+#undef XPM_ADJ_ARGS
     return hipGetLastError();
 }
 

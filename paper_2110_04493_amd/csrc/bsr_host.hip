@@ -371,7 +371,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     if (prof) HIPCHK(hipEventRecord(P.ev[4], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 1));
     HIPCHK(bsr_adjoint(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
-                       (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (const double *)T.tA.p,
+                       (const uint2 *)T.rt.p, (const int64_t *)T.tb.p,
+                       (const int32_t *)T.cols.p, (const double *)T.tA.p,
                        (const double *)T.tB.p, (const int32_t *)G.lo.p,
                        (const int64_t *)G.woff.p, (const uint2 *)G.rt.p,
                        (const int64_t *)G.tb.p, (const int32_t *)G.cols.p, (const double *)G.tA.p,

@@ -102,9 +102,9 @@ int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz) {
     return EXPM_OK;
 }
 
-// Exact-size copy of a device CSR (checkpoints, Taylor terms).
+// Copy of a device CSR (checkpoints, Taylor terms) into dst's buffers,
+// grown when too small.
 int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src) {
-    release(P, dst);
     CHK(ensure_csr(P, dst, src.n, src.nnz));
     HIPCHK(hipMemcpyAsync(dst.rp.p, src.rp.p, sizeof(int64_t) * (src.n + 1),
                           hipMemcpyDeviceToDevice, P.st));
@@ -115,6 +115,21 @@ int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src) {
                               P.st));
     }
     return EXPM_OK;
+}
+
+DCsr &push_reuse(std::vector<DCsr> &live, std::vector<DCsr> &pool) {
+    live.emplace_back();
+    if (!pool.empty()) {
+        live.back() = pool.back();
+        pool.pop_back();
+    }
+    return live.back();
+}
+
+void retire(std::vector<DCsr> &live, std::vector<DCsr> &pool) {
+    // reversed, so that push_reuse hands entry i its own buffers back
+    for (auto it = live.rbegin(); it != live.rend(); ++it) pool.push_back(*it);
+    live.clear();
 }
 
 int sync(expm_plan_s &P) {
@@ -463,15 +478,15 @@ int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal) {
     return EXPM_OK;
 }
 
+// Forgets the state of the last forward; the buffers stay with the plan
+// for the next call (expm_free releases them).
 void free_adjoint_state(expm_plan_s &P) {
-    for (auto &A : P.taylor) release(P, A);
-    for (auto &A : P.ckpt) release(P, A);
-    P.taylor.clear();
-    P.ckpt.clear();
+    retire(P.taylor, P.taylor_pool);
+    retire(P.ckpt, P.ckpt_pool);
     P.ckpt_at.clear();
     P.sq_path.clear();
-    release(P, P.TN);
-    release(P, P.Epat);
+    P.TN.nnz = 0;
+    P.Epat.nnz = 0;
     P.theta.clear();
     P.have_fwd = false;
 }
@@ -668,8 +683,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     CHK(copy_csr(P, P.S, P.H0));
     CHK(copy_csr(P, P.T, P.H0));
     if (keep) {
-        P.taylor.emplace_back();
-        CHK(copy_csr(P, P.taylor.back(), P.H0));
+        CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.H0));
     }
     S.taylor_terms = 1;
     const CsrView H0v = P.H0.view();
@@ -689,8 +703,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.S.nnz = kept;
         S.taylor_terms = i;
         if (keep) {
-            P.taylor.emplace_back();
-            CHK(copy_csr(P, P.taylor.back(), P.S));
+            CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.S));
         }
         CHK(sparse_add(P, P.T, P.S, P.Tnew));
         std::swap(P.T, P.Tnew);
@@ -703,9 +716,8 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     CHK(sync(P));
     memcpy(&P.T.nnz, P.host, sizeof(int64_t));
     if (keep) {
-        P.ckpt.emplace_back();
         P.ckpt_at.push_back(0);
-        CHK(copy_csr(P, P.ckpt.back(), P.T));
+        CHK(copy_csr(P, push_reuse(P.ckpt, P.ckpt_pool), P.T));
     }
     // Checkpoints every ck squarings, counted back from T_{N-1}: the
     // iterates recomputed by the adjoint are then the cheaper early ones of
@@ -721,9 +733,8 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         std::swap(P.T, P.Tnew);
         P.T.nnz = S.sq_kept[i];
         if (keep && !last && i >= ck_off && (i - ck_off) % ck == 0) {
-            P.ckpt.emplace_back();
             P.ckpt_at.push_back(i);
-            CHK(copy_csr(P, P.ckpt.back(), P.T));
+            CHK(copy_csr(P, push_reuse(P.ckpt, P.ckpt_pool), P.T));
         }
     }
     S.squarings = N;
@@ -830,12 +841,10 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     CHK(ensure(P, g, sizeof(double) * (P.TN.nnz + 1)));
     MaskTerm none{empty_view(), empty_view(), 0.0};
     CHK(masked(P, P.TN.view(), Ev, 1.0, none, none, 1.0, (double *)g.p));
-    // iterates of the current segment: seg[j] = T^_{base + j}
-    std::vector<DCsr> seg;
+    // iterates of the current segment: seg[j] = T^_{base + j} (buffers kept
+    // by the plan from call to call)
+    std::vector<DCsr> &seg = P.seg_pool;
     int seg_base = -1;
-    auto free_iterates = at_exit([&] {
-        for (auto &A : seg) release(P, A);
-    });
     // T^_{N-1}'s tiles from the forward's last product serve the first
     // adjoint step (the largest iterate).  The tile sets trade places and
     // come back, so their buffers keep their sizes from call to call.
@@ -858,14 +867,12 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             Tp = &P.ckpt[ci];
         } else {
             if (seg_base != base) {
-                for (auto &A : seg) release(P, A);
-                seg.clear();
-                seg.resize(next - base);
+                if ((int)seg.size() < next - base) seg.resize(next - base);
                 seg_base = base;
                 const DCsr *prev = &P.ckpt[ci];
                 for (int j = base + 1; j <= std::min(next - 1, N - 1); ++j) {
                     CHK(square_step(P, *prev, seg[j - base], 0.0, true, P.theta[j - 1], false,
-                                    true, 0, j));
+                                    false, 0, j));
                     prev = &seg[j - base];
                 }
             }
@@ -912,13 +919,8 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             std::swap(P.tsG.tB, P.adj_tiles);
             std::swap(P.tsG.tA, P.adj_tilesA);
         }
-        if (k - 1 == base && seg_base == base) {
-            for (auto &A : seg) release(P, A);
-            seg.clear();
-            seg_base = -1;
-        }
+        if (k - 1 == base && seg_base == base) seg_base = -1;
     }
-    for (auto &A : seg) release(P, A);
     if (g_stale)
         CHK(gather_tiles(P, *Tk, P.tsG, (const double *)P.tsG.tB.p, (double *)g.p));
     // Taylor seed: g is dL/dT^_0 on supp(T^_0) = P.ckpt[0].
@@ -1126,8 +1128,11 @@ void expm_free(expm_plan_t p) {
     release(P, P.tsT);
     release(P, P.tsG);
     release(P, P.fwd_ts);
-    DCsr *mats[] = {&P.H0, &P.S, &P.Snew, &P.T, &P.Tnew, &P.Hpat_t, &P.Hp, &P.Eperm};
+    DCsr *mats[] = {&P.H0, &P.S,  &P.Snew, &P.T,     &P.Tnew,
+                    &P.Hpat_t, &P.Hp, &P.Eperm, &P.TN, &P.Epat};
     for (DCsr *m : mats) release(P, *m);
+    for (auto *v : {&P.taylor_pool, &P.ckpt_pool, &P.seg_pool})
+        for (DCsr &A : *v) release(P, A);
     while (!P.outputs.empty()) out_free(P, P.outputs.back());
     (void)hipStreamSynchronize(P.st);
     if (P.have_events)

@@ -157,7 +157,8 @@ hipError_t bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk, const 
                        int32_t *ck, int64_t *ct, hipStream_t st);
 hipError_t bsr_groups4(const int64_t *tb, int64_t nb, int64_t *gcnt, hipStream_t st);
 hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, const uint2 *trt,
-                       const int64_t *ttb, const double *tA, const double *tB, const int32_t *glo,
+                       const int64_t *ttb, const int32_t *tcols, const double *tA,
+                       const double *tB, const int32_t *glo,
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,

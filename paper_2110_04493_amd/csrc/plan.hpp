@@ -59,6 +59,9 @@ struct expm_plan_s {
     double a = 0;
     std::vector<xpm::host::DCsr> taylor;        // S^_1 .. S^_M'
     std::vector<xpm::host::DCsr> ckpt;          // kept iterates T^_k, k = ckpt_at[j]
+    // buffers of earlier calls' terms, checkpoints and recomputed iterates,
+    // reused entry for entry so that repeated calls do not reallocate
+    std::vector<xpm::host::DCsr> taylor_pool, ckpt_pool, seg_pool;
     std::vector<int> ckpt_at;                   // 0, then every ck back from N - 1
     xpm::host::DCsr TN;                         // T^_N
     // T^_{N-1} as tiles (pattern and both layouts) when the last squaring ran
@@ -134,6 +137,10 @@ void release(expm_plan_s &P, Buf &b);
 void release(expm_plan_s &P, DCsr &A);
 int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz);
 int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src);
+// Appends an entry to live, reusing the buffers of the entry at the same
+// position in an earlier call (kept in pool by retire).
+DCsr &push_reuse(std::vector<DCsr> &live, std::vector<DCsr> &pool);
+void retire(std::vector<DCsr> &live, std::vector<DCsr> &pool);
 int sync(expm_plan_s &P);
 int scan(expm_plan_s &P, const int64_t *in, int64_t *out, int64_t n);
 void *out_alloc(expm_plan_s &P, size_t bytes);
