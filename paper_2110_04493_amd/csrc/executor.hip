@@ -357,6 +357,51 @@ int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst) {
     return EXPM_OK;
 }
 
+// dst = sum of the Taylor terms P.taylor in order (exact zeros removed): one
+// multi-term pass when every row fits the kernel's LDS slice, else the
+// terms added pairwise (the same sums in the same order).
+int sum_taylor(expm_plan_s &P, DCsr &dst) {
+    const int m = (int)P.taylor.size();
+    const int64_t n = P.taylor[0].n;
+    if (m == 1) return copy_csr(P, dst, P.taylor[0]);
+    if (m <= kSumMaxTerms) {
+        SumTerms T{};
+        for (int t = 0; t < m; ++t) {
+            T.rp[t] = (const int64_t *)P.taylor[t].rp.p;
+            T.ci[t] = (const int32_t *)P.taylor[t].ci.p;
+            T.v[t] = (const double *)P.taylor[t].v.p;
+        }
+        T.m = m;
+        CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.flags, sizeof(int) * 4));
+        HIPCHK(hipMemsetAsync(P.flags.p, 0, sizeof(int), P.st));
+        HIPCHK(sum_terms_count(T, n, (int64_t *)P.cnt.p, (int *)P.flags.p, P.st));
+        CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
+        int64_t *hl = (int64_t *)P.host;
+        HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.krp.p + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, P.st));
+        HIPCHK(hipMemcpyAsync(hl + 1, P.flags.p, sizeof(int), hipMemcpyDeviceToHost, P.st));
+        CHK(sync(P));
+        const int64_t nnz = hl[0];
+        const int overflow = (int)(hl[1] & 0xffffffff);
+        if (!overflow) {
+            CHK(ensure_csr(P, dst, n, nnz));
+            HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1),
+                                  hipMemcpyDeviceToDevice, P.st));
+            HIPCHK(sum_terms_write(T, n, (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
+                                   (double *)dst.v.p, P.st));
+            return EXPM_OK;
+        }
+    }
+    CHK(copy_csr(P, dst, P.taylor[0]));
+    for (int t = 1; t < m; ++t) {
+        CHK(sparse_add(P, dst, P.taylor[t], P.Tnew));
+        std::swap(dst, P.Tnew);
+    }
+    return EXPM_OK;
+}
+
 // Device transpose of A into dst.
 int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst) {
     const int64_t n = A.n;
@@ -681,10 +726,8 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     if (ck <= 0) ck = std::max(1, (int)ceil(sqrt((double)N)));
     P.ck = ck;
     CHK(copy_csr(P, P.S, P.H0));
-    CHK(copy_csr(P, P.T, P.H0));
-    if (keep) {
-        CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.H0));
-    }
+    // the terms are kept (the adjoint needs them, and T_0 is their sum)
+    CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.H0));
     S.taylor_terms = 1;
     const CsrView H0v = P.H0.view();
     for (int i = 2; i <= M; ++i) {
@@ -702,13 +745,11 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         std::swap(P.S, P.Snew);
         P.S.nnz = kept;
         S.taylor_terms = i;
-        if (keep) {
-            CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.S));
-        }
-        CHK(sparse_add(P, P.T, P.S, P.Tnew));
-        std::swap(P.T, P.Tnew);
+        CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.S));
     }
     P.Mp = S.taylor_terms;
+    // T_0 = S_1 + ... + S_M' (Eq. 4.14's sum), term after term
+    CHK(sum_taylor(P, P.T));
     S.t_taylor_ms = ms_since(t_taylor0);
     // T's true nnz (the add only bounds it)
     HIPCHK(hipMemcpyAsync(P.host, (int64_t *)P.T.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,

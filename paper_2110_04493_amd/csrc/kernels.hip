@@ -602,6 +602,138 @@ hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, dou
     return hipGetLastError();
 }
 
+// One wave per row.  The distinct columns of the row over all terms are
+// marked in a bit map over the row's column window (prefix counts give each
+// its rank); the terms then add into an accumulator per rank, one term after
+// the other, and the nonzero sums are counted or written in column order.
+constexpr int kSumWaves = 4;      // rows per workgroup
+constexpr int kSumWords = 512;    // bit-map words per wave (16384 columns)
+constexpr int kSumAcc = 1024;     // distinct columns per wave
+
+template <bool kWrite>
+__global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int64_t n,
+                                                                  int64_t *cnt, int *overflow,
+                                                                  const int64_t *orp,
+                                                                  int32_t *oci, double *ov) {
+    __shared__ uint2 sbits[kSumWaves][kSumWords];
+    __shared__ double sacc[kSumWaves][kSumAcc];
+    __shared__ int32_t scol[kSumWaves][kSumAcc];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * kSumWaves + wv;
+    if (i >= n) return;
+    auto sync_wave = []() {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    };
+    int mn = INT32_MAX, mx = -1;
+    if (lane < T.m) {
+        const int64_t b = T.rp[lane][i], e = T.rp[lane][i + 1];
+        if (e > b) {
+            mn = T.ci[lane][b];
+            mx = T.ci[lane][e - 1];
+        }
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (mx < 0) {
+        if (!kWrite && lane == 0) cnt[i] = 0;
+        return;
+    }
+    const int lo = mn & ~31;
+    const int W = ((mx - lo) >> 5) + 1;
+    if (W > kSumWords) {
+        if (!kWrite && lane == 0) {
+            cnt[i] = 0;
+            atomicOr(overflow, 1);
+        }
+        return;
+    }
+    uint2 *bits = sbits[wv];
+    for (int w = lane; w < W; w += kWave) bits[w] = make_uint2(0u, 0u);
+    sync_wave();
+    for (int t = 0; t < T.m; ++t) {
+        const int64_t b = T.rp[t][i], e = T.rp[t][i + 1];
+        for (int64_t p = b + lane; p < e; p += kWave) {
+            const int d = T.ci[t][p] - lo;
+            atomicOr(&bits[d >> 5].x, 1u << (d & 31));
+        }
+    }
+    sync_wave();
+    unsigned carry = 0;
+    for (int w0 = 0; w0 < W; w0 += kWave) {
+        const int w = w0 + lane;
+        const unsigned pc = w < W ? __popc(bits[w].x) : 0u;
+        const unsigned inc = wave_incl_scan(pc);
+        if (w < W) bits[w].y = carry + inc - pc;
+        carry += __shfl(inc, kWave - 1);
+    }
+    const int U = (int)carry;
+    if (U > kSumAcc) {
+        if (!kWrite && lane == 0) {
+            cnt[i] = 0;
+            atomicOr(overflow, 1);
+        }
+        return;
+    }
+    double *acc = sacc[wv];
+    int32_t *col = scol[wv];
+    for (int r = lane; r < U; r += kWave) acc[r] = 0.0;
+    sync_wave();
+    auto rank = [&](int c) {
+        const int d = c - lo;
+        const uint2 e2 = bits[d >> 5];
+        return (int)(e2.y + __popc(e2.x & ((1u << (d & 31)) - 1u)));
+    };
+    // terms in order; within one term a row's columns are distinct
+    for (int t = 0; t < T.m; ++t) {
+        const int64_t b = T.rp[t][i], e = T.rp[t][i + 1];
+        for (int64_t p = b + lane; p < e; p += kWave) {
+            const int c = T.ci[t][p];
+            const int r = rank(c);
+            acc[r] += T.v[t][p];
+            col[r] = c;
+        }
+        sync_wave();
+    }
+    if (!kWrite) {
+        long long k = 0;
+        for (int r = lane; r < U; r += kWave) k += acc[r] != 0.0;
+        k = wave_sum_ll(k);
+        if (lane == 0) cnt[i] = k;
+        return;
+    }
+    int64_t o = orp[i];
+    for (int r0 = 0; r0 < U; r0 += kWave) {
+        const int r = r0 + lane;
+        const bool keep = r < U && acc[r] != 0.0;
+        const unsigned long long bm = __ballot(keep);
+        if (keep) {
+            const int64_t q = o + __popcll(bm & ((1ull << lane) - 1ull));
+            oci[q] = col[r];
+            ov[q] = acc[r];
+        }
+        o += __popcll(bm);
+    }
+}
+
+hipError_t sum_terms_count(const SumTerms &T, int64_t n, int64_t *cnt, int *overflow,
+                           hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_terms<false>, dim3((unsigned)((n + kSumWaves - 1) / kSumWaves)),
+                       dim3(kWave * kSumWaves), 0, st, T, n, cnt, overflow,
+                       (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t sum_terms_write(const SumTerms &T, int64_t n, const int64_t *orp, int32_t *oci,
+                           double *ov, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_terms<true>, dim3((unsigned)((n + kSumWaves - 1) / kSumWaves)),
+                       dim3(kWave * kSumWaves), 0, st, T, n, (int64_t *)nullptr, (int *)nullptr,
+                       orp, oci, ov);
+    return hipGetLastError();
+}
+
 __global__ void k_identity(int64_t n, int64_t *rp, int32_t *ci, double *v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= n) rp[i] = i;

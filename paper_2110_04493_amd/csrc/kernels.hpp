@@ -209,6 +209,23 @@ hipError_t extract_block(const int64_t *rp, const int32_t *ci, const double *v, 
 hipError_t add_count(CsrView A, CsrView B, int64_t *cnt, hipStream_t st);
 hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, double *cv,
                      hipStream_t st);
+// T = S_1 + ... + S_m (m <= kSumMaxTerms terms of one n x n shape), summed
+// entry by entry in term order (bitwise what adding the terms one after
+// another gives) with exact zeros removed; two passes (count, then write).
+// A row whose column window or number of distinct columns exceeds the
+// kernel's LDS slice sets *overflow (count pass) and is not summed: the
+// caller then adds the terms pairwise instead.
+constexpr int kSumMaxTerms = 32;
+struct SumTerms {
+    const int64_t *rp[kSumMaxTerms];
+    const int32_t *ci[kSumMaxTerms];
+    const double *v[kSumMaxTerms];
+    int m;
+};
+hipError_t sum_terms_count(const SumTerms &T, int64_t n, int64_t *cnt, int *overflow,
+                           hipStream_t st);
+hipError_t sum_terms_write(const SumTerms &T, int64_t n, const int64_t *orp, int32_t *oci,
+                           double *ov, hipStream_t st);
 // Identity matrix rows.
 hipError_t fill_identity(int64_t n, int64_t *rp, int32_t *ci, double *v, hipStream_t st);
 

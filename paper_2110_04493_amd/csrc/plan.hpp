@@ -150,6 +150,7 @@ int plan_mn(double nh, double eps, int *Mo, int *No);
 int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, double div,
            bool rowsq, int64_t *total);
 int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst);
+int sum_taylor(expm_plan_s &P, DCsr &dst);
 int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
 int check_view(const expm_csr_cview *H);

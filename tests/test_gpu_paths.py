@@ -102,3 +102,29 @@ def test_adjoint_mixed_paths(reorder):
         assert rel <= TOL
         mixed += any(paths) and not all(paths)
     assert mixed > 0
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_wide_rows_taylor_sum(adjoint):
+    """A ring of 20,000 nodes in natural order: the rows of the first and
+    last node span the whole index range, wider than the LDS slice of the
+    multi-term Taylor sum, which then falls back to pairwise adds."""
+    n = 20000
+    T = W.tridiag(n, 1.0, -2.0, 1.0, 0.4)
+    r = np.concatenate([T.rows(), [0, n - 1]])
+    c = np.concatenate([T.col.astype(np.int64), [n - 1, 0]])
+    v = np.concatenate([T.val, [0.4, 0.4]])
+    H, eps = W.csr_from_coo(n, r, c, v), 1e-12
+    if adjoint:
+        dg, _ = gpu_grad(H, eps, density=0.05, reorder=0)
+        do, _ = oracle_grad(H, eps, density=0.05)
+        rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+        print(f"[wide rows] adjoint rel={rel:.2e}", flush=True)
+        assert rel <= TOL
+        return
+    Eg, sg = run_gpu(H, eps, reorder=0)
+    Eo, so = run_oracle(H, eps)
+    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
+    print(f"[wide rows] M={sg['M']} N={sg['N']} terms={sg['taylor_terms']} relF={rel:.2e}",
+          flush=True)
+    assert rel <= TOL and ok
