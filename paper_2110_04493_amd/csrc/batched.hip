@@ -468,7 +468,7 @@ int batched(expm_plan_s &P, BatchBufs &B, int count, const expm_csr_cview *H, co
     }
     // --- Taylor seed for all instances at once
     CHK(copy_csr(P, P.S, P.H0));
-    CHK(copy_csr(P, P.T, P.H0));
+    CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.H0));   // the terms, summed below
     int maxM = 0;
     for (auto &I : A) maxM = std::max(maxM, I.M);
     std::vector<double> egs(K);
@@ -517,9 +517,9 @@ int batched(expm_plan_s &P, BatchBufs &B, int count, const expm_csr_cview *H, co
             else
                 A[k].terms = i;
         }
-        CHK(sparse_add(P, P.T, P.S, P.Tnew));
-        std::swap(P.T, P.Tnew);
+        CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.S));
     }
+    CHK(sum_taylor(P, P.T));
     HIPCHK(hipMemcpyAsync(P.host, (int64_t *)P.T.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
     CHK(sync(P));
