@@ -11,9 +11,10 @@
 //
 // Latency is hidden inside the wave rather than by occupancy (long rows need
 // tens of KB of LDS each): the left factor's row is read 64 entries at a
-// time, one per lane, and broadcast with readlane; every right-factor row is
-// loaded kUnroll chunks of 64 at a time before any LDS work, and the
-// accumulation uses LDS atomics without return, so nothing waits on them.
+// time, one per lane, and broadcast with readlane; a long right-factor row is
+// loaded kUnroll chunks of 64 at a time before any LDS work, short ones
+// (stencil rows) kShortRows rows at a time, and the accumulation uses LDS
+// atomics without return, so nothing waits on them.
 // One right-factor row feeds one instruction, so no two lanes of an
 // instruction hit the same slot, and the LDS executes a wave's instructions
 // in order: the sum for every slot is formed in the left row's storage order
@@ -71,6 +72,14 @@ __device__ __forceinline__ double readlane_f64(double x, int j) {
     return __longlong_as_double(readlane_i64(__double_as_longlong(x), j));
 }
 
+// Right-factor rows of at most kShortChunks * 64 entries are loaded
+// kShortRows rows at a time (all loads in flight before any LDS work);
+// longer rows go one at a time, kUnroll chunks of 64 per round.  Either way
+// each call of f covers one chunk of one right-factor row, and the calls
+// follow the left row's storage order.
+constexpr int kShortRows = 4;
+constexpr int kShortChunks = 2;
+
 // Calls f(col, a, b) for every partial product a_ik * b_kj of row i of A*B,
 // with a_ik taken in A's storage order and, for each of them, B's row k in
 // chunks of 64 lanes (f runs on the lanes holding an entry).
@@ -90,7 +99,34 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
             s1 = B.rp[k + 1];
         }
         const int m = (int)((e - p0) < kWave ? (e - p0) : kWave);
-        for (int j = 0; j < m; ++j) {
+        const unsigned long long shortm = __ballot(p < e && s1 - s0 <= kShortChunks * kWave);
+        for (int j = 0; j < m;) {
+            const int un = m - j < kShortRows ? m - j : kShortRows;
+            const unsigned long long grp = ((1ull << un) - 1ull) << j;
+            if ((shortm & grp) == grp) {
+                int c[kShortRows][kShortChunks];
+                double v[kShortRows][kShortChunks], a[kShortRows];
+#pragma unroll
+                for (int u = 0; u < kShortRows; ++u) {
+                    const int jj = u < un ? j + u : j;
+                    a[u] = readlane_f64(av, jj);
+                    const int64_t q0 = readlane_i64(s0, jj), q1 = readlane_i64(s1, jj);
+#pragma unroll
+                    for (int h = 0; h < kShortChunks; ++h) {
+                        const int64_t q = q0 + h * kWave + lane;
+                        const bool ok = u < un && q < q1;
+                        c[u][h] = ok ? B.ci[q] : -1;
+                        v[u][h] = ok ? B.v[q] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kShortRows; ++u)
+#pragma unroll
+                    for (int h = 0; h < kShortChunks; ++h)
+                        if (c[u][h] >= 0) f(c[u][h], a[u], v[u][h]);
+                j += un;
+                continue;
+            }
             const double a = readlane_f64(av, j);
             const int64_t q0 = readlane_i64(s0, j), q1 = readlane_i64(s1, j);
             for (int64_t qb = q0; qb < q1; qb += kUnroll * kWave) {
@@ -110,6 +146,7 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
                 for (int u = 0; u < kUnroll; ++u)
                     if (c[u] >= 0) f(c[u], a, v[u]);
             }
+            ++j;
         }
     }
 }
@@ -130,7 +167,32 @@ __device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, i
             s1 = B.rp[k + 1];
         }
         const int m = (int)((e - p0) < kWave ? (e - p0) : kWave);
-        for (int j = 0; j < m; ++j) {
+        const unsigned long long shortm = __ballot(p < e && s1 - s0 <= kShortChunks * kWave);
+        for (int j = 0; j < m;) {
+            const int un = m - j < kShortRows ? m - j : kShortRows;
+            const unsigned long long grp = ((1ull << un) - 1ull) << j;
+            if ((shortm & grp) == grp) {
+                int c[kShortRows][kShortChunks];
+                bool any[kShortRows][kShortChunks];
+#pragma unroll
+                for (int u = 0; u < kShortRows; ++u) {
+                    const int jj = u < un ? j + u : j;
+                    const int64_t q0 = readlane_i64(s0, jj), q1 = readlane_i64(s1, jj);
+#pragma unroll
+                    for (int h = 0; h < kShortChunks; ++h) {
+                        const int64_t q = q0 + h * kWave + lane;
+                        c[u][h] = u < un && q < q1 ? B.ci[q] : -1;
+                        any[u][h] = u < un && q0 + h * kWave < q1;   // uniform
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kShortRows; ++u)
+#pragma unroll
+                    for (int h = 0; h < kShortChunks; ++h)
+                        if (any[u][h]) f(c[u][h], c[u][h] >= 0);
+                j += un;
+                continue;
+            }
             const int64_t q0 = readlane_i64(s0, j), q1 = readlane_i64(s1, j);
             for (int64_t qb = q0; qb < q1; qb += kUnroll * kWave) {
                 int c[kUnroll];
@@ -143,6 +205,7 @@ __device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, i
                 for (int u = 0; u < kUnroll; ++u)
                     if (qb + u * kWave < q1) f(c[u], c[u] >= 0);
             }
+            ++j;
         }
     }
 }
