@@ -891,6 +891,24 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // come back, so their buffers keep their sizes from call to call.
     bool fwd_tiles = P.fwd_ts_ok && N >= 1;
     P.fwd_ts_ok = false;
+    // The tiles the recomputation builds for each step's input are kept for
+    // that iterate's adjoint step when ck tile sets of the largest iterate
+    // take at most a quarter of the device memory.  The kept sets stay with
+    // the plan, so later calls reuse their buffers.
+    bool retain = false;
+    {
+        size_t fr = 0, tot = 0;
+        const size_t one = fwd_tiles ? P.fwd_ts.tA.bytes + P.fwd_ts.tB.bytes + P.fwd_ts.seg.bytes
+                                     : 0;
+        if (one > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess)
+            retain = (size_t)ck * one <= tot / 4;
+        (void)hipGetLastError();
+    }
+    if ((int)P.kts.size() < ck) {
+        P.kts.resize(ck);
+        P.kts_ok.resize(ck);
+    }
+    std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
     const DCsr *Tk = &P.TN;   // pattern of g
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     bool g_tiles = false;     // ... and g's values as tiles
@@ -910,10 +928,16 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             if (seg_base != base) {
                 if ((int)seg.size() < next - base) seg.resize(next - base);
                 seg_base = base;
+                std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
                 const DCsr *prev = &P.ckpt[ci];
                 for (int j = base + 1; j <= std::min(next - 1, N - 1); ++j) {
                     CHK(square_step(P, *prev, seg[j - base], 0.0, true, P.theta[j - 1], false,
                                     false, 0, j));
+                    const int pos = j - 1 - base;   // P.tsT holds T_{j-1}'s tiles
+                    if (retain && P.sq_path[j - 1] && pos < (int)P.kts.size()) {
+                        std::swap(P.tsT, P.kts[pos]);
+                        P.kts_ok[pos] = 1;
+                    }
                     prev = &seg[j - base];
                 }
             }
@@ -925,8 +949,13 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         const bool tiles = (int)P.sq_path.size() >= k && P.sq_path[k - 1] != 0;
         bool have_pattern = false, t_ready = false;
         if (tiles) {
+            const int pos = km1 - base;
             if (k == N && fwd_tiles) {
                 std::swap(P.tsT, P.fwd_ts);
+                t_ready = true;
+            } else if (seg_base == base && pos < (int)P.kts_ok.size() && P.kts_ok[pos]) {
+                std::swap(P.tsT, P.kts[pos]);
+                P.kts_ok[pos] = 0;
                 t_ready = true;
             } else {
                 double fill = 0.0;
@@ -1169,6 +1198,7 @@ void expm_free(expm_plan_t p) {
     release(P, P.tsT);
     release(P, P.tsG);
     release(P, P.fwd_ts);
+    for (TileSet &ts : P.kts) release(P, ts);
     DCsr *mats[] = {&P.H0, &P.S,  &P.Snew, &P.T,     &P.Tnew,
                     &P.Hpat_t, &P.Hp, &P.Eperm, &P.TN, &P.Epat};
     for (DCsr *m : mats) release(P, *m);

@@ -68,6 +68,10 @@ struct expm_plan_s {
     // on tiles: the first adjoint step needs exactly these
     xpm::host::TileSet fwd_ts;
     bool fwd_ts_ok = false;
+    // the recomputed iterates of one checkpoint segment as tiles (position
+    // j - base), kept for the adjoint steps when they fit the memory budget
+    std::vector<xpm::host::TileSet> kts;
+    std::vector<char> kts_ok;
     xpm::host::DCsr Epat;                       // pattern of the returned E
     std::vector<double> theta;       // squaring thresholds, 1..N
     bool zero_h = false;
