@@ -608,7 +608,7 @@ hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, dou
 // the other, and the nonzero sums are counted or written in column order.
 constexpr int kSumWaves = 4;      // rows per workgroup
 constexpr int kSumWords = 512;    // bit-map words per wave (16384 columns)
-constexpr int kSumAcc = 1024;     // distinct columns per wave
+constexpr int kSumAcc = 256;      // distinct columns per wave
 
 template <bool kWrite>
 __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int64_t n,

@@ -26,7 +26,7 @@ constexpr int kBfsThreads = 1024;
 constexpr int kCellMax = 256;      // largest cell the ordering accepts
 constexpr int kPermWaves = 4;        // output rows (waves) per workgroup
 constexpr int kPermLdsWords = 1024;  // bit-map words per wave in LDS
-constexpr int kPermCache = 16;       // mapped columns held per lane
+constexpr int kPermCache = 32;       // mapped columns held per lane
 
 __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
