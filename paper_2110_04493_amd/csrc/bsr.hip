@@ -399,7 +399,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
     int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
-    double *__restrict__ tmx, uint4 *__restrict__ trc) {
+    double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg) {
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
@@ -453,13 +453,15 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         if (ct < 0) continue;
         *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
         if (!tsq) continue;
-        // the tile's share of ||I + C||_F^2 over the rows below n, its
-        // nonzero slots, their smallest and largest magnitudes and the
-        // nonzeros of each of its 16 rows (slots outside the matrix hold
-        // zeros); lane holds (i, j) = (4 r + lane / 16, lane % 16)
+        // the tile's sum of squares, its nonzero slots, their smallest and
+        // largest magnitudes and the nonzeros of each of its 16 rows, all
+        // over the rows below n (slots outside the matrix hold zeros); for
+        // the diagonal tile also sum (2 c_ii + 1), which turns its share of
+        // ||C||_F^2 into its share of ||I + C||_F^2.  Lane holds
+        // (i, j) = (4 r + lane / 16, lane % 16).
         const int rows = (int)min<int64_t>(kTile, n - I * kTile);
         const bool dtile = J[t] == (int)I;
-        double s = 0.0, mn = INFINITY, mx = 0.0;
+        double s = 0.0, mn = INFINITY, mx = 0.0, dg = 0.0;
         long long nz = 0;
         uint32_t rc[4] = {0u, 0u, 0u, 0u};   // byte i % 4 of word i / 4: row i
 #pragma unroll
@@ -467,8 +469,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
             const int i = 4 * r + (lane >> 4);
             const bool in = i < rows;
             const double v = in ? acc[t][r] : 0.0;
-            const double f = dtile && i == (lane & 15) ? v + 1.0 : v;
-            if (in) s = fma(f, f, s);
+            s = fma(v, v, s);
+            if (in && i == (lane & 15)) dg += fma(2.0, v, 1.0);
             nz += v != 0.0;
             if (v != 0.0) mn = fmin(mn, fabs(v));
             mx = fmax(mx, fabs(v));
@@ -482,6 +484,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         nz = wave_sum_ll(nz);
         mn = wave_min_f64(mn);
         mx = wave_max_f64(mx);
+        if (dtile) {
+            dg = wave_sum(dg);
+            if (lane == 0) bdg[I] = dg;
+        }
         if (lane == 0) {
             tsq[ct] = s;
             tnz[ct] = (int32_t)nz;
@@ -495,13 +501,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
 // ----------------------------------------------------------------- norm, compaction
 
 // Per block row, from the per-tile partials the product wrote: the sum over
-// its candidate slots of (c_ij + delta_ij)^2 for the rows below n, plus 1 for
-// each such row whose diagonal tile is absent; and the count of nonzero
+// its candidate slots of (c_ij + delta_ij)^2 for the rows below n (the
+// tiles' sums of squares, plus the diagonal tile's sum of (2 c_ii + 1), or
+// plus 1 for each row when that tile is absent); and the count of nonzero
 // slots.  Tiles are taken lane-strided in index order, then a fixed
 // butterfly, so the result is reproducible.
 __global__ void k_bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                                  const int32_t *ccols, const double *tsq, const int32_t *tnz,
-                                 double *bsq, int64_t *bnz) {
+                                 const double *bdg, double *bsq, int64_t *bnz) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= nb) return;
     const int lane = lane_id();
@@ -519,7 +526,7 @@ __global__ void k_bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, cons
     nz = wave_sum_ll(nz);
     diag = __ballot(diag) != 0ull;
     if (lane == 0) {
-        bsq[I] = diag ? s : s + rows;
+        bsq[I] = diag ? s + bdg[I] : s + rows;
         bnz[I] = nz;
     }
 }
@@ -750,22 +757,22 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
-                             int32_t *tnz, double *tmn, double *tmx, uint4 *trc,
+                             int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
                              int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz, tmn, tmx, trc);
+                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg);
     return hipGetLastError();
 }
 
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
-                          double *bsq, int64_t *bnz, hipStream_t st) {
+                          const double *bdg, double *bsq, int64_t *bnz, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_norm_tiles, dim3((nb + 3) / 4), dim3(256), 0, st, n, nb, ctb, ccnt,
-                       ccols, tsq, tnz, bsq, bnz);
+                       ccols, tsq, tnz, bdg, bsq, bnz);
     return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         CHK(ensure(P, P.c_mn, sizeof(double) * (ctiles + 1)));
         CHK(ensure(P, P.c_mx, sizeof(double) * (ctiles + 1)));
         CHK(ensure(P, P.c_rc, sizeof(uint4) * (ctiles + 1)));
+        CHK(ensure(P, P.b_dg, sizeof(double) * (nb + 1)));
     }
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
                         (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p,
@@ -162,7 +163,8 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              tile_norms ? (int32_t *)P.c_nz.p : nullptr,
                              tile_norms ? (double *)P.c_mn.p : nullptr,
                              tile_norms ? (double *)P.c_mx.p : nullptr,
-                             tile_norms ? (uint4 *)P.c_rc.p : nullptr, nwork, st));
+                             tile_norms ? (uint4 *)P.c_rc.p : nullptr,
+                             tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     *ctiles_out = ctiles;
@@ -239,8 +241,8 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     CHK(ensure(P, P.tmp2, sizeof(int64_t) * (nb + 1)));
     HIPCHK(bsr_norm_tiles(n, nb, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
                           (const int32_t *)P.c_cols.p, (const double *)P.c_sq.p,
-                          (const int32_t *)P.c_nz.p, (double *)P.b_sq.p, (int64_t *)P.b_nz.p,
-                          st));
+                          (const int32_t *)P.c_nz.p, (const double *)P.b_dg.p,
+                          (double *)P.b_sq.p, (int64_t *)P.b_nz.p, st));
     if (!use_fixed)
         HIPCHK(sum_values((const double *)P.b_sq.p, nb, (double *)P.part.p, kParts,
                           (double *)P.norm2.p, st));
@@ -261,6 +263,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         if (!use_fixed)
             for (int j = 0; j < 4; ++j)
                 HIPCHK(filter_pass_tiles((const double *)P.c_tiles.p, (const double *)P.c_mn.p,
+                                         (const double *)P.c_mx.p, (const double *)P.c_sq.p,
                                          ctiles, ctl, (double *)P.part.p, kParts, st));
         HIPCHK(bsr_count(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
                          (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,

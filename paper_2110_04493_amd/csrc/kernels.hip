@@ -364,6 +364,8 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass(const double *__restr
 // 32 contiguous bytes.
 __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *__restrict__ tiles,
                                                                  const double *__restrict__ tmin,
+                                                                 const double *__restrict__ tmax,
+                                                                 const double *__restrict__ tsq,
                                                                  int64_t ntiles, FilterCtl *c,
                                                                  double *part) {
     typedef double v4 __attribute__((ext_vector_type(4)));
@@ -374,7 +376,11 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
     double s = 0.0;
     for (int64_t t = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; t < ntiles;
          t += (int64_t)gridDim.x * wpb) {
-        if (tmin[t] > theta) continue;
+        if (tmin[t] > theta) continue;   // nothing at or below theta
+        if (tmax[t] <= theta) {            // everything at or below theta
+            if (lane == 0) s += tsq[t];
+            continue;
+        }
         const v4 x = *(const v4 *)(tiles + t * 256 + 4 * lane);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -415,11 +421,12 @@ __device__ void filter_pass_end(double s, double theta, FilterCtl *c, double *pa
     }
 }
 
-hipError_t filter_pass_tiles(const double *tiles, const double *tmin, int64_t ntiles,
-                             FilterCtl *c, double *part, int nparts, hipStream_t st) {
+hipError_t filter_pass_tiles(const double *tiles, const double *tmin, const double *tmax,
+                             const double *tsq, int64_t ntiles, FilterCtl *c, double *part,
+                             int nparts, hipStream_t st) {
     nparts = parts_for(ntiles * 16, nparts);
     hipLaunchKernelGGL(k_filter_pass_tiles, dim3(nparts), dim3(kRedBlock), 0, st, tiles, tmin,
-                       ntiles, c, part);
+                       tmax, tsq, ntiles, c, part);
     return hipGetLastError();
 }
 

@@ -81,11 +81,14 @@ hipError_t filter_init(FilterCtl *c, double eg_scale, const double *norm2, doubl
 hipError_t filter_init_theta(FilterCtl *c, double theta, hipStream_t st);
 // One Algorithm 4.1 pass (sum of v^2 over |v| <= theta) plus the controller
 // update; no-ops once the controller is done.
-// The same pass over candidate tiles of 256 values; tmin[t] is the smallest
-// nonzero magnitude of tile t, and tiles whose nonzeros all exceed the
-// current threshold are skipped without being read.
-hipError_t filter_pass_tiles(const double *tiles, const double *tmin, int64_t ntiles,
-                             FilterCtl *c, double *part, int nparts, hipStream_t st);
+// The same pass over candidate tiles of 256 values.  tmin[t] / tmax[t] are
+// the smallest nonzero and the largest magnitude of tile t and tsq[t] its
+// sum of squares: a tile whose nonzeros all exceed the current threshold is
+// skipped, one whose slots are all at most the threshold adds tsq[t], and
+// only the tiles in between are read.
+hipError_t filter_pass_tiles(const double *tiles, const double *tmin, const double *tmax,
+                             const double *tsq, int64_t ntiles, FilterCtl *c, double *part,
+                             int nparts, hipStream_t st);
 hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
                        double *part, int nparts, hipStream_t st);
 // Kept counts per row (|v| > theta); with addI the identity is added (E = I + T).
@@ -130,11 +133,11 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
-                             int32_t *tnz, double *tmn, double *tmx, uint4 *trc,
+                             int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
                              int64_t nwork, hipStream_t st);
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
-                          double *bsq, int64_t *bnz, hipStream_t st);
+                          const double *bdg, double *bsq, int64_t *bnz, hipStream_t st);
 hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, double *rowsq, hipStream_t st);
 // Compaction of the candidate tiles (kept: |v| > c->theta) into CSR: kept

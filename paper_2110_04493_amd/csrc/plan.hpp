@@ -97,6 +97,8 @@ struct expm_plan_s {
     // per candidate tile: its share of ||I + T~||_F^2, its nonzero slots,
     // their smallest and largest magnitudes and the nonzeros of each row
     xpm::host::Buf c_sq, c_nz, c_mn, c_mx, c_rc;
+    // per block row: the diagonal tile's sum of (2 c_ii + 1)
+    xpm::host::Buf b_dg;
     // panels of four block rows for the product (p_*: origin, words, column
     // counts and lists, work groups)
     xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
