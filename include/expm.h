@@ -87,8 +87,11 @@ typedef struct {
     double e_r;              /* Algorithm 4.1 tolerance e_r (default 0.1)      */
     int max_filter_iter;     /* Algorithm 4.1 iteration cap (default 64)       */
     int keep_checkpoints;    /* 1: keep what expm_sparse_backward needs         */
-    int checkpoint_interval; /* squaring iterates kept every c steps; 0 picks
-                                c = ceil(sqrt(N)), 1 keeps all of them         */
+    int checkpoint_interval; /* squaring iterates the adjoint keeps: c >= 1
+                                keeps every c-th one counted back from T_{N-1}
+                                (1 keeps all of them); 0 (default) keeps
+                                ceil(sqrt(N)) of them, the last iterates
+                                T_{N-C} .. T_{N-1}, the costliest to recompute */
     void *stream;            /* hipStream_t for every launch and copy          */
     const expm_allocator *allocator; /* outputs; NULL = library allocation     */
     int profile;             /* 1: time the kernel phases of every squaring

@@ -722,8 +722,16 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     P.M = M;
     P.N = N;
     P.a = a;
-    int ck = P.opts.checkpoint_interval;
-    if (ck <= 0) ck = std::max(1, (int)ceil(sqrt((double)N)));
+    // Checkpoints of the squaring iterates (the adjoint recomputes the rest):
+    // with checkpoint_interval c >= 1, every c-th iterate counted back from
+    // T_{N-1}; with 0, ceil(sqrt(N)) of them, on the last iterates
+    // T_{N-C} .. T_{N-1}.  Every iterate that is not a checkpoint is
+    // recomputed exactly once, and the iterates grow with every squaring,
+    // so the last ones are the most expensive to recompute; the early ones
+    // the first segment then holds are small.
+    const bool ck_last = P.opts.checkpoint_interval <= 0;
+    const int ck = ck_last ? std::max(1, (int)ceil(sqrt((double)N)))
+                           : P.opts.checkpoint_interval;
     P.ck = ck;
     CHK(copy_csr(P, P.S, P.H0));
     // the terms are kept (the adjoint needs them, and T_0 is their sum)
@@ -760,10 +768,10 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.ckpt_at.push_back(0);
         CHK(copy_csr(P, push_reuse(P.ckpt, P.ckpt_pool), P.T));
     }
-    // Checkpoints every ck squarings, counted back from T_{N-1}: the
-    // iterates recomputed by the adjoint are then the cheaper early ones of
-    // each segment (the iterates grow with every squaring).
     const int ck_off = N >= 1 ? (N - 1) % ck : 0;
+    auto is_ckpt = [&](int i) {
+        return ck_last ? i >= N - ck : i >= ck_off && (i - ck_off) % ck == 0;
+    };
     // Step 4: squarings.  Step 5 (E = I + T_N) is fused into the last one.
     DCsr Eout;
     for (int i = 1; i <= N; ++i) {
@@ -773,7 +781,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.theta.push_back(S.sq_theta[i]);
         std::swap(P.T, P.Tnew);
         P.T.nnz = S.sq_kept[i];
-        if (keep && !last && i >= ck_off && (i - ck_off) % ck == 0) {
+        if (keep && !last && is_ckpt(i)) {
             P.ckpt_at.push_back(i);
             CHK(copy_csr(P, push_reuse(P.ckpt, P.ckpt_pool), P.T));
         }
@@ -860,7 +868,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         if (nnzH) HIPCHK(hipMemsetAsync(dH, 0, sizeof(double) * nnzH, st));
         return EXPM_OK;
     }
-    const int N = P.N, ck = P.ck;
+    const int N = P.N;
     // G_N on supp(T_N): E = I + T_N.  With reordering dE is first moved onto
     // the entries of E' (the pattern kept in Epat).
     Buf g, gn, dEp, dHp;
@@ -891,9 +899,14 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // come back, so their buffers keep their sizes from call to call.
     bool fwd_tiles = P.fwd_ts_ok && N >= 1;
     P.fwd_ts_ok = false;
+    int seg_max = 1;   // the longest checkpoint segment
+    for (size_t c = 0; c < P.ckpt_at.size(); ++c) {
+        const int nx = c + 1 < P.ckpt_at.size() ? P.ckpt_at[c + 1] : N;
+        seg_max = std::max(seg_max, nx - P.ckpt_at[c]);
+    }
     // The tiles the recomputation builds for each step's input are kept for
-    // that iterate's adjoint step when ck tile sets of the largest iterate
-    // take at most a quarter of the device memory.  The kept sets stay with
+    // that iterate's adjoint step when one segment's worth of tile sets of
+    // the largest iterate takes at most a quarter of the device memory.  The kept sets stay with
     // the plan, so later calls reuse their buffers.
     bool retain = false;
     {
@@ -901,12 +914,12 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         const size_t one = fwd_tiles ? P.fwd_ts.tA.bytes + P.fwd_ts.tB.bytes + P.fwd_ts.seg.bytes
                                      : 0;
         if (one > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess)
-            retain = (size_t)ck * one <= tot / 4;
+            retain = (size_t)seg_max * one <= tot / 4;
         (void)hipGetLastError();
     }
-    if ((int)P.kts.size() < ck) {
-        P.kts.resize(ck);
-        P.kts_ok.resize(ck);
+    if ((int)P.kts.size() < seg_max) {
+        P.kts.resize(seg_max);
+        P.kts_ok.resize(seg_max);
     }
     std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
     const DCsr *Tk = &P.TN;   // pattern of g
