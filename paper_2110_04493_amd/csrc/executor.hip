@@ -764,9 +764,15 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
                           st));
     CHK(sync(P));
     memcpy(&P.T.nnz, P.host, sizeof(int64_t));
+    // The current iterate; a checkpoint takes over P.T's buffers (no copy)
+    // and is read by the next squaring in place.
+    const DCsr *cur = &P.T;
     if (keep) {
+        P.ckpt.reserve(N + 1);
         P.ckpt_at.push_back(0);
-        CHK(copy_csr(P, push_reuse(P.ckpt, P.ckpt_pool), P.T));
+        DCsr &slot = push_reuse(P.ckpt, P.ckpt_pool);
+        std::swap(slot, P.T);
+        cur = &slot;
     }
     const int ck_off = N >= 1 ? (N - 1) % ck : 0;
     auto is_ckpt = [&](int i) {
@@ -777,17 +783,21 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     for (int i = 1; i <= N; ++i) {
         const double ri = ldexp(r0, i);
         const bool last = i == N;
-        CHK(square_step(P, P.T, P.Tnew, a * ri, false, 0.0, false, false, i, i));
+        CHK(square_step(P, *cur, P.Tnew, a * ri, false, 0.0, false, false, i, i));
         P.theta.push_back(S.sq_theta[i]);
         std::swap(P.T, P.Tnew);
         P.T.nnz = S.sq_kept[i];
+        cur = &P.T;
         if (keep && !last && is_ckpt(i)) {
             P.ckpt_at.push_back(i);
-            CHK(copy_csr(P, push_reuse(P.ckpt, P.ckpt_pool), P.T));
+            DCsr &slot = push_reuse(P.ckpt, P.ckpt_pool);
+            std::swap(slot, P.T);
+            cur = &slot;
         }
     }
     S.squarings = N;
-    if (keep) CHK(copy_csr(P, P.TN, P.T));
+    if (N == 0 && cur != &P.T) CHK(copy_csr(P, P.T, *cur));   // T_0 is also T_N
+    if (keep) std::swap(P.TN, P.T);   // T_N stays for the adjoint
     if (keep && N >= 1 && (int)P.sq_path.size() >= N && P.sq_path[N - 1]) {
         std::swap(P.tsT, P.fwd_ts);   // the tiles of T_{N-1}, input of the last product
         P.fwd_ts_ok = true;
@@ -795,13 +805,17 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     // E = I + T_N (exact zeros not stored)
     {
         // T_N becomes the candidate of the compaction (buffers handed over,
-        // not copied; P.T is rebuilt by the next call)
-        std::swap(P.crp, P.T.rp);
-        std::swap(P.cci, P.T.ci);
-        std::swap(P.cv, P.T.v);
+        // not copied, and handed back to P.TN after the write when kept)
+        DCsr &TNs = keep ? P.TN : P.T;
+        auto swap_cand = [&] {
+            std::swap(P.crp, TNs.rp);
+            std::swap(P.cci, TNs.ci);
+            std::swap(P.cv, TNs.v);
+        };
+        swap_cand();
         FilterCtl h{};
         int64_t kept;
-        CHK(filter_and_count(P, n, P.T.nnz, 0.0, nullptr, true, -1.0, true, &h, &kept));
+        CHK(filter_and_count(P, n, TNs.nnz, 0.0, nullptr, true, -1.0, true, &h, &kept));
         int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
         int32_t *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * kept);
         double *v = (double *)out_alloc(P, sizeof(double) * kept);
@@ -827,6 +841,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         HIPCHK(write_kept((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
                           (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, erp, eci, ev,
                           st));
+        if (keep) swap_cand();
         if (P.perm_active) {
             int64_t *em = nullptr;
             if (keep) {
