@@ -904,7 +904,8 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     CsrView Ev = CsrView{n, (const int64_t *)P.Epat.rp.p, (const int32_t *)P.Epat.ci.p, dEu};
     CHK(ensure(P, g, sizeof(double) * (P.TN.nnz + 1)));
     MaskTerm none{empty_view(), empty_view(), 0.0};
-    CHK(masked(P, P.TN.view(), Ev, 1.0, none, none, 1.0, (double *)g.p));
+    HIPCHK(values_at_t((const int64_t *)P.TN.rp.p, (const int32_t *)P.TN.ci.p, Ev.rp, Ev.v, n,
+                       (double *)g.p, st));
     // iterates of the current segment: seg[j] = T^_{base + j} (buffers kept
     // by the plan from call to call)
     std::vector<DCsr> &seg = P.seg_pool;

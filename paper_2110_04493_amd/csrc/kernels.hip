@@ -741,6 +741,31 @@ hipError_t sum_terms_write(const SumTerms &T, int64_t n, const int64_t *orp, int
     return hipGetLastError();
 }
 
+// Values of E = I + T (exact zeros dropped) at T's entries.  Row by row the
+// two patterns differ at most at the diagonal: E has one entry more when T
+// has no diagonal entry, one fewer when T's diagonal entry was -1.
+__global__ void k_values_at_t(const int64_t *trp, const int32_t *tci, const int64_t *erp,
+                              const double *ev, int64_t n, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const int64_t tb = trp[i], te = trp[i + 1], eb = erp[i];
+    const int64_t delta = (erp[i + 1] - eb) - (te - tb);   // +1, 0 or -1
+    for (int64_t q = tb + lane_id(); q < te; q += kWave) {
+        const int c = tci[q];
+        int64_t pos = q - tb;
+        if (delta != 0 && c > i) pos += delta;
+        out[q] = delta < 0 && c == i ? 0.0 : ev[eb + pos];
+    }
+}
+
+hipError_t values_at_t(const int64_t *trp, const int32_t *tci, const int64_t *erp,
+                       const double *ev, int64_t n, double *out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_values_at_t, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, trp, tci,
+                       erp, ev, n, out);
+    return hipGetLastError();
+}
+
 __global__ void k_identity(int64_t n, int64_t *rp, int32_t *ci, double *v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= n) rp[i] = i;

@@ -229,6 +229,11 @@ hipError_t sum_terms_count(const SumTerms &T, int64_t n, int64_t *cnt, int *over
                            hipStream_t st);
 hipError_t sum_terms_write(const SumTerms &T, int64_t n, const int64_t *orp, int32_t *oci,
                            double *ov, hipStream_t st);
+// out (aligned with T's entries) = the values of E = I + T (E as returned:
+// exact zeros dropped, so E's row differs from T's at most at the diagonal)
+// at T's entries; 0 where E dropped a diagonal entry.
+hipError_t values_at_t(const int64_t *trp, const int32_t *tci, const int64_t *erp,
+                       const double *ev, int64_t n, double *out, hipStream_t st);
 // Identity matrix rows.
 hipError_t fill_identity(int64_t n, int64_t *rp, int32_t *ci, double *v, hipStream_t st);
 
