@@ -12,9 +12,10 @@ Prints one JSON line.  `value` is the wall time of one step in seconds
 of the squarings: its launches are timed with HIP events on the library's
 stream inside the timed steps (profile mode 2: event pairs only, read after
 each call), and its algorithmic flops per launch come from untimed passes
-before them with the full profile (profile mode 1, which counts the partial
-products of every step and waits for the device after each step; the
-per-step table and phase times come from the second of those passes).  `cpu_baseline`
+after them, on a plan of their own, with the full profile (profile mode 1,
+which counts the partial products of every step and waits for the device
+after each step; the per-step table and phase times come from the second of
+those passes).  `cpu_baseline`
 times the CPU oracle on a bounded sample of the same workload family.
 """
 from __future__ import annotations
@@ -40,7 +41,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--side", type=int, default=300, help="grid side (300 -> n = 90,000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=150)
@@ -172,15 +173,11 @@ def main():
             plan.backward(dE, val.numel())
         return v.numel()
 
-    # Untimed passes with the full profile (phase timers and the
-    # algorithmic work of every squaring step, which needs a wait after each
-    # step); the timed steps then run with the tile kernel timers only.
-    pplan = api.Plan("cuda", api.Options(keep_checkpoints=not args.forward_only, profile=1))
-    for _ in range(2):   # the first call also grows the plan's workspace
-        step(pplan)
-    torch.cuda.synchronize()
-    pstats = pplan.stats()
-    pplan.close()
+    # The timed steps run with the tile kernel timers only; untimed passes
+    # with the full profile (phase timers and the algorithmic work of every
+    # squaring step, which needs a wait after each step) follow on a plan of
+    # their own.  The warmup calls also let the plan's workspace reach its
+    # steady size (buffers that trade roles grow over the first calls).
     plan = api.Plan("cuda", api.Options(keep_checkpoints=not args.forward_only, profile=2))
     for _ in range(args.warmup):
         step(plan)
@@ -204,6 +201,12 @@ def main():
     t_all = time.perf_counter() - t_all0
     plan.close()
     sec = t_all / args.steps
+    pplan = api.Plan("cuda", api.Options(keep_checkpoints=not args.forward_only, profile=1))
+    for _ in range(2):   # the first call also grows the plan's workspace
+        step(pplan)
+    torch.cuda.synchronize()
+    pstats = pplan.stats()
+    pplan.close()
 
     fl, by, tnum, per = numeric_roofline(pstats, n)
     tflops = fl / (tnum * 1e9)

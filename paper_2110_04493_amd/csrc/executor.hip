@@ -77,6 +77,43 @@ int ensure(expm_plan_s &P, Buf &b, size_t bytes) {
     return EXPM_OK;
 }
 
+// Buffers that trade places between roles (iterates and checkpoints, tile
+// sets) are grown to the largest size their roles need, once, so that
+// later calls allocate nothing: b is grown to ref's capacity when smaller.
+int reserve_as(expm_plan_s &P, Buf &b, const Buf &ref) {
+    if (b.bytes >= ref.bytes || ref.bytes == 0) return EXPM_OK;
+    if (b.p) {
+        HIPCHK(hipFreeAsync(b.p, P.st));
+        P.live -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (hipMallocAsync(&b.p, ref.bytes, P.st) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(EXPM_ENOMEM, "cannot allocate %zu bytes of device workspace", ref.bytes);
+    }
+    b.bytes = ref.bytes;
+    P.live += b.bytes;
+    P.peak = std::max(P.peak, P.live);
+    return EXPM_OK;
+}
+
+int reserve_as(expm_plan_s &P, DCsr &d, const DCsr &ref) {
+    CHK(reserve_as(P, d.rp, ref.rp));
+    CHK(reserve_as(P, d.ci, ref.ci));
+    return reserve_as(P, d.v, ref.v);
+}
+
+int reserve_as(expm_plan_s &P, TileSet &t, const TileSet &ref) {
+    Buf *a[] = {&t.lo, &t.words, &t.woff, &t.rt, &t.cnt, &t.tb, &t.tA, &t.tB, &t.cols, &t.rows,
+                &t.seg};
+    const Buf *r[] = {&ref.lo, &ref.words, &ref.woff, &ref.rt,   &ref.cnt, &ref.tb,
+                      &ref.tA, &ref.tB,    &ref.cols, &ref.rows, &ref.seg};
+    for (int j = 0; j < 11; ++j) CHK(reserve_as(P, *a[j], *r[j]));
+    return EXPM_OK;
+}
+
 void release(expm_plan_s &P, Buf &b) {
     if (b.p) {
         (void)hipFreeAsync(b.p, P.st);
@@ -622,6 +659,13 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     free_adjoint_state(P);
     P.fwd_ts_ok = false;
     memset(&P.stats, 0, sizeof P.stats);
+    // the iterate buffers that rotate through the checkpoints take the size
+    // of the last call's T_N (no effect on a first call)
+    if (P.opts.keep_checkpoints) {
+        CHK(reserve_as(P, P.T, P.TN));
+        CHK(reserve_as(P, P.Tnew, P.TN));
+        for (DCsr &A : P.ckpt_pool) CHK(reserve_as(P, A, P.TN));
+    }
     P.have_stats = false;
     P.perm_active = false;
     P.peak = P.live;
@@ -926,16 +970,32 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // the plan, so later calls reuse their buffers.
     bool retain = false;
     {
-        size_t fr = 0, tot = 0;
+        // the device's total memory, queried once per plan (a query of the
+        // free memory can stall while the driver reclaims another process's)
+        if (P.dev_mem == 0) {
+            int dev = 0;
+            size_t tot = 0;
+            if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&tot, dev) == hipSuccess)
+                P.dev_mem = tot;
+            (void)hipGetLastError();
+        }
         const size_t one = fwd_tiles ? P.fwd_ts.tA.bytes + P.fwd_ts.tB.bytes + P.fwd_ts.seg.bytes
                                      : 0;
-        if (one > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess)
-            retain = (size_t)seg_max * one <= tot / 4;
-        (void)hipGetLastError();
+        retain = one > 0 && (size_t)seg_max * one <= P.dev_mem / 4;
     }
     if ((int)P.kts.size() < seg_max) {
         P.kts.resize(seg_max);
         P.kts_ok.resize(seg_max);
+    }
+    // the tile sets that trade places below take the size of the largest
+    // iterate's (T_{N-1}'s, from the forward)
+    if (fwd_tiles) {
+        CHK(reserve_as(P, P.tsT, P.fwd_ts));
+        CHK(reserve_as(P, P.tsG, P.fwd_ts));
+        if (retain)
+            for (int j = 0; j < seg_max; ++j) CHK(reserve_as(P, P.kts[j], P.fwd_ts));
+        CHK(reserve_as(P, P.adj_tiles, P.fwd_ts.tB));
+        CHK(reserve_as(P, P.adj_tilesA, P.fwd_ts.tA));
     }
     std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
     const DCsr *Tk = &P.TN;   // pattern of g

@@ -72,6 +72,7 @@ struct expm_plan_s {
     // j - base), kept for the adjoint steps when they fit the memory budget
     std::vector<xpm::host::TileSet> kts;
     std::vector<char> kts_ok;
+    size_t dev_mem = 0;   // device memory in bytes (0: not queried yet)
     xpm::host::DCsr Epat;                       // pattern of the returned E
     std::vector<double> theta;       // squaring thresholds, 1..N
     bool zero_h = false;
@@ -139,6 +140,9 @@ AtExit<F> at_exit(F f) {
 double ms_since(std::chrono::steady_clock::time_point t0);
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int ensure(expm_plan_s &P, Buf &b, size_t bytes);
+int reserve_as(expm_plan_s &P, Buf &b, const Buf &ref);
+int reserve_as(expm_plan_s &P, DCsr &d, const DCsr &ref);
+int reserve_as(expm_plan_s &P, TileSet &t, const TileSet &ref);
 void release(expm_plan_s &P, Buf &b);
 void release(expm_plan_s &P, DCsr &A);
 int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz);

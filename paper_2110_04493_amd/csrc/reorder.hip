@@ -50,7 +50,7 @@ __device__ __forceinline__ long long wave_max_ll(long long x) {
 __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *srcp,
                                                      int32_t *dist, int32_t *q0, int32_t *q1,
                                                      const int32_t *other, int32_t *res) {
-    __shared__ int s_next, s_size;
+    __shared__ int s_cnt[3];   // rotating frontier sizes, as in k_bfs_lds
     __shared__ long long s_best[kBfsThreads / kWave];
     __shared__ int s_unreached;
     const int tid = threadIdx.x;
@@ -59,15 +59,16 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *s
         const int src = *srcp;
         atomicExch(&dist[src], 0);
         q0[0] = src;
-        s_size = 1;
-        s_next = 0;
+        s_cnt[0] = 1;
+        s_cnt[1] = 0;
+        s_cnt[2] = 0;
         s_unreached = 0;
     }
     __syncthreads();
-    int level = 0;
+    int level = 0, c0 = 0, c1 = 1, c2 = 2;
     int32_t *cur = q0, *nxt = q1;
     for (;;) {
-        const int size = s_size;
+        const int size = s_cnt[c0];
         if (size == 0) break;
         for (int i = tid; i < size; i += kBfsThreads) {
             const int v = cur[i];
@@ -75,15 +76,15 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *s
                 const int u = G.ci[p];
                 // a stale -1 only costs a failed compare-and-swap
                 if (dist[u] == -1 && atomicCAS(&dist[u], -1, level + 1) == -1)
-                    nxt[atomicAdd(&s_next, 1)] = u;
+                    nxt[atomicAdd(&s_cnt[c1], 1)] = u;
             }
         }
+        if (tid == 0) s_cnt[c2] = 0;
         __syncthreads();
-        if (tid == 0) {
-            s_size = s_next;
-            s_next = 0;
-        }
-        __syncthreads();
+        const int t0 = c0;
+        c0 = c1;
+        c1 = c2;
+        c2 = t0;
         int32_t *t = cur;
         cur = nxt;
         nxt = t;
@@ -125,7 +126,11 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_
                                                          int32_t *gq1, const int32_t *other,
                                                          int32_t *res) {
     extern __shared__ uint32_t sm[];
-    __shared__ int s_next, s_size, s_unreached;
+    // frontier sizes rotate through three counters, so that one barrier per
+    // level suffices: level L reads s_cnt[L % 3], counts the next frontier
+    // into s_cnt[(L + 1) % 3] and clears s_cnt[(L + 2) % 3], last read (as
+    // a size) before the previous level's barrier
+    __shared__ int s_cnt[3], s_unreached;
     __shared__ long long s_best[kBfsThreads / kWave];
     const int tid = threadIdx.x;
     const int64_t n = G.n;
@@ -139,15 +144,16 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_
         vis[src >> 5] |= 1u << (src & 31);
         dist[src] = 0;
         lq0[0] = src;
-        s_size = 1;
-        s_next = 0;
+        s_cnt[0] = 1;
+        s_cnt[1] = 0;
+        s_cnt[2] = 0;
         s_unreached = 0;
     }
     __syncthreads();
-    int level = 0;
+    int level = 0, c0 = 0, c1 = 1, c2 = 2;
     int32_t *lcur = lq0, *lnxt = lq1, *gcur = gq0, *gnxt = gq1;
     for (;;) {
-        const int size = s_size;
+        const int size = s_cnt[c0];
         if (size == 0) break;
         for (int i = tid; i < size; i += kBfsThreads) {
             const int v = i < kQCap ? lcur[i] : gcur[i];
@@ -157,16 +163,16 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_
                 if (vis[u >> 5] & bit) continue;
                 if (atomicOr(&vis[u >> 5], bit) & bit) continue;
                 dist[u] = level + 1;
-                const int pos = atomicAdd(&s_next, 1);
+                const int pos = atomicAdd(&s_cnt[c1], 1);
                 if (pos < kQCap) lnxt[pos] = u; else gnxt[pos] = u;
             }
         }
+        if (tid == 0) s_cnt[c2] = 0;
         __syncthreads();
-        if (tid == 0) {
-            s_size = s_next;
-            s_next = 0;
-        }
-        __syncthreads();
+        const int t0 = c0;
+        c0 = c1;
+        c1 = c2;
+        c2 = t0;
         int32_t *t = lcur;
         lcur = lnxt;
         lnxt = t;
