@@ -395,8 +395,9 @@ int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst) {
 }
 
 // dst = sum of the Taylor terms P.taylor in order (exact zeros removed): one
-// multi-term pass when every row fits the kernel's LDS slice, else the
-// terms added pairwise (the same sums in the same order).
+// multi-term pass (rows too wide for LDS in global scratch), or, past
+// kSumMaxTerms terms, the terms added pairwise (the same sums in the same
+// order).
 int sum_taylor(expm_plan_s &P, DCsr &dst) {
     const int m = (int)P.taylor.size();
     const int64_t n = P.taylor[0].n;
@@ -411,25 +412,34 @@ int sum_taylor(expm_plan_s &P, DCsr &dst) {
         T.m = m;
         CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
         CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
+        CHK(ensure(P, P.tmp2, sizeof(int64_t) * (n + 1)));
         CHK(ensure(P, P.flags, sizeof(int) * 4));
-        HIPCHK(hipMemsetAsync(P.flags.p, 0, sizeof(int), P.st));
-        HIPCHK(sum_terms_count(T, n, (int64_t *)P.cnt.p, (int *)P.flags.p, P.st));
-        CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
+        // global scratch of the rows too wide for LDS
+        int64_t *bytes = (int64_t *)P.tmp1.p, *goff = (int64_t *)P.tmp2.p;
+        HIPCHK(sum_terms_bounds(T, n, bytes, P.st));
+        CHK(scan(P, bytes, goff, n));
         int64_t *hl = (int64_t *)P.host;
+        HIPCHK(hipMemcpyAsync(hl, goff + n, sizeof(int64_t), hipMemcpyDeviceToHost, P.st));
+        CHK(sync(P));
+        CHK(ensure(P, P.scratch, (size_t)hl[0] + 256));
+        char *gscr = (char *)P.scratch.p;
+        HIPCHK(hipMemsetAsync(P.flags.p, 0, sizeof(int), P.st));
+        HIPCHK(sum_terms_count(T, n, gscr, goff, (int64_t *)P.cnt.p, (int *)P.flags.p, P.st));
+        CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
         HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.krp.p + n, sizeof(int64_t),
                               hipMemcpyDeviceToHost, P.st));
         HIPCHK(hipMemcpyAsync(hl + 1, P.flags.p, sizeof(int), hipMemcpyDeviceToHost, P.st));
         CHK(sync(P));
         const int64_t nnz = hl[0];
-        const int overflow = (int)(hl[1] & 0xffffffff);
-        if (!overflow) {
-            CHK(ensure_csr(P, dst, n, nnz));
-            HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1),
-                                  hipMemcpyDeviceToDevice, P.st));
-            HIPCHK(sum_terms_write(T, n, (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
-                                   (double *)dst.v.p, P.st));
-            return EXPM_OK;
-        }
+        if ((int)(hl[1] & 0xffffffff))
+            return fail(EXPM_EHIP, "Taylor sum: a row exceeded its working memory");
+        CHK(ensure_csr(P, dst, n, nnz));
+        HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1),
+                              hipMemcpyDeviceToDevice, P.st));
+        HIPCHK(sum_terms_write(T, n, gscr, goff, (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
+                               (double *)dst.v.p, P.st));
+        return EXPM_OK;
     }
     CHK(copy_csr(P, dst, P.taylor[0]));
     for (int t = 1; t < m; ++t) {

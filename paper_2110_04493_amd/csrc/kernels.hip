@@ -617,45 +617,79 @@ constexpr int kSumWaves = 4;      // rows per workgroup
 constexpr int kSumWords = 512;    // bit-map words per wave (16384 columns)
 constexpr int kSumAcc = 256;      // distinct columns per wave
 
+// Per row: the global scratch bytes a row needs when its column window or
+// its distinct-column bound (the sum of its term lengths) exceeds the LDS
+// slice, else 0.
+__global__ void k_sum_bounds(SumTerms T, int64_t n, int64_t *bytes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int mn = INT32_MAX, mx = -1;
+    int64_t ub = 0;
+    for (int t = 0; t < T.m; ++t) {
+        const int64_t b = T.rp[t][i], e = T.rp[t][i + 1];
+        if (e > b) {
+            mn = min(mn, T.ci[t][b]);
+            mx = max(mx, T.ci[t][e - 1]);
+            ub += e - b;
+        }
+    }
+    int64_t need = 0;
+    if (mx >= 0) {
+        const int64_t W = ((mx - (mn & ~31)) >> 5) + 1;
+        if (W > kSumWords || ub > kSumAcc) need = (8 * W + 12 * ub + 255) & ~int64_t(255);
+    }
+    bytes[i] = need;
+}
+
 template <bool kWrite>
 __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int64_t n,
                                                                   int64_t *cnt, int *overflow,
                                                                   const int64_t *orp,
-                                                                  int32_t *oci, double *ov) {
+                                                                  int32_t *oci, double *ov,
+                                                                  char *gscr,
+                                                                  const int64_t *goff) {
     __shared__ uint2 sbits[kSumWaves][kSumWords];
     __shared__ double sacc[kSumWaves][kSumAcc];
     __shared__ int32_t scol[kSumWaves][kSumAcc];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     const int64_t i = (int64_t)blockIdx.x * kSumWaves + wv;
     if (i >= n) return;
-    auto sync_wave = []() {
+    // rows too wide for the LDS slice work in their own global scratch
+    const bool big = goff[i + 1] > goff[i];
+    auto sync_wave = [big]() {
+        if (big) __threadfence();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
     };
     int mn = INT32_MAX, mx = -1;
+    int64_t ub = 0;
     if (lane < T.m) {
         const int64_t b = T.rp[lane][i], e = T.rp[lane][i + 1];
         if (e > b) {
             mn = T.ci[lane][b];
             mx = T.ci[lane][e - 1];
+            ub = e - b;
         }
     }
     mn = wave_min(mn);
     mx = wave_max(mx);
+    ub = wave_sum_ll(ub);
     if (mx < 0) {
         if (!kWrite && lane == 0) cnt[i] = 0;
         return;
     }
     const int lo = mn & ~31;
     const int W = ((mx - lo) >> 5) + 1;
-    if (W > kSumWords) {
+    if (!big && (W > kSumWords || ub > kSumAcc)) {   // bounds disagree: not summed
         if (!kWrite && lane == 0) {
             cnt[i] = 0;
             atomicOr(overflow, 1);
         }
         return;
     }
-    uint2 *bits = sbits[wv];
+    uint2 *bits = big ? (uint2 *)(gscr + goff[i]) : sbits[wv];
+    double *acc = big ? (double *)(bits + W) : sacc[wv];
+    int32_t *col = big ? (int32_t *)(acc + ub) : scol[wv];
     for (int w = lane; w < W; w += kWave) bits[w] = make_uint2(0u, 0u);
     sync_wave();
     for (int t = 0; t < T.m; ++t) {
@@ -675,15 +709,6 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
         carry += __shfl(inc, kWave - 1);
     }
     const int U = (int)carry;
-    if (U > kSumAcc) {
-        if (!kWrite && lane == 0) {
-            cnt[i] = 0;
-            atomicOr(overflow, 1);
-        }
-        return;
-    }
-    double *acc = sacc[wv];
-    int32_t *col = scol[wv];
     for (int r = lane; r < U; r += kWave) acc[r] = 0.0;
     sync_wave();
     auto rank = [&](int c) {
@@ -723,21 +748,29 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
     }
 }
 
-hipError_t sum_terms_count(const SumTerms &T, int64_t n, int64_t *cnt, int *overflow,
-                           hipStream_t st) {
+hipError_t sum_terms_bounds(const SumTerms &T, int64_t n, int64_t *bytes, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sum_terms<false>, dim3((unsigned)((n + kSumWaves - 1) / kSumWaves)),
-                       dim3(kWave * kSumWaves), 0, st, T, n, cnt, overflow,
-                       (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr);
+    hipLaunchKernelGGL(k_sum_bounds, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, T, n,
+                       bytes);
     return hipGetLastError();
 }
 
-hipError_t sum_terms_write(const SumTerms &T, int64_t n, const int64_t *orp, int32_t *oci,
-                           double *ov, hipStream_t st) {
+hipError_t sum_terms_count(const SumTerms &T, int64_t n, char *gscr, const int64_t *goff,
+                           int64_t *cnt, int *overflow, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_terms<false>, dim3((unsigned)((n + kSumWaves - 1) / kSumWaves)),
+                       dim3(kWave * kSumWaves), 0, st, T, n, cnt, overflow,
+                       (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, gscr,
+                       goff);
+    return hipGetLastError();
+}
+
+hipError_t sum_terms_write(const SumTerms &T, int64_t n, char *gscr, const int64_t *goff,
+                           const int64_t *orp, int32_t *oci, double *ov, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sum_terms<true>, dim3((unsigned)((n + kSumWaves - 1) / kSumWaves)),
                        dim3(kWave * kSumWaves), 0, st, T, n, (int64_t *)nullptr, (int *)nullptr,
-                       orp, oci, ov);
+                       orp, oci, ov, gscr, goff);
     return hipGetLastError();
 }
 

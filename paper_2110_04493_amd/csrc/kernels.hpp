@@ -215,9 +215,10 @@ hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, dou
 // T = S_1 + ... + S_m (m <= kSumMaxTerms terms of one n x n shape), summed
 // entry by entry in term order (bitwise what adding the terms one after
 // another gives) with exact zeros removed; two passes (count, then write).
-// A row whose column window or number of distinct columns exceeds the
-// kernel's LDS slice sets *overflow (count pass) and is not summed: the
-// caller then adds the terms pairwise instead.
+// Rows whose column window or distinct-column bound exceeds the kernel's
+// LDS slice work in global scratch: sum_terms_bounds gives each row's bytes
+// (0 for LDS rows), and goff is their exclusive scan (n + 1 entries).
+// *overflow is set if a row needed scratch it was not given.
 constexpr int kSumMaxTerms = 32;
 struct SumTerms {
     const int64_t *rp[kSumMaxTerms];
@@ -225,10 +226,11 @@ struct SumTerms {
     const double *v[kSumMaxTerms];
     int m;
 };
-hipError_t sum_terms_count(const SumTerms &T, int64_t n, int64_t *cnt, int *overflow,
-                           hipStream_t st);
-hipError_t sum_terms_write(const SumTerms &T, int64_t n, const int64_t *orp, int32_t *oci,
-                           double *ov, hipStream_t st);
+hipError_t sum_terms_bounds(const SumTerms &T, int64_t n, int64_t *bytes, hipStream_t st);
+hipError_t sum_terms_count(const SumTerms &T, int64_t n, char *gscr, const int64_t *goff,
+                           int64_t *cnt, int *overflow, hipStream_t st);
+hipError_t sum_terms_write(const SumTerms &T, int64_t n, char *gscr, const int64_t *goff,
+                           const int64_t *orp, int32_t *oci, double *ov, hipStream_t st);
 // out (aligned with T's entries) = the values of E = I + T (E as returned:
 // exact zeros dropped, so E's row differs from T's at most at the diagonal)
 // at T's entries; 0 where E dropped a diagonal entry.
