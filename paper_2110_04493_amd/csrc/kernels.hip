@@ -615,11 +615,18 @@ hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, dou
 // the other, and the nonzero sums are counted or written in column order.
 constexpr int kSumWaves = 4;      // rows per workgroup
 constexpr int kSumWords = 512;    // bit-map words per wave (16384 columns)
-constexpr int kSumAcc = 256;      // distinct columns per wave
+constexpr int kSumAcc = 256;      // distinct columns per wave (sparse rows)
+constexpr int kSumDense = 1024;   // column block of a dense row (8 KB of LDS)
+static_assert(kSumWords * 8 + kSumAcc * 12 <= kSumDense * 8, "sparse row slice fits");
 
-// Per row: the global scratch bytes a row needs when its column window or
-// its distinct-column bound (the sum of its term lengths) exceeds the LDS
-// slice, else 0.
+__device__ __forceinline__ int64_t readlane_i64_(int64_t x, int j) {
+    const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffff), j);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), j);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Per row: the global scratch bytes a row needs when its column window
+// exceeds the LDS bit map, else 0.
 __global__ void k_sum_bounds(SumTerms T, int64_t n, int64_t *bytes) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -636,7 +643,7 @@ __global__ void k_sum_bounds(SumTerms T, int64_t n, int64_t *bytes) {
     int64_t need = 0;
     if (mx >= 0) {
         const int64_t W = ((mx - (mn & ~31)) >> 5) + 1;
-        if (W > kSumWords || ub > kSumAcc) need = (8 * W + 12 * ub + 255) & ~int64_t(255);
+        if (W > kSumWords) need = (8 * W + 12 * ub + 255) & ~int64_t(255);
     }
     bytes[i] = need;
 }
@@ -648,13 +655,13 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
                                                                   int32_t *oci, double *ov,
                                                                   char *gscr,
                                                                   const int64_t *goff) {
-    __shared__ uint2 sbits[kSumWaves][kSumWords];
-    __shared__ double sacc[kSumWaves][kSumAcc];
-    __shared__ int32_t scol[kSumWaves][kSumAcc];
+    // one LDS slice per wave: the bit map, accumulator and columns of a
+    // sparse row, or the dense accumulator of a column block
+    __shared__ double slds[kSumWaves][kSumDense];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     const int64_t i = (int64_t)blockIdx.x * kSumWaves + wv;
     if (i >= n) return;
-    // rows too wide for the LDS slice work in their own global scratch
+    // rows too wide for the LDS bit map work in their own global scratch
     const bool big = goff[i + 1] > goff[i];
     auto sync_wave = [big]() {
         if (big) __threadfence();
@@ -680,16 +687,64 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
     }
     const int lo = mn & ~31;
     const int W = ((mx - lo) >> 5) + 1;
-    if (!big && (W > kSumWords || ub > kSumAcc)) {   // bounds disagree: not summed
+    if (!big && W > kSumWords) {   // the bounds disagree: not summed
         if (!kWrite && lane == 0) {
             cnt[i] = 0;
             atomicOr(overflow, 1);
         }
         return;
     }
-    uint2 *bits = big ? (uint2 *)(gscr + goff[i]) : sbits[wv];
-    double *acc = big ? (double *)(bits + W) : sacc[wv];
-    int32_t *col = big ? (int32_t *)(acc + ub) : scol[wv];
+    if (!big && ub > kSumAcc) {
+        // Many distinct columns in a narrow window: dense accumulation in
+        // blocks of kSumDense columns, each starting at the smallest column
+        // not yet taken (lane t < m keeps term t's position).
+        double *acc = slds[wv];
+        const int tl = lane < T.m ? lane : 0;   // in-range term index
+        int64_t cur = lane < T.m ? T.rp[tl][i] : 0;
+        const int64_t end = lane < T.m ? T.rp[tl][i + 1] : 0;
+        long long kept = 0;
+        int64_t o = kWrite ? orp[i] : 0;
+        for (;;) {
+            const int head = cur < end ? T.ci[tl][cur] : INT32_MAX;
+            const int c0 = wave_min(head);
+            if (c0 == INT32_MAX) break;
+            for (int r = lane; r < kSumDense; r += kWave) acc[r] = 0.0;
+            sync_wave();
+            for (int t = 0; t < T.m; ++t) {
+                int64_t b = readlane_i64_(cur, t);
+                const int64_t e = readlane_i64_(end, t);
+                for (;;) {
+                    const int64_t p = b + lane;
+                    const int c = p < e ? T.ci[t][p] : INT32_MAX;
+                    const bool in = (int64_t)c < (int64_t)c0 + kSumDense;
+                    if (in) acc[c - c0] += T.v[t][p];
+                    const int k = __popcll(__ballot(in));
+                    b += k;
+                    if (k < kWave) break;
+                }
+                if (lane == t) cur = b;
+                sync_wave();
+            }
+            for (int r0 = 0; r0 < kSumDense; r0 += kWave) {
+                const int r = r0 + lane;
+                const bool keep = acc[r] != 0.0;
+                const unsigned long long bm = __ballot(keep);
+                if (kWrite && keep) {
+                    const int64_t q = o + __popcll(bm & ((1ull << lane) - 1ull));
+                    oci[q] = c0 + r;
+                    ov[q] = acc[r];
+                }
+                o += __popcll(bm);
+                kept += __popcll(bm);
+            }
+            sync_wave();
+        }
+        if (!kWrite && lane == 0) cnt[i] = kept;
+        return;
+    }
+    uint2 *bits = big ? (uint2 *)(gscr + goff[i]) : (uint2 *)slds[wv];
+    double *acc = big ? (double *)(bits + W) : (double *)(bits + kSumWords);
+    int32_t *col = big ? (int32_t *)(acc + ub) : (int32_t *)(acc + kSumAcc);
     for (int w = lane; w < W; w += kWave) bits[w] = make_uint2(0u, 0u);
     sync_wave();
     for (int t = 0; t < T.m; ++t) {

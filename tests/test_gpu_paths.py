@@ -128,3 +128,24 @@ def test_wide_rows_taylor_sum(adjoint):
     print(f"[wide rows] M={sg['M']} N={sg['N']} terms={sg['taylor_terms']} relF={rel:.2e}",
           flush=True)
     assert rel <= TOL and ok
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_dense_rows_taylor_sum(adjoint):
+    """A random matrix whose Taylor seed has rows of several hundred
+    distinct columns in a narrow window: the multi-term sum accumulates
+    those rows densely, block by block."""
+    H, eps = W.random_sparse(700, 0.012, 21, kind="general", scale=2.0), 1e-12
+    if adjoint:
+        dg, _ = gpu_grad(H, eps, density=0.05)
+        do, _ = oracle_grad(H, eps, density=0.05)
+        rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+        print(f"[dense rows] adjoint rel={rel:.2e}", flush=True)
+        assert rel <= TOL
+        return
+    Eg, sg = run_gpu(H, eps)
+    Eo, so = run_oracle(H, eps)
+    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
+    print(f"[dense rows] M={sg['M']} N={sg['N']} terms={sg['taylor_terms']} "
+          f"nnz(E)/n={Eg.nnz / H.n:.0f} relF={rel:.2e}", flush=True)
+    assert rel <= TOL and ok
