@@ -667,7 +667,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     hipStream_t st = P.st;
     const int64_t n = Hv->n, nnz = Hv->nnz;
     free_adjoint_state(P);
-    P.fwd_ts_ok = false;
+    std::fill(P.cts_ok.begin(), P.cts_ok.end(), 0);
     memset(&P.stats, 0, sizeof P.stats);
     // the iterate buffers that rotate through the checkpoints take the size
     // of the last call's T_N (no effect on a first call)
@@ -834,28 +834,49 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     };
     // Step 4: squarings.  Step 5 (E = I + T_N) is fused into the last one.
     DCsr Eout;
+    if (keep && (int)P.cts.size() < N + 1) {
+        P.cts.resize(N + 1);
+        P.cts_ok.resize(N + 1, 0);
+    }
+    // tile sets of the checkpoints other than T_{N-1} are kept while their
+    // total stays within an eighth of the device memory
+    if (P.dev_mem == 0) {
+        int dev = 0;
+        size_t tot = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&tot, dev) == hipSuccess)
+            P.dev_mem = tot;
+        (void)hipGetLastError();
+    }
+    size_t kept_tiles = 0;
+    int cur_ck = keep ? 0 : -1;   // checkpoint index of *cur, or -1
     for (int i = 1; i <= N; ++i) {
         const double ri = ldexp(r0, i);
         const bool last = i == N;
         CHK(square_step(P, *cur, P.Tnew, a * ri, false, 0.0, false, false, i, i));
+        if (cur_ck >= 0 && P.sq_path[i - 1]) {   // P.tsT holds the checkpoint's tiles
+            const size_t b = P.tsT.tA.bytes + P.tsT.tB.bytes + P.tsT.seg.bytes;
+            if (last || kept_tiles + b <= P.dev_mem / 8) {
+                std::swap(P.tsT, P.cts[cur_ck]);
+                P.cts_ok[cur_ck] = 1;
+                kept_tiles += b;
+            }
+        }
         P.theta.push_back(S.sq_theta[i]);
         std::swap(P.T, P.Tnew);
         P.T.nnz = S.sq_kept[i];
         cur = &P.T;
+        cur_ck = -1;
         if (keep && !last && is_ckpt(i)) {
             P.ckpt_at.push_back(i);
             DCsr &slot = push_reuse(P.ckpt, P.ckpt_pool);
             std::swap(slot, P.T);
             cur = &slot;
+            cur_ck = (int)P.ckpt.size() - 1;
         }
     }
     S.squarings = N;
     if (N == 0 && cur != &P.T) CHK(copy_csr(P, P.T, *cur));   // T_0 is also T_N
     if (keep) std::swap(P.TN, P.T);   // T_N stays for the adjoint
-    if (keep && N >= 1 && (int)P.sq_path.size() >= N && P.sq_path[N - 1]) {
-        std::swap(P.tsT, P.fwd_ts);   // the tiles of T_{N-1}, input of the last product
-        P.fwd_ts_ok = true;
-    }
     // E = I + T_N (exact zeros not stored)
     {
         // T_N becomes the candidate of the compaction (buffers handed over,
@@ -967,8 +988,12 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // T^_{N-1}'s tiles from the forward's last product serve the first
     // adjoint step (the largest iterate).  The tile sets trade places and
     // come back, so their buffers keep their sizes from call to call.
-    bool fwd_tiles = P.fwd_ts_ok && N >= 1;
-    P.fwd_ts_ok = false;
+    // the largest kept tile set (T_{N-1}'s, the last checkpoint's), the
+    // size every rotating tile set below grows to
+    const int lastc = (int)P.ckpt_at.size() - 1;
+    const bool fwd_tiles = N >= 1 && lastc >= 0 && lastc < (int)P.cts_ok.size() &&
+                           P.cts_ok[lastc] && P.ckpt_at[lastc] == N - 1;
+    const TileSet *big_ts = fwd_tiles ? &P.cts[lastc] : nullptr;
     int seg_max = 1;   // the longest checkpoint segment
     for (size_t c = 0; c < P.ckpt_at.size(); ++c) {
         const int nx = c + 1 < P.ckpt_at.size() ? P.ckpt_at[c + 1] : N;
@@ -989,7 +1014,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
                 P.dev_mem = tot;
             (void)hipGetLastError();
         }
-        const size_t one = fwd_tiles ? P.fwd_ts.tA.bytes + P.fwd_ts.tB.bytes + P.fwd_ts.seg.bytes
+        const size_t one = fwd_tiles ? big_ts->tA.bytes + big_ts->tB.bytes + big_ts->seg.bytes
                                      : 0;
         retain = one > 0 && (size_t)seg_max * one <= P.dev_mem / 4;
     }
@@ -1000,12 +1025,13 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // the tile sets that trade places below take the size of the largest
     // iterate's (T_{N-1}'s, from the forward)
     if (fwd_tiles) {
-        CHK(reserve_as(P, P.tsT, P.fwd_ts));
-        CHK(reserve_as(P, P.tsG, P.fwd_ts));
+        const TileSet ref = *big_ts;   // sizes only
+        CHK(reserve_as(P, P.tsT, ref));
+        CHK(reserve_as(P, P.tsG, ref));
         if (retain)
-            for (int j = 0; j < seg_max; ++j) CHK(reserve_as(P, P.kts[j], P.fwd_ts));
-        CHK(reserve_as(P, P.adj_tiles, P.fwd_ts.tB));
-        CHK(reserve_as(P, P.adj_tilesA, P.fwd_ts.tA));
+            for (int j = 0; j < seg_max; ++j) CHK(reserve_as(P, P.kts[j], ref));
+        CHK(reserve_as(P, P.adj_tiles, ref.tB));
+        CHK(reserve_as(P, P.adj_tilesA, ref.tA));
     }
     std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
     const DCsr *Tk = &P.TN;   // pattern of g
@@ -1049,8 +1075,9 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         bool have_pattern = false, t_ready = false;
         if (tiles) {
             const int pos = km1 - base;
-            if (k == N && fwd_tiles) {
-                std::swap(P.tsT, P.fwd_ts);
+            if (km1 == base && ci < (int)P.cts_ok.size() && P.cts_ok[ci]) {
+                std::swap(P.tsT, P.cts[ci]);   // kept by the forward
+                P.cts_ok[ci] = 0;
                 t_ready = true;
             } else if (seg_base == base && pos < (int)P.kts_ok.size() && P.kts_ok[pos]) {
                 std::swap(P.tsT, P.kts[pos]);
@@ -1092,6 +1119,15 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     }
     if (g_stale)
         CHK(gather_tiles(P, *Tk, P.tsG, (const double *)P.tsG.tB.p, (double *)g.p));
+    // The checkpoints' tile sets trade places with P.tsT in the next forward:
+    // they take its size now (they are all free), within the same budget
+    // as the kept tiles, so that later calls allocate nothing.
+    if (fwd_tiles) {
+        const size_t one = P.tsT.tA.bytes + P.tsT.tB.bytes + P.tsT.seg.bytes;
+        if ((size_t)P.ckpt_at.size() * one <= P.dev_mem / 8)
+            for (size_t c = 0; c < P.ckpt_at.size() && c < P.cts.size(); ++c)
+                CHK(reserve_as(P, P.cts[c], P.tsT));
+    }
     // Taylor seed: g is dL/dT^_0 on supp(T^_0) = P.ckpt[0].
     const int Mp = (int)P.taylor.size();
     CsrView G0 = CsrView{n, (const int64_t *)P.ckpt[0].rp.p, (const int32_t *)P.ckpt[0].ci.p,
@@ -1296,7 +1332,7 @@ void expm_free(expm_plan_t p) {
     for (Buf *b : rbufs) release(P, *b);
     release(P, P.tsT);
     release(P, P.tsG);
-    release(P, P.fwd_ts);
+    for (TileSet &ts : P.cts) release(P, ts);
     for (TileSet &ts : P.kts) release(P, ts);
     DCsr *mats[] = {&P.H0, &P.S,  &P.Snew, &P.T,     &P.Tnew,
                     &P.Hpat_t, &P.Hp, &P.Eperm, &P.TN, &P.Epat};

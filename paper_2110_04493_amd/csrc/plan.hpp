@@ -64,10 +64,12 @@ struct expm_plan_s {
     std::vector<xpm::host::DCsr> taylor_pool, ckpt_pool, seg_pool;
     std::vector<int> ckpt_at;                   // 0, then every ck back from N - 1
     xpm::host::DCsr TN;                         // T^_N
-    // T^_{N-1} as tiles (pattern and both layouts) when the last squaring ran
-    // on tiles: the first adjoint step needs exactly these
-    xpm::host::TileSet fwd_ts;
-    bool fwd_ts_ok = false;
+    // checkpoint j's iterate as tiles (pattern and both layouts), kept from
+    // the forward product that took it as input, for that iterate's adjoint
+    // step (T^_{N-1}, the largest, always when the last squaring ran on
+    // tiles; the others within a memory budget)
+    std::vector<xpm::host::TileSet> cts;
+    std::vector<char> cts_ok;
     // the recomputed iterates of one checkpoint segment as tiles (position
     // j - base), kept for the adjoint steps when they fit the memory budget
     std::vector<xpm::host::TileSet> kts;
