@@ -985,55 +985,19 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // by the plan from call to call)
     std::vector<DCsr> &seg = P.seg_pool;
     int seg_base = -1;
-    // T^_{N-1}'s tiles from the forward's last product serve the first
-    // adjoint step (the largest iterate).  The tile sets trade places and
-    // come back, so their buffers keep their sizes from call to call.
-    // the largest kept tile set (T_{N-1}'s, the last checkpoint's), the
-    // size every rotating tile set below grows to
+    // The forward kept the tiles of the checkpoint iterates it multiplied
+    // (T^_{N-1}'s, the largest, always); the tile sets that trade places
+    // below take that size once, so later calls allocate nothing.
     const int lastc = (int)P.ckpt_at.size() - 1;
     const bool fwd_tiles = N >= 1 && lastc >= 0 && lastc < (int)P.cts_ok.size() &&
                            P.cts_ok[lastc] && P.ckpt_at[lastc] == N - 1;
-    const TileSet *big_ts = fwd_tiles ? &P.cts[lastc] : nullptr;
-    int seg_max = 1;   // the longest checkpoint segment
-    for (size_t c = 0; c < P.ckpt_at.size(); ++c) {
-        const int nx = c + 1 < P.ckpt_at.size() ? P.ckpt_at[c + 1] : N;
-        seg_max = std::max(seg_max, nx - P.ckpt_at[c]);
-    }
-    // The tiles the recomputation builds for each step's input are kept for
-    // that iterate's adjoint step when one segment's worth of tile sets of
-    // the largest iterate takes at most a quarter of the device memory.  The kept sets stay with
-    // the plan, so later calls reuse their buffers.
-    bool retain = false;
-    {
-        // the device's total memory, queried once per plan (a query of the
-        // free memory can stall while the driver reclaims another process's)
-        if (P.dev_mem == 0) {
-            int dev = 0;
-            size_t tot = 0;
-            if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&tot, dev) == hipSuccess)
-                P.dev_mem = tot;
-            (void)hipGetLastError();
-        }
-        const size_t one = fwd_tiles ? big_ts->tA.bytes + big_ts->tB.bytes + big_ts->seg.bytes
-                                     : 0;
-        retain = one > 0 && (size_t)seg_max * one <= P.dev_mem / 4;
-    }
-    if ((int)P.kts.size() < seg_max) {
-        P.kts.resize(seg_max);
-        P.kts_ok.resize(seg_max);
-    }
-    // the tile sets that trade places below take the size of the largest
-    // iterate's (T_{N-1}'s, from the forward)
     if (fwd_tiles) {
-        const TileSet ref = *big_ts;   // sizes only
+        const TileSet ref = P.cts[lastc];   // sizes only
         CHK(reserve_as(P, P.tsT, ref));
         CHK(reserve_as(P, P.tsG, ref));
-        if (retain)
-            for (int j = 0; j < seg_max; ++j) CHK(reserve_as(P, P.kts[j], ref));
         CHK(reserve_as(P, P.adj_tiles, ref.tB));
         CHK(reserve_as(P, P.adj_tilesA, ref.tA));
     }
-    std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
     const DCsr *Tk = &P.TN;   // pattern of g
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     bool g_tiles = false;     // ... and g's values as tiles
@@ -1053,16 +1017,10 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
             if (seg_base != base) {
                 if ((int)seg.size() < next - base) seg.resize(next - base);
                 seg_base = base;
-                std::fill(P.kts_ok.begin(), P.kts_ok.end(), 0);
                 const DCsr *prev = &P.ckpt[ci];
                 for (int j = base + 1; j <= std::min(next - 1, N - 1); ++j) {
                     CHK(square_step(P, *prev, seg[j - base], 0.0, true, P.theta[j - 1], false,
                                     false, 0, j));
-                    const int pos = j - 1 - base;   // P.tsT holds T_{j-1}'s tiles
-                    if (retain && P.sq_path[j - 1] && pos < (int)P.kts.size()) {
-                        std::swap(P.tsT, P.kts[pos]);
-                        P.kts_ok[pos] = 1;
-                    }
                     prev = &seg[j - base];
                 }
             }
@@ -1074,14 +1032,9 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         const bool tiles = (int)P.sq_path.size() >= k && P.sq_path[k - 1] != 0;
         bool have_pattern = false, t_ready = false;
         if (tiles) {
-            const int pos = km1 - base;
             if (km1 == base && ci < (int)P.cts_ok.size() && P.cts_ok[ci]) {
                 std::swap(P.tsT, P.cts[ci]);   // kept by the forward
                 P.cts_ok[ci] = 0;
-                t_ready = true;
-            } else if (seg_base == base && pos < (int)P.kts_ok.size() && P.kts_ok[pos]) {
-                std::swap(P.tsT, P.kts[pos]);
-                P.kts_ok[pos] = 0;
                 t_ready = true;
             } else {
                 double fill = 0.0;
@@ -1333,7 +1286,6 @@ void expm_free(expm_plan_t p) {
     release(P, P.tsT);
     release(P, P.tsG);
     for (TileSet &ts : P.cts) release(P, ts);
-    for (TileSet &ts : P.kts) release(P, ts);
     DCsr *mats[] = {&P.H0, &P.S,  &P.Snew, &P.T,     &P.Tnew,
                     &P.Hpat_t, &P.Hp, &P.Eperm, &P.TN, &P.Epat};
     for (DCsr *m : mats) release(P, *m);

@@ -70,10 +70,6 @@ struct expm_plan_s {
     // tiles; the others within a memory budget)
     std::vector<xpm::host::TileSet> cts;
     std::vector<char> cts_ok;
-    // the recomputed iterates of one checkpoint segment as tiles (position
-    // j - base), kept for the adjoint steps when they fit the memory budget
-    std::vector<xpm::host::TileSet> kts;
-    std::vector<char> kts_ok;
     size_t dev_mem = 0;   // device memory in bytes (0: not queried yet)
     xpm::host::DCsr Epat;                       // pattern of the returned E
     std::vector<double> theta;       // squaring thresholds, 1..N
