@@ -465,6 +465,23 @@ int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst) {
     return EXPM_OK;
 }
 
+// dst: A's transposed pattern; its value array holds, for every entry, the
+// position (int64) of the same entry in A.
+int transpose_pos(expm_plan_s &P, const DCsr &A, DCsr &dst) {
+    const int64_t n = A.n;
+    CHK(ensure_csr(P, dst, n, A.nnz));
+    CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.tmp2, sizeof(int64_t) * (n + 1)));
+    CHK(ensure(P, P.cci, sizeof(int32_t) * A.nnz));
+    CHK(ensure(P, P.cv, sizeof(int64_t) * A.nnz));
+    CHK(ensure(P, P.scan_tmp, scan_tmp_bytes(n)));
+    HIPCHK(transpose_index(A.view(), A.nnz, (int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
+                           (int64_t *)dst.v.p, (int64_t *)P.tmp1.p, (int64_t *)P.tmp2.p,
+                           (int32_t *)P.cci.p, (int64_t *)P.cv.p, P.scan_tmp.p,
+                           P.scan_tmp.bytes, P.st));
+    return EXPM_OK;
+}
+
 // Masked products on the mask's pattern (see masked_products).  The scratch
 // for rows whose working set exceeds LDS is sized by a first call and the
 // call is repeated once with enough room.
@@ -962,12 +979,12 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     // G_N on supp(T_N): E = I + T_N.  With reordering dE is first moved onto
     // the entries of E' (the pattern kept in Epat).
     Buf g, gn, dEp, dHp;
-    DCsr Tt, H0t, St;
+    DCsr Tt, H0t, St, Snt;
     Buf acc, acc2;
     std::vector<Buf> D;
     auto free_locals = at_exit([&] {
         for (Buf *b : {&g, &gn, &dEp, &dHp, &acc, &acc2}) release(P, *b);
-        for (DCsr *m : {&Tt, &H0t, &St}) release(P, *m);
+        for (DCsr *m : {&Tt, &H0t, &St, &Snt}) release(P, *m);
         for (auto &b : D) release(P, b);
     });
     const double *dEu = dE;
@@ -1093,6 +1110,12 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     CHK(ensure(P, acc, sizeof(double) * (nnzH + 1)));
     CHK(ensure(P, acc2, sizeof(double) * (nnzH + 1)));
     if (nnzH) HIPCHK(hipMemsetAsync(acc.p, 0, sizeof(double) * nnzH, st));
+    // acc accumulates sum_i (S^_i^T D_{i+1}) / (i+1) on H's pattern.  Each of
+    // its entries is an inner product of a column of S^_i with a column of
+    // D_{i+1} (whose pattern is that of S^_{i+1}), so both terms are taken
+    // by columns: St and Snt hold the transposed patterns of S^_i and
+    // S^_{i+1} with the positions of their entries in the untransposed ones.
+    if (Mp >= 2) CHK(transpose_pos(P, P.taylor[Mp - 1], Snt));
     for (int i = Mp - 1; i >= 1; --i) {
         const DCsr &Si = P.taylor[i - 1], &Sn = P.taylor[i];
         CsrView Dn = CsrView{n, (const int64_t *)Sn.rp.p, (const int32_t *)Sn.ci.p,
@@ -1100,13 +1123,15 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         CHK(ensure(P, D[i], sizeof(double) * (Si.nnz + 1)));
         MaskTerm t1{Dn, H0t.view(), 1.0};
         CHK(masked(P, Si.view(), G0, 1.0, t1, none, (double)(i + 1), (double *)D[i].p));
-        CHK(transpose_csr(P, Si, St));
-        MaskTerm t3{St.view(), Dn, 1.0};
-        CsrView accv = CsrView{n, (const int64_t *)P.H0.rp.p, (const int32_t *)P.H0.ci.p,
-                               (const double *)acc.p};
-        CHK(masked(P, P.H0.view(), accv, 1.0, t3, none, (double)(i + 1),
-                   (double *)acc2.p));
+        CHK(transpose_pos(P, Si, St));
+        const PosCsr a{(const int64_t *)St.rp.p, (const int32_t *)St.ci.p,
+                       (const int64_t *)St.v.p, (const double *)Si.v.p};
+        const PosCsr bt{(const int64_t *)Snt.rp.p, (const int32_t *)Snt.ci.p,
+                        (const int64_t *)Snt.v.p, (const double *)D[i + 1].p};
+        HIPCHK(masked_dot(P.H0.view(), (const double *)acc.p, a, bt, (double)(i + 1),
+                          (double *)acc2.p, st));
         std::swap(acc, acc2);
+        std::swap(St, Snt);
     }
     // dH = 2^-N (acc + D_1); S^_1 = H0 shares H's pattern (H' with reordering,
     // whose entries hmap sends back to H's).
@@ -1129,6 +1154,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     release(P, Tt);
     release(P, H0t);
     release(P, St);
+    release(P, Snt);
     CHK(sync(P));
     return EXPM_OK;
 }

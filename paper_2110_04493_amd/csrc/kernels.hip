@@ -7,6 +7,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace xpm {
 
 // ============================================================== scan
@@ -879,13 +881,19 @@ __global__ void k_colcount(CsrView A, int64_t nnz, int64_t *colcnt) {
         atomicAdd((unsigned long long *)&colcnt[A.ci[p]], 1ull);
 }
 
-__global__ void k_colfill(CsrView A, int64_t *fillpos, int32_t *tci, double *tv) {
+// The payload of each transposed entry: its value (V = double) or its
+// position in A (V = int64_t).
+template <typename V>
+__global__ void k_colfill(CsrView A, int64_t *fillpos, int32_t *tci, V *tv) {
     int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (i >= A.n) return;
     for (int64_t p = A.rp[i] + lane_id(); p < A.rp[i + 1]; p += kWave) {
         int64_t d = (int64_t)atomicAdd((unsigned long long *)&fillpos[A.ci[p]], 1ull);
         tci[d] = (int32_t)i;
-        tv[d] = A.v[p];
+        if constexpr (std::is_same<V, double>::value)
+            tv[d] = A.v[p];
+        else
+            tv[d] = p;
     }
 }
 
@@ -895,9 +903,10 @@ __global__ void k_colfill(CsrView A, int64_t *fillpos, int32_t *tci, double *tv)
 // memory.
 constexpr int kRankLds = 1024;
 
+template <typename V>
 __global__ __launch_bounds__(256) void k_rank_rows(const int64_t *rp, int64_t n,
-                                                   const int32_t *uci, const double *uv,
-                                                   int32_t *ci, double *v) {
+                                                   const int32_t *uci, const V *uv,
+                                                   int32_t *ci, V *v) {
     __shared__ int32_t skey[4][kRankLds];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     const int64_t i = (int64_t)blockIdx.x * 4 + wv;
@@ -926,9 +935,10 @@ __global__ __launch_bounds__(256) void k_rank_rows(const int64_t *rp, int64_t n,
     }
 }
 
-hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double *tv,
-                     int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, double *tmp_v,
-                     void *scan_tmp, size_t scan_tmp_bytes_, hipStream_t st) {
+template <typename V>
+static hipError_t transpose_t(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, V *tv,
+                              int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, V *tmp_v,
+                              void *scan_tmp, size_t scan_tmp_bytes_, hipStream_t st) {
     int64_t n = A.n;
     hipError_t e = hipMemsetAsync(colcnt, 0, sizeof(int64_t) * (n > 0 ? n : 1), st);
     if (e != hipSuccess || n == 0) {
@@ -943,10 +953,24 @@ hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double 
     e = hipMemcpyAsync(fillpos, trp, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
     // unsorted rows into the scratch arrays, then each entry to its rank
-    hipLaunchKernelGGL(k_colfill, g, b, 0, st, A, fillpos, tmp_ci, tmp_v);
-    hipLaunchKernelGGL(k_rank_rows, dim3((n + 3) / 4), dim3(256), 0, st, trp, n, tmp_ci, tmp_v,
-                       tci, tv);
+    hipLaunchKernelGGL(k_colfill<V>, g, b, 0, st, A, fillpos, tmp_ci, tmp_v);
+    hipLaunchKernelGGL(k_rank_rows<V>, dim3((n + 3) / 4), dim3(256), 0, st, trp, n, tmp_ci,
+                       tmp_v, tci, tv);
     return hipGetLastError();
+}
+
+hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double *tv,
+                     int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, double *tmp_v,
+                     void *scan_tmp, size_t scan_tmp_bytes_, hipStream_t st) {
+    return transpose_t<double>(A, nnz, trp, tci, tv, colcnt, fillpos, tmp_ci, tmp_v, scan_tmp,
+                               scan_tmp_bytes_, st);
+}
+
+hipError_t transpose_index(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, int64_t *tpos,
+                           int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, int64_t *tmp_pos,
+                           void *scan_tmp, size_t scan_tmp_bytes_, hipStream_t st) {
+    return transpose_t<int64_t>(A, nnz, trp, tci, tpos, colcnt, fillpos, tmp_ci, tmp_pos,
+                                scan_tmp, scan_tmp_bytes_, st);
 }
 
 }  // namespace xpm

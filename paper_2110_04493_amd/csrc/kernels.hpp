@@ -245,6 +245,11 @@ hipError_t fill_identity(int64_t n, int64_t *rp, int32_t *ci, double *v, hipStre
 hipError_t transpose(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, double *tv,
                      int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, double *tmp_v,
                      void *scan_tmp, size_t scan_tmp_bytes, hipStream_t st);
+// The transposed pattern with, in place of values, the position in A of
+// every transposed entry (tpos / tmp_pos: nnz int64 each).
+hipError_t transpose_index(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, int64_t *tpos,
+                           int64_t *colcnt, int64_t *fillpos, int32_t *tmp_ci, int64_t *tmp_pos,
+                           void *scan_tmp, size_t scan_tmp_bytes, hipStream_t st);
 
 // ------------------------------------------------------------- masked products
 // out[e] (aligned with the stored entries of mask M) =
@@ -260,5 +265,18 @@ size_t masked_meta_bytes(int64_t n);
 hipError_t masked_products(CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2,
                            double div, double *out, void *scratch, size_t scratch_bytes,
                            size_t *needed, hipStream_t st);
+// The same for one product whose left factor's rows and right factor's
+// columns are both at hand, as inner products: for (r, c) in supp(M),
+//   out[e] = (sum_k A(r,k) B(k,c)) / div + dv[e].
+// A by rows: rp/ci of A, the value of entry p being av[apos[p]]; B by
+// columns: rp/ci of B^T, the value of entry p being bv[bpos[p]].
+struct PosCsr {
+    const int64_t *rp;
+    const int32_t *ci;
+    const int64_t *pos;
+    const double *v;
+};
+hipError_t masked_dot(CsrView M, const double *dv, PosCsr A, PosCsr Bt, double div, double *out,
+                      hipStream_t st);
 
 }  // namespace xpm

@@ -160,6 +160,7 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
 int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst);
 int sum_taylor(expm_plan_s &P, DCsr &dst);
 int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
+int transpose_pos(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
 int check_view(const expm_csr_cview *H);
 void free_adjoint_state(expm_plan_s &P);

@@ -622,6 +622,72 @@ __global__ __launch_bounds__(512) void k_masked(
     for (int64_t t = lane; t < c; t += kWave) out[o + t] = acc[t];
 }
 
+// Inner-product form of a single masked product: one wave per row r of M.
+// A's row r (its column keys and values) is staged in LDS; for every
+// column c of M's row, the lanes take the entries of B's column c and find
+// their row index among A's keys by binary search.  Each lane accumulates
+// its own products and a fixed butterfly adds the lanes, so the result is
+// reproducible.  Rows of A longer than the LDS stage are searched in memory.
+constexpr int kDotWaves = 4, kDotLds = 512;
+
+__global__ __launch_bounds__(kWave * kDotWaves) void k_masked_dot(
+    CsrView M, const double *__restrict__ dv, PosCsr A, PosCsr Bt, double div,
+    double *__restrict__ out) {
+    __shared__ int32_t skey[kDotWaves][kDotLds];
+    __shared__ double sval[kDotWaves][kDotLds];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    const int64_t r = (int64_t)blockIdx.x * kDotWaves + wv;
+    if (r >= M.n) return;
+    const int64_t mo = M.rp[r], ml = M.rp[r + 1] - mo;
+    if (ml == 0) return;
+    const int64_t ao = A.rp[r], al = A.rp[r + 1] - ao;
+    const bool staged = al <= kDotLds;
+    int32_t *key = skey[wv];
+    double *val = sval[wv];
+    if (staged) {
+        for (int64_t t = lane; t < al; t += kWave) {
+            key[t] = A.ci[ao + t];
+            val[t] = A.v[A.pos[ao + t]];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int64_t t = 0; t < ml; ++t) {
+        const int32_t c = M.ci[mo + t];
+        double s = 0.0;
+        if (al > 0) {
+            for (int64_t p = Bt.rp[c] + lane; p < Bt.rp[c + 1]; p += kWave) {
+                const int32_t k = Bt.ci[p];
+                int64_t lo = 0, hi = al;
+                if (staged) {
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi) >> 1;
+                        if (key[mid] < k) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo < al && key[lo] == k) s += val[lo] * Bt.v[Bt.pos[p]];
+                } else {
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi) >> 1;
+                        if (A.ci[ao + mid] < k) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo < al && A.ci[ao + lo] == k)
+                        s += A.v[A.pos[ao + lo]] * Bt.v[Bt.pos[p]];
+                }
+            }
+        }
+        s = wave_sum(s);
+        if (lane == 0) out[mo + t] = s / div + dv[mo + t];
+    }
+}
+
+hipError_t masked_dot(CsrView M, const double *dv, PosCsr A, PosCsr Bt, double div, double *out,
+                      hipStream_t st) {
+    if (M.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_masked_dot, dim3((unsigned)((M.n + kDotWaves - 1) / kDotWaves)),
+                       dim3(kWave * kDotWaves), 0, st, M, dv, A, Bt, div, out);
+    return hipGetLastError();
+}
+
 __global__ void k_masked_bin(CsrView M, Caps caps, int *counts, int32_t *lists, int64_t *sb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < M.n;
