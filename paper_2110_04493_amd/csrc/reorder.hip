@@ -42,6 +42,25 @@ __device__ __forceinline__ long long wave_max_ll(long long x) {
     return x;
 }
 
+// Calls f(u) for every column u of G's row v.  The columns are loaded
+// kNbrBatch at a time, all loads issued before the first use, so that a
+// level of the search waits for one memory round trip per batch instead of
+// one per edge.
+constexpr int kNbrBatch = 8;
+
+template <typename F>
+__device__ __forceinline__ void for_neighbours(const CsrView &G, int v, F &&f) {
+    const int64_t b = G.rp[v], e = G.rp[v + 1];
+    for (int64_t p0 = b; p0 < e; p0 += kNbrBatch) {
+        int u[kNbrBatch];
+#pragma unroll
+        for (int j = 0; j < kNbrBatch; ++j) u[j] = p0 + j < e ? G.ci[p0 + j] : -1;
+#pragma unroll
+        for (int j = 0; j < kNbrBatch; ++j)
+            if (u[j] >= 0) f(u[j]);
+    }
+}
+
 // Breadth-first distances from *srcp over G's out-edges, in one workgroup
 // (level-synchronous; the frontier of a mesh is small).  dist must hold -1.
 // Nodes not reached get (largest distance + 1).  Writes res[0] = the node
@@ -72,12 +91,11 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *s
         if (size == 0) break;
         for (int i = tid; i < size; i += kBfsThreads) {
             const int v = cur[i];
-            for (int64_t p = G.rp[v]; p < G.rp[v + 1]; ++p) {
-                const int u = G.ci[p];
+            for_neighbours(G, v, [&](int u) {
                 // a stale -1 only costs a failed compare-and-swap
                 if (dist[u] == -1 && atomicCAS(&dist[u], -1, level + 1) == -1)
                     nxt[atomicAdd(&s_cnt[c1], 1)] = u;
-            }
+            });
         }
         if (tid == 0) s_cnt[c2] = 0;
         __syncthreads();
@@ -157,15 +175,14 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_
         if (size == 0) break;
         for (int i = tid; i < size; i += kBfsThreads) {
             const int v = i < kQCap ? lcur[i] : gcur[i];
-            for (int64_t p = G.rp[v]; p < G.rp[v + 1]; ++p) {
-                const int u = G.ci[p];
+            for_neighbours(G, v, [&](int u) {
                 const uint32_t bit = 1u << (u & 31);
-                if (vis[u >> 5] & bit) continue;
-                if (atomicOr(&vis[u >> 5], bit) & bit) continue;
+                if (vis[u >> 5] & bit) return;
+                if (atomicOr(&vis[u >> 5], bit) & bit) return;
                 dist[u] = level + 1;
                 const int pos = atomicAdd(&s_cnt[c1], 1);
                 if (pos < kQCap) lnxt[pos] = u; else gnxt[pos] = u;
-            }
+            });
         }
         if (tid == 0) s_cnt[c2] = 0;
         __syncthreads();

@@ -149,3 +149,30 @@ def test_dense_rows_taylor_sum(adjoint):
     print(f"[dense rows] M={sg['M']} N={sg['N']} terms={sg['taylor_terms']} "
           f"nnz(E)/n={Eg.nnz / H.n:.0f} relF={rel:.2e}", flush=True)
     assert rel <= TOL and ok
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_long_column_taylor_adjoint(adjoint):
+    """A ring of 1,500 nodes with one full column: every Taylor term has a
+    column of about n entries, so the Taylor adjoint's inner products read
+    that column from memory rather than from its LDS stage (512 entries)."""
+    n = 1500
+    T = W.tridiag(n, 1.0, -2.0, 1.0, 0.4)
+    r = np.concatenate([T.rows(), [0, n - 1], np.arange(2, n - 1)])
+    c = np.concatenate([T.col.astype(np.int64), [n - 1, 0], np.zeros(n - 3, np.int64)])
+    v = np.concatenate([T.val, [0.4, 0.4], np.full(n - 3, 0.05)])
+    H, eps = W.csr_from_coo(n, r, c, v), 1e-12
+    assert np.count_nonzero(H.col == 0) > 512
+    if adjoint:
+        dg, _ = gpu_grad(H, eps, density=0.05)
+        do, _ = oracle_grad(H, eps, density=0.05)
+        rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+        print(f"[long column] adjoint rel={rel:.2e}", flush=True)
+        assert rel <= TOL
+        return
+    Eg, sg = run_gpu(H, eps)
+    Eo, so = run_oracle(H, eps)
+    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
+    print(f"[long column] M={sg['M']} N={sg['N']} terms={sg['taylor_terms']} relF={rel:.2e}",
+          flush=True)
+    assert rel <= TOL and ok
