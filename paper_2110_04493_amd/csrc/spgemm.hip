@@ -79,6 +79,11 @@ __device__ __forceinline__ double readlane_f64(double x, int j) {
 // follow the left row's storage order.
 constexpr int kShortRows = 4;
 constexpr int kShortChunks = 2;
+// Right-factor rows of at most kTinyLen entries (stencil rows) are loaded
+// kTinyRows at a time into one 64-lane chunk, kTinyLen lanes per row, and
+// then handed to f one row at a time (the lanes of the other rows idle).
+constexpr int kTinyRows = 8;
+constexpr int kTinyLen = kWave / kTinyRows;
 
 // Calls f(col, a, b) for every partial product a_ik * b_kj of row i of A*B,
 // with a_ik taken in A's storage order and, for each of them, B's row k in
@@ -100,7 +105,27 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
         }
         const int m = (int)((e - p0) < kWave ? (e - p0) : kWave);
         const unsigned long long shortm = __ballot(p < e && s1 - s0 <= kShortChunks * kWave);
+        const unsigned long long tinym = __ballot(p < e && s1 - s0 <= kTinyLen);
         for (int j = 0; j < m;) {
+            {
+                const int un = m - j < kTinyRows ? m - j : kTinyRows;
+                const unsigned long long grp = ((1ull << un) - 1ull) << j;
+                if ((tinym & grp) == grp) {
+                    const int u = lane / kTinyLen, h = lane % kTinyLen;
+                    const int src = j + (u < un ? u : 0);
+                    const int64_t q0 = __shfl(s0, src), q1 = __shfl(s1, src);
+                    const double a = __shfl(av, src);
+                    const int64_t q = q0 + h;
+                    const bool ok = u < un && q < q1;
+                    const int c = ok ? B.ci[q] : -1;
+                    const double v = ok ? B.v[q] : 0.0;
+#pragma unroll
+                    for (int g = 0; g < kTinyRows; ++g)
+                        if (u == g && c >= 0) f(c, a, v);
+                    j += un;
+                    continue;
+                }
+            }
             const int un = m - j < kShortRows ? m - j : kShortRows;
             const unsigned long long grp = ((1ull << un) - 1ull) << j;
             if ((shortm & grp) == grp) {
@@ -168,7 +193,25 @@ __device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, i
         }
         const int m = (int)((e - p0) < kWave ? (e - p0) : kWave);
         const unsigned long long shortm = __ballot(p < e && s1 - s0 <= kShortChunks * kWave);
+        const unsigned long long tinym = __ballot(p < e && s1 - s0 <= kTinyLen);
         for (int j = 0; j < m;) {
+            {
+                const int un = m - j < kTinyRows ? m - j : kTinyRows;
+                const unsigned long long grp = ((1ull << un) - 1ull) << j;
+                if ((tinym & grp) == grp) {
+                    const int u = lane / kTinyLen, h = lane % kTinyLen;
+                    const int src = j + (u < un ? u : 0);
+                    const int64_t q0 = __shfl(s0, src), q1 = __shfl(s1, src);
+                    const int64_t q = q0 + h;
+                    const int c = u < un && q < q1 ? B.ci[q] : -1;
+                    // every lane takes part in every call; only one row's
+                    // lanes are valid in each, in the left row's order
+#pragma unroll
+                    for (int g = 0; g < kTinyRows; ++g) f(c, u == g && c >= 0);
+                    j += un;
+                    continue;
+                }
+            }
             const int un = m - j < kShortRows ? m - j : kShortRows;
             const unsigned long long grp = ((1ull << un) - 1ull) << j;
             if ((shortm & grp) == grp) {
