@@ -950,12 +950,23 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         E->val = v;
         S.nnz_e = kept;
         if (keep) {
-            CHK(ensure_csr(P, P.Epat, n, kept));
-            HIPCHK(hipMemcpyAsync(P.Epat.rp.p, erp, sizeof(int64_t) * (n + 1),
-                                  hipMemcpyDeviceToDevice, st));
-            if (kept)
-                HIPCHK(hipMemcpyAsync(P.Epat.ci.p, eci, sizeof(int32_t) * kept,
+            // the adjoint needs the pattern of E' (of E without reordering):
+            // E' is workspace and its pattern buffers simply change hands;
+            // E itself belongs to the caller and is copied
+            if (P.perm_active) {
+                std::swap(P.Epat.rp, P.Eperm.rp);
+                std::swap(P.Epat.ci, P.Eperm.ci);
+            } else {
+                CHK(ensure(P, P.Epat.rp, sizeof(int64_t) * (n + 1)));
+                CHK(ensure(P, P.Epat.ci, sizeof(int32_t) * kept));
+                HIPCHK(hipMemcpyAsync(P.Epat.rp.p, erp, sizeof(int64_t) * (n + 1),
                                       hipMemcpyDeviceToDevice, st));
+                if (kept)
+                    HIPCHK(hipMemcpyAsync(P.Epat.ci.p, eci, sizeof(int32_t) * kept,
+                                          hipMemcpyDeviceToDevice, st));
+            }
+            P.Epat.n = n;
+            P.Epat.nnz = kept;
         }
     }
     S.peak_workspace_bytes = P.peak;

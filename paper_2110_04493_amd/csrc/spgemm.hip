@@ -666,18 +666,25 @@ __global__ __launch_bounds__(512) void k_masked(
 }
 
 // Inner-product form of a single masked product: one wave per row r of M.
-// A's row r (its column keys and values) is staged in LDS; for every
-// column c of M's row, the lanes take the entries of B's column c and find
-// their row index among A's keys by binary search.  Each lane accumulates
-// its own products and a fixed butterfly adds the lanes, so the result is
-// reproducible.  Rows of A longer than the LDS stage are searched in memory.
+// A's row r (its column keys and values) is staged in LDS, and each entry of
+// B's column c is looked up among A's keys by binary search.  When the mask
+// row has at most kDotCols entries whose B columns hold at most
+// kDotChunks * 64 entries together, all of them are loaded at once (their
+// keys and positions, then their values: two memory round trips for the
+// whole row), the products go to LDS and each output sums its own span of
+// them in a fixed order.  Other rows take the columns one at a time, each
+// lane accumulating its own products before a fixed butterfly adds the
+// lanes.  Either way the result is reproducible.  Rows of A longer than the
+// LDS stage are searched in memory.
 constexpr int kDotWaves = 4, kDotLds = 512;
+constexpr int kDotCols = 8, kDotChunks = 8;
 
 __global__ __launch_bounds__(kWave * kDotWaves) void k_masked_dot(
     CsrView M, const double *__restrict__ dv, PosCsr A, PosCsr Bt, double div,
     double *__restrict__ out) {
     __shared__ int32_t skey[kDotWaves][kDotLds];
     __shared__ double sval[kDotWaves][kDotLds];
+    __shared__ double sprod[kDotWaves][kDotChunks * kWave];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     const int64_t r = (int64_t)blockIdx.x * kDotWaves + wv;
     if (r >= M.n) return;
@@ -695,27 +702,85 @@ __global__ __launch_bounds__(kWave * kDotWaves) void k_masked_dot(
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
+    // the position of key k among A's row r, or -1
+    auto find = [&](int32_t k) -> int64_t {
+        int64_t lo = 0, hi = al;
+        if (staged) {
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (key[mid] < k) lo = mid + 1; else hi = mid;
+            }
+            return lo < al && key[lo] == k ? lo : -1;
+        }
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (A.ci[ao + mid] < k) lo = mid + 1; else hi = mid;
+        }
+        return lo < al && A.ci[ao + lo] == k ? lo : -1;
+    };
+    auto a_at = [&](int64_t j) { return staged ? val[j] : A.v[A.pos[ao + j]]; };
+    if (staged && ml <= kDotCols) {
+        int64_t b0 = 0, len = 0;
+        if (lane < ml) {
+            const int32_t c = M.ci[mo + lane];
+            b0 = Bt.rp[c];
+            len = Bt.rp[c + 1] - b0;
+        }
+        int64_t st[kDotCols + 1], bs[kDotCols];
+        st[0] = 0;
+#pragma unroll
+        for (int t = 0; t < kDotCols; ++t) {
+            bs[t] = t < ml ? readlane_i64(b0, t) : 0;
+            st[t + 1] = st[t] + (t < ml ? readlane_i64(len, t) : 0);
+        }
+        const int64_t tot = st[kDotCols];
+        if (tot <= kDotChunks * kWave) {
+            double *prod = sprod[wv];
+            int32_t kq[kDotChunks];
+            int64_t pq[kDotChunks];
+            double vq[kDotChunks];
+#pragma unroll
+            for (int q = 0; q < kDotChunks; ++q) {
+                const int64_t f = q * kWave + lane;
+                int t = 0;
+#pragma unroll
+                for (int u = 1; u < kDotCols; ++u)
+                    if (u < ml && f >= st[u]) t = u;
+                const bool ok = f < tot;
+                const int64_t p = bs[t] + (f - st[t]);
+                kq[q] = ok ? Bt.ci[p] : -1;
+                pq[q] = ok ? Bt.pos[p] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < kDotChunks; ++q) vq[q] = kq[q] >= 0 ? Bt.v[pq[q]] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kDotChunks; ++q) {
+                const int64_t f = q * kWave + lane;
+                if (f < tot) {
+                    const int64_t j = find(kq[q]);
+                    prod[f] = j >= 0 ? val[j] * vq[q] : 0.0;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < kDotCols; ++t) {
+                if (t >= ml) break;
+                double s = 0.0;
+                for (int64_t f = st[t] + lane; f < st[t + 1]; f += kWave) s += prod[f];
+                s = wave_sum(s);
+                if (lane == 0) out[mo + t] = s / div + dv[mo + t];
+            }
+            return;
+        }
+    }
     for (int64_t t = 0; t < ml; ++t) {
         const int32_t c = M.ci[mo + t];
         double s = 0.0;
         if (al > 0) {
             for (int64_t p = Bt.rp[c] + lane; p < Bt.rp[c + 1]; p += kWave) {
-                const int32_t k = Bt.ci[p];
-                int64_t lo = 0, hi = al;
-                if (staged) {
-                    while (lo < hi) {
-                        const int64_t mid = (lo + hi) >> 1;
-                        if (key[mid] < k) lo = mid + 1; else hi = mid;
-                    }
-                    if (lo < al && key[lo] == k) s += val[lo] * Bt.v[Bt.pos[p]];
-                } else {
-                    while (lo < hi) {
-                        const int64_t mid = (lo + hi) >> 1;
-                        if (A.ci[ao + mid] < k) lo = mid + 1; else hi = mid;
-                    }
-                    if (lo < al && A.ci[ao + lo] == k)
-                        s += A.v[A.pos[ao + lo]] * Bt.v[Bt.pos[p]];
-                }
+                const int64_t j = find(Bt.ci[p]);
+                if (j >= 0) s += a_at(j) * Bt.v[Bt.pos[p]];
             }
         }
         s = wave_sum(s);
