@@ -451,7 +451,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         if (t >= ng) break;
         const int64_t ct = tile_of(clo, cwoff, crt, ctb, I, J[t]);
         if (ct < 0) continue;
-        *(d4 *)(ctiles + ct * kTileElems + 4 * lane) = acc[t];
+        // candidate tiles are written once and read back by later kernels,
+        // after far more data than the caches hold has passed: streaming
+        // stores keep them from displacing the operand tiles still in use
+        __builtin_nontemporal_store(acc[t], (d4 *)(ctiles + ct * kTileElems + 4 * lane));
         if (!tsq) continue;
         // the tile's sum of squares, its nonzero slots, their smallest and
         // largest magnitudes and the nonzeros of each of its 16 rows, all

@@ -194,13 +194,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         d4 o;
 #pragma unroll
         for (int r = 0; r < 4; ++r) o[r] = m[r] != 0.0 ? acc[t][r] : 0.0;
-        *(d4 *)(out + tt * kTileElems + 4 * lane) = o;
+        // the new gradient's tiles are read only by the next adjoint step:
+        // streaming stores keep them from displacing this step's operands
+        __builtin_nontemporal_store(o, (d4 *)(out + tt * kTileElems + 4 * lane));
         if (!outA) continue;
         // the same tile in the A operand layout: o[r] is entry (4 r + lane / 16,
         // lane % 16)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            outA[tt * kTileElems + offA(4 * r + (lane >> 4), lane & 15)] = o[r];
+            __builtin_nontemporal_store(o[r],
+                                        &outA[tt * kTileElems + offA(4 * r + (lane >> 4), lane & 15)]);
     }
 }
 
