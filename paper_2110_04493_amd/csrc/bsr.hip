@@ -548,11 +548,12 @@ __device__ __forceinline__ bool bsr_keep(int64_t i, int col, int64_t n, double v
 // With the per-tile summaries of the product (tmn, tmx: smallest nonzero and
 // largest magnitude, trc: nonzeros per row), a tile whose slots are all at
 // most theta is skipped, and one whose nonzeros all exceed theta is counted
-// from trc without reading it.
+// from trc without reading it; with krc, the tiles in between are counted
+// from the last filter pass's counts, so no tile is read.
 __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
                             const int32_t *ccols, const double *ctiles, const double *tmn,
-                            const double *tmx, const uint4 *trc, const FilterCtl *c,
-                            int64_t *cnt) {
+                            const double *tmx, const uint4 *trc, const uint4 *krc,
+                            const FilterCtl *c, int64_t *cnt) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= (n + kTile - 1) / kTile) return;
     const int lane = lane_id();
@@ -560,24 +561,58 @@ __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
     const double theta = c->theta;
     int k4[4] = {0, 0, 0, 0};
     const int64_t base = ctb[I], cntI = ccnt[I];
-    for (int64_t t = 0; t < cntI; ++t) {
-        const int64_t tt = base + t;
-        if (tmx) {
-            if (tmx[tt] <= theta) continue;
-            if (tmn[tt] > theta) {
-                if ((lane & 15) == 0) {
-                    const uint4 q = trc[tt];
+    for (int64_t c0 = 0; c0 < cntI; c0 += kWave) {
+        // one lane per tile: the summaries of 64 tiles are read together;
+        // h holds the row counts in 16-bit fields, row r in half r & 1 of
+        // word r >> 1 (at most 16 per tile, 1024 per round)
+        const int64_t t = c0 + lane, tt = base + t;
+        uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        bool rd = false;
+        if (t < cntI) {
+            if (!tmx) {
+                rd = true;
+            } else if (tmx[tt] > theta) {
+                const bool whole = tmn[tt] > theta;
+                if (whole || krc) {
+                    // wholly kept: the product's row counts; in between:
+                    // the counts the last filter pass took at this threshold
+                    const uint4 q = whole ? trc[tt] : krc[tt];
                     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) k4[k] += (int)((w[k] >> (8 * g)) & 0xffu);
+                    for (int k = 0; k < 4; ++k)
+#pragma unroll
+                        for (int gg = 0; gg < 4; ++gg) {
+                            const int row = gg + 4 * k;
+                            h[row >> 1] += ((w[k] >> (8 * gg)) & 0xffu) << (16 * (row & 1));
+                        }
+                } else {
+                    rd = true;
                 }
-                continue;
             }
         }
-        const int col = 16 * ccols[tt] + (lane & 15);
-        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) k4[k] += bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) h[j] += __shfl_xor(h[j], o);
+        if ((lane & 15) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int row = g + 4 * k;
+                k4[k] += (int)((h[row >> 1] >> (16 * (row & 1))) & 0xffffu);
+            }
+        }
+        // tiles without usable counts are read, one at a time by all lanes
+        unsigned long long m = __ballot(rd);
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int64_t tr = base + c0 + l;
+            const int col = 16 * ccols[tr] + (lane & 15);
+            const d4 v = *(const d4 *)(ctiles + tr * kTileElems + 4 * lane);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                k4[k] += bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -608,11 +643,7 @@ __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
     }
     const int64_t base = ctb[I], cntI = ccnt[I];
     const uint32_t below = (1u << cl) - 1u;
-    for (int64_t t = 0; t < cntI; ++t) {
-        const int64_t tt = base + t;
-        if (tmx && tmx[tt] <= theta) continue;   // nothing kept
-        const int col = 16 * ccols[tt] + cl;
-        const d4 v = *(const d4 *)(ctiles + tt * kTileElems + 4 * lane);
+    auto emit = [&](int col, const d4 &v) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const bool keep = bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
@@ -623,6 +654,35 @@ __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
                 ov[q] = v[k];
             }
             out[k] += __popc(gm);
+        }
+    };
+    for (int64_t c0 = 0; c0 < cntI; c0 += kWave) {
+        // one lane per tile: which of 64 tiles keep anything, and their block
+        // columns, in one round trip; then the tiles that do, in order, the
+        // next one's load in flight while the current one is written
+        const int64_t t = c0 + lane;
+        const bool some = t < cntI && (!tmx || tmx[base + t] > theta);
+        const int bc = some ? ccols[base + t] : 0;
+        unsigned long long m = __ballot(some);
+        if (!m) continue;
+        int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        int col = 16 * __builtin_amdgcn_readlane(bc, l) + cl;
+        d4 v = *(const d4 *)(ctiles + (base + c0 + l) * kTileElems + 4 * lane);
+        for (;;) {
+            const bool more = m != 0;
+            int col2 = col;
+            d4 v2 = v;
+            if (more) {
+                l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                col2 = 16 * __builtin_amdgcn_readlane(bc, l) + cl;
+                v2 = *(const d4 *)(ctiles + (base + c0 + l) * kTileElems + 4 * lane);
+            }
+            emit(col, v);
+            if (!more) break;
+            col = col2;
+            v = v2;
         }
     }
 }
@@ -790,11 +850,12 @@ hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
 
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const double *tmn, const double *tmx,
-                     const uint4 *trc, const FilterCtl *c, int64_t *cnt, hipStream_t st) {
+                     const uint4 *trc, const uint4 *krc, const FilterCtl *c, int64_t *cnt,
+                     hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int64_t nb = (n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_bsr_count, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
-                       ctiles, tmn, tmx, trc, c, cnt);
+                       ctiles, tmn, tmx, trc, krc, c, cnt);
     return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         CHK(ensure(P, P.c_mn, sizeof(double) * (ctiles + 1)));
         CHK(ensure(P, P.c_mx, sizeof(double) * (ctiles + 1)));
         CHK(ensure(P, P.c_rc, sizeof(uint4) * (ctiles + 1)));
+        CHK(ensure(P, P.c_kc, sizeof(uint4) * (ctiles + 1)));
         CHK(ensure(P, P.b_dg, sizeof(double) * (nb + 1)));
     }
     HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
@@ -191,7 +192,7 @@ int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand) {
     CHK(ensure(P, P.crp, sizeof(int64_t) * (n + 1)));
     FilterCtl *ctl = (FilterCtl *)P.ctl.p;
     HIPCHK(filter_init_theta(ctl, 0.0, st));   // keep every nonzero slot
-    HIPCHK(bsr_count(n, ctb, ccnt, ccols, ctl_tiles, nullptr, nullptr, nullptr, ctl,
+    HIPCHK(bsr_count(n, ctb, ccnt, ccols, ctl_tiles, nullptr, nullptr, nullptr, nullptr, ctl,
                      (int64_t *)P.cnt.p, st));
     CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.crp.p, n));
     int64_t *hl = (int64_t *)P.host;
@@ -264,11 +265,16 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
             for (int j = 0; j < 4; ++j)
                 HIPCHK(filter_pass_tiles((const double *)P.c_tiles.p, (const double *)P.c_mn.p,
                                          (const double *)P.c_mx.p, (const double *)P.c_sq.p,
-                                         ctiles, ctl, (double *)P.part.p, kParts, st));
+                                         ctiles, ctl, (double *)P.part.p, kParts,
+                                         (uint4 *)P.c_kc.p, st));
+        // the passes' counts hold for the final threshold only when a pass
+        // ran at it: not with a fixed threshold, nor when a = 0 (then no
+        // tile lies between its smallest nonzero and the threshold 0)
         HIPCHK(bsr_count(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
                          (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,
                          (const double *)P.c_mn.p, (const double *)P.c_mx.p,
-                         (const uint4 *)P.c_rc.p, ctl, (int64_t *)P.cnt.p, st));
+                         (const uint4 *)P.c_rc.p, use_fixed ? nullptr : (const uint4 *)P.c_kc.p,
+                         ctl, (int64_t *)P.cnt.p, st));
         CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
         HIPCHK(hipMemcpyAsync(P.host, ctl, sizeof(FilterCtl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hl + 8, (int64_t *)P.krp.p + n, sizeof(int64_t),

@@ -369,7 +369,8 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
                                                                  const double *__restrict__ tmax,
                                                                  const double *__restrict__ tsq,
                                                                  int64_t ntiles, FilterCtl *c,
-                                                                 double *part) {
+                                                                 double *part,
+                                                                 uint4 *__restrict__ krc) {
     typedef double v4 __attribute__((ext_vector_type(4)));
     if (c->done) return;
     const double theta = c->theta;
@@ -384,9 +385,19 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
             continue;
         }
         const v4 x = *(const v4 *)(tiles + t * 256 + 4 * lane);
+        uint32_t w[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r) {
             if (fabs(x[r]) <= theta) s = fma(x[r], x[r], s);
+            // entries above theta per tile row: lane l holds row l / 16 + 4 r
+            // (column l % 16), so each 16-lane group of the ballot is one row
+            const unsigned long long k = __ballot(fabs(x[r]) > theta);
+            w[r] = 0;
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                w[r] |= (uint32_t)__popcll((k >> (16 * g)) & 0xffffull) << (8 * g);
+        }
+        if (krc && lane == 0) krc[t] = make_uint4(w[0], w[1], w[2], w[3]);
     }
     filter_pass_end(s, theta, c, part);
 }
@@ -425,10 +436,10 @@ __device__ void filter_pass_end(double s, double theta, FilterCtl *c, double *pa
 
 hipError_t filter_pass_tiles(const double *tiles, const double *tmin, const double *tmax,
                              const double *tsq, int64_t ntiles, FilterCtl *c, double *part,
-                             int nparts, hipStream_t st) {
+                             int nparts, uint4 *krc, hipStream_t st) {
     nparts = parts_for(ntiles * 16, nparts);
     hipLaunchKernelGGL(k_filter_pass_tiles, dim3(nparts), dim3(kRedBlock), 0, st, tiles, tmin,
-                       tmax, tsq, ntiles, c, part);
+                       tmax, tsq, ntiles, c, part, krc);
     return hipGetLastError();
 }
 

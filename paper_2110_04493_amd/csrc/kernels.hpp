@@ -85,10 +85,14 @@ hipError_t filter_init_theta(FilterCtl *c, double theta, hipStream_t st);
 // the smallest nonzero and the largest magnitude of tile t and tsq[t] its
 // sum of squares: a tile whose nonzeros all exceed the current threshold is
 // skipped, one whose slots are all at most the threshold adds tsq[t], and
-// only the tiles in between are read.
+// only the tiles in between are read.  krc (may be NULL) receives, for
+// every tile the pass reads, its entries above the pass's threshold per tile
+// row (the trc layout of the product); since a tile is read exactly when
+// its smallest nonzero is at most the threshold and its largest magnitude
+// above it, the last pass leaves the final counts of every such tile.
 hipError_t filter_pass_tiles(const double *tiles, const double *tmin, const double *tmax,
                              const double *tsq, int64_t ntiles, FilterCtl *c, double *part,
-                             int nparts, hipStream_t st);
+                             int nparts, uint4 *krc, hipStream_t st);
 hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
                        double *part, int nparts, hipStream_t st);
 // Kept counts per row (|v| > theta); with addI the identity is added (E = I + T).
@@ -142,10 +146,13 @@ hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
                      const double *ctiles, double *rowsq, hipStream_t st);
 // Compaction of the candidate tiles (kept: |v| > c->theta) into CSR: kept
 // counts per row, then the entries.  tmn / tmx / trc (may be NULL) are the
-// per-tile summaries the product leaves with its norm partials.
+// per-tile summaries the product leaves with its norm partials; krc (may be
+// NULL, only with tmn / tmx) holds the counts that the last pass of
+// Algorithm 4.1 recorded for the tiles it read at the final threshold.
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const double *tmn, const double *tmx,
-                     const uint4 *trc, const FilterCtl *c, int64_t *cnt, hipStream_t st);
+                     const uint4 *trc, const uint4 *krc, const FilterCtl *c, int64_t *cnt,
+                     hipStream_t st);
 hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const double *tmx, const FilterCtl *c,
                      const int64_t *orp, int32_t *oci, double *ov, hipStream_t st);

@@ -95,7 +95,7 @@ struct expm_plan_s {
         c_rt;
     // per candidate tile: its share of ||I + T~||_F^2, its nonzero slots,
     // their smallest and largest magnitudes and the nonzeros of each row
-    xpm::host::Buf c_sq, c_nz, c_mn, c_mx, c_rc;
+    xpm::host::Buf c_sq, c_nz, c_mn, c_mx, c_rc, c_kc;
     // per block row: the diagonal tile's sum of (2 c_ii + 1)
     xpm::host::Buf b_dg;
     // panels of four block rows for the product (p_*: origin, words, column
