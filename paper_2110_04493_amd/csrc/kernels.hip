@@ -377,14 +377,8 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
     constexpr int wpb = kRedBlock / kWave;
     const int lane = lane_id();
     double s = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; t < ntiles;
-         t += (int64_t)gridDim.x * wpb) {
-        if (tmin[t] > theta) continue;   // nothing at or below theta
-        if (tmax[t] <= theta) {            // everything at or below theta
-            if (lane == 0) s += tsq[t];
-            continue;
-        }
-        const v4 x = *(const v4 *)(tiles + t * 256 + 4 * lane);
+    // the tile entries at or below theta and their counts above it, per row
+    auto take = [&](const v4 &x, int64_t t) {
         uint32_t w[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -398,6 +392,43 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
                 w[r] |= (uint32_t)__popcll((k >> (16 * g)) & 0xffffull) << (8 * g);
         }
         if (krc && lane == 0) krc[t] = make_uint4(w[0], w[1], w[2], w[3]);
+    };
+    // each wave takes 64 consecutive tiles at a time: one lane per tile
+    // reads its summaries (a tile wholly at or below theta adds its stored
+    // sum of squares), then the tiles in between are read in order with the
+    // next one's load in flight
+    const int64_t nchunk = (ntiles + kWave - 1) / kWave;
+    for (int64_t q = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; q < nchunk;
+         q += (int64_t)gridDim.x * wpb) {
+        const int64_t t0 = q * kWave, t = t0 + lane;
+        bool mid = false;
+        if (t < ntiles && tmin[t] <= theta) {   // something at or below theta
+            if (tmax[t] <= theta)
+                s += tsq[t];                      // everything at or below theta
+            else
+                mid = true;
+        }
+        unsigned long long m = __ballot(mid);
+        if (!m) continue;
+        int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        int64_t tt = t0 + l;
+        v4 x = *(const v4 *)(tiles + tt * 256 + 4 * lane);
+        for (;;) {
+            const bool more = m != 0;
+            int64_t tt2 = tt;
+            v4 x2 = x;
+            if (more) {
+                l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                tt2 = t0 + l;
+                x2 = *(const v4 *)(tiles + tt2 * 256 + 4 * lane);
+            }
+            take(x, tt);
+            if (!more) break;
+            tt = tt2;
+            x = x2;
+        }
     }
     filter_pass_end(s, theta, c, part);
 }
