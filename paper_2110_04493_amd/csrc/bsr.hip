@@ -123,33 +123,37 @@ __global__ void k_bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, con
     const int loI = lo[I];
     const int64_t w0 = woff[I], tbI = tb[I];
     const unsigned long long above = lane == kWave - 1 ? 0ull : ~0ull << (lane + 1);
+    // chunks of 64 entries; the next chunk's block columns are loaded while
+    // the current one is handled, and they also give the length of the
+    // chunk's last segment (a segment holds at most 16 entries, so it ends
+    // within the next chunk)
+    int J = b + lane < e ? T.ci[b + lane] >> 4 : INT32_MAX;
+    int Jprev = -1;   // block column of the previous chunk's last entry
     for (int64_t c0 = b; c0 < e; c0 += kWave) {
-        // segment starts of this chunk by ballot; a start's length runs to the
-        // next start, or past the chunk end for the chunk's last segment
-        const int64_t p = c0 + lane;
+        const int64_t p = c0 + lane, pn = p + kWave;
         const bool valid = p < e;
-        const int J = valid ? T.ci[p] >> 4 : INT32_MAX;
-        int Jprev = __shfl_up(J, 1);
-        if (lane == 0) Jprev = c0 > b ? T.ci[c0 - 1] >> 4 : -1;
-        const bool start = valid && J != Jprev;
-        const unsigned long long sm = __ballot(start);
-        if (!start) continue;
-        const unsigned long long nx = sm & above;
-        int64_t len;
-        if (nx) {
-            len = __ffsll((long long)nx) - 1 - lane;
-        } else {
-            int64_t q = min<int64_t>(e, c0 + kWave);
-            len = q - p;
-            while (q < e && (T.ci[q] >> 4) == J) {
-                ++len;
-                ++q;
-            }
-        }
         const int d = J - loI;
-        const uint2 w = rt[w0 + (d >> 5)];
-        const int64_t tt = tbI + w.y + __popc(w.x & ((1u << (d & 31)) - 1u));
-        seg[tt * kTile + r] = (p << 5) | len;
+        uint2 w = make_uint2(0u, 0u);
+        if (valid) w = rt[w0 + (d >> 5)];
+        const int Jn = pn < e ? T.ci[pn] >> 4 : INT32_MAX;
+        const int Jlast = __builtin_amdgcn_readlane(J, kWave - 1);
+        const unsigned long long cont = __ballot(pn < e && Jn == Jlast);
+        int Jp = __shfl_up(J, 1);
+        if (lane == 0) Jp = Jprev;
+        const bool start = valid && J != Jp;
+        const unsigned long long sm = __ballot(start);
+        if (start) {
+            const unsigned long long nx = sm & above;
+            int64_t len;
+            if (nx)
+                len = __ffsll((long long)nx) - 1 - lane;
+            else   // the chunk's last segment: to the chunk's end, then on
+                len = min<int64_t>(e, c0 + kWave) - p + __popcll(cont);
+            const int64_t tt = tbI + w.y + __popc(w.x & ((1u << (d & 31)) - 1u));
+            seg[tt * kTile + r] = (p << 5) | len;
+        }
+        Jprev = Jlast;
+        J = Jn;
     }
 }
 
