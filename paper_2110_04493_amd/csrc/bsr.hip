@@ -35,14 +35,18 @@ __global__ void k_bsr_bounds(CsrView T, int64_t nb, int32_t *lo, int64_t *words)
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= nb) return;
     const int64_t r0 = I * kTile, r1 = min<int64_t>(r0 + kTile, T.n);
+    // one lane per row of the block row
     int mn = INT32_MAX, mx = -1;
-    for (int64_t i = r0; i < r1; ++i) {
+    const int64_t i = r0 + lane_id();
+    if (lane_id() < kTile && i < r1) {
         const int64_t b = T.rp[i], e = T.rp[i + 1];
-        if (e > b && lane_id() == 0) {
-            mn = min(mn, T.ci[b] >> 4);
-            mx = max(mx, T.ci[e - 1] >> 4);
+        if (e > b) {
+            mn = T.ci[b] >> 4;
+            mx = T.ci[e - 1] >> 4;
         }
     }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
     if (lane_id() == 0) {
         if (mx < 0) {
             lo[I] = 0;
@@ -71,12 +75,23 @@ __global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const 
     for (int64_t w = lane; w < W; w += kWave) bm[w] = 0;
     wfence();
     const int base = lo[I];
-    const int64_t r1 = min<int64_t>(I * kTile + kTile, T.n);
-    for (int64_t i = I * kTile; i < r1; ++i)
-        for (int64_t p = T.rp[i] + lane; p < T.rp[i + 1]; p += kWave) {
-            const int d = (T.ci[p] >> 4) - base;
-            atomicOr(&bm[d >> 5], 1u << (d & 31));
+    // the block row's 16 rows are one contiguous range of entries; four
+    // chunks of 64 are loaded before their bits are set
+    const int64_t p0 = T.rp[I * kTile], p1 = T.rp[min<int64_t>(I * kTile + kTile, T.n)];
+    for (int64_t q = p0; q < p1; q += 4 * kWave) {
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t p = q + u * kWave + lane;
+            c[u] = p < p1 ? T.ci[p] >> 4 : -1;
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c[u] >= 0) {
+                const int d = c[u] - base;
+                atomicOr(&bm[d >> 5], 1u << (d & 31));
+            }
+    }
     wfence();
     unsigned carry = 0;
     for (int64_t b0 = 0; b0 < W; b0 += kWave) {
