@@ -317,6 +317,16 @@ __global__ void k_bsr_groups(const int64_t *ccnt, int64_t nb, int64_t *gcnt, int
     if (I < nb) gcnt[I] = (ccnt[I] + group - 1) / group;
 }
 
+// owner[w] = i for every work item w in [ofs[i], ofs[i + 1]) (ofs: the
+// exclusive scan of the work-item counts, ofs[m] the total), so that a work
+// item finds its panel or block row with one load instead of a binary
+// search of dependent loads.
+__global__ void k_work_owner(const int64_t *ofs, int64_t m, int32_t *owner) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int64_t w = ofs[i]; w < ofs[i + 1]; ++w) owner[w] = (int32_t)i;
+}
+
 // ----------------------------------------------------------------- product
 
 // ----------------------------------------------------------------- panels
@@ -413,7 +423,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
     const int32_t *__restrict__ tcols, const double *__restrict__ tA,
     const double *__restrict__ tB, const int64_t *__restrict__ pgofs,
-    const int64_t *__restrict__ nwork_dev, int64_t np,
+    const int64_t *__restrict__ nwork_dev, const int32_t *__restrict__ owner,
     const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
@@ -422,12 +432,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
-    int64_t lo_p = 0, hi_p = np - 1;   // last panel with pgofs[p] <= w
-    while (lo_p < hi_p) {
-        const int64_t mid = (lo_p + hi_p + 1) >> 1;
-        if (pgofs[mid] <= w) lo_p = mid; else hi_p = mid - 1;
-    }
-    const int64_t p = lo_p;
+    const int64_t p = owner[w];   // the panel: pgofs[p] <= w < pgofs[p + 1]
     const int64_t I = p * kPanel + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (I >= nb) return;
     const int64_t g0 = (w - pgofs[p]) * kGroup;
@@ -810,6 +815,13 @@ hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipS
     return hipGetLastError();
 }
 
+hipError_t work_owner(const int64_t *ofs, int64_t m, int32_t *owner, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_work_owner, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, ofs, m,
+                       owner);
+    return hipGetLastError();
+}
+
 hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                      const int64_t *tb, int32_t *tcols, int32_t *trows, hipStream_t st) {
     if (nb == 0) return hipSuccess;
@@ -836,7 +848,7 @@ hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const i
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
-                             const int64_t *pofs, const int32_t *pcols,
+                             const int32_t *owner, const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
@@ -844,7 +856,7 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
-                       nwork_dev, (nb + kPanel - 1) / kPanel, pofs, pcols, clo, cwoff, crt, ctb,
+                       nwork_dev, owner, pofs, pcols, clo, cwoff, crt, ctb,
                        ctiles, n, tsq, tnz, tmn, tmx, trc, bdg);
     return hipGetLastError();
 }

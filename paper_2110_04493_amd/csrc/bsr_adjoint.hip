@@ -95,17 +95,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     // T's block columns (T^T's block rows), sorted by K
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ ck,
     const int64_t *__restrict__ ct,
-    const int64_t *__restrict__ gofs, double *__restrict__ out, double *__restrict__ outA,
-    int64_t nwork) {
+    const int64_t *__restrict__ gofs, const int32_t *__restrict__ owner,
+    double *__restrict__ out, double *__restrict__ outA, int64_t nwork) {
     const int lane = lane_id();
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (w >= nwork) return;
-    int64_t a0 = 0, a1 = nb - 1;   // last I with gofs[I] <= w
-    while (a0 < a1) {
-        const int64_t mid = (a0 + a1 + 1) >> 1;
-        if (gofs[mid] <= w) a0 = mid; else a1 = mid - 1;
-    }
-    const int64_t I = a0;
+    const int64_t I = owner[w];   // the block row: gofs[I] <= w < gofs[I + 1]
     const int64_t t0 = (w - gofs[I]) * kGroup;             // first tile (rank in block row I)
     const int64_t cntI = ttb[I + 1] - ttb[I];
     const int ng = (int)min<int64_t>(kGroup, cntI - t0);
@@ -266,13 +261,13 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
-                       const int64_t *gofs, double *out, double *outA, int64_t nwork,
-                       hipStream_t st) {
+                       const int64_t *gofs, const int32_t *owner, double *out, double *outA,
+                       int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     const dim3 grid((unsigned)((nwork + 3) / 4)), block(256);
 #define XPM_ADJ_ARGS                                                                           \
     nb, tlo, twoff, trt, ttb, tcols, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, \
-        gofs, out, outA, nwork
+        gofs, owner, out, outA, nwork
     if (kAdjSplit) {
         hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1>), grid, block, 0, st, XPM_ADJ_ARGS);
         hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2>), grid, block, 0, st, XPM_ADJ_ARGS);

@@ -146,6 +146,8 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                               (int32_t *)P.p_cols.p, st));
         HIPCHK(bsr_panel_groups((const int64_t *)P.p_cnt.p, nb, (int64_t *)P.p_gcnt.p, st));
         CHK(scan(P, (const int64_t *)P.p_gcnt.p, (int64_t *)P.p_gofs.p, np));
+        CHK(ensure(P, P.p_owner, sizeof(int32_t) * (bsr_panel_work_bound(ctiles, nb) + 1)));
+        HIPCHK(work_owner((const int64_t *)P.p_gofs.p, np, (int32_t *)P.p_owner.p, st));
         // launched on a bound of the work-item count (a panel's union holds
         // at most the sum of its rows' tiles); the kernel reads the exact
         // count, p_gofs[np], and surplus workgroups return at once
@@ -156,6 +158,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
     HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
                              (const double *)ts.tA.p, (const double *)ts.tB.p,
                              (const int64_t *)P.p_gofs.p, (const int64_t *)P.p_gofs.p + (nb + 3) / 4,
+                             (const int32_t *)P.p_owner.p,
                              (const int64_t *)P.p_ofs.p, (const int32_t *)P.p_cols.p,
                              (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
                              (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
@@ -374,6 +377,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                           st));
     CHK(sync(P));
     const int64_t nwork = hl[0];
+    CHK(ensure(P, P.g_owner, sizeof(int32_t) * (nwork + 1)));
+    HIPCHK(work_owner((const int64_t *)P.g_ofs.p, nb, (int32_t *)P.g_owner.p, st));
     CHK(ensure(P, P.adj_tiles, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
     CHK(ensure(P, P.adj_tilesA, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
     const bool prof = P.opts.profile == 1 && P.have_events;
@@ -386,7 +391,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const int64_t *)G.woff.p, (const uint2 *)G.rt.p,
                        (const int64_t *)G.tb.p, (const int32_t *)G.cols.p, (const double *)G.tA.p,
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
-                       (const int64_t *)P.g_ofs.p, (double *)P.adj_tiles.p,
+                       (const int64_t *)P.g_ofs.p, (const int32_t *)P.g_owner.p,
+                       (double *)P.adj_tiles.p,
                        (double *)P.adj_tilesA.p, nwork, st));
     if (light_profile(P)) CHK(ktimer_mark(P, 1));
     if (prof) {

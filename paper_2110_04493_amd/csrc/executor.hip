@@ -1314,7 +1314,7 @@ void expm_free(expm_plan_t p) {
                     &P.g_cnt, &P.g_ofs, &P.b_sq, &P.b_nz, &P.tc_cnt, &P.tc_ptr,
                     &P.tc_fill, &P.tc_k, &P.tc_t, &P.adj_tiles, &P.adj_tilesA, &P.c_rt, &P.p_lo,
                     &P.p_words, &P.p_woff, &P.p_cnt, &P.p_ofs, &P.p_gcnt, &P.p_gofs,
-                    &P.p_cols, &P.c_sq, &P.c_nz, &P.c_mn, &P.c_mx, &P.c_rc, &P.c_kc, &P.b_dg};
+                    &P.p_owner, &P.g_owner, &P.p_cols, &P.c_sq, &P.c_nz, &P.c_mn, &P.c_mx, &P.c_rc, &P.c_kc, &P.b_dg};
     for (Buf *b : tbufs) release(P, *b);
     Buf *rbufs[] = {&P.order, &P.newidx, &P.hmap, &P.emap, &P.ro_rb, &P.ro_d0, &P.ro_d1,
                     &P.ro_d3, &P.ro_q0, &P.ro_q1, &P.ro_cell, &P.ro_cnt, &P.ro_off,

@@ -131,10 +131,14 @@ hipError_t bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, const uint
                    const int64_t *tb, int64_t *seg, hipStream_t st);
 hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const int32_t *trows,
                         const int64_t *seg, double *tA, double *tB, hipStream_t st);
+// owner[w] = i for every w in [ofs[i], ofs[i + 1]), i < m (ofs: exclusive
+// scan with the total in ofs[m]): the panel or block row of each work item
+// of the tile product and adjoint kernels.
+hipError_t work_owner(const int64_t *ofs, int64_t m, int32_t *owner, hipStream_t st);
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
-                             const int64_t *pofs, const int32_t *pcols,
+                             const int32_t *owner, const int64_t *pofs, const int32_t *pcols,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
@@ -172,8 +176,8 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int64_t *gwoff, const uint2 *grt, const int64_t *gtb,
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
-                       const int64_t *gofs, double *out, double *outA, int64_t nwork,
-                       hipStream_t st);
+                       const int64_t *gofs, const int32_t *owner, double *out, double *outA,
+                       int64_t nwork, hipStream_t st);
 hipError_t bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                       const int64_t *tb, const double *tiles, double *out, hipStream_t st);
 

@@ -100,7 +100,7 @@ struct expm_plan_s {
     xpm::host::Buf b_dg;
     // panels of four block rows for the product (p_*: origin, words, column
     // counts and lists, work groups)
-    xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols;
+    xpm::host::Buf p_lo, p_words, p_woff, p_cnt, p_ofs, p_gcnt, p_gofs, p_cols, p_owner, g_owner;
     // block-column lists of T (the block rows of T^T) for the adjoint; the
     // adjoint step's output tiles in the B and A operand layouts
     xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles, adj_tilesA;
