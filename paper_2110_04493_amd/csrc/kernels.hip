@@ -657,6 +657,7 @@ hipError_t add_write(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, dou
 // marked in a bit map over the row's column window (prefix counts give each
 // its rank); the terms then add into an accumulator per rank, one term after
 // the other, and the nonzero sums are counted or written in column order.
+constexpr int kSumBatch = 8;      // terms whose first chunks load together
 constexpr int kSumWaves = 4;      // rows per workgroup
 constexpr int kSumWords = 512;    // bit-map words per wave (16384 columns)
 constexpr int kSumAcc = 256;      // distinct columns per wave (sparse rows)
@@ -714,12 +715,14 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
     };
     int mn = INT32_MAX, mx = -1;
     int64_t ub = 0;
+    int64_t tb = 0, te = 0;   // lane t < m: term t's entries of row i
     if (lane < T.m) {
-        const int64_t b = T.rp[lane][i], e = T.rp[lane][i + 1];
-        if (e > b) {
-            mn = T.ci[lane][b];
-            mx = T.ci[lane][e - 1];
-            ub = e - b;
+        tb = T.rp[lane][i];
+        te = T.rp[lane][i + 1];
+        if (te > tb) {
+            mn = T.ci[lane][tb];
+            mx = T.ci[lane][te - 1];
+            ub = te - tb;
         }
     }
     mn = wave_min(mn);
@@ -791,11 +794,32 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
     int32_t *col = big ? (int32_t *)(acc + ub) : (int32_t *)(acc + kSumAcc);
     for (int w = lane; w < W; w += kWave) bits[w] = make_uint2(0u, 0u);
     sync_wave();
-    for (int t = 0; t < T.m; ++t) {
-        const int64_t b = T.rp[t][i], e = T.rp[t][i + 1];
-        for (int64_t p = b + lane; p < e; p += kWave) {
-            const int d = T.ci[t][p] - lo;
-            atomicOr(&bits[d >> 5].x, 1u << (d & 31));
+    // the first 64 entries of kSumBatch terms are loaded together; longer
+    // term rows continue one chunk at a time
+    for (int t0 = 0; t0 < T.m; t0 += kSumBatch) {
+        int c[kSumBatch];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int t = t0 + u;
+            c[u] = -1;
+            if (t < T.m) {
+                const int64_t p = readlane_i64_(tb, t) + lane;
+                if (p < readlane_i64_(te, t)) c[u] = T.ci[t][p];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            if (c[u] >= 0) {
+                const int d = c[u] - lo;
+                atomicOr(&bits[d >> 5].x, 1u << (d & 31));
+            }
+            const int t = t0 + u;
+            if (t >= T.m) continue;
+            const int64_t e = readlane_i64_(te, t);
+            for (int64_t p = readlane_i64_(tb, t) + kWave + lane; p < e; p += kWave) {
+                const int d = T.ci[t][p] - lo;
+                atomicOr(&bits[d >> 5].x, 1u << (d & 31));
+            }
         }
     }
     sync_wave();
@@ -815,16 +839,42 @@ __global__ __launch_bounds__(kWave * kSumWaves) void k_sum_terms(SumTerms T, int
         const uint2 e2 = bits[d >> 5];
         return (int)(e2.y + __popc(e2.x & ((1u << (d & 31)) - 1u)));
     };
-    // terms in order; within one term a row's columns are distinct
-    for (int t = 0; t < T.m; ++t) {
-        const int64_t b = T.rp[t][i], e = T.rp[t][i + 1];
-        for (int64_t p = b + lane; p < e; p += kWave) {
-            const int c = T.ci[t][p];
-            const int r = rank(c);
-            acc[r] += T.v[t][p];
-            col[r] = c;
+    // terms in order; within one term a row's columns are distinct.  The
+    // first 64 entries of kSumBatch terms are loaded together.
+    for (int t0 = 0; t0 < T.m; t0 += kSumBatch) {
+        int c[kSumBatch];
+        double v[kSumBatch];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int t = t0 + u;
+            c[u] = -1;
+            v[u] = 0.0;
+            if (t < T.m) {
+                const int64_t p = readlane_i64_(tb, t) + lane;
+                if (p < readlane_i64_(te, t)) {
+                    c[u] = T.ci[t][p];
+                    v[u] = T.v[t][p];
+                }
+            }
         }
-        sync_wave();
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int t = t0 + u;
+            if (t >= T.m) break;
+            if (c[u] >= 0) {
+                const int r = rank(c[u]);
+                acc[r] += v[u];
+                col[r] = c[u];
+            }
+            const int64_t e = readlane_i64_(te, t);
+            for (int64_t p = readlane_i64_(tb, t) + kWave + lane; p < e; p += kWave) {
+                const int cc = T.ci[t][p];
+                const int r = rank(cc);
+                acc[r] += T.v[t][p];
+                col[r] = cc;
+            }
+            sync_wave();
+        }
     }
     if (!kWrite) {
         long long k = 0;
