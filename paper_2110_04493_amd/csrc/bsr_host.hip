@@ -17,9 +17,36 @@ void release(expm_plan_s &P, TileSet &ts) {
 }
 
 // Tile pattern of T (origin, bit maps with prefix counts, tile bases) and
-// T's fill: stored entries over tile slots.
-int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill) {
+// C's tile pattern counts for C = 2T + T*T from T's tile pattern ts: per
+// block row the origin and bit-map words (P.c_lo, P.c_words, P.c_woff) and
+// the tile counts (P.c_cnt, P.c_tb); the totals are c_woff[nb], c_tb[nb].
+static int c_pattern_count(expm_plan_s &P, const TileSet &ts, int64_t n) {
     hipStream_t st = P.st;
+    const int64_t nb = ts.nb;
+    CHK(ensure(P, P.c_lo, sizeof(int32_t) * (nb + 1)));
+    CHK(ensure(P, P.c_words, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.c_woff, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.c_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.c_tb, sizeof(int64_t) * (nb + 1)));
+    const int32_t *lo = (const int32_t *)ts.lo.p;
+    const int64_t *woff = (const int64_t *)ts.woff.p, *tb = (const int64_t *)ts.tb.p;
+    const uint2 *rt = (const uint2 *)ts.rt.p;
+    HIPCHK(bsr_cbounds(nb, lo, woff, rt, tb, (int32_t *)P.c_lo.p, (int64_t *)P.c_words.p, st));
+    CHK(scan(P, (const int64_t *)P.c_words.p, (int64_t *)P.c_woff.p, nb));
+    HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
+                        (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p, nullptr, nullptr,
+                        nullptr, st));
+    CHK(scan(P, (const int64_t *)P.c_cnt.p, (int64_t *)P.c_tb.p, nb));
+    return EXPM_OK;
+}
+
+// T's fill: stored entries over tile slots.  With with_c, the counts of the
+// product's tile pattern are taken too and read back with T's tile count
+// (one wait instead of two), for the tile_product call that follows.
+int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill,
+                bool with_c) {
+    hipStream_t st = P.st;
+    P.c_pre = false;
     const int64_t n = T.n, nb = (n + 15) / 16;
     ts.nb = nb;
     CHK(ensure(P, ts.lo, sizeof(int32_t) * (nb + 1)));
@@ -44,10 +71,22 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
     HIPCHK(bsr_bitmap(T, nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
                       (uint2 *)ts.rt.p, (int64_t *)ts.cnt.p, st));
     CHK(scan(P, (const int64_t *)ts.cnt.p, (int64_t *)ts.tb.p, nb));
+    if (with_c) CHK(c_pattern_count(P, ts, n));
     HIPCHK(hipMemcpyAsync(hl, (int64_t *)ts.tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
+    if (with_c) {
+        HIPCHK(hipMemcpyAsync(hl + 1, (int64_t *)P.c_tb.p + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hl + 2, (int64_t *)P.c_woff.p + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+    }
     CHK(sync(P));
     ts.ntiles = hl[0];
+    if (with_c) {
+        P.c_pre = true;
+        P.c_pre_tiles = hl[1];
+        P.c_pre_words = hl[2];
+    }
     CHK(ensure(P, ts.cols, sizeof(int32_t) * (ts.ntiles + 1)));
     CHK(ensure(P, ts.rows, sizeof(int32_t) * (ts.ntiles + 1)));
     HIPCHK(bsr_tcols(nb, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
@@ -84,27 +123,26 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
     const int64_t n = T.n, nb = ts.nb;
     int64_t *hl = (int64_t *)P.host;
     CHK(bsr_tiles(P, T, ts));
-    // C's tile pattern
-    CHK(ensure(P, P.c_lo, sizeof(int32_t) * (nb + 1)));
-    CHK(ensure(P, P.c_words, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.c_woff, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.c_cnt, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.c_tb, sizeof(int64_t) * (nb + 1)));
+    // C's tile pattern (its counts already read back by bsr_pattern when it
+    // ran with with_c just before)
     const int32_t *lo = (const int32_t *)ts.lo.p;
     const int64_t *woff = (const int64_t *)ts.woff.p, *tb = (const int64_t *)ts.tb.p;
     const uint2 *rt = (const uint2 *)ts.rt.p;
-    HIPCHK(bsr_cbounds(nb, lo, woff, rt, tb, (int32_t *)P.c_lo.p, (int64_t *)P.c_words.p, st));
-    CHK(scan(P, (const int64_t *)P.c_words.p, (int64_t *)P.c_woff.p, nb));
-    HIPCHK(bsr_cpattern(n, nb, lo, woff, rt, (const int32_t *)P.c_lo.p,
-                        (const int64_t *)P.c_woff.p, (int64_t *)P.c_cnt.p, nullptr, nullptr,
-                        nullptr, st));
-    CHK(scan(P, (const int64_t *)P.c_cnt.p, (int64_t *)P.c_tb.p, nb));
-    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.c_tb.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
-                          st));
-    HIPCHK(hipMemcpyAsync(hl + 2, (int64_t *)P.c_woff.p + nb, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, st));
-    CHK(sync(P));
-    const int64_t ctiles = hl[0], cwords = hl[2];
+    int64_t ctiles, cwords;
+    if (P.c_pre) {
+        ctiles = P.c_pre_tiles;
+        cwords = P.c_pre_words;
+        P.c_pre = false;
+    } else {
+        CHK(c_pattern_count(P, ts, n));
+        HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.c_tb.p + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hl + 2, (int64_t *)P.c_woff.p + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        ctiles = hl[0];
+        cwords = hl[2];
+    }
     CHK(ensure(P, P.c_cols, sizeof(int32_t) * (ctiles + 1)));
     CHK(ensure(P, P.c_tiles, sizeof(double) * 256 * (size_t)(ctiles + 1)));
     CHK(ensure(P, P.c_rt, sizeof(uint2) * (cwords + 1)));

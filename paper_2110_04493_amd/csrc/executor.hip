@@ -622,17 +622,21 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
     } else {
         if (!addI && tiles_allowed(P, n)) {
             double fill = 0.0;
-            CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill));
+            // once a step has run on tiles the next ones will too (the fill
+            // grows with the band): take the product's pattern counts along
+            const bool likely = !P.sq_path.empty() && P.sq_path.back() != 0;
+            CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill, likely));
             have_pattern = true;
             tiles = P.tsT.ntiles > 0 && P.tsT.ntiles < INT32_MAX && fill >= P.bsr_min_fill;
         }
         if (step >= 1) P.sq_path.push_back(tiles ? 1 : 0);
     }
     if (stat_i > 0 && stat_i < EXPM_MAXSTEP && !tiles) P.stats.sq_tiles[stat_i] = 0;
+    if (!tiles) P.c_pre = false;
     if (tiles) {
         if (!have_pattern) {
             double fill;
-            CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill));
+            CHK(bsr_pattern(P, T.view(), T.nnz, P.tsT, &fill, true));
         }
         return square_step_bsr(P, T, dst, a_ri, use_fixed, theta_fixed, exact_alloc, stat_i);
     }

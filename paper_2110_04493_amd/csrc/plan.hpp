@@ -81,6 +81,10 @@ struct expm_plan_s {
     // profiling: events around the phases of the last sparse product
     hipEvent_t ev[8] = {};
     bool have_events = false;
+    // C's tile count and rank-table size, read back with T's tile count by
+    // bsr_pattern(with_c) for the tile product that follows it
+    bool c_pre = false;
+    int64_t c_pre_tiles = 0, c_pre_words = 0;
     // opts.profile == 2: an event pair around every tile product (kind 0) and
     // adjoint tile (kind 1) launch, read once the call has synchronised
     std::vector<hipEvent_t> kt_ev;
@@ -164,7 +168,8 @@ int transpose_pos(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
 int check_view(const expm_csr_cview *H);
 void free_adjoint_state(expm_plan_s &P);
-int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill);
+int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill,
+                bool with_c = false);
 int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts);
 bool tiles_allowed(const expm_plan_s &P, int64_t n);
 int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out);
