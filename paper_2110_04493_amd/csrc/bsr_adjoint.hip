@@ -96,10 +96,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ ck,
     const int64_t *__restrict__ ct,
     const int64_t *__restrict__ gofs, const int32_t *__restrict__ owner,
-    double *__restrict__ out, double *__restrict__ outA, int64_t nwork) {
+    double *__restrict__ out, double *__restrict__ outA, const int64_t *__restrict__ nwork_dev) {
     const int lane = lane_id();
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (w >= nwork) return;
+    if (w >= *nwork_dev) return;   // the grid covers a bound of the count
     const int64_t I = owner[w];   // the block row: gofs[I] <= w < gofs[I + 1]
     const int64_t t0 = (w - gofs[I]) * kGroup;             // first tile (rank in block row I)
     const int64_t cntI = ttb[I + 1] - ttb[I];
@@ -262,12 +262,12 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
                        const int64_t *gofs, const int32_t *owner, double *out, double *outA,
-                       int64_t nwork, hipStream_t st) {
+                       const int64_t *nwork_dev, int64_t nwork, hipStream_t st) {
     if (nwork == 0) return hipSuccess;
     const dim3 grid((unsigned)((nwork + 3) / 4)), block(256);
 #define XPM_ADJ_ARGS                                                                           \
     nb, tlo, twoff, trt, ttb, tcols, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, \
-        gofs, owner, out, outA, nwork
+        gofs, owner, out, outA, nwork_dev
     if (kAdjSplit) {
         hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1>), grid, block, 0, st, XPM_ADJ_ARGS);
         hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2>), grid, block, 0, st, XPM_ADJ_ARGS);

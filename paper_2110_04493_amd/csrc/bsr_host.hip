@@ -410,11 +410,9 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     CHK(ensure(P, P.g_ofs, sizeof(int64_t) * (nb + 1)));
     HIPCHK(bsr_groups4((const int64_t *)T.tb.p, nb, (int64_t *)P.g_cnt.p, st));
     CHK(scan(P, (const int64_t *)P.g_cnt.p, (int64_t *)P.g_ofs.p, nb));
-    int64_t *hl = (int64_t *)P.host;
-    HIPCHK(hipMemcpyAsync(hl, (int64_t *)P.g_ofs.p + nb, sizeof(int64_t), hipMemcpyDeviceToHost,
-                          st));
-    CHK(sync(P));
-    const int64_t nwork = hl[0];
+    // launched on a bound of the work-item count (each block row rounds up
+    // once); the kernel reads the exact count, g_ofs[nb]
+    const int64_t nwork = T.ntiles / 4 + nb + 1;
     CHK(ensure(P, P.g_owner, sizeof(int32_t) * (nwork + 1)));
     HIPCHK(work_owner((const int64_t *)P.g_ofs.p, nb, (int32_t *)P.g_owner.p, st));
     CHK(ensure(P, P.adj_tiles, sizeof(double) * 256 * (size_t)(T.ntiles + 1)));
@@ -431,7 +429,7 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
                        (const int64_t *)P.g_ofs.p, (const int32_t *)P.g_owner.p,
                        (double *)P.adj_tiles.p,
-                       (double *)P.adj_tilesA.p, nwork, st));
+                       (double *)P.adj_tilesA.p, (const int64_t *)P.g_ofs.p + nb, nwork, st));
     if (light_profile(P)) CHK(ktimer_mark(P, 1));
     if (prof) {
         HIPCHK(hipEventRecord(P.ev[5], st));

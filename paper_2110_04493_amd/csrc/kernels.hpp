@@ -177,7 +177,7 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
                        const int64_t *gofs, const int32_t *owner, double *out, double *outA,
-                       int64_t nwork, hipStream_t st);
+                       const int64_t *nwork_dev, int64_t nwork, hipStream_t st);
 hipError_t bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                       const int64_t *tb, const double *tiles, double *out, hipStream_t st);
 
