@@ -190,11 +190,11 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(CsrView T, int64_t ntiles,
         bB[4 * lane + q] = 0.0;
     }
     wfence();
-    const int64_t I = trows[tt];
+    // rows past the matrix have no segment (the table starts zeroed), so the
+    // segment loads need nothing else first
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         const int r = 4 * rr + (lane >> 4);
-        if (I * kTile + r >= T.n) continue;
         const int64_t s = seg[tt * kTile + r];
         const int j = lane & 15;
         if (j < (int)(s & 31)) {
@@ -209,6 +209,7 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(CsrView T, int64_t ntiles,
     *(d4 *)(tA + tt * kTileElems + 4 * lane) = *(const d4 *)(bA + 4 * lane);
     *(d4 *)(tB + tt * kTileElems + 4 * lane) = *(const d4 *)(bB + 4 * lane);
     (void)tcols;
+    (void)trows;
 }
 
 // ----------------------------------------------------------------- C pattern
