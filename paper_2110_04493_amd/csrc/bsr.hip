@@ -76,7 +76,10 @@ __global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const 
     wfence();
     const int base = lo[I];
     // the block row's 16 rows are one contiguous range of entries; four
-    // chunks of 64 are loaded before their bits are set
+    // chunks of 64 are loaded before their bits are set.  Within a row the
+    // columns ascend, so neighbouring lanes mostly share a block column:
+    // only the first lane of each run sets its bit (a dense row would
+    // otherwise send 64 atomics per instruction to the same word)
     const int64_t p0 = T.rp[I * kTile], p1 = T.rp[min<int64_t>(I * kTile + kTile, T.n)];
     for (int64_t q = p0; q < p1; q += 4 * kWave) {
         int c[4];
@@ -86,11 +89,13 @@ __global__ __launch_bounds__(64) void k_bsr_bitmap(CsrView T, int64_t nb, const 
             c[u] = p < p1 ? T.ci[p] >> 4 : -1;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (c[u] >= 0) {
+        for (int u = 0; u < 4; ++u) {
+            const int prev = __shfl_up(c[u], 1);
+            if (c[u] >= 0 && (lane == 0 || prev != c[u])) {
                 const int d = c[u] - base;
                 atomicOr(&bm[d >> 5], 1u << (d & 31));
             }
+        }
     }
     wfence();
     unsigned carry = 0;
