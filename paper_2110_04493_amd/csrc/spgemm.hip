@@ -178,9 +178,12 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
 
 // Calls f(col, valid) on every lane for each chunk of 64 entries of the
 // right-factor rows that row i of A selects (valid = the lane holds an
-// entry).  All lanes take part, so f may use cross-lane operations.
-template <class F>
-__device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, int64_t i, F &&f) {
+// entry).  All lanes take part, so f may use cross-lane operations.  Rows
+// of at most kTinyLen entries, eight to a chunk, go instead to g(col), once
+// for every lane that holds an entry (g works lane by lane).
+template <class F, class G>
+__device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, int64_t i, F &&f,
+                                           G &&g) {
     const int lane = lane_id();
     const int64_t b = A.rp[i], e = A.rp[i + 1];
     for (int64_t p0 = b; p0 < e; p0 += kWave) {
@@ -204,10 +207,7 @@ __device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, i
                     const int64_t q0 = __shfl(s0, src), q1 = __shfl(s1, src);
                     const int64_t q = q0 + h;
                     const int c = u < un && q < q1 ? B.ci[q] : -1;
-                    // every lane takes part in every call; only one row's
-                    // lanes are valid in each, in the left row's order
-#pragma unroll
-                    for (int g = 0; g < kTinyRows; ++g) f(c, u == g && c >= 0);
+                    if (c >= 0) g(c);
                     j += un;
                     continue;
                 }
@@ -422,6 +422,9 @@ __global__ __launch_bounds__(512) void k_symbolic(CsrView A, CsrView B, int addA
         } else {
             atomicOr(&bm[w], 1u << (d & 31));
         }
+    }, [&](int col) {
+        const int d = col - base;
+        atomicOr(&bm[d >> 5], 1u << (d & 31));
     });
     phase_fence<kGlobal>();
     long long s = 0;
