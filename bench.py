@@ -138,7 +138,7 @@ def numeric_roofline(stats: dict, n: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus N > 1 is not "
+        print(json.dumps({"error": "the library runs on exactly one GPU; --gpus N > 1 is not "
                                    "supported (see the multi-GPU design notes)"}))
         sys.exit(2)
     if args.copy_calibration:
