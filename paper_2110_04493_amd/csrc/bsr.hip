@@ -688,31 +688,35 @@ __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
     };
     for (int64_t c0 = 0; c0 < cntI; c0 += kWave) {
         // one lane per tile: which of 64 tiles keep anything, and their block
-        // columns, in one round trip; then the tiles that do, in order, the
-        // next one's load in flight while the current one is written
+        // columns, in one round trip; then the tiles that do, in order, with
+        // the loads of the next two in flight while the current one is written
         const int64_t t = c0 + lane;
         const bool some = t < cntI && (!tmx || tmx[base + t] > theta);
         const int bc = some ? ccols[base + t] : 0;
         unsigned long long m = __ballot(some);
-        if (!m) continue;
-        int l = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        int col = 16 * __builtin_amdgcn_readlane(bc, l) + cl;
-        d4 v = *(const d4 *)(ctiles + (base + c0 + l) * kTileElems + 4 * lane);
-        for (;;) {
-            const bool more = m != 0;
-            int col2 = col;
-            d4 v2 = v;
-            if (more) {
-                l = __ffsll((long long)m) - 1;
-                m &= m - 1;
-                col2 = 16 * __builtin_amdgcn_readlane(bc, l) + cl;
-                v2 = *(const d4 *)(ctiles + (base + c0 + l) * kTileElems + 4 * lane);
-            }
-            emit(col, v);
-            if (!more) break;
-            col = col2;
-            v = v2;
+        auto pop = [&](int &col, d4 &v) {
+            if (!m) return false;
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            col = 16 * __builtin_amdgcn_readlane(bc, l) + cl;
+            v = *(const d4 *)(ctiles + (base + c0 + l) * kTileElems + 4 * lane);
+            return true;
+        };
+        int col0 = 0, col1 = 0;
+        d4 v0 = d4{0.0, 0.0, 0.0, 0.0}, v1 = v0;
+        bool h0 = pop(col0, v0);
+        bool h1 = pop(col1, v1);
+        while (h0) {
+            int col2 = 0;
+            d4 v2 = d4{0.0, 0.0, 0.0, 0.0};
+            const bool h2 = pop(col2, v2);
+            emit(col0, v0);
+            col0 = col1;
+            v0 = v1;
+            h0 = h1;
+            col1 = col2;
+            v1 = v2;
+            h1 = h2;
         }
     }
 }
