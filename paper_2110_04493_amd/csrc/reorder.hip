@@ -10,12 +10,14 @@
 // neighbouring line; grouping nodes into compact 2D cells roughly halves the
 // tiles per block row and the matrix-core work of the late squarings.
 //
-// The cells come from graph distances alone, with no coordinates: breadth-
+// The order comes from graph distances alone, with no coordinates: breadth-
 // first distances d1, d3 from two far-apart nodes (u1, the node farthest
 // from node 0, and u3, the node farthest from both node 0 and u1) act as two
-// coordinates, and nodes are grouped by (d1 / 4, d3 / 8) and ordered by
-// cell, then by index.  Graphs without such structure (small diameter, so
-// very full cells) keep their order.
+// coordinates.  Nodes are cut into strips of kStrip values of d1; each strip
+// is walked along d3 (every other strip backwards) and, for one value of d3,
+// by d1 and then index.  On a 2D mesh a run of 16 consecutive nodes is then
+// a compact patch, and a patch's neighbours lie in few runs.  Graphs without
+// such structure (small diameter, so very full cells) keep their order.
 #include <string.h>
 
 #include "plan.hpp"
@@ -24,6 +26,7 @@ namespace xpm {
 
 constexpr int kBfsThreads = 1024;
 constexpr int kCellMax = 256;      // largest cell the ordering accepts
+constexpr int kStrip = 5;          // d1 values per strip
 constexpr int kPermWaves = 4;        // output rows (waves) per workgroup
 constexpr int kPermLdsWords = 1024;  // bit-map words per wave in LDS
 constexpr int kPermCache = 32;       // mapped columns held per lane
@@ -223,12 +226,16 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_
     }
 }
 
-// Cell of every node and the cell populations.
-__global__ void k_cell_count(int64_t n, const int32_t *d1, const int32_t *d3, int64_t kb,
+// Cell of every node and the cell populations: strips of kStrip values of
+// d1, each walked along d3, every other strip in the opposite direction;
+// a cell is one value of d3 within a strip.
+__global__ void k_cell_count(int64_t n, const int32_t *d1, const int32_t *d3, int64_t maxd3,
                              int64_t *cell, int64_t *cnt) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int64_t c = (int64_t)(d1[v] / 4) * kb + d3[v] / 8;
+    const int64_t strip = d1[v] / kStrip;
+    const int64_t pos = (strip & 1) ? maxd3 - d3[v] : d3[v];
+    const int64_t c = strip * (maxd3 + 1) + pos;
     cell[v] = c;
     atomicAdd((unsigned long long *)&cnt[c], 1ull);
 }
@@ -258,17 +265,22 @@ __global__ void k_cell_scatter(int64_t n, const int64_t *cell, const int64_t *co
     tmp[pos] = (int32_t)v;
 }
 
-// One wave per cell: members in ascending node index (rank by counting).
+// One wave per cell: members by ascending d1, then node index (rank by
+// counting).
 __global__ void k_cell_sort(int64_t ncell, const int64_t *coff, const int32_t *tmp,
-                            int32_t *order, int32_t *newidx) {
+                            const int32_t *d1, int32_t *order, int32_t *newidx) {
     const int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (c >= ncell) return;
     const int64_t o = coff[c];
     const int k = (int)(coff[c + 1] - o);
     for (int j = lane_id(); j < k; j += kWave) {
         const int32_t x = tmp[o + j];
+        const int32_t dx = d1[x];
         int r = 0;
-        for (int i = 0; i < k; ++i) r += tmp[o + i] < x;
+        for (int i = 0; i < k; ++i) {
+            const int32_t y = tmp[o + i], dy = d1[y];
+            r += dy < dx || (dy == dx && y < x);
+        }
         order[o + r] = x;
         newidx[x] = (int32_t)(o + r);
     }
@@ -445,7 +457,7 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
     HIPCHK(hipMemcpyAsync(hb, rb, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, st));
     CHK(sync(P));
     const int64_t maxd1 = hb[4], maxd3 = hb[8];
-    const int64_t kb = maxd3 / 8 + 1, ncell = (maxd1 / 4 + 1) * kb;
+    const int64_t ncell = (maxd1 / kStrip + 1) * (maxd3 + 1);
     if (ncell > 4 * n + 1024) return EXPM_OK;   // path-like: the natural order is kept
     CHK(ensure(P, P.ro_cell, sizeof(int64_t) * n));
     CHK(ensure(P, P.ro_cnt, sizeof(int64_t) * (ncell + 1)));
@@ -453,7 +465,7 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
     int64_t *cell = (int64_t *)P.ro_cell.p, *cnt = (int64_t *)P.ro_cnt.p,
             *off = (int64_t *)P.ro_off.p;
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (ncell + 1), st));
-    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d1, d3, kb,
+    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d1, d3, maxd3,
                        cell, cnt);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_max_i64, dim3(blocks_for(ncell, 256) < 1024 ? blocks_for(ncell, 256)
@@ -471,7 +483,7 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
                        cnt, q0);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(ncell, 4)), dim3(256), 0, st, ncell, off,
-                       q0, (int32_t *)P.order.p, (int32_t *)P.newidx.p);
+                       q0, d1, (int32_t *)P.order.p, (int32_t *)P.newidx.p);
     HIPCHK(hipGetLastError());
     *active = true;
     return EXPM_OK;
