@@ -61,7 +61,9 @@ def parse():
     return ap.parse_args()
 
 
-TILE_SOURCES = ("paper_2110_04493_amd/csrc/bsr.hip", "paper_2110_04493_amd/csrc/bsr_common.hpp")
+# the tile kernels and the locality ordering that shapes their tiles
+TILE_SOURCES = ("paper_2110_04493_amd/csrc/bsr.hip", "paper_2110_04493_amd/csrc/bsr_common.hpp",
+                "paper_2110_04493_amd/csrc/reorder.hip")
 TRAFFIC_FILE = "profiles/k_bsr_numeric_panel_grid300_traffic.md"
 
 
