@@ -100,10 +100,14 @@ typedef struct {
                                 sq_in, tile_* and adj_tile_* of expm_stats);
                                 this waits for the device after every step.
                                 2: only an event pair around every launch of
-                                the tile product and the adjoint tile kernel,
-                                read once the call has synchronised (fields
-                                tile_launches, tile_ms, adj_tile_launches,
-                                adj_tile_ms; tile_flops stays 0).
+                                the tile product and the adjoint tile kernel
+                                (fields tile_launches, tile_ms,
+                                adj_tile_launches, adj_tile_ms; tile_flops
+                                stays 0), and one around the whole forward
+                                (t_total_ms); expm_sparse does not wait for
+                                them: they are read at the next wait of the
+                                plan (the end of expm_sparse_backward,
+                                expm_get_stats, or the next call).
                                 0 (default): off                              */
     int reorder;             /* locality reordering: the rows and columns of H
                                 are permuted symmetrically (2D cells from graph
@@ -136,8 +140,12 @@ typedef struct {
     /* with opts.profile == 1: per squaring step i, the partial products of
      * T*T (sq_fma), the stored entries of the input iterate (sq_in), and the
      * device time in ms of the symbolic, numeric and filter+compaction
-     * phases; t_taylor_ms is the whole Taylor phase, t_backward_ms the last
-     * expm_sparse_backward call. */
+     * phases; t_taylor_ms is the whole Taylor phase.  t_total_ms is the
+     * last expm_sparse call: its wall time after a final wait with profile
+     * 1, its device time between two events with profile 2, and only the
+     * host's part of it with profile 0 (no final wait).  t_backward_ms is
+     * the wall time of the last expm_sparse_backward call, which always
+     * ends with a wait. */
     int64_t sq_fma[EXPM_MAXSTEP], sq_in[EXPM_MAXSTEP];
     double t_sym_ms[EXPM_MAXSTEP], t_num_ms[EXPM_MAXSTEP], t_filter_ms[EXPM_MAXSTEP];
     double t_taylor_ms, t_backward_ms, t_total_ms;

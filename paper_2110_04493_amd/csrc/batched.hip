@@ -686,6 +686,7 @@ extern "C" int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cvie
     using namespace xpm::host;
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
     BatchBufs B;
+    collect_forward(*p);
     p->kt_used = 0;
     p->kt_kind.clear();
     int s = batched(*p, B, count, H, eps, E);

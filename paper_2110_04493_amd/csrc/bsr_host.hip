@@ -457,11 +457,12 @@ int ktimer_mark(expm_plan_s &P, int kind) {
     return EXPM_OK;
 }
 
-void ktimer_collect(expm_plan_s &P) {
-    for (size_t j = 0; j + 1 < P.kt_used; j += 2) {
+void ktimer_collect_set(expm_plan_s &P, std::vector<hipEvent_t> &ev, std::vector<char> &kind,
+                       size_t &used) {
+    for (size_t j = 0; j + 1 < used; j += 2) {
         float t = 0.f;
-        if (hipEventElapsedTime(&t, P.kt_ev[j], P.kt_ev[j + 1]) != hipSuccess) continue;
-        if (P.kt_kind[j / 2] == 0) {
+        if (hipEventElapsedTime(&t, ev[j], ev[j + 1]) != hipSuccess) continue;
+        if (kind[j / 2] == 0) {
             P.stats.tile_launches += 1;
             P.stats.tile_ms += t;
         } else {
@@ -470,8 +471,20 @@ void ktimer_collect(expm_plan_s &P) {
         }
     }
     (void)hipGetLastError();
-    P.kt_used = 0;
-    P.kt_kind.clear();
+    used = 0;
+    kind.clear();
+}
+
+void ktimer_collect(expm_plan_s &P) { ktimer_collect_set(P, P.kt_ev, P.kt_kind, P.kt_used); }
+
+// The timers of a forward run in profile mode 2, once its events are done.
+void collect_forward(expm_plan_s &P) {
+    if (!P.fwd_pending) return;
+    (void)hipEventSynchronize(P.ev[7]);
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, P.ev[6], P.ev[7]) == hipSuccess) P.stats.t_total_ms = t;
+    ktimer_collect_set(P, P.kt_ev_fwd, P.kt_kind_fwd, P.kt_used_fwd);
+    P.fwd_pending = false;
 }
 
 int gather_tiles(expm_plan_s &P, const DCsr &A, const TileSet &ts, const double *tiles,

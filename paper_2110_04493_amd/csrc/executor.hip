@@ -1245,14 +1245,30 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
 int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E) {
     g_err.clear();
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
+    collect_forward(*p);
     const auto t0 = std::chrono::steady_clock::now();
     p->kt_used = 0;
     p->kt_kind.clear();
+    const bool lazy = light_profile(*p);
+    if (lazy) (void)hipEventRecord(p->ev[6], p->st);
     int s = forward(*p, H, eps, E);
     if (s == EXPM_OK) {
-        (void)hipStreamSynchronize(p->st);
-        p->stats.t_total_ms = ms_since(t0);
-        ktimer_collect(*p);
+        if (lazy) {
+            // no wait: the timers are read after a later one
+            (void)hipEventRecord(p->ev[7], p->st);
+            std::swap(p->kt_ev, p->kt_ev_fwd);
+            std::swap(p->kt_kind, p->kt_kind_fwd);
+            std::swap(p->kt_used, p->kt_used_fwd);
+            p->kt_used = 0;
+            p->kt_kind.clear();
+            p->fwd_pending = true;
+        } else if (p->opts.profile == 1) {
+            (void)hipStreamSynchronize(p->st);
+            p->stats.t_total_ms = ms_since(t0);
+            ktimer_collect(*p);
+        } else {
+            p->stats.t_total_ms = ms_since(t0);   // host time of the call
+        }
     }
     if (s != EXPM_OK) {
         p->stats.status = s;
@@ -1280,6 +1296,7 @@ int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals) 
     int s = backward(*p, dE_vals, dH_vals);
     if (s == EXPM_OK) {
         p->stats.t_backward_ms = ms_since(t0);
+        collect_forward(*p);   // the backward has waited for the device
         ktimer_collect(*p);
     }
     if (s != EXPM_OK) {
@@ -1293,6 +1310,7 @@ int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals) 
 int expm_get_stats(expm_plan_t p, expm_stats *out) {
     if (!p || !out) return fail(EXPM_EINVAL, "NULL argument");
     if (!p->have_stats) return fail(EXPM_ESTATE, "no call has completed on this plan");
+    collect_forward(*p);
     *out = p->stats;
     return EXPM_OK;
 }
@@ -1337,6 +1355,7 @@ void expm_free(expm_plan_t p) {
     if (P.have_events)
         for (hipEvent_t &e : P.ev) (void)hipEventDestroy(e);
     for (hipEvent_t &e : P.kt_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t &e : P.kt_ev_fwd) (void)hipEventDestroy(e);
     if (P.host) (void)hipHostFree(P.host);
     (void)hipGetLastError();
     delete p;

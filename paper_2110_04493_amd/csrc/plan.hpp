@@ -90,6 +90,14 @@ struct expm_plan_s {
     std::vector<hipEvent_t> kt_ev;
     std::vector<char> kt_kind;
     size_t kt_used = 0;
+    // ... and the forward's timers are read only after a later wait (the
+    // end of expm_sparse_backward, expm_get_stats or the next forward), so
+    // that expm_sparse returns without waiting: they move to this second
+    // set, and ev[6] / ev[7] bracket the forward
+    std::vector<hipEvent_t> kt_ev_fwd;
+    std::vector<char> kt_kind_fwd;
+    size_t kt_used_fwd = 0;
+    bool fwd_pending = false;
     int64_t last_fma = 0;
     // 16 x 16 tile path of the squaring: T's tile pattern (origin, bit-map
     // words, rank tables, tile bases), its tiles in both operand layouts, C's
@@ -198,6 +206,9 @@ void release(expm_plan_s &P, TileSet &ts);
 bool light_profile(const expm_plan_s &P);
 int ktimer_mark(expm_plan_s &P, int kind);
 void ktimer_collect(expm_plan_s &P);
+void collect_forward(expm_plan_s &P);
+void ktimer_collect_set(expm_plan_s &P, std::vector<hipEvent_t> &ev, std::vector<char> &kind,
+                       size_t &used);
 int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
                 const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap);
