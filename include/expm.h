@@ -110,7 +110,7 @@ typedef struct {
                                 expm_get_stats, or the next call).
                                 0 (default): off                              */
     int reorder;             /* locality reordering: the rows and columns of H
-                                are permuted symmetrically (2D cells from graph
+                                are permuted symmetrically (strips of graph
                                 distances) before the method runs and E is
                                 permuted back, so that band tiles of the late
                                 squarings are fuller.  Results are those of
