@@ -82,6 +82,18 @@ def test_reorder_matches_natural_order():
     assert (sa["M"], sa["N"]) == (sb["M"], sb["N"])
 
 
+def test_reorder_fills_tiles():
+    """The locality ordering packs the band of a 60 x 60 grid into far fewer
+    16 x 16 tiles than the natural order (every squaring on tiles; on the
+    oracle's last iterate the strips need about half the tiles)."""
+    H, eps = W.config5(60)
+    _, sa = run_gpu(H, eps, reorder=0, tile_min_fill=0.0)
+    _, sb = run_gpu(H, eps, reorder=1, tile_min_fill=0.0)
+    ta, tb = sa["sq_tiles"][-1], sb["sq_tiles"][-1]   # steps 1 .. N in order
+    print(f"[reorder tiles] last step: natural {ta}, ordered {tb}", flush=True)
+    assert 0 < tb < 0.8 * ta
+
+
 @pytest.mark.parametrize("reorder", [0, 1])
 def test_adjoint_mixed_paths(reorder):
     """Fill thresholds between the two paths: the late squaring steps run on
