@@ -330,11 +330,39 @@ int ora_choose_mn(double nh, double eps, int *Mout, int *Nout) {
 /* Algorithm 4.1                                                           */
 /* ---------------------------------------------------------------------- */
 
-/* Filter the value array v (length m) against the budget eg.  On return
- * keep[j] = 1 for the entries that stay in the filtered matrix, *theta is the
- * last entry threshold eps_f and *iters the number of passes.  The vector b
- * of the algorithm is represented by the flags inb[j] (entry j still in b).
- * With eg <= 0 only exact zeros are dropped. */
+/* Sum of v_j^2 over the entries with |v_j| <= theta (the dropped set of a
+ * threshold), in the fixed chunk order of sumsq_masked. */
+static double dropped_sumsq(const double *v, int64_t m, double theta) {
+    int64_t nch = (m + ORA_CHUNK - 1) / ORA_CHUNK;
+    double *part = (double *)malloc((size_t)(nch > 0 ? nch : 1) * sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nch; c++) {
+        int64_t lo = c * ORA_CHUNK, hi = lo + ORA_CHUNK < m ? lo + ORA_CHUNK : m;
+        double s = 0.0;
+        for (int64_t j = lo; j < hi; j++)
+            if (fabs(v[j]) <= theta) s += v[j] * v[j];
+        part[c] = s;
+    }
+    double s = 0.0;
+    for (int64_t c = 0; c < nch; c++) s += part[c];
+    free(part);
+    return s;
+}
+
+/* Algorithm 4.1, the forward-error filter.  Given the values v (length m)
+ * of a candidate matrix and an absolute Frobenius budget eg, it looks for an
+ * entry threshold theta whose dropped set, the entries with |v| <= theta,
+ * has a Frobenius norm d(theta) of at most eg (1 + e_r).  The first trial
+ * threshold is the budget itself.  While the dropped norm is too large, the
+ * threshold is lowered in proportion: with the ratio q = d(theta) / theta,
+ * the next threshold is eg / q.  The threshold then falls strictly at every
+ * pass (Theorem 4.1), so each dropped set lies inside the previous one.
+ *
+ * On return keep[j] = 1 for |v_j| > theta (an entry equal to the threshold
+ * is dropped), *theta_out is the last threshold, *iters_out the number of
+ * passes and *b_out the dropped norm at that threshold.  More than maxit
+ * passes is ORA_ENOTCONV.  With eg <= 0 only exact zeros are dropped (the
+ * unfiltered method). */
 int ora_filter(const double *v, int64_t m, double eg, double er, int maxit,
                double *theta_out, int *iters_out, double *b_out, unsigned char *keep) {
     if (eg <= 0.0) {
@@ -344,24 +372,20 @@ int ora_filter(const double *v, int64_t m, double eg, double er, int maxit,
         *b_out = 0.0;
         return ORA_OK;
     }
-    unsigned char *inb = keep;       /* reuse: inb = 1 - keep at the end   */
-    for (int64_t j = 0; j < m; j++) inb[j] = 1;          /* b_0 = A        */
-    double mn = 1.0, b = INFINITY, theta = 0.0;
+    double theta = eg, d;
     int it = 0;
-    while (b > eg * (1.0 + er)) {
+    for (;;) {
         if (it >= maxit) return ORA_ENOTCONV;
-        theta = eg / mn;                                  /* eps_f^(n+1)    */
-        #pragma omp parallel for schedule(static)
-        for (int64_t j = 0; j < m; j++)                   /* b_n(p) = 0     */
-            if (inb[j] && fabs(v[j]) > theta) inb[j] = 0;
-        b = sqrt(sumsq_masked(v, inb, m));                /* b_{n+1}        */
-        mn = b / theta;                                   /* m_{n+1}        */
+        d = sqrt(dropped_sumsq(v, m, theta));
         it++;
+        if (d <= eg * (1.0 + er)) break;
+        const double q = d / theta;
+        theta = eg / q;
     }
-    for (int64_t j = 0; j < m; j++) keep[j] = !inb[j];   /* A~ = A - b_n   */
+    for (int64_t j = 0; j < m; j++) keep[j] = fabs(v[j]) > theta;
     *theta_out = theta;
     *iters_out = it;
-    *b_out = b;
+    *b_out = d;
     return ORA_OK;
 }
 

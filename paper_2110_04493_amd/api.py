@@ -15,10 +15,15 @@ from . import capi
 
 
 class _TorchAllocator:
-    """Allocator callback handing torch uint8 buffers to the library."""
+    """Allocator callback handing torch uint8 buffers to the library.
 
-    def __init__(self, device):
+    Buffers are allocated on the plan's stream, the stream the library writes
+    them on, so that torch's caching allocator orders their reuse after the
+    library's work."""
+
+    def __init__(self, device, stream):
         self.device = device
+        self.stream = stream
         self.live: dict[int, torch.Tensor] = {}
         self._alloc = capi.ALLOC_FN(self._do_alloc)
         self._free = capi.FREE_FN(self._do_free)
@@ -26,7 +31,8 @@ class _TorchAllocator:
 
     def _do_alloc(self, nbytes, stream, ctx):
         try:
-            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(self.stream):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         except RuntimeError:
             return None
         self.live[t.data_ptr()] = t
@@ -36,11 +42,18 @@ class _TorchAllocator:
         self.live.pop(ptr, None)
 
     def take(self, ptr: int, count: int, dtype: torch.dtype) -> torch.Tensor:
-        """Moves ownership of one output buffer to the caller as a typed view."""
+        """Moves ownership of one output buffer to the caller as a typed view.
+        The caller's current stream is made to wait for the plan's stream
+        (see Plan._handover); the buffer is marked as used on the current
+        stream so that torch does not reuse it before that stream's work on
+        it is done."""
         if count == 0:
             self.live.pop(ptr, None)
             return torch.empty(0, dtype=dtype, device=self.device)
         t = self.live.pop(ptr)
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            t.record_stream(cur)
         nbytes = count * torch.empty(0, dtype=dtype).element_size()
         return t[:nbytes].view(dtype)
 
@@ -83,7 +96,7 @@ class Plan:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.options = options or Options()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.alloc = _TorchAllocator(self.device)
+        self.alloc = _TorchAllocator(self.device, self.stream)
         o = capi.expm_opts_default()
         o.normal = self.options.normal
         o.filter_mode = self.options.filter_mode
@@ -100,7 +113,23 @@ class Plan:
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)
 
+    def _inputs_ready(self):
+        """The library reads its inputs on the plan's stream: order that
+        after the caller's current stream, which produced them."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _handover(self):
+        """Outputs are written on the plan's stream (expm_sparse returns
+        without waiting for the device): order the caller's current stream
+        after it before the caller sees them."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def _take(self, E: capi.expm_csr):
+        self._handover()
         n = E.n
         rp = self.alloc.take(E.rowptr, n + 1, torch.int64)
         ci = self.alloc.take(E.col, E.nnz, torch.int32) if E.col else \
@@ -114,14 +143,22 @@ class Plan:
         """E = e^H as (rowptr int64, col int32, val float64) device tensors."""
         _check_inputs(crow, col, val)
         with torch.cuda.device(self.device):
+            self._inputs_ready()
             E = capi.expm_sparse(self.handle, _view(crow, col, val), eps)
             return self._take(E)
 
     def backward(self, dE: torch.Tensor, nnz_h: int) -> torch.Tensor:
         dE = dE.contiguous().to(torch.float64)
-        dH = torch.empty(nnz_h, dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
+            with torch.cuda.stream(self.stream):
+                dH = torch.empty(nnz_h, dtype=torch.float64, device=self.device)
+            self._inputs_ready()
             capi.expm_sparse_backward(self.handle, dE.data_ptr(), dH.data_ptr())
+            self._handover()
+            cur = torch.cuda.current_stream(self.device)
+            if cur != self.stream:
+                dE.record_stream(self.stream)
+                dH.record_stream(cur)
         return dH
 
     def expm_batched(self, mats, eps):
@@ -130,6 +167,7 @@ class Plan:
             _check_inputs(crow, col, val)
             views.append(_view(crow, col, val))
         with torch.cuda.device(self.device):
+            self._inputs_ready()
             outs = capi.expm_sparse_batched(self.handle, views, list(eps))
             return [self._take(E) for E in outs]
 
@@ -138,7 +176,7 @@ class Plan:
 
     def close(self):
         if getattr(self, "handle", None):
-            torch.cuda.current_stream(self.device).synchronize()
+            self.stream.synchronize()
             capi.expm_free(self.handle)
             self.handle = None
 

@@ -139,8 +139,10 @@ __global__ void k_validate(CsrView A, int64_t nnz, int *flag) {
     if (i >= A.n) return;
     int f = 0;
     int64_t b = A.rp[i], e = A.rp[i + 1];
+    // every row checks both of its bounds: rows run in parallel, so a row
+    // cannot rely on the previous row's check of its start
     if (i == 0 && b != 0) f |= 1;
-    if (e < b || e > nnz) f |= 1;
+    if (b < 0 || b > nnz || e < b || e > nnz) f |= 1;
     if (!(f & 1)) {
         for (int64_t p = b + lane_id(); p < e; p += kWave) {
             int c = A.ci[p];

@@ -34,7 +34,8 @@ __all__ = [
     "Csr", "csr_from_coo", "tridiag", "grid_edges", "laplacian_from_edges",
     "grid_laplacian", "random_adjacency", "norm1", "config1", "config2",
     "config3", "config4_instance", "config4", "config5", "loss_weights",
-    "random_sparse", "to_dense", "table2_matrix", "table4_matrix",
+    "random_sparse", "to_dense", "table2_matrix", "table4_matrix", "circulant",
+    "perm_plus_identity",
 ]
 
 
@@ -294,3 +295,35 @@ def random_sparse(n: int, density: float, seed: int, kind: str = "general",
     D = D + D.T if kind == "symmetric" else D - D.T
     rr, cc = np.nonzero(D)
     return csr_from_coo(n, rr, cc, D[rr, cc] * scale)
+
+
+def circulant(n: int, offsets, values, bump: float = 0.0) -> Csr:
+    """Sparse circulant matrix sum_k values[k] * P^offsets[k], P the cyclic
+    shift (P[i, (i+1) mod n] = 1): normal and, for offsets not symmetric
+    about 0, not symmetric.  ``bump`` is added to entry (0, 1), which makes
+    the matrix non-normal by a controlled amount."""
+    i = np.arange(n, dtype=np.int64)
+    r = np.concatenate([i for _ in offsets])
+    c = np.concatenate([(i + o) % n for o in offsets])
+    v = np.concatenate([np.full(n, float(x)) for x in values])
+    A = csr_from_coo(n, r, c, v, sum_duplicates=True)
+    if bump:
+        p = int(np.searchsorted(A.col[A.rowptr[0]:A.rowptr[1]], 1)) + int(A.rowptr[0])
+        if p >= A.rowptr[1] or A.col[p] != 1:
+            raise ValueError("entry (0, 1) must be stored to bump it")
+        A.val[p] += bump
+    return A
+
+
+def perm_plus_identity(n: int, c: float, s: float, seed: int) -> Csr:
+    """c I + s Q with Q the matrix of a random permutation without fixed
+    points: normal (Q is orthogonal), not symmetric unless Q is an
+    involution."""
+    rng = np.random.default_rng(seed)
+    while True:
+        q = rng.permutation(n)
+        if not np.any(q == np.arange(n)):
+            break
+    i = np.arange(n, dtype=np.int64)
+    return csr_from_coo(n, np.concatenate([i, i]), np.concatenate([i, q]),
+                        np.concatenate([np.full(n, c), np.full(n, s)]))

@@ -90,7 +90,12 @@ def test_batched_single_and_empty():
     rel, ok, _, _ = compare(outs[0], Eo, final_theta(so))
     assert rel <= TOL and ok
     assert (st["M"], st["N"]) == (so["M"], so["N"])
-    assert run_batched([], []) == ([], {}) or True
+    # an empty batch is a valid call that returns no outputs
+    plan = api.Plan("cuda")
+    try:
+        assert plan.expm_batched([], []) == []
+    finally:
+        plan.close()
 
 
 def test_batched_invalid_instance():

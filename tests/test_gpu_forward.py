@@ -42,6 +42,15 @@ def check_parity(H, eps, count_tol=0.002, **kw):
         assert abs(a - b) <= count_tol * b + 2
     for a, b in zip(sg["sq_cand"], so["sq_cand"]):
         assert abs(a - b) <= count_tol * b + 2
+    # Taylor terms (Eq. 4.10-4.14): candidate and kept counts of every term
+    # the two sides formed; the candidate count of a term is exact (a
+    # product's pattern, rounding-free), the kept count may differ only by
+    # entries at the threshold
+    assert len(sg["taylor_cand"]) == len(so["taylor_cand"])
+    for a, b in zip(sg["taylor_cand"], so["taylor_cand"]):
+        assert abs(a - b) <= count_tol * b + 2
+    for a, b in zip(sg["taylor_kept"], so["taylor_kept"]):
+        assert abs(a - b) <= count_tol * b + 2
     return Eg, sg, Eo, so
 
 
@@ -179,6 +188,53 @@ def test_plan_reuse_many_calls():
             assert rel <= TOL and ok
     finally:
         plan.close()
+
+
+NORMALITY_CASES = {
+    "circulant": (lambda: W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5]), 1),
+    "perm_plus_identity": (lambda: W.perm_plus_identity(50, 0.7, 1.3, 21), 1),
+    "circulant_commutator_below": (lambda: W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5],
+                                                       bump=2.0 ** -46), 1),
+    "circulant_commutator_above": (lambda: W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5],
+                                                       bump=2.0 ** -42), 0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NORMALITY_CASES))
+def test_normality_cases_on_gpu(name):
+    """Normal matrices that are neither symmetric nor skew-symmetric, and
+    near-normal ones on either side of the commutator threshold of the
+    normality test (Alg. 4.2 step 2): the device test must take the same
+    decision as the oracle (check_parity compares it), hence the same a."""
+    make, expect = NORMALITY_CASES[name]
+    _, sg, _, so = check_parity(make(), 1e-12)
+    assert sg["normal"] == so["normal"] == expect
+    # 1/(N+1) exactly, or 1/||H||_F with the norm summed in another order
+    assert abs(sg["a"] - so["a"]) <= 4e-16 * so["a"]
+
+
+def test_config3_regime_against_oracle():
+    """Config 3's regime (unit 5-point grid, H = -0.5 L, eps_tol = 1e-10) at
+    300 x 300 (n = 90,000) against the oracle with the full parity bar, and
+    sampled rows against the Kronecker closed form of the unit grid."""
+    from _closed_forms import path_laplacian_expm, unit_grid_expm_row
+    side, t, eps = 300, 0.5, 1e-10
+    H = W.grid_laplacian(side, side, None).scaled(-t)
+    Eg, sg, Eo, so = check_parity(H, eps)
+    P = path_laplacian_expm(side, t)
+    theta = final_theta(so)
+    rng = np.random.default_rng(3001)
+    for i in [0, side - 1, H.n // 2 + side // 2, H.n - 1, *rng.integers(0, H.n, 4).tolist()]:
+        b, e = int(Eg.rowptr[i]), int(Eg.rowptr[i + 1])
+        exact = unit_grid_expm_row(P, side, i)
+        got = np.zeros(H.n)
+        got[Eg.col[b:e]] = Eg.val[b:e]
+        assert np.linalg.norm(got - exact) <= 10 * eps * np.linalg.norm(exact)
+        # an entry the filter dropped is small: at most twice the final
+        # threshold plus the method's error on the row
+        miss = np.ones(H.n, bool)
+        miss[Eg.col[b:e]] = False
+        assert np.abs(exact[miss]).max(initial=0.0) <= 2 * theta + 10 * eps * np.linalg.norm(exact)
 
 
 def test_config2_full_size():

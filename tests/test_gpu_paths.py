@@ -188,3 +188,27 @@ def test_long_column_taylor_adjoint(adjoint):
     print(f"[long column] M={sg['M']} N={sg['N']} terms={sg['taylor_terms']} relF={rel:.2e}",
           flush=True)
     assert rel <= TOL and ok
+
+
+def test_row_product_global_scratch():
+    """A row whose accumulator does not fit the largest LDS class: a dense
+    first row on a tridiagonal matrix of order 9000.  The product's row 0
+    then has 9000 candidate columns, 8 * 9000 + 8 * ceil(9000 / 32) = 74,256
+    bytes of accumulator and rank table, above the 65,536-byte LDS class, so
+    the row products run it on global scratch.  Scalar rows only (no tiles),
+    natural order."""
+    n = 9000
+    T = W.tridiag(n, 1.0, -2.0, 1.0, 0.5)
+    rng = np.random.default_rng(77)
+    r = np.concatenate([T.rows(), np.zeros(n, np.int64)])
+    c = np.concatenate([T.col.astype(np.int64), np.arange(n)])
+    v = np.concatenate([T.val, 1e-2 * rng.uniform(0.1, 1.0, n)])
+    H = W.csr_from_coo(n, r, c, v, sum_duplicates=True)
+    assert 8 * n + 8 * ((n + 31) // 32) > 65536
+    Eg, sg = run_gpu(H, 1e-12, reorder=0, tile_min_fill=2.0)
+    Eo, so = run_oracle(H, 1e-12)
+    assert np.all(np.diff(Eo.rowptr)[:10] == n)          # dense rows reached the output
+    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
+    print(f"[global scratch rows] relF={rel:.2e} only={og},{oo}", flush=True)
+    assert rel <= TOL and ok
+    assert (sg["M"], sg["N"]) == (so["M"], so["N"])

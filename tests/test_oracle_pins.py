@@ -288,6 +288,62 @@ def test_dense_pade_agreement(kind, seed, scale, eps):
     assert res.stats["normal"] == (1 if kind != "general" else 0)
 
 
+# ------------------------------------------------ normality test (Alg. 4.2 step 2)
+# The filter constant a is 1/(N+1) for normal H and min(1/(N+1), 1/||H||_F)
+# otherwise; normality of a matrix that is neither symmetric nor
+# skew-symmetric is decided by ||H H^T - H^T H||_F <= 16 u ||H||_F^2.  The
+# circulants below have dyadic entries, so both products are exact up to
+# terms below 2^-90 and the commutator norm is known in advance.
+
+def _commutator_ratio(A):
+    D = W.to_dense(A)
+    c = np.linalg.norm(D @ D.T - D.T @ D)
+    return c / (16 * 2.0 ** -53 * np.sum(A.val ** 2))
+
+
+NORMALITY_CASES = {
+    # name: (matrix, expected normality)
+    "circulant": (lambda: W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5]), 1),
+    "perm_plus_identity": (lambda: W.perm_plus_identity(50, 0.7, 1.3, 21), 1),
+    "circulant_commutator_below": (lambda: W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5],
+                                                       bump=2.0 ** -46), 1),
+    "circulant_commutator_above": (lambda: W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5],
+                                                       bump=2.0 ** -42), 0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NORMALITY_CASES))
+def test_normality_of_nonsymmetric_matrices(name):
+    """Normal matrices that are not (skew-)symmetric, and near-normal ones on
+    either side of the commutator threshold: the decision, the resulting a,
+    and the exponential against a dense Pade expm."""
+    make, expect = NORMALITY_CASES[name]
+    A = make()
+    D = W.to_dense(A)
+    assert np.abs(D - D.T).max() > 0 and np.abs(D + D.T).max() > 0
+    ratio = _commutator_ratio(A)
+    # the cases sit well away from the threshold (ratio 1)
+    assert (ratio <= 0.25) if expect else (ratio >= 3.0)
+    eps = 1e-12
+    res = oracle.expm(A.rowptr, A.col, A.val, eps)
+    st = res.stats
+    assert st["normal"] == expect
+    N, nh = st["N"], math.sqrt(np.sum(A.val ** 2))
+    assert st["a"] == (1.0 / (N + 1) if expect else min(1.0 / (N + 1), 1.0 / nh))
+    E = W.to_dense(W.Csr(A.n, res.rowptr, res.col, res.val))
+    assert relF(E, sla.expm(D)) <= 10 * eps
+
+
+def test_normality_override():
+    """opts.normal forces the decision either way (a follows it)."""
+    A = W.circulant(40, [0, 1, 3], [-1.0, 2.0, 0.5])
+    for forced in (0, 1):
+        st = oracle.expm(A.rowptr, A.col, A.val, 1e-12, normal=forced).stats
+        N, nh = st["N"], math.sqrt(np.sum(A.val ** 2))
+        assert st["normal"] == forced
+        assert st["a"] == (1.0 / (N + 1) if forced else min(1.0 / (N + 1), 1.0 / nh))
+
+
 def test_grid_rows_sum_to_one():
     """e^{-tau L} of a graph Laplacian has unit row sums and symmetric,
     nonnegative entries up to the filter threshold."""
