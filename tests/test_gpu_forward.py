@@ -164,6 +164,46 @@ def test_invalid_inputs_raise():
     assert Eg.nnz > 0
 
 
+def test_negative_row_start_rejected():
+    """A row pointer whose interior entry is negative (rp[1] = -3, so row 1
+    starts before the arrays) is rejected by the validation, which checks
+    both bounds of every row before reading any of its entries."""
+    from paper_2110_04493_amd import capi
+    bad = W.Csr(3, np.array([0, -3, 2, 4], np.int64), np.array([0, 1, 1, 2], np.int32),
+                np.ones(4))
+    with pytest.raises(capi.ExpmError) as e:
+        run_gpu(bad, 1e-12)
+    assert e.value.code == capi.EXPM_EINVAL
+
+
+def test_plan_on_a_non_current_stream():
+    """A plan bound to a stream other than torch's current one: its inputs
+    are produced on the current stream right before each call, and its
+    outputs are used on the current stream right after it, with no explicit
+    synchronisation; every result must still match the oracle."""
+    import torch
+    from paper_2110_04493_amd import api
+    side = 60
+    L = W.grid_laplacian(side, side, np.random.default_rng(61))
+    H = L.scaled(-20.0 / W.norm1(L))
+    Eo, so = run_oracle(H, 1e-12)
+    s = torch.cuda.Stream()
+    plan = api.Plan("cuda", stream=s)
+    try:
+        crow, col, val = to_device(H)
+        for _ in range(3):
+            v_in = val * 1.0                        # written on the current stream
+            rp, ci, v = plan.expm(crow, col, v_in, 1e-12)
+            del v_in
+            got = (v * 1.0, rp.clone(), ci.clone())  # read on the current stream
+            torch.cuda.current_stream().synchronize()
+            Eg = W.Csr(H.n, got[1].cpu().numpy(), got[2].cpu().numpy(), got[0].cpu().numpy())
+            rel, ok, _, _ = compare(Eg, Eo, final_theta(so))
+            assert rel <= TOL and ok
+    finally:
+        plan.close()
+
+
 def test_deterministic_bitwise():
     H, eps = W.config1()
     E1, _ = run_gpu(H, eps)
