@@ -208,6 +208,28 @@ int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cview *H, const
  * instance).  Errors: EXPM_ESTATE if no call has run. */
 int expm_get_stats(expm_plan_t p, expm_stats *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as expm_sparse, with every device workspace buffer cut from a
+ * static device array of EXPM_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on each GPU it runs on until the process ends, and E written into
+ * buffers the caller owns: E_rowptr int64[n+1], E_col int32[capacity],
+ * E_val double[capacity] (device pointers; may be NULL when capacity is 0).
+ * The call allocates and frees no device or pinned memory (host bookkeeping
+ * uses the C++ heap); like expm_sparse it reads sizes back from the device.
+ * Options come from the plan; keep_checkpoints and profile are ignored (no
+ * expm_sparse_backward after this call: it returns EXPM_ESTATE).  Results
+ * are ready in order on opts.stream.  Every call on one GPU shares that
+ * GPU's array, whatever the plan: calls that overlap in time on one GPU
+ * (other threads, other streams) race and must not be issued.
+ * *nnz_e (may be NULL) receives nnz(E) once it is known, also when it
+ * exceeds capacity.  Errors: those of expm_sparse, and EXPM_ENOMEM when the
+ * workspace does not fit the static array (rejected up front when H alone
+ * is too large) or nnz(E) > capacity. */
+#define EXPM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int expm_sparse_noalloc(expm_plan_t p, const expm_csr_cview *H, double eps, int64_t *E_rowptr,
+                        int32_t *E_col, double *E_val, int64_t capacity, int64_t *nnz_e);
+
 /* Frees one output returned by this plan and zeroes *E. */
 void expm_csr_release(expm_plan_t p, expm_csr *E);
 

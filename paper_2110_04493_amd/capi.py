@@ -32,7 +32,10 @@ ERROR_NAMES = {0: "EXPM_OK", -1: "EXPM_EINVAL", -2: "EXPM_ENOMEM", -3: "EXPM_EHI
 # Every function the header declares.
 SYMBOLS = ["expm_opts_default", "expm_plan", "expm_sparse", "expm_sparse_backward",
            "expm_sparse_batched", "expm_get_stats", "expm_csr_release", "expm_free",
-           "expm_last_error", "expm_r0", "expm_choose_mn"]
+           "expm_last_error", "expm_r0", "expm_choose_mn", "expm_sparse_noalloc"]
+
+# bytes of the static device array behind expm_sparse_noalloc (expm.h)
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class expm_csr_cview(C.Structure):
@@ -137,6 +140,8 @@ def lib():
         L.expm_r0.restype = C.c_double
         L.expm_choose_mn.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]
+        L.expm_sparse_noalloc.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_double, _P, _P,
+                                          _P, C.c_int64, C.POINTER(C.c_int64)]
         for name in SYMBOLS:
             if name not in ("expm_opts_default", "expm_csr_release", "expm_free",
                             "expm_last_error", "expm_r0"):
@@ -166,6 +171,21 @@ def expm_sparse(plan: int, H: expm_csr_cview, eps: float) -> expm_csr:
     E = expm_csr()
     check(lib().expm_sparse(_P(plan), C.byref(H), float(eps), C.byref(E)), "expm_sparse")
     return E
+
+
+def expm_sparse_noalloc(plan: int, H: expm_csr_cview, eps: float, rowptr_ptr: int,
+                        col_ptr: int, val_ptr: int, capacity: int) -> int:
+    """E into caller buffers (device pointers), workspace from the library's
+    static scratch; returns nnz(E).  On an error the raised ExpmError
+    carries nnz(E) in .nnz_e when it was known (-1 otherwise)."""
+    nnz = C.c_int64(-1)
+    code = lib().expm_sparse_noalloc(_P(plan), C.byref(H), float(eps), _P(rowptr_ptr),
+                                     _P(col_ptr), _P(val_ptr), int(capacity), C.byref(nnz))
+    if code != EXPM_OK:
+        err = ExpmError(code, "expm_sparse_noalloc", expm_last_error())
+        err.nnz_e = nnz.value
+        raise err
+    return nnz.value
 
 
 def expm_sparse_backward(plan: int, dE_ptr: int, dH_ptr: int) -> None:

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,9 +49,66 @@ int fail(int code, const char *fmt, ...) {
 namespace xpm {
 namespace host {
 
+// Fixed-region mode: returns b's range to the free list, merged with its
+// free neighbours.
+static void arena_put(expm_plan_s &P, Buf &b) {
+    if (!b.p) return;
+    size_t off = (size_t)((char *)b.p - P.arena), len = b.bytes;
+    auto next = P.arena_free.lower_bound(off);
+    // a range that overlaps a free one was already returned (a copy of the
+    // buffer released twice): keep the list as it is
+    const bool overlap =
+        (next != P.arena_free.end() && next->first < off + len) ||
+        (next != P.arena_free.begin() && std::prev(next)->first + std::prev(next)->second > off);
+    if (overlap) {
+        b.p = nullptr;
+        b.bytes = 0;
+        return;
+    }
+    if (next != P.arena_free.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+            off = prev->first;
+            len += prev->second;
+            P.arena_free.erase(prev);
+        }
+    }
+    if (next != P.arena_free.end() && off + len == next->first) {
+        len += next->second;
+        P.arena_free.erase(next);
+    }
+    P.arena_free[off] = len;
+    P.live -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Fixed-region mode: b becomes a range of at least `bytes` bytes (the first
+// free range that holds it); its old contents are not kept, as with the
+// pool.
+static int arena_grow(expm_plan_s &P, Buf &b, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    arena_put(P, b);
+    for (auto it = P.arena_free.begin(); it != P.arena_free.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, rest = it->second - bytes;
+        P.arena_free.erase(it);
+        if (rest) P.arena_free[off + bytes] = rest;
+        b.p = P.arena + off;
+        b.bytes = bytes;
+        P.live += bytes;
+        P.peak = std::max(P.peak, P.live);
+        return EXPM_OK;
+    }
+    return fail(EXPM_ENOMEM,
+                "the %zu-byte static scratch of expm_sparse_noalloc is exhausted (no free range "
+                "of %zu bytes with %zu bytes in use)", P.arena_bytes, bytes, P.live);
+}
+
 int ensure(expm_plan_s &P, Buf &b, size_t bytes) {
     if (bytes == 0) bytes = 8;
     if (b.bytes >= bytes) return EXPM_OK;
+    if (P.arena) return arena_grow(P, b, bytes);
     if (b.p) {
         HIPCHK(hipFreeAsync(b.p, P.st));
         P.live -= b.bytes;
@@ -82,6 +140,7 @@ int ensure(expm_plan_s &P, Buf &b, size_t bytes) {
 // later calls allocate nothing: b is grown to ref's capacity when smaller.
 int reserve_as(expm_plan_s &P, Buf &b, const Buf &ref) {
     if (b.bytes >= ref.bytes || ref.bytes == 0) return EXPM_OK;
+    if (P.arena) return arena_grow(P, b, ref.bytes);
     if (b.p) {
         HIPCHK(hipFreeAsync(b.p, P.st));
         P.live -= b.bytes;
@@ -115,7 +174,9 @@ int reserve_as(expm_plan_s &P, TileSet &t, const TileSet &ref) {
 }
 
 void release(expm_plan_s &P, Buf &b) {
-    if (b.p) {
+    if (b.p && P.arena) {
+        arena_put(P, b);
+    } else if (b.p) {
         (void)hipFreeAsync(b.p, P.st);
         P.live -= b.bytes;
     }
@@ -183,6 +244,7 @@ int scan(expm_plan_s &P, const int64_t *in, int64_t *out, int64_t n) {
 
 void *out_alloc(expm_plan_s &P, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    if (P.arena) return nullptr;   // outputs come from alloc_output only
     void *p = nullptr;
     if (P.opts.allocator && P.opts.allocator->alloc) {
         p = P.opts.allocator->alloc(bytes, P.st, P.opts.allocator->ctx);
@@ -195,7 +257,7 @@ void *out_alloc(expm_plan_s &P, size_t bytes) {
 }
 
 void out_free(expm_plan_s &P, void *p) {
-    if (!p) return;
+    if (!p || P.arena) return;   // fixed-region outputs belong to the caller
     auto it = std::find(P.outputs.begin(), P.outputs.end(), p);
     if (it == P.outputs.end()) return;
     P.outputs.erase(it);
@@ -203,6 +265,33 @@ void out_free(expm_plan_s &P, void *p) {
         P.opts.allocator->free(p, P.st, P.opts.allocator->ctx);
     else
         (void)hipFreeAsync(p, P.st);
+}
+
+int alloc_output(expm_plan_s &P, int64_t n, int64_t nnz, int64_t **rp, int32_t **ci,
+                 double **v) {
+    if (P.arena) {
+        P.na_need = nnz;
+        if (nnz > P.na_cap)
+            return fail(EXPM_ENOMEM, "the output holds %lld entries, more than the %lld the "
+                        "caller's buffers take", (long long)nnz, (long long)P.na_cap);
+        *rp = P.na_rp;
+        *ci = P.na_ci;
+        *v = P.na_v;
+        return EXPM_OK;
+    }
+    *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
+    *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * nnz);
+    *v = (double *)out_alloc(P, sizeof(double) * nnz);
+    if (!*rp || !*ci || !*v) {
+        out_free(P, *rp);
+        out_free(P, *ci);
+        out_free(P, *v);
+        *rp = nullptr;
+        *ci = nullptr;
+        *v = nullptr;
+        return fail(EXPM_ENOMEM, "cannot allocate the output (%lld entries)", (long long)nnz);
+    }
+    return EXPM_OK;
 }
 
 // ------------------------------------------------------------------ planner
@@ -518,15 +607,10 @@ int check_view(const expm_csr_cview *H) {
 }
 
 int output_identity(expm_plan_s &P, int64_t n, expm_csr *E) {
-    int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
-    int32_t *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * n);
-    double *v = (double *)out_alloc(P, sizeof(double) * n);
-    if (!rp || !ci || !v) {
-        out_free(P, rp);
-        out_free(P, ci);
-        out_free(P, v);
-        return fail(EXPM_ENOMEM, "cannot allocate the output");
-    }
+    int64_t *rp;
+    int32_t *ci;
+    double *v;
+    CHK(alloc_output(P, n, n, &rp, &ci, &v));
     HIPCHK(fill_identity(n, rp, ci, v, P.st));
     E->n = n;
     E->nnz = n;
@@ -702,8 +786,14 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     P.peak = P.live;
     if (n == 0) {
         E->n = 0;
-        int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t));
-        if (!rp) return fail(EXPM_ENOMEM, "cannot allocate the output");
+        int64_t *rp;
+        int32_t *ci;
+        double *v;
+        CHK(alloc_output(P, 0, 0, &rp, &ci, &v));
+        if (!P.arena) {   // only the row pointer is handed out
+            out_free(P, ci);
+            out_free(P, v);
+        }
         HIPCHK(hipMemsetAsync(rp, 0, sizeof(int64_t), st));
         E->rowptr = rp;
         P.have_stats = true;
@@ -912,16 +1002,10 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         FilterCtl h{};
         int64_t kept;
         CHK(filter_and_count(P, n, TNs.nnz, 0.0, nullptr, true, -1.0, true, &h, &kept));
-        int64_t *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
-        int32_t *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * kept);
-        double *v = (double *)out_alloc(P, sizeof(double) * kept);
-        if (!rp || !ci || !v) {
-            out_free(P, rp);
-            out_free(P, ci);
-            out_free(P, v);
-            return fail(EXPM_ENOMEM, "cannot allocate the output (%lld entries)",
-                        (long long)kept);
-        }
+        int64_t *rp;
+        int32_t *ci;
+        double *v;
+        CHK(alloc_output(P, n, kept, &rp, &ci, &v));
         // with reordering E' = I + T'_N goes to workspace and is permuted back
         int64_t *erp = rp;
         int32_t *eci = ci;
@@ -1177,6 +1261,35 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
 }  // namespace host
 }  // namespace xpm
 
+// ============================================================ fixed region
+// The workspace of expm_sparse_noalloc: one static device array per GPU,
+// held from the library's load until the process ends.  In host code its
+// name is only a host-side handle; the device address of each GPU's copy is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and only that address is handed to kernels and copies.
+namespace {
+static __device__ __align__(256) char scratch[EXPM_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up on first use.
+int scratch_address(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(EXPM_EHIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(EXPM_EHIP, "no device address for the static scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return EXPM_OK;
+}
+}  // namespace
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -1232,6 +1345,17 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
         }
     }
     (void)hipGetLastError();
+    // the shadow plan of expm_sparse_noalloc and the current device's
+    // scratch address (set up here, so that the call itself looks up nothing)
+    P->na = new (std::nothrow) expm_plan_s();
+    void *sp = nullptr;
+    const int ss = P->na ? scratch_address(&sp) : fail(EXPM_ENOMEM, "cannot allocate the plan");
+    if (ss != EXPM_OK) {
+        delete P->na;
+        (void)hipHostFree(P->host);
+        delete P;
+        return ss;
+    }
     if (o.profile) {
         P->have_events = true;
         for (hipEvent_t &e : P->ev)
@@ -1281,6 +1405,58 @@ int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E)
             memset(E, 0, sizeof *E);
         }
         free_adjoint_state(*p);
+    }
+    return s;
+}
+
+int expm_sparse_noalloc(expm_plan_t p, const expm_csr_cview *H, double eps, int64_t *E_rowptr,
+                        int32_t *E_col, double *E_val, int64_t capacity, int64_t *nnz_e) {
+    g_err.clear();
+    if (nnz_e) *nnz_e = -1;
+    if (!p || !p->na) return fail(EXPM_EINVAL, "plan is NULL");
+    CHK(check_view(H));
+    if (!E_rowptr || capacity < 0 || (capacity > 0 && (!E_col || !E_val)))
+        return fail(EXPM_EINVAL, "invalid output buffers");
+    // the smallest workspace any input needs: H's pattern and values twice
+    // (the copy and its transpose) and eight row arrays
+    const double least = 24.0 * (double)H->nnz + 64.0 * (double)(H->n + 1);
+    if (least > (double)EXPM_NOALLOC_SCRATCH_BYTES)
+        return fail(EXPM_ENOMEM, "H (n = %lld, nnz = %lld) needs more workspace than the "
+                    "%zu-byte static scratch of expm_sparse_noalloc holds",
+                    (long long)H->n, (long long)H->nnz, (size_t)EXPM_NOALLOC_SCRATCH_BYTES);
+    void *base = nullptr;
+    CHK(scratch_address(&base));
+    // The call runs on the plan's shadow, reset: its buffers are cut from
+    // the scratch afresh (nothing of an earlier call is kept there).
+    expm_plan_s &S = *p->na;
+    S = expm_plan_s();
+    S.opts = p->opts;
+    S.opts.keep_checkpoints = 0;
+    S.opts.profile = 0;
+    S.opts.allocator = nullptr;
+    S.st = p->st;
+    S.host = p->host;
+    S.bsr_min_fill = p->bsr_min_fill;
+    S.dev_mem = p->dev_mem;
+    S.arena = (char *)base;
+    S.arena_bytes = EXPM_NOALLOC_SCRATCH_BYTES;
+    S.arena_free[0] = EXPM_NOALLOC_SCRATCH_BYTES;
+    S.na_rp = E_rowptr;
+    S.na_ci = E_col;
+    S.na_v = E_val;
+    S.na_cap = capacity;
+    // the plan's own forward state does not describe this call
+    free_adjoint_state(*p);
+    expm_csr E{};
+    int s = forward(S, H, eps, &E);
+    if (nnz_e && S.na_need >= 0) *nnz_e = S.na_need;
+    S.stats.status = s;
+    p->stats = S.stats;
+    p->have_stats = true;
+    S.host = nullptr;
+    if (s != EXPM_OK) {
+        (void)hipStreamSynchronize(p->st);
+        (void)hipGetLastError();
     }
     return s;
 }
@@ -1356,6 +1532,7 @@ void expm_free(expm_plan_t p) {
         for (hipEvent_t &e : P.ev) (void)hipEventDestroy(e);
     for (hipEvent_t &e : P.kt_ev) (void)hipEventDestroy(e);
     for (hipEvent_t &e : P.kt_ev_fwd) (void)hipEventDestroy(e);
+    delete P.na;   // its buffers lie in the static scratch: nothing to free
     if (P.host) (void)hipHostFree(P.host);
     (void)hipGetLastError();
     delete p;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <chrono>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,23 @@ struct expm_plan_s {
     expm_opts opts{};
     hipStream_t st = nullptr;
     size_t live = 0, peak = 0;
+
+    // Fixed-region mode (expm_sparse_noalloc): every workspace buffer is cut
+    // from [arena, arena + arena_bytes) by a first-fit allocator over the
+    // free ranges (offset -> length, adjacent ranges merged) instead of the
+    // stream-ordered pool; everything runs on one stream, so a range freed
+    // and handed out again is reused in stream order.  The output goes to
+    // the caller's buffers na_rp / na_ci / na_v of na_cap entries (na_need:
+    // nnz(E) once known).
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    std::map<size_t, size_t> arena_free;
+    int64_t *na_rp = nullptr;
+    int32_t *na_ci = nullptr;
+    double *na_v = nullptr;
+    int64_t na_cap = 0, na_need = -1;
+    // the shadow plan a fixed-region call runs on (created with the plan)
+    expm_plan_s *na = nullptr;
 
     // workspace
     xpm::host::Buf lo, words, woff, ub, cnt, crp, bitmaps, lists, counts, scan_tmp, part, ctl, rowsq, norm2,
@@ -165,6 +183,11 @@ int sync(expm_plan_s &P);
 int scan(expm_plan_s &P, const int64_t *in, int64_t *out, int64_t n);
 void *out_alloc(expm_plan_s &P, size_t bytes);
 void out_free(expm_plan_s &P, void *p);
+// The three arrays of an output CSR with n rows and nnz entries: from the
+// caller's allocator (or the pool), or, in fixed-region mode, the caller's
+// buffers after a capacity check.  On failure nothing stays allocated.
+int alloc_output(expm_plan_s &P, int64_t n, int64_t nnz, int64_t **rp, int32_t **ci,
+                 double **v);
 double plan_r0(int M, double x);
 int plan_mn(double nh, double eps, int *Mo, int *No);
 int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, double div,
