@@ -38,7 +38,8 @@ def build() -> str:
 
 class _Opts(C.Structure):
     _fields_ = [("normal", C.c_int), ("filter_mode", C.c_int), ("e_r", C.c_double),
-                ("max_iter", C.c_int), ("keep", C.c_int)]
+                ("max_iter", C.c_int), ("keep", C.c_int), ("norm", C.c_int),
+                ("exact_ri", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -51,7 +52,8 @@ class _Stats(C.Structure):
                 ("sq_theta", C.c_double * MAXSTEP), ("sq_normF", C.c_double * MAXSTEP),
                 ("sq_budget", C.c_double * MAXSTEP), ("sq_dropped", C.c_double * MAXSTEP),
                 ("sq_iters", C.c_int * MAXSTEP),
-                ("sq_cand", C.c_int64 * MAXSTEP), ("sq_kept", C.c_int64 * MAXSTEP)]
+                ("sq_cand", C.c_int64 * MAXSTEP), ("sq_kept", C.c_int64 * MAXSTEP),
+                ("sq_band", C.c_int64 * MAXSTEP), ("sq_ri", C.c_double * MAXSTEP)]
 
 
 _lib = None
@@ -84,6 +86,11 @@ def _load():
         lib.ora_backward.argtypes = [_P, _P, _P]
         lib.ora_free.argtypes = [_P]
         lib.ora_threads.restype = C.c_int
+        lib.ora_spmm.restype = None
+        lib.ora_spmm.argtypes = [C.c_int64, _P, _P, _P, C.c_int64, _P, _P]
+        lib.ora_power_norms.argtypes = [C.c_int64, _P, _P, _P, C.c_int, _P]
+        lib.ora_alpha_hat.argtypes = [C.c_double, C.c_int, C.c_int, C.c_double, _P, C.c_int,
+                                      C.POINTER(C.c_int64)]
         _lib = lib
     return _lib
 
@@ -152,8 +159,11 @@ def _stats_dict(s: _Stats) -> dict:
     d["taylor_iters"] = list(s.taylor_iters[2:T + 2])
     d["taylor_cand"] = list(s.taylor_cand[2:T + 2])
     d["taylor_kept"] = list(s.taylor_kept[2:T + 2])
-    for k in ("sq_theta", "sq_normF", "sq_budget", "sq_dropped", "sq_iters", "sq_cand", "sq_kept"):
+    for k in ("sq_theta", "sq_normF", "sq_budget", "sq_dropped", "sq_iters", "sq_cand", "sq_kept",
+              "sq_ri"):
         d[k] = list(getattr(s, k)[1:Nsq + 1])
+    d["sq_band"] = list(s.sq_band[0:Nsq + 1])        # l(T^_0) .. l(T^_N)
+    d["theta0"] = s.sq_theta[0]                       # FPIM's threshold of T_0
     return d
 
 
@@ -162,12 +172,14 @@ class Run:
     ``keep`` so that :meth:`backward` can run."""
 
     def __init__(self, rowptr, col, val, eps: float, *, normal: int = -1,
-                 filter_mode: int = 0, e_r: float = 0.1, max_iter: int = 64, keep: bool = True):
+                 filter_mode: int = 0, e_r: float = 0.1, max_iter: int = 64, keep: bool = True,
+                 norm: int = 0, exact_ri: bool = False):
         lib = _load()
         rp, ci, v = _csr_arrays(rowptr, col, val)
         self.n = rp.size - 1
         self._H = (rp, ci, v)
-        o = _Opts(int(normal), int(filter_mode), float(e_r), int(max_iter), int(keep))
+        o = _Opts(int(normal), int(filter_mode), float(e_r), int(max_iter), int(keep), int(norm),
+                  int(exact_ri))
         st = C.c_int()
         self._h = lib.ora_expm(self.n, _ptr(rp), _ptr(ci), _ptr(v), float(eps), C.byref(o), C.byref(st))
         if st.value:
@@ -247,3 +259,40 @@ def matmul(n: int, A, B):
         return rp, ci, v
     finally:
         lib.ora_free(h)
+
+
+def spmm(A, X) -> np.ndarray:
+    """Y = A X for a CSR matrix A = (rowptr, col, val) and a dense X (n x m)."""
+    lib = _load()
+    rp, ci, v = _csr_arrays(*A)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n, m = X.shape
+    Y = np.empty((n, m), np.float64)
+    lib.ora_spmm(n, _ptr(rp), _ptr(ci), _ptr(v), m, _ptr(X), _ptr(Y))
+    return Y
+
+
+def power_norms(A, K: int) -> np.ndarray:
+    """||A^k||_F for k = 1..K by plain sparse products."""
+    lib = _load()
+    rp, ci, v = _csr_arrays(*A)
+    out = np.zeros(K, np.float64)
+    st = lib.ora_power_norms(rp.size - 1, _ptr(rp), _ptr(ci), _ptr(v), int(K), _ptr(out))
+    if st:
+        raise OracleError(st, "power_norms")
+    return out
+
+
+def alpha_hat(ri: float, i: int, N: int, norm: float = 0.0, power_norms=None) -> int:
+    """alpha-hat_i of Eq. (4.8) (from ||H|| = norm) or, given power_norms
+    [||H^k||, k = 1..K], of Eq. (4.9)."""
+    lib = _load()
+    out = C.c_int64()
+    if power_norms is None:
+        st = lib.ora_alpha_hat(float(ri), int(i), int(N), float(norm), None, 0, C.byref(out))
+    else:
+        hk = np.ascontiguousarray(power_norms, dtype=np.float64)
+        st = lib.ora_alpha_hat(float(ri), int(i), int(N), 0.0, _ptr(hk), hk.size, C.byref(out))
+    if st:
+        raise OracleError(st, "alpha_hat")
+    return out.value

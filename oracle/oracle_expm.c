@@ -55,10 +55,16 @@
 
 typedef struct {
     int normal;          /* -1 auto, 0 non-normal, 1 normal               */
-    int filter_mode;     /* 0: paper filter, 1: none (plain PIM, a = 0)   */
+    int filter_mode;     /* 0: paper filter, 1: none (plain PIM, a = 0),
+                            2: fixed relative threshold (FPIM, section 2) */
     double e_r;          /* Algorithm 4.1 tolerance                        */
     int max_iter;        /* Algorithm 4.1 iteration cap                    */
     int keep;            /* keep intermediates (needed for the adjoint)    */
+    int norm;            /* ||H|| in steps 1-3 of Algorithm 4.2 (M, N, a,
+                            r0, the Taylor budget): 0 Frobenius, 1 the
+                            1-norm (largest absolute column sum)           */
+    int exact_ri;        /* 0: r_i = 2^i r0; 1: r_i = 2 r_{i-1} + r_{i-1}^2,
+                            the recurrence of Eq. (4.3)                     */
 } ora_opts;
 
 typedef struct {
@@ -71,6 +77,9 @@ typedef struct {
     double sq_dropped[ORA_MAXSTEP];
     int sq_iters[ORA_MAXSTEP];
     int64_t sq_cand[ORA_MAXSTEP], sq_kept[ORA_MAXSTEP];
+    /* l(T^_i) of Eq. (3.1), i = 0..N, and the error bound r_i, i = 1..N */
+    int64_t sq_band[ORA_MAXSTEP];
+    double sq_ri[ORA_MAXSTEP];
 } ora_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -138,6 +147,31 @@ static double sumsq_masked(const double *v, const unsigned char *mask, int64_t m
 
 /* Frobenius norm of the stored values. */
 static double fro(const mat *A) { return sqrt(sumsq_masked(A->v, NULL, mat_nnz(A))); }
+
+/* Matrix 1-norm: the largest sum of absolute values over the columns,
+ * each column summed in row order. */
+static double norm1(const mat *A) {
+    double *cs = (double *)calloc((size_t)(A->n > 0 ? A->n : 1), sizeof(double));
+    for (int64_t i = 0; i < A->n; i++)
+        for (int64_t p = A->rp[i]; p < A->rp[i + 1]; p++) cs[A->ci[p]] += fabs(A->v[p]);
+    double m = 0.0;
+    for (int64_t j = 0; j < A->n; j++) m = cs[j] > m ? cs[j] : m;
+    free(cs);
+    return m;
+}
+
+/* Bandwidth l(A) = l1(A) + l2(A) of Eq. (3.1): the largest j - i plus the
+ * largest i - j over the stored entries (0 for a matrix with none). */
+static int64_t band_l(const mat *A) {
+    int64_t l1 = INT64_MIN, l2 = INT64_MIN;
+    for (int64_t i = 0; i < A->n; i++)
+        for (int64_t p = A->rp[i]; p < A->rp[i + 1]; p++) {
+            int64_t d = (int64_t)A->ci[p] - i;
+            if (d > l1) l1 = d;
+            if (-d > l2) l2 = -d;
+        }
+    return l1 == INT64_MIN ? 0 : l1 + l2;
+}
 
 static int cmp_i32(const void *a, const void *b) {
     int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
@@ -412,6 +446,18 @@ static int mat_select(mat *B, const mat *A, const unsigned char *keep) {
     return ORA_OK;
 }
 
+/* The fixed filter of the FPIM (section 2): entries with |v| <= theta are
+ * removed. */
+static int filter_fixed(mat *B, const mat *A, double theta) {
+    int64_t m = mat_nnz(A);
+    unsigned char *keep = (unsigned char *)malloc((size_t)(m > 0 ? m : 1));
+    if (!keep) return ORA_ENOMEM;
+    for (int64_t j = 0; j < m; j++) keep[j] = fabs(A->v[j]) > theta;
+    int st = mat_select(B, A, keep);
+    free(keep);
+    return st;
+}
+
 static int filter_mat(mat *B, const mat *A, double eg, const ora_opts *o,
                       double *theta, int *iters, double *dropped) {
     int64_t m = mat_nnz(A);
@@ -506,8 +552,9 @@ ora_run *ora_expm(int64_t n, const int64_t *rp, const int32_t *ci, const double 
     memcpy(H.v, v, (size_t)rp[n] * sizeof(double));
 
     ora_stats *S = &r->st;
-    S->nh = fro(&H);
-    if (S->nh == 0.0) {                   /* e^0 = I                      */
+    const double nh_fro = fro(&H);
+    S->nh = o->norm == 1 ? norm1(&H) : nh_fro;         /* ||H|| of steps 1-3 */
+    if (nh_fro == 0.0) {                  /* e^0 = I                      */
         mat_identity(&r->E, n);
         mat_free(&H);
         *status = ORA_OK;
@@ -519,12 +566,15 @@ ora_run *ora_expm(int64_t n, const int64_t *rp, const int32_t *ci, const double 
     if (st) goto fail;
     if (S->N >= ORA_MAXSTEP - 1 || S->M >= ORA_MAXSTEP - 1) { st = ORA_ERANGE; goto fail; }
 
-    /* Step 2: filter constant a. */
+    /* Step 2: filter constant a (the normality test is in the Frobenius
+     * norm whatever norm steps 1-3 use).  Without the paper's filter (plain
+     * PIM, or the FPIM's fixed threshold) the Taylor terms keep every
+     * nonzero: a = 0. */
     if (o->normal >= 0) S->normal = o->normal;
-    else { S->normal = is_normal(&H, S->nh, &st); if (st) goto fail; }
+    else { S->normal = is_normal(&H, nh_fro, &st); if (st) goto fail; }
     S->a = 1.0 / (S->N + 1);
     if (!S->normal && 1.0 / S->nh < S->a) S->a = 1.0 / S->nh;
-    if (o->filter_mode == 1) S->a = 0.0;
+    if (o->filter_mode == 1 || o->filter_mode == 2) S->a = 0.0;
 
     /* Step 3: H0 = H 2^-N (exact), r0, eg0 = a r0 / (M e^{2||H0||}). */
     for (int64_t p = 0; p < rp[n]; p++) H.v[p] = ldexp(H.v[p], -S->N);
@@ -559,10 +609,22 @@ ora_run *ora_expm(int64_t n, const int64_t *rp, const int32_t *ci, const double 
         T = Tn;
     }
     mat_free(&Sm);
+    if (o->filter_mode == 2) {
+        /* FPIM: T_0 loses its entries at or below eps ||T_0||_1 */
+        mat Tn;
+        S->sq_theta[0] = eps * norm1(&T);
+        st = filter_fixed(&Tn, &T, S->sq_theta[0]);
+        if (st) goto fail;
+        mat_free(&T);
+        T = Tn;
+    }
+    S->sq_band[0] = band_l(&T);
 
-    /* Step 4: N filtered squarings T~ = 2T + T*T, budget a r_i ||I + T~||_F. */
+    /* Step 4: N filtered squarings T~ = 2T + T*T, budget a r_i ||I + T~||_F
+     * (FPIM: fixed threshold eps ||T~||_1). */
     mat I;
     if (mat_identity(&I, n)) { st = ORA_ENOMEM; goto fail; }
+    double ri = S->r0;
     for (int i = 1; i <= S->N; i++) {
         if (o->keep) { mat_copy(&r->T[r->nT], &T); r->nT++; }
         mat P, Tt, F, Tn;
@@ -572,15 +634,23 @@ ora_run *ora_expm(int64_t n, const int64_t *rp, const int32_t *ci, const double 
         mat_free(&P);
         st = spadd(&F, 1.0, &I, 1.0, &Tt, 0);
         if (st) goto fail;
-        double ri = ldexp(S->r0, i);
+        ri = o->exact_ri ? 2.0 * ri + ri * ri : ldexp(S->r0, i);     /* Eq. (4.3) */
+        S->sq_ri[i] = ri;
         S->sq_normF[i] = fro(&F);
         mat_free(&F);
-        S->sq_budget[i] = S->a * ri * S->sq_normF[i];
         S->sq_cand[i] = mat_nnz(&Tt);
-        st = filter_mat(&Tn, &Tt, S->sq_budget[i], o, &S->sq_theta[i], &S->sq_iters[i],
-                        &S->sq_dropped[i]);
+        if (o->filter_mode == 2) {
+            S->sq_theta[i] = S->sq_budget[i] = eps * norm1(&Tt);
+            S->sq_dropped[i] = sqrt(dropped_sumsq(Tt.v, mat_nnz(&Tt), S->sq_theta[i]));
+            st = filter_fixed(&Tn, &Tt, S->sq_theta[i]);
+        } else {
+            S->sq_budget[i] = S->a * ri * S->sq_normF[i];
+            st = filter_mat(&Tn, &Tt, S->sq_budget[i], o, &S->sq_theta[i], &S->sq_iters[i],
+                            &S->sq_dropped[i]);
+        }
         if (st) goto fail;
         S->sq_kept[i] = mat_nnz(&Tn);
+        S->sq_band[i] = band_l(&Tn);
         mat_free(&Tt);
         mat_free(&T);
         T = Tn;
@@ -724,6 +794,75 @@ ora_run *ora_matmul(int64_t n, const int64_t *arp, const int32_t *aci, const dou
     *status = spgemm(&r->E, &A, &B);
     r->status = *status;
     return r;
+}
+
+/* alpha-hat_i of Eq. (4.8) and (4.9): the least M1 2^N1 (M1 >= 1, N1 >= 0)
+ * for which a degree-M1 Taylor seed squared N1 times reaches the relative
+ * error r_i on H 2^(i-N), i.e. 2^N1 r0(M1, x) <= r_i, where x is
+ *   (4.8)  ||H|| 2^(i-N-N1), with norm = ||H||  (hk == NULL), or
+ *   (4.9)  h_{M1, N+N1-i} = 2^(i-N-N1) max_{M1+1 <= k <= 2 M1 + 1} hk[k-1]^(1/k),
+ *          with hk[k-1] = ||H^k|| for k = 1..K, which limits M1 to (K-1)/2.
+ * For each N1 the least M1 that meets the bound is taken (as in problem
+ * (4.20)); *out receives the cost, or -1 when no pair qualifies. */
+int ora_alpha_hat(double ri, int i, int N, double norm, const double *hk, int K, int64_t *out) {
+    int64_t best = -1;
+    const int m1max = hk ? (K - 1) / 2 : 170;
+    for (int N1 = 0; N1 <= 60; N1++) {
+        for (int M1 = 1; M1 <= m1max && M1 <= 170; M1++) {
+            double h = norm;
+            if (hk) {
+                h = 0.0;
+                for (int k = M1 + 1; k <= 2 * M1 + 1; k++) {
+                    const double e = pow(hk[k - 1], 1.0 / k);
+                    if (e > h) h = e;
+                }
+            }
+            const double x = ldexp(h, i - N - N1);
+            if (ldexp(ora_r0(M1, x), N1) <= ri) {
+                const int64_t cost = (int64_t)M1 << N1;
+                if (best < 0 || cost < best) best = cost;
+                break;
+            }
+        }
+    }
+    *out = best;
+    return best < 0 ? ORA_ERANGE : ORA_OK;
+}
+
+/* Y = A X for a CSR matrix A (n x n) and a dense row-major X (n x m): row i
+ * of Y is the sum over the stored entries of row i, in column order, of
+ * a_ik times row k of X.  The action e^H R of section 5.3 and the time step
+ * U_{k+1} = e^H U_k of Eq. (2.2) with E = e^H. */
+void ora_spmm(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, int64_t m,
+              const double *X, double *Y) {
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        double *y = Y + i * m;
+        for (int64_t c = 0; c < m; c++) y[c] = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            const double a = v[p];
+            const double *x = X + (int64_t)ci[p] * m;
+            for (int64_t c = 0; c < m; c++) y[c] += a * x[c];
+        }
+    }
+}
+
+/* ||H^k||_F for k = 1..K (out[k-1]), by K - 1 plain sparse products. */
+int ora_power_norms(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, int K,
+                    double *out) {
+    mat H = {n, (int64_t *)rp, (int32_t *)ci, (double *)v}, P;
+    if (K < 1) return ORA_OK;
+    if (mat_copy(&P, &H)) return ORA_ENOMEM;
+    out[0] = fro(&P);
+    for (int k = 2; k <= K; k++) {
+        mat Q;
+        if (spgemm(&Q, &P, &H)) { mat_free(&P); return ORA_ENOMEM; }
+        mat_free(&P);
+        P = Q;
+        out[k - 1] = fro(&P);
+    }
+    mat_free(&P);
+    return ORA_OK;
 }
 
 int ora_threads(void) { return omp_get_max_threads(); }
