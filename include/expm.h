@@ -49,15 +49,28 @@ extern "C" {
 #define EXPM_FILTER_NONE 1  /* a = 0: plain precise integration, only exact zeros
                                are dropped (section 4.2: a_i = 0 is the original
                                method)                                            */
+#define EXPM_FILTER_FIXED_REL 2 /* the FPIM's fixed filter (section 2): the Taylor
+                               terms keep every nonzero (a = 0); T_0 and each
+                               squaring candidate lose their entries with
+                               |v| <= eps ||.||_1 (largest absolute column sum
+                               of that matrix); eps is then the filter
+                               parameter, and still sets (M, N) by (4.20)     */
+
+#define EXPM_NORM_FRO 0     /* ||H|| of Algorithm 4.2 steps 1-3: Frobenius       */
+#define EXPM_NORM_ONE 1     /* ... or the 1-norm (largest absolute column sum)    */
 
 #define EXPM_MAXSTEP 128
 
-/* Borrowed read-only CSR view (device pointers). */
+/* Borrowed read-only CSR view: device pointers, or host pointers when
+ * on_host = 1 (expm_sparse, expm_sparse_noalloc, expm_analyze,
+ * expm_power_norms and expm_spmm's matrix then copy it to the device
+ * first; expm_sparse_batched takes device views only). */
 typedef struct {
     int64_t n, nnz;
     const int64_t *rowptr;
     const int32_t *col;
     const double *val;
+    int on_host;
 } expm_csr_cview;
 
 /* Output CSR (device pointers).  Owned by the caller's allocator when one is
@@ -121,6 +134,17 @@ typedef struct {
                                 tiles when T's stored entries fill at least
                                 this fraction of its tiles: < 0 (default)
                                 picks 0.2, 0 always tiles, > 1 never          */
+    int norm;                /* EXPM_NORM_FRO (default) | EXPM_NORM_ONE: the
+                                norm of H in problem (4.20), in a and in the
+                                Taylor budget (Algorithm 4.2 steps 1-3); the
+                                normality test, Algorithm 4.1 and the
+                                squaring budgets stay in the Frobenius norm  */
+    int exact_ri;            /* 0 (default): r_i = 2^i r0, the paper's
+                                simplification; 1: r_i = 2 r_{i-1} + r_{i-1}^2,
+                                the recurrence of Eq. (4.3)                   */
+    int diagnostics;         /* 1: per-step bandwidths l(T^_i) of Eq. (3.1),
+                                in the caller's ordering, into expm_stats
+                                (one extra pass over every iterate)          */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',
@@ -164,6 +188,21 @@ typedef struct {
     /* per squaring step: the number of 16x16 candidate tiles its product
        filled (capped at INT32_MAX), or 0 when it ran on scalar rows */
     int sq_tiles[EXPM_MAXSTEP];
+    /* the error bound r_i of step i (2^i r0, or Eq. (4.3) with exact_ri) */
+    double sq_ri[EXPM_MAXSTEP];
+    /* with opts.diagnostics: l(T^_i) of Eq. (3.1) for i = 0..N, in the
+       caller's row and column order (-1 when not computed) */
+    int64_t sq_band[EXPM_MAXSTEP];
+    /* EXPM_FILTER_FIXED_REL: the threshold T_0 was filtered with */
+    double theta0;
+    /* with opts.profile == 1, over the same launches as tile_flops: the
+       algorithmic bytes of the tile product (12 per stored entry of T read
+       once, 8 (n + 1) for its row pointer, 12 per nonzero candidate written
+       once), and the algorithmic flops and bytes of the adjoint tile step:
+       2 per partial product of G T^T and T^T G that lands in the mask plus
+       2 per mask entry; 12 per stored entry of G and of T read once, 8 per
+       mask entry written */
+    double tile_bytes, adj_tile_flops, adj_tile_bytes;
 } expm_stats;
 
 typedef struct expm_plan_s *expm_plan_t;
@@ -207,6 +246,56 @@ int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cview *H, const
 /* Statistics of the last expm_sparse call (for batched calls, of the last
  * instance).  Errors: EXPM_ESTATE if no call has run. */
 int expm_get_stats(expm_plan_t p, expm_stats *out);
+
+/* The plan of Algorithm 4.2 for one input, before running it. */
+typedef struct {
+    int64_t n, nnz;
+    double norm_h;     /* ||H|| in opts.norm                                  */
+    double norm_fro;   /* ||H||_F (the normality test's scale)                */
+    int M, N;          /* problem (4.20) at norm_h and eps                    */
+    int normal;        /* Algorithm 4.2 step 2 (test or opts.normal)          */
+    double a;          /* filter constant: 1/(N+1), or min(1/(N+1), 1/||H||)
+                          for non-normal H; 0 without the paper's filter      */
+    double h0, r0;     /* ||H 2^-N|| and the bound of Eq. (4.5)               */
+    double eg0;        /* the Taylor terms' budget a r0 / (M e^{2 h0})        */
+} expm_analysis;
+
+/* Algorithm 4.2 steps 1-3 for H and eps_tol (as expm_sparse would take
+ * them on this plan): validates H, computes its norms on the device, and
+ * fills *out; nothing else runs and no output is allocated.  A zero H gives
+ * M = N = 0.  Errors: EXPM_EINVAL, EXPM_ERANGE, EXPM_ENOMEM, EXPM_EHIP. */
+int expm_analyze(expm_plan_t p, const expm_csr_cview *H, double eps, expm_analysis *out);
+
+/* Y = A X on the device: A an n x n CSR view (typically E = e^H), X and Y
+ * dense n x m, row-major with leading dimensions ldx, ldy >= m (device
+ * pointers; Y must not overlap X).  Section 5.3 checks large exponentials
+ * through E R with R = rand(n, 1000).  Each row of Y sums its products in
+ * the column order of A's row.  Errors: EXPM_EINVAL, EXPM_ENOMEM, EXPM_EHIP. */
+int expm_spmm(expm_plan_t p, const expm_csr_cview *A, int64_t m, const double *X, int64_t ldx,
+              double *Y, int64_t ldy);
+
+/* Time stepping with a computed exponential, Eq. (2.2): U_{k+1} = E U_k for
+ * k = 0 .. steps-1, U_0 given (n x m, row-major, leading dimension m), and
+ * U_steps written to U (device pointers; U may equal U0).  Errors as
+ * expm_spmm. */
+int expm_propagate(expm_plan_t p, const expm_csr_cview *E, int64_t m, const double *U0,
+                   int steps, double *U);
+
+/* ||H^k||_F for k = 1..K into out[0..K-1] (host array), by K - 1 unfiltered
+ * sparse products on the device: the norms of the powers that h_{M,N} of
+ * section 4.2 (the refinement before Eq. (4.9)) takes its maximum over.
+ * Errors: EXPM_EINVAL, EXPM_ENOMEM, EXPM_EHIP. */
+int expm_power_norms(expm_plan_t p, const expm_csr_cview *H, int K, double *out);
+
+/* Host helper, Eq. (4.8)/(4.9): alpha-hat_i, the least M1 2^N1 (M1 >= 1,
+ * 0 <= N1 <= 60) with 2^N1 r0(M1, x) <= r_i, where x = norm 2^(i-N-N1)
+ * (Eq. 4.8, hk = NULL) or x = 2^(i-N-N1) max over M1+1 <= k <= 2M1+1 of
+ * hk[k-1]^(1/k) with hk[k-1] = ||H^k|| for k = 1..K (Eq. 4.9, M1 then at
+ * most (K-1)/2); for each N1 the least qualifying M1 is taken.
+ * alpha-hat_i lambda(H) bounds the epsilon-bandwidth of e^{H 2^(i-N)}
+ * (Eq. 4.7).  Errors: EXPM_EINVAL, EXPM_ERANGE (no pair qualifies). */
+int expm_alpha_hat(double ri, int i, int N, double norm, const double *hk, int K,
+                   int64_t *out);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

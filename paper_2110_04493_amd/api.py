@@ -85,6 +85,9 @@ class Options:
     profile: int = 0           # 1: phase timers and work counts, 2: tile kernel timers only
     reorder: int = -1
     tile_min_fill: float = -1.0
+    norm: int = capi.EXPM_NORM_FRO
+    exact_ri: bool = False
+    diagnostics: bool = False
 
 
 class Plan:
@@ -109,6 +112,9 @@ class Plan:
         o.profile = int(self.options.profile)
         o.reorder = int(self.options.reorder)
         o.tile_min_fill = float(self.options.tile_min_fill)
+        o.norm = int(self.options.norm)
+        o.exact_ri = int(self.options.exact_ri)
+        o.diagnostics = int(self.options.diagnostics)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)
@@ -173,6 +179,49 @@ class Plan:
 
     def stats(self) -> dict:
         return capi.expm_get_stats(self.handle)
+
+    def analyze(self, crow, col, val, eps: float) -> dict:
+        """Algorithm 4.2 steps 1-3 for H (norms, (M, N), normality, a, r0,
+        the Taylor budget) without running the method."""
+        _check_inputs(crow, col, val)
+        with torch.cuda.device(self.device):
+            self._inputs_ready()
+            return capi.expm_analyze(self.handle, _view(crow, col, val), eps)
+
+    def spmm(self, crow, col, val, X: torch.Tensor) -> torch.Tensor:
+        """Y = A X for a CSR matrix A (typically E) and a dense block X."""
+        _check_inputs(crow, col, val)
+        X = X.contiguous()
+        if X.dtype != torch.float64 or X.device != val.device or X.dim() != 2:
+            raise TypeError("X must be a 2-D float64 tensor on the matrix's device")
+        with torch.cuda.device(self.device):
+            with torch.cuda.stream(self.stream):
+                Y = torch.empty_like(X)
+            self._inputs_ready()
+            capi.expm_spmm(self.handle, _view(crow, col, val), X.shape[1], X.data_ptr(),
+                           X.shape[1], Y.data_ptr(), Y.shape[1])
+            self._handover()
+        return Y
+
+    def propagate(self, crow, col, val, U0: torch.Tensor, steps: int) -> torch.Tensor:
+        """U_steps of Eq. (2.2)'s time stepping U_{k+1} = E U_k."""
+        _check_inputs(crow, col, val)
+        U0 = U0.contiguous()
+        with torch.cuda.device(self.device):
+            with torch.cuda.stream(self.stream):
+                U = torch.empty_like(U0)
+            self._inputs_ready()
+            capi.expm_propagate(self.handle, _view(crow, col, val), U0.shape[1], U0.data_ptr(),
+                                int(steps), U.data_ptr())
+            self._handover()
+        return U
+
+    def power_norms(self, crow, col, val, K: int) -> list:
+        """||H^k||_F for k = 1..K (the norms behind h_{M,N} of Eq. (4.9))."""
+        _check_inputs(crow, col, val)
+        with torch.cuda.device(self.device):
+            self._inputs_ready()
+            return capi.expm_power_norms(self.handle, _view(crow, col, val), K)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -24,6 +24,9 @@ EXPM_ESTATE = -7
 EXPM_NORMAL_AUTO = -1
 EXPM_FILTER_PAPER = 0
 EXPM_FILTER_NONE = 1
+EXPM_FILTER_FIXED_REL = 2
+EXPM_NORM_FRO = 0
+EXPM_NORM_ONE = 1
 EXPM_MAXSTEP = 128
 
 ERROR_NAMES = {0: "EXPM_OK", -1: "EXPM_EINVAL", -2: "EXPM_ENOMEM", -3: "EXPM_EHIP",
@@ -32,7 +35,8 @@ ERROR_NAMES = {0: "EXPM_OK", -1: "EXPM_EINVAL", -2: "EXPM_ENOMEM", -3: "EXPM_EHI
 # Every function the header declares.
 SYMBOLS = ["expm_opts_default", "expm_plan", "expm_sparse", "expm_sparse_backward",
            "expm_sparse_batched", "expm_get_stats", "expm_csr_release", "expm_free",
-           "expm_last_error", "expm_r0", "expm_choose_mn", "expm_sparse_noalloc"]
+           "expm_last_error", "expm_r0", "expm_choose_mn", "expm_sparse_noalloc",
+           "expm_analyze", "expm_spmm", "expm_propagate", "expm_power_norms", "expm_alpha_hat"]
 
 # bytes of the static device array behind expm_sparse_noalloc (expm.h)
 NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -40,7 +44,7 @@ NOALLOC_SCRATCH_BYTES = 256 << 20
 
 class expm_csr_cview(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
-                ("col", C.c_void_p), ("val", C.c_void_p)]
+                ("col", C.c_void_p), ("val", C.c_void_p), ("on_host", C.c_int)]
 
 
 class expm_csr(C.Structure):
@@ -61,7 +65,8 @@ class expm_opts(C.Structure):
                 ("max_filter_iter", C.c_int), ("keep_checkpoints", C.c_int),
                 ("checkpoint_interval", C.c_int), ("stream", C.c_void_p),
                 ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int),
-                ("reorder", C.c_int), ("tile_min_fill", C.c_double)]
+                ("reorder", C.c_int), ("tile_min_fill", C.c_double), ("norm", C.c_int),
+                ("exact_ri", C.c_int), ("diagnostics", C.c_int)]
 
 
 _S = EXPM_MAXSTEP
@@ -86,7 +91,10 @@ class expm_stats(C.Structure):
                 ("t_total_ms", C.c_double),
                 ("tile_launches", C.c_int64), ("tile_ms", C.c_double),
                 ("tile_flops", C.c_double), ("adj_tile_launches", C.c_int64),
-                ("adj_tile_ms", C.c_double), ("sq_tiles", C.c_int * _S)]
+                ("adj_tile_ms", C.c_double), ("sq_tiles", C.c_int * _S),
+                ("sq_ri", C.c_double * _S), ("sq_band", C.c_int64 * _S),
+                ("theta0", C.c_double), ("tile_bytes", C.c_double),
+                ("adj_tile_flops", C.c_double), ("adj_tile_bytes", C.c_double)]
 
     def to_dict(self) -> dict:
         d = {k: getattr(self, k) for k in ("status", "M", "N", "taylor_terms", "normal",
@@ -94,15 +102,26 @@ class expm_stats(C.Structure):
                                            "nnz_e", "peak_workspace_bytes", "t_taylor_ms",
                                            "t_backward_ms", "t_total_ms", "tile_launches",
                                            "tile_ms", "tile_flops", "adj_tile_launches",
-                                           "adj_tile_ms")}
+                                           "adj_tile_ms", "theta0", "tile_bytes",
+                                           "adj_tile_flops", "adj_tile_bytes")}
         T, N = self.taylor_terms, self.squarings
         for k in ("taylor_theta", "taylor_iters", "taylor_cand", "taylor_kept"):
             d[k] = list(getattr(self, k)[2:T + 2])
         for k in ("sq_theta", "sq_normF", "sq_budget", "sq_dropped", "sq_iters", "sq_cand",
                   "sq_kept", "sq_fma", "sq_in", "t_sym_ms", "t_num_ms", "t_filter_ms",
-                  "sq_tiles"):
+                  "sq_tiles", "sq_ri"):
             d[k] = list(getattr(self, k)[1:N + 1])
+        d["sq_band"] = list(self.sq_band[0:N + 1])   # l(T^_0) .. l(T^_N), -1: not computed
         return d
+
+
+class expm_analysis(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("norm_h", C.c_double),
+                ("norm_fro", C.c_double), ("M", C.c_int), ("N", C.c_int), ("normal", C.c_int),
+                ("a", C.c_double), ("h0", C.c_double), ("r0", C.c_double), ("eg0", C.c_double)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ExpmError(RuntimeError):
@@ -142,6 +161,15 @@ def lib():
                                      C.POINTER(C.c_int)]
         L.expm_sparse_noalloc.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_double, _P, _P,
                                           _P, C.c_int64, C.POINTER(C.c_int64)]
+        L.expm_analyze.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_double,
+                                   C.POINTER(expm_analysis)]
+        L.expm_spmm.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_int64, _P, C.c_int64, _P,
+                                C.c_int64]
+        L.expm_propagate.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_int64, _P, C.c_int, _P]
+        L.expm_power_norms.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_int,
+                                       C.POINTER(C.c_double)]
+        L.expm_alpha_hat.argtypes = [C.c_double, C.c_int, C.c_int, C.c_double,
+                                     C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int64)]
         for name in SYMBOLS:
             if name not in ("expm_opts_default", "expm_csr_release", "expm_free",
                             "expm_last_error", "expm_r0"):
@@ -186,6 +214,42 @@ def expm_sparse_noalloc(plan: int, H: expm_csr_cview, eps: float, rowptr_ptr: in
         err.nnz_e = nnz.value
         raise err
     return nnz.value
+
+
+def expm_analyze(plan: int, H: expm_csr_cview, eps: float) -> dict:
+    a = expm_analysis()
+    check(lib().expm_analyze(_P(plan), C.byref(H), float(eps), C.byref(a)), "expm_analyze")
+    return a.to_dict()
+
+
+def expm_spmm(plan: int, A: expm_csr_cview, m: int, X_ptr: int, ldx: int, Y_ptr: int,
+              ldy: int) -> None:
+    check(lib().expm_spmm(_P(plan), C.byref(A), int(m), _P(X_ptr), int(ldx), _P(Y_ptr),
+                          int(ldy)), "expm_spmm")
+
+
+def expm_propagate(plan: int, E: expm_csr_cview, m: int, U0_ptr: int, steps: int,
+                   U_ptr: int) -> None:
+    check(lib().expm_propagate(_P(plan), C.byref(E), int(m), _P(U0_ptr), int(steps),
+                               _P(U_ptr)), "expm_propagate")
+
+
+def expm_power_norms(plan: int, H: expm_csr_cview, K: int) -> list:
+    out = (C.c_double * max(K, 1))()
+    check(lib().expm_power_norms(_P(plan), C.byref(H), int(K), out), "expm_power_norms")
+    return [out[k] for k in range(K)]
+
+
+def expm_alpha_hat(ri: float, i: int, N: int, norm: float = 0.0, hk=None) -> int:
+    out = C.c_int64()
+    if hk is None:
+        code = lib().expm_alpha_hat(float(ri), int(i), int(N), float(norm), None, 0,
+                                    C.byref(out))
+    else:
+        arr = (C.c_double * len(hk))(*[float(x) for x in hk])
+        code = lib().expm_alpha_hat(float(ri), int(i), int(N), 0.0, arr, len(hk), C.byref(out))
+    check(code, "expm_alpha_hat")
+    return out.value
 
 
 def expm_sparse_backward(plan: int, dE_ptr: int, dH_ptr: int) -> None:

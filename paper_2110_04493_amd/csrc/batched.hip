@@ -313,6 +313,13 @@ int batched(expm_plan_s &P, BatchBufs &B, int count, const expm_csr_cview *H, co
     free_adjoint_state(P);
     memset(&P.stats, 0, sizeof P.stats);
     if (count == 0) return EXPM_OK;
+    if (P.opts.filter_mode == EXPM_FILTER_FIXED_REL || P.opts.norm != EXPM_NORM_FRO ||
+        P.opts.exact_ri)
+        return fail(EXPM_ENOTIMPL, "the batched path runs the default filter, norm and error "
+                                   "recurrence only");
+    for (int k = 0; k < count; ++k)
+        if (H[k].on_host) return fail(EXPM_EINVAL, "instance %d: the batched path takes device "
+                                                   "views only", k);
     std::vector<Inst> in(count);
     for (int k = 0; k < count; ++k) {
         CHK(check_view(&H[k]));

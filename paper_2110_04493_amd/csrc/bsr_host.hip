@@ -274,6 +274,9 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         HIPCHK(hipEventRecord(P.ev[0], st));
     }
     int64_t ctiles = 0;
+    // the FPIM's filter (forward steps): a threshold from the candidate's
+    // 1-norm instead of Algorithm 4.1
+    const bool fpim = P.fpim_eps > 0.0 && !use_fixed;
     CHK(tile_product(P, T.view(), prof, true, &ctiles));
     // ||I + T~||_F and the nonzero candidate count
     CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));
@@ -285,7 +288,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                           (const int32_t *)P.c_cols.p, (const double *)P.c_sq.p,
                           (const int32_t *)P.c_nz.p, (const double *)P.b_dg.p,
                           (double *)P.b_sq.p, (int64_t *)P.b_nz.p, st));
-    if (!use_fixed)
+    if (!use_fixed && !fpim)
         HIPCHK(sum_values((const double *)P.b_sq.p, nb, (double *)P.part.p, kParts,
                           (double *)P.norm2.p, st));
     CHK(scan(P, (const int64_t *)P.b_nz.p, (int64_t *)P.tmp2.p, nb));
@@ -294,11 +297,19 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
     CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
     FilterCtl *ctl = (FilterCtl *)P.ctl.p;
-    if (use_fixed)
+    if (fpim) {
+        CHK(ensure(P, P.colsum, sizeof(double) * (n + 1)));
+        CHK(ensure(P, P.amax, sizeof(unsigned long long) * 2));
+        HIPCHK(fpim_theta_tiles(n, ctiles, (const int32_t *)P.c_cols.p,
+                                (const double *)P.c_tiles.p, (double *)P.colsum.p,
+                                (unsigned long long *)P.amax.p, P.fpim_eps, ctl, st));
+        use_fixed = true;
+    } else if (use_fixed) {
         HIPCHK(filter_init_theta(ctl, theta_fixed, st));
-    else
+    } else {
         HIPCHK(filter_init(ctl, a_ri, (const double *)P.norm2.p, P.opts.e_r,
                            P.opts.max_filter_iter, st));
+    }
     FilterCtl h{};
     int64_t kept = 0, cand_nz = 0;
     for (int round = 0;; ++round) {
@@ -353,6 +364,7 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         S.tile_launches += 1;
         S.tile_ms += t1;
         S.tile_flops += 2.0 * (double)fma + 2.0 * (double)T.nnz;
+        S.tile_bytes += 12.0 * (double)T.nnz + 8.0 * (double)(n + 1) + 12.0 * (double)cand_nz;
         if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
             S.t_sym_ms[stat_i] = t0;
             S.t_num_ms[stat_i] = t1;
@@ -367,10 +379,46 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         S.sq_iters[stat_i] = h.iter;
         S.sq_cand[stat_i] = cand_nz;
         S.sq_kept[stat_i] = kept;
-        S.sq_budget[stat_i] = h.eg;
-        S.sq_normF[stat_i] = a_ri > 0 ? h.eg / a_ri : 0.0;
+        S.sq_budget[stat_i] = fpim ? h.theta : h.eg;
+        S.sq_normF[stat_i] = a_ri > 0 && !fpim ? h.eg / a_ri : 0.0;
         S.sq_dropped[stat_i] = h.b;
     }
+    return EXPM_OK;
+}
+
+// The number of partial products of G T^T and T^T G (G on Tk's pattern,
+// T = Tp) whose position lies in Tp's pattern, for the profile statistics:
+// the masked row product run on all-ones values.
+static int count_adjoint_products(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, double *pp) {
+    const int64_t n = Tp.n;
+    DCsr Tt;
+    Buf ones_p, ones_k, cnt;
+    auto free_locals = at_exit([&] {
+        release(P, Tt);
+        release(P, ones_p);
+        release(P, ones_k);
+        release(P, cnt);
+    });
+    CHK(transpose_csr(P, Tp, Tt));
+    CHK(ensure(P, ones_p, sizeof(double) * (Tp.nnz + 1)));
+    CHK(ensure(P, ones_k, sizeof(double) * (Tk.nnz + 1)));
+    CHK(ensure(P, cnt, sizeof(double) * (Tp.nnz + 1)));
+    HIPCHK(fill_f64((double *)ones_p.p, Tp.nnz, 1.0, P.st));
+    HIPCHK(fill_f64((double *)ones_k.p, Tk.nnz, 1.0, P.st));
+    const CsrView G1{n, (const int64_t *)Tk.rp.p, (const int32_t *)Tk.ci.p,
+                     (const double *)ones_k.p};
+    const CsrView Tt1{n, (const int64_t *)Tt.rp.p, (const int32_t *)Tt.ci.p,
+                      (const double *)ones_p.p};
+    const CsrView M{n, (const int64_t *)Tp.rp.p, (const int32_t *)Tp.ci.p, nullptr};
+    const MaskTerm t1{G1, Tt1, 1.0}, t2{Tt1, G1, 1.0};
+    CHK(masked(P, M, G1, 0.0, t1, t2, 1.0, (double *)cnt.p));
+    CHK(ensure(P, P.norm2, sizeof(double) * 2));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    HIPCHK(sum_values((const double *)cnt.p, Tp.nnz, (double *)P.part.p, kParts,
+                      (double *)P.norm2.p, P.st));
+    HIPCHK(hipMemcpyAsync(P.host, P.norm2.p, sizeof(double), hipMemcpyDeviceToHost, P.st));
+    CHK(sync(P));
+    memcpy(pp, P.host, sizeof(double));
     return EXPM_OK;
 }
 
@@ -438,6 +486,14 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
         HIPCHK(hipEventElapsedTime(&t, P.ev[4], P.ev[5]));
         P.stats.adj_tile_launches += 1;
         P.stats.adj_tile_ms += t;
+        // algorithmic work of the step: the partial products of G T^T and
+        // T^T G that land in T's pattern, counted by the masked row product
+        // on all-ones values (exact integers in double), 2 flops each, plus
+        // 2 per mask entry; bytes: G and T read once, the output written
+        double pp = 0.0;
+        CHK(count_adjoint_products(P, Tp, Tk, &pp));
+        P.stats.adj_tile_flops += 2.0 * pp + 2.0 * (double)Tp.nnz;
+        P.stats.adj_tile_bytes += 12.0 * (double)Tk.nnz + 20.0 * (double)Tp.nnz;
     }
     if (want_csr) CHK(gather_tiles(P, Tp, T, (const double *)P.adj_tiles.p, out));
     return EXPM_OK;

@@ -427,9 +427,9 @@ int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
     CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
     CHK(ensure(P, P.cnt, sizeof(int64_t) * (n + 1)));
     FilterCtl *ctl = (FilterCtl *)P.ctl.p;
-    if (use_fixed)
+    if (use_fixed && theta_fixed != kThetaOnDevice)
         HIPCHK(filter_init_theta(ctl, theta_fixed, st));
-    else
+    else if (!use_fixed)
         HIPCHK(filter_init(ctl, eg_scale, norm2, P.opts.e_r, P.opts.max_filter_iter, st));
     const int64_t *crp = (const int64_t *)P.crp.p;
     for (int round = 0;; ++round) {
@@ -725,8 +725,21 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
         return square_step_bsr(P, T, dst, a_ri, use_fixed, theta_fixed, exact_alloc, stat_i);
     }
     int64_t cand;
-    CHK(spgemm(P, T.view(), T.nnz, T.view(), 2.0, 1.0, !use_fixed, &cand));
-    if (!use_fixed) {
+    // the FPIM's filter (forward steps): a threshold from the candidate's
+    // 1-norm instead of Algorithm 4.1
+    const bool fpim = P.fpim_eps > 0.0 && !use_fixed;
+    CHK(spgemm(P, T.view(), T.nnz, T.view(), 2.0, 1.0, !use_fixed && !fpim, &cand));
+    if (fpim) {
+        CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
+        CHK(ensure(P, P.colsum, sizeof(double) * (n + 1)));
+        CHK(ensure(P, P.amax, sizeof(unsigned long long) * 2));
+        HIPCHK(fpim_theta_rows((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
+                               (const double *)P.cv.p, n, (double *)P.colsum.p,
+                               (unsigned long long *)P.amax.p, P.fpim_eps, (FilterCtl *)P.ctl.p,
+                               P.st));
+        use_fixed = true;
+        theta_fixed = kThetaOnDevice;
+    } else if (!use_fixed) {
         CHK(ensure(P, P.norm2, sizeof(double) * 2));
         CHK(ensure(P, P.part, sizeof(double) * kParts));
         HIPCHK(sum_values((const double *)P.rowsq.p, n, (double *)P.part.p, kParts,
@@ -756,10 +769,84 @@ int square_step(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_
         S.sq_iters[stat_i] = h.iter;
         S.sq_cand[stat_i] = cand;
         S.sq_kept[stat_i] = kept;
-        S.sq_budget[stat_i] = h.eg;
-        S.sq_normF[stat_i] = a_ri > 0 ? h.eg / a_ri : 0.0;
+        S.sq_budget[stat_i] = fpim ? h.theta : h.eg;
+        S.sq_normF[stat_i] = a_ri > 0 && !fpim ? h.eg / a_ri : 0.0;
         S.sq_dropped[stat_i] = h.b;
     }
+    return EXPM_OK;
+}
+
+// Algorithm 4.2 steps 1-3 on H: copies H into dst (from host memory when
+// the view says so), validates it, computes ||H||_F and the norm of
+// opts.norm on the device, then (M, N) by problem (4.20), the normality and
+// a, r0 and eg0.  A zero H gives M = N = 0 and norm_fro = 0.
+int plan_input(expm_plan_s &P, const expm_csr_cview *Hv, double eps, DCsr &dst,
+               expm_analysis *A) {
+    hipStream_t st = P.st;
+    const int64_t n = Hv->n, nnz = Hv->nnz;
+    memset(A, 0, sizeof *A);
+    A->n = n;
+    A->nnz = nnz;
+    const hipMemcpyKind kind = Hv->on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    CHK(ensure_csr(P, dst, n, nnz));
+    HIPCHK(hipMemcpyAsync(dst.rp.p, Hv->rowptr, sizeof(int64_t) * (n + 1), kind, st));
+    if (nnz) {
+        HIPCHK(hipMemcpyAsync(dst.ci.p, Hv->col, sizeof(int32_t) * nnz, kind, st));
+        HIPCHK(hipMemcpyAsync(dst.v.p, Hv->val, sizeof(double) * nnz, kind, st));
+    }
+    // validate + ||H||_F
+    CHK(ensure(P, P.flags, sizeof(int) * 4));
+    CHK(ensure(P, P.norm2, sizeof(double) * 2));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    HIPCHK(hipMemsetAsync(P.flags.p, 0, sizeof(int), st));
+    HIPCHK(validate_csr(dst.view(), nnz, (int *)P.flags.p, st));
+    HIPCHK(sumsq((const double *)dst.v.p, nullptr, nnz, (double *)P.part.p, kParts,
+                 (double *)P.norm2.p, st));
+    HIPCHK(hipMemcpyAsync(P.host, P.flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char *)P.host + 8, P.norm2.p, sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    CHK(sync(P));
+    int flag;
+    double nh2;
+    memcpy(&flag, P.host, sizeof flag);
+    memcpy(&nh2, (char *)P.host + 8, sizeof nh2);
+    if (flag & 1) return fail(EXPM_EINVAL, "rowptr is not a valid CSR row pointer");
+    if (flag & 2) return fail(EXPM_EINVAL, "column indices out of range or not strictly increasing");
+    if (flag & 4) return fail(EXPM_EINVAL, "H holds NaN or Inf");
+    const double nf = sqrt(nh2);
+    A->norm_fro = nf;
+    A->norm_h = nf;
+    if (nf == 0.0) return EXPM_OK;
+    if (P.opts.norm == EXPM_NORM_ONE) {
+        // the largest column sum: row sums of H^T, each in row order of H
+        DCsr Ht;
+        auto free_ht = at_exit([&] { release(P, Ht); });
+        CHK(transpose_csr(P, dst, Ht));
+        CHK(ensure(P, P.amax, sizeof(unsigned long long) * 2));
+        HIPCHK(row_abs_max(Ht.view(), (unsigned long long *)P.amax.p, st));
+        HIPCHK(hipMemcpyAsync(P.host, P.amax.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        memcpy(&A->norm_h, P.host, sizeof(double));
+    }
+    const double nh = A->norm_h;
+    int M, N;
+    int s = plan_mn(nh, eps, &M, &N);
+    if (s == EXPM_ERANGE) return fail(EXPM_ERANGE, "no (M, N) satisfies problem (4.20)");
+    if (s) return fail(s, "invalid norm %g", nh);
+    if (N >= EXPM_MAXSTEP - 1 || M >= EXPM_MAXSTEP - 1)
+        return fail(EXPM_ERANGE, "(M, N) = (%d, %d) exceeds the step limit", M, N);
+    int normal = P.opts.normal;
+    if (normal < 0) CHK(detect_normal(P, dst, nf, &normal));
+    double a = 1.0 / (N + 1);
+    if (!normal && 1.0 / nh < a) a = 1.0 / nh;
+    if (P.opts.filter_mode != EXPM_FILTER_PAPER) a = 0.0;
+    A->M = M;
+    A->N = N;
+    A->normal = normal;
+    A->a = a;
+    A->h0 = ldexp(nh, -N);
+    A->r0 = plan_r0(M, A->h0);
+    A->eg0 = a * A->r0 / (M * exp(2.0 * A->h0));
     return EXPM_OK;
 }
 
@@ -799,39 +886,12 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.have_stats = true;
         return EXPM_OK;
     }
-    // own copy of H's pattern; H0 values
-    CHK(ensure_csr(P, P.H0, n, nnz));
-    HIPCHK(hipMemcpyAsync(P.H0.rp.p, Hv->rowptr, sizeof(int64_t) * (n + 1),
-                          hipMemcpyDeviceToDevice, st));
-    if (nnz) {
-        HIPCHK(hipMemcpyAsync(P.H0.ci.p, Hv->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice,
-                              st));
-        HIPCHK(hipMemcpyAsync(P.H0.v.p, Hv->val, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
-                              st));
-    }
-    // validate + ||H||_F
-    CHK(ensure(P, P.flags, sizeof(int) * 4));
-    CHK(ensure(P, P.norm2, sizeof(double) * 2));
-    CHK(ensure(P, P.part, sizeof(double) * kParts));
-    HIPCHK(hipMemsetAsync(P.flags.p, 0, sizeof(int), st));
-    HIPCHK(validate_csr(P.H0.view(), nnz, (int *)P.flags.p, st));
-    HIPCHK(sumsq((const double *)P.H0.v.p, nullptr, nnz, (double *)P.part.p, kParts,
-                 (double *)P.norm2.p, st));
-    HIPCHK(hipMemcpyAsync(P.host, P.flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char *)P.host + 8, P.norm2.p, sizeof(double), hipMemcpyDeviceToHost,
-                          st));
-    CHK(sync(P));
-    int flag;
-    double nh2;
-    memcpy(&flag, P.host, sizeof flag);
-    memcpy(&nh2, (char *)P.host + 8, sizeof nh2);
-    if (flag & 1) return fail(EXPM_EINVAL, "rowptr is not a valid CSR row pointer");
-    if (flag & 2) return fail(EXPM_EINVAL, "column indices out of range or not strictly increasing");
-    if (flag & 4) return fail(EXPM_EINVAL, "H holds NaN or Inf");
+    expm_analysis A{};
+    CHK(plan_input(P, Hv, eps, P.H0, &A));
     expm_stats &S = P.stats;
-    const double nh = sqrt(nh2);
+    const double nh = A.norm_h;
     S.norm_h = nh;
-    if (nh == 0.0) {
+    if (A.norm_fro == 0.0) {
         P.zero_h = true;
         CHK(output_identity(P, n, E));
         P.Epat.n = 0;
@@ -841,22 +901,17 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         return EXPM_OK;
     }
     P.zero_h = false;
-    // Step 1: (M, N); step 2: a.
-    int M, N;
-    int s = plan_mn(nh, eps, &M, &N);
-    if (s == EXPM_ERANGE) return fail(EXPM_ERANGE, "no (M, N) satisfies problem (4.20)");
-    if (s) return fail(s, "invalid norm %g", nh);
-    if (N >= EXPM_MAXSTEP - 1 || M >= EXPM_MAXSTEP - 1)
-        return fail(EXPM_ERANGE, "(M, N) = (%d, %d) exceeds the step limit", M, N);
-    int normal = P.opts.normal;
-    if (normal < 0) CHK(detect_normal(P, P.H0, nh, &normal));
-    double a = 1.0 / (N + 1);
-    if (!normal && 1.0 / nh < a) a = 1.0 / nh;
-    if (P.opts.filter_mode == EXPM_FILTER_NONE) a = 0.0;
+    const int M = A.M, N = A.N;
+    const double a = A.a;
     S.M = M;
     S.N = N;
-    S.normal = normal;
+    S.normal = A.normal;
     S.a = a;
+    const bool fpim = P.opts.filter_mode == EXPM_FILTER_FIXED_REL;
+    P.fpim_eps = fpim ? eps : 0.0;
+    const bool diag = P.opts.diagnostics != 0;
+    for (int i = 0; i < EXPM_MAXSTEP; ++i) S.sq_band[i] = -1;
+    if (diag) CHK(ensure(P, P.bands, sizeof(long long) * 2 * (N + 1)));
     const bool keep = P.opts.keep_checkpoints != 0;
     // Locality reordering: H' = P H P^T replaces H; E is permuted back below.
     {
@@ -879,8 +934,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     const auto t_taylor0 = std::chrono::steady_clock::now();
     // Step 3: H0 = H 2^-N, r0, eg0, Taylor seed.
     HIPCHK(scale_ldexp((const double *)P.H0.v.p, (double *)P.H0.v.p, nnz, -N, st));
-    const double h0 = ldexp(nh, -N), r0 = plan_r0(M, h0);
-    const double eg0 = a * r0 / (M * exp(2.0 * h0));
+    const double h0 = A.h0, r0 = A.r0, eg0 = A.eg0;
     S.h0 = h0;
     S.r0 = r0;
     S.eg0 = eg0;
@@ -929,6 +983,31 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
                           st));
     CHK(sync(P));
     memcpy(&P.T.nnz, P.host, sizeof(int64_t));
+    if (fpim) {
+        // the FPIM's filter of T_0: entries at or below eps ||T_0||_1 leave
+        // (T_0's buffers serve as the candidate, and the kept entries go
+        // back to T_0's buffers)
+        auto swap_cand = [&] {
+            std::swap(P.crp, P.T.rp);
+            std::swap(P.cci, P.T.ci);
+            std::swap(P.cv, P.T.v);
+        };
+        swap_cand();
+        CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
+        CHK(ensure(P, P.colsum, sizeof(double) * (n + 1)));
+        CHK(ensure(P, P.amax, sizeof(unsigned long long) * 2));
+        HIPCHK(fpim_theta_rows((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
+                               (const double *)P.cv.p, n, (double *)P.colsum.p,
+                               (unsigned long long *)P.amax.p, eps, (FilterCtl *)P.ctl.p, st));
+        FilterCtl h{};
+        int64_t kept;
+        CHK(filter_and_count(P, n, P.T.nnz, 0.0, nullptr, true, -2.0, false, &h, &kept));
+        CHK(write_filtered(P, n, P.T, kept, false, false));
+        P.T.nnz = kept;
+        S.theta0 = h.theta;
+    }
+    if (diag) HIPCHK(band_of(P.T.view(), P.perm_active ? (const int32_t *)P.order.p : nullptr,
+                            (long long *)P.bands.p, st));
     // The current iterate; a checkpoint takes over P.T's buffers (no copy)
     // and is read by the next squaring in place.
     const DCsr *cur = &P.T;
@@ -960,10 +1039,16 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     }
     size_t kept_tiles = 0;
     int cur_ck = keep ? 0 : -1;   // checkpoint index of *cur, or -1
+    double ri = r0;
     for (int i = 1; i <= N; ++i) {
-        const double ri = ldexp(r0, i);
+        // Eq. (4.3): r_i = 2 r_{i-1} + r_{i-1}^2, or its simplification 2^i r0
+        ri = P.opts.exact_ri ? 2.0 * ri + ri * ri : ldexp(r0, i);
+        S.sq_ri[i] = ri;
         const bool last = i == N;
         CHK(square_step(P, *cur, P.Tnew, a * ri, false, 0.0, false, false, i, i));
+        if (diag)
+            HIPCHK(band_of(P.Tnew.view(), P.perm_active ? (const int32_t *)P.order.p : nullptr,
+                           (long long *)P.bands.p + 2 * i, st));
         if (cur_ck >= 0 && P.sq_path[i - 1]) {   // P.tsT holds the checkpoint's tiles
             const size_t b = P.tsT.tA.bytes + P.tsT.tB.bytes + P.tsT.seg.bytes;
             if (last || kept_tiles + b <= P.dev_mem / 8) {
@@ -1056,6 +1141,14 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
             P.Epat.n = n;
             P.Epat.nnz = kept;
         }
+    }
+    if (diag) {
+        long long *hb = (long long *)P.host;
+        HIPCHK(hipMemcpyAsync(hb, P.bands.p, sizeof(long long) * 2 * (N + 1),
+                              hipMemcpyDeviceToHost, st));
+        CHK(sync(P));
+        for (int i = 0; i <= N; ++i)
+            S.sq_band[i] = hb[2 * i] == LLONG_MIN ? 0 : hb[2 * i] + hb[2 * i + 1];
     }
     S.peak_workspace_bytes = P.peak;
     P.have_fwd = keep;
@@ -1307,6 +1400,9 @@ void expm_opts_default(expm_opts *o) {
     o->allocator = nullptr;
     o->reorder = -1;
     o->tile_min_fill = -1.0;
+    o->norm = EXPM_NORM_FRO;
+    o->exact_ri = 0;
+    o->diagnostics = 0;
 }
 
 int expm_plan(expm_plan_t *out, const expm_opts *opts) {
@@ -1318,8 +1414,13 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
         o = *opts;
     else
         expm_opts_default(&o);
-    if (o.filter_mode != EXPM_FILTER_PAPER && o.filter_mode != EXPM_FILTER_NONE)
+    if (o.filter_mode != EXPM_FILTER_PAPER && o.filter_mode != EXPM_FILTER_NONE &&
+        o.filter_mode != EXPM_FILTER_FIXED_REL)
         return fail(EXPM_EINVAL, "unknown filter_mode %d", o.filter_mode);
+    if (o.norm != EXPM_NORM_FRO && o.norm != EXPM_NORM_ONE)
+        return fail(EXPM_EINVAL, "unknown norm %d", o.norm);
+    if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1)
+        return fail(EXPM_EINVAL, "invalid option value");
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
         o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1 || o.profile < 0 ||
         o.profile > 2 ||
@@ -1491,6 +1592,170 @@ int expm_get_stats(expm_plan_t p, expm_stats *out) {
     return EXPM_OK;
 }
 
+int expm_analyze(expm_plan_t p, const expm_csr_cview *H, double eps, expm_analysis *out) {
+    g_err.clear();
+    if (!p || !out) return fail(EXPM_EINVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    CHK(check_view(H));
+    if (!(eps >= ldexp(1.0, -60) && eps < 1.0))
+        return fail(EXPM_EINVAL, "eps = %g outside [2^-60, 1)", eps);
+    if (H->n == 0) return EXPM_OK;
+    // a scratch copy of H: the plan's own state (the adjoint's) stays intact
+    DCsr Hc;
+    auto free_hc = at_exit([&] { release(*p, Hc); });
+    const int s = plan_input(*p, H, eps, Hc, out);
+    if (s != EXPM_OK) {
+        (void)hipStreamSynchronize(p->st);
+        (void)hipGetLastError();
+    }
+    return s;
+}
+
+// A device view of A: A itself, or (on_host) a copy in the plan's workspace.
+static int device_view(expm_plan_s &P, const expm_csr_cview *A, DCsr &copy, CsrView *out) {
+    CHK(check_view(A));
+    if (!A->on_host) {
+        *out = CsrView{A->n, A->rowptr, A->col, A->val};
+        return EXPM_OK;
+    }
+    CHK(ensure_csr(P, copy, A->n, A->nnz));
+    HIPCHK(hipMemcpyAsync(copy.rp.p, A->rowptr, sizeof(int64_t) * (A->n + 1),
+                          hipMemcpyHostToDevice, P.st));
+    if (A->nnz) {
+        HIPCHK(hipMemcpyAsync(copy.ci.p, A->col, sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice,
+                              P.st));
+        HIPCHK(hipMemcpyAsync(copy.v.p, A->val, sizeof(double) * A->nnz, hipMemcpyHostToDevice,
+                              P.st));
+    }
+    *out = copy.view();
+    return EXPM_OK;
+}
+
+int expm_spmm(expm_plan_t p, const expm_csr_cview *A, int64_t m, const double *X, int64_t ldx,
+              double *Y, int64_t ldy) {
+    g_err.clear();
+    if (!p) return fail(EXPM_EINVAL, "plan is NULL");
+    if (m < 0 || ldx < m || ldy < m) return fail(EXPM_EINVAL, "invalid block shape");
+    if (m > 0 && A && A->n > 0 && (!X || !Y)) return fail(EXPM_EINVAL, "X or Y is NULL");
+    DCsr copy;
+    auto free_copy = at_exit([&] { release(*p, copy); });
+    CsrView Av;
+    CHK(device_view(*p, A, copy, &Av));
+    HIPCHK(spmm(Av, m, X, ldx, Y, ldy, p->st));
+    return EXPM_OK;
+}
+
+int expm_propagate(expm_plan_t p, const expm_csr_cview *E, int64_t m, const double *U0,
+                   int steps, double *U) {
+    g_err.clear();
+    if (!p) return fail(EXPM_EINVAL, "plan is NULL");
+    if (m < 0 || steps < 0) return fail(EXPM_EINVAL, "invalid block shape or step count");
+    CHK(check_view(E));
+    const int64_t n = E->n;
+    if (n == 0 || m == 0) return EXPM_OK;
+    if (!U0 || !U) return fail(EXPM_EINVAL, "U0 or U is NULL");
+    DCsr copy;
+    Buf a, b;
+    auto free_locals = at_exit([&] {
+        release(*p, copy);
+        release(*p, a);
+        release(*p, b);
+    });
+    CsrView Ev;
+    CHK(device_view(*p, E, copy, &Ev));
+    const size_t bytes = sizeof(double) * (size_t)n * (size_t)m;
+    if (steps == 0) {
+        if (U != U0) HIPCHK(hipMemcpyAsync(U, U0, bytes, hipMemcpyDeviceToDevice, p->st));
+        return EXPM_OK;
+    }
+    // U_{k+1} = E U_k through two workspace blocks; the last step writes U
+    // (U may be U0: U0 is only read by the first step)
+    CHK(ensure(*p, a, bytes));
+    CHK(ensure(*p, b, bytes));
+    const double *src = U0;
+    for (int k = 0; k < steps; ++k) {
+        double *dst = k == steps - 1 ? (steps == 1 && U == U0 ? (double *)a.p : U)
+                                     : (double *)(k % 2 ? b.p : a.p);
+        HIPCHK(spmm(Ev, m, src, m, dst, m, p->st));
+        src = dst;
+    }
+    if (src != U) HIPCHK(hipMemcpyAsync(U, src, bytes, hipMemcpyDeviceToDevice, p->st));
+    return EXPM_OK;
+}
+
+int expm_power_norms(expm_plan_t p, const expm_csr_cview *H, int K, double *out) {
+    g_err.clear();
+    if (!p || (K > 0 && !out)) return fail(EXPM_EINVAL, "NULL argument");
+    if (K < 0) return fail(EXPM_EINVAL, "K < 0");
+    expm_plan_s &P = *p;
+    DCsr copy, cur;
+    auto free_locals = at_exit([&] {
+        release(P, copy);
+        release(P, cur);
+    });
+    CsrView Hv;
+    CHK(device_view(P, H, copy, &Hv));
+    const int64_t n = H->n;
+    CHK(ensure(P, P.norm2, sizeof(double) * 2));
+    CHK(ensure(P, P.part, sizeof(double) * kParts));
+    auto read_norm = [&](const double *v, int64_t m, double *dst) -> int {
+        HIPCHK(sumsq(v, nullptr, m, (double *)P.part.p, kParts, (double *)P.norm2.p, P.st));
+        HIPCHK(hipMemcpyAsync(P.host, P.norm2.p, sizeof(double), hipMemcpyDeviceToHost, P.st));
+        CHK(sync(P));
+        double s2;
+        memcpy(&s2, P.host, sizeof s2);
+        *dst = sqrt(s2);
+        return EXPM_OK;
+    };
+    if (K == 0) return EXPM_OK;
+    CHK(read_norm(Hv.v, H->nnz, &out[0]));
+    // cur = H^k, k = 1..K (unfiltered products; structural zeros add nothing)
+    CsrView Pk = Hv;
+    int64_t nnzk = H->nnz;
+    for (int k = 2; k <= K; ++k) {
+        int64_t cand;
+        CHK(spgemm(P, Pk, nnzk, Hv, 0.0, 1.0, false, &cand));
+        CHK(ensure_csr(P, cur, n, cand));
+        HIPCHK(hipMemcpyAsync(cur.rp.p, P.crp.p, sizeof(int64_t) * (n + 1),
+                              hipMemcpyDeviceToDevice, P.st));
+        if (cand) {
+            HIPCHK(hipMemcpyAsync(cur.ci.p, P.cci.p, sizeof(int32_t) * cand,
+                                  hipMemcpyDeviceToDevice, P.st));
+            HIPCHK(hipMemcpyAsync(cur.v.p, P.cv.p, sizeof(double) * cand, hipMemcpyDeviceToDevice,
+                                  P.st));
+        }
+        Pk = cur.view();
+        nnzk = cand;
+        CHK(read_norm((const double *)cur.v.p, cand, &out[k - 1]));
+    }
+    return EXPM_OK;
+}
+
+int expm_alpha_hat(double ri, int i, int N, double norm, const double *hk, int K,
+                   int64_t *out) {
+    if (!out || !(ri > 0.0) || (hk && K < 3) || (!hk && !(norm >= 0.0)))
+        return fail(EXPM_EINVAL, "invalid argument");
+    int64_t best = -1;
+    const int m1max = hk ? std::min(170, (K - 1) / 2) : 170;
+    for (int N1 = 0; N1 <= 60; ++N1) {
+        for (int M1 = 1; M1 <= m1max; ++M1) {
+            double h = norm;
+            if (hk) {   // h_{M1, .} of Eq. (4.9), before its 2^-(N+N1-i) scaling
+                h = 0.0;
+                for (int k = M1 + 1; k <= 2 * M1 + 1; ++k) h = std::max(h, pow(hk[k - 1], 1.0 / k));
+            }
+            const double x = ldexp(h, i - N - N1);
+            if (ldexp(plan_r0(M1, x), N1) <= ri) {
+                const int64_t cost = (int64_t)M1 << N1;
+                if (best < 0 || cost < best) best = cost;
+                break;
+            }
+        }
+    }
+    *out = best;
+    return best < 0 ? fail(EXPM_ERANGE, "no (M1, N1) reaches r_i = %g", ri) : EXPM_OK;
+}
+
 void expm_csr_release(expm_plan_t p, expm_csr *E) {
     if (!p || !E) return;
     out_free(*p, E->rowptr);
@@ -1518,6 +1783,7 @@ void expm_free(expm_plan_t p) {
                     &P.ro_d3, &P.ro_q0, &P.ro_q1, &P.ro_cell, &P.ro_cnt, &P.ro_off,
                     &P.ro_pcnt, &P.ro_pw, &P.ro_pofs, &P.ro_gbits};
     for (Buf *b : rbufs) release(P, *b);
+    for (Buf *b : {&P.colsum, &P.amax, &P.bands}) release(P, *b);
     release(P, P.tsT);
     release(P, P.tsG);
     for (TileSet &ts : P.cts) release(P, ts);

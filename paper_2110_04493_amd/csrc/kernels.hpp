@@ -290,4 +290,24 @@ struct PosCsr {
 hipError_t masked_dot(CsrView M, const double *dv, PosCsr A, PosCsr Bt, double div, double *out,
                       hipStream_t st);
 
+// ------------------------------------------------------------- extras.hip
+hipError_t fill_f64(double *p, int64_t m, double x, hipStream_t st);
+// *out = bit pattern of the largest row sum of |a_ij| (rows summed in order).
+hipError_t row_abs_max(CsrView A, unsigned long long *out, hipStream_t st);
+// The FPIM's fixed threshold on a candidate (CSR rows or tiles): the
+// controller c is set to theta = eps * (largest column sum of |v|); colsum
+// holds n doubles of workspace, mx one word.
+hipError_t fpim_theta_rows(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                           double *colsum, unsigned long long *mx, double eps, FilterCtl *c,
+                           hipStream_t st);
+hipError_t fpim_theta_tiles(int64_t n, int64_t ntiles, const int32_t *ccols, const double *ctiles,
+                            double *colsum, unsigned long long *mx, double eps, FilterCtl *c,
+                            hipStream_t st);
+// out[0] = l1, out[1] = l2 of Eq. (3.1) in the caller's ordering (order[]:
+// library row -> caller row, or NULL); both LLONG_MIN for an empty matrix.
+hipError_t band_of(CsrView T, const int32_t *order, long long *out, hipStream_t st);
+// Y = A X (X, Y dense row-major, leading dimensions ldx, ldy).
+hipError_t spmm(CsrView A, int64_t m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                hipStream_t st);
+
 }  // namespace xpm

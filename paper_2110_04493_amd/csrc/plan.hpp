@@ -146,6 +146,11 @@ struct expm_plan_s {
     // default 0.2, where the two paths cost about the same on MI355X at
     // n = 90,000 in natural order)
     double bsr_min_fill = 0.2;
+    // EXPM_FILTER_FIXED_REL: the filter parameter eps of the running forward
+    // (0 otherwise); column sums and a max word for its thresholds; the
+    // bandwidth pairs (l1, l2) of T_0 .. T_N with opts.diagnostics
+    double fpim_eps = 0.0;
+    xpm::host::Buf colsum, amax, bands;
 };
 
 namespace xpm {
@@ -198,6 +203,19 @@ int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int transpose_pos(expm_plan_s &P, const DCsr &A, DCsr &dst);
 int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal);
 int check_view(const expm_csr_cview *H);
+// A fixed threshold already set in the filter controller on the device
+// (theta_fixed argument of filter_and_count).
+constexpr double kThetaOnDevice = -2.0;
+int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
+                     const double *norm2, bool use_fixed, double theta_fixed, bool addI,
+                     FilterCtl *hctl, int64_t *kept);
+int write_filtered(expm_plan_s &P, int64_t n, DCsr &dst, int64_t kept, bool addI,
+                   bool exact_alloc);
+int masked(expm_plan_s &P, CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2,
+           double div, double *out);
+int plan_input(expm_plan_s &P, const expm_csr_cview *Hv, double eps, DCsr &dst,
+               expm_analysis *A);
+int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E);
 void free_adjoint_state(expm_plan_s &P);
 int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill,
                 bool with_c = false);

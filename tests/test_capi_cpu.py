@@ -35,6 +35,7 @@ def test_defaults():
     o = capi.expm_opts_default()
     assert (o.normal, o.filter_mode, o.e_r, o.max_filter_iter, o.keep_checkpoints,
             o.reorder) == (-1, 0, 0.1, 64, 0, -1)
+    assert (o.norm, o.exact_ri, o.diagnostics) == (capi.EXPM_NORM_FRO, 0, 0)
     assert capi.expm_last_error() == ""
 
 
@@ -74,3 +75,17 @@ def test_plan_rejects_invalid_options(field, value):
     with pytest.raises(capi.ExpmError) as e:
         capi.expm_plan(o)
     assert e.value.code == capi.EXPM_EINVAL
+
+
+@pytest.mark.parametrize("nh,eps", [(244.9, 1e-16), (50.0, 1e-12), (3.0, 1e-10)])
+def test_alpha_hat_matches_oracle(nh, eps):
+    """Eq. (4.8) and (4.9) from the library's host helper against the
+    oracle's (which Table 3 row 3 pins)."""
+    M, N = oracle.choose_mn(nh, eps)
+    r0 = oracle.r0(M, nh * 2.0 ** -N)
+    hk = [nh ** (1.0 - 0.02 * k) for k in range(1, 2 * 30 + 2)]   # a decreasing h sequence
+    for i in range(0, N + 1):
+        ri = 2.0 ** i * r0
+        assert capi.expm_alpha_hat(ri, i, N, norm=nh) == oracle.alpha_hat(ri, i, N, norm=nh)
+        assert capi.expm_alpha_hat(ri, i, N, hk=hk) == oracle.alpha_hat(ri, i, N,
+                                                                         power_norms=hk)

@@ -1,0 +1,270 @@
+"""GPU parity of the options and diagnostics beyond the default method:
+the 1-norm for (M, N), the exact error recurrence of Eq. (4.3), the FPIM's
+fixed filter (section 2), the bandwidths of the iterates (Eq. (3.1),
+Table 3), the plan of steps 1-3 before a run, host-memory inputs, the norms
+of the powers of H (section 4.2), and the action E R / time stepping of
+section 5.3 and Eq. (2.2).  Same bar as the forward parity tests."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_04493_amd import workloads as W
+from _helpers import compare, final_theta, run_gpu, run_oracle, to_device
+from test_gpu_forward import check_parity
+from test_gpu_adjoint import gpu_grad
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def grid(side, seed, norm1):
+    L = W.grid_laplacian(side, side, np.random.default_rng(seed))
+    return L.scaled(-norm1 / W.norm1(L))
+
+
+# ------------------------------------------------ norm, error recurrence, FPIM
+
+@pytest.mark.parametrize("name,H,eps", [
+    ("general", W.random_sparse(150, 0.03, 51, kind="general", scale=1.1), 1e-12),
+    ("grid", grid(45, 52, 50.0), 1e-12)], ids=["general", "grid"])
+def test_norm_one(name, H, eps):
+    _, sg, _, so = check_parity(H, eps, norm=1)
+    assert abs(sg["norm_h"] - so["nh"]) <= 1e-14 * so["nh"]
+
+
+def test_exact_error_recurrence():
+    H = grid(40, 53, 30.0)
+    _, sg, _, so = check_parity(H, 1e-12, exact_ri=True)
+    # the same recurrence from an r0 whose ||H|| was summed in another order
+    for a, b in zip(sg["sq_ri"], so["sq_ri"]):
+        assert abs(a - b) <= 1e-13 * b
+
+
+@pytest.mark.parametrize("fill", [-1.0, 0.0, 2.0])
+def test_fpim_fixed_filter(fill):
+    """The FPIM's filter on both product paths (tiles and rows): the
+    thresholds come from column sums taken in another order than the
+    oracle's, so the kept sets may differ only at the threshold."""
+    H = grid(50, 54, 40.0)
+    Eg, sg = run_gpu(H, 1e-12, filter_mode=2, tile_min_fill=fill)
+    Eo, so = run_oracle(H, 1e-12, filter_mode=2)
+    rel, ok, og, oo = compare(Eg, Eo, so["sq_theta"][-1])
+    print(f"[fpim fill={fill}] relF={rel:.2e} only={og},{oo}", flush=True)
+    assert rel <= TOL and ok
+    assert abs(sg["theta0"] - so["theta0"]) <= 1e-12 * so["theta0"]
+    for a, b in zip(sg["sq_theta"], so["sq_theta"]):
+        assert abs(a - b) <= 1e-12 * b
+    for a, b in zip(sg["sq_kept"], so["sq_kept"]):
+        assert abs(a - b) <= 0.002 * b + 2
+
+
+def test_fpim_config1_and_adjoint():
+    """Config 1 (10 tridiag(1,-2,1), n = 1000) under the FPIM, and the
+    adjoint with the FPIM's masks frozen against the oracle's."""
+    H, eps = W.config1()
+    check_parity(H, eps, filter_mode=2)
+    G = W.grid_laplacian(24, 24, np.random.default_rng(55)).scaled(-0.3)
+    dg, _ = gpu_grad(G, 1e-12, density=0.2, filter_mode=2)
+    run = oracle.Run(G.rowptr, G.col, G.val, 1e-12, filter_mode=2, keep=True)
+    res = run.result()
+    rows = np.repeat(np.arange(G.n), np.diff(res.rowptr))
+    do = run.backward(W.loss_weights(rows, res.col, G.n, density=0.2))
+    run.close()
+    assert np.linalg.norm(dg - do) <= TOL * np.linalg.norm(do)
+
+
+def test_batched_refuses_variants():
+    from paper_2110_04493_amd import api, capi
+    plan = api.Plan("cuda", api.Options(filter_mode=2))
+    try:
+        with pytest.raises(capi.ExpmError) as e:
+            plan.expm_batched([to_device(W.tridiag(20, 1.0, -2.0, 1.0))], [1e-12])
+        assert e.value.code == capi.EXPM_ENOTIMPL
+    finally:
+        plan.close()
+
+
+# ------------------------------------------------ bandwidth diagnostics (Table 3)
+
+@pytest.mark.parametrize("reorder", [0, 1])
+def test_band_diagnostics_table3(reorder):
+    """l(T^_i) per squaring, in the caller's ordering whether or not the
+    library reorders internally: equal to the oracle's and to Table 3 row 1
+    (tridiag(1,-2,1), n = 10^4, eps_tol = 1e-16)."""
+    g = json.load(open(os.path.join(GOLD, "tables23.json")))
+    H, eps = W.table2_matrix(g["n"])
+    _, sg = run_gpu(H, eps, diagnostics=True, reorder=reorder)
+    so = run_oracle(H, eps)[1]
+    assert sg["sq_band"] == so["sq_band"]
+    assert sg["sq_band"][1:] == g["table3_lambda_T_hat"]
+
+
+def test_band_diagnostics_grid_reordered():
+    H = grid(70, 56, 30.0)
+    _, sg = run_gpu(H, 1e-12, diagnostics=True, reorder=1)
+    so = run_oracle(H, 1e-12)[1]
+    assert sg["sq_band"] == so["sq_band"]
+    _, s0 = run_gpu(H, 1e-12)
+    assert s0["sq_band"] == [-1] * (s0["N"] + 1)
+
+
+# ------------------------------------------------ plan before the run, host inputs
+
+@pytest.mark.parametrize("norm", [0, 1])
+def test_analyze_matches_oracle_plan(norm):
+    import torch
+    from paper_2110_04493_amd import api
+    H = W.random_sparse(120, 0.04, 57, kind="general", scale=0.9)
+    plan = api.Plan("cuda", api.Options(norm=norm))
+    try:
+        A = plan.analyze(*to_device(H), 1e-12)
+    finally:
+        plan.close()
+    so = run_oracle(H, 1e-12, norm=norm)[1]
+    assert (A["M"], A["N"], A["normal"], A["n"], A["nnz"]) == (so["M"], so["N"], so["normal"],
+                                                                H.n, H.nnz)
+    for k, ko in (("norm_h", "nh"), ("a", "a"), ("h0", "h0"), ("r0", "r0"), ("eg0", "eg0")):
+        assert abs(A[k] - so[ko]) <= 1e-13 * abs(so[ko]), k
+
+
+def test_analyze_keeps_adjoint_state():
+    """expm_analyze between a forward and its backward leaves the backward
+    intact (it works on a scratch copy of its input)."""
+    import torch
+    from paper_2110_04493_amd import api
+    H = grid(20, 58, 10.0)
+    other = W.random_sparse(60, 0.05, 59, kind="general")
+    plan = api.Plan("cuda", api.Options(keep_checkpoints=True))
+    try:
+        rp, ci, v = plan.expm(*to_device(H), 1e-12)
+        plan.analyze(*to_device(other), 1e-10)
+        rows = np.repeat(np.arange(H.n), np.diff(rp.cpu().numpy()))
+        g = W.loss_weights(rows, ci.cpu().numpy(), H.n, density=0.2)
+        dH = plan.backward(torch.from_numpy(g).cuda(), H.nnz).cpu().numpy()
+    finally:
+        plan.close()
+    run = oracle.Run(H.rowptr, H.col, H.val, 1e-12, keep=True)
+    res = run.result()
+    rows = np.repeat(np.arange(H.n), np.diff(res.rowptr))
+    do = run.backward(W.loss_weights(rows, res.col, H.n, density=0.2))
+    run.close()
+    assert np.linalg.norm(dH - do) <= TOL * np.linalg.norm(do)
+
+
+def test_host_inputs():
+    """A view of host memory (on_host = 1) gives the same E as the device
+    input."""
+    import ctypes
+    import torch
+    from paper_2110_04493_amd import api, capi
+    H = grid(30, 60, 20.0)
+    Ed, _ = run_gpu(H, 1e-12)
+    plan = api.Plan("cuda")
+    try:
+        rp, ci, v = (np.ascontiguousarray(H.rowptr), np.ascontiguousarray(H.col),
+                     np.ascontiguousarray(H.val))
+        view = capi.expm_csr_cview(H.n, H.nnz, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 1)
+        E = capi.expm_sparse(plan.handle, view, 1e-12)
+        erp, eci, ev = plan._take(E)
+        torch.cuda.synchronize()
+        Eh = W.Csr(H.n, erp.cpu().numpy(), eci.cpu().numpy(), ev.cpu().numpy())
+    finally:
+        plan.close()
+    assert np.array_equal(Eh.rowptr, Ed.rowptr) and np.array_equal(Eh.col, Ed.col)
+    assert np.array_equal(Eh.val, Ed.val)
+
+
+# ------------------------------------------------ norms of powers (Eq. 4.9)
+
+def test_power_norms():
+    import torch
+    from paper_2110_04493_amd import api
+    H = W.tridiag(2000, 1.0, -2.0, 1.0)
+    A = W.random_sparse(200, 0.02, 61, kind="general", scale=0.5)
+    plan = api.Plan("cuda")
+    try:
+        g1 = plan.power_norms(*to_device(H), 41)
+        g2 = plan.power_norms(*to_device(A), 12)
+    finally:
+        plan.close()
+    o1 = oracle.power_norms((H.rowptr, H.col, H.val), 41)
+    o2 = oracle.power_norms((A.rowptr, A.col, A.val), 12)
+    # k products deep, each entry a sum with cancellation (alternating
+    # signs in the powers of tridiag(1,-2,1)) rounded in another order and
+    # with fused multiply-adds on the GPU: about k u of drift at power k
+    assert np.max(np.abs(np.array(g1) / o1 - 1)) <= 41 * 2 ** -53 * 1000
+    assert np.max(np.abs(np.array(g2) / o2 - 1)) <= 1e-13
+
+
+# ------------------------------------------------ E R and time stepping
+
+def gpu_spmm(E, X):
+    import torch
+    from paper_2110_04493_amd import api
+    plan = api.Plan("cuda")
+    try:
+        Y = plan.spmm(*to_device(E), torch.from_numpy(X).cuda())
+        torch.cuda.synchronize()
+        return Y.cpu().numpy()
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("m", [1, 37, 64, 130])
+def test_spmm_kernel(m):
+    """The product kernel on identical inputs: ragged column chunks, rows
+    of every length up to several hundred, empty rows, n not a multiple of
+    the four rows of a workgroup."""
+    rng = np.random.default_rng(62 + m)
+    A = W.random_sparse(1003, 0.01, 63, kind="general")
+    A.val[A.rowptr[5]:A.rowptr[6]] = 0.0
+    r = np.concatenate([A.rows(), np.full(700, 17)])
+    c = np.concatenate([A.col.astype(np.int64), rng.integers(0, 1003, 700)])
+    v = np.concatenate([A.val, rng.standard_normal(700)])
+    A = W.csr_from_coo(1003, r, c, v)
+    keep = A.rows() != 40
+    A = W.csr_from_coo(1003, A.rows()[keep], A.col[keep], A.val[keep])
+    X = rng.standard_normal((1003, m))
+    Y = gpu_spmm(A, X)
+    Yo = oracle.spmm((A.rowptr, A.col, A.val), X)
+    assert np.linalg.norm(Y - Yo) <= 1e-14 * np.linalg.norm(Yo)
+
+
+def test_action_against_oracle():
+    """Section 5.3's check E R, R = rand(n, m): the GPU's E times R against
+    the oracle's E times R."""
+    H = grid(40, 64, 30.0)
+    Eg, _ = run_gpu(H, 1e-12)
+    Eo, _ = run_oracle(H, 1e-12)
+    R = np.random.default_rng(65).random((H.n, 100))
+    Y = gpu_spmm(Eg, R)
+    Yo = oracle.spmm((Eo.rowptr, Eo.col, Eo.val), R)
+    assert np.linalg.norm(Y - Yo) <= TOL * np.linalg.norm(Yo)
+
+
+def test_propagate():
+    """Eq. (2.2): U_k = E^k U_0 by repeated products, in place and not."""
+    import torch
+    from paper_2110_04493_amd import api
+    H = grid(25, 66, 5.0)
+    Eo, _ = run_oracle(H, 1e-12)
+    U0 = np.random.default_rng(67).standard_normal((H.n, 3))
+    ref = U0
+    for _ in range(5):
+        ref = oracle.spmm((Eo.rowptr, Eo.col, Eo.val), ref)
+    plan = api.Plan("cuda")
+    try:
+        dev = to_device(Eo)
+        U = plan.propagate(*dev, torch.from_numpy(U0).cuda(), 5).cpu().numpy()
+        U1 = plan.propagate(*dev, torch.from_numpy(U0).cuda(), 1).cpu().numpy()
+        U0k = plan.propagate(*dev, torch.from_numpy(U0).cuda(), 0).cpu().numpy()
+    finally:
+        plan.close()
+    assert np.linalg.norm(U - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert np.linalg.norm(U1 - oracle.spmm((Eo.rowptr, Eo.col, Eo.val), U0)) <= \
+        1e-13 * np.linalg.norm(U1)
+    assert np.array_equal(U0k, U0)
