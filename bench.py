@@ -15,8 +15,12 @@ each call), and its algorithmic flops per launch come from untimed passes
 after them, on a plan of their own, with the full profile (profile mode 1,
 which counts the partial products of every step and waits for the device
 after each step; the per-step table and phase times come from the second of
-those passes).  `cpu_baseline`
-times the CPU oracle on a bounded sample of the same workload family.
+those passes).  The bound of each roofline object is the roof that the
+kernel's arithmetic intensity (algorithmic flops per algorithmic byte) meets
+first.  `adjoint` is the same for the adjoint tile step.  `other_workloads`
+holds short measurements of the differentiation, large-grid, batched and
+E R configurations.  `cpu_baseline` times the CPU oracle, forward +
+adjoint, on the benchmark's own workload.
 """
 from __future__ import annotations
 
@@ -44,7 +48,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--side", type=int, default=300, help="grid side (300 -> n = 90,000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-side", type=int, default=150)
+    ap.add_argument("--cpu-sample-side", type=int, default=0,
+                    help="time the oracle on a smaller grid of the same family instead of the "
+                         "benchmark's own workload (0: the full workload, the default)")
+    ap.add_argument("--cpu-runs", type=int, default=1,
+                    help="oracle runs for the CPU baseline (the median is reported)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the lines of the other workloads (differentiation, large grid, "
+                         "batched, E R) that follow the headline line")
     ap.add_argument("--forward-only", action="store_true")
     ap.add_argument("--workload", choices=["grid", "batched", "grad"], default="grid",
                     help="grid: the headline 2D heat-conduction workload (default); batched: "
@@ -112,6 +123,44 @@ def copy_calibration(nbytes: int):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}), flush=True)
+
+
+def kernel_roofline(flops: float, nbytes: float, ms: float) -> dict:
+    """Roofline of one launch from its algorithmic flops and bytes: the
+    bound is the roof its arithmetic intensity (flops per algorithmic byte)
+    meets first, the achieved rate is in that roof's unit, and frac is
+    achieved / peak, i.e. the launch's time at that roof over its measured
+    time."""
+    intensity = flops / nbytes if nbytes else float("inf")
+    if intensity >= RIDGE:
+        ach = flops / (ms * 1e9)
+        out = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4)}
+    else:
+        ach = nbytes / (ms * 1e6)
+        out = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+               "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4)}
+    out["flop_per_byte"] = round(intensity, 2)
+    return out
+
+
+def adjoint_roofline(tl: dict, pstats: dict, steps: int) -> dict:
+    """The adjoint tile step (its two kernels under one event pair per step)
+    against its roofline: launch times from the timed steps; algorithmic
+    flops and bytes per launch from the profiled pass (2 per partial
+    product of G T^T and T^T G landing in the mask plus 2 per mask entry;
+    G and T read once, the masked output written once)."""
+    if not tl["adj_launches"] or not pstats.get("adj_tile_launches"):
+        return {"kernel": "k_bsr_adjoint", "launches": tl["adj_launches"]}
+    avg_ms = tl["adj_ms"] / tl["adj_launches"]
+    fl = pstats["adj_tile_flops"] / pstats["adj_tile_launches"]
+    by = pstats["adj_tile_bytes"] / pstats["adj_tile_launches"]
+    out = kernel_roofline(fl, by, avg_ms)
+    out.update({"kernel": "k_bsr_adjoint", "launches": tl["adj_launches"],
+                "avg_launch_ms": round(avg_ms, 4), "ms_per_step": round(tl["adj_ms"] / steps, 3),
+                "algorithmic_flop_per_launch": round(fl),
+                "algorithmic_bytes_per_launch": round(by)})
+    return out
 
 
 def numeric_roofline(stats: dict, n: int):
@@ -223,12 +272,12 @@ def main():
                   f"{tl['launches'] / args.steps}", file=sys.stderr)
         avg_ms = tl["ms"] / tl["launches"]
         fl_launch = pstats["tile_flops"] / pstats["tile_launches"]
-        ach = fl_launch / (avg_ms * 1e9)
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
-                "traffic": measured_traffic(fl_launch), "kernel": "k_bsr_numeric_panel",
-                "launches": tl["launches"], "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_flop_per_launch": round(fl_launch)}
+        by_launch = pstats["tile_bytes"] / pstats["tile_launches"]
+        roof = kernel_roofline(fl_launch, by_launch, avg_ms)
+        roof.update({"traffic": measured_traffic(fl_launch), "kernel": "k_bsr_numeric_panel",
+                     "launches": tl["launches"], "avg_launch_ms": round(avg_ms, 4),
+                     "algorithmic_flop_per_launch": round(fl_launch),
+                     "algorithmic_bytes_per_launch": round(by_launch)})
     else:
         bound = "alu" if fl / by > RIDGE else "hbm"
         if bound == "alu":
@@ -254,8 +303,7 @@ def main():
         "forward_ms": round(float(np.median(fwd_ms)), 3),
         "adjoint_ms": round(float(np.median(bwd_ms)), 3),
         "roofline": roof,
-        "adjoint_tile_kernel": {"kernel": "k_bsr_adjoint", "launches": tl["adj_launches"],
-                                "ms": round(tl["adj_ms"] / max(args.steps, 1), 3)},
+        "adjoint": adjoint_roofline(tl, pstats, args.steps),
         "squaring_spgemm": {"kernel": "numeric pass (k_numeric rows / k_bsr_numeric tiles)",
                             "source": "untimed pass with per-step phase timers",
                             "ms": round(tnum, 3),
@@ -271,6 +319,8 @@ def main():
                      "filter": round(sum(pstats["t_filter_ms"]), 3),
                      "taylor": round(pstats["t_taylor_ms"], 3)},
     }
+    if not args.no_extras:
+        out["other_workloads"] = other_workloads(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, n)
     print(json.dumps(out), flush=True)
@@ -361,28 +411,182 @@ def bench_grad(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, n_full):
-    """The oracle on a bounded sample: the same workload family on a
-    side x side grid (default 150 -> n = 22,500), forward + adjoint, scaled
-    linearly in the number of rows to the benchmark's n."""
+    """The oracle, as it stands, on the host cores: forward + adjoint of the
+    same workload (the full 300 x 300 grid by default; --cpu-sample-side
+    picks a smaller grid of the same family, reported as measured, not
+    scaled), the median of --cpu-runs runs, wall time of the oracle calls
+    only (input generation and the loss weights excluded)."""
     import oracle
     from paper_2110_04493_amd import workloads as W
-    H, eps = W.config2(args.cpu_sample_side)
-    t0 = time.perf_counter()
-    run = oracle.Run(H.rowptr, H.col, H.val, eps, keep=not args.forward_only)
-    res = run.result()
-    if not args.forward_only:
-        rows = np.repeat(np.arange(H.n), np.diff(res.rowptr))
-        run.backward(W.loss_weights(rows, res.col, H.n, density=0.02))
-    dt = time.perf_counter() - t0
-    run.close()
-    scale = n_full / H.n
-    return {"value": round(dt * scale, 3), "unit": "s", "cores": oracle.threads(),
+    side = args.cpu_sample_side or args.side
+    H, eps = W.config2(side)
+    times, fwd = [], []
+    for r in range(max(args.cpu_runs, 1)):
+        print(f"cpu_baseline: oracle run {r + 1} on the {side}x{side} grid", file=sys.stderr,
+              flush=True)
+        t0 = time.perf_counter()
+        run = oracle.Run(H.rowptr, H.col, H.val, eps, keep=not args.forward_only)
+        res = run.result()
+        t1 = time.perf_counter()
+        print(f"cpu_baseline: forward {t1 - t0:.1f} s", file=sys.stderr, flush=True)
+        tb = 0.0
+        if not args.forward_only:
+            rows = np.repeat(np.arange(H.n), np.diff(res.rowptr))
+            g = W.loss_weights(rows, res.col, H.n, density=0.02)
+            t2 = time.perf_counter()
+            run.backward(g)
+            tb = time.perf_counter() - t2
+            print(f"cpu_baseline: adjoint {tb:.1f} s", file=sys.stderr, flush=True)
+        run.close()
+        times.append(t1 - t0 + tb)
+        fwd.append(t1 - t0)
+    full = H.n == n_full
+    return {"value": round(float(np.median(times)), 3), "unit": "s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"oracle forward{'' if args.forward_only else ' + adjoint'} on the "
-                      f"{args.cpu_sample_side}x{args.cpu_sample_side} grid of the same family "
-                      f"(n={H.n}, M={res.stats['M']}, N={res.stats['N']}) took {dt:.2f} s; "
-                      f"scaled x{scale:.1f} (linear in rows) to n={n_full}"}
+            "sample": (f"oracle forward{'' if args.forward_only else ' + adjoint'} on "
+                       + ("the benchmark's own workload" if full else
+                          f"the {side}x{side} grid of the same family (n={H.n}; not scaled)")
+                       + f", M={res.stats['M']}, N={res.stats['N']}, median of {len(times)} "
+                       f"run(s), forward {np.median(fwd):.2f} s"),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def other_workloads(args) -> dict:
+    """Short measurements of the other configurations, after the headline:
+    the differentiation workload (200 x 200 grid, forward + adjoint), the
+    action E R of the headline E with R = rand(n, 1000) (section 5.3), the
+    large unit grid (1448 x 1448, one forward on a fresh plan: time, nnz(E),
+    peak device memory) and a batch of uneven instances against a
+    per-matrix loop."""
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    out = {}
+    print("other workloads: differentiation", file=sys.stderr, flush=True)
+    out["differentiation"] = grad_numbers(3, 5)
+    print("other workloads: action E R", file=sys.stderr, flush=True)
+    out["action"] = action_numbers(args.side, 1000)
+    print("other workloads: large grid", file=sys.stderr, flush=True)
+    out["large_grid"] = large_grid_numbers()
+    print("other workloads: batched", file=sys.stderr, flush=True)
+    out["batched"] = batched_numbers(64, 500, 2000, 1, 3)
+    return out
+
+
+def grad_numbers(warmup: int, steps: int) -> dict:
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    H, eps = W.config5(200)
+    crow, col, val = (torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val))
+    plan = api.Plan("cuda", api.Options(keep_checkpoints=True))
+    rp, ci, v = plan.expm(crow, col, val, eps)
+    rows = np.repeat(np.arange(H.n), np.diff(rp.cpu().numpy()))
+    dE = torch.from_numpy(W.loss_weights(rows, ci.cpu().numpy(), H.n, density=0.02)).cuda()
+    tf, tfb = [], []
+    for it in range(warmup + steps):
+        t1, _ = _sync_time(lambda: plan.expm(crow, col, val, eps))
+        t2, _ = _sync_time(lambda: plan.backward(dE, val.numel()))
+        if it >= warmup:
+            tf.append(t1)
+            tfb.append(t1 + t2)
+    st = plan.stats()
+    plan.close()
+    return {"workload": "200x200 grid (n=40000), lognormal(0,0.5), H=-5L/||L||_1, eps 1e-12, "
+                        "loss sum(G.*E), G 2% N(0,1)",
+            "fwd_adjoint_s": round(float(np.median(tfb)), 5),
+            "forward_s": round(float(np.median(tf)), 5), "M": st["M"], "N": st["N"],
+            "nnz_e": int(st["nnz_e"]), "steps": steps}
+
+
+def action_numbers(side: int, m: int) -> dict:
+    """Y = E R for the headline workload's E and R = rand(n, m): kernel
+    time from HIP events on the product's stream; algorithmic flops 2 nnz(E) m,
+    algorithmic bytes 12 nnz(E) + 8 (n + 1) + 16 n m (E read once, R read
+    once, Y written once)."""
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    H, eps = W.config2(side)
+    dev = [torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)]
+    plan = api.Plan("cuda")
+    rp, ci, v = plan.expm(*dev, eps)
+    R = torch.rand((H.n, m), dtype=torch.float64, device="cuda")
+    Y = plan.spmm(rp, ci, v, R)   # warmup
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    ms = []
+    for _ in range(reps):
+        with torch.cuda.stream(plan.stream):
+            ev0.record(plan.stream)
+            Y = plan.spmm(rp, ci, v, R)
+            ev1.record(plan.stream)
+        ev1.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    nnz = int(v.numel())
+    plan.close()
+    t = float(np.median(ms))
+    fl = 2.0 * nnz * m
+    by = 12.0 * nnz + 8.0 * (H.n + 1) + 16.0 * H.n * m
+    roof = kernel_roofline(fl, by, t)
+    roof.update({"kernel": "k_spmm", "ms": round(t, 3), "algorithmic_flop": fl,
+                 "algorithmic_bytes": by})
+    return {"workload": f"E of the {side}x{side} grid (nnz {nnz}) times rand(n, {m})",
+            "roofline": roof}
+
+
+def large_grid_numbers() -> dict:
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    H, eps = W.config3(1448)
+    dev = [torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)]
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    plan = api.Plan("cuda")
+    t, (rp, ci, v) = _sync_time(lambda: plan.expm(*dev, eps))
+    st = plan.stats()
+    nnz = int(v.numel())
+    del rp, ci, v
+    plan.close()
+    return {"workload": "1448x1448 unit grid (n=2096704), H=-0.5L, eps 1e-10, one forward on a "
+                        "fresh plan (allocation included)",
+            "forward_s": round(t, 4), "M": st["M"], "N": st["N"], "nnz_e": nnz,
+            "library_workspace_peak_gib": round(st["peak_workspace_bytes"] / 2 ** 30, 2)}
+
+
+def batched_numbers(count: int, nmin: int, nmax: int, warmup: int, steps: int) -> dict:
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    inst = [W.config4_instance(j, nmin=nmin, nmax=nmax) for j in range(count)]
+    dev = [tuple(torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)) for H, _ in inst]
+    eps = [e for _, e in inst]
+    plan = api.Plan("cuda", api.Options())
+    tb, tl = [], []
+    for it in range(warmup + steps):
+        t_b, outs = _sync_time(lambda: plan.expm_batched(dev, eps))
+        del outs
+        t_l, outs = _sync_time(lambda: [plan.expm(*d, e) for d, e in zip(dev, eps)])
+        del outs
+        if it >= warmup:
+            tb.append(t_b)
+            tl.append(t_l)
+    plan.close()
+    return {"workload": f"{count} instances of the batched family, n in [{nmin}, {nmax}] "
+                        "(half unit grids, tau in [1, 20]; half random adjacency, beta in "
+                        "[0.1, 1]), eps 1e-12",
+            "batched_s": round(float(np.median(tb)), 5),
+            "loop_s": round(float(np.median(tl)), 5),
+            "speedup_vs_loop": round(float(np.median(tl)) / float(np.median(tb)), 3)}
 
 
 if __name__ == "__main__":
