@@ -1631,6 +1631,33 @@ static int device_view(expm_plan_s &P, const expm_csr_cview *A, DCsr &copy, CsrV
     return EXPM_OK;
 }
 
+// Y = A X for a block of m columns: on A's 16 x 16 tiles (matrix cores) when
+// its stored entries fill at least kSpmmMinFill of its tiles, else from the
+// CSR rows.  *ts receives the tiles when they are built (so that repeated
+// products reuse them); tiles_ready says they already hold A's.
+constexpr double kSpmmMinFill = 0.15;
+
+static int spmm_any(expm_plan_s &P, CsrView Av, int64_t nnz, int64_t m, const double *X,
+                    int64_t ldx, double *Y, int64_t ldy, TileSet &ts, int *use_tiles) {
+    if (*use_tiles < 0) {
+        *use_tiles = 0;
+        if (Av.n > 0 && nnz > 0 && m > 0 && tiles_allowed(P, Av.n)) {
+            double fill = 0.0;
+            CHK(bsr_pattern(P, Av, nnz, ts, &fill));
+            if (fill >= kSpmmMinFill && ts.ntiles < INT32_MAX) {
+                CHK(bsr_tiles(P, Av, ts));
+                *use_tiles = 1;
+            }
+        }
+    }
+    if (*use_tiles)
+        HIPCHK(spmm_tiles(Av.n, ts.nb, (const int64_t *)ts.tb.p, (const int32_t *)ts.cols.p,
+                          (const double *)ts.tA.p, m, X, ldx, Y, ldy, P.st));
+    else
+        HIPCHK(spmm(Av, m, X, ldx, Y, ldy, P.st));
+    return EXPM_OK;
+}
+
 int expm_spmm(expm_plan_t p, const expm_csr_cview *A, int64_t m, const double *X, int64_t ldx,
               double *Y, int64_t ldy) {
     g_err.clear();
@@ -1638,11 +1665,15 @@ int expm_spmm(expm_plan_t p, const expm_csr_cview *A, int64_t m, const double *X
     if (m < 0 || ldx < m || ldy < m) return fail(EXPM_EINVAL, "invalid block shape");
     if (m > 0 && A && A->n > 0 && (!X || !Y)) return fail(EXPM_EINVAL, "X or Y is NULL");
     DCsr copy;
-    auto free_copy = at_exit([&] { release(*p, copy); });
+    TileSet ts;
+    auto free_locals = at_exit([&] {
+        release(*p, copy);
+        release(*p, ts);
+    });
     CsrView Av;
     CHK(device_view(*p, A, copy, &Av));
-    HIPCHK(spmm(Av, m, X, ldx, Y, ldy, p->st));
-    return EXPM_OK;
+    int use_tiles = -1;
+    return spmm_any(*p, Av, A->nnz, m, X, ldx, Y, ldy, ts, &use_tiles);
 }
 
 int expm_propagate(expm_plan_t p, const expm_csr_cview *E, int64_t m, const double *U0,
@@ -1656,10 +1687,13 @@ int expm_propagate(expm_plan_t p, const expm_csr_cview *E, int64_t m, const doub
     if (!U0 || !U) return fail(EXPM_EINVAL, "U0 or U is NULL");
     DCsr copy;
     Buf a, b;
+    TileSet ts;
+    int use_tiles = -1;
     auto free_locals = at_exit([&] {
         release(*p, copy);
         release(*p, a);
         release(*p, b);
+        release(*p, ts);
     });
     CsrView Ev;
     CHK(device_view(*p, E, copy, &Ev));
@@ -1676,7 +1710,7 @@ int expm_propagate(expm_plan_t p, const expm_csr_cview *E, int64_t m, const doub
     for (int k = 0; k < steps; ++k) {
         double *dst = k == steps - 1 ? (steps == 1 && U == U0 ? (double *)a.p : U)
                                      : (double *)(k % 2 ? b.p : a.p);
-        HIPCHK(spmm(Ev, m, src, m, dst, m, p->st));
+        CHK(spmm_any(*p, Ev, E->nnz, m, src, m, dst, m, ts, &use_tiles));
         src = dst;
     }
     if (src != U) HIPCHK(hipMemcpyAsync(U, src, bytes, hipMemcpyDeviceToDevice, p->st));

@@ -225,6 +225,88 @@ __global__ __launch_bounds__(256) void k_spmm(CsrView A, int64_t m, const double
     if (in) Y[i * ldy + c] = acc;
 }
 
+// Y = A X with A held as 16 x 16 tiles (the tile pattern of the squaring:
+// tb block-row tile bases, tcols block columns, tA tiles in the A operand
+// layout) on the FP64 matrix cores.  One wave per (block row I, 64 columns of
+// X): four 16 x 16 output tiles, each the sum over A's tiles (I, K) of
+// A_IK X_K, X_K the 16 rows of X from 16 K on (rows past n read as 0).  The
+// next tile's operands load while the current tile's 16 instructions issue.
+// Lane l holds X(16 K + 4 s + l / 16, c0 + 16 u + l % 16) as the B operand
+// of slice s for output tile u (16 contiguous lanes read 128 contiguous
+// bytes of one row of X).  The four waves of a workgroup take four
+// consecutive block rows and the same columns, which read mostly the same
+// rows of X.
+__global__ __launch_bounds__(256) void k_spmm_tiles(int64_t n, int64_t nb, const int64_t *tb,
+                                                    const int32_t *tcols,
+                                                    const double *__restrict__ tA, int64_t m,
+                                                    const double *__restrict__ X, int64_t ldx,
+                                                    double *__restrict__ Y, int64_t ldy,
+                                                    int64_t ngroups) {
+    const int lane = lane_id();
+    const int64_t rows4 = (nb + 3) / 4;
+    const int64_t g = (int64_t)blockIdx.x / rows4;
+    const int64_t I = ((int64_t)blockIdx.x % rows4) * 4 + threadIdx.x / kWave;
+    if (I >= nb || g >= ngroups) return;
+    const int64_t c0 = g * 64 + (lane & 15);
+    const int rsub = lane >> 4;
+    d4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int64_t t, d4 &a, d4 (&b)[4]) {
+        a = *(const d4 *)(tA + t * kTileElems + 4 * lane);
+        const int64_t K = tcols[t];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t r = 16 * K + 4 * s + rsub;
+            const bool rin = r < n;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t c = c0 + 16 * u;
+                b[u][s] = rin && c < m ? X[r * ldx + c] : 0.0;
+            }
+        }
+    };
+    const int64_t t0 = tb[I], t1 = tb[I + 1];
+    if (t0 < t1) {
+        d4 a, b[4];
+        load(t0, a, b);
+        for (int64_t t = t0; t < t1; ++t) {
+            d4 a2 = a, b2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b2[u] = b[u];
+            if (t + 1 < t1) load(t + 1, a2, b2);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = mfma16(a, b[u], acc[u]);
+            a = a2;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b[u] = b2[u];
+        }
+    }
+    // result (i, j) of tile u sits in register i / 4 of lane j + 16 (i mod 4)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = 16 * I + 4 * r + rsub;
+        if (i >= n) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + 16 * u;
+            if (c < m) Y[i * ldy + c] = acc[u][r];
+        }
+    }
+}
+
+hipError_t spmm_tiles(int64_t n, int64_t nb, const int64_t *tb, const int32_t *tcols,
+                      const double *tA, int64_t m, const double *X, int64_t ldx, double *Y,
+                      int64_t ldy, hipStream_t st) {
+    if (n == 0 || m == 0) return hipSuccess;
+    const int64_t ngroups = (m + 63) / 64, rows4 = (nb + 3) / 4;
+    const int64_t blocks = ngroups * rows4;
+    if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_spmm_tiles, dim3((unsigned)blocks), dim3(256), 0, st, n, nb, tb, tcols,
+                       tA, m, X, ldx, Y, ldy, ngroups);
+    return hipGetLastError();
+}
+
 hipError_t spmm(CsrView A, int64_t m, const double *X, int64_t ldx, double *Y, int64_t ldy,
                 hipStream_t st) {
     if (A.n == 0 || m == 0) return hipSuccess;

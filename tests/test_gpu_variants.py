@@ -234,6 +234,23 @@ def test_spmm_kernel(m):
     assert np.linalg.norm(Y - Yo) <= 1e-14 * np.linalg.norm(Yo)
 
 
+@pytest.mark.parametrize("m", [1, 37, 64, 130])
+def test_spmm_tile_kernel(m):
+    """The matrix-core product on 16 x 16 tiles (taken when the entries fill
+    enough of their tiles): a dense band of half-width 20 with a few empty
+    rows, n = 1003 (a partial last block row), ragged column chunks."""
+    rng = np.random.default_rng(70 + m)
+    n = 1003
+    i = np.repeat(np.arange(n), 41)
+    j = i + np.tile(np.arange(-20, 21), n)
+    ok = (j >= 0) & (j < n) & (i % 97 != 5)
+    A = W.csr_from_coo(n, i[ok], j[ok], rng.standard_normal(int(ok.sum())))
+    X = rng.standard_normal((n, m))
+    Y = gpu_spmm(A, X)
+    Yo = oracle.spmm((A.rowptr, A.col, A.val), X)
+    assert np.linalg.norm(Y - Yo) <= 1e-14 * np.linalg.norm(Yo)
+
+
 def test_action_against_oracle():
     """Section 5.3's check E R, R = rand(n, m): the GPU's E times R against
     the oracle's E times R."""
