@@ -129,7 +129,13 @@ typedef struct {
                                 squarings are fuller.  Results are those of
                                 the unpermuted method up to rounding order.
                                 -1 (default) on for n >= 4096 when the tile
-                                product can run, 0 off, 1 on                  */
+                                product can run, 0 off, 1 on; where the
+                                graph has no 2D structure (path-like, or
+                                small diameter) the level ordering below is
+                                taken instead when it narrows the band.
+                                2: the level ordering (Cuthill-McKee-like:
+                                breadth-first levels from a far node, then
+                                the distance from a second far node)         */
     double tile_min_fill;    /* a squaring step (and its adjoint) runs on 16x16
                                 tiles when T's stored entries fill at least
                                 this fraction of its tiles: < 0 (default)
@@ -203,6 +209,8 @@ typedef struct {
        2 per mask entry; 12 per stored entry of G and of T read once, 8 per
        mask entry written */
     double tile_bytes, adj_tile_flops, adj_tile_bytes;
+    /* the locality ordering applied: 0 none, 1 strips, 2 levels */
+    int ordering;
 } expm_stats;
 
 typedef struct expm_plan_s *expm_plan_t;

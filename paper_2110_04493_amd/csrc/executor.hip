@@ -916,8 +916,10 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     // Locality reordering: H' = P H P^T replaces H; E is permuted back below.
     {
         const int ro = P.opts.reorder;
-        if (ro == 1 || (ro < 0 && n >= 4096 && tiles_allowed(P, n)))
-            CHK(compute_reorder(P, P.H0.view(), &P.perm_active));
+        P.ordering = 0;
+        if (ro >= 1 || (ro < 0 && n >= 4096 && tiles_allowed(P, n)))
+            CHK(compute_reorder(P, P.H0.view(), nnz, ro == 2 ? 2 : 1, &P.perm_active));
+        S.ordering = P.perm_active ? P.ordering : 0;
         if (P.perm_active) {
             CHK(ensure_csr(P, P.Hp, n, nnz));
             int64_t *hm = nullptr;
@@ -1422,7 +1424,7 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1)
         return fail(EXPM_EINVAL, "invalid option value");
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
-        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 1 || o.profile < 0 ||
+        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 2 || o.profile < 0 ||
         o.profile > 2 ||
         !(o.tile_min_fill == o.tile_min_fill))
         return fail(EXPM_EINVAL, "invalid option value");

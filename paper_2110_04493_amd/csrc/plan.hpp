@@ -151,6 +151,7 @@ struct expm_plan_s {
     // bandwidth pairs (l1, l2) of T_0 .. T_N with opts.diagnostics
     double fpim_eps = 0.0;
     xpm::host::Buf colsum, amax, bands;
+    int ordering = 0;   // the ordering applied by the running call: 0 none, 1 strips, 2 levels
 };
 
 namespace xpm {
@@ -250,7 +251,7 @@ void ktimer_collect(expm_plan_s &P);
 void collect_forward(expm_plan_s &P);
 void ktimer_collect_set(expm_plan_s &P, std::vector<hipEvent_t> &ev, std::vector<char> &kind,
                        size_t &used);
-int compute_reorder(expm_plan_s &P, CsrView G, bool *active);
+int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *active);
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
                 const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap);
 int scatter_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst);

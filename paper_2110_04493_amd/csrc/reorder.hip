@@ -26,6 +26,7 @@ namespace xpm {
 
 constexpr int kBfsThreads = 1024;
 constexpr int kCellMax = 256;      // largest cell the ordering accepts
+constexpr int kLevelMax = 4096;    // largest level the level ordering accepts
 constexpr int kStrip = 5;          // d1 values per strip
 constexpr int kPermWaves = 4;        // output rows (waves) per workgroup
 constexpr int kPermLdsWords = 1024;  // bit-map words per wave in LDS
@@ -256,6 +257,15 @@ __global__ void k_max_i64(const int64_t *a, int64_t n, int32_t *out) {
     }
 }
 
+// The level ordering: cell = breadth-first level d1 (distance from u1).
+__global__ void k_level_count(int64_t n, const int32_t *d1, int64_t *cell, int64_t *cnt) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t c = d1[v] < 0 ? 0 : d1[v];   // unreached nodes (other components) first
+    cell[v] = c;
+    atomicAdd((unsigned long long *)&cnt[c], 1ull);
+}
+
 __global__ void k_cell_scatter(int64_t n, const int64_t *cell, const int64_t *coff,
                                int64_t *cfill, int32_t *tmp) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,8 +275,8 @@ __global__ void k_cell_scatter(int64_t n, const int64_t *cell, const int64_t *co
     tmp[pos] = (int32_t)v;
 }
 
-// One wave per cell: members by ascending d1, then node index (rank by
-// counting).
+// One wave per cell: members by ascending key (d1 for the strips, d3 for the
+// levels), then node index (rank by counting).
 __global__ void k_cell_sort(int64_t ncell, const int64_t *coff, const int32_t *tmp,
                             const int32_t *d1, int32_t *order, int32_t *newidx) {
     const int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -419,10 +429,64 @@ static unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 namespace host {
 
+// The level ordering of G (a Cuthill-McKee-like order): nodes by their
+// breadth-first level from the far node u1, within a level by the distance
+// from u3 and then index.  An edge joins nodes of one level or of adjacent
+// levels, so the bandwidth l of the reordered matrix is at most four times
+// the largest level.  With `force` unset it is taken only when that bound
+// is below the bandwidth of the given order.
+static int level_order(expm_plan_s &P, CsrView G, int64_t nnz, int64_t maxd1, bool force,
+                       bool *active) {
+    hipStream_t st = P.st;
+    const int64_t n = G.n, ncell = maxd1 + 1;
+    int32_t *rb = (int32_t *)P.ro_rb.p, *d1 = (int32_t *)P.ro_d1.p, *d3 = (int32_t *)P.ro_d3.p,
+            *q0 = (int32_t *)P.ro_q0.p;
+    CHK(ensure(P, P.ro_cell, sizeof(int64_t) * n));
+    CHK(ensure(P, P.ro_cnt, sizeof(int64_t) * (ncell + 1)));
+    CHK(ensure(P, P.ro_off, sizeof(int64_t) * (ncell + 1)));
+    CHK(ensure(P, P.bands, sizeof(long long) * 2));
+    int64_t *cell = (int64_t *)P.ro_cell.p, *cnt = (int64_t *)P.ro_cnt.p,
+            *off = (int64_t *)P.ro_off.p;
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (ncell + 1), st));
+    HIPCHK(hipMemsetAsync(rb + 10, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_level_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d1, cell, cnt);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_max_i64, dim3(blocks_for(ncell, 256) < 1024 ? blocks_for(ncell, 256)
+                                                                       : 1024),
+                       dim3(256), 0, st, cnt, ncell, rb + 10);
+    HIPCHK(hipGetLastError());
+    HIPCHK(band_of(G, nullptr, (long long *)P.bands.p, st));
+    CHK(scan(P, cnt, off, ncell));
+    int32_t *hb = (int32_t *)P.host;
+    HIPCHK(hipMemcpyAsync(hb + 10, rb + 10, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hb + 12, P.bands.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    const int64_t maxlevel = hb[10];
+    long long lb[2];
+    memcpy(lb, hb + 12, sizeof lb);
+    const long long band = lb[0] == LLONG_MIN ? 0 : lb[0] + lb[1];
+    (void)nnz;
+    if (maxlevel > kLevelMax) return EXPM_OK;               // sorting a level would not pay
+    if (!force && 4 * maxlevel >= band) return EXPM_OK;    // the given order is as narrow
+    CHK(ensure(P, P.order, sizeof(int32_t) * n));
+    CHK(ensure(P, P.newidx, sizeof(int32_t) * n));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (ncell + 1), st));
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, cell, off,
+                       cnt, q0);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(ncell, 4)), dim3(256), 0, st, ncell, off,
+                       q0, d3, (int32_t *)P.order.p, (int32_t *)P.newidx.p);
+    HIPCHK(hipGetLastError());
+    *active = true;
+    P.ordering = 2;
+    return EXPM_OK;
+}
+
 // Computes the cell ordering of G's pattern into P.order (new -> old) and
-// P.newidx (old -> new); *active = false when the graph has no usable 2D
-// structure (then nothing is permuted).
-int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
+// P.newidx (old -> new); *active = false when no ordering applies (then
+// nothing is permuted).  mode 1: the strips, else the level ordering when
+// it narrows the band; mode 2: the level ordering.
+int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *active) {
     hipStream_t st = P.st;
     const int64_t n = G.n;
     *active = false;
@@ -457,8 +521,10 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
     HIPCHK(hipMemcpyAsync(hb, rb, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, st));
     CHK(sync(P));
     const int64_t maxd1 = hb[4], maxd3 = hb[8];
+    if (mode == 2) return level_order(P, G, nnz, maxd1, true, active);
     const int64_t ncell = (maxd1 / kStrip + 1) * (maxd3 + 1);
-    if (ncell > 4 * n + 1024) return EXPM_OK;   // path-like: the natural order is kept
+    // path-like: the level ordering, if it narrows the band
+    if (ncell > 4 * n + 1024) return level_order(P, G, nnz, maxd1, false, active);
     CHK(ensure(P, P.ro_cell, sizeof(int64_t) * n));
     CHK(ensure(P, P.ro_cnt, sizeof(int64_t) * (ncell + 1)));
     CHK(ensure(P, P.ro_off, sizeof(int64_t) * (ncell + 1)));
@@ -475,7 +541,8 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
     CHK(scan(P, cnt, off, ncell));
     HIPCHK(hipMemcpyAsync(hb + 9, rb + 9, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     CHK(sync(P));
-    if (hb[9] > kCellMax) return EXPM_OK;       // no 2D structure: keep the order
+    // no 2D structure: the level ordering, if it narrows the band
+    if (hb[9] > kCellMax) return level_order(P, G, nnz, maxd1, false, active);
     CHK(ensure(P, P.order, sizeof(int32_t) * n));
     CHK(ensure(P, P.newidx, sizeof(int32_t) * n));
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (ncell + 1), st));
@@ -486,6 +553,7 @@ int compute_reorder(expm_plan_s &P, CsrView G, bool *active) {
                        q0, d1, (int32_t *)P.order.p, (int32_t *)P.newidx.p);
     HIPCHK(hipGetLastError());
     *active = true;
+    P.ordering = 1;
     return EXPM_OK;
 }
 

@@ -65,9 +65,11 @@ def test_choose_mn_rejects_bad_input():
 
 @pytest.mark.parametrize("field,value", [("filter_mode", 7), ("e_r", -0.5),
                                          ("max_filter_iter", 0), ("normal", 2),
-                                         ("checkpoint_interval", -1), ("reorder", 2),
+                                         ("checkpoint_interval", -1), ("reorder", 3),
                                          ("profile", 3), ("profile", -1),
-                                         ("tile_min_fill", float("nan"))])
+                                         ("tile_min_fill", float("nan")), ("norm", 2),
+                                         ("filter_mode", 3), ("exact_ri", 2),
+                                         ("diagnostics", -1)])
 def test_plan_rejects_invalid_options(field, value):
     """Option validation runs before the plan touches the device."""
     o = capi.expm_opts_default()

@@ -285,3 +285,55 @@ def test_propagate():
     assert np.linalg.norm(U1 - oracle.spmm((Eo.rowptr, Eo.col, Eo.val), U0)) <= \
         1e-13 * np.linalg.norm(U1)
     assert np.array_equal(U0k, U0)
+
+
+# ------------------------------------------------ level ordering (non-mesh inputs)
+
+def scrambled_band(n, half, seed):
+    """A banded matrix (half-bandwidth `half`) with its rows and columns
+    permuted at random: no 2D structure, and a wide band in its own order."""
+    rng = np.random.default_rng(seed)
+    i = np.repeat(np.arange(n), 2 * half + 1)
+    j = i + np.tile(np.arange(-half, half + 1), n)
+    ok = (j >= 0) & (j < n)
+    i, j = i[ok], j[ok]
+    v = rng.standard_normal(i.size)
+    keep = i <= j
+    i, j, v = i[keep], j[keep], v[keep]
+    r = np.concatenate([i, j[i != j]])
+    c = np.concatenate([j, i[i != j]])
+    w = np.concatenate([v, v[i != j]])
+    p = rng.permutation(n)
+    return W.csr_from_coo(n, p[r], p[c], w * 0.3)
+
+
+def test_level_ordering_scrambled_band():
+    """A scrambled band has no 2D structure: the default takes the level
+    ordering, which narrows the band (fewer tiles in the last squaring) and
+    leaves the result that of the method in the given order."""
+    H = scrambled_band(6000, 3, 71)
+    Eg, sg = run_gpu(H, 1e-12)
+    Eo, so = run_oracle(H, 1e-12)
+    rel, ok, _, _ = compare(Eg, Eo, final_theta(so))
+    assert rel <= TOL and ok
+    assert sg["ordering"] == 2
+    # on tiles at every step, the last candidate needs far fewer tiles
+    Et, st = run_gpu(H, 1e-12, tile_min_fill=0.0)
+    _, s0 = run_gpu(H, 1e-12, reorder=0, tile_min_fill=0.0)
+    assert st["ordering"] == 2 and s0["ordering"] == 0
+    rel, ok, _, _ = compare(Et, Eo, final_theta(so))
+    assert rel <= TOL and ok
+    print(f"[level ordering] last-step tiles {st['sq_tiles'][-1]} vs {s0['sq_tiles'][-1]} in "
+          "the given order", flush=True)
+    assert 4 * st["sq_tiles"][-1] < s0["sq_tiles"][-1]
+
+
+def test_level_ordering_forced_on_grid():
+    H = grid(65, 72, 20.0)
+    Eg, sg = run_gpu(H, 1e-12, reorder=2)
+    assert sg["ordering"] == 2
+    Eo, so = run_oracle(H, 1e-12)
+    rel, ok, _, _ = compare(Eg, Eo, final_theta(so))
+    assert rel <= TOL and ok
+    _, s1 = run_gpu(H, 1e-12)
+    assert s1["ordering"] == 1
