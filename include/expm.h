@@ -24,6 +24,12 @@
  *    output is allocated, the outputs are left zeroed, and expm_last_error()
  *    returns a message for the calling thread.
  *  - A plan is not thread-safe; separate plans may be used concurrently.
+ *  - Outputs written on opts.stream are ready in stream order there only:
+ *    expm_sparse returns without waiting for the device.
+ *  - Tracing: each call marks its phases (plan, Taylor seed, squarings,
+ *    finish; adjoint squarings and seed) as ROCTX ranges; with EXPM_LOG=1
+ *    in the environment every expm_sparse call prints one line of its
+ *    statistics on stderr.
  */
 #ifndef EXPM_H
 #define EXPM_H

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexpm_gfx950.so")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 SOURCES = ["kernels.hip", "spgemm.hip", "bsr.hip", "bsr_adjoint.hip", "bsr_host.hip", "executor.hip",
            "batched.hip", "reorder.hip", "extras.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -45,7 +46,8 @@ def build(verbose: bool = False) -> str:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     r = subprocess.run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined",
-                        "-o", tmp, *objs],
+                        "-o", tmp, *objs, "-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx",
+                        "-Wl,-rpath," + ROCM_LIB],
                        capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError(f"link failed:\n{r.stderr}")

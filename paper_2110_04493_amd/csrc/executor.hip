@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -886,6 +887,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.have_stats = true;
         return EXPM_OK;
     }
+    TraceRange phase("expm plan (steps 1-3)");
     expm_analysis A{};
     CHK(plan_input(P, Hv, eps, P.H0, &A));
     expm_stats &S = P.stats;
@@ -933,6 +935,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
             std::swap(P.H0, P.Hp);
         }
     }
+    phase.next("expm taylor seed");
     const auto t_taylor0 = std::chrono::steady_clock::now();
     // Step 3: H0 = H 2^-N, r0, eg0, Taylor seed.
     HIPCHK(scale_ldexp((const double *)P.H0.v.p, (double *)P.H0.v.p, nnz, -N, st));
@@ -980,6 +983,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     // T_0 = S_1 + ... + S_M' (Eq. 4.14's sum), term after term
     CHK(sum_taylor(P, P.T));
     S.t_taylor_ms = ms_since(t_taylor0);
+    phase.next("expm squarings");
     // T's true nnz (the add only bounds it)
     HIPCHK(hipMemcpyAsync(P.host, (int64_t *)P.T.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
@@ -1073,6 +1077,7 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         }
     }
     S.squarings = N;
+    phase.next("expm finish (E = I + T_N)");
     if (N == 0 && cur != &P.T) CHK(copy_csr(P, P.T, *cur));   // T_0 is also T_N
     if (keep) std::swap(P.TN, P.T);   // T_N stays for the adjoint
     // E = I + T_N (exact zeros not stored)
@@ -1209,6 +1214,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         CHK(reserve_as(P, P.adj_tiles, ref.tB));
         CHK(reserve_as(P, P.adj_tilesA, ref.tA));
     }
+    TraceRange phase("expm adjoint squarings");
     const DCsr *Tk = &P.TN;   // pattern of g
     bool g_ready = false;     // P.tsG already holds Tk's tile pattern
     bool g_tiles = false;     // ... and g's values as tiles
@@ -1293,6 +1299,7 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
                 CHK(reserve_as(P, P.cts[c], P.tsT));
     }
     // Taylor seed: g is dL/dT^_0 on supp(T^_0) = P.ckpt[0].
+    phase.next("expm adjoint taylor seed");
     const int Mp = (int)P.taylor.size();
     CsrView G0 = CsrView{n, (const int64_t *)P.ckpt[0].rp.p, (const int32_t *)P.ckpt[0].ci.p,
                          (const double *)g.p};
@@ -1469,6 +1476,31 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     return EXPM_OK;
 }
 
+// EXPM_LOG=1 in the environment: one line per expm_sparse call on stderr
+// with the plan of steps 1-3 and, per squaring, the kept entries, the
+// threshold and the filter passes.
+static void log_call(const expm_plan_s &P, int64_t n, double eps, int status) {
+    static const bool on = [] {
+        const char *e = getenv("EXPM_LOG");
+        return e && atoi(e) > 0;
+    }();
+    if (!on) return;
+    const expm_stats &S = P.stats;
+    std::string line;
+    char buf[160];
+    snprintf(buf, sizeof buf, "expm: n=%lld eps=%.3g status=%d M=%d N=%d normal=%d a=%.4g "
+             "||H||=%.6g taylor_terms=%d nnz(E)=%lld", (long long)n, eps, status, S.M, S.N,
+             S.normal, S.a, S.norm_h, S.taylor_terms, (long long)S.nnz_e);
+    line += buf;
+    for (int i = 1; i <= S.squarings && i < EXPM_MAXSTEP; ++i) {
+        snprintf(buf, sizeof buf, " | %d: kept=%lld theta=%.3g iters=%d%s", i,
+                 (long long)S.sq_kept[i], S.sq_theta[i], S.sq_iters[i],
+                 S.sq_tiles[i] ? " tiles" : "");
+        line += buf;
+    }
+    fprintf(stderr, "%s\n", line.c_str());
+}
+
 int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E) {
     g_err.clear();
     if (!p) return fail(EXPM_EINVAL, "plan is NULL");
@@ -1497,6 +1529,7 @@ int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E)
             p->stats.t_total_ms = ms_since(t0);   // host time of the call
         }
     }
+    log_call(*p, H ? H->n : 0, eps, s);
     if (s != EXPM_OK) {
         p->stats.status = s;
         (void)hipStreamSynchronize(p->st);

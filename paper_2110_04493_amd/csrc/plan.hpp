@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/expm.h"
 #include "kernels.hpp"
 
@@ -158,6 +160,21 @@ namespace xpm {
 namespace host {
 
 constexpr int kParts = 1024;
+
+// A named range for ROCm's tracing tools (rocprofv3 --marker-trace): the
+// phases of a call show up on the timeline; without a tool attached the
+// calls do nothing.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    // ends this range and opens the next phase's
+    void next(const char *name) {
+        roctxRangePop();
+        roctxRangePushA(name);
+    }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Runs f when the enclosing scope ends: releases a function's local
 // workspace on its error returns too (release is idempotent).

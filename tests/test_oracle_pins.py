@@ -455,3 +455,19 @@ def test_invalid_inputs():
     col[0], col[1] = col[1], col[0]
     with pytest.raises(oracle.OracleError):
         oracle.expm(A.rowptr, col, A.val, 1e-12)
+
+
+def test_filter_iteration_cap():
+    """Algorithm 4.1 capped at one pass on values that need two reports
+    non-convergence (ORA_ENOTCONV), in the filter and in a whole run."""
+    v = np.array([1.0, 0.5, 0.3, 0.2, 0.1])
+    _, _, it, _ = oracle.filter_values(v, 0.3)
+    assert it >= 2
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.filter_values(v, 0.3, max_iter=1)
+    assert e.value.code == oracle.ENOTCONV
+    L = W.grid_laplacian(20, 20, np.random.default_rng(81))
+    H = L.scaled(-50.0 / W.norm1(L))
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.expm(H.rowptr, H.col, H.val, 1e-12, max_iter=1)
+    assert e.value.code == oracle.ENOTCONV
