@@ -279,12 +279,18 @@ class ExpmFn(torch.autograd.Function):
         return None, None, dH, None, None
 
 
-def expm_batched(mats, eps, **options):
+def expm_batched(mats, eps, tune: bool = False, **options):
     """Exponentials of several CSR matrices (list of (crow, col, vals)) in one
-    batched call; returns a list of (rowptr, col, val)."""
+    batched call; returns a list of (rowptr, col, val).  With tune, the tile
+    threshold comes from the autotuner's cache for the batch's architecture
+    and shape bucket (tuned on this batch when the bucket is new)."""
     if not mats:
         return []
-    plan = Plan(mats[0][2].device, Options(**options))
+    opts = Options(**options)
+    if tune:
+        from . import autotune
+        opts, _ = autotune.tuned_batched_options(mats, eps, base=opts)
+    plan = Plan(mats[0][2].device, opts)
     try:
         return plan.expm_batched(mats, eps)
     finally:
