@@ -957,14 +957,16 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     const int ck = ck_last ? std::max(1, (int)ceil(sqrt((double)N)))
                            : P.opts.checkpoint_interval;
     P.ck = ck;
-    CHK(copy_csr(P, P.S, P.H0));
-    // the terms are kept (the adjoint needs them, and T_0 is their sum)
+    // the terms are kept (the adjoint needs them, and T_0 is their sum):
+    // each is written straight into its slot, where the next product reads it
+    P.taylor.reserve(M + 1);
     CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.H0));
     S.taylor_terms = 1;
     const CsrView H0v = P.H0.view();
     for (int i = 2; i <= M; ++i) {
         int64_t cand;
-        CHK(spgemm(P, P.S.view(), P.S.nnz, H0v, 0.0, (double)i, false, &cand));
+        const DCsr &prev = P.taylor.back();
+        CHK(spgemm(P, prev.view(), prev.nnz, H0v, 0.0, (double)i, false, &cand));
         FilterCtl h{};
         int64_t kept;
         CHK(filter_and_count(P, n, cand, eg0, nullptr, false, 0.0, false, &h, &kept));
@@ -973,11 +975,9 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         S.taylor_cand[i] = cand;
         S.taylor_kept[i] = kept;
         if (kept == 0) break;   // later terms are exactly zero
-        CHK(write_filtered(P, n, P.Snew, kept, false, false));
-        std::swap(P.S, P.Snew);
-        P.S.nnz = kept;
+        DCsr &slot = push_reuse(P.taylor, P.taylor_pool);
+        CHK(write_filtered(P, n, slot, kept, false, false));
         S.taylor_terms = i;
-        CHK(copy_csr(P, push_reuse(P.taylor, P.taylor_pool), P.S));
     }
     P.Mp = S.taylor_terms;
     // T_0 = S_1 + ... + S_M' (Eq. 4.14's sum), term after term
