@@ -217,6 +217,9 @@ typedef struct {
     double tile_bytes, adj_tile_flops, adj_tile_bytes;
     /* the locality ordering applied: 0 none, 1 strips, 2 levels */
     int ordering;
+    /* 1 when the last expm_sparse_backward ran its first step on the rows
+       of the nonzeros of dL/dE (fewer than a hundredth of E's entries) */
+    int adj_sparse_first;
 } expm_stats;
 
 typedef struct expm_plan_s *expm_plan_t;

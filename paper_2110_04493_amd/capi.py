@@ -95,7 +95,7 @@ class expm_stats(C.Structure):
                 ("sq_ri", C.c_double * _S), ("sq_band", C.c_int64 * _S),
                 ("theta0", C.c_double), ("tile_bytes", C.c_double),
                 ("adj_tile_flops", C.c_double), ("adj_tile_bytes", C.c_double),
-                ("ordering", C.c_int)]
+                ("ordering", C.c_int), ("adj_sparse_first", C.c_int)]
 
     def to_dict(self) -> dict:
         d = {k: getattr(self, k) for k in ("status", "M", "N", "taylor_terms", "normal",
@@ -104,7 +104,8 @@ class expm_stats(C.Structure):
                                            "t_backward_ms", "t_total_ms", "tile_launches",
                                            "tile_ms", "tile_flops", "adj_tile_launches",
                                            "adj_tile_ms", "theta0", "tile_bytes",
-                                           "adj_tile_flops", "adj_tile_bytes", "ordering")}
+                                           "adj_tile_flops", "adj_tile_bytes", "ordering",
+                                           "adj_sparse_first")}
         T, N = self.taylor_terms, self.squarings
         for k in ("taylor_theta", "taylor_iters", "taylor_cand", "taylor_kept"):
             d[k] = list(getattr(self, k)[2:T + 2])

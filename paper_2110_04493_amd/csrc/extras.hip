@@ -177,6 +177,35 @@ hipError_t band_of(CsrView T, const int32_t *order, long long *out, hipStream_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ position maps
+// dst[q] = src[pos[q]]  /  dst[pos[q]] += src[q]  (pos a permutation of the
+// entries: each dst entry is touched once).
+__global__ void k_gather_pos(const double *src, const int64_t *pos, int64_t m, double *dst) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) dst[q] = src[pos[q]];
+}
+
+__global__ void k_add_scatter_pos(const double *src, const int64_t *pos, int64_t m, double *dst) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) dst[pos[q]] += src[q];
+}
+
+hipError_t gather_pos(const double *src, const int64_t *pos, int64_t m, double *dst,
+                      hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, src, pos,
+                       m, dst);
+    return hipGetLastError();
+}
+
+hipError_t add_scatter_pos(const double *src, const int64_t *pos, int64_t m, double *dst,
+                           hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_scatter_pos, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                       src, pos, m, dst);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Y = A X
 // One wave per (row i, chunk of 64 columns of X); lane = column.  The row's
 // entries are read 64 at a time (one lane each) and broadcast with

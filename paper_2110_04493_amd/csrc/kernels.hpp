@@ -306,6 +306,11 @@ hipError_t fpim_theta_tiles(int64_t n, int64_t ntiles, const int32_t *ccols, con
 // out[0] = l1, out[1] = l2 of Eq. (3.1) in the caller's ordering (order[]:
 // library row -> caller row, or NULL); both LLONG_MIN for an empty matrix.
 hipError_t band_of(CsrView T, const int32_t *order, long long *out, hipStream_t st);
+// dst[q] = src[pos[q]]  /  dst[pos[q]] += src[q] (pos: a permutation).
+hipError_t gather_pos(const double *src, const int64_t *pos, int64_t m, double *dst,
+                      hipStream_t st);
+hipError_t add_scatter_pos(const double *src, const int64_t *pos, int64_t m, double *dst,
+                           hipStream_t st);
 // Y = A X (X, Y dense row-major, leading dimensions ldx, ldy): from CSR, or
 // from A's 16 x 16 tiles (A operand layout) on the matrix cores.
 hipError_t spmm(CsrView A, int64_t m, const double *X, int64_t ldx, double *Y, int64_t ldy,

@@ -120,3 +120,16 @@ def test_config5_full_size():
     """The differentiation workload at full size (n = 40,000)."""
     H, eps = W.config5()
     check(H, eps, density=0.02)
+
+
+@pytest.mark.parametrize("density,sparse", [(0.004, 1), (0.3, 0)])
+def test_sparse_incoming_gradient(density, sparse):
+    """A loss on 0.4% of E's entries gives a dL/dE that is mostly exact
+    zeros: the first adjoint step then runs on the rows of its nonzeros (a
+    denser loss keeps the tiles); both agree with the oracle."""
+    L = W.grid_laplacian(60, 60, np.random.default_rng(91))
+    H = L.scaled(-30.0 / W.norm1(L))
+    dg, st = gpu_grad(H, 1e-12, density=density)
+    do, _ = oracle_grad(H, 1e-12, density=density)
+    assert st["adj_sparse_first"] == sparse
+    assert np.linalg.norm(dg - do) <= TOL * np.linalg.norm(do)
