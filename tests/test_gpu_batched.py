@@ -106,3 +106,19 @@ def test_batched_invalid_instance():
     with pytest.raises(capi.ExpmError) as e:
         run_batched([good, bad], [1e-12, 1e-12])
     assert e.value.code == capi.EXPM_EINVAL
+
+
+def test_batched_family_at_stated_sizes():
+    """Instances of the batched family at its stated sizes that the oracle
+    can run in seconds: two grids near n = 20,000 with the smaller tau
+    (j = 38: n = 18,395, tau = 1.43; j = 114: n = 18,627, tau = 2.58) and two
+    adjacency instances whose exponentials are dense (j = 59: n = 1,066;
+    j = 191: n = 990, beta = 0.99), in one batched call, each against the
+    oracle and against its own single call."""
+    mats, eps = [], []
+    for j in (38, 59, 114, 191):
+        H, e = W.config4_instance(j)
+        mats.append(H)
+        eps.append(e)
+    assert [H.n for H in mats] == [18395, 1066, 18627, 990]
+    check_all(mats, eps)
