@@ -42,6 +42,7 @@
 #include <math.h>
 #include <omp.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -651,6 +652,9 @@ ora_run *ora_expm(int64_t n, const int64_t *rp, const int32_t *ci, const double 
         if (st) goto fail;
         S->sq_kept[i] = mat_nnz(&Tn);
         S->sq_band[i] = band_l(&Tn);
+        if (getenv("ORA_PROGRESS"))   /* long runs report each step as it ends */
+            fprintf(stderr, "oracle: squaring %d of %d done, %lld entries kept\n", i, S->N,
+                    (long long)S->sq_kept[i]);
         mat_free(&Tt);
         mat_free(&T);
         T = Tn;

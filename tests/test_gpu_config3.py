@@ -58,3 +58,60 @@ def test_config3_full_size_sampled_rows():
         print(f"[config3] worst sampled-row relF {worst:.2e}", flush=True)
     finally:
         plan.close()
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("EXPM_FULL_ORACLE"),
+                    reason="the oracle at this size needs minutes and ~90 GB of host memory; "
+                           "set EXPM_FULL_ORACLE=1 to run it")
+def test_config3_full_size_against_oracle():
+    """The whole of E at full size against the oracle's (same parity bar as
+    every other case), compared in chunks of rows."""
+    import os
+    import torch
+    import oracle
+    from paper_2110_04493_amd import api
+    H, eps = W.config3(SIDE)
+    plan = api.Plan("cuda")
+    try:
+        rp, ci, v = plan.expm(*to_device(H), eps)
+        torch.cuda.synchronize()
+        st = plan.stats()
+        g_rp, g_ci, g_v = rp.cpu().numpy(), ci.cpu().numpy(), v.cpu().numpy()
+        del rp, ci, v
+    finally:
+        plan.close()
+    print(f"[config3 oracle] GPU done: nnz(E)={g_v.size}", flush=True)
+    os.environ["ORA_PROGRESS"] = "1"
+    res = oracle.expm(H.rowptr, H.col, H.val, eps)
+    theta = res.stats["sq_theta"][-1]
+    assert (st["M"], st["N"]) == (res.stats["M"], res.stats["N"])
+    num = den = 0.0
+    only_g = only_o = 0
+    ok = True
+    for r0 in range(0, H.n, 65536):
+        r1 = min(H.n, r0 + 65536)
+        kg = np.repeat(np.arange(r0, r1, dtype=np.int64), np.diff(g_rp[r0:r1 + 1])) * H.n + \
+            g_ci[g_rp[r0]:g_rp[r1]]
+        ko = np.repeat(np.arange(r0, r1, dtype=np.int64), np.diff(res.rowptr[r0:r1 + 1])) * H.n + \
+            res.col[res.rowptr[r0]:res.rowptr[r1]]
+        vg = g_v[g_rp[r0]:g_rp[r1]]
+        vo = res.val[res.rowptr[r0]:res.rowptr[r1]]
+        u = np.union1d(kg, ko)
+        a = np.zeros(u.size)
+        b = np.zeros(u.size)
+        a[np.searchsorted(u, kg)] = vg
+        b[np.searchsorted(u, ko)] = vo
+        num += float(np.sum((a - b) ** 2))
+        den += float(np.sum(b ** 2))
+        og = np.setdiff1d(kg, ko, assume_unique=True)
+        oo = np.setdiff1d(ko, kg, assume_unique=True)
+        only_g += og.size
+        only_o += oo.size
+        vals = np.concatenate([a[np.searchsorted(u, og)], b[np.searchsorted(u, oo)]])
+        ok = ok and bool(np.all((np.abs(vals) >= theta / 2) & (np.abs(vals) <= 2 * theta)))
+        if (r0 // 65536) % 8 == 7:
+            print(f"[config3 oracle] compared rows below {r1}", flush=True)
+    rel = (num / den) ** 0.5
+    print(f"[config3 oracle] relF={rel:.3e} only_gpu={only_g} only_oracle={only_o} "
+          f"nnz={g_v.size}/{res.val.size}", flush=True)
+    assert rel <= 1e-11 and ok
