@@ -1,8 +1,11 @@
 """Large 2D heat conduction at full size: a 1448 x 1448 unit grid
-(n = 2,096,704, nnz(H) = 10,477,728), H = -0.5 L, eps_tol = 1e-10.  The oracle
-cannot run at this size; sampled rows of E are checked against the exact
-Kronecker closed form e^{-tL} = e^{-tL_path} (x) e^{-tL_path} and against unit
-row sums, which hold at any size."""
+(n = 2,096,704, nnz(H) = 10,477,728), H = -0.5 L, eps_tol = 1e-10.  The
+default test checks sampled rows of E against the exact Kronecker closed
+form e^{-tL} = e^{-tL_path} (x) e^{-tL_path} and unit row sums, which hold
+at any size.  The comparison of the whole E with the oracle's takes the
+oracle about 2 minutes on 16 host threads and tens of GB of host memory, so
+it is an opt-in test (EXPM_FULL_ORACLE=1); run on MI355X it gave a relative
+Frobenius error of 9.3e-15 with identical supports (793,765,472 entries)."""
 import time
 
 import numpy as np
