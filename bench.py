@@ -477,10 +477,56 @@ def other_workloads(args) -> dict:
     out["differentiation"] = grad_numbers(3, 5)
     print("other workloads: action E R", file=sys.stderr, flush=True)
     out["action"] = action_numbers(args.side, 1000)
+    print("other workloads: checkpoint placements", file=sys.stderr, flush=True)
+    out["checkpoints"] = checkpoint_numbers(args.side)
     print("other workloads: large grid", file=sys.stderr, flush=True)
     out["large_grid"] = large_grid_numbers()
     print("other workloads: batched", file=sys.stderr, flush=True)
     out["batched"] = batched_numbers(64, 500, 2000, 1, 3)
+    print("other workloads: batched at the stated size range", file=sys.stderr, flush=True)
+    out["batched_stated_range"] = batched_numbers(8, 500, 20000, 1, 1)
+    return out
+
+
+def checkpoint_numbers(side: int) -> dict:
+    """The headline step (forward + adjoint) under three checkpoint
+    placements: the default (the last ceil(sqrt(N)) iterates), every
+    ceil(sqrt(N))-th iterate counted back from T_{N-1}, and every iterate;
+    median step time of 4 steps after 2 warmup steps, and the device memory
+    the plan holds by then (free memory before and after)."""
+    import math
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    H, eps = W.config2(side)
+    dev = [torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)]
+    out = {}
+    dE = None
+    for name, interval in (("last_sqrtN", 0), ("every_sqrtN", -1), ("all", 1)):
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        if interval < 0:
+            probe = api.Plan("cuda")
+            N = probe.analyze(*dev, eps)["N"]
+            probe.close()
+            interval = max(1, math.ceil(math.sqrt(N)))
+        plan = api.Plan("cuda", api.Options(keep_checkpoints=True, checkpoint_interval=interval))
+        ts = []
+        for it in range(6):
+            if dE is None:
+                rp, ci, v = plan.expm(*dev, eps)
+                rows = np.repeat(np.arange(H.n), np.diff(rp.cpu().numpy()))
+                dE = torch.from_numpy(W.loss_weights(rows, ci.cpu().numpy(), H.n,
+                                                     density=0.02)).cuda()
+                plan.backward(dE, H.nnz)
+                continue
+            t, _ = _sync_time(lambda: (plan.expm(*dev, eps), plan.backward(dE, H.nnz)))
+            if it >= 2:
+                ts.append(t)
+        torch.cuda.synchronize()
+        free1, _ = torch.cuda.mem_get_info()
+        plan.close()
+        out[name] = {"checkpoint_interval": interval, "step_s": round(float(np.median(ts)), 5),
+                     "device_memory_gb": round((free0 - free1) / 1e9, 1)}
     return out
 
 
