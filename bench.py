@@ -489,9 +489,10 @@ def other_workloads(args) -> dict:
 
 
 def checkpoint_numbers(side: int) -> dict:
-    """The headline step (forward + adjoint) under three checkpoint
-    placements: the default (the last ceil(sqrt(N)) iterates), every
-    ceil(sqrt(N))-th iterate counted back from T_{N-1}, and every iterate;
+    """The headline step (forward + adjoint) under four checkpoint
+    placements: the default (every iterate while they fit a memory budget),
+    the last ceil(sqrt(N)) iterates, every ceil(sqrt(N))-th iterate counted
+    back from T_{N-1}, and every iterate;
     median step time of 4 steps after 2 warmup steps, and the device memory
     the plan holds by then (free memory before and after)."""
     import math
@@ -501,10 +502,10 @@ def checkpoint_numbers(side: int) -> dict:
     dev = [torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)]
     out = {}
     dE = None
-    for name, interval in (("last_sqrtN", 0), ("every_sqrtN", -1), ("all", 1)):
+    for name, interval in (("default", 0), ("last_sqrtN", -1), ("every_sqrtN", -2), ("all", 1)):
         torch.cuda.synchronize()
         free0, _ = torch.cuda.mem_get_info()
-        if interval < 0:
+        if interval == -2:
             probe = api.Plan("cuda")
             N = probe.analyze(*dev, eps)["N"]
             probe.close()

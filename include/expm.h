@@ -108,9 +108,13 @@ typedef struct {
     int keep_checkpoints;    /* 1: keep what expm_sparse_backward needs         */
     int checkpoint_interval; /* squaring iterates the adjoint keeps: c >= 1
                                 keeps every c-th one counted back from T_{N-1}
-                                (1 keeps all of them); 0 (default) keeps
-                                ceil(sqrt(N)) of them, the last iterates
-                                T_{N-C} .. T_{N-1}, the costliest to recompute */
+                                (1 keeps all of them); -1 keeps ceil(sqrt(N))
+                                of them, the last iterates T_{N-C} .. T_{N-1},
+                                the costliest to recompute; 0 (default) keeps
+                                those and also the earlier iterates, one
+                                after another, while their CSR arrays fit in
+                                a sixteenth of the device memory (then the
+                                adjoint recomputes nothing)                  */
     void *stream;            /* hipStream_t for every launch and copy          */
     const expm_allocator *allocator; /* outputs; NULL = library allocation     */
     int profile;             /* 1: time the kernel phases of every squaring

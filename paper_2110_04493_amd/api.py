@@ -81,7 +81,7 @@ class Options:
     e_r: float = 0.1
     max_filter_iter: int = 64
     keep_checkpoints: bool = False
-    checkpoint_interval: int = 0
+    checkpoint_interval: int = 0   # 0: auto (all iterates while they fit), -1: last ceil(sqrt(N))
     profile: int = 0           # 1: phase timers and work counts, 2: tile kernel timers only
     reorder: int = -1
     tile_min_fill: float = -1.0

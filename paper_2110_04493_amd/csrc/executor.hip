@@ -948,15 +948,21 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     P.a = a;
     // Checkpoints of the squaring iterates (the adjoint recomputes the rest):
     // with checkpoint_interval c >= 1, every c-th iterate counted back from
-    // T_{N-1}; with 0, ceil(sqrt(N)) of them, on the last iterates
+    // T_{N-1}; with -1, ceil(sqrt(N)) of them, on the last iterates
     // T_{N-C} .. T_{N-1}.  Every iterate that is not a checkpoint is
     // recomputed exactly once, and the iterates grow with every squaring,
     // so the last ones are the most expensive to recompute; the early ones
-    // the first segment then holds are small.
-    const bool ck_last = P.opts.checkpoint_interval <= 0;
-    const int ck = ck_last ? std::max(1, (int)ceil(sqrt((double)N)))
-                           : P.opts.checkpoint_interval;
+    // the first segment then holds are small.  With 0 (the default) the
+    // earlier iterates are kept too, one after another, while their CSR
+    // arrays fit in a sixteenth of the device memory: then nothing is
+    // recomputed (the checkpoints' tile sets, kept within their own budget,
+    // also spare the adjoint the tile assembly).
+    const int ci_opt = P.opts.checkpoint_interval;
+    const bool ck_last = ci_opt <= 0;
+    const bool ck_fill = ci_opt == 0;
+    const int ck = ck_last ? std::max(1, (int)ceil(sqrt((double)N))) : ci_opt;
     P.ck = ck;
+    size_t extra_ckpt_bytes = 0;
     // the terms are kept (the adjoint needs them, and T_0 is their sum):
     // each is written straight into its slot, where the next product reads it
     P.taylor.reserve(M + 1);
@@ -1068,7 +1074,15 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.T.nnz = S.sq_kept[i];
         cur = &P.T;
         cur_ck = -1;
-        if (keep && !last && is_ckpt(i)) {
+        bool keep_i = keep && !last && is_ckpt(i);
+        if (keep && !last && !keep_i && ck_fill) {
+            const size_t b = 12 * (size_t)S.sq_kept[i] + 8 * (size_t)(n + 1);
+            if (extra_ckpt_bytes + b <= P.dev_mem / 16) {
+                keep_i = true;
+                extra_ckpt_bytes += b;
+            }
+        }
+        if (keep_i) {
             P.ckpt_at.push_back(i);
             DCsr &slot = push_reuse(P.ckpt, P.ckpt_pool);
             std::swap(slot, P.T);
@@ -1492,7 +1506,7 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1)
         return fail(EXPM_EINVAL, "invalid option value");
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
-        o.checkpoint_interval < 0 || o.reorder < -1 || o.reorder > 2 || o.profile < 0 ||
+        o.checkpoint_interval < -1 || o.reorder < -1 || o.reorder > 2 || o.profile < 0 ||
         o.profile > 2 ||
         !(o.tile_min_fill == o.tile_min_fill))
         return fail(EXPM_EINVAL, "invalid option value");

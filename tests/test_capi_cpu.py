@@ -65,7 +65,7 @@ def test_choose_mn_rejects_bad_input():
 
 @pytest.mark.parametrize("field,value", [("filter_mode", 7), ("e_r", -0.5),
                                          ("max_filter_iter", 0), ("normal", 2),
-                                         ("checkpoint_interval", -1), ("reorder", 3),
+                                         ("checkpoint_interval", -2), ("reorder", 3),
                                          ("profile", 3), ("profile", -1),
                                          ("tile_min_fill", float("nan")), ("norm", 2),
                                          ("filter_mode", 3), ("exact_ri", 2),

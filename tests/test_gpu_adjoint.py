@@ -56,7 +56,7 @@ def test_random_small(kind, seed, scale):
     check(H, 1e-14)
 
 
-@pytest.mark.parametrize("ck", [0, 1, 2, 100])
+@pytest.mark.parametrize("ck", [-1, 0, 1, 2, 100])
 def test_grid_checkpoint_intervals(ck):
     rng = np.random.default_rng(3)
     L = W.grid_laplacian(24, 24, rng)
@@ -110,10 +110,13 @@ def test_autograd_function():
     assert np.linalg.norm(dg - do) <= TOL * np.linalg.norm(do)
 
 
-def test_config5_reduced():
-    """The differentiation workload's family at 80 x 80 (n = 6,400)."""
+@pytest.mark.parametrize("ck", [0, -1])
+def test_config5_reduced(ck):
+    """The differentiation workload's family at 80 x 80 (n = 6,400), with
+    the default checkpoints (every iterate fits) and with ceil(sqrt(N))
+    checkpoints and recomputation."""
     H, eps = W.config5(80)
-    check(H, eps, density=0.02)
+    check(H, eps, density=0.02, checkpoint_interval=ck)
 
 
 def test_config5_full_size():
