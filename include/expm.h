@@ -161,6 +161,10 @@ typedef struct {
     int diagnostics;         /* 1: per-step bandwidths l(T^_i) of Eq. (3.1),
                                 in the caller's ordering, into expm_stats
                                 (one extra pass over every iterate)          */
+    int literal_a;           /* filter constant a for non-normal H:
+                                0 (default) min(1/(N+1), 1/||H||); 1 the
+                                1/||H|| of Algorithm 4.2 step 2 and section
+                                4.2, also where it exceeds 1/(N+1)           */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',
@@ -276,7 +280,8 @@ typedef struct {
     int M, N;          /* problem (4.20) at norm_h and eps                    */
     int normal;        /* Algorithm 4.2 step 2 (test or opts.normal)          */
     double a;          /* filter constant: 1/(N+1), or min(1/(N+1), 1/||H||)
-                          for non-normal H; 0 without the paper's filter      */
+                          for non-normal H (1/||H|| with opts.literal_a); 0
+                          without the paper's filter                          */
     double h0, r0;     /* ||H 2^-N|| and the bound of Eq. (4.5)               */
     double eg0;        /* the Taylor terms' budget a r0 / (M e^{2 h0})        */
 } expm_analysis;

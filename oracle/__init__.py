@@ -39,7 +39,7 @@ def build() -> str:
 class _Opts(C.Structure):
     _fields_ = [("normal", C.c_int), ("filter_mode", C.c_int), ("e_r", C.c_double),
                 ("max_iter", C.c_int), ("keep", C.c_int), ("norm", C.c_int),
-                ("exact_ri", C.c_int)]
+                ("exact_ri", C.c_int), ("literal_a", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -173,13 +173,13 @@ class Run:
 
     def __init__(self, rowptr, col, val, eps: float, *, normal: int = -1,
                  filter_mode: int = 0, e_r: float = 0.1, max_iter: int = 64, keep: bool = True,
-                 norm: int = 0, exact_ri: bool = False):
+                 norm: int = 0, exact_ri: bool = False, literal_a: bool = False):
         lib = _load()
         rp, ci, v = _csr_arrays(rowptr, col, val)
         self.n = rp.size - 1
         self._H = (rp, ci, v)
         o = _Opts(int(normal), int(filter_mode), float(e_r), int(max_iter), int(keep), int(norm),
-                  int(exact_ri))
+                  int(exact_ri), int(literal_a))
         st = C.c_int()
         self._h = lib.ora_expm(self.n, _ptr(rp), _ptr(ci), _ptr(v), float(eps), C.byref(o), C.byref(st))
         if st.value:

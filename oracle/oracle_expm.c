@@ -66,6 +66,9 @@ typedef struct {
                             1-norm (largest absolute column sum)           */
     int exact_ri;        /* 0: r_i = 2^i r0; 1: r_i = 2 r_{i-1} + r_{i-1}^2,
                             the recurrence of Eq. (4.3)                     */
+    int literal_a;       /* non-normal H: 0 a = min(1/(N+1), 1/||H||);
+                            1 a = 1/||H|| as step 2 of Algorithm 4.2 and
+                            section 4.2 state it                           */
 } ora_opts;
 
 typedef struct {
@@ -574,7 +577,7 @@ ora_run *ora_expm(int64_t n, const int64_t *rp, const int32_t *ci, const double 
     if (o->normal >= 0) S->normal = o->normal;
     else { S->normal = is_normal(&H, nh_fro, &st); if (st) goto fail; }
     S->a = 1.0 / (S->N + 1);
-    if (!S->normal && 1.0 / S->nh < S->a) S->a = 1.0 / S->nh;
+    if (!S->normal && (o->literal_a || 1.0 / S->nh < S->a)) S->a = 1.0 / S->nh;
     if (o->filter_mode == 1 || o->filter_mode == 2) S->a = 0.0;
 
     /* Step 3: H0 = H 2^-N (exact), r0, eg0 = a r0 / (M e^{2||H0||}). */

@@ -88,6 +88,7 @@ class Options:
     norm: int = capi.EXPM_NORM_FRO
     exact_ri: bool = False
     diagnostics: bool = False
+    literal_a: bool = False    # non-normal H: a = 1/||H|| (Algorithm 4.2 step 2) instead of the min
 
 
 class Plan:
@@ -115,6 +116,7 @@ class Plan:
         o.norm = int(self.options.norm)
         o.exact_ri = int(self.options.exact_ri)
         o.diagnostics = int(self.options.diagnostics)
+        o.literal_a = int(self.options.literal_a)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)

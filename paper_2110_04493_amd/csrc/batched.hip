@@ -466,7 +466,7 @@ int batched(expm_plan_s &P, BatchBufs &B, int count, const expm_csr_cview *H, co
             Inst &I = A[k];
             I.normal = nf[k];
             I.a = 1.0 / (I.N + 1);
-            if (!I.normal && 1.0 / I.nh < I.a) I.a = 1.0 / I.nh;
+            if (!I.normal && (P.opts.literal_a || 1.0 / I.nh < I.a)) I.a = 1.0 / I.nh;
             if (P.opts.filter_mode == EXPM_FILTER_NONE) I.a = 0.0;
             const double h0 = ldexp(I.nh, -I.N);
             I.r0 = plan_r0(I.M, h0);

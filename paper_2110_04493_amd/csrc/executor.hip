@@ -839,7 +839,7 @@ int plan_input(expm_plan_s &P, const expm_csr_cview *Hv, double eps, DCsr &dst,
     int normal = P.opts.normal;
     if (normal < 0) CHK(detect_normal(P, dst, nf, &normal));
     double a = 1.0 / (N + 1);
-    if (!normal && 1.0 / nh < a) a = 1.0 / nh;
+    if (!normal && (P.opts.literal_a || 1.0 / nh < a)) a = 1.0 / nh;
     if (P.opts.filter_mode != EXPM_FILTER_PAPER) a = 0.0;
     A->M = M;
     A->N = N;
@@ -1487,6 +1487,7 @@ void expm_opts_default(expm_opts *o) {
     o->norm = EXPM_NORM_FRO;
     o->exact_ri = 0;
     o->diagnostics = 0;
+    o->literal_a = 0;
 }
 
 int expm_plan(expm_plan_t *out, const expm_opts *opts) {
@@ -1503,7 +1504,8 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
         return fail(EXPM_EINVAL, "unknown filter_mode %d", o.filter_mode);
     if (o.norm != EXPM_NORM_FRO && o.norm != EXPM_NORM_ONE)
         return fail(EXPM_EINVAL, "unknown norm %d", o.norm);
-    if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1)
+    if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1 ||
+        o.literal_a < 0 || o.literal_a > 1)
         return fail(EXPM_EINVAL, "invalid option value");
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
         o.checkpoint_interval < -1 || o.reorder < -1 || o.reorder > 2 || o.profile < 0 ||

@@ -327,3 +327,36 @@ def perm_plus_identity(n: int, c: float, s: float, seed: int) -> Csr:
     i = np.arange(n, dtype=np.int64)
     return csr_from_coo(n, np.concatenate([i, i]), np.concatenate([i, q]),
                         np.concatenate([np.full(n, c), np.full(n, s)]))
+
+
+def structural_hamiltonian(rows: int, cols: int, dt: float, alpha: float = 0.0,
+                           beta: float = 0.0, seed: int = 0, sigma: float = 0.3,
+                           ground: float = 0.05) -> tuple[Csr, np.ndarray, np.ndarray]:
+    """H = dt * Theta of Eq. (2.1) for a lumped mass-spring grid: masses m_i
+    ~ lognormal(0, sigma) at the nodes of a rows x cols 5-point grid,
+    springs of stiffness ~ lognormal(0, sigma) along its edges, and a
+    grounding spring of stiffness ``ground`` at every node (so that K is
+    positive definite).  Damping is Rayleigh's, C = alpha M + beta K.  The
+    state is U = (a, v) (displacements, then velocities), so
+        Theta = [[0, I], [-M^{-1} K, -M^{-1} C]],  n = 2 rows cols,
+    and H is not normal.  Returns (H, m, K as a dense-free Csr of order
+    rows cols): the masses and stiffness that define the energy norm
+    U^T diag(K, M) U, which e^H preserves without damping and does not
+    increase with it."""
+    rng = np.random.default_rng(seed)
+    m = rows * cols
+    mass = rng.lognormal(0.0, sigma, m)
+    e = grid_edges(rows, cols)
+    K = laplacian_from_edges(m, e, rng.lognormal(0.0, sigma, len(e)))
+    kd = K.val.copy()
+    rr = np.repeat(np.arange(m, dtype=np.int64), np.diff(K.rowptr))
+    kd[rr == K.col] += ground
+    K = Csr(m, K.rowptr.copy(), K.col.copy(), kd)
+    mk = kd / mass[rr]                        # M^{-1} K, row by row
+    ident = np.arange(m, dtype=np.int64)
+    r = np.concatenate([ident, m + rr, m + rr, m + ident])
+    c = np.concatenate([m + ident, K.col.astype(np.int64), m + K.col.astype(np.int64), m + ident])
+    v = np.concatenate([np.ones(m), -mk, -beta * mk, np.full(m, -alpha)])
+    keep = v != 0.0
+    H = csr_from_coo(2 * m, r[keep], c[keep], v[keep] * dt, sum_duplicates=True)
+    return H, mass, K

@@ -24,7 +24,7 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 def check_parity(H, eps, count_tol=0.002, **kw):
     print(f"[parity] n={H.n} nnz={H.nnz} eps={eps} {H.meta.get('name', '')} {kw}", flush=True)
     Eg, sg = run_gpu(H, eps, **kw)
-    okw = {k: kw[k] for k in ("filter_mode", "normal", "norm", "exact_ri") if k in kw}
+    okw = {k: kw[k] for k in ("filter_mode", "normal", "norm", "exact_ri", "literal_a") if k in kw}
     Eo, so = run_oracle(H, eps, **okw)
     rel, supp_ok, og, oo = compare(Eg, Eo, final_theta(so))
     print(f"  relF={rel:.3e} only_gpu={og} only_oracle={oo} M,N={sg['M']},{sg['N']} "

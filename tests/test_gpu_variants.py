@@ -337,3 +337,24 @@ def test_level_ordering_forced_on_grid():
     assert rel <= TOL and ok
     _, s1 = run_gpu(H, 1e-12)
     assert s1["ordering"] == 1
+
+
+# ------------------------------------------------ structural Hamiltonian, literal a
+
+@pytest.mark.parametrize("side,dt,literal", [(40, 0.5, False), (40, 0.5, True), (100, 0.5, False)])
+def test_structural_hamiltonian(side, dt, literal):
+    """H = dt Theta of Eq. (2.1) for a damped mass-spring grid (n = 2 side^2,
+    non-normal), with both readings of the filter constant."""
+    H, _, _ = W.structural_hamiltonian(side, side, dt, alpha=0.02, beta=0.01, seed=3)
+    _, sg, _, so = check_parity(H, 1e-12, literal_a=literal)
+    assert sg["normal"] == 0 and abs(sg["a"] - so["a"]) <= 1e-14 * so["a"]
+
+
+def test_literal_a_small_norm():
+    """||H||_F = 2.5: 1/||H|| exceeds 1/(N+1), so the literal reading sets a
+    larger filter constant; both runs agree with the oracle."""
+    H, _, _ = W.structural_hamiltonian(12, 12, 1.0, alpha=0.05, beta=0.01, seed=13)
+    H = H.scaled(2.5 / np.linalg.norm(H.val))
+    _, s0, _, _ = check_parity(H, 1e-12, literal_a=False)
+    _, s1, _, _ = check_parity(H, 1e-12, literal_a=True)
+    assert s1["a"] > s0["a"] and abs(s1["a"] * s1["norm_h"] - 1.0) <= 1e-14
