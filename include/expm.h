@@ -250,6 +250,21 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts);
  * EXPM_ENOMEM, EXPM_EHIP. */
 int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E);
 
+/* Algorithm 4.2 for a complex H: the paper states the method for H in
+ * C^{n x n} (section 4).  H->val points at 2 nnz doubles, the real and the
+ * imaginary part of each entry in turn (the layout of C99 double _Complex
+ * and std::complex<double>), and E->val receives 2 nnz(E) doubles the same
+ * way.  The steps are those of expm_sparse with complex arithmetic: the
+ * normality test of step 2 compares H H^* with H^* H (an exactly Hermitian
+ * or skew-Hermitian H is normal), and Algorithm 4.1 filters by the modulus
+ * |z| = sqrt(re^2 + im^2), summing |z|^2 over the dropped entries.  Every
+ * product runs on scalar rows (no locality reordering and no tile path).
+ * Options as for expm_sparse, except: filter_mode EXPM_FILTER_FIXED_REL and
+ * norm EXPM_NORM_ONE give EXPM_ENOTIMPL, and no adjoint is kept (a later
+ * expm_sparse_backward returns EXPM_ESTATE).  Statistics as for expm_sparse.
+ * Errors: those of expm_sparse, EXPM_ENOTIMPL. */
+int expm_sparse_z(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E);
+
 /* Adjoint of the last expm_sparse call on p (which must have run with
  * keep_checkpoints = 1): given dL/dE aligned with the stored entries of that
  * E (device double[nnz(E)]), writes dL/dH aligned with the stored entries of

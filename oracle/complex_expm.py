@@ -20,11 +20,11 @@ in ``oracle_expm.c``, with complex entries:
            set of a threshold theta is {|z| <= theta}, its norm is
            sqrt(sum |z|^2) over that set.
 
-A sparse product is scipy's CSR product (a library primitive); its
-structural pattern (every (i, j) reached by some a_ik b_kj, also where the
-values cancel) is taken from a second product of the patterns, so that a
-candidate keeps its exact zeros until the filter removes them, as in the
-real oracle.  Sums run in scipy's order; nothing else is fused or reordered.
+A sparse product is formed from four real products of the real oracle
+(each keeps the structural pattern: every (i, j) reached by some
+a_ik b_kj, also where the values cancel), so that a candidate keeps its
+exact zeros until the filter removes them, as in the real oracle; sums of
+matrices are scipy's.  Nothing else is fused or reordered.
 
 Parity status: pinned by tests/test_oracle_complex.py (the real oracle on
 real inputs, closed forms of e^{-itL} from a symmetric eigensolver,
@@ -36,6 +36,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import Result, choose_mn, r0, OracleError, EINVAL, ENOTCONV, ERANGE
+from . import matmul as _real_matmul
 
 MAXSTEP = 256
 
@@ -76,8 +77,30 @@ def _aligned(C: sp.csr_matrix, pattern: sp.csr_matrix) -> sp.csr_matrix:
 
 
 def matmul(A: sp.csr_matrix, B: sp.csr_matrix) -> sp.csr_matrix:
-    """A B with its full structural pattern (exact zeros stored)."""
-    return _aligned(A @ B, _pattern(A) @ _pattern(B))
+    """A B with its full structural pattern (exact zeros stored), from four
+    real products by the real oracle's sparse product (which keeps the
+    structural pattern): (Ar + i Ai)(Br + i Bi) = (Ar Br - Ai Bi) +
+    i (Ar Bi + Ai Br).  The real and imaginary parts of a matrix share its
+    pattern (explicit zeros kept), so the four products share the pattern
+    of A B."""
+    n = A.shape[0]
+    def part(X, f):
+        return (X.indptr.astype(np.int64), X.indices.astype(np.int32),
+                np.ascontiguousarray(f(X.data)))
+    re = lambda x: x.real
+    im = lambda x: x.imag
+    rr = _real_matmul(n, part(A, re), part(B, re))
+    ii = _real_matmul(n, part(A, im), part(B, im))
+    ri = _real_matmul(n, part(A, re), part(B, im))
+    ir = _real_matmul(n, part(A, im), part(B, re))
+    for x in (ii, ri, ir):
+        assert np.array_equal(x[0], rr[0]) and np.array_equal(x[1], rr[1])
+    v = np.empty(rr[2].size, np.complex128)
+    v.real = rr[2] - ii[2]
+    v.imag = ri[2] + ir[2]
+    out = sp.csr_matrix((v, rr[1].astype(np.int64), rr[0]), shape=A.shape)
+    out.has_sorted_indices = True
+    return out
 
 
 def add(alpha, A: sp.csr_matrix, beta, B: sp.csr_matrix, drop_zeros: bool) -> sp.csr_matrix:
@@ -207,6 +230,11 @@ def expm(rowptr, col, val, eps: float, *, normal: int = -1, filter_mode: int = 0
         terms = i
         T = add(1.0, T, 1.0, S, True)                          # T0 += S_i
     st["taylor_terms"] = terms
+    # per-term lists for i = 2 .. terms + 1, as the real oracle reports them
+    # (the term after the last one is zero when it was never formed)
+    for k, z in (("taylor_cand", 0), ("taylor_theta", 0.0), ("taylor_iters", 0),
+                 ("taylor_kept", 0)):
+        st[k] = (st[k] + [z] * terms)[:terms]
     ri = rr0                                                   # step 4
     for i in range(1, N + 1):
         Tt = add(2.0, T, 1.0, matmul(T, T), False)

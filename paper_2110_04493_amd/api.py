@@ -63,12 +63,12 @@ def _view(crow: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> capi.expm
     return capi.expm_csr_cview(n, val.numel(), crow.data_ptr(), col.data_ptr(), val.data_ptr())
 
 
-def _check_inputs(crow, col, val):
+def _check_inputs(crow, col, val, vdtype=torch.float64):
     dev = val.device
     if dev.type != "cuda":
         raise ValueError("the gfx950 library takes device tensors (no CPU path)")
-    if crow.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float64:
-        raise TypeError("expects int64 row pointers, int32 columns and float64 values")
+    if crow.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != vdtype:
+        raise TypeError(f"expects int64 row pointers, int32 columns and {vdtype} values")
     for t in (crow, col, val):
         if not t.is_contiguous() or t.device != dev:
             raise ValueError("inputs must be contiguous tensors on one device")
@@ -136,14 +136,14 @@ class Plan:
         if cur != self.stream:
             cur.wait_stream(self.stream)
 
-    def _take(self, E: capi.expm_csr):
+    def _take(self, E: capi.expm_csr, vdtype=torch.float64):
         self._handover()
         n = E.n
         rp = self.alloc.take(E.rowptr, n + 1, torch.int64)
         ci = self.alloc.take(E.col, E.nnz, torch.int32) if E.col else \
             torch.empty(0, dtype=torch.int32, device=self.device)
-        v = self.alloc.take(E.val, E.nnz, torch.float64) if E.val else \
-            torch.empty(0, dtype=torch.float64, device=self.device)
+        v = self.alloc.take(E.val, E.nnz, vdtype) if E.val else \
+            torch.empty(0, dtype=vdtype, device=self.device)
         capi.expm_csr_release(self.handle, E)
         return rp, ci, v
 
@@ -154,6 +154,15 @@ class Plan:
             self._inputs_ready()
             E = capi.expm_sparse(self.handle, _view(crow, col, val), eps)
             return self._take(E)
+
+    def expm_z(self, crow, col, val, eps: float):
+        """E = e^H for complex H (complex128 values), as (rowptr int64, col
+        int32, val complex128) device tensors."""
+        _check_inputs(crow, col, val, torch.complex128)
+        with torch.cuda.device(self.device):
+            self._inputs_ready()
+            E = capi.expm_sparse_z(self.handle, _view(crow, col, val), eps)
+            return self._take(E, torch.complex128)
 
     def backward(self, dE: torch.Tensor, nnz_h: int) -> torch.Tensor:
         dE = dE.contiguous().to(torch.float64)

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexpm_gfx950.so")
 ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 SOURCES = ["kernels.hip", "spgemm.hip", "bsr.hip", "bsr_adjoint.hip", "bsr_host.hip", "executor.hip",
-           "batched.hip", "reorder.hip", "extras.hip"]
+           "batched.hip", "reorder.hip", "extras.hip", "complex.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -36,7 +36,8 @@ ERROR_NAMES = {0: "EXPM_OK", -1: "EXPM_EINVAL", -2: "EXPM_ENOMEM", -3: "EXPM_EHI
 SYMBOLS = ["expm_opts_default", "expm_plan", "expm_sparse", "expm_sparse_backward",
            "expm_sparse_batched", "expm_get_stats", "expm_csr_release", "expm_free",
            "expm_last_error", "expm_r0", "expm_choose_mn", "expm_sparse_noalloc",
-           "expm_analyze", "expm_spmm", "expm_propagate", "expm_power_norms", "expm_alpha_hat"]
+           "expm_analyze", "expm_spmm", "expm_propagate", "expm_power_norms", "expm_alpha_hat",
+           "expm_sparse_z"]
 
 # bytes of the static device array behind expm_sparse_noalloc (expm.h)
 NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -148,6 +149,8 @@ def lib():
         L.expm_opts_default.restype = None
         L.expm_plan.argtypes = [C.POINTER(_P), C.POINTER(expm_opts)]
         L.expm_sparse.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_double, C.POINTER(expm_csr)]
+        L.expm_sparse_z.argtypes = [_P, C.POINTER(expm_csr_cview), C.c_double,
+                                    C.POINTER(expm_csr)]
         L.expm_sparse_backward.argtypes = [_P, _P, _P]
         L.expm_sparse_batched.argtypes = [_P, C.c_int, C.POINTER(expm_csr_cview),
                                           C.POINTER(C.c_double), C.POINTER(expm_csr)]
@@ -156,6 +159,7 @@ def lib():
         L.expm_csr_release.restype = None
         L.expm_free.argtypes = [_P]
         L.expm_free.restype = None
+        L.expm_last_error.argtypes = []
         L.expm_last_error.restype = C.c_char_p
         L.expm_r0.argtypes = [C.c_int, C.c_double]
         L.expm_r0.restype = C.c_double
@@ -200,6 +204,13 @@ def expm_plan(opts: expm_opts) -> int:
 def expm_sparse(plan: int, H: expm_csr_cview, eps: float) -> expm_csr:
     E = expm_csr()
     check(lib().expm_sparse(_P(plan), C.byref(H), float(eps), C.byref(E)), "expm_sparse")
+    return E
+
+
+def expm_sparse_z(plan: int, H: expm_csr_cview, eps: float) -> expm_csr:
+    """Complex H (val: nnz (real, imaginary) pairs of doubles)."""
+    E = expm_csr()
+    check(lib().expm_sparse_z(_P(plan), C.byref(H), float(eps), C.byref(E)), "expm_sparse_z")
     return E
 
 

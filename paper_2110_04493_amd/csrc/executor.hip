@@ -26,6 +26,13 @@ namespace host {
 
 thread_local std::string g_err;
 
+// write_kept without the batched arguments (the signature of write_kept_z)
+static hipError_t write_kept_real(const int64_t *crp, const int32_t *cci, const double *cv,
+                                  int64_t n, const FilterCtl *c, int addI, const int64_t *orp,
+                                  int32_t *oci, double *ov, hipStream_t st) {
+    return write_kept(crp, cci, cv, n, c, addI, orp, oci, ov, st);
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
         .count();
@@ -192,10 +199,10 @@ void release(expm_plan_s &P, DCsr &A) {
     A.n = A.nnz = 0;
 }
 
-int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz) {
+int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz, int vw) {
     CHK(ensure(P, A.rp, sizeof(int64_t) * (n + 1)));
     CHK(ensure(P, A.ci, sizeof(int32_t) * nnz));
-    CHK(ensure(P, A.v, sizeof(double) * nnz));
+    CHK(ensure(P, A.v, sizeof(double) * vw * nnz));
     A.n = n;
     A.nnz = nnz;
     return EXPM_OK;
@@ -203,15 +210,15 @@ int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz) {
 
 // Copy of a device CSR (checkpoints, Taylor terms) into dst's buffers,
 // grown when too small.
-int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src) {
-    CHK(ensure_csr(P, dst, src.n, src.nnz));
+int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src, int vw) {
+    CHK(ensure_csr(P, dst, src.n, src.nnz, vw));
     HIPCHK(hipMemcpyAsync(dst.rp.p, src.rp.p, sizeof(int64_t) * (src.n + 1),
                           hipMemcpyDeviceToDevice, P.st));
     if (src.nnz) {
         HIPCHK(hipMemcpyAsync(dst.ci.p, src.ci.p, sizeof(int32_t) * src.nnz,
                               hipMemcpyDeviceToDevice, P.st));
-        HIPCHK(hipMemcpyAsync(dst.v.p, src.v.p, sizeof(double) * src.nnz, hipMemcpyDeviceToDevice,
-                              P.st));
+        HIPCHK(hipMemcpyAsync(dst.v.p, src.v.p, sizeof(double) * vw * src.nnz,
+                              hipMemcpyDeviceToDevice, P.st));
     }
     return EXPM_OK;
 }
@@ -269,7 +276,7 @@ void out_free(expm_plan_s &P, void *p) {
 }
 
 int alloc_output(expm_plan_s &P, int64_t n, int64_t nnz, int64_t **rp, int32_t **ci,
-                 double **v) {
+                 double **v, int vw) {
     if (P.arena) {
         P.na_need = nnz;
         if (nnz > P.na_cap)
@@ -282,7 +289,7 @@ int alloc_output(expm_plan_s &P, int64_t n, int64_t nnz, int64_t **rp, int32_t *
     }
     *rp = (int64_t *)out_alloc(P, sizeof(int64_t) * (n + 1));
     *ci = (int32_t *)out_alloc(P, sizeof(int32_t) * nnz);
-    *v = (double *)out_alloc(P, sizeof(double) * nnz);
+    *v = (double *)out_alloc(P, sizeof(double) * vw * nnz);
     if (!*rp || !*ci || !*v) {
         out_free(P, *rp);
         out_free(P, *ci);
@@ -344,7 +351,7 @@ int plan_mn(double nh, double eps, int *Mo, int *No) {
 // (P.crp, P.cci, P.cv).  Returns the candidate total in *total; with rowsq
 // the per-row sums of (c + delta)^2 are left in P.rowsq.
 int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, double div, bool rowsq,
-           int64_t *total) {
+           int64_t *total, bool cplx) {
     const int64_t n = A.n;
     hipStream_t st = P.st;
     CHK(ensure(P, P.lo, sizeof(int32_t) * n));
@@ -376,9 +383,9 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
     HIPCHK(symbolic(A, B, alphaA != 0.0, (const int32_t *)P.lo.p, woff, (uint32_t *)P.bitmaps.p,
                     cnt, symc, (const int32_t *)P.lists.p, n, st));
     CHK(scan(P, cnt, crp, n));
-    HIPCHK(numeric_scratch_sizes(woff, crp, n, (int64_t *)P.sbytes.p, st));
+    HIPCHK(numeric_scratch_sizes(woff, crp, n, (int64_t *)P.sbytes.p, st, cplx));
     CHK(scan(P, (const int64_t *)P.sbytes.p, (int64_t *)P.soff.p, n));
-    HIPCHK(bin_rows(woff, crp, n, 1, (int *)P.counts.p, (int32_t *)P.lists.p, st));
+    HIPCHK(bin_rows(woff, crp, n, cplx ? 2 : 1, (int *)P.counts.p, (int32_t *)P.lists.p, st));
     if (prof) {
         // partial products = sum of ub minus the rows of the alphaA*A term
         CHK(ensure(P, P.tmp1, sizeof(int64_t) * (n + 1)));
@@ -396,7 +403,7 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
     int numc[kNumClasses];
     memcpy(numc, hl + 2, sizeof numc);
     CHK(ensure(P, P.cci, sizeof(int32_t) * cand));
-    CHK(ensure(P, P.cv, sizeof(double) * cand));
+    CHK(ensure(P, P.cv, sizeof(double) * (cplx ? 2 : 1) * cand));
     if (gscratch) CHK(ensure(P, P.scratch, (size_t)gscratch));
     if (rowsq) CHK(ensure(P, P.rowsq, sizeof(double) * (n + 1)));
     if (prof) {
@@ -405,10 +412,11 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
         P.last_fma = alphaA != 0.0 ? ubt - nnzA : ubt;
         HIPCHK(hipEventRecord(P.ev[1], st));
     }
-    HIPCHK(numeric(A, B, alphaA, div, (const int32_t *)P.lo.p, woff,
-                   (const uint32_t *)P.bitmaps.p, crp, (int32_t *)P.cci.p, (double *)P.cv.p,
-                   rowsq ? (double *)P.rowsq.p : nullptr, numc, (const int32_t *)P.lists.p, n,
-                   P.scratch.p, (const int64_t *)P.soff.p, st));
+    HIPCHK((cplx ? numeric_z : numeric)(A, B, alphaA, div, (const int32_t *)P.lo.p, woff,
+                                        (const uint32_t *)P.bitmaps.p, crp, (int32_t *)P.cci.p,
+                                        (double *)P.cv.p, rowsq ? (double *)P.rowsq.p : nullptr,
+                                        numc, (const int32_t *)P.lists.p, n, P.scratch.p,
+                                        (const int64_t *)P.soff.p, st));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     *total = cand;
     return EXPM_OK;
@@ -421,7 +429,7 @@ int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, do
 // (or -1 to keep everything) skips the search.
 int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
                      const double *norm2, bool use_fixed, double theta_fixed, bool addI,
-                     FilterCtl *hctl, int64_t *kept) {
+                     FilterCtl *hctl, int64_t *kept, bool cplx) {
     hipStream_t st = P.st;
     CHK(ensure(P, P.ctl, sizeof(FilterCtl)));
     CHK(ensure(P, P.part, sizeof(double) * kParts));
@@ -436,11 +444,15 @@ int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
     for (int round = 0;; ++round) {
         if (!use_fixed) {
             for (int j = 0; j < 4; ++j)
-                HIPCHK(filter_pass((const double *)P.cv.p, crp + n, cand, ctl, (double *)P.part.p,
-                                   kParts, st));
+                HIPCHK((cplx ? filter_pass_z : filter_pass)((const double *)P.cv.p, crp + n, cand,
+                                                            ctl, (double *)P.part.p, kParts, st));
         }
-        HIPCHK(count_kept(crp, (const int32_t *)P.cci.p, (const double *)P.cv.p, n, ctl,
-                          addI ? 1 : 0, (int64_t *)P.cnt.p, st));
+        if (cplx)
+            HIPCHK(count_kept_z(crp, (const int32_t *)P.cci.p, (const double *)P.cv.p, n, ctl,
+                                addI ? 1 : 0, (int64_t *)P.cnt.p, st));
+        else
+            HIPCHK(count_kept(crp, (const int32_t *)P.cci.p, (const double *)P.cv.p, n, ctl,
+                              addI ? 1 : 0, (int64_t *)P.cnt.p, st));
         CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
         HIPCHK(hipMemcpyAsync(P.host, ctl, sizeof(FilterCtl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync((char *)P.host + 256, (int64_t *)P.krp.p + n, sizeof(int64_t),
@@ -461,14 +473,15 @@ int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
 // Writes the kept candidate entries (rows from P.krp) into dst (capacity
 // must hold `kept` entries; dst.rp receives P.krp).
 int write_filtered(expm_plan_s &P, int64_t n, DCsr &dst, int64_t kept, bool addI,
-                   bool exact_alloc) {
+                   bool exact_alloc, bool cplx) {
     if (exact_alloc) release(P, dst);
-    CHK(ensure_csr(P, dst, n, kept));
+    CHK(ensure_csr(P, dst, n, kept, cplx ? 2 : 1));
     HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
                           P.st));
-    HIPCHK(write_kept((const int64_t *)P.crp.p, (const int32_t *)P.cci.p, (const double *)P.cv.p,
-                      n, (const FilterCtl *)P.ctl.p, addI ? 1 : 0, (const int64_t *)dst.rp.p,
-                      (int32_t *)dst.ci.p, (double *)dst.v.p, P.st));
+    HIPCHK((cplx ? write_kept_z : write_kept_real)(
+        (const int64_t *)P.crp.p, (const int32_t *)P.cci.p, (const double *)P.cv.p, n,
+        (const FilterCtl *)P.ctl.p, addI ? 1 : 0, (const int64_t *)dst.rp.p, (int32_t *)dst.ci.p,
+        (double *)dst.v.p, P.st));
     return EXPM_OK;
 }
 
@@ -1467,6 +1480,31 @@ int scratch_address(void **out) {
 }
 }  // namespace
 
+// EXPM_LOG=1 in the environment: one line per expm_sparse call on stderr
+// with the plan of steps 1-3 and, per squaring, the kept entries, the
+// threshold and the filter passes.
+void xpm::host::log_call(const expm_plan_s &P, int64_t n, double eps, int status) {
+    static const bool on = [] {
+        const char *e = getenv("EXPM_LOG");
+        return e && atoi(e) > 0;
+    }();
+    if (!on) return;
+    const expm_stats &S = P.stats;
+    std::string line;
+    char buf[160];
+    snprintf(buf, sizeof buf, "expm: n=%lld eps=%.3g status=%d M=%d N=%d normal=%d a=%.4g "
+             "||H||=%.6g taylor_terms=%d nnz(E)=%lld", (long long)n, eps, status, S.M, S.N,
+             S.normal, S.a, S.norm_h, S.taylor_terms, (long long)S.nnz_e);
+    line += buf;
+    for (int i = 1; i <= S.squarings && i < EXPM_MAXSTEP; ++i) {
+        snprintf(buf, sizeof buf, " | %d: kept=%lld theta=%.3g iters=%d%s", i,
+                 (long long)S.sq_kept[i], S.sq_theta[i], S.sq_iters[i],
+                 S.sq_tiles[i] ? " tiles" : "");
+        line += buf;
+    }
+    fprintf(stderr, "%s\n", line.c_str());
+}
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -1553,30 +1591,6 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     return EXPM_OK;
 }
 
-// EXPM_LOG=1 in the environment: one line per expm_sparse call on stderr
-// with the plan of steps 1-3 and, per squaring, the kept entries, the
-// threshold and the filter passes.
-static void log_call(const expm_plan_s &P, int64_t n, double eps, int status) {
-    static const bool on = [] {
-        const char *e = getenv("EXPM_LOG");
-        return e && atoi(e) > 0;
-    }();
-    if (!on) return;
-    const expm_stats &S = P.stats;
-    std::string line;
-    char buf[160];
-    snprintf(buf, sizeof buf, "expm: n=%lld eps=%.3g status=%d M=%d N=%d normal=%d a=%.4g "
-             "||H||=%.6g taylor_terms=%d nnz(E)=%lld", (long long)n, eps, status, S.M, S.N,
-             S.normal, S.a, S.norm_h, S.taylor_terms, (long long)S.nnz_e);
-    line += buf;
-    for (int i = 1; i <= S.squarings && i < EXPM_MAXSTEP; ++i) {
-        snprintf(buf, sizeof buf, " | %d: kept=%lld theta=%.3g iters=%d%s", i,
-                 (long long)S.sq_kept[i], S.sq_theta[i], S.sq_iters[i],
-                 S.sq_tiles[i] ? " tiles" : "");
-        line += buf;
-    }
-    fprintf(stderr, "%s\n", line.c_str());
-}
 
 int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E) {
     g_err.clear();

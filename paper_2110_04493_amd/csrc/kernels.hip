@@ -1068,3 +1068,278 @@ hipError_t transpose_index(CsrView A, int64_t nnz, int64_t *trp, int32_t *tci, i
 }
 
 }  // namespace xpm
+
+namespace xpm {
+
+// ============================================================== complex values
+// A complex entry is a double2 (real, imaginary).  Its modulus is
+// sqrt(re^2 + im^2) with each product and the sum rounded once (no fused
+// multiply-add), and Algorithm 4.1 sums the squared moduli of the dropped
+// entries.
+
+__device__ __forceinline__ double mod2_z(double2 z) {
+#pragma clang fp contract(off)
+    return z.x * z.x + z.y * z.y;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_filter_pass_z(const double2 *__restrict__ v,
+                                                             const int64_t *count,
+                                                             int64_t maxcount, FilterCtl *c,
+                                                             double *part) {
+    if (c->done) return;
+    const double theta = c->theta;
+    const int64_t m = count ? *count : maxcount;
+    double s = 0.0;
+    int64_t stride = (int64_t)gridDim.x * kRedBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; j < m; j += stride) {
+        const double q = mod2_z(v[j]);
+        if (sqrt(q) <= theta) s += q;
+    }
+    filter_pass_end(s, theta, c, part);
+}
+
+hipError_t filter_pass_z(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
+                         double *part, int nparts, hipStream_t st) {
+    nparts = parts_for(maxcount, nparts);
+    hipLaunchKernelGGL(k_filter_pass_z, dim3(nparts), dim3(kRedBlock), 0, st, (const double2 *)v,
+                       count, maxcount, c, part);
+    return hipGetLastError();
+}
+
+// Kept entries (|z| > theta) per row; with addI the diagonal becomes 1 + z
+// (dropped if exactly 0) or is inserted as 1.
+__global__ void k_count_kept_z(const int64_t *crp, const int32_t *cci, const double2 *cv,
+                               int64_t n, const FilterCtl *c, int addI, int64_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const double theta = c->theta;
+    long long k = 0;
+    int dstate = 0;   // 0 absent/dropped, 1 kept, 2 kept but 1 + z == 0
+    for (int64_t p = crp[i] + lane_id(); p < crp[i + 1]; p += kWave) {
+        const double2 x = cv[p];
+        const bool keep = sqrt(mod2_z(x)) > theta;
+        k += keep;
+        if (addI && cci[p] == i && keep) dstate = (x.x + 1.0 == 0.0 && x.y == 0.0) ? 2 : 1;
+    }
+    k = wave_sum_ll(k);
+    if (addI) dstate = wave_max(dstate);
+    if (lane_id() == 0) cnt[i] = k + (addI ? (dstate == 0 ? 1 : (dstate == 2 ? -1 : 0)) : 0);
+}
+
+__global__ void k_write_kept_z(const int64_t *crp, const int32_t *cci, const double2 *cv,
+                               int64_t n, const FilterCtl *c, int addI, const int64_t *orp,
+                               int32_t *oci, double2 *ov) {
+    int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const double theta = c->theta;
+    const int64_t b = crp[i], e = crp[i + 1];
+    int dstate = 0;
+    if (addI) {
+        for (int64_t p = b + lane_id(); p < e; p += kWave) {
+            const double2 x = cv[p];
+            if (cci[p] == i && sqrt(mod2_z(x)) > theta)
+                dstate = (x.x + 1.0 == 0.0 && x.y == 0.0) ? 2 : 1;
+        }
+        dstate = wave_max(dstate);
+    }
+    const bool insert = addI && dstate == 0;
+    const int64_t out = orp[i];
+    int64_t written = 0;
+    bool inserted = false;
+    for (int64_t p0 = b; p0 < e; p0 += kWave) {
+        const int64_t p = p0 + lane_id();
+        const bool valid = p < e;
+        const int col = valid ? cci[p] : 0;
+        double2 x = valid ? cv[p] : make_double2(0.0, 0.0);
+        bool keep = valid && sqrt(mod2_z(x)) > theta;
+        if (addI && keep && col == i) {
+            x.x += 1.0;
+            if (x.x == 0.0 && x.y == 0.0) keep = false;
+        }
+        if (insert && !inserted) {
+            // the identity entry goes before the first column > i
+            const unsigned long long after = __ballot(valid && col > i);
+            const unsigned long long pre = __ballot(keep && col < i);
+            if (after) {
+                const int64_t pos = written + __popcll(pre);
+                if (lane_id() == 0) {
+                    oci[out + pos] = (int32_t)i;
+                    ov[out + pos] = make_double2(1.0, 0.0);
+                }
+                inserted = true;
+                const unsigned long long km = __ballot(keep);
+                const int64_t my = written + __popcll(km & lanemask_lt()) + (col > i ? 1 : 0);
+                if (keep) {
+                    oci[out + my] = col;
+                    ov[out + my] = x;
+                }
+                written += __popcll(km) + 1;
+                continue;
+            }
+        }
+        const unsigned long long km = __ballot(keep);
+        const int64_t my = written + __popcll(km & lanemask_lt());
+        if (keep) {
+            oci[out + my] = col;
+            ov[out + my] = x;
+        }
+        written += __popcll(km);
+    }
+    if (insert && !inserted && lane_id() == 0) {
+        oci[out + written] = (int32_t)i;
+        ov[out + written] = make_double2(1.0, 0.0);
+    }
+}
+
+hipError_t count_kept_z(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                        const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int wpb = 4;
+    hipLaunchKernelGGL(k_count_kept_z, dim3((n + wpb - 1) / wpb), dim3(wpb * kWave), 0, st, crp,
+                       cci, (const double2 *)cv, n, c, addI, cnt);
+    return hipGetLastError();
+}
+
+hipError_t write_kept_z(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                        const FilterCtl *c, int addI, const int64_t *orp, int32_t *oci,
+                        double *ov, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int wpb = 4;
+    hipLaunchKernelGGL(k_write_kept_z, dim3((n + wpb - 1) / wpb), dim3(wpb * kWave), 0, st, crp,
+                       cci, (const double2 *)cv, n, c, addI, orp, oci, (double2 *)ov);
+    return hipGetLastError();
+}
+
+// C = A + B (complex values), exact zeros dropped; one thread per row.
+__global__ void k_add_z(CsrView A, CsrView B, int64_t *cnt, const int64_t *crp, int32_t *cci,
+                        double2 *cv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const double2 *av = (const double2 *)A.v, *bv = (const double2 *)B.v;
+    int64_t p = A.rp[i], pe = A.rp[i + 1], q = B.rp[i], qe = B.rp[i + 1];
+    const int64_t o = crp ? crp[i] : 0;
+    int64_t k = 0;
+    while (p < pe || q < qe) {
+        const int ja = p < pe ? A.ci[p] : INT32_MAX;
+        const int jb = q < qe ? B.ci[q] : INT32_MAX;
+        int j;
+        double2 s;
+        if (ja == jb) {
+            j = ja;
+            s = make_double2(av[p].x + bv[q].x, av[p].y + bv[q].y);
+            ++p;
+            ++q;
+        } else if (ja < jb) {
+            j = ja;
+            s = av[p++];
+        } else {
+            j = jb;
+            s = bv[q++];
+        }
+        if (s.x == 0.0 && s.y == 0.0) continue;
+        if (crp) {
+            cci[o + k] = j;
+            cv[o + k] = s;
+        }
+        k++;
+    }
+    if (!crp) cnt[i] = k;
+}
+
+hipError_t add_count_z(CsrView A, CsrView B, int64_t *cnt, hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_z, dim3((A.n + 127) / 128), dim3(128), 0, st, A, B, cnt,
+                       (const int64_t *)nullptr, (int32_t *)nullptr, (double2 *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t add_write_z(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, double *cv,
+                       hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_z, dim3((A.n + 127) / 128), dim3(128), 0, st, A, B,
+                       (int64_t *)nullptr, crp, cci, (double2 *)cv);
+    return hipGetLastError();
+}
+
+// flags[0] = 1 if pattern(A) == pattern(B); flags[1] = values equal;
+// flags[2] = values negated (complex values, nnz entries).
+__global__ void k_compare_z(CsrView A, CsrView B, int64_t nnz, int *flags) {
+    bool pat = false, eq = true, neg = true;
+    const double2 *av = (const double2 *)A.v, *bv = (const double2 *)B.v;
+    const int64_t m = nnz > A.n + 1 ? nnz : A.n + 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+        if (j <= A.n && A.rp[j] != B.rp[j]) pat = true;
+        if (j < nnz) {
+            if (A.ci[j] != B.ci[j]) pat = true;
+            const double2 a = av[j], b = bv[j];
+            if (a.x != b.x || a.y != b.y) eq = false;
+            if (a.x != -b.x || a.y != -b.y) neg = false;
+        }
+    }
+    const unsigned long long bp = __ballot(pat), be = __ballot(!eq), bn = __ballot(!neg);
+    if (lane_id() == 0) {
+        if (bp) atomicAnd(&flags[0], 0);
+        if (be) atomicAnd(&flags[1], 0);
+        if (bn) atomicAnd(&flags[2], 0);
+    }
+}
+
+hipError_t compare_csr_z(CsrView A, CsrView B, int64_t nnz, int *flags, hipStream_t st) {
+    const int64_t m = nnz > A.n + 1 ? nnz : A.n + 1;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_compare_z, dim3((unsigned)blocks), dim3(256), 0, st, A, B, nnz, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_identity_z(int64_t n, int64_t *rp, int32_t *ci, double2 *v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) rp[i] = i;
+    if (i < n) {
+        ci[i] = (int32_t)i;
+        v[i] = make_double2(1.0, 0.0);
+    }
+}
+
+hipError_t fill_identity_z(int64_t n, int64_t *rp, int32_t *ci, double *v, hipStream_t st) {
+    hipLaunchKernelGGL(k_identity_z, dim3((n + 256) / 256), dim3(256), 0, st, n, rp, ci,
+                       (double2 *)v);
+    return hipGetLastError();
+}
+
+// flag |= 4 if any of v[0..m) is NaN or Inf.
+__global__ void k_finite(const double *v, int64_t m, int *flag) {
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride)
+        bad |= !isfinite(v[j]);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flag, 4);
+}
+
+hipError_t check_finite(const double *v, int64_t m, int *flag, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_finite, dim3((unsigned)blocks), dim3(256), 0, st, v, m, flag);
+    return hipGetLastError();
+}
+
+// dst[q] = conj(src[pos[q]]) (complex values).
+__global__ void k_gather_conj(const double2 *src, const int64_t *pos, int64_t m, double2 *dst) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const double2 z = src[pos[q]];
+    dst[q] = make_double2(z.x, -z.y);
+}
+
+hipError_t gather_conj_z(const double *src, const int64_t *pos, int64_t m, double *dst,
+                         hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_conj, dim3((m + 255) / 256), dim3(256), 0, st,
+                       (const double2 *)src, pos, m, (double2 *)dst);
+    return hipGetLastError();
+}
+
+}  // namespace xpm

@@ -55,7 +55,8 @@ hipError_t compare_csr(CsrView A, CsrView B, int64_t nnz, int *flags, hipStream_
 // 32), bitmap words, and the number of partial products ub.
 hipError_t row_bounds(CsrView A, CsrView B, int addA, int32_t *lo, int64_t *words, int64_t *ub,
                       hipStream_t st);
-// Class of every row from a per-row byte requirement; rows listed per class.
+// Class of every row from a per-row byte requirement (kind 0 symbolic, 1
+// numeric, 2 complex numeric); rows listed per class.
 // counts[kClasses] must be zeroed by the caller (done inside); lists is
 // kClasses * n int32.
 hipError_t bin_rows(const int64_t *words, const int64_t *cnt, int64_t n, int kind, int *counts,
@@ -71,9 +72,18 @@ hipError_t numeric(CsrView A, CsrView B, double alphaA, double div, const int32_
                    const int64_t *woff, const uint32_t *bitmaps, const int64_t *crp, int32_t *cci,
                    double *cv, double *rowsq, const int *host_counts, const int32_t *lists,
                    int64_t n, void *scratch, const int64_t *scratch_off, hipStream_t st);
-// Per-row byte requirement of the global-memory numeric class (for scratch).
+// The same product on complex values: A.v, B.v and cv hold a (real,
+// imaginary) pair of doubles per entry; alphaA and div are real; rowsq as
+// above with |c_ij + delta_ij|^2.  Rows binned with kind 2.
+hipError_t numeric_z(CsrView A, CsrView B, double alphaA, double div, const int32_t *lo,
+                     const int64_t *woff, const uint32_t *bitmaps, const int64_t *crp,
+                     int32_t *cci, double *cv, double *rowsq, const int *host_counts,
+                     const int32_t *lists, int64_t n, void *scratch, const int64_t *scratch_off,
+                     hipStream_t st);
+// Per-row byte requirement of the global-memory numeric class (for scratch;
+// cplx: the complex accumulators).
 hipError_t numeric_scratch_sizes(const int64_t *woff, const int64_t *crp, int64_t n,
-                                 int64_t *bytes, hipStream_t st);
+                                 int64_t *bytes, hipStream_t st, bool cplx = false);
 
 // ------------------------------------------------------------- filter
 hipError_t filter_init(FilterCtl *c, double eg_scale, const double *norm2, double er, int maxit,
@@ -289,6 +299,27 @@ struct PosCsr {
 };
 hipError_t masked_dot(CsrView M, const double *dv, PosCsr A, PosCsr Bt, double div, double *out,
                       hipStream_t st);
+
+// ------------------------------------------------------------- complex values
+// Value arrays hold a (real, imaginary) pair of doubles per entry (kernels.hip).
+// Algorithm 4.1 on the moduli |z| = sqrt(re^2 + im^2).
+hipError_t filter_pass_z(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
+                         double *part, int nparts, hipStream_t st);
+hipError_t count_kept_z(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                        const FilterCtl *c, int addI, int64_t *cnt, hipStream_t st);
+hipError_t write_kept_z(const int64_t *crp, const int32_t *cci, const double *cv, int64_t n,
+                        const FilterCtl *c, int addI, const int64_t *orp, int32_t *oci,
+                        double *ov, hipStream_t st);
+hipError_t add_count_z(CsrView A, CsrView B, int64_t *cnt, hipStream_t st);
+hipError_t add_write_z(CsrView A, CsrView B, const int64_t *crp, int32_t *cci, double *cv,
+                       hipStream_t st);
+hipError_t compare_csr_z(CsrView A, CsrView B, int64_t nnz, int *flags, hipStream_t st);
+hipError_t fill_identity_z(int64_t n, int64_t *rp, int32_t *ci, double *v, hipStream_t st);
+// flag |= 4 if any of v[0..m) (doubles) is NaN or Inf.
+hipError_t check_finite(const double *v, int64_t m, int *flag, hipStream_t st);
+// dst[q] = conj(src[pos[q]]).
+hipError_t gather_conj_z(const double *src, const int64_t *pos, int64_t m, double *dst,
+                         hipStream_t st);
 
 // ------------------------------------------------------------- extras.hip
 hipError_t fill_f64(double *p, int64_t m, double x, hipStream_t st);

@@ -188,6 +188,7 @@ AtExit<F> at_exit(F f) {
     return AtExit<F>{f};
 }
 
+extern thread_local std::string g_err;   // message of the calling thread's last error
 double ms_since(std::chrono::steady_clock::time_point t0);
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int ensure(expm_plan_s &P, Buf &b, size_t bytes);
@@ -196,8 +197,9 @@ int reserve_as(expm_plan_s &P, DCsr &d, const DCsr &ref);
 int reserve_as(expm_plan_s &P, TileSet &t, const TileSet &ref);
 void release(expm_plan_s &P, Buf &b);
 void release(expm_plan_s &P, DCsr &A);
-int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz);
-int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src);
+// vw: doubles per value (2 for complex matrices)
+int ensure_csr(expm_plan_s &P, DCsr &A, int64_t n, int64_t nnz, int vw = 1);
+int copy_csr(expm_plan_s &P, DCsr &dst, const DCsr &src, int vw = 1);
 // Appends an entry to live, reusing the buffers of the entry at the same
 // position in an earlier call (kept in pool by retire).
 DCsr &push_reuse(std::vector<DCsr> &live, std::vector<DCsr> &pool);
@@ -210,11 +212,12 @@ void out_free(expm_plan_s &P, void *p);
 // caller's allocator (or the pool), or, in fixed-region mode, the caller's
 // buffers after a capacity check.  On failure nothing stays allocated.
 int alloc_output(expm_plan_s &P, int64_t n, int64_t nnz, int64_t **rp, int32_t **ci,
-                 double **v);
+                 double **v, int vw = 1);
 double plan_r0(int M, double x);
 int plan_mn(double nh, double eps, int *Mo, int *No);
+// cplx: complex values (a (real, imaginary) pair of doubles per entry)
 int spgemm(expm_plan_s &P, CsrView A, int64_t nnzA, CsrView B, double alphaA, double div,
-           bool rowsq, int64_t *total);
+           bool rowsq, int64_t *total, bool cplx = false);
 int sparse_add(expm_plan_s &P, const DCsr &A, const DCsr &B, DCsr &dst);
 int sum_taylor(expm_plan_s &P, DCsr &dst);
 int transpose_csr(expm_plan_s &P, const DCsr &A, DCsr &dst);
@@ -226,14 +229,18 @@ int check_view(const expm_csr_cview *H);
 constexpr double kThetaOnDevice = -2.0;
 int filter_and_count(expm_plan_s &P, int64_t n, int64_t cand, double eg_scale,
                      const double *norm2, bool use_fixed, double theta_fixed, bool addI,
-                     FilterCtl *hctl, int64_t *kept);
+                     FilterCtl *hctl, int64_t *kept, bool cplx = false);
 int write_filtered(expm_plan_s &P, int64_t n, DCsr &dst, int64_t kept, bool addI,
-                   bool exact_alloc);
+                   bool exact_alloc, bool cplx = false);
 int masked(expm_plan_s &P, CsrView M, CsrView D, double gamma, MaskTerm t1, MaskTerm t2,
            double div, double *out);
 int plan_input(expm_plan_s &P, const expm_csr_cview *Hv, double eps, DCsr &dst,
                expm_analysis *A);
 int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E);
+// Algorithm 4.2 over C (complex.hip)
+int forward_z(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E);
+// EXPM_LOG=1: one line of the call's statistics on stderr
+void log_call(const expm_plan_s &P, int64_t n, double eps, int status);
 void free_adjoint_state(expm_plan_s &P);
 int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill,
                 bool with_c = false);

@@ -85,21 +85,47 @@ constexpr int kShortChunks = 2;
 constexpr int kTinyRows = 8;
 constexpr int kTinyLen = kWave / kTinyRows;
 
+// Values as real (V = double) or complex (V = double2: real and imaginary
+// part, interleaved in the value array): load, zero, and the cross-lane
+// moves of one value.
+template <class V>
+__device__ __forceinline__ V load_val(const double *v, int64_t p);
+template <>
+__device__ __forceinline__ double load_val<double>(const double *v, int64_t p) {
+    return v[p];
+}
+template <>
+__device__ __forceinline__ double2 load_val<double2>(const double *v, int64_t p) {
+    return ((const double2 *)v)[p];
+}
+__device__ __forceinline__ double val_readlane(double x, int j) { return readlane_f64(x, j); }
+__device__ __forceinline__ double2 val_readlane(double2 x, int j) {
+    return make_double2(readlane_f64(x.x, j), readlane_f64(x.y, j));
+}
+__device__ __forceinline__ double val_shfl(double x, int j) { return __shfl(x, j); }
+__device__ __forceinline__ double2 val_shfl(double2 x, int j) {
+    return make_double2(__shfl(x.x, j), __shfl(x.y, j));
+}
+template <class V>
+__device__ __forceinline__ V val_zero() {
+    return V{};
+}
+
 // Calls f(col, a, b) for every partial product a_ik * b_kj of row i of A*B,
 // with a_ik taken in A's storage order and, for each of them, B's row k in
 // chunks of 64 lanes (f runs on the lanes holding an entry).
-template <class F>
+template <class V = double, class F>
 __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B, int64_t i,
                                              F &&f) {
     const int lane = lane_id();
     const int64_t b = A.rp[i], e = A.rp[i + 1];
     for (int64_t p0 = b; p0 < e; p0 += kWave) {
         const int64_t p = p0 + lane;
-        double av = 0.0;
+        V av = val_zero<V>();
         int64_t s0 = 0, s1 = 0;
         if (p < e) {
             const int k = A.ci[p];
-            av = A.v[p];
+            av = load_val<V>(A.v, p);
             s0 = B.rp[k];
             s1 = B.rp[k + 1];
         }
@@ -114,11 +140,11 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
                     const int u = lane / kTinyLen, h = lane % kTinyLen;
                     const int src = j + (u < un ? u : 0);
                     const int64_t q0 = __shfl(s0, src), q1 = __shfl(s1, src);
-                    const double a = __shfl(av, src);
+                    const V a = val_shfl(av, src);
                     const int64_t q = q0 + h;
                     const bool ok = u < un && q < q1;
                     const int c = ok ? B.ci[q] : -1;
-                    const double v = ok ? B.v[q] : 0.0;
+                    const V v = ok ? load_val<V>(B.v, q) : val_zero<V>();
 #pragma unroll
                     for (int g = 0; g < kTinyRows; ++g)
                         if (u == g && c >= 0) f(c, a, v);
@@ -130,18 +156,18 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
             const unsigned long long grp = ((1ull << un) - 1ull) << j;
             if ((shortm & grp) == grp) {
                 int c[kShortRows][kShortChunks];
-                double v[kShortRows][kShortChunks], a[kShortRows];
+                V v[kShortRows][kShortChunks], a[kShortRows];
 #pragma unroll
                 for (int u = 0; u < kShortRows; ++u) {
                     const int jj = u < un ? j + u : j;
-                    a[u] = readlane_f64(av, jj);
+                    a[u] = val_readlane(av, jj);
                     const int64_t q0 = readlane_i64(s0, jj), q1 = readlane_i64(s1, jj);
 #pragma unroll
                     for (int h = 0; h < kShortChunks; ++h) {
                         const int64_t q = q0 + h * kWave + lane;
                         const bool ok = u < un && q < q1;
                         c[u][h] = ok ? B.ci[q] : -1;
-                        v[u][h] = ok ? B.v[q] : 0.0;
+                        v[u][h] = ok ? load_val<V>(B.v, q) : val_zero<V>();
                     }
                 }
 #pragma unroll
@@ -152,19 +178,19 @@ __device__ __forceinline__ void for_products(const CsrView &A, const CsrView &B,
                 j += un;
                 continue;
             }
-            const double a = readlane_f64(av, j);
+            const V a = val_readlane(av, j);
             const int64_t q0 = readlane_i64(s0, j), q1 = readlane_i64(s1, j);
             for (int64_t qb = q0; qb < q1; qb += kUnroll * kWave) {
                 int c[kUnroll];
-                double v[kUnroll];
+                V v[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     const int64_t q = qb + u * kWave + lane;
                     c[u] = -1;
-                    v[u] = 0.0;
+                    v[u] = val_zero<V>();
                     if (q < q1) {
                         c[u] = B.ci[q];
-                        v[u] = B.v[q];
+                        v[u] = load_val<V>(B.v, q);
                     }
                 }
 #pragma unroll
@@ -255,9 +281,10 @@ __device__ __forceinline__ void for_chunks(const CsrView &A, const CsrView &B, i
 
 // ============================================================== binning
 // kind 0: symbolic (bit map), 1: numeric and masked (accumulator + bit map
-// with prefix counts).
+// with prefix counts), 2: numeric on complex values (two accumulators per
+// slot).
 __device__ __forceinline__ int64_t row_bytes(int kind, int64_t W, int64_t c) {
-    return kind == 0 ? 4 * W : 8 * c + 8 * W;
+    return kind == 0 ? 4 * W : (kind == 2 ? 16 : 8) * c + 8 * W;
 }
 
 struct Caps {
@@ -555,18 +582,18 @@ __global__ __launch_bounds__(512) void k_numeric(
 }
 
 __global__ void k_numeric_scratch(const int64_t *woff, const int64_t *crp, int64_t n,
-                                  int64_t *bytes) {
+                                  int kind, int64_t *bytes) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t need = row_bytes(1, woff[i + 1] - woff[i], crp[i + 1] - crp[i]);
+    const int64_t need = row_bytes(kind, woff[i + 1] - woff[i], crp[i + 1] - crp[i]);
     bytes[i] = need <= kNumCap[kNumClasses - 2] ? 0 : (need + 255) & ~int64_t(255);
 }
 
 hipError_t numeric_scratch_sizes(const int64_t *woff, const int64_t *crp, int64_t n,
-                                 int64_t *bytes, hipStream_t st) {
+                                 int64_t *bytes, hipStream_t st, bool cplx) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_numeric_scratch, dim3((n + 255) / 256), dim3(256), 0, st, woff, crp, n,
-                       bytes);
+                       cplx ? 2 : 1, bytes);
     return hipGetLastError();
 }
 
@@ -588,6 +615,99 @@ hipError_t numeric(CsrView A, CsrView B, double alphaA, double div, const int32_
             hipLaunchKernelGGL(k_numeric<true>, grid, block, 0, st, A, B, alphaA, div, lo, woff,
                                bitmaps, crp, cci, cv, rowsq, list, m, wpb, g_remap, 0, (char *)scratch,
                                scratch_off);
+    }
+    return hipGetLastError();
+}
+
+// Complex values (a double2 per entry, real and imaginary part): the same
+// product with two LDS accumulators per slot, added one after the other in
+// the same order as the real kernel's single one.
+template <bool kGlobal>
+__global__ __launch_bounds__(512) void k_numeric_z(
+    CsrView A, CsrView B, double alphaA, double div, const int32_t *__restrict__ lo,
+    const int64_t *__restrict__ woff, const uint32_t *__restrict__ bitmaps,
+    const int64_t *__restrict__ crp, int32_t *__restrict__ cci, double2 *__restrict__ cv,
+    double *__restrict__ rowsq, const int32_t *__restrict__ list, int nlist, int wpb,
+    int remap, int cap_bytes, char *__restrict__ scratch,
+    const int64_t *__restrict__ scratch_off) {
+    extern __shared__ double smem_f64[];
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    const int64_t idx = (int64_t)(remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * wpb + wave;
+    if (idx >= nlist) return;
+    const int64_t i = list[idx];
+    const int64_t w0 = woff[i], W = woff[i + 1] - w0;
+    const int64_t o = crp[i], c = crp[i + 1] - o;
+    if (c == 0) {
+        if (rowsq && lane == 0) rowsq[i] = 1.0;
+        return;
+    }
+    char *mem = kGlobal ? scratch + scratch_off[i] : (char *)smem_f64 + (int64_t)wave * cap_bytes;
+    double *acc = (double *)mem;   // slot t: acc[2t] real, acc[2t + 1] imaginary part
+    uint2 *bp = (uint2 *)(mem + 16 * c);
+    const int base = lo[i];
+
+    load_rank_table(bitmaps + w0, W, bp);
+    for (int64_t t = lane; t < 2 * c; t += kWave) acc[t] = 0.0;
+    phase_fence<kGlobal>();
+    if (alphaA != 0.0) {
+        for (int64_t p = A.rp[i] + lane; p < A.rp[i + 1]; p += kWave) {
+            const unsigned r = rank_of(bp, A.ci[p] - base);
+            const double2 z = load_val<double2>(A.v, p);
+            acc_add<kGlobal>(&acc[2 * r], alphaA * z.x);
+            acc_add<kGlobal>(&acc[2 * r + 1], alphaA * z.y);
+        }
+    }
+    for_products<double2>(A, B, i, [&](int col, double2 a, double2 bv) {
+        const unsigned r = rank_of(bp, col - base);
+        acc_add<kGlobal>(&acc[2 * r], a.x * bv.x - a.y * bv.y);
+        acc_add<kGlobal>(&acc[2 * r + 1], a.x * bv.y + a.y * bv.x);
+    });
+    phase_fence<kGlobal>();
+    double s = 0.0;
+    bool diag = false;
+    for (int64_t t = lane; t < c; t += kWave) {
+        const int col = column_of(bp, W, (unsigned)t, base);
+        double re = acc[2 * t], im = acc[2 * t + 1];
+        if (div != 1.0) {
+            re = re / div;
+            im = im / div;
+        }
+        cci[o + t] = col;
+        cv[o + t] = make_double2(re, im);
+        if (rowsq) {
+            const double f = col == i ? re + 1.0 : re;
+            diag |= col == i;
+            s = fma(f, f, s);
+            s = fma(im, im, s);
+        }
+    }
+    if (rowsq) {
+        s = wave_sum(s);
+        const bool any = __ballot(diag) != 0;
+        if (lane == 0) rowsq[i] = any ? s : s + 1.0;
+    }
+}
+
+hipError_t numeric_z(CsrView A, CsrView B, double alphaA, double div, const int32_t *lo,
+                     const int64_t *woff, const uint32_t *bitmaps, const int64_t *crp,
+                     int32_t *cci, double *cv, double *rowsq, const int *host_counts,
+                     const int32_t *lists, int64_t n, void *scratch, const int64_t *scratch_off,
+                     hipStream_t st) {
+    for (int c = 0; c < kNumClasses; c++) {
+        const int m = host_counts[c];
+        if (m == 0) continue;
+        const int wpb = kNumWpb[c];
+        dim3 grid((m + wpb - 1) / wpb), block(wpb * kWave);
+        const int32_t *list = lists + (int64_t)c * n;
+        if (kNumCap[c] > 0)
+            hipLaunchKernelGGL(k_numeric_z<false>, grid, block, (size_t)wpb * kNumCap[c], st, A,
+                               B, alphaA, div, lo, woff, bitmaps, crp, cci, (double2 *)cv, rowsq,
+                               list, m, wpb, g_remap, kNumCap[c], (char *)nullptr,
+                               (const int64_t *)nullptr);
+        else
+            hipLaunchKernelGGL(k_numeric_z<true>, grid, block, 0, st, A, B, alphaA, div, lo, woff,
+                               bitmaps, crp, cci, (double2 *)cv, rowsq, list, m, wpb, g_remap, 0,
+                               (char *)scratch, scratch_off);
     }
     return hipGetLastError();
 }

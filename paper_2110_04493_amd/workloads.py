@@ -35,7 +35,8 @@ __all__ = [
     "grid_laplacian", "random_adjacency", "norm1", "config1", "config2",
     "config3", "config4_instance", "config4", "config5", "loss_weights",
     "random_sparse", "to_dense", "table2_matrix", "table4_matrix", "circulant",
-    "perm_plus_identity",
+    "perm_plus_identity", "structural_hamiltonian", "magnetic_laplacian", "schrodinger_grid",
+    "complex_random",
 ]
 
 
@@ -60,12 +61,12 @@ class Csr:
         return np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.rowptr))
 
 
-def csr_from_coo(n: int, r, c, v, *, sum_duplicates: bool = False) -> Csr:
+def csr_from_coo(n: int, r, c, v, *, sum_duplicates: bool = False, dtype=np.float64) -> Csr:
     """Sorted CSR from coordinates.  Duplicates keep the first occurrence
-    unless ``sum_duplicates``."""
+    unless ``sum_duplicates``.  ``dtype`` float64 or complex128."""
     r = np.asarray(r, dtype=np.int64)
     c = np.asarray(c, dtype=np.int64)
-    v = np.asarray(v, dtype=np.float64)
+    v = np.asarray(v, dtype=dtype)
     key = r * n + c
     order = np.argsort(key, kind="stable")
     key = key[order]
@@ -75,7 +76,12 @@ def csr_from_coo(n: int, r, c, v, *, sum_duplicates: bool = False) -> Csr:
         first[1:] = key[1:] != key[:-1]
         if sum_duplicates:
             seg = np.cumsum(first) - 1
-            v = np.bincount(seg, weights=v, minlength=int(first.sum()))
+            m = int(first.sum())
+            if np.iscomplexobj(v):
+                v = np.bincount(seg, weights=v.real, minlength=m) \
+                    + 1j * np.bincount(seg, weights=v.imag, minlength=m)
+            else:
+                v = np.bincount(seg, weights=v, minlength=m)
             key = key[first]
         else:
             key = key[first]
@@ -85,7 +91,7 @@ def csr_from_coo(n: int, r, c, v, *, sum_duplicates: bool = False) -> Csr:
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.add.at(rowptr, rr + 1, 1)
     rowptr = np.cumsum(rowptr).astype(np.int64)
-    return Csr(n, rowptr, cc.astype(np.int32), np.ascontiguousarray(v, dtype=np.float64))
+    return Csr(n, rowptr, cc.astype(np.int32), np.ascontiguousarray(v, dtype=dtype))
 
 
 def to_dense(A: Csr) -> np.ndarray:
@@ -360,3 +366,49 @@ def structural_hamiltonian(rows: int, cols: int, dt: float, alpha: float = 0.0,
     keep = v != 0.0
     H = csr_from_coo(2 * m, r[keep], c[keep], v[keep] * dt, sum_duplicates=True)
     return H, mass, K
+
+
+# --------------------------------------------------------------------------
+# Complex matrices (the method is stated for H in C^{n x n}).
+# --------------------------------------------------------------------------
+
+def magnetic_laplacian(rows: int, cols: int, seed: int = 0, sigma: float = 0.4,
+                       phase: float = 0.7) -> Csr:
+    """Hermitian magnetic Laplacian of a rows x cols 5-point grid: D - A with
+    A_jk = w e^{i phi}, A_kj = w e^{-i phi} for each edge (j, k), weights
+    w ~ lognormal(0, sigma), phases phi ~ U[-phase, phase], D the weighted
+    degrees (complex128 values)."""
+    rng = np.random.default_rng(seed)
+    n = rows * cols
+    e = grid_edges(rows, cols)
+    w = rng.lognormal(0.0, sigma, len(e))
+    ph = rng.uniform(-phase, phase, len(e))
+    deg = np.zeros(n)
+    np.add.at(deg, e[:, 0], w)
+    np.add.at(deg, e[:, 1], w)
+    z = w * np.exp(1j * ph)
+    return csr_from_coo(n, np.concatenate([e[:, 0], e[:, 1], np.arange(n)]),
+                        np.concatenate([e[:, 1], e[:, 0], np.arange(n)]),
+                        np.concatenate([-z, -np.conj(z), deg.astype(complex)]),
+                        dtype=np.complex128)
+
+
+def schrodinger_grid(side: int, t: float, vmax: float = 1.0, seed: int = 0) -> Csr:
+    """H = -i t (L + V) for a side x side unit grid Laplacian L and a random
+    potential V ~ U[0, vmax] on the diagonal: skew-Hermitian, so e^H is the
+    unitary propagator of the discrete Schroedinger equation over time t."""
+    rng = np.random.default_rng(seed)
+    L = grid_laplacian(side, side)
+    d = L.rows() == L.col
+    v = L.val.astype(complex)
+    v[d] += rng.uniform(0.0, vmax, side * side)
+    return Csr(L.n, L.rowptr.copy(), L.col.copy(), np.ascontiguousarray(-1j * t * v))
+
+
+def complex_random(n: int, density: float, seed: int, scale: float = 1.0) -> Csr:
+    """Random sparse complex matrix (general, not normal): the pattern of
+    random_sparse with independent N(0, scale^2) real and imaginary parts."""
+    A = random_sparse(n, density, seed)
+    rng = np.random.default_rng(seed + 1)
+    v = scale * (rng.standard_normal(A.nnz) + 1j * rng.standard_normal(A.nnz))
+    return Csr(n, A.rowptr, A.col, np.ascontiguousarray(v))

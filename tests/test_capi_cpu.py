@@ -29,6 +29,9 @@ def test_library_exports_every_symbol():
     for name in header_functions():
         assert hasattr(L, name), name
         assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+        # every binding declares its argument types, so that ctypes converts
+        # (and checks) each argument instead of guessing
+        assert getattr(L, name).argtypes is not None, name
 
 
 def test_defaults():
