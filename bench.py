@@ -467,9 +467,9 @@ def other_workloads(args) -> dict:
     """Short measurements of the other configurations, after the headline:
     the differentiation workload (200 x 200 grid, forward + adjoint), the
     action E R of the headline E with R = rand(n, 1000) (section 5.3), the
-    large unit grid (1448 x 1448, one forward on a fresh plan: time, nnz(E),
-    peak device memory) and a batch of uneven instances against a
-    per-matrix loop."""
+    checkpoint placements, the large unit grid (1448 x 1448, one forward on
+    a fresh plan: time, nnz(E), peak device memory), a complex H, and a
+    batch of uneven instances against a per-matrix loop."""
     import torch
     from paper_2110_04493_amd import api, workloads as W
     out = {}
@@ -481,11 +481,39 @@ def other_workloads(args) -> dict:
     out["checkpoints"] = checkpoint_numbers(args.side)
     print("other workloads: large grid", file=sys.stderr, flush=True)
     out["large_grid"] = large_grid_numbers()
+    print("other workloads: complex H", file=sys.stderr, flush=True)
+    out["complex"] = complex_numbers(args.side, 1, 3)
     print("other workloads: batched", file=sys.stderr, flush=True)
     out["batched"] = batched_numbers(64, 500, 2000, 1, 3)
     print("other workloads: batched at the stated size range", file=sys.stderr, flush=True)
     out["batched_stated_range"] = batched_numbers(8, 500, 20000, 1, 1)
     return out
+
+
+def complex_numbers(side: int, warmup: int, steps: int) -> dict:
+    """The complex entry point on the discrete Schroedinger propagator
+    H = -i t (L + V) of a side x side unit grid (t = 1, V ~ U[0, 1]): median
+    forward time on a warm plan, and the sizes."""
+    import torch
+    from paper_2110_04493_amd import api, workloads as W
+    H = W.schrodinger_grid(side, 1.0, vmax=1.0, seed=7000)
+    dev = (torch.from_numpy(H.rowptr).cuda(), torch.from_numpy(H.col).cuda(),
+           torch.from_numpy(H.val).cuda())
+    plan = api.Plan("cuda")
+    ts = []
+    nnz = 0
+    for it in range(warmup + steps):
+        t, (rp, ci, v) = _sync_time(lambda: plan.expm_z(*dev, 1e-12))
+        nnz = int(v.numel())
+        del rp, ci, v
+        if it >= warmup:
+            ts.append(t)
+    st = plan.stats()
+    plan.close()
+    return {"workload": f"H = -i t (L + V), {side}x{side} unit grid (n={side * side}), t=1, "
+                        "V ~ U[0,1], eps 1e-12, complex128, scalar-row path",
+            "forward_s": round(float(np.median(ts)), 5), "M": st["M"], "N": st["N"],
+            "normal": st["normal"], "nnz_e": nnz}
 
 
 def checkpoint_numbers(side: int) -> dict:
