@@ -66,6 +66,11 @@ def parse():
     ap.add_argument("--count", type=int, default=64, help="batched: number of instances")
     ap.add_argument("--nmin", type=int, default=500, help="batched: smallest n")
     ap.add_argument("--nmax", type=int, default=2000, help="batched: largest n")
+    ap.add_argument("--wave-gb", type=float, default=0.0,
+                    help="batched: run the instances in waves whose dense-output estimate "
+                         "(60 n^2 bytes each: E, the iterates and the candidate as if dense) "
+                         "stays within this many GB, each wave's outputs counted and freed "
+                         "before the next (0: one call for all)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (the "
                          "reference kernel for scaling HBM counter readings) and exit")
@@ -346,15 +351,42 @@ def bench_batched(args):
     inst = [W.config4_instance(j, nmin=args.nmin, nmax=args.nmax) for j in range(args.count)]
     dev = [tuple(torch.from_numpy(a).cuda() for a in (H.rowptr, H.col, H.val)) for H, _ in inst]
     eps = [e for _, e in inst]
+    # waves: instances in index order, each wave within the dense-output budget
+    waves = [list(range(len(inst)))]
+    if args.wave_gb > 0:
+        waves, cur, used = [], [], 0.0
+        for j, (H, _) in enumerate(inst):
+            need = 60.0 * H.n * H.n / 1e9
+            if cur and used + need > args.wave_gb:
+                waves.append(cur)
+                cur, used = [], 0.0
+            cur.append(j)
+            used += need
+        if cur:
+            waves.append(cur)
     plan = api.Plan("cuda", api.Options())
+
+    def run_batched():
+        nnz = 0
+        for wv in waves:
+            outs = plan.expm_batched([dev[j] for j in wv], [eps[j] for j in wv])
+            nnz += sum(int(o[2].numel()) for o in outs)
+            del outs
+        return nnz
+
+    def run_loop():
+        nnz = 0
+        for d, e in zip(dev, eps):
+            out = plan.expm(*d, e)
+            nnz += int(out[2].numel())
+            del out
+        return nnz
+
     tb, tl = [], []
     for it in range(args.warmup + args.steps):
-        t_b, outs = _sync_time(lambda: plan.expm_batched(dev, eps))
-        nnz_b = sum(int(o[2].numel()) for o in outs)
-        del outs
-        t_l, outs = _sync_time(lambda: [plan.expm(*d, e) for d, e in zip(dev, eps)])
-        nnz_l = sum(int(o[2].numel()) for o in outs)
-        del outs
+        t_b, nnz_b = _sync_time(run_batched)
+        t_l, nnz_l = _sync_time(run_loop)
+        print(f"batched pass {it}: {t_b:.3f} s, loop {t_l:.3f} s", file=sys.stderr, flush=True)
         if it >= args.warmup:
             tb.append(t_b)
             tl.append(t_l)
@@ -369,7 +401,8 @@ def bench_batched(args):
                                   f"[{args.nmin}, {args.nmax}], half unit grids (tau in [1, 20]), "
                                   "half random adjacency (beta in [0.1, 1]), eps 1e-12",
                       "count": args.count, "sum_n": int(sum(H.n for H, _ in inst)),
-                      "nnz_e_total": nnz_b, "parallelism": "single GPU"},
+                      "nnz_e_total": nnz_b, "waves": len(waves),
+                      "parallelism": "single GPU"},
            "loop_s": round(float(np.median(tl)), 5),
            "speedup_vs_loop": round(float(np.median(tl)) / sec, 3)}
     print(json.dumps(out), flush=True)
@@ -510,10 +543,41 @@ def complex_numbers(side: int, warmup: int, steps: int) -> dict:
             ts.append(t)
     st = plan.stats()
     plan.close()
-    return {"workload": f"H = -i t (L + V), {side}x{side} unit grid (n={side * side}), t=1, "
+    # the squaring products' numeric pass (k_numeric_z) from an untimed pass
+    # with per-step phase timers: 8 flops per complex partial product of
+    # T T and 4 per stored entry of T (the 2T term); 20 bytes (value and
+    # column) per stored entry of T read once, 8 (n + 1) for its row
+    # pointer and 20 per candidate written once
+    pplan = api.Plan("cuda", api.Options(profile=1))
+    for _ in range(2):
+        out = pplan.expm_z(*dev, 1e-12)
+        del out
+    torch.cuda.synchronize()
+    ps = pplan.stats()
+    pplan.close()
+    n = side * side
+    fl = sum(8.0 * f + 4.0 * k for f, k in zip(ps["sq_fma"], ps["sq_in"]))
+    by = sum(20.0 * k + 8.0 * (n + 1) + 20.0 * c for k, c in zip(ps["sq_in"], ps["sq_cand"]))
+    ms = sum(ps["t_num_ms"])
+    bound = "alu" if fl / by > RIDGE else "hbm"
+    if bound == "alu":
+        ach = fl / (ms * 1e9)
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4)}
+    else:
+        ach = by / (ms * 1e6)
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4)}
+    roof.update({"kernel": "k_numeric_z (numeric pass of the squarings)", "ms": round(ms, 3),
+                 "algorithmic_flop": fl, "algorithmic_bytes": by,
+                 "flop_per_byte": round(fl / by, 2)})
+    return {"workload": f"H = -i t (L + V), {side}x{side} unit grid (n={n}), t=1, "
                         "V ~ U[0,1], eps 1e-12, complex128, scalar-row path",
             "forward_s": round(float(np.median(ts)), 5), "M": st["M"], "N": st["N"],
-            "normal": st["normal"], "nnz_e": nnz}
+            "normal": st["normal"], "nnz_e": nnz, "squaring_numeric": roof,
+            "phase_ms": {"symbolic": round(sum(ps["t_sym_ms"]), 3), "numeric": round(ms, 3),
+                         "filter": round(sum(ps["t_filter_ms"]), 3),
+                         "taylor": round(ps["t_taylor_ms"], 3)}}
 
 
 def checkpoint_numbers(side: int) -> dict:

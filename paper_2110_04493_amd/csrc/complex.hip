@@ -253,6 +253,21 @@ int forward_z(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E)
                              &kept, true));
         CHK(write_filtered(P, n, Tn, kept, false, false, true));
         Tn.nnz = kept;
+        if (P.opts.profile == 1 && P.have_events) {
+            // phase times of the step (symbolic, numeric, filter and
+            // compaction) and its partial products, as for real H
+            HIPCHK(hipEventRecord(P.ev[3], st));
+            HIPCHK(hipEventSynchronize(P.ev[3]));
+            float t0, t1, t2;
+            HIPCHK(hipEventElapsedTime(&t0, P.ev[0], P.ev[1]));
+            HIPCHK(hipEventElapsedTime(&t1, P.ev[1], P.ev[2]));
+            HIPCHK(hipEventElapsedTime(&t2, P.ev[2], P.ev[3]));
+            S.t_sym_ms[i] = t0;
+            S.t_num_ms[i] = t1;
+            S.t_filter_ms[i] = t2;
+            S.sq_fma[i] = P.last_fma;
+            S.sq_in[i] = T.nnz;
+        }
         std::swap(T, Tn);
         if (diag) HIPCHK(band_of(T.view(), nullptr, (long long *)P.bands.p + 2 * i, st));
         S.sq_theta[i] = h.theta;
