@@ -57,12 +57,13 @@ def parse():
                     help="skip the lines of the other workloads (differentiation, large grid, "
                          "batched, E R) that follow the headline line")
     ap.add_argument("--forward-only", action="store_true")
-    ap.add_argument("--workload", choices=["grid", "batched", "grad"], default="grid",
+    ap.add_argument("--workload", choices=["grid", "batched", "grad", "complex"], default="grid",
                     help="grid: the headline 2D heat-conduction workload (default); batched: "
                          "many uneven instances of the batched family in one call, timed "
                          "against a per-matrix loop; grad: the differentiation workload "
                          "(200 x 200 grid, forward + adjoint), timed against a forward-only "
-                         "loop")
+                         "loop; complex: the complex entry point on the Schroedinger "
+                         "propagator of the --side grid")
     ap.add_argument("--count", type=int, default=64, help="batched: number of instances")
     ap.add_argument("--nmin", type=int, default=500, help="batched: smallest n")
     ap.add_argument("--nmax", type=int, default=2000, help="batched: largest n")
@@ -205,6 +206,17 @@ def main():
         return
     if args.workload == "grad":
         bench_grad(args)
+        return
+    if args.workload == "complex":
+        c = complex_numbers(args.side, args.warmup, args.steps)
+        sec = c["forward_s"]
+        print(json.dumps({"metric": "complex expm wall time (forward)", "value": sec,
+                          "unit": "s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3),
+                          "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "c128", "data": "synthetic",
+                          "config": {"workload": c["workload"], "parallelism": "single GPU"},
+                          "roofline": c["squaring_numeric"], "detail": c}), flush=True)
         return
     import torch
     from paper_2110_04493_amd import api, workloads as W
@@ -368,18 +380,28 @@ def bench_batched(args):
 
     def run_batched():
         nnz = 0
-        for wv in waves:
+        for k, wv in enumerate(waves):
             outs = plan.expm_batched([dev[j] for j in wv], [eps[j] for j in wv])
             nnz += sum(int(o[2].numel()) for o in outs)
             del outs
+            if len(waves) > 1:
+                print(f"batched: wave {k + 1} of {len(waves)} done ({len(wv)} instances)",
+                      file=sys.stderr, flush=True)
+            if len(waves) > 1:
+                # the outputs' memory goes back to the device for the
+                # library's workspace of the next wave
+                torch.cuda.empty_cache()
         return nnz
 
     def run_loop():
         nnz = 0
-        for d, e in zip(dev, eps):
+        for j, (d, e) in enumerate(zip(dev, eps)):
             out = plan.expm(*d, e)
             nnz += int(out[2].numel())
             del out
+            if len(waves) > 1 and (j + 1) % 16 == 0:
+                torch.cuda.synchronize()
+                print(f"loop: {j + 1} of {len(dev)} instances done", file=sys.stderr, flush=True)
         return nnz
 
     tb, tl = [], []

@@ -165,6 +165,12 @@ typedef struct {
                                 0 (default) min(1/(N+1), 1/||H||); 1 the
                                 1/||H|| of Algorithm 4.2 step 2 and section
                                 4.2, also where it exceeds 1/(N+1)           */
+    int batch_solo_n;        /* expm_sparse_batched: instances of order n >=
+                                this run one after another through the
+                                single-matrix path (locality ordering, tiles
+                                sized to the instance); the others share the
+                                stacked pass.  Default 4096; 0 stacks every
+                                instance                                     */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',
@@ -278,8 +284,10 @@ int expm_sparse_backward(expm_plan_t p, const double *dE_vals, double *dH_vals);
 
 /* Algorithm 4.2 for `count` independent matrices H[k] with tolerances
  * eps[k] (host array), in one pass: every kernel launch of a step serves
- * the rows of all instances still active at that step.  E[k] as for
- * expm_sparse.  Errors as expm_sparse; on error no E[k] is allocated. */
+ * the rows of all instances still active at that step.  Instances of order
+ * at least opts.batch_solo_n run after that pass, one by one, as
+ * expm_sparse would run them.  E[k] as for expm_sparse.  Errors as
+ * expm_sparse; on error no E[k] is allocated. */
 int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cview *H, const double *eps,
                         expm_csr *E);
 

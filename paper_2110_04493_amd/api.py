@@ -89,6 +89,7 @@ class Options:
     exact_ri: bool = False
     diagnostics: bool = False
     literal_a: bool = False    # non-normal H: a = 1/||H|| (Algorithm 4.2 step 2) instead of the min
+    batch_solo_n: int = 4096   # expm_batched: instances with n >= this run on their own (0: none)
 
 
 class Plan:
@@ -117,6 +118,7 @@ class Plan:
         o.exact_ri = int(self.options.exact_ri)
         o.diagnostics = int(self.options.diagnostics)
         o.literal_a = int(self.options.literal_a)
+        o.batch_solo_n = int(self.options.batch_solo_n)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)

@@ -67,7 +67,8 @@ class expm_opts(C.Structure):
                 ("checkpoint_interval", C.c_int), ("stream", C.c_void_p),
                 ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int),
                 ("reorder", C.c_int), ("tile_min_fill", C.c_double), ("norm", C.c_int),
-                ("exact_ri", C.c_int), ("diagnostics", C.c_int), ("literal_a", C.c_int)]
+                ("exact_ri", C.c_int), ("diagnostics", C.c_int), ("literal_a", C.c_int),
+                ("batch_solo_n", C.c_int)]
 
 
 _S = EXPM_MAXSTEP

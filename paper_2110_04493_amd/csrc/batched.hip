@@ -696,7 +696,38 @@ extern "C" int expm_sparse_batched(expm_plan_t p, int count, const expm_csr_cvie
     collect_forward(*p);
     p->kt_used = 0;
     p->kt_kind.clear();
-    int s = batched(*p, B, count, H, eps, E);
+    // large instances (n >= opts.batch_solo_n) run on their own after the
+    // stacked pass of the others
+    std::vector<int> solo, stack;
+    for (int k = 0; k < count && H && eps && E; ++k)
+        (p->opts.batch_solo_n > 0 && H[k].n >= p->opts.batch_solo_n ? solo : stack).push_back(k);
+    int s;
+    if (solo.empty()) {
+        s = batched(*p, B, count, H, eps, E);
+    } else {
+        for (int k = 0; k < count; ++k) memset(&E[k], 0, sizeof E[k]);
+        std::vector<expm_csr_cview> hs;
+        std::vector<double> es;
+        for (int k : stack) {
+            hs.push_back(H[k]);
+            es.push_back(eps[k]);
+        }
+        std::vector<expm_csr> outs(stack.size());
+        s = batched(*p, B, (int)stack.size(), hs.data(), es.data(), outs.data());
+        if (s == EXPM_OK)
+            for (size_t i = 0; i < stack.size(); ++i) E[stack[i]] = outs[i];
+        else
+            for (expm_csr &o : outs) {
+                out_free(*p, o.rowptr);
+                out_free(*p, o.col);
+                out_free(*p, o.val);
+            }
+        for (size_t i = 0; s == EXPM_OK && i < solo.size(); ++i) {
+            s = forward(*p, &H[solo[i]], eps[solo[i]], &E[solo[i]]);
+            if (s != EXPM_OK) s = fail(s, "instance %d: %s", solo[i], g_err.c_str());
+        }
+        free_adjoint_state(*p);   // no adjoint follows a batched call
+    }
     free_bufs(*p, B);
     if (s == EXPM_OK && light_profile(*p)) {
         (void)hipStreamSynchronize(p->st);

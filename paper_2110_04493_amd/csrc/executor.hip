@@ -1526,6 +1526,7 @@ void expm_opts_default(expm_opts *o) {
     o->exact_ri = 0;
     o->diagnostics = 0;
     o->literal_a = 0;
+    o->batch_solo_n = 4096;
 }
 
 int expm_plan(expm_plan_t *out, const expm_opts *opts) {
@@ -1543,7 +1544,7 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.norm != EXPM_NORM_FRO && o.norm != EXPM_NORM_ONE)
         return fail(EXPM_EINVAL, "unknown norm %d", o.norm);
     if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1 ||
-        o.literal_a < 0 || o.literal_a > 1)
+        o.literal_a < 0 || o.literal_a > 1 || o.batch_solo_n < 0)
         return fail(EXPM_EINVAL, "invalid option value");
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
         o.checkpoint_interval < -1 || o.reorder < -1 || o.reorder > 2 || o.profile < 0 ||

@@ -38,7 +38,8 @@ def test_defaults():
     o = capi.expm_opts_default()
     assert (o.normal, o.filter_mode, o.e_r, o.max_filter_iter, o.keep_checkpoints,
             o.reorder) == (-1, 0, 0.1, 64, 0, -1)
-    assert (o.norm, o.exact_ri, o.diagnostics, o.literal_a) == (capi.EXPM_NORM_FRO, 0, 0, 0)
+    assert (o.norm, o.exact_ri, o.diagnostics, o.literal_a, o.batch_solo_n) == \
+        (capi.EXPM_NORM_FRO, 0, 0, 0, 4096)
     assert capi.expm_last_error() == ""
 
 
@@ -72,7 +73,8 @@ def test_choose_mn_rejects_bad_input():
                                          ("profile", 3), ("profile", -1),
                                          ("tile_min_fill", float("nan")), ("norm", 2),
                                          ("filter_mode", 3), ("exact_ri", 2),
-                                         ("diagnostics", -1), ("literal_a", 2)])
+                                         ("diagnostics", -1), ("literal_a", 2),
+                                         ("batch_solo_n", -1)])
 def test_plan_rejects_invalid_options(field, value):
     """Option validation runs before the plan touches the device."""
     o = capi.expm_opts_default()

@@ -108,17 +108,33 @@ def test_batched_invalid_instance():
     assert e.value.code == capi.EXPM_EINVAL
 
 
-def test_batched_family_at_stated_sizes():
+@pytest.mark.parametrize("solo_n", [4096, 0])
+def test_batched_family_at_stated_sizes(solo_n):
     """Instances of the batched family at its stated sizes that the oracle
     can run in seconds: two grids near n = 20,000 with the smaller tau
     (j = 38: n = 18,395, tau = 1.43; j = 114: n = 18,627, tau = 2.58) and two
     adjacency instances whose exponentials are dense (j = 59: n = 1,066;
     j = 191: n = 990, beta = 0.99), in one batched call, each against the
-    oracle and against its own single call."""
+    oracle and against its own single call; the two grids run on their own
+    (default routing) or in the stack with the others (solo_n = 0)."""
     mats, eps = [], []
     for j in (38, 59, 114, 191):
         H, e = W.config4_instance(j)
         mats.append(H)
         eps.append(e)
     assert [H.n for H in mats] == [18395, 1066, 18627, 990]
-    check_all(mats, eps)
+    check_all(mats, eps, batch_solo_n=solo_n)
+
+
+def test_batched_routing_errors_free_everything():
+    """An invalid instance among those that run on their own fails the whole
+    call with EXPM_EINVAL (outputs of the stacked pass released)."""
+    from paper_2110_04493_amd import capi
+    small = W.tridiag(100, 1.0, -2.0, 1.0)
+    big = W.tridiag(5000, 1.0, -2.0, 1.0)
+    big.val[7] = np.nan
+    with pytest.raises(capi.ExpmError) as e:
+        run_batched([small, big], [1e-12, 1e-12])
+    assert e.value.code == capi.EXPM_EINVAL
+    outs, _ = run_batched([small, W.tridiag(5000, 1.0, -2.0, 1.0)], [1e-12, 1e-12])
+    assert outs[1].n == 5000 and outs[0].n == 100
