@@ -171,6 +171,13 @@ typedef struct {
                                 sized to the instance); the others share the
                                 stacked pass.  Default 4096; 0 stacks every
                                 instance                                     */
+    int use_symmetry;        /* 1 (default): for an exactly symmetric H (every
+                                T_i is then symmetric) the summed Taylor seed
+                                is made exactly symmetric (its upper triangle
+                                mirrored; the terms agree to rounding) and
+                                each tile product forms the candidate's tiles
+                                on and right of the diagonal only, the others
+                                being their transposes; 0: every tile formed */
 } expm_opts;
 
 /* Per-call statistics (indices as in the paper: Taylor term i = 2..M',
@@ -234,6 +241,9 @@ typedef struct {
     /* 1 when the last expm_sparse_backward ran its first step on the rows
        of the nonzeros of dL/dE (fewer than a hundredth of E's entries) */
     int adj_sparse_first;
+    /* 1 when H was exactly symmetric and opts.use_symmetry formed only the
+       upper triangle of each tile candidate */
+    int symmetric;
 } expm_stats;
 
 typedef struct expm_plan_s *expm_plan_t;

@@ -90,6 +90,7 @@ class Options:
     diagnostics: bool = False
     literal_a: bool = False    # non-normal H: a = 1/||H|| (Algorithm 4.2 step 2) instead of the min
     batch_solo_n: int = 4096   # expm_batched: instances with n >= this run on their own (0: none)
+    use_symmetry: bool = True  # symmetric H: tile products form the upper triangle only
 
 
 class Plan:
@@ -119,6 +120,7 @@ class Plan:
         o.diagnostics = int(self.options.diagnostics)
         o.literal_a = int(self.options.literal_a)
         o.batch_solo_n = int(self.options.batch_solo_n)
+        o.use_symmetry = int(self.options.use_symmetry)
         self._opts = o
         with torch.cuda.device(self.device):
             self.handle = capi.expm_plan(o)

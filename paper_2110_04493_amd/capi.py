@@ -68,7 +68,7 @@ class expm_opts(C.Structure):
                 ("allocator", C.POINTER(expm_allocator)), ("profile", C.c_int),
                 ("reorder", C.c_int), ("tile_min_fill", C.c_double), ("norm", C.c_int),
                 ("exact_ri", C.c_int), ("diagnostics", C.c_int), ("literal_a", C.c_int),
-                ("batch_solo_n", C.c_int)]
+                ("batch_solo_n", C.c_int), ("use_symmetry", C.c_int)]
 
 
 _S = EXPM_MAXSTEP
@@ -97,7 +97,7 @@ class expm_stats(C.Structure):
                 ("sq_ri", C.c_double * _S), ("sq_band", C.c_int64 * _S),
                 ("theta0", C.c_double), ("tile_bytes", C.c_double),
                 ("adj_tile_flops", C.c_double), ("adj_tile_bytes", C.c_double),
-                ("ordering", C.c_int), ("adj_sparse_first", C.c_int)]
+                ("ordering", C.c_int), ("adj_sparse_first", C.c_int), ("symmetric", C.c_int)]
 
     def to_dict(self) -> dict:
         d = {k: getattr(self, k) for k in ("status", "M", "N", "taylor_terms", "normal",
@@ -107,7 +107,7 @@ class expm_stats(C.Structure):
                                            "tile_ms", "tile_flops", "adj_tile_launches",
                                            "adj_tile_ms", "theta0", "tile_bytes",
                                            "adj_tile_flops", "adj_tile_bytes", "ordering",
-                                           "adj_sparse_first")}
+                                           "adj_sparse_first", "symmetric")}
         T, N = self.taylor_terms, self.squarings
         for k in ("taylor_theta", "taylor_iters", "taylor_cand", "taylor_kept"):
             d[k] = list(getattr(self, k)[2:T + 2])

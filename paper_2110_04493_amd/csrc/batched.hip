@@ -312,6 +312,7 @@ int batched(expm_plan_s &P, BatchBufs &B, int count, const expm_csr_cview *H, co
     for (int k = 0; k < count; ++k) memset(&E[k], 0, sizeof E[k]);
     free_adjoint_state(P);
     memset(&P.stats, 0, sizeof P.stats);
+    P.sym_h = false;   // the stacked products form every candidate tile
     if (count == 0) return EXPM_OK;
     if (P.opts.filter_mode == EXPM_FILTER_FIXED_REL || P.opts.norm != EXPM_NORM_FRO ||
         P.opts.exact_ri)

@@ -368,12 +368,14 @@ __global__ void k_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cw
 }
 
 // Union of the C block-column lists of a panel: counts (pcols == NULL) or
-// the sorted list at pofs[p].
+// the sorted list at pofs[p].  With upper, only the block columns at or
+// right of the panel's first block row (a symmetric C is formed from its
+// upper triangle).
 __global__ __launch_bounds__(64) void k_panel_cols(int64_t nb, const int32_t *clo,
                                                    const int64_t *cwoff, const uint2 *crt,
                                                    const int32_t *plo, const int64_t *pwoff,
                                                    int64_t *pcnt, const int64_t *pofs,
-                                                   int32_t *pcols) {
+                                                   int32_t *pcols, int upper) {
     extern __shared__ uint32_t bm[];
     const int64_t p = blockIdx.x;
     const int lane = lane_id();
@@ -394,10 +396,16 @@ __global__ __launch_bounds__(64) void k_panel_cols(int64_t nb, const int32_t *cl
     }
     wfence();
     const int base = plo[p];
+    const int64_t first = upper ? p * kPanel : INT32_MIN;   // smallest block column kept
     unsigned carry = 0;
     for (int64_t b0 = 0; b0 < PW; b0 += kWave) {
         const int64_t w = b0 + lane;
         uint32_t x = w < PW ? bm[w] : 0u;
+        const int64_t c0 = base + 32 * w;   // block column of bit 0
+        if (c0 + 32 <= first)
+            x = 0u;
+        else if (c0 < first)
+            x &= ~((1u << (unsigned)(first - c0)) - 1u);
         const unsigned pc = __popc(x);
         const unsigned inc = wave_incl_scan(pc);
         if (pcols && w < PW) {
@@ -434,7 +442,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
     int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
-    double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg) {
+    double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper) {
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
@@ -444,8 +452,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int64_t g0 = (w - pgofs[p]) * kGroup;
     const int ng = (int)min<int64_t>(kGroup, pofs[p + 1] - pofs[p] - g0);
     int J[kGroup];
+    // with upper, the tiles left of the diagonal are not formed here (they
+    // are the transposes of tiles right of it)
+    bool act[kGroup];
 #pragma unroll
-    for (int t = 0; t < kGroup; ++t) J[t] = t < ng ? pcols[pofs[p] + g0 + t] : -1;
+    for (int t = 0; t < kGroup; ++t) {
+        J[t] = t < ng ? pcols[pofs[p] + g0 + t] : -1;
+        act[t] = t < ng && (!upper || J[t] >= (int)I);
+    }
     d4 acc[kGroup];
 #pragma unroll
     for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -454,6 +468,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
 #pragma unroll
         for (int t = 0; t < kGroup; ++t) {
             if (t >= ng) break;
+            if (!act[t]) continue;
             const int64_t tt = tile_of(lo, woff, rt, tb, I, J[t]);
             if (tt < 0) continue;
             const d4 b = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
@@ -473,12 +488,13 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         const int64_t tbK = tb[K];
 #pragma unroll
         for (int t = 0; t < kGroup; ++t)
-            if (t < ng) ti[t] = tile_in_row(loK, w0, WK, tbK, rt, J[t]);
+            if (act[t]) ti[t] = tile_in_row(loK, w0, WK, tbK, rt, J[t]);
     };
     pipe_products<kGroup>(nk, item, look, tA, tB, acc);
 #pragma unroll
     for (int t = 0; t < kGroup; ++t) {
         if (t >= ng) break;
+        if (!act[t]) continue;
         const int64_t ct = tile_of(clo, cwoff, crt, ctb, I, J[t]);
         if (ct < 0) continue;
         // candidate tiles are written once and read back by later kernels,
@@ -529,6 +545,122 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
             trc[ct] = make_uint4(rc[0], rc[1], rc[2], rc[3]);
         }
     }
+}
+
+// ----------------------------------------------------------------- mirror
+// A symmetric C formed from its tiles on and right of the diagonal: every
+// candidate tile (I, J) with J < I becomes the transpose of tile (J, I),
+// with the same per-tile summaries (sum of squares, nonzero count, smallest
+// nonzero and largest magnitude) and its own per-row nonzero counts.  One
+// workgroup per block row, its four waves taking every fourth tile.  The
+// lanes look up the source tiles of 64 tiles at once (all lookups in
+// flight), and each wave loads its next tile while it transposes the
+// current one through LDS (rows padded to 17 doubles).  A missing tile
+// (J, I) sets *bad (C's pattern not symmetric) and leaves an empty tile.
+__global__ __launch_bounds__(256) void k_bsr_mirror(int64_t nb, const int32_t *__restrict__ clo,
+                                                    const int64_t *__restrict__ cwoff,
+                                                    const uint2 *__restrict__ crt,
+                                                    const int64_t *__restrict__ ctb,
+                                                    const int64_t *__restrict__ ccnt,
+                                                    const int32_t *__restrict__ ccols,
+                                                    double *__restrict__ ctiles, double *tsq,
+                                                    int32_t *tnz, double *tmn, double *tmx,
+                                                    uint4 *trc, int *bad) {
+    __shared__ double sm[4][kTile * (kTile + 1)];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    const int64_t I = blockIdx.x;
+    if (I >= nb) return;
+    double *M = sm[wv];
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t b = ctb[I], cnt = ccnt[I];
+    for (int64_t c0 = 0; c0 < cnt; c0 += kWave) {
+        // lane l: source of tile b + c0 + l (-1: on or right of the
+        // diagonal, or past the row; -2: missing)
+        const int64_t tl = c0 + lane;
+        int64_t src = -1;
+        if (tl < cnt) {
+            const int J = ccols[b + tl];
+            if (J < (int)I) {
+                src = tile_of(clo, cwoff, crt, ctb, J, (int)I);
+                if (src < 0) src = -2;
+            }
+        }
+        if (__ballot(src == -2) && lane == 0) atomicOr(bad, 1);
+        const unsigned long long todo = __ballot(src != -1);
+        if (!todo) break;   // columns ascend: nothing left of the diagonal remains
+        // the summaries shared with the source tile, one lane per tile (the
+        // source tiles lie right of the diagonal: the product wrote them)
+        if (tsq && wv == 0 && src != -1) {
+            const int64_t t = b + tl;
+            const bool ok = src >= 0;
+            tsq[t] = ok ? tsq[src] : 0.0;
+            tnz[t] = ok ? tnz[src] : 0;
+            tmn[t] = ok ? tmn[src] : INFINITY;
+            tmx[t] = ok ? tmx[src] : 0.0;
+        }
+        // this wave's tiles of the chunk: lanes wv, wv + 4, ...
+        unsigned long long mine = todo & (0x1111111111111111ull << wv);
+        auto load = [&](int j, d4 &v, int64_t &s) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(src & 0xffffffff), j);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(src >> 32), j);
+            s = (int64_t)(((uint64_t)hi << 32) | lo);
+            v = s >= 0 ? *(const d4 *)(ctiles + s * kTileElems + 4 * lane)
+                       : d4{0.0, 0.0, 0.0, 0.0};
+        };
+        if (!mine) continue;
+        int j = __ffsll((long long)mine) - 1;
+        mine &= mine - 1;
+        d4 v;
+        int64_t s;
+        load(j, v, s);
+        for (;;) {
+            const bool more = mine != 0;
+            int j2 = 0;
+            d4 v2 = v;
+            int64_t s2 = -1;
+            if (more) {
+                j2 = __ffsll((long long)mine) - 1;
+                mine &= mine - 1;
+                load(j2, v2, s2);
+            }
+            const int64_t t = b + c0 + j;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) M[(4 * k + g) * (kTile + 1) + c] = v[k];
+            wfence();
+            // lane holds (r, c) = (4 k + g, c) of the new tile, i.e.
+            // (c, 4 k + g) of the source
+            d4 u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k] = M[c * (kTile + 1) + 4 * k + g];
+            wfence();
+            *(d4 *)(ctiles + t * kTileElems + 4 * lane) = u;
+            if (tsq) {
+                uint32_t rc[4] = {0u, 0u, 0u, 0u};   // byte i % 4 of word i / 4: row i
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned long long m = __ballot(u[r] != 0.0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        rc[r] |= (uint32_t)__popcll((m >> (16 * q)) & 0xffffull) << (8 * q);
+                }
+                if (lane == 0) trc[t] = make_uint4(rc[0], rc[1], rc[2], rc[3]);
+            }
+            if (!more) break;
+            j = j2;
+            v = v2;
+            s = s2;
+        }
+    }
+}
+
+hipError_t bsr_mirror(int64_t nb, const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
+                      const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                      double *ctiles, double *tsq, int32_t *tnz, double *tmn, double *tmx,
+                      uint4 *trc, int *bad, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_mirror, dim3((unsigned)nb), dim3(256), 0, st, nb, clo, cwoff, crt,
+                       ctb, ccnt, ccols, ctiles, tsq, tnz, tmn, tmx, trc, bad);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- norm, compaction
@@ -803,11 +935,12 @@ hipError_t bsr_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cwoff
 
 hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64_t *cwoff,
                           const uint2 *crt, const int32_t *plo, const int64_t *pwoff,
-                          int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st) {
+                          int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st,
+                          bool upper) {
     const int64_t np = (nb + kPanel - 1) / kPanel;
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_panel_cols, dim3((unsigned)np), dim3(64), bsr_lds_words(n) * 4, st, nb,
-                       clo, cwoff, crt, plo, pwoff, pcnt, pofs, pcols);
+                       clo, cwoff, crt, plo, pwoff, pcnt, pofs, pcols, upper ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -862,12 +995,12 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
-                             int64_t nwork, hipStream_t st) {
+                             int64_t nwork, hipStream_t st, bool upper) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, owner, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg);
+                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0);
     return hipGetLastError();
 }
 

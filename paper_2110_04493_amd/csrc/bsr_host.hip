@@ -117,7 +117,8 @@ int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts) {
 // tile_norms the product also leaves each tile's share of ||I + T~||_F^2 and
 // its nonzero count in P.c_sq / P.c_nz.  *ctiles_out receives the number of
 // candidate tiles.
-int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out) {
+int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out,
+                 bool upper) {
     hipStream_t st = P.st;
     TileSet &ts = P.tsT;
     const int64_t n = T.n, nb = ts.nb;
@@ -176,12 +177,12 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         CHK(scan(P, (const int64_t *)P.p_words.p, (int64_t *)P.p_woff.p, np));
         HIPCHK(bsr_panel_cols(n, nb, clo, cwoff, (const uint2 *)P.c_rt.p,
                               (const int32_t *)P.p_lo.p, (const int64_t *)P.p_woff.p,
-                              (int64_t *)P.p_cnt.p, nullptr, nullptr, st));
+                              (int64_t *)P.p_cnt.p, nullptr, nullptr, st, upper));
         CHK(scan(P, (const int64_t *)P.p_cnt.p, (int64_t *)P.p_ofs.p, np));
         HIPCHK(bsr_panel_cols(n, nb, clo, cwoff, (const uint2 *)P.c_rt.p,
                               (const int32_t *)P.p_lo.p, (const int64_t *)P.p_woff.p,
                               (int64_t *)P.p_cnt.p, (const int64_t *)P.p_ofs.p,
-                              (int32_t *)P.p_cols.p, st));
+                              (int32_t *)P.p_cols.p, st, upper));
         HIPCHK(bsr_panel_groups((const int64_t *)P.p_cnt.p, nb, (int64_t *)P.p_gcnt.p, st));
         CHK(scan(P, (const int64_t *)P.p_gcnt.p, (int64_t *)P.p_gofs.p, np));
         CHK(ensure(P, P.p_owner, sizeof(int32_t) * (bsr_panel_work_bound(ctiles, nb) + 1)));
@@ -206,9 +207,22 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              tile_norms ? (double *)P.c_mn.p : nullptr,
                              tile_norms ? (double *)P.c_mx.p : nullptr,
                              tile_norms ? (uint4 *)P.c_rc.p : nullptr,
-                             tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st));
+                             tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st, upper));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
+    if (upper) {
+        // the tiles left of the diagonal: transposes of those right of it
+        CHK(ensure(P, P.mirror_bad, sizeof(int)));
+        HIPCHK(hipMemsetAsync(P.mirror_bad.p, 0, sizeof(int), st));
+        HIPCHK(bsr_mirror(nb, (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
+                          (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
+                          (const int64_t *)P.c_cnt.p, (const int32_t *)P.c_cols.p,
+                          (double *)P.c_tiles.p, tile_norms ? (double *)P.c_sq.p : nullptr,
+                          tile_norms ? (int32_t *)P.c_nz.p : nullptr,
+                          tile_norms ? (double *)P.c_mn.p : nullptr,
+                          tile_norms ? (double *)P.c_mx.p : nullptr,
+                          tile_norms ? (uint4 *)P.c_rc.p : nullptr, (int *)P.mirror_bad.p, st));
+    }
     *ctiles_out = ctiles;
     return EXPM_OK;
 }
@@ -277,7 +291,10 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     // the FPIM's filter (forward steps): a threshold from the candidate's
     // 1-norm instead of Algorithm 4.1
     const bool fpim = P.fpim_eps > 0.0 && !use_fixed;
-    CHK(tile_product(P, T.view(), prof, true, &ctiles));
+    // an exactly symmetric T (symmetric H, see forward) gives a symmetric
+    // candidate: only its tiles on and right of the diagonal are formed
+    const bool upper = P.sym_h;
+    CHK(tile_product(P, T.view(), prof, true, &ctiles, upper));
     // ||I + T~||_F and the nonzero candidate count
     CHK(ensure(P, P.b_sq, sizeof(double) * (nb + 1)));
     CHK(ensure(P, P.b_nz, sizeof(int64_t) * (nb + 1)));
@@ -333,7 +350,15 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hl + 9, (int64_t *)P.tmp2.p + nb, sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
+        if (upper && round == 0) {
+            hl[10] = 0;
+            HIPCHK(hipMemcpyAsync(hl + 10, P.mirror_bad.p, sizeof(int), hipMemcpyDeviceToHost,
+                                  st));
+        }
         CHK(sync(P));
+        if (upper && round == 0 && (int)hl[10])
+            return fail(EXPM_EHIP, "internal error: the candidate of a symmetric iterate has "
+                                   "an unsymmetric tile pattern");
         memcpy(&h, P.host, sizeof h);
         kept = hl[8];
         cand_nz = hl[9];
@@ -363,8 +388,20 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
         const int64_t fma = hl[16] - T.nnz;
         S.tile_launches += 1;
         S.tile_ms += t1;
-        S.tile_flops += 2.0 * (double)fma + 2.0 * (double)T.nnz;
-        S.tile_bytes += 12.0 * (double)T.nnz + 8.0 * (double)(n + 1) + 12.0 * (double)cand_nz;
+        if (upper) {
+            // the product forms the candidate on and right of the diagonal:
+            // (fma + nnz(T)) / 2 partial products land there (a symmetric
+            // pattern puts nnz(T) of them on the diagonal), with at most
+            // (nnz(T) + n) / 2 entries of T added (the 2T term); it still
+            // reads all of T, and writes at most (cand_nz + n) / 2 candidates
+            S.tile_flops += (double)fma + (double)T.nnz + (double)T.nnz + (double)n;
+            S.tile_bytes += 12.0 * (double)T.nnz + 8.0 * (double)(n + 1) +
+                            6.0 * (double)(cand_nz + n);
+        } else {
+            S.tile_flops += 2.0 * (double)fma + 2.0 * (double)T.nnz;
+            S.tile_bytes += 12.0 * (double)T.nnz + 8.0 * (double)(n + 1) +
+                            12.0 * (double)cand_nz;
+        }
         if (stat_i > 0 && stat_i < EXPM_MAXSTEP) {
             S.t_sym_ms[stat_i] = t0;
             S.t_num_ms[stat_i] = t1;

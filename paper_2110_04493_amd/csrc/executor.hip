@@ -647,6 +647,7 @@ int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal) {
     CHK(sync(P));
     int f[3];
     memcpy(f, P.host, sizeof f);
+    P.last_sym = f[0] && f[1];
     if (f[0] && (f[1] || f[2])) {
         *normal = 1;
         release(P, Ht);
@@ -682,6 +683,59 @@ int detect_normal(expm_plan_s &P, const DCsr &H, double nh, int *normal) {
     release(P, X);
     release(P, Y);
     release(P, Z);
+    return EXPM_OK;
+}
+
+// Is H exactly symmetric (pattern and values)?
+int exact_symmetry(expm_plan_s &P, const DCsr &H, int *sym) {
+    DCsr Ht;
+    auto free_ht = at_exit([&] { release(P, Ht); });
+    CHK(transpose_csr(P, H, Ht));
+    CHK(ensure(P, P.flags, sizeof(int) * 4));
+    const int ones[3] = {1, 1, 1};
+    HIPCHK(hipMemcpyAsync(P.flags.p, ones, sizeof ones, hipMemcpyHostToDevice, P.st));
+    HIPCHK(compare_csr(H.view(), Ht.view(), H.nnz, (int *)P.flags.p, P.st));
+    HIPCHK(hipMemcpyAsync(P.host, P.flags.p, sizeof(int) * 3, hipMemcpyDeviceToHost, P.st));
+    CHK(sync(P));
+    int f[3];
+    memcpy(f, P.host, sizeof f);
+    *sym = f[0] && f[1];
+    return EXPM_OK;
+}
+
+// T <- U + U^T for U the part of T on and right of the diagonal: an exactly
+// symmetric T_0 for symmetric H (the Taylor terms are symmetric up to
+// rounding only).  Uses P.S, P.Snew and P.Tnew as workspace.
+int symmetrize_upper(expm_plan_s &P, DCsr &T) {
+    const int64_t n = T.n;
+    hipStream_t st = P.st;
+    DCsr &Su = P.S, &Lt = P.Snew, &Tn = P.Tnew;
+    CHK(ensure(P, P.sym_cnt, sizeof(int64_t) * (n + 1)));
+    int64_t *cnt = (int64_t *)P.sym_cnt.p;
+    int64_t *hl = (int64_t *)P.host;
+    // the strictly upper part
+    CHK(ensure(P, Su.rp, sizeof(int64_t) * (n + 1)));
+    HIPCHK(triu_strict(T.view(), cnt, nullptr, nullptr, nullptr, st));
+    CHK(scan(P, cnt, (int64_t *)Su.rp.p, n));
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)Su.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    const int64_t nu = hl[0];
+    CHK(ensure_csr(P, Su, n, nu));
+    HIPCHK(triu_strict(T.view(), nullptr, (const int64_t *)Su.rp.p, (int32_t *)Su.ci.p,
+                       (double *)Su.v.p, st));
+    // its transpose, then U^T's rows followed by U's
+    CHK(transpose_csr(P, Su, Lt));
+    HIPCHK(sym_rows(Lt.view(), T.view(), cnt, nullptr, nullptr, nullptr, st));
+    CHK(ensure(P, Tn.rp, sizeof(int64_t) * (n + 1)));
+    CHK(scan(P, cnt, (int64_t *)Tn.rp.p, n));
+    HIPCHK(hipMemcpyAsync(hl, (int64_t *)Tn.rp.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CHK(sync(P));
+    const int64_t m = hl[0];
+    CHK(ensure_csr(P, Tn, n, m));
+    HIPCHK(sym_rows(Lt.view(), T.view(), nullptr, (const int64_t *)Tn.rp.p, (int32_t *)Tn.ci.p,
+                    (double *)Tn.v.p, st));
+    std::swap(T, Tn);
+    T.nnz = m;
     return EXPM_OK;
 }
 
@@ -902,6 +956,8 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     }
     TraceRange phase("expm plan (steps 1-3)");
     expm_analysis A{};
+    P.last_sym = -1;
+    P.sym_h = false;
     CHK(plan_input(P, Hv, eps, P.H0, &A));
     expm_stats &S = P.stats;
     const double nh = A.norm_h;
@@ -924,6 +980,14 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     S.a = a;
     const bool fpim = P.opts.filter_mode == EXPM_FILTER_FIXED_REL;
     P.fpim_eps = fpim ? eps : 0.0;
+    // Exactly symmetric H: every T_i is symmetric, so the tile products form
+    // only the candidate's upper triangle (T_0, symmetric up to rounding, is
+    // made exactly symmetric first)
+    if (P.opts.use_symmetry && N >= 1 && tiles_allowed(P, n)) {
+        int sym = P.last_sym;
+        if (sym < 0) CHK(exact_symmetry(P, P.H0, &sym));
+        P.sym_h = sym == 1;
+    }
     const bool diag = P.opts.diagnostics != 0;
     for (int i = 0; i < EXPM_MAXSTEP; ++i) S.sq_band[i] = -1;
     if (diag) CHK(ensure(P, P.bands, sizeof(long long) * 2 * (N + 1)));
@@ -1031,6 +1095,8 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         P.T.nnz = kept;
         S.theta0 = h.theta;
     }
+    if (P.sym_h) CHK(symmetrize_upper(P, P.T));
+    S.symmetric = P.sym_h ? 1 : 0;
     if (diag) HIPCHK(band_of(P.T.view(), P.perm_active ? (const int32_t *)P.order.p : nullptr,
                             (long long *)P.bands.p, st));
     // The current iterate; a checkpoint takes over P.T's buffers (no copy)
@@ -1527,6 +1593,7 @@ void expm_opts_default(expm_opts *o) {
     o->diagnostics = 0;
     o->literal_a = 0;
     o->batch_solo_n = 4096;
+    o->use_symmetry = 1;
 }
 
 int expm_plan(expm_plan_t *out, const expm_opts *opts) {
@@ -1544,7 +1611,8 @@ int expm_plan(expm_plan_t *out, const expm_opts *opts) {
     if (o.norm != EXPM_NORM_FRO && o.norm != EXPM_NORM_ONE)
         return fail(EXPM_EINVAL, "unknown norm %d", o.norm);
     if (o.exact_ri < 0 || o.exact_ri > 1 || o.diagnostics < 0 || o.diagnostics > 1 ||
-        o.literal_a < 0 || o.literal_a > 1 || o.batch_solo_n < 0)
+        o.literal_a < 0 || o.literal_a > 1 || o.batch_solo_n < 0 || o.use_symmetry < 0 ||
+        o.use_symmetry > 1)
         return fail(EXPM_EINVAL, "invalid option value");
     if (!(o.e_r >= 0.0) || o.max_filter_iter < 1 || o.normal < -1 || o.normal > 1 ||
         o.checkpoint_interval < -1 || o.reorder < -1 || o.reorder > 2 || o.profile < 0 ||

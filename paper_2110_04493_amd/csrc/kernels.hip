@@ -1343,3 +1343,73 @@ hipError_t gather_conj_z(const double *src, const int64_t *pos, int64_t m, doubl
 }
 
 }  // namespace xpm
+
+namespace xpm {
+
+// ============================================================== symmetric iterates
+// One wave per row.  k_triu: the entries right of the diagonal (count, or
+// write at orp).  k_sym_rows: row i of U^T + U, where Lt holds the
+// transposed strictly upper part (its row i: columns left of i), followed
+// by the entries of T on and right of the diagonal, in column order.
+
+__global__ void k_triu(CsrView T, int64_t *cnt, const int64_t *orp, int32_t *oci, double *ov) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= T.n) return;
+    int64_t k = 0;
+    const int64_t o = orp ? orp[i] : 0;
+    for (int64_t p0 = T.rp[i]; p0 < T.rp[i + 1]; p0 += kWave) {
+        const int64_t p = p0 + lane_id();
+        const bool take = p < T.rp[i + 1] && T.ci[p] > i;
+        const unsigned long long m = __ballot(take);
+        if (orp && take) {
+            const int64_t q = o + k + __popcll(m & lanemask_lt());
+            oci[q] = T.ci[p];
+            ov[q] = T.v[p];
+        }
+        k += __popcll(m);
+    }
+    if (!orp && lane_id() == 0) cnt[i] = k;
+}
+
+__global__ void k_sym_rows(CsrView Lt, CsrView T, int64_t *cnt, const int64_t *orp, int32_t *oci,
+                           double *ov) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= T.n) return;
+    const int64_t nl = Lt.rp[i + 1] - Lt.rp[i];
+    const int64_t o = orp ? orp[i] : 0;
+    if (orp)
+        for (int64_t q = lane_id(); q < nl; q += kWave) {
+            oci[o + q] = Lt.ci[Lt.rp[i] + q];
+            ov[o + q] = Lt.v[Lt.rp[i] + q];
+        }
+    int64_t k = nl;
+    for (int64_t p0 = T.rp[i]; p0 < T.rp[i + 1]; p0 += kWave) {
+        const int64_t p = p0 + lane_id();
+        const bool take = p < T.rp[i + 1] && T.ci[p] >= i;
+        const unsigned long long m = __ballot(take);
+        if (orp && take) {
+            const int64_t q = o + k + __popcll(m & lanemask_lt());
+            oci[q] = T.ci[p];
+            ov[q] = T.v[p];
+        }
+        k += __popcll(m);
+    }
+    if (!orp && lane_id() == 0) cnt[i] = k;
+}
+
+hipError_t triu_strict(CsrView T, int64_t *cnt, const int64_t *orp, int32_t *oci, double *ov,
+                       hipStream_t st) {
+    if (T.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_triu, dim3((T.n + 3) / 4), dim3(256), 0, st, T, cnt, orp, oci, ov);
+    return hipGetLastError();
+}
+
+hipError_t sym_rows(CsrView Lt, CsrView T, int64_t *cnt, const int64_t *orp, int32_t *oci,
+                    double *ov, hipStream_t st) {
+    if (T.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sym_rows, dim3((T.n + 3) / 4), dim3(256), 0, st, Lt, T, cnt, orp, oci,
+                       ov);
+    return hipGetLastError();
+}
+
+}  // namespace xpm

@@ -130,9 +130,11 @@ hipError_t bsr_cpattern(int64_t n, int64_t nb, const int32_t *lo, const int64_t 
 // panels of 4 block rows sharing column groups (bsr.hip)
 hipError_t bsr_panel_bounds(int64_t nb, const int32_t *clo, const int64_t *cwoff, int32_t *plo,
                             int64_t *pwords, hipStream_t st);
+// upper: only block columns at or right of each panel's first block row
 hipError_t bsr_panel_cols(int64_t n, int64_t nb, const int32_t *clo, const int64_t *cwoff,
                           const uint2 *crt, const int32_t *plo, const int64_t *pwoff,
-                          int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st);
+                          int64_t *pcnt, const int64_t *pofs, int32_t *pcols, hipStream_t st,
+                          bool upper = false);
 int64_t bsr_panel_work_bound(int64_t ctiles, int64_t nb);
 hipError_t bsr_panel_groups(const int64_t *pcnt, int64_t nb, int64_t *gcnt, hipStream_t st);
 hipError_t bsr_tcols(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
@@ -152,7 +154,14 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
-                             int64_t nwork, hipStream_t st);
+                             int64_t nwork, hipStream_t st, bool upper = false);
+// Symmetric C: candidate tiles left of the diagonal from the transposes of
+// those right of it, with their summaries (tsq may be NULL: values only);
+// *bad |= 1 where the mirror tile is missing.
+hipError_t bsr_mirror(int64_t nb, const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
+                      const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
+                      double *ctiles, double *tsq, int32_t *tnz, double *tmn, double *tmx,
+                      uint4 *trc, int *bad, hipStream_t st);
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
                           const double *bdg, double *bsq, int64_t *bnz, hipStream_t st);
@@ -320,6 +329,16 @@ hipError_t check_finite(const double *v, int64_t m, int *flag, hipStream_t st);
 // dst[q] = conj(src[pos[q]]).
 hipError_t gather_conj_z(const double *src, const int64_t *pos, int64_t m, double *dst,
                          hipStream_t st);
+
+// ------------------------------------------------------------- symmetric iterates
+// The entries right of the diagonal of T: row counts (orp == NULL) or the
+// entries written at orp.  sym_rows: U + U^T from the transposed strictly
+// upper part Lt and T's entries on and right of the diagonal (counts, or
+// the entries at orp; rows in column order).
+hipError_t triu_strict(CsrView T, int64_t *cnt, const int64_t *orp, int32_t *oci, double *ov,
+                       hipStream_t st);
+hipError_t sym_rows(CsrView Lt, CsrView T, int64_t *cnt, const int64_t *orp, int32_t *oci,
+                    double *ov, hipStream_t st);
 
 // ------------------------------------------------------------- extras.hip
 hipError_t fill_f64(double *p, int64_t m, double x, hipStream_t st);

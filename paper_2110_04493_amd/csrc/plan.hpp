@@ -154,6 +154,12 @@ struct expm_plan_s {
     double fpim_eps = 0.0;
     xpm::host::Buf colsum, amax, bands;
     int ordering = 0;   // the ordering applied by the running call: 0 none, 1 strips, 2 levels
+    // H exactly symmetric (and opts.use_symmetry): T_0 is made exactly
+    // symmetric and every squaring's tile product forms the candidate's
+    // upper triangle only (the row product keeps exact symmetry by itself)
+    bool sym_h = false;
+    int last_sym = -1;   // exact symmetry found by the last normality test (-1: not run)
+    xpm::host::Buf mirror_bad, sym_cnt;
 };
 
 namespace xpm {
@@ -246,7 +252,10 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
                 bool with_c = false);
 int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts);
 bool tiles_allowed(const expm_plan_s &P, int64_t n);
-int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out);
+// upper: a symmetric candidate, formed on and right of the diagonal and
+// mirrored to the left of it
+int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t *ctiles_out,
+                 bool upper = false);
 int tile_candidates(expm_plan_s &P, CsrView T, int64_t *cand);
 int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool use_fixed,
                     double theta_fixed, bool exact_alloc, int stat_i);

@@ -74,7 +74,7 @@ def test_choose_mn_rejects_bad_input():
                                          ("tile_min_fill", float("nan")), ("norm", 2),
                                          ("filter_mode", 3), ("exact_ri", 2),
                                          ("diagnostics", -1), ("literal_a", 2),
-                                         ("batch_solo_n", -1)])
+                                         ("batch_solo_n", -1), ("use_symmetry", 2)])
 def test_plan_rejects_invalid_options(field, value):
     """Option validation runs before the plan touches the device."""
     o = capi.expm_opts_default()

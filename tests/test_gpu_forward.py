@@ -280,3 +280,25 @@ def test_config2_full_size():
     Eg, sg, Eo, so = check_parity(H, eps)
     rs = np.add.reduceat(Eg.val, Eg.rowptr[:-1])
     assert np.max(np.abs(rs - 1)) <= 100 * eps
+
+
+@pytest.mark.parametrize("use_sym", [True, False])
+def test_symmetric_upper_triangle_products(use_sym):
+    """A symmetric H on the tile path: with use_symmetry the squarings form
+    only the candidate tiles on and right of the diagonal (the others are
+    their transposes); both ways agree with the oracle, and the returned E
+    is then exactly symmetric."""
+    L = W.grid_laplacian(70, 70, np.random.default_rng(81))
+    H = L.scaled(-40.0 / W.norm1(L))
+    Eg, sg, _, _ = check_parity(H, 1e-12, use_symmetry=use_sym, tile_min_fill=0.0)
+    assert sg["symmetric"] == (1 if use_sym else 0)
+    if use_sym:
+        D = np.zeros((H.n, H.n))
+        D[Eg.rows(), Eg.col] = Eg.val
+        assert np.array_equal(D, D.T)
+
+
+def test_symmetry_not_used_for_unsymmetric_h():
+    H = W.random_sparse(300, 0.02, 82, kind="general", scale=0.9)
+    _, sg, _, _ = check_parity(H, 1e-12, tile_min_fill=0.0)
+    assert sg["symmetric"] == 0
