@@ -430,6 +430,12 @@ __global__ __launch_bounds__(64) void k_panel_cols(int64_t nb, const int32_t *cl
 // of the next K before issuing the matrix instructions of the current one.
 // The kernel waits on memory far more than on the matrix cores, so it is
 // held to 128 registers: four waves per SIMD instead of two or three.
+// With upper (a symmetric T, hence a symmetric C) the panels' column lists
+// start at the panel's first block row, each wave skips the tiles left of
+// its diagonal, and every off-diagonal tile it forms is also written,
+// transposed through LDS, to the mirror tile left of the diagonal (with
+// the same sum of squares, nonzero count and magnitudes, and that tile's
+// own per-row counts).
 template <int kGroup>
 __global__ __launch_bounds__(kWave * kPanel)
 __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
@@ -442,7 +448,11 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
     int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
-    double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper) {
+    double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper,
+    int *__restrict__ bad) {
+    // with upper: one transposed tile per wave passes through LDS (rows
+    // padded to 17 doubles)
+    __shared__ double tsm[kPanel][kTile * (kTile + 1)];
     const int lane = lane_id();
     const int64_t w = blockIdx.x;
     if (w >= *nwork_dev) return;
@@ -501,6 +511,35 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
         // after far more data than the caches hold has passed: streaming
         // stores keep them from displacing the operand tiles still in use
         __builtin_nontemporal_store(acc[t], (d4 *)(ctiles + ct * kTileElems + 4 * lane));
+        // with upper, tile (J, I) left of the diagonal is this one's
+        // transpose: lane holds (4 k + lane / 16, lane % 16) of it, i.e.
+        // (lane % 16, 4 k + lane / 16) of acc
+        int64_t ctT = -1;
+        uint32_t rcT[4] = {0u, 0u, 0u, 0u};
+        if (upper && J[t] != (int)I) {
+            ctT = tile_of(clo, cwoff, crt, ctb, J[t], (int)I);
+            if (ctT < 0) {
+                if (lane == 0) atomicOr(bad, 1);
+            } else {
+                double *M = tsm[threadIdx.x / kWave];
+                const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) M[(4 * k + g) * (kTile + 1) + c] = acc[t][k];
+                wfence();
+                d4 u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[k] = M[c * (kTile + 1) + 4 * k + g];
+                wfence();
+                __builtin_nontemporal_store(u, (d4 *)(ctiles + ctT * kTileElems + 4 * lane));
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned long long m = __ballot(u[r] != 0.0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        rcT[r] |= (uint32_t)__popcll((m >> (16 * q)) & 0xffffull) << (8 * q);
+                }
+            }
+        }
         if (!tsq) continue;
         // the tile's sum of squares, its nonzero slots, their smallest and
         // largest magnitudes and the nonzeros of each of its 16 rows, all
@@ -543,124 +582,15 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
             tmn[ct] = mn;
             tmx[ct] = mx;
             trc[ct] = make_uint4(rc[0], rc[1], rc[2], rc[3]);
+            if (ctT >= 0) {   // the transpose: same values, its own row counts
+                tsq[ctT] = s;
+                tnz[ctT] = (int32_t)nz;
+                tmn[ctT] = mn;
+                tmx[ctT] = mx;
+                trc[ctT] = make_uint4(rcT[0], rcT[1], rcT[2], rcT[3]);
+            }
         }
     }
-}
-
-// ----------------------------------------------------------------- mirror
-// A symmetric C formed from its tiles on and right of the diagonal: every
-// candidate tile (I, J) with J < I becomes the transpose of tile (J, I),
-// with the same per-tile summaries (sum of squares, nonzero count, smallest
-// nonzero and largest magnitude) and its own per-row nonzero counts.  One
-// workgroup per block row, its four waves taking every fourth tile.  The
-// lanes look up the source tiles of 64 tiles at once (all lookups in
-// flight), and each wave loads its next tile while it transposes the
-// current one through LDS (rows padded to 17 doubles).  A missing tile
-// (J, I) sets *bad (C's pattern not symmetric) and leaves an empty tile.
-__global__ __launch_bounds__(256) void k_bsr_mirror(int64_t nb, const int32_t *__restrict__ clo,
-                                                    const int64_t *__restrict__ cwoff,
-                                                    const uint2 *__restrict__ crt,
-                                                    const int64_t *__restrict__ ctb,
-                                                    const int64_t *__restrict__ ccnt,
-                                                    const int32_t *__restrict__ ccols,
-                                                    double *__restrict__ ctiles, double *tsq,
-                                                    int32_t *tnz, double *tmn, double *tmx,
-                                                    uint4 *trc, int *bad) {
-    __shared__ double sm[4][kTile * (kTile + 1)];
-    const int wv = threadIdx.x / kWave, lane = lane_id();
-    const int64_t I = blockIdx.x;
-    if (I >= nb) return;
-    double *M = sm[wv];
-    const int g = lane >> 4, c = lane & 15;
-    const int64_t b = ctb[I], cnt = ccnt[I];
-    for (int64_t c0 = 0; c0 < cnt; c0 += kWave) {
-        // lane l: source of tile b + c0 + l (-1: on or right of the
-        // diagonal, or past the row; -2: missing)
-        const int64_t tl = c0 + lane;
-        int64_t src = -1;
-        if (tl < cnt) {
-            const int J = ccols[b + tl];
-            if (J < (int)I) {
-                src = tile_of(clo, cwoff, crt, ctb, J, (int)I);
-                if (src < 0) src = -2;
-            }
-        }
-        if (__ballot(src == -2) && lane == 0) atomicOr(bad, 1);
-        const unsigned long long todo = __ballot(src != -1);
-        if (!todo) break;   // columns ascend: nothing left of the diagonal remains
-        // the summaries shared with the source tile, one lane per tile (the
-        // source tiles lie right of the diagonal: the product wrote them)
-        if (tsq && wv == 0 && src != -1) {
-            const int64_t t = b + tl;
-            const bool ok = src >= 0;
-            tsq[t] = ok ? tsq[src] : 0.0;
-            tnz[t] = ok ? tnz[src] : 0;
-            tmn[t] = ok ? tmn[src] : INFINITY;
-            tmx[t] = ok ? tmx[src] : 0.0;
-        }
-        // this wave's tiles of the chunk: lanes wv, wv + 4, ...
-        unsigned long long mine = todo & (0x1111111111111111ull << wv);
-        auto load = [&](int j, d4 &v, int64_t &s) {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(src & 0xffffffff), j);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(src >> 32), j);
-            s = (int64_t)(((uint64_t)hi << 32) | lo);
-            v = s >= 0 ? *(const d4 *)(ctiles + s * kTileElems + 4 * lane)
-                       : d4{0.0, 0.0, 0.0, 0.0};
-        };
-        if (!mine) continue;
-        int j = __ffsll((long long)mine) - 1;
-        mine &= mine - 1;
-        d4 v;
-        int64_t s;
-        load(j, v, s);
-        for (;;) {
-            const bool more = mine != 0;
-            int j2 = 0;
-            d4 v2 = v;
-            int64_t s2 = -1;
-            if (more) {
-                j2 = __ffsll((long long)mine) - 1;
-                mine &= mine - 1;
-                load(j2, v2, s2);
-            }
-            const int64_t t = b + c0 + j;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) M[(4 * k + g) * (kTile + 1) + c] = v[k];
-            wfence();
-            // lane holds (r, c) = (4 k + g, c) of the new tile, i.e.
-            // (c, 4 k + g) of the source
-            d4 u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) u[k] = M[c * (kTile + 1) + 4 * k + g];
-            wfence();
-            *(d4 *)(ctiles + t * kTileElems + 4 * lane) = u;
-            if (tsq) {
-                uint32_t rc[4] = {0u, 0u, 0u, 0u};   // byte i % 4 of word i / 4: row i
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const unsigned long long m = __ballot(u[r] != 0.0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        rc[r] |= (uint32_t)__popcll((m >> (16 * q)) & 0xffffull) << (8 * q);
-                }
-                if (lane == 0) trc[t] = make_uint4(rc[0], rc[1], rc[2], rc[3]);
-            }
-            if (!more) break;
-            j = j2;
-            v = v2;
-            s = s2;
-        }
-    }
-}
-
-hipError_t bsr_mirror(int64_t nb, const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
-                      const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                      double *ctiles, double *tsq, int32_t *tnz, double *tmn, double *tmx,
-                      uint4 *trc, int *bad, hipStream_t st) {
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_mirror, dim3((unsigned)nb), dim3(256), 0, st, nb, clo, cwoff, crt,
-                       ctb, ccnt, ccols, ctiles, tsq, tnz, tmn, tmx, trc, bad);
-    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- norm, compaction
@@ -995,12 +925,12 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
-                             int64_t nwork, hipStream_t st, bool upper) {
+                             int64_t nwork, hipStream_t st, bool upper, int *bad) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, owner, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0);
+                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0, bad);
     return hipGetLastError();
 }
 

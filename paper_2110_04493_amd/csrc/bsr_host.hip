@@ -192,6 +192,10 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         // count, p_gofs[np], and surplus workgroups return at once
     }
     const int64_t nwork = bsr_panel_work_bound(ctiles, nb);
+    if (upper) {
+        CHK(ensure(P, P.mirror_bad, sizeof(int)));
+        HIPCHK(hipMemsetAsync(P.mirror_bad.p, 0, sizeof(int), st));
+    }
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
@@ -207,22 +211,10 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              tile_norms ? (double *)P.c_mn.p : nullptr,
                              tile_norms ? (double *)P.c_mx.p : nullptr,
                              tile_norms ? (uint4 *)P.c_rc.p : nullptr,
-                             tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st, upper));
+                             tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st, upper,
+                             upper ? (int *)P.mirror_bad.p : nullptr));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
-    if (upper) {
-        // the tiles left of the diagonal: transposes of those right of it
-        CHK(ensure(P, P.mirror_bad, sizeof(int)));
-        HIPCHK(hipMemsetAsync(P.mirror_bad.p, 0, sizeof(int), st));
-        HIPCHK(bsr_mirror(nb, (const int32_t *)P.c_lo.p, (const int64_t *)P.c_woff.p,
-                          (const uint2 *)P.c_rt.p, (const int64_t *)P.c_tb.p,
-                          (const int64_t *)P.c_cnt.p, (const int32_t *)P.c_cols.p,
-                          (double *)P.c_tiles.p, tile_norms ? (double *)P.c_sq.p : nullptr,
-                          tile_norms ? (int32_t *)P.c_nz.p : nullptr,
-                          tile_norms ? (double *)P.c_mn.p : nullptr,
-                          tile_norms ? (double *)P.c_mx.p : nullptr,
-                          tile_norms ? (uint4 *)P.c_rc.p : nullptr, (int *)P.mirror_bad.p, st));
-    }
     *ctiles_out = ctiles;
     return EXPM_OK;
 }

@@ -147,6 +147,9 @@ hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const i
 // scan with the total in ofs[m]): the panel or block row of each work item
 // of the tile product and adjoint kernels.
 hipError_t work_owner(const int64_t *ofs, int64_t m, int32_t *owner, hipStream_t st);
+// With upper (a symmetric C), the product forms the tiles on and right of
+// the diagonal and writes each off-diagonal one's transpose (values and
+// summaries) to the tile left of it; *bad |= 1 where that tile is missing.
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
@@ -154,14 +157,8 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
-                             int64_t nwork, hipStream_t st, bool upper = false);
-// Symmetric C: candidate tiles left of the diagonal from the transposes of
-// those right of it, with their summaries (tsq may be NULL: values only);
-// *bad |= 1 where the mirror tile is missing.
-hipError_t bsr_mirror(int64_t nb, const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
-                      const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
-                      double *ctiles, double *tsq, int32_t *tnz, double *tmn, double *tmx,
-                      uint4 *trc, int *bad, hipStream_t st);
+                             int64_t nwork, hipStream_t st, bool upper = false,
+                             int *bad = nullptr);
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
                           const double *bdg, double *bsq, int64_t *bnz, hipStream_t st);
