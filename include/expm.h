@@ -231,7 +231,9 @@ typedef struct {
     /* with opts.profile == 1, over the same launches as tile_flops: the
        algorithmic bytes of the tile product (12 per stored entry of T read
        once, 8 (n + 1) for its row pointer, 12 per nonzero candidate written
-       once), and the algorithmic flops and bytes of the adjoint tile step:
+       once; for a symmetric T, whose product forms the partial products on
+       and right of the diagonal only, tile_flops counts those), and the
+       algorithmic flops and bytes of the adjoint tile step:
        2 per partial product of G T^T and T^T G that lands in the mask plus
        2 per mask entry; 12 per stored entry of G and of T read once, 8 per
        mask entry written */

@@ -385,10 +385,11 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
             // (fma + nnz(T)) / 2 partial products land there (a symmetric
             // pattern puts nnz(T) of them on the diagonal), with at most
             // (nnz(T) + n) / 2 entries of T added (the 2T term); it still
-            // reads all of T, and writes at most (cand_nz + n) / 2 candidates
+            // reads all of T, and writes every candidate (the transposes
+            // too)
             S.tile_flops += (double)fma + (double)T.nnz + (double)T.nnz + (double)n;
             S.tile_bytes += 12.0 * (double)T.nnz + 8.0 * (double)(n + 1) +
-                            6.0 * (double)(cand_nz + n);
+                            12.0 * (double)cand_nz;
         } else {
             S.tile_flops += 2.0 * (double)fma + 2.0 * (double)T.nnz;
             S.tile_bytes += 12.0 * (double)T.nnz + 8.0 * (double)(n + 1) +
