@@ -172,13 +172,19 @@ def adjoint_roofline(tl: dict, pstats: dict, steps: int) -> dict:
 def numeric_roofline(stats: dict, n: int):
     """Algorithmic work of the numeric SpGEMM pass over all squaring steps.
     Per step i: flops = 2 * (partial products of T*T) + 2 * nnz(T_{i-1})
-    (the 2T term); bytes = 12 * nnz(T_{i-1}) + 8 * (n + 1) (input CSR read
-    once) + 12 * cand_i (candidate CSR written once)."""
+    (the 2T term), or, for a symmetric T on tiles (only the upper triangle
+    formed), (fma + nnz) + (nnz + n), as the library counts it; bytes =
+    12 * nnz(T_{i-1}) + 8 * (n + 1) (input CSR read once) + 12 * cand_i
+    (candidate CSR written once)."""
     fl = by = t = 0.0
     per = []
+    sym = bool(stats.get("symmetric", 0))
     for i in range(stats["N"]):
         fma, nin, cand = stats["sq_fma"][i], stats["sq_in"][i], stats["sq_cand"][i]
-        f = 2.0 * fma + 2.0 * nin
+        if sym and stats["sq_tiles"][i]:
+            f = float(fma + nin) + float(nin + n)
+        else:
+            f = 2.0 * fma + 2.0 * nin
         b = 12.0 * nin + 8.0 * (n + 1) + 12.0 * cand
         ms = stats["t_num_ms"][i]
         fl += f
