@@ -449,7 +449,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
     int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
     double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper,
-    int *__restrict__ bad) {
+    int *__restrict__ bad, int64_t *__restrict__ tmir) {
     // with upper: one transposed tile per wave passes through LDS (rows
     // padded to 17 doubles)
     __shared__ double tsm[kPanel][kTile * (kTile + 1)];
@@ -588,6 +588,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
                 tmn[ctT] = mn;
                 tmx[ctT] = mx;
                 trc[ctT] = make_uint4(rcT[0], rcT[1], rcT[2], rcT[3]);
+            }
+            if (tmir) {   // the pairing the filter passes use
+                tmir[ct] = ctT >= 0 ? ctT : -1;
+                if (ctT >= 0) tmir[ctT] = -2;
             }
         }
     }
@@ -925,12 +929,13 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int32_t *clo, const int64_t *cwoff, const uint2 *crt,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
-                             int64_t nwork, hipStream_t st, bool upper, int *bad) {
+                             int64_t nwork, hipStream_t st, bool upper, int *bad,
+                             int64_t *tmir) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
                        nwork_dev, owner, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0, bad);
+                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0, bad, tmir);
     return hipGetLastError();
 }
 

@@ -195,6 +195,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
     if (upper) {
         CHK(ensure(P, P.mirror_bad, sizeof(int)));
         HIPCHK(hipMemsetAsync(P.mirror_bad.p, 0, sizeof(int), st));
+        if (tile_norms) CHK(ensure(P, P.c_mir, sizeof(int64_t) * (ctiles + 1)));
     }
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
@@ -212,7 +213,8 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              tile_norms ? (double *)P.c_mx.p : nullptr,
                              tile_norms ? (uint4 *)P.c_rc.p : nullptr,
                              tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st, upper,
-                             upper ? (int *)P.mirror_bad.p : nullptr));
+                             upper ? (int *)P.mirror_bad.p : nullptr,
+                             upper && tile_norms ? (int64_t *)P.c_mir.p : nullptr));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     *ctiles_out = ctiles;
@@ -327,7 +329,8 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                 HIPCHK(filter_pass_tiles((const double *)P.c_tiles.p, (const double *)P.c_mn.p,
                                          (const double *)P.c_mx.p, (const double *)P.c_sq.p,
                                          ctiles, ctl, (double *)P.part.p, kParts,
-                                         (uint4 *)P.c_kc.p, st));
+                                         (uint4 *)P.c_kc.p, st,
+                                         upper ? (const int64_t *)P.c_mir.p : nullptr));
         // the passes' counts hold for the final threshold only when a pass
         // ran at it: not with a fixed threshold, nor when a = 0 (then no
         // tile lies between its smallest nonzero and the threshold 0)

@@ -372,19 +372,26 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
                                                                  const double *__restrict__ tsq,
                                                                  int64_t ntiles, FilterCtl *c,
                                                                  double *part,
-                                                                 uint4 *__restrict__ krc) {
+                                                                 uint4 *__restrict__ krc,
+                                                                 const int64_t *__restrict__ tmir) {
     typedef double v4 __attribute__((ext_vector_type(4)));
     if (c->done) return;
     const double theta = c->theta;
     constexpr int wpb = kRedBlock / kWave;
     const int lane = lane_id();
     double s = 0.0;
-    // the tile entries at or below theta and their counts above it, per row
-    auto take = [&](const v4 &x, int64_t t) {
+    // the tile entries at or below theta and their counts above it, per row;
+    // a tile with a mirror (tmir >= 0: the candidate is symmetric, the
+    // mirror its transpose) counts twice, and the mirror's row counts are
+    // this tile's column counts
+    auto take = [&](const v4 &x, int64_t t, int64_t mir) {
         uint32_t w[4];
+        const double wt = mir >= 0 ? 2.0 : 1.0;
+        int cc = 0;   // entries above theta in column lane % 16 of this lane's rows
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (fabs(x[r]) <= theta) s = fma(x[r], x[r], s);
+            if (fabs(x[r]) <= theta) s = fma(wt * x[r], x[r], s);
+            cc += fabs(x[r]) > theta;
             // entries above theta per tile row: lane l holds row l / 16 + 4 r
             // (column l % 16), so each 16-lane group of the ballot is one row
             const unsigned long long k = __ballot(fabs(x[r]) > theta);
@@ -394,19 +401,31 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
                 w[r] |= (uint32_t)__popcll((k >> (16 * g)) & 0xffffull) << (8 * g);
         }
         if (krc && lane == 0) krc[t] = make_uint4(w[0], w[1], w[2], w[3]);
+        if (krc && mir >= 0) {
+            cc += __shfl_xor(cc, 16);
+            cc += __shfl_xor(cc, 32);   // lane l: column l % 16's count
+            uint32_t u[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int col = 0; col < 16; ++col)
+                u[col >> 2] |= (uint32_t)__builtin_amdgcn_readlane(cc, col) << (8 * (col & 3));
+            if (lane == 0) krc[mir] = make_uint4(u[0], u[1], u[2], u[3]);
+        }
     };
     // each wave takes 64 consecutive tiles at a time: one lane per tile
     // reads its summaries (a tile wholly at or below theta adds its stored
     // sum of squares), then the tiles in between are read in order with the
     // next one's load in flight
+    // (with tmir, the tiles marked -2, mirrors of others, are left out)
     const int64_t nchunk = (ntiles + kWave - 1) / kWave;
     for (int64_t q = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; q < nchunk;
          q += (int64_t)gridDim.x * wpb) {
         const int64_t t0 = q * kWave, t = t0 + lane;
         bool mid = false;
-        if (t < ntiles && tmin[t] <= theta) {   // something at or below theta
+        int64_t mir = -1;
+        if (t < ntiles) mir = tmir ? tmir[t] : -1;
+        if (t < ntiles && mir != -2 && tmin[t] <= theta) {   // something at or below theta
             if (tmax[t] <= theta)
-                s += tsq[t];                      // everything at or below theta
+                s += (mir >= 0 ? 2.0 : 1.0) * tsq[t];      // everything at or below theta
             else
                 mid = true;
         }
@@ -426,7 +445,8 @@ __global__ __launch_bounds__(kRedBlock) void k_filter_pass_tiles(const double *_
                 tt2 = t0 + l;
                 x2 = *(const v4 *)(tiles + tt2 * 256 + 4 * lane);
             }
-            take(x, tt);
+            const int64_t mt = tmir ? tmir[tt] : -1;
+            take(x, tt, mt);
             if (!more) break;
             tt = tt2;
             x = x2;
@@ -469,10 +489,10 @@ __device__ void filter_pass_end(double s, double theta, FilterCtl *c, double *pa
 
 hipError_t filter_pass_tiles(const double *tiles, const double *tmin, const double *tmax,
                              const double *tsq, int64_t ntiles, FilterCtl *c, double *part,
-                             int nparts, uint4 *krc, hipStream_t st) {
+                             int nparts, uint4 *krc, hipStream_t st, const int64_t *tmir) {
     nparts = parts_for(ntiles * 16, nparts);
     hipLaunchKernelGGL(k_filter_pass_tiles, dim3(nparts), dim3(kRedBlock), 0, st, tiles, tmin,
-                       tmax, tsq, ntiles, c, part, krc);
+                       tmax, tsq, ntiles, c, part, krc, tmir);
     return hipGetLastError();
 }
 

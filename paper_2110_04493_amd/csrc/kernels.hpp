@@ -100,9 +100,15 @@ hipError_t filter_init_theta(FilterCtl *c, double theta, hipStream_t st);
 // row (the trc layout of the product); since a tile is read exactly when
 // its smallest nonzero is at most the threshold and its largest magnitude
 // above it, the last pass leaves the final counts of every such tile.
+// tmir (may be NULL): for a symmetric candidate formed on and right of the
+// diagonal, per tile the index of its mirror tile (its transpose, left of
+// the diagonal), -1 for a diagonal tile and -2 for a mirror: mirrors are
+// not read, their partners count twice, and krc of each mirror receives
+// its partner's column counts.
 hipError_t filter_pass_tiles(const double *tiles, const double *tmin, const double *tmax,
                              const double *tsq, int64_t ntiles, FilterCtl *c, double *part,
-                             int nparts, uint4 *krc, hipStream_t st);
+                             int nparts, uint4 *krc, hipStream_t st,
+                             const int64_t *tmir = nullptr);
 hipError_t filter_pass(const double *v, const int64_t *count, int64_t maxcount, FilterCtl *c,
                        double *part, int nparts, hipStream_t st);
 // Kept counts per row (|v| > theta); with addI the identity is added (E = I + T).
@@ -149,7 +155,8 @@ hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const i
 hipError_t work_owner(const int64_t *ofs, int64_t m, int32_t *owner, hipStream_t st);
 // With upper (a symmetric C), the product forms the tiles on and right of
 // the diagonal and writes each off-diagonal one's transpose (values and
-// summaries) to the tile left of it; *bad |= 1 where that tile is missing.
+// summaries) to the tile left of it; *bad |= 1 where that tile is missing;
+// tmir (may be NULL) receives the pairing of filter_pass_tiles.
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
@@ -158,7 +165,7 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
                              int64_t nwork, hipStream_t st, bool upper = false,
-                             int *bad = nullptr);
+                             int *bad = nullptr, int64_t *tmir = nullptr);
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
                           const double *bdg, double *bsq, int64_t *bnz, hipStream_t st);

@@ -160,6 +160,7 @@ struct expm_plan_s {
     bool sym_h = false;
     int last_sym = -1;   // exact symmetry found by the last normality test (-1: not run)
     xpm::host::Buf mirror_bad, sym_cnt;
+    xpm::host::Buf c_mir;   // per candidate tile: its mirror, -1 (diagonal) or -2 (a mirror)
 };
 
 namespace xpm {
