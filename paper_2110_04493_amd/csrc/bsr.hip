@@ -178,8 +178,9 @@ __global__ void k_bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, con
 }
 
 // One wave per tile: the tile is assembled in LDS in both operand layouts
-// from its row segments (16 lanes per row, consecutive entries) and written
-// out whole, 32 contiguous bytes per lane.
+// (the B layout only when tA is NULL) from its row segments (16 lanes per
+// row, consecutive entries) and written out whole, 32 contiguous bytes per
+// lane.
 __global__ __launch_bounds__(256) void k_bsr_assemble(CsrView T, int64_t ntiles,
                                                       const int32_t *tcols, const int32_t *trows,
                                                       const int64_t *seg, double *tA,
@@ -206,15 +207,37 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(CsrView T, int64_t ntiles,
             const int64_t p = (s >> 5) + j;
             const int c = T.ci[p] & 15;
             const double v = T.v[p];
-            bA[offA(r, c)] = v;
+            if (tA) bA[offA(r, c)] = v;
             bB[offB(r, c)] = v;
         }
     }
     wfence();
-    *(d4 *)(tA + tt * kTileElems + 4 * lane) = *(const d4 *)(bA + 4 * lane);
+    if (tA) *(d4 *)(tA + tt * kTileElems + 4 * lane) = *(const d4 *)(bA + 4 * lane);
     *(d4 *)(tB + tt * kTileElems + 4 * lane) = *(const d4 *)(bB + 4 * lane);
     (void)tcols;
     (void)trows;
+}
+
+// For a symmetric tile pattern: mir[t] = the index of tile t's transpose
+// (block row and column exchanged).  A missing transpose sets *bad and
+// leaves 0, a valid index.
+__global__ void k_bsr_tile_mirrors(int64_t ntiles, const int32_t *lo, const int64_t *woff,
+                                   const uint2 *rt, const int64_t *tb, const int32_t *tcols,
+                                   const int32_t *trows, int64_t *mir, int *bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t m = tile_of(lo, woff, rt, tb, tcols[t], trows[t]);
+    if (m < 0) atomicOr(bad, 1);
+    mir[t] = m < 0 ? 0 : m;
+}
+
+hipError_t bsr_tile_mirrors(int64_t ntiles, const int32_t *lo, const int64_t *woff,
+                            const uint2 *rt, const int64_t *tb, const int32_t *tcols,
+                            const int32_t *trows, int64_t *mir, int *bad, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_tile_mirrors, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
+                       st, ntiles, lo, woff, rt, tb, tcols, trows, mir, bad);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- C pattern
@@ -449,7 +472,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
     int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
     double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper,
-    int *__restrict__ bad, int64_t *__restrict__ tmir) {
+    int *__restrict__ bad, int64_t *__restrict__ tmir, const int64_t *__restrict__ amir) {
     // with upper: one transposed tile per wave passes through LDS (rows
     // padded to 17 doubles)
     __shared__ double tsm[kPanel][kTile * (kTile + 1)];
@@ -487,9 +510,11 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
     }
     const int64_t t0 = tb[I], nk = tb[I + 1] - t0;
     const int jlo = J[0], jhi = last_of(J, ng);
+    // A operand T_IK: tile t0 + r in the A layout, or, for a symmetric T
+    // assembled in the B layout only (amir), the B layout of its transpose
     auto item = [&](int64_t r, int &K, int &a) {
         K = tcols[t0 + r];
-        a = (int)(t0 + r);
+        a = amir ? (int)amir[t0 + r] : (int)(t0 + r);
     };
     auto look = [&](int K, int (&ti)[kGroup]) {
         const int loK = lo[K];
@@ -930,12 +955,13 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
                              int64_t nwork, hipStream_t st, bool upper, int *bad,
-                             int64_t *tmir) {
+                             int64_t *tmir, const int64_t *amir) {
     if (nwork == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
-                       dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols, tA, tB, pgofs,
-                       nwork_dev, owner, pofs, pcols, clo, cwoff, crt, ctb,
-                       ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0, bad, tmir);
+                       dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols,
+                       amir ? tB : tA, tB, pgofs, nwork_dev, owner, pofs, pcols, clo, cwoff, crt,
+                       ctb, ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0, bad, tmir,
+                       amir);
     return hipGetLastError();
 }
 

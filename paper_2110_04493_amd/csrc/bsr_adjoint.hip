@@ -78,8 +78,9 @@ __global__ void k_bsr_colsort(const int64_t *ptr, int64_t nb, const int32_t *uk,
 // One wave per work item: a block row I of T and up to kGroup of its tiles.
 // kPart 0 computes the whole step; kPart 1 only 2 G + G T^T (unmasked, into
 // out) and kPart 2 adds T^T G to it, masks, and writes both layouts: the two
-// halves need fewer registers each, so more waves fit on a SIMD.
-template <int kGroup, int kPart>
+// halves need fewer registers each, so more waves fit on a SIMD.  kSym: T is
+// symmetric and assembled in the B layout only (tA unused).
+template <int kGroup, int kPart, bool kSym>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bsr_adjoint(
     int64_t nb,
     // T = T_{k-1}: pattern (with each tile's block column) and tiles
@@ -146,12 +147,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             K = gcols[g0 + r];
             a = (int)(g0 + r);
         };
-        auto look = [&](int K, int (&ti)[kGroup]) {
+        if constexpr (kSym) {
+            // (T_JK)^T = T_KJ: tile J of T's block row K, in the B layout
+            const int jlo = J[0], jhi = last_of(J, ng);
+            auto look = [&](int K, int (&ti)[kGroup]) {
+                const int loK = tlo[K];
+                const int64_t w0 = twoff[K], WK = twoff[K + 1] - w0;
+                if (WK == 0 || jhi < loK || jlo >= loK + 32 * (int)WK) return;
+                const int64_t tbK = ttb[K];
 #pragma unroll
-            for (int t = 0; t < kGroup; ++t)
-                ti[t] = tile_in_row(loJ[t], w0J[t], WJ[t], tbJ[t], trt, K);
-        };
-        pipe_products<kGroup>(gtb[I + 1] - g0, item, look, gA, tA, acc);
+                for (int t = 0; t < kGroup; ++t)
+                    if (t < ng) ti[t] = tile_in_row(loK, w0, WK, tbK, trt, J[t]);
+            };
+            pipe_products<kGroup>(gtb[I + 1] - g0, item, look, gA, tB, acc);
+        } else {
+            // tile K of T's block row J in the A layout, read as a B
+            // operand, is (T_JK)^T
+            auto look = [&](int K, int (&ti)[kGroup]) {
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t)
+                    ti[t] = tile_in_row(loJ[t], w0J[t], WJ[t], tbJ[t], trt, K);
+            };
+            pipe_products<kGroup>(gtb[I + 1] - g0, item, look, gA, tA, acc);
+        }
     }
     if constexpr (kPart == 1) {
 #pragma unroll
@@ -262,17 +280,20 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
                        const int64_t *gofs, const int32_t *owner, double *out, double *outA,
-                       const int64_t *nwork_dev, int64_t nwork, hipStream_t st) {
+                       const int64_t *nwork_dev, int64_t nwork, hipStream_t st, bool symT) {
     if (nwork == 0) return hipSuccess;
     const dim3 grid((unsigned)((nwork + 3) / 4)), block(256);
 #define XPM_ADJ_ARGS                                                                           \
     nb, tlo, twoff, trt, ttb, tcols, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, \
         gofs, owner, out, outA, nwork_dev
-    if (kAdjSplit) {
-        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1>), grid, block, 0, st, XPM_ADJ_ARGS);
-        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2>), grid, block, 0, st, XPM_ADJ_ARGS);
+    if (symT) {
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1, true>), grid, block, 0, st, XPM_ADJ_ARGS);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2, true>), grid, block, 0, st, XPM_ADJ_ARGS);
+    } else if (kAdjSplit) {
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1, false>), grid, block, 0, st, XPM_ADJ_ARGS);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2, false>), grid, block, 0, st, XPM_ADJ_ARGS);
     } else {
-        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 0>), grid, block, 0, st, XPM_ADJ_ARGS);
+        hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 0, false>), grid, block, 0, st, XPM_ADJ_ARGS);
     }
 #undef XPM_ADJ_ARGS
     return hipGetLastError();

@@ -10,8 +10,8 @@ namespace xpm {
 namespace host {
 
 void release(expm_plan_s &P, TileSet &ts) {
-    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt,   &ts.cnt,
-                  &ts.tb, &ts.tA,    &ts.tB,   &ts.cols, &ts.rows, &ts.seg};
+    Buf *all[] = {&ts.lo, &ts.words, &ts.woff, &ts.rt,   &ts.cnt, &ts.tb,
+                  &ts.tA, &ts.tB,    &ts.cols, &ts.rows, &ts.seg, &ts.mir};
     for (Buf *b : all) release(P, *b);
     ts.nb = ts.ntiles = 0;
 }
@@ -98,16 +98,28 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
 
 // T's values as tiles of the pattern, in both operand layouts: a table of
 // row segments, then every tile assembled whole.
-int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts) {
+int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts, bool b_only) {
     const size_t nt = (size_t)(ts.ntiles > 0 ? ts.ntiles : 1);
-    CHK(ensure(P, ts.tA, sizeof(double) * 256 * nt));
+    ts.b_only = b_only;
+    if (b_only) {
+        // symmetric T: the A layout of tile (I, K) is the B layout of (K, I)
+        CHK(ensure(P, ts.mir, sizeof(int64_t) * nt));
+        CHK(ensure(P, P.mirror_bad, sizeof(int)));
+        HIPCHK(bsr_tile_mirrors(ts.ntiles, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
+                                (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p,
+                                (const int32_t *)ts.cols.p, (const int32_t *)ts.rows.p,
+                                (int64_t *)ts.mir.p, (int *)P.mirror_bad.p, P.st));
+    } else {
+        CHK(ensure(P, ts.tA, sizeof(double) * 256 * nt));
+    }
     CHK(ensure(P, ts.tB, sizeof(double) * 256 * nt));
     CHK(ensure(P, ts.seg, sizeof(int64_t) * 16 * nt));
     HIPCHK(hipMemsetAsync(ts.seg.p, 0, sizeof(int64_t) * 16 * nt, P.st));
     HIPCHK(bsr_seg(T, (const int32_t *)ts.lo.p, (const int64_t *)ts.woff.p,
                    (const uint2 *)ts.rt.p, (const int64_t *)ts.tb.p, (int64_t *)ts.seg.p, P.st));
     HIPCHK(bsr_assemble(T, ts.ntiles, (const int32_t *)ts.cols.p, (const int32_t *)ts.rows.p,
-                        (const int64_t *)ts.seg.p, (double *)ts.tA.p, (double *)ts.tB.p, P.st));
+                        (const int64_t *)ts.seg.p, b_only ? nullptr : (double *)ts.tA.p,
+                        (double *)ts.tB.p, P.st));
     return EXPM_OK;
 }
 
@@ -123,7 +135,11 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
     TileSet &ts = P.tsT;
     const int64_t n = T.n, nb = ts.nb;
     int64_t *hl = (int64_t *)P.host;
-    CHK(bsr_tiles(P, T, ts));
+    if (upper) {   // flags a pattern found unsymmetric (T's tiles or C's)
+        CHK(ensure(P, P.mirror_bad, sizeof(int)));
+        HIPCHK(hipMemsetAsync(P.mirror_bad.p, 0, sizeof(int), st));
+    }
+    CHK(bsr_tiles(P, T, ts, upper));
     // C's tile pattern (its counts already read back by bsr_pattern when it
     // ran with with_c just before)
     const int32_t *lo = (const int32_t *)ts.lo.p;
@@ -192,11 +208,7 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
         // count, p_gofs[np], and surplus workgroups return at once
     }
     const int64_t nwork = bsr_panel_work_bound(ctiles, nb);
-    if (upper) {
-        CHK(ensure(P, P.mirror_bad, sizeof(int)));
-        HIPCHK(hipMemsetAsync(P.mirror_bad.p, 0, sizeof(int), st));
-        if (tile_norms) CHK(ensure(P, P.c_mir, sizeof(int64_t) * (ctiles + 1)));
-    }
+    if (upper && tile_norms) CHK(ensure(P, P.c_mir, sizeof(int64_t) * (ctiles + 1)));
     if (prof) HIPCHK(hipEventRecord(P.ev[1], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     HIPCHK(bsr_numeric_panel(nb, lo, woff, rt, tb, (const int32_t *)ts.cols.p,
@@ -214,7 +226,8 @@ int tile_product(expm_plan_s &P, CsrView T, bool prof, bool tile_norms, int64_t 
                              tile_norms ? (uint4 *)P.c_rc.p : nullptr,
                              tile_norms ? (double *)P.b_dg.p : nullptr, nwork, st, upper,
                              upper ? (int *)P.mirror_bad.p : nullptr,
-                             upper && tile_norms ? (int64_t *)P.c_mir.p : nullptr));
+                             upper && tile_norms ? (int64_t *)P.c_mir.p : nullptr,
+                             upper ? (const int64_t *)ts.mir.p : nullptr));
     if (prof) HIPCHK(hipEventRecord(P.ev[2], st));
     if (light_profile(P)) CHK(ktimer_mark(P, 0));
     *ctiles_out = ctiles;
@@ -463,7 +476,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     hipStream_t st = P.st;
     TileSet &T = P.tsT, &G = P.tsG;
     const int64_t nb = T.nb;
-    if (!t_tiles_ready) CHK(bsr_tiles(P, Tp.view(), T));
+    // a symmetric T (symmetric H) is assembled in the B layout only
+    if (!t_tiles_ready) CHK(bsr_tiles(P, Tp.view(), T, P.sym_h));
     const CsrView Gv{Tk.n, (const int64_t *)Tk.rp.p, (const int32_t *)Tk.ci.p, g};
     double fg;
     if (!g_pattern_ready) CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));
@@ -510,7 +524,8 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
                        (const int64_t *)P.g_ofs.p, (const int32_t *)P.g_owner.p,
                        (double *)P.adj_tiles.p,
-                       (double *)P.adj_tilesA.p, (const int64_t *)P.g_ofs.p + nb, nwork, st));
+                       (double *)P.adj_tilesA.p, (const int64_t *)P.g_ofs.p + nb, nwork, st,
+                       T.b_only));
     if (light_profile(P)) CHK(ktimer_mark(P, 1));
     if (prof) {
         HIPCHK(hipEventRecord(P.ev[5], st));

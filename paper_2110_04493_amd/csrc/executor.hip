@@ -173,11 +173,11 @@ int reserve_as(expm_plan_s &P, DCsr &d, const DCsr &ref) {
 }
 
 int reserve_as(expm_plan_s &P, TileSet &t, const TileSet &ref) {
-    Buf *a[] = {&t.lo, &t.words, &t.woff, &t.rt, &t.cnt, &t.tb, &t.tA, &t.tB, &t.cols, &t.rows,
-                &t.seg};
+    Buf *a[] = {&t.lo, &t.words, &t.woff, &t.rt,   &t.cnt, &t.tb,
+                &t.tA, &t.tB,    &t.cols, &t.rows, &t.seg, &t.mir};
     const Buf *r[] = {&ref.lo, &ref.words, &ref.woff, &ref.rt,   &ref.cnt, &ref.tb,
-                      &ref.tA, &ref.tB,    &ref.cols, &ref.rows, &ref.seg};
-    for (int j = 0; j < 11; ++j) CHK(reserve_as(P, *a[j], *r[j]));
+                      &ref.tA, &ref.tB,    &ref.cols, &ref.rows, &ref.seg, &ref.mir};
+    for (int j = 0; j < 12; ++j) CHK(reserve_as(P, *a[j], *r[j]));
     return EXPM_OK;
 }
 

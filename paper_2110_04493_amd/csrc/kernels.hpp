@@ -149,6 +149,11 @@ hipError_t bsr_seg(CsrView T, const int32_t *lo, const int64_t *woff, const uint
                    const int64_t *tb, int64_t *seg, hipStream_t st);
 hipError_t bsr_assemble(CsrView T, int64_t ntiles, const int32_t *tcols, const int32_t *trows,
                         const int64_t *seg, double *tA, double *tB, hipStream_t st);
+// Symmetric tile pattern: mir[t] = index of tile t's transpose (0 and
+// *bad |= 1 where it is missing).
+hipError_t bsr_tile_mirrors(int64_t ntiles, const int32_t *lo, const int64_t *woff,
+                            const uint2 *rt, const int64_t *tb, const int32_t *tcols,
+                            const int32_t *trows, int64_t *mir, int *bad, hipStream_t st);
 // owner[w] = i for every w in [ofs[i], ofs[i + 1]), i < m (ofs: exclusive
 // scan with the total in ofs[m]): the panel or block row of each work item
 // of the tile product and adjoint kernels.
@@ -156,7 +161,9 @@ hipError_t work_owner(const int64_t *ofs, int64_t m, int32_t *owner, hipStream_t
 // With upper (a symmetric C), the product forms the tiles on and right of
 // the diagonal and writes each off-diagonal one's transpose (values and
 // summaries) to the tile left of it; *bad |= 1 where that tile is missing;
-// tmir (may be NULL) receives the pairing of filter_pass_tiles.
+// tmir (may be NULL) receives the pairing of filter_pass_tiles.  amir (may
+// be NULL): T symmetric and assembled in the B layout only; its A operands
+// are read from the B layout of each tile's transpose (amir[t]).
 hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                              const int64_t *tb, const int32_t *tcols, const double *tA,
                              const double *tB, const int64_t *pgofs, const int64_t *nwork_dev,
@@ -165,7 +172,8 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              const int64_t *ctb, double *ctiles, int64_t n, double *tsq,
                              int32_t *tnz, double *tmn, double *tmx, uint4 *trc, double *bdg,
                              int64_t nwork, hipStream_t st, bool upper = false,
-                             int *bad = nullptr, int64_t *tmir = nullptr);
+                             int *bad = nullptr, int64_t *tmir = nullptr,
+                             const int64_t *amir = nullptr);
 hipError_t bsr_norm_tiles(int64_t n, int64_t nb, const int64_t *ctb, const int64_t *ccnt,
                           const int32_t *ccols, const double *tsq, const int32_t *tnz,
                           const double *bdg, double *bsq, int64_t *bnz, hipStream_t st);
@@ -200,7 +208,8 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int32_t *gcols, const double *gA, const double *gB,
                        const int64_t *cptr, const int32_t *ck, const int64_t *ct,
                        const int64_t *gofs, const int32_t *owner, double *out, double *outA,
-                       const int64_t *nwork_dev, int64_t nwork, hipStream_t st);
+                       const int64_t *nwork_dev, int64_t nwork, hipStream_t st,
+                       bool symT = false);   // symT: T symmetric, B layout only
 hipError_t bsr_gather(CsrView T, const int32_t *lo, const int64_t *woff, const uint2 *rt,
                       const int64_t *tb, const double *tiles, double *out, hipStream_t st);
 

@@ -37,7 +37,11 @@ struct DCsr {
 struct TileSet {
     Buf lo, words, woff, rt, cnt, tb, tA, tB, cols, rows, seg;   // cols / rows: block column
                                                                  // and row of every tile
+    // for a symmetric matrix assembled in the B layout only: per tile the
+    // index of its transpose, whose B-layout bytes are this tile's A layout
+    Buf mir;
     int64_t nb = 0, ntiles = 0;
+    bool b_only = false;
 };
 
 
@@ -251,7 +255,8 @@ void log_call(const expm_plan_s &P, int64_t n, double eps, int status);
 void free_adjoint_state(expm_plan_s &P);
 int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fill,
                 bool with_c = false);
-int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts);
+// b_only: T is symmetric; only the B layout is assembled, with ts.mir
+int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts, bool b_only = false);
 bool tiles_allowed(const expm_plan_s &P, int64_t n);
 // upper: a symmetric candidate, formed on and right of the diagonal and
 // mirrored to the left of it
