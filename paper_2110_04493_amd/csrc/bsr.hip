@@ -444,88 +444,18 @@ __global__ __launch_bounds__(64) void k_panel_cols(int64_t nb, const int32_t *cl
     if (lane == 0 && !pcols) pcnt[p] = carry;
 }
 
-// One workgroup per work item (panel, group of kGroup panel columns); wave
-// w computes block row kPanel p + w.  C_IJ = (2 I) T_IJ + sum_K T_IK T_KJ
-// with K ascending over the tiles of T's block row I.  The lanes first find,
-// 64 values of K at a time, the tiles T_KJ of the group (one K per lane, all
-// lookups in flight together); the product loop then walks the K that have
-// at least one, reading their indices with readlane, and loads the operands
-// of the next K before issuing the matrix instructions of the current one.
-// The kernel waits on memory far more than on the matrix cores, so it is
-// held to 128 registers: four waves per SIMD instead of two or three.
-// With upper (a symmetric T, hence a symmetric C) the panels' column lists
-// start at the panel's first block row, each wave skips the tiles left of
-// its diagonal, and every off-diagonal tile it forms is also written,
-// transposed through LDS, to the mirror tile left of the diagonal (with
-// the same sum of squares, nonzero count and magnitudes, and that tile's
-// own per-row counts).
+// The end of a panel work item: each output tile t < ng with act[t] that is
+// in C's pattern is written (streaming stores) with its summaries; with
+// upper its transpose too, passed through the wave's LDS tile M.
 template <int kGroup>
-__global__ __launch_bounds__(kWave * kPanel)
-__attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
-    int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
-    const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
-    const int32_t *__restrict__ tcols, const double *__restrict__ tA,
-    const double *__restrict__ tB, const int64_t *__restrict__ pgofs,
-    const int64_t *__restrict__ nwork_dev, const int32_t *__restrict__ owner,
-    const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
+__device__ __forceinline__ void panel_epilogue(
+    int64_t I, int ng, const int (&J)[kGroup], const bool (&act)[kGroup], const d4 (&acc)[kGroup],
     const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
     const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
     int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
     double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper,
-    int *__restrict__ bad, int64_t *__restrict__ tmir, const int64_t *__restrict__ amir) {
-    // with upper: one transposed tile per wave passes through LDS (rows
-    // padded to 17 doubles)
-    __shared__ double tsm[kPanel][kTile * (kTile + 1)];
+    int *__restrict__ bad, int64_t *__restrict__ tmir, double *M) {
     const int lane = lane_id();
-    const int64_t w = blockIdx.x;
-    if (w >= *nwork_dev) return;
-    const int64_t p = owner[w];   // the panel: pgofs[p] <= w < pgofs[p + 1]
-    const int64_t I = p * kPanel + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (I >= nb) return;
-    const int64_t g0 = (w - pgofs[p]) * kGroup;
-    const int ng = (int)min<int64_t>(kGroup, pofs[p + 1] - pofs[p] - g0);
-    int J[kGroup];
-    // with upper, the tiles left of the diagonal are not formed here (they
-    // are the transposes of tiles right of it)
-    bool act[kGroup];
-#pragma unroll
-    for (int t = 0; t < kGroup; ++t) {
-        J[t] = t < ng ? pcols[pofs[p] + g0 + t] : -1;
-        act[t] = t < ng && (!upper || J[t] >= (int)I);
-    }
-    d4 acc[kGroup];
-#pragma unroll
-    for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    {
-        const d4 two = two_identity_a(lane);
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t) {
-            if (t >= ng) break;
-            if (!act[t]) continue;
-            const int64_t tt = tile_of(lo, woff, rt, tb, I, J[t]);
-            if (tt < 0) continue;
-            const d4 b = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
-            acc[t] = mfma16(two, b, acc[t]);
-        }
-    }
-    const int64_t t0 = tb[I], nk = tb[I + 1] - t0;
-    const int jlo = J[0], jhi = last_of(J, ng);
-    // A operand T_IK: tile t0 + r in the A layout, or, for a symmetric T
-    // assembled in the B layout only (amir), the B layout of its transpose
-    auto item = [&](int64_t r, int &K, int &a) {
-        K = tcols[t0 + r];
-        a = amir ? (int)amir[t0 + r] : (int)(t0 + r);
-    };
-    auto look = [&](int K, int (&ti)[kGroup]) {
-        const int loK = lo[K];
-        const int64_t w0 = woff[K], WK = woff[K + 1] - w0;
-        if (WK == 0 || jhi < loK || jlo >= loK + 32 * (int)WK) return;
-        const int64_t tbK = tb[K];
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t)
-            if (act[t]) ti[t] = tile_in_row(loK, w0, WK, tbK, rt, J[t]);
-    };
-    pipe_products<kGroup>(nk, item, look, tA, tB, acc);
 #pragma unroll
     for (int t = 0; t < kGroup; ++t) {
         if (t >= ng) break;
@@ -546,7 +476,6 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
             if (ctT < 0) {
                 if (lane == 0) atomicOr(bad, 1);
             } else {
-                double *M = tsm[threadIdx.x / kWave];
                 const int g = lane >> 4, c = lane & 15;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) M[(4 * k + g) * (kTile + 1) + c] = acc[t][k];
@@ -620,6 +549,94 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
             }
         }
     }
+}
+
+// One workgroup per work item (panel, group of kGroup panel columns); wave
+// w computes block row kPanel p + w.  C_IJ = (2 I) T_IJ + sum_K T_IK T_KJ
+// with K ascending over the tiles of T's block row I.  The lanes first find,
+// 64 values of K at a time, the tiles T_KJ of the group (one K per lane, all
+// lookups in flight together); the product loop then walks the K that have
+// at least one, reading their indices with readlane, and loads the operands
+// of the next K before issuing the matrix instructions of the current one.
+// The kernel waits on memory far more than on the matrix cores, so it is
+// held to 128 registers: four waves per SIMD instead of two or three.
+// With upper (a symmetric T, hence a symmetric C) the panels' column lists
+// start at the panel's first block row, each wave skips the tiles left of
+// its diagonal, and every off-diagonal tile it forms is also written,
+// transposed through LDS, to the mirror tile left of the diagonal (with
+// the same sum of squares, nonzero count and magnitudes, and that tile's
+// own per-row counts).
+template <int kGroup>
+__global__ __launch_bounds__(kWave * kPanel)
+__attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
+    int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
+    const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
+    const int32_t *__restrict__ tcols, const double *__restrict__ tA,
+    const double *__restrict__ tB, const int64_t *__restrict__ pgofs,
+    const int64_t *__restrict__ nwork_dev, const int32_t *__restrict__ owner,
+    const int64_t *__restrict__ pofs, const int32_t *__restrict__ pcols,
+    const int32_t *__restrict__ clo, const int64_t *__restrict__ cwoff,
+    const uint2 *__restrict__ crt, const int64_t *__restrict__ ctb, double *__restrict__ ctiles,
+    int64_t n, double *__restrict__ tsq, int32_t *__restrict__ tnz, double *__restrict__ tmn,
+    double *__restrict__ tmx, uint4 *__restrict__ trc, double *__restrict__ bdg, int upper,
+    int *__restrict__ bad, int64_t *__restrict__ tmir, const int64_t *__restrict__ amir,
+    int xcd) {
+    // with upper: one transposed tile per wave passes through LDS (rows
+    // padded to 17 doubles)
+    __shared__ double tsm[kPanel][kTile * (kTile + 1)];
+    const int lane = lane_id();
+    const int64_t nw = *nwork_dev;
+    const int64_t w = xcd ? xcd_item(blockIdx.x, nw) : (int64_t)blockIdx.x;
+    if (w < 0 || w >= nw) return;
+    const int64_t p = owner[w];   // the panel: pgofs[p] <= w < pgofs[p + 1]
+    const int64_t I = p * kPanel + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (I >= nb) return;
+    const int64_t g0 = (w - pgofs[p]) * kGroup;
+    const int ng = (int)min<int64_t>(kGroup, pofs[p + 1] - pofs[p] - g0);
+    int J[kGroup];
+    // with upper, the tiles left of the diagonal are not formed here (they
+    // are the transposes of tiles right of it)
+    bool act[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        J[t] = t < ng ? pcols[pofs[p] + g0 + t] : -1;
+        act[t] = t < ng && (!upper || J[t] >= (int)I);
+    }
+    d4 acc[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    {
+        const d4 two = two_identity_a(lane);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            if (t >= ng) break;
+            if (!act[t]) continue;
+            const int64_t tt = tile_of(lo, woff, rt, tb, I, J[t]);
+            if (tt < 0) continue;
+            const d4 b = *(const d4 *)(tB + tt * kTileElems + 4 * lane);
+            acc[t] = mfma16(two, b, acc[t]);
+        }
+    }
+    const int64_t t0 = tb[I], nk = tb[I + 1] - t0;
+    const int jlo = J[0], jhi = last_of(J, ng);
+    // A operand T_IK: tile t0 + r in the A layout, or, for a symmetric T
+    // assembled in the B layout only (amir), the B layout of its transpose
+    auto item = [&](int64_t r, int &K, int &a) {
+        K = tcols[t0 + r];
+        a = amir ? (int)amir[t0 + r] : (int)(t0 + r);
+    };
+    auto look = [&](int K, int (&ti)[kGroup]) {
+        const int loK = lo[K];
+        const int64_t w0 = woff[K], WK = woff[K + 1] - w0;
+        if (WK == 0 || jhi < loK || jlo >= loK + 32 * (int)WK) return;
+        const int64_t tbK = tb[K];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t)
+            if (act[t]) ti[t] = tile_in_row(loK, w0, WK, tbK, rt, J[t]);
+    };
+    pipe_products<kGroup>(nk, item, look, tA, tB, acc);
+    panel_epilogue<kGroup>(I, ng, J, act, acc, clo, cwoff, crt, ctb, ctiles, n, tsq, tnz, tmn, tmx,
+                           trc, bdg, upper, bad, tmir, tsm[threadIdx.x / kWave]);
 }
 
 // ----------------------------------------------------------------- norm, compaction
@@ -957,11 +974,17 @@ hipError_t bsr_numeric_panel(int64_t nb, const int32_t *lo, const int64_t *woff,
                              int64_t nwork, hipStream_t st, bool upper, int *bad,
                              int64_t *tmir, const int64_t *amir) {
     if (nwork == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)nwork),
+    // work items spread over the XCDs in contiguous ranges (EXPM_TILE_XCD=0:
+    // round robin, the hardware's order)
+    static const int xcd = [] {
+        const char *e = getenv("EXPM_TILE_XCD");
+        return e && e[0] == '0' ? 0 : 1;
+    }();
+    hipLaunchKernelGGL(k_bsr_numeric_panel<kPanelGroup>, dim3((unsigned)(nwork + 8)),
                        dim3(kWave * kPanel), 0, st, nb, lo, woff, rt, tb, tcols,
                        amir ? tB : tA, tB, pgofs, nwork_dev, owner, pofs, pcols, clo, cwoff, crt,
                        ctb, ctiles, n, tsq, tnz, tmn, tmx, trc, bdg, upper ? 1 : 0, bad, tmir,
-                       amir);
+                       amir, xcd);
     return hipGetLastError();
 }
 

@@ -97,10 +97,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ ck,
     const int64_t *__restrict__ ct,
     const int64_t *__restrict__ gofs, const int32_t *__restrict__ owner,
-    double *__restrict__ out, double *__restrict__ outA, const int64_t *__restrict__ nwork_dev) {
+    double *__restrict__ out, double *__restrict__ outA, const int64_t *__restrict__ nwork_dev,
+    int xcd) {
     const int lane = lane_id();
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (w >= *nwork_dev) return;   // the grid covers a bound of the count
+    // blocks of four work items; with xcd, contiguous ranges of blocks per
+    // XCD (the grid covers a bound of the count, plus 8 blocks)
+    const int64_t nw = *nwork_dev, wpb = blockDim.x / kWave;
+    const int64_t blk = xcd ? xcd_item(blockIdx.x, (nw + wpb - 1) / wpb) : (int64_t)blockIdx.x;
+    if (blk < 0) return;
+    const int64_t w = blk * wpb + threadIdx.x / kWave;
+    if (w >= nw) return;
     const int64_t I = owner[w];   // the block row: gofs[I] <= w < gofs[I + 1]
     const int64_t t0 = (w - gofs[I]) * kGroup;             // first tile (rank in block row I)
     const int64_t cntI = ttb[I + 1] - ttb[I];
@@ -282,10 +288,14 @@ hipError_t bsr_adjoint(int64_t nb, const int32_t *tlo, const int64_t *twoff, con
                        const int64_t *gofs, const int32_t *owner, double *out, double *outA,
                        const int64_t *nwork_dev, int64_t nwork, hipStream_t st, bool symT) {
     if (nwork == 0) return hipSuccess;
-    const dim3 grid((unsigned)((nwork + 3) / 4)), block(256);
+    static const int xcd = [] {
+        const char *e = getenv("EXPM_TILE_XCD");
+        return e && e[0] == '0' ? 0 : 1;
+    }();
+    const dim3 grid((unsigned)((nwork + 3) / 4 + 8)), block(256);
 #define XPM_ADJ_ARGS                                                                           \
     nb, tlo, twoff, trt, ttb, tcols, tA, tB, glo, gwoff, grt, gtb, gcols, gA, gB, cptr, ck, ct, \
-        gofs, owner, out, outA, nwork_dev
+        gofs, owner, out, outA, nwork_dev, xcd
     if (symT) {
         hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 1, true>), grid, block, 0, st, XPM_ADJ_ARGS);
         hipLaunchKernelGGL((k_bsr_adjoint<kAdjGroup, 2, true>), grid, block, 0, st, XPM_ADJ_ARGS);

@@ -90,4 +90,16 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
 }
 
+// Work item of block b when the count is known only on the device: XCD
+// b % 8 takes the contiguous range [x per, (x + 1) per), per = ceil(count /
+// 8), in the order its blocks are dispatched, so that work items close in
+// the list (which read the same operands) share that XCD's L2.  -1 for a
+// surplus block; the grid needs at least 8 per blocks (count + 7).
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t count) {
+    constexpr int64_t kXcd = 8;
+    const int64_t per = (count + kXcd - 1) / kXcd, j = b / kXcd;
+    if (j >= per) return -1;
+    return (b % kXcd) * per + j;
+}
+
 }  // namespace xpm
