@@ -482,24 +482,38 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
     double fg;
     if (!g_pattern_ready) CHK(bsr_pattern(P, Gv, Tk.nnz, G, &fg));
     if (!(g_pattern_ready && g_tiles_ready)) CHK(bsr_tiles(P, Gv, G));
-    // T's block columns as sorted lists (T^T's block rows)
-    CHK(ensure(P, P.tc_cnt, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.tc_ptr, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.tc_fill, sizeof(int64_t) * (nb + 1)));
-    CHK(ensure(P, P.tc_k, sizeof(int32_t) * 2 * (T.ntiles + 1)));
-    CHK(ensure(P, P.tc_t, sizeof(int64_t) * 2 * (T.ntiles + 1)));
-    int32_t *uk = (int32_t *)P.tc_k.p, *ck = uk + (T.ntiles + 1);
-    int64_t *ut = (int64_t *)P.tc_t.p, *ct = ut + (T.ntiles + 1);
-    HIPCHK(hipMemsetAsync(P.tc_cnt.p, 0, sizeof(int64_t) * (nb + 1), st));
-    HIPCHK(bsr_colcount(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
-                        (const uint2 *)T.rt.p, (int64_t *)P.tc_cnt.p, st));
-    CHK(scan(P, (const int64_t *)P.tc_cnt.p, (int64_t *)P.tc_ptr.p, nb));
-    HIPCHK(hipMemcpyAsync(P.tc_fill.p, P.tc_ptr.p, sizeof(int64_t) * nb, hipMemcpyDeviceToDevice,
-                          st));
-    HIPCHK(bsr_colfill(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
-                       (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (int64_t *)P.tc_fill.p,
-                       uk, ut, st));
-    HIPCHK(bsr_colsort((const int64_t *)P.tc_ptr.p, nb, uk, ut, ck, ct, st));
+    // T's block columns as sorted lists (T^T's block rows): for a symmetric
+    // T its block rows themselves, each tile T_IK standing for its mirror
+    // T_KI (the mirror index of the B-layout-only assembly)
+    const int64_t *cptr;
+    const int32_t *ck;
+    const int64_t *ct;
+    if (T.b_only) {
+        cptr = (const int64_t *)T.tb.p;
+        ck = (const int32_t *)T.cols.p;
+        ct = (const int64_t *)T.mir.p;
+    } else {
+        CHK(ensure(P, P.tc_cnt, sizeof(int64_t) * (nb + 1)));
+        CHK(ensure(P, P.tc_ptr, sizeof(int64_t) * (nb + 1)));
+        CHK(ensure(P, P.tc_fill, sizeof(int64_t) * (nb + 1)));
+        CHK(ensure(P, P.tc_k, sizeof(int32_t) * 2 * (T.ntiles + 1)));
+        CHK(ensure(P, P.tc_t, sizeof(int64_t) * 2 * (T.ntiles + 1)));
+        int32_t *uk = (int32_t *)P.tc_k.p, *sk = uk + (T.ntiles + 1);
+        int64_t *ut = (int64_t *)P.tc_t.p, *stt = ut + (T.ntiles + 1);
+        HIPCHK(hipMemsetAsync(P.tc_cnt.p, 0, sizeof(int64_t) * (nb + 1), st));
+        HIPCHK(bsr_colcount(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
+                            (const uint2 *)T.rt.p, (int64_t *)P.tc_cnt.p, st));
+        CHK(scan(P, (const int64_t *)P.tc_cnt.p, (int64_t *)P.tc_ptr.p, nb));
+        HIPCHK(hipMemcpyAsync(P.tc_fill.p, P.tc_ptr.p, sizeof(int64_t) * nb,
+                              hipMemcpyDeviceToDevice, st));
+        HIPCHK(bsr_colfill(nb, (const int32_t *)T.lo.p, (const int64_t *)T.woff.p,
+                           (const uint2 *)T.rt.p, (const int64_t *)T.tb.p, (int64_t *)P.tc_fill.p,
+                           uk, ut, st));
+        HIPCHK(bsr_colsort((const int64_t *)P.tc_ptr.p, nb, uk, ut, sk, stt, st));
+        cptr = (const int64_t *)P.tc_ptr.p;
+        ck = sk;
+        ct = stt;
+    }
     // work items: four output tiles of one block row of T each
     CHK(ensure(P, P.g_cnt, sizeof(int64_t) * (nb + 1)));
     CHK(ensure(P, P.g_ofs, sizeof(int64_t) * (nb + 1)));
@@ -521,7 +535,7 @@ int adjoint_step_bsr(expm_plan_s &P, const DCsr &Tp, const DCsr &Tk, const doubl
                        (const double *)T.tB.p, (const int32_t *)G.lo.p,
                        (const int64_t *)G.woff.p, (const uint2 *)G.rt.p,
                        (const int64_t *)G.tb.p, (const int32_t *)G.cols.p, (const double *)G.tA.p,
-                       (const double *)G.tB.p, (const int64_t *)P.tc_ptr.p, ck, ct,
+                       (const double *)G.tB.p, cptr, ck, ct,
                        (const int64_t *)P.g_ofs.p, (const int32_t *)P.g_owner.p,
                        (double *)P.adj_tiles.p,
                        (double *)P.adj_tilesA.p, (const int64_t *)P.g_ofs.p + nb, nwork, st,
