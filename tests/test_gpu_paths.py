@@ -212,3 +212,41 @@ def test_row_product_global_scratch():
     print(f"[global scratch rows] relF={rel:.2e} only={og},{oo}", flush=True)
     assert rel <= TOL and ok
     assert (sg["M"], sg["N"]) == (so["M"], so["N"])
+
+
+_WORK_ORDER_CHILD = r"""
+import sys, numpy as np
+sys.path.insert(0, sys.argv[2])
+sys.path.insert(0, sys.argv[3])
+from paper_2110_04493_amd import workloads as W
+from test_gpu_adjoint import gpu_grad
+from _helpers import run_gpu
+H, eps = W.config5(48)
+E, _ = run_gpu(H, eps, tile_min_fill=0.0)
+dH, _ = gpu_grad(H, eps, density=0.2, tile_min_fill=0.0)
+np.savez(sys.argv[1], col=E.col, val=E.val, dH=dH)
+"""
+
+
+def test_work_order_does_not_change_bits(tmp_path):
+    """The tile product and adjoint kernels give every work item the same
+    arithmetic wherever it runs: a child process with the work items in the
+    hardware's round-robin order over the XCDs (EXPM_TILE_XCD=0) returns the
+    same bits of E and dL/dH as the default per-XCD ranges."""
+    import os
+    import subprocess
+    import sys
+    H, eps = W.config5(48)
+    E, _ = run_gpu(H, eps, tile_min_fill=0.0)
+    dH, _ = gpu_grad(H, eps, density=0.2, tile_min_fill=0.0)
+    out = tmp_path / "rr.npz"
+    here = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ, EXPM_TILE_XCD="0")
+    print("[work order] child with round-robin work items", flush=True)
+    r = subprocess.run([sys.executable, "-c", _WORK_ORDER_CHILD, str(out), os.path.dirname(here),
+                        here], env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    z = np.load(out)
+    assert np.array_equal(z["col"], E.col)
+    assert np.array_equal(z["val"].view(np.uint64), E.val.view(np.uint64))
+    assert np.array_equal(z["dH"].view(np.uint64), dH.view(np.uint64))
