@@ -2009,7 +2009,7 @@ void expm_free(expm_plan_t p) {
                     &P.p_owner, &P.g_owner, &P.p_cols, &P.c_sq, &P.c_nz, &P.c_mn, &P.c_mx, &P.c_rc, &P.c_kc, &P.b_dg};
     for (Buf *b : tbufs) release(P, *b);
     Buf *rbufs[] = {&P.order, &P.newidx, &P.hmap, &P.emap, &P.ro_rb, &P.ro_d0, &P.ro_d1,
-                    &P.ro_d3, &P.ro_q0, &P.ro_q1, &P.ro_cell, &P.ro_cnt, &P.ro_off,
+                    &P.ro_d3, &P.ro_q0, &P.ro_q1, &P.ro_ell, &P.ro_cell, &P.ro_cnt, &P.ro_off,
                     &P.ro_pcnt, &P.ro_pw, &P.ro_pofs, &P.ro_gbits};
     for (Buf *b : rbufs) release(P, *b);
     for (Buf *b : {&P.colsum, &P.amax, &P.bands}) release(P, *b);

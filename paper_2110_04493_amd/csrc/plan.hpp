@@ -145,7 +145,8 @@ struct expm_plan_s {
     // replaces H0 and E = P^T E' P; hmap / emap give, for each entry of H' / of
     // the returned E, the index of the matching entry of H / of E'
     bool perm_active = false;
-    xpm::host::Buf order, newidx, hmap, emap, ro_rb, ro_d0, ro_d1, ro_d3, ro_q0, ro_q1, ro_cell,
+    xpm::host::Buf order, newidx, hmap, emap, ro_rb, ro_d0, ro_d1, ro_d3, ro_q0, ro_q1, ro_ell,
+        ro_cell,
         ro_cnt, ro_off, ro_pcnt, ro_pw, ro_pofs, ro_gbits;
     xpm::host::DCsr Hp, Eperm;
     // tile fill of T from which the tile product is used (opts.tile_min_fill;

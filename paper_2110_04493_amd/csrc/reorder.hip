@@ -65,13 +65,48 @@ __device__ __forceinline__ void for_neighbours(const CsrView &G, int v, F &&f) {
     }
 }
 
+// G's rows in a fixed width of kEll slots per node (unused slots -1), so
+// that a search level reads a node's neighbours in one round trip (two
+// 16-byte loads) instead of two (the row bounds, then the columns); a row
+// longer than kEll is marked with -2 in its first slot and read from G.
+constexpr int kEll = 8;
+
+__global__ void k_ell(CsrView G, int32_t *ell) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= G.n) return;
+    const int64_t b = G.rp[v], d = G.rp[v + 1] - b;
+    int32_t r[kEll];
+#pragma unroll
+    for (int j = 0; j < kEll; ++j) r[j] = j < d ? G.ci[b + j] : -1;
+    if (d > kEll) r[0] = -2;
+    int4 *o = (int4 *)(ell + v * kEll);
+    o[0] = make_int4(r[0], r[1], r[2], r[3]);
+    o[1] = make_int4(r[4], r[5], r[6], r[7]);
+}
+
+template <typename F>
+__device__ __forceinline__ void for_neighbours_ell(const CsrView &G, const int32_t *ell, int v,
+                                                   F &&f) {
+    const int4 *e = (const int4 *)(ell + (int64_t)v * kEll);
+    const int4 x = e[0], y = e[1];
+    if (x.x == -2) {
+        for_neighbours(G, v, f);
+        return;
+    }
+    const int u[kEll] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int j = 0; j < kEll; ++j)
+        if (u[j] >= 0) f(u[j]);
+}
+
 // Breadth-first distances from *srcp over G's out-edges, in one workgroup
 // (level-synchronous; the frontier of a mesh is small).  dist must hold -1.
 // Nodes not reached get (largest distance + 1).  Writes res[0] = the node
 // maximising dist (or min(dist, other) when other is given), smallest index
 // on ties, and res[1] = the largest distance.
-__global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *srcp,
-                                                     int32_t *dist, int32_t *q0, int32_t *q1,
+__global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *ell,
+                                                     const int32_t *srcp, int32_t *dist,
+                                                     int32_t *q0, int32_t *q1,
                                                      const int32_t *other, int32_t *res) {
     __shared__ int s_cnt[3];   // rotating frontier sizes, as in k_bfs_lds
     __shared__ long long s_best[kBfsThreads / kWave];
@@ -95,7 +130,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *s
         if (size == 0) break;
         for (int i = tid; i < size; i += kBfsThreads) {
             const int v = cur[i];
-            for_neighbours(G, v, [&](int u) {
+            for_neighbours_ell(G, ell, v, [&](int u) {
                 // a stale -1 only costs a failed compare-and-swap
                 if (dist[u] == -1 && atomicCAS(&dist[u], -1, level + 1) == -1)
                     nxt[atomicAdd(&s_cnt[c1], 1)] = u;
@@ -143,10 +178,10 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(CsrView G, const int32_t *s
 constexpr int kQCap = 4096;
 constexpr int64_t kBfsLdsNodes = 200000;   // bit map + queues stay under 64 KB
 
-__global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_t *srcp,
-                                                         int32_t *dist, int32_t *gq0,
-                                                         int32_t *gq1, const int32_t *other,
-                                                         int32_t *res) {
+__global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_t *ell,
+                                                         const int32_t *srcp, int32_t *dist,
+                                                         int32_t *gq0, int32_t *gq1,
+                                                         const int32_t *other, int32_t *res) {
     extern __shared__ uint32_t sm[];
     // frontier sizes rotate through three counters, so that one barrier per
     // level suffices: level L reads s_cnt[L % 3], counts the next frontier
@@ -179,7 +214,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_lds(CsrView G, const int32_
         if (size == 0) break;
         for (int i = tid; i < size; i += kBfsThreads) {
             const int v = i < kQCap ? lcur[i] : gcur[i];
-            for_neighbours(G, v, [&](int u) {
+            for_neighbours_ell(G, ell, v, [&](int u) {
                 const uint32_t bit = 1u << (u & 31);
                 if (vis[u >> 5] & bit) return;
                 if (atomicOr(&vis[u >> 5], bit) & bit) return;
@@ -500,16 +535,20 @@ int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *acti
     int32_t *rb = (int32_t *)P.ro_rb.p, *d0 = (int32_t *)P.ro_d0.p, *d1 = (int32_t *)P.ro_d1.p,
             *d3 = (int32_t *)P.ro_d3.p, *q0 = (int32_t *)P.ro_q0.p, *q1 = (int32_t *)P.ro_q1.p;
     HIPCHK(hipMemsetAsync(rb, 0, sizeof(int32_t) * 16, st));
+    CHK(ensure(P, P.ro_ell, sizeof(int32_t) * kEll * n));
+    int32_t *ell = (int32_t *)P.ro_ell.p;
+    hipLaunchKernelGGL(k_ell, dim3(blocks_for(n, 256)), dim3(256), 0, st, G, ell);
+    HIPCHK(hipGetLastError());
     auto bfs = [&](const int32_t *srcp, int32_t *dist, const int32_t *other, int32_t *res) {
         if (n <= kBfsLdsNodes) {
             const size_t lds = sizeof(uint32_t) * ((n + 31) / 32) + sizeof(int32_t) * 2 * kQCap;
-            hipLaunchKernelGGL(k_bfs_lds, dim3(1), dim3(kBfsThreads), lds, st, G, srcp, dist, q0,
-                               q1, other, res);
+            hipLaunchKernelGGL(k_bfs_lds, dim3(1), dim3(kBfsThreads), lds, st, G, ell, srcp, dist,
+                               q0, q1, other, res);
             return hipGetLastError();
         }
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, dist, n, -1);
-        hipLaunchKernelGGL(k_bfs, dim3(1), dim3(kBfsThreads), 0, st, G, srcp, dist, q0, q1, other,
-                           res);
+        hipLaunchKernelGGL(k_bfs, dim3(1), dim3(kBfsThreads), 0, st, G, ell, srcp, dist, q0, q1,
+                           other, res);
         return hipGetLastError();
     };
     // rb: [0] node 0 | [1..2] u1, max d0 | [3..4] u3 = argmax min(d0, d1), max d1 |
