@@ -27,7 +27,7 @@ namespace xpm {
 constexpr int kBfsThreads = 1024;
 constexpr int kCellMax = 256;      // largest cell the ordering accepts
 constexpr int kLevelMax = 4096;    // largest level the level ordering accepts
-constexpr int kStrip = 5;          // d1 values per strip
+constexpr int kStrip = 8;          // d1 values per strip
 constexpr int kPermWaves = 4;        // output rows (waves) per workgroup
 constexpr int kPermLdsWords = 1024;  // bit-map words per wave in LDS
 constexpr int kPermCache = 32;       // mapped columns held per lane
