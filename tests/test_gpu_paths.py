@@ -21,6 +21,26 @@ def cases():
     yield "general", W.random_sparse(150, 0.03, 3, kind="general", scale=1.2), 1e-12
     yield "adjacency", W.config4_instance(1, nmin=100, nmax=300)[0], 1e-12
     yield "disconnected", disconnected(), 1e-12
+    yield "hub", hub(), 1e-12
+
+
+def hub():
+    """A grid plus one node joined to every seventh grid node: rows longer
+    than the searches' fixed-width neighbour lists (eight slots) are read
+    from the CSR rows instead."""
+    rng = np.random.default_rng(13)
+    A = W.grid_laplacian(24, 25, rng)
+    m = A.n
+    r = [A.rows()]
+    c = [A.col.astype(np.int64)]
+    v = [A.val]
+    spokes = np.arange(0, m, 7)
+    w = 0.05 * rng.uniform(0.5, 1.0, spokes.size)
+    r += [np.full(spokes.size, m), spokes, [m]]
+    c += [spokes, np.full(spokes.size, m), [m]]
+    v += [w, w, [-w.sum()]]
+    H = W.csr_from_coo(m + 1, np.concatenate(r), np.concatenate(c), np.concatenate(v))
+    return H.scaled(-20.0 / W.norm1(H))
 
 
 def disconnected():
