@@ -96,7 +96,8 @@ int bsr_pattern(expm_plan_s &P, CsrView T, int64_t nnz, TileSet &ts, double *fil
     return EXPM_OK;
 }
 
-// T's values as tiles of the pattern, in both operand layouts: a table of
+// T's values as tiles of the pattern, in both operand layouts (with b_only,
+// for a symmetric T, the B layout and each tile's mirror index): a table of
 // row segments, then every tile assembled whole.
 int bsr_tiles(expm_plan_s &P, CsrView T, TileSet &ts, bool b_only) {
     const size_t nt = (size_t)(ts.ntiles > 0 ? ts.ntiles : 1);
