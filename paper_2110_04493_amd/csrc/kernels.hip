@@ -80,6 +80,36 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const int64_t *in, in
     }
 }
 
+// k_scan_final with each block's offset summed by the block itself from the
+// reduce pass's block totals (for few blocks: one launch fewer than a
+// separate pass over them); the last block writes the total to out[n].
+constexpr int64_t kScanFuseBlocks = 2048;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final_fused(const int64_t *in, int64_t n,
+                                                                 const int64_t *bsum, int64_t nb,
+                                                                 int64_t *out) {
+    long long part = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanBlock) part += bsum[b];
+    long long boff;
+    block_excl_scan(part, &boff);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    long long v[kScanItems];
+    long long s = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t idx = base + j;
+        v[j] = idx < n ? in[idx] : 0;
+        s += v[j];
+    }
+    long long tot;
+    long long ex = block_excl_scan(s, &tot) + boff;
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t idx = base + j;
+        if (idx < n) out[idx] = ex;
+        ex += v[j];
+    }
+    if ((int64_t)blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = boff + tot;
+}
+
 // Arrays of up to kScanSmall entries are scanned by one block in one launch
 // (tile by tile with a running carry): most scans here are over block rows
 // or panels, where the three launches would cost more than the work.
@@ -127,6 +157,11 @@ hipError_t scan_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, in, n, bsum);
+    if (nb <= kScanFuseBlocks) {
+        hipLaunchKernelGGL(k_scan_final_fused, dim3(nb), dim3(kScanBlock), 0, st, in, n, bsum,
+                           nb, out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(kScanBlock), 0, st, bsum, nb, out + n);
     hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBlock), 0, st, in, n, bsum, out);
     return hipGetLastError();
