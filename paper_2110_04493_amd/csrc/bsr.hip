@@ -26,7 +26,7 @@
 namespace xpm {
 
 constexpr int kPanel = 4;        // block rows per panel (one wave each)
-constexpr int kPanelGroup = 4;   // output tiles per wave
+constexpr int kPanelGroup = 2;   // output tiles per wave
 
 // ----------------------------------------------------------------- T -> tiles
 
@@ -558,8 +558,10 @@ __device__ __forceinline__ void panel_epilogue(
 // lookups in flight together); the product loop then walks the K that have
 // at least one, reading their indices with readlane, and loads the operands
 // of the next K before issuing the matrix instructions of the current one.
-// The kernel waits on memory far more than on the matrix cores, so it is
-// held to 128 registers: four waves per SIMD instead of two or three.
+// The kernel waits on the latency of its operand loads far more than on the
+// matrix cores, so it takes two output tiles per wave and is held to 80
+// registers: six waves per SIMD keep more loads in flight than four waves
+// of four tiles (128 registers) or eight of one.
 // With upper (a symmetric T, hence a symmetric C) the panels' column lists
 // start at the panel's first block row, each wave skips the tiles left of
 // its diagonal, and every off-diagonal tile it forms is also written,
@@ -568,7 +570,7 @@ __device__ __forceinline__ void panel_epilogue(
 // own per-row counts).
 template <int kGroup>
 __global__ __launch_bounds__(kWave * kPanel)
-__attribute__((amdgpu_waves_per_eu(4))) void k_bsr_numeric_panel(
+__attribute__((amdgpu_waves_per_eu(6))) void k_bsr_numeric_panel(
     int64_t nb, const int32_t *__restrict__ lo, const int64_t *__restrict__ woff,
     const uint2 *__restrict__ rt, const int64_t *__restrict__ tb,
     const int32_t *__restrict__ tcols, const double *__restrict__ tA,
