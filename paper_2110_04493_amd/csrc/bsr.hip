@@ -689,19 +689,23 @@ __device__ __forceinline__ bool bsr_keep(int64_t i, int col, int64_t n, double v
 // largest magnitude, trc: nonzeros per row), a tile whose slots are all at
 // most theta is skipped, and one whose nonzeros all exceed theta is counted
 // from trc without reading it; with krc, the tiles in between are counted
-// from the last filter pass's counts, so no tile is read.
+// from the last filter pass's counts, so no tile is read.  With rcnt, the
+// kept entries of each of the 16 rows in each round of 64 tiles too, at
+// rcnt[(rofs[I] + round) * 16 + row] (for k_bsr_write_rounds).
 __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
                             const int32_t *ccols, const double *ctiles, const double *tmn,
                             const double *tmx, const uint4 *trc, const uint4 *krc,
-                            const FilterCtl *c, int64_t *cnt) {
+                            const FilterCtl *c, int64_t *cnt, int32_t *rcnt,
+                            const int64_t *rofs) {
     const int64_t I = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (I >= (n + kTile - 1) / kTile) return;
     const int lane = lane_id();
     const int g = lane >> 4;
     const double theta = c->theta;
-    int k4[4] = {0, 0, 0, 0};
+    int k4[4] = {0, 0, 0, 0};   // kept per row, reduced over the 16 lanes of each group
     const int64_t base = ctb[I], cntI = ccnt[I];
     for (int64_t c0 = 0; c0 < cntI; c0 += kWave) {
+        int r4[4] = {0, 0, 0, 0};   // this round's, per lane
         // one lane per tile: the summaries of 64 tiles are read together;
         // h holds the row counts in 16-bit fields, row r in half r & 1 of
         // word r >> 1 (at most 16 per tile, 1024 per round)
@@ -738,7 +742,7 @@ __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int row = g + 4 * k;
-                k4[k] += (int)((h[row >> 1] >> (16 * (row & 1))) & 0xffffu);
+                r4[k] += (int)((h[row >> 1] >> (16 * (row & 1))) & 0xffffu);
             }
         }
         // tiles without usable counts are read, one at a time by all lanes
@@ -751,13 +755,20 @@ __global__ void k_bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt,
             const d4 v = *(const d4 *)(ctiles + tr * kTileElems + 4 * lane);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                k4[k] += bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+                r4[k] += bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) r4[k] += __shfl_xor(r4[k], o);
+            k4[k] += r4[k];
+        }
+        if (rcnt && (lane & 15) == 0) {
+            const int64_t q = rofs[I] + c0 / kWave;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rcnt[q * kTile + g + 4 * k] = r4[k];
         }
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) k4[k] += __shfl_xor(k4[k], o);
     if ((lane & 15) == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -828,6 +839,79 @@ __global__ void k_bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt,
             v1 = v2;
             h1 = h2;
         }
+    }
+}
+
+// k_bsr_write with one wave per round of 64 tiles of a block row (work item
+// w: block row owner[w], round w - rofs[I]) instead of one per block row, so
+// that a long block row is written by several waves at once: each round's
+// rows start after the kept entries that k_bsr_count found in the row's
+// earlier rounds (rcnt).
+__global__ void k_bsr_write_rounds(int64_t n, const int64_t *ctb, const int64_t *ccnt,
+                                   const int32_t *ccols, const double *ctiles, const double *tmx,
+                                   const FilterCtl *c, const int64_t *orp, const int32_t *rcnt,
+                                   const int64_t *rofs, const int32_t *owner,
+                                   const int64_t *nwork_dev, int32_t *oci, double *ov) {
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (w >= *nwork_dev) return;
+    const int64_t I = owner[w];
+    const int64_t q = w - rofs[I];
+    const int lane = lane_id();
+    const int g = lane >> 4, cl = lane & 15;
+    const double theta = c->theta;
+    int64_t out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = I * kTile + g + 4 * k;
+        int64_t o = i < n ? orp[i] : 0;
+        for (int64_t qq = 0; qq < q; ++qq) o += rcnt[(rofs[I] + qq) * kTile + g + 4 * k];
+        out[k] = o;
+    }
+    const int64_t base = ctb[I], cntI = ccnt[I];
+    const uint32_t below = (1u << cl) - 1u;
+    auto emit = [&](int col, const d4 &v) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool keep = bsr_keep(I * kTile + g + 4 * k, col, n, v[k], theta);
+            const uint32_t gm = (uint32_t)(__ballot(keep) >> (16 * g)) & 0xffffu;
+            if (keep) {
+                const int64_t p = out[k] + __popc(gm & below);
+                oci[p] = col;
+                ov[p] = v[k];
+            }
+            out[k] += __popc(gm);
+        }
+    };
+    // the round's tiles: which of them keep anything, and their block
+    // columns, in one round trip; then those that do, in order, with the
+    // loads of the next two in flight while the current one is written
+    const int64_t c0 = q * kWave, t = c0 + lane;
+    const bool some = t < cntI && (!tmx || tmx[base + t] > theta);
+    const int bc = some ? ccols[base + t] : 0;
+    unsigned long long m = __ballot(some);
+    auto pop = [&](int &col, d4 &v) {
+        if (!m) return false;
+        const int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        col = 16 * __builtin_amdgcn_readlane(bc, l) + cl;
+        v = *(const d4 *)(ctiles + (base + c0 + l) * kTileElems + 4 * lane);
+        return true;
+    };
+    int col0 = 0, col1 = 0;
+    d4 v0 = d4{0.0, 0.0, 0.0, 0.0}, v1 = v0;
+    bool h0 = pop(col0, v0);
+    bool h1 = pop(col1, v1);
+    while (h0) {
+        int col2 = 0;
+        d4 v2 = d4{0.0, 0.0, 0.0, 0.0};
+        const bool h2 = pop(col2, v2);
+        emit(col0, v0);
+        col0 = col1;
+        v0 = v1;
+        h0 = h1;
+        col1 = col2;
+        v1 = v2;
+        h1 = h2;
     }
 }
 
@@ -1011,11 +1095,31 @@ hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const double *tmn, const double *tmx,
                      const uint4 *trc, const uint4 *krc, const FilterCtl *c, int64_t *cnt,
-                     hipStream_t st) {
+                     hipStream_t st, int32_t *rcnt, const int64_t *rofs) {
     if (n == 0) return hipSuccess;
     const int64_t nb = (n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_bsr_count, dim3((nb + 3) / 4), dim3(256), 0, st, n, ctb, ccnt, ccols,
-                       ctiles, tmn, tmx, trc, krc, c, cnt);
+                       ctiles, tmn, tmx, trc, krc, c, cnt, rcnt, rofs);
+    return hipGetLastError();
+}
+
+hipError_t bsr_write_rounds(int64_t n, const int64_t *ctb, const int64_t *ccnt,
+                            const int32_t *ccols, const double *ctiles, const double *tmx,
+                            const FilterCtl *c, const int64_t *orp, const int32_t *rcnt,
+                            const int64_t *rofs, const int32_t *owner, int64_t nwork,
+                            int32_t *oci, double *ov, hipStream_t st) {
+    if (n == 0 || nwork == 0) return hipSuccess;
+    const int64_t nb = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_bsr_write_rounds, dim3((unsigned)((nwork + 3) / 4)), dim3(256), 0, st, n,
+                       ctb, ccnt, ccols, ctiles, tmx, c, orp, rcnt, rofs, owner, rofs + nb, oci,
+                       ov);
+    return hipGetLastError();
+}
+
+hipError_t bsr_rounds(const int64_t *ccnt, int64_t nb, int64_t *rnd, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_groups, dim3((nb + 255) / 256), dim3(256), 0, st, ccnt, nb, rnd,
+                       kWave);
     return hipGetLastError();
 }
 

@@ -337,6 +337,16 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     }
     FilterCtl h{};
     int64_t kept = 0, cand_nz = 0;
+    // the compaction's rounds of 64 candidate tiles per block row (a bound
+    // of their count launches the write; it reads the exact one)
+    const int64_t nround = ctiles / kWave + nb + 1;
+    CHK(ensure(P, P.r_cnt, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.r_ofs, sizeof(int64_t) * (nb + 1)));
+    CHK(ensure(P, P.r_rows, sizeof(int32_t) * 16 * (nround + 1)));   // 16 rows a round
+    CHK(ensure(P, P.r_owner, sizeof(int32_t) * (nround + 1)));
+    HIPCHK(bsr_rounds((const int64_t *)P.c_cnt.p, nb, (int64_t *)P.r_cnt.p, st));
+    CHK(scan(P, (const int64_t *)P.r_cnt.p, (int64_t *)P.r_ofs.p, nb));
+    HIPCHK(work_owner((const int64_t *)P.r_ofs.p, nb, (int32_t *)P.r_owner.p, st));
     for (int round = 0;; ++round) {
         if (!use_fixed)
             for (int j = 0; j < 4; ++j)
@@ -352,7 +362,8 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
                          (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,
                          (const double *)P.c_mn.p, (const double *)P.c_mx.p,
                          (const uint4 *)P.c_rc.p, use_fixed ? nullptr : (const uint4 *)P.c_kc.p,
-                         ctl, (int64_t *)P.cnt.p, st));
+                         ctl, (int64_t *)P.cnt.p, st, (int32_t *)P.r_rows.p,
+                         (const int64_t *)P.r_ofs.p));
         CHK(scan(P, (const int64_t *)P.cnt.p, (int64_t *)P.krp.p, n));
         HIPCHK(hipMemcpyAsync(P.host, ctl, sizeof(FilterCtl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hl + 8, (int64_t *)P.krp.p + n, sizeof(int64_t),
@@ -382,10 +393,12 @@ int square_step_bsr(expm_plan_s &P, const DCsr &T, DCsr &dst, double a_ri, bool 
     CHK(ensure_csr(P, dst, n, kept));
     HIPCHK(hipMemcpyAsync(dst.rp.p, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
                           st));
-    HIPCHK(bsr_write(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
-                     (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,
-                     (const double *)P.c_mx.p, ctl, (const int64_t *)dst.rp.p,
-                     (int32_t *)dst.ci.p, (double *)dst.v.p, st));
+    HIPCHK(bsr_write_rounds(n, (const int64_t *)P.c_tb.p, (const int64_t *)P.c_cnt.p,
+                            (const int32_t *)P.c_cols.p, (const double *)P.c_tiles.p,
+                            (const double *)P.c_mx.p, ctl, (const int64_t *)dst.rp.p,
+                            (const int32_t *)P.r_rows.p, (const int64_t *)P.r_ofs.p,
+                            (const int32_t *)P.r_owner.p, nround, (int32_t *)dst.ci.p,
+                            (double *)dst.v.p, st));
     expm_stats &S = P.stats;
     if (prof) {
         HIPCHK(hipEventRecord(P.ev[3], st));

@@ -2013,7 +2013,8 @@ void expm_free(expm_plan_t p) {
                     &P.ro_pcnt, &P.ro_pw, &P.ro_pofs, &P.ro_gbits};
     for (Buf *b : rbufs) release(P, *b);
     for (Buf *b : {&P.colsum, &P.amax, &P.bands}) release(P, *b);
-    for (Buf *b : {&P.mirror_bad, &P.sym_cnt, &P.c_mir}) release(P, *b);
+    for (Buf *b : {&P.mirror_bad, &P.sym_cnt, &P.c_mir, &P.r_cnt, &P.r_ofs, &P.r_rows, &P.r_owner})
+        release(P, *b);
     release(P, P.tsT);
     release(P, P.tsG);
     for (TileSet &ts : P.cts) release(P, ts);

@@ -187,10 +187,20 @@ hipError_t bsr_rowsq(int64_t n, const int64_t *ctb, const int64_t *ccnt, const i
 hipError_t bsr_count(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const double *tmn, const double *tmx,
                      const uint4 *trc, const uint4 *krc, const FilterCtl *c, int64_t *cnt,
-                     hipStream_t st);
+                     hipStream_t st, int32_t *rcnt = nullptr, const int64_t *rofs = nullptr);
 hipError_t bsr_write(int64_t n, const int64_t *ctb, const int64_t *ccnt, const int32_t *ccols,
                      const double *ctiles, const double *tmx, const FilterCtl *c,
                      const int64_t *orp, int32_t *oci, double *ov, hipStream_t st);
+// rounds of 64 tiles per block row (rnd[I] = ceil(ccnt[I] / 64)); the
+// compaction with one wave per round (rofs: exclusive scan of rnd with the
+// total at rofs[nb], owner its work map, rcnt the per-round row counts of
+// bsr_count; nwork: a bound of the round count)
+hipError_t bsr_rounds(const int64_t *ccnt, int64_t nb, int64_t *rnd, hipStream_t st);
+hipError_t bsr_write_rounds(int64_t n, const int64_t *ctb, const int64_t *ccnt,
+                            const int32_t *ccols, const double *ctiles, const double *tmx,
+                            const FilterCtl *c, const int64_t *orp, const int32_t *rcnt,
+                            const int64_t *rofs, const int32_t *owner, int64_t nwork,
+                            int32_t *oci, double *ov, hipStream_t st);
 
 // adjoint on tiles (bsr_adjoint.hip)
 hipError_t bsr_colcount(int64_t nb, const int32_t *lo, const int64_t *woff, const uint2 *rt,

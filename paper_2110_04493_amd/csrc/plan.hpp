@@ -166,6 +166,9 @@ struct expm_plan_s {
     int last_sym = -1;   // exact symmetry found by the last normality test (-1: not run)
     xpm::host::Buf mirror_bad, sym_cnt;
     xpm::host::Buf c_mir;   // per candidate tile: its mirror, -1 (diagonal) or -2 (a mirror)
+    // the compaction's rounds of 64 candidate tiles: per block row their
+    // count and offsets, per round the kept entries of its 16 rows, work map
+    xpm::host::Buf r_cnt, r_ofs, r_rows, r_owner;
 };
 
 namespace xpm {
