@@ -276,7 +276,9 @@ int expm_sparse(expm_plan_t p, const expm_csr_cview *H, double eps, expm_csr *E)
  * normality test of step 2 compares H H^* with H^* H (an exactly Hermitian
  * or skew-Hermitian H is normal), and Algorithm 4.1 filters by the modulus
  * |z| = sqrt(re^2 + im^2), summing |z|^2 over the dropped entries.  Every
- * product runs on scalar rows (no locality reordering and no tile path).
+ * product runs on scalar rows (no tile path); the locality reordering runs
+ * only when opts.reorder >= 1 (the default, -1, leaves complex H in its
+ * order: the row products gain nothing from it).
  * Options as for expm_sparse, except: filter_mode EXPM_FILTER_FIXED_REL and
  * norm EXPM_NORM_ONE give EXPM_ENOTIMPL, and no adjoint is kept (a later
  * expm_sparse_backward returns EXPM_ESTATE).  Statistics as for expm_sparse.

@@ -208,6 +208,25 @@ int forward_z(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E)
     S.eg0 = eg0;
     const bool diag = P.opts.diagnostics != 0;
     if (diag) CHK(ensure(P, P.bands, sizeof(long long) * 2 * (N + 1)));
+    // Locality reordering on request (reorder >= 1; the default leaves complex
+    // H in its order, since the complex row products, the only complex path,
+    // gain nothing from it): H' = P H P^T replaces H, and E is permuted back
+    // at the end.
+    {
+        const int ro = P.opts.reorder;
+        P.ordering = 0;
+        if (ro >= 1)
+            CHK(compute_reorder(P, H0.view(), nnz, ro == 2 ? 2 : 1, &P.perm_active));
+        S.ordering = P.perm_active ? P.ordering : 0;
+        if (P.perm_active) {
+            CHK(ensure_csr(P, P.Hp, n, nnz, 2));
+            CHK(permute_csr(P, H0.view(), nnz, (const int32_t *)P.order.p,
+                            (const int32_t *)P.newidx.p, (int64_t *)P.Hp.rp.p,
+                            (int32_t *)P.Hp.ci.p, (double *)P.Hp.v.p, nullptr, true));
+            std::swap(P.H0, P.Hp);
+        }
+    }
+    const int32_t *border = P.perm_active ? (const int32_t *)P.order.p : nullptr;
 
     phase.next("expm_z taylor seed");
     const auto t_taylor0 = std::chrono::steady_clock::now();
@@ -235,7 +254,7 @@ int forward_z(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E)
         S.taylor_terms = i;
     }
     S.t_taylor_ms = ms_since(t_taylor0);
-    if (diag) HIPCHK(band_of(T.view(), nullptr, (long long *)P.bands.p, st));
+    if (diag) HIPCHK(band_of(T.view(), border, (long long *)P.bands.p, st));
 
     phase.next("expm_z squarings");
     double ri = r0;
@@ -269,7 +288,7 @@ int forward_z(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E)
             S.sq_in[i] = T.nnz;
         }
         std::swap(T, Tn);
-        if (diag) HIPCHK(band_of(T.view(), nullptr, (long long *)P.bands.p + 2 * i, st));
+        if (diag) HIPCHK(band_of(T.view(), border, (long long *)P.bands.p + 2 * i, st));
         S.sq_theta[i] = h.theta;
         S.sq_iters[i] = h.iter;
         S.sq_cand[i] = cand;
@@ -299,11 +318,26 @@ int forward_z(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E)
         int32_t *ci;
         double *v;
         CHK(alloc_output(P, n, kept, &rp, &ci, &v, 2));
-        HIPCHK(hipMemcpyAsync(rp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+        // E' (the reordered result) goes to the workspace and is permuted
+        // back into the caller's order; without reordering E is written
+        // directly
+        int64_t *erp = rp;
+        int32_t *eci = ci;
+        double *ev = v;
+        if (P.perm_active) {
+            CHK(ensure_csr(P, P.Eperm, n, kept, 2));
+            erp = (int64_t *)P.Eperm.rp.p;
+            eci = (int32_t *)P.Eperm.ci.p;
+            ev = (double *)P.Eperm.v.p;
+        }
+        HIPCHK(hipMemcpyAsync(erp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
                               st));
         HIPCHK(write_kept_z((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
-                            (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, rp, ci, v,
-                            st));
+                            (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, erp, eci,
+                            ev, st));
+        if (P.perm_active)
+            CHK(permute_csr(P, P.Eperm.view(), kept, (const int32_t *)P.newidx.p,
+                            (const int32_t *)P.order.p, rp, ci, v, nullptr, true));
         E->n = n;
         E->nnz = kept;
         E->rowptr = rp;

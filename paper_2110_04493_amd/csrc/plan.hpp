@@ -295,8 +295,10 @@ void collect_forward(expm_plan_s &P);
 void ktimer_collect_set(expm_plan_s &P, std::vector<hipEvent_t> &ev, std::vector<char> &kind,
                        size_t &used);
 int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *active);
+// cplx: complex values (pairs of doubles)
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
-                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap);
+                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap,
+                bool cplx = false);
 int scatter_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst);
 
 }  // namespace host

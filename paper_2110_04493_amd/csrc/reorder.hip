@@ -363,7 +363,7 @@ __global__ void k_perm_words(CsrView X, const int32_t *src_row, const int32_t *c
 // output entry, the index of its input entry.
 __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
     CsrView X, const int32_t *src_row, const int32_t *colmap, const int64_t *orp, int32_t *oci,
-    double *ov, int64_t *emap, const int64_t *gofs, uint2 *gbits) {
+    double *ov, int64_t *emap, const int64_t *gofs, uint2 *gbits, int cplx) {
     __shared__ uint2 lbits[kPermWaves][kPermLdsWords];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     const int64_t r = (int64_t)blockIdx.x * kPermWaves + wv;
@@ -443,7 +443,10 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
         const uint32_t wx = ld(&bits[2 * (d >> 5)]), wy = ld(&bits[2 * (d >> 5) + 1]);
         const int64_t q = ob + wy + __popc(wx & ((1u << (d & 31)) - 1u));
         oci[q] = c;
-        ov[q] = X.v[p];
+        if (cplx)   // complex values: pairs of doubles
+            ((double2 *)ov)[q] = ((const double2 *)X.v)[p];
+        else
+            ov[q] = X.v[p];
         if (emap) emap[q] = p;
     };
     if (cached) {
@@ -599,7 +602,8 @@ int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *acti
 // Output CSR (orp, oci, ov; caller-allocated, nnz entries) whose row r is
 // row src_row[r] of X with columns mapped by colmap, sorted.
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
-                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap) {
+                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap,
+                bool cplx) {
     hipStream_t st = P.st;
     const int64_t n = X.n;
     CHK(ensure(P, P.ro_pcnt, sizeof(int64_t) * (n + 1)));
@@ -620,7 +624,7 @@ int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
     if (nnz > 0) {
         hipLaunchKernelGGL(k_perm_rows, dim3((unsigned)((n + kPermWaves - 1) / kPermWaves)),
                            dim3(kWave * kPermWaves), 0, st, X, src_row, colmap, orp, oci, ov,
-                           emap, pofs, (uint2 *)P.ro_gbits.p);
+                           emap, pofs, (uint2 *)P.ro_gbits.p, cplx ? 1 : 0);
         HIPCHK(hipGetLastError());
     }
     return EXPM_OK;

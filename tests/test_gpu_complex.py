@@ -124,6 +124,22 @@ def test_options(opts):
     check_z(W.schrodinger_grid(24, 0.8, seed=65), 1e-12, **opts)
 
 
+@pytest.mark.parametrize("case", ["schrodinger", "magnetic", "general"])
+def test_locality_reordering(case):
+    """The locality ordering forced on (reorder = 1; by default it applies
+    from n = 4096): H is permuted before the method and E back after it, so
+    the result is the oracle's up to rounding order."""
+    if case == "schrodinger":
+        H = W.schrodinger_grid(40, 1.0, seed=70)
+    elif case == "magnetic":
+        H = W.magnetic_laplacian(30, 30, seed=71).scaled(-1.0)
+    else:
+        H = W.complex_random(300, 0.02, 72, scale=0.8)
+    _, sg, _, _ = check_z(H, 1e-12, reorder=1)
+    if case != "general":
+        assert sg["ordering"] >= 1
+
+
 def test_real_input_matches_real_path():
     """Imaginary parts zero: the complex path agrees with the real one
     (rows, no reordering) entry by entry."""
