@@ -53,6 +53,10 @@ def parse():
                          "benchmark's own workload (0: the full workload, the default)")
     ap.add_argument("--cpu-runs", type=int, default=1,
                     help="oracle runs for the CPU baseline (the median is reported)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only time the CPU oracle (the cpu_baseline measurement, with the "
+                         "thread count OMP_NUM_THREADS gives it) and print it as one JSON line; "
+                         "the GPU is not used")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the lines of the other workloads (differentiation, large grid, "
                          "batched, E R) that follow the headline line")
@@ -206,6 +210,11 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.cpu_only:
+        from paper_2110_04493_amd import workloads as W
+        H, _ = W.config2(args.side)
+        print(json.dumps({"cpu_baseline": cpu_baseline(args, H.n)}), flush=True)
         return
     if args.workload == "batched":
         bench_batched(args)

@@ -751,6 +751,8 @@ int ora_backward(const ora_run *r, const double *dE, double *dH) {
         mat_free(&Tt); mat_free(&P1); mat_free(&P2); mat_free(&Sum1); mat_free(&Sum);
         free(g);
         g = gn;
+        if (getenv("ORA_PROGRESS"))
+            fprintf(stderr, "oracle: adjoint of squaring %d done\n", k);
     }
     /* Taylor seed.  g is dL/dT^_0 on supp(T^_0). */
     mat G0 = r->T[0];
