@@ -1173,8 +1173,40 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
     phase.next("expm finish (E = I + T_N)");
     if (N == 0 && cur != &P.T) CHK(copy_csr(P, P.T, *cur));   // T_0 is also T_N
     if (keep) std::swap(P.TN, P.T);   // T_N stays for the adjoint
-    // E = I + T_N (exact zeros not stored)
-    {
+    // E = I + T_N: T_N's entries as they are, the diagonal 1 + t (inserted as
+    // 1 where T_N has none, left out where 1 + t is exactly zero).  With
+    // reordering, the permutation back to the caller's order adds the
+    // identity on its way (one pass over T'_N instead of two).
+    if (P.perm_active) {
+        const DCsr &TNs = keep ? P.TN : P.T;
+        CHK(ensure(P, P.krp, sizeof(int64_t) * (n + 1)));
+        int64_t kept = 0, gw = 0;
+        CHK(permute_count(P, TNs.view(), (const int32_t *)P.newidx.p, (const int32_t *)P.order.p,
+                          (int64_t *)P.krp.p, true, &kept, &gw));
+        int64_t *rp;
+        int32_t *ci;
+        double *v;
+        CHK(alloc_output(P, n, kept, &rp, &ci, &v));
+        HIPCHK(hipMemcpyAsync(rp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+                              st));
+        int64_t *tm = nullptr;
+        if (keep) {
+            CHK(ensure(P, P.tmap, sizeof(int64_t) * (TNs.nnz + 1)));
+            tm = (int64_t *)P.tmap.p;
+        }
+        CHK(permute_write(P, TNs.view(), TNs.nnz, (const int32_t *)P.newidx.p,
+                          (const int32_t *)P.order.p, rp, ci, v, nullptr, tm, gw, false, true));
+        E->n = n;
+        E->nnz = kept;
+        E->rowptr = rp;
+        E->col = ci;
+        E->val = v;
+        S.nnz_e = kept;
+        if (keep) {   // the adjoint reads dL/dE through tmap, not E's pattern
+            P.Epat.n = n;
+            P.Epat.nnz = kept;
+        }
+    } else {
         // T_N becomes the candidate of the compaction (buffers handed over,
         // not copied, and handed back to P.TN after the write when kept)
         DCsr &TNs = keep ? P.TN : P.T;
@@ -1191,31 +1223,12 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         int32_t *ci;
         double *v;
         CHK(alloc_output(P, n, kept, &rp, &ci, &v));
-        // with reordering E' = I + T'_N goes to workspace and is permuted back
-        int64_t *erp = rp;
-        int32_t *eci = ci;
-        double *ev = v;
-        if (P.perm_active) {
-            CHK(ensure_csr(P, P.Eperm, n, kept));
-            erp = (int64_t *)P.Eperm.rp.p;
-            eci = (int32_t *)P.Eperm.ci.p;
-            ev = (double *)P.Eperm.v.p;
-        }
-        HIPCHK(hipMemcpyAsync(erp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+        HIPCHK(hipMemcpyAsync(rp, P.krp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
                               st));
         HIPCHK(write_kept((const int64_t *)P.crp.p, (const int32_t *)P.cci.p,
-                          (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, erp, eci, ev,
+                          (const double *)P.cv.p, n, (const FilterCtl *)P.ctl.p, 1, rp, ci, v,
                           st));
         if (keep) swap_cand();
-        if (P.perm_active) {
-            int64_t *em = nullptr;
-            if (keep) {
-                CHK(ensure(P, P.emap, sizeof(int64_t) * (kept + 1)));
-                em = (int64_t *)P.emap.p;
-            }
-            CHK(permute_csr(P, P.Eperm.view(), kept, (const int32_t *)P.newidx.p,
-                            (const int32_t *)P.order.p, rp, ci, v, em));
-        }
         E->n = n;
         E->nnz = kept;
         E->rowptr = rp;
@@ -1223,21 +1236,11 @@ int forward(expm_plan_s &P, const expm_csr_cview *Hv, double eps, expm_csr *E) {
         E->val = v;
         S.nnz_e = kept;
         if (keep) {
-            // the adjoint needs the pattern of E' (of E without reordering):
-            // E' is workspace and its pattern buffers simply change hands;
-            // E itself belongs to the caller and is copied
-            if (P.perm_active) {
-                std::swap(P.Epat.rp, P.Eperm.rp);
-                std::swap(P.Epat.ci, P.Eperm.ci);
-            } else {
-                CHK(ensure(P, P.Epat.rp, sizeof(int64_t) * (n + 1)));
-                CHK(ensure(P, P.Epat.ci, sizeof(int32_t) * kept));
-                HIPCHK(hipMemcpyAsync(P.Epat.rp.p, erp, sizeof(int64_t) * (n + 1),
-                                      hipMemcpyDeviceToDevice, st));
-                if (kept)
-                    HIPCHK(hipMemcpyAsync(P.Epat.ci.p, eci, sizeof(int32_t) * kept,
-                                          hipMemcpyDeviceToDevice, st));
-            }
+            // the adjoint needs E's row pointers (E belongs to the caller):
+            // row by row E and T_N differ at most at the diagonal
+            CHK(ensure(P, P.Epat.rp, sizeof(int64_t) * (n + 1)));
+            HIPCHK(hipMemcpyAsync(P.Epat.rp.p, rp, sizeof(int64_t) * (n + 1),
+                                  hipMemcpyDeviceToDevice, st));
             P.Epat.n = n;
             P.Epat.nnz = kept;
         }
@@ -1302,28 +1305,26 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
         return EXPM_OK;
     }
     const int N = P.N;
-    // G_N on supp(T_N): E = I + T_N.  With reordering dE is first moved onto
-    // the entries of E' (the pattern kept in Epat).
-    Buf g, gn, dEp, dHp, tv, t2v;
+    // G_N on supp(T_N): E = I + T_N, dL/dT_N = dL/dE at T_N's entries.
+    Buf g, gn, dHp, tv, t2v;
     DCsr Tt, H0t, St, Snt, Gc, Gct;
     Buf acc, acc2;
     std::vector<Buf> D;
     auto free_locals = at_exit([&] {
-        for (Buf *b : {&g, &gn, &dEp, &dHp, &acc, &acc2, &tv, &t2v}) release(P, *b);
+        for (Buf *b : {&g, &gn, &dHp, &acc, &acc2, &tv, &t2v}) release(P, *b);
         for (DCsr *m : {&Tt, &H0t, &St, &Snt, &Gc, &Gct}) release(P, *m);
         for (auto &b : D) release(P, b);
     });
-    const double *dEu = dE;
-    if (P.perm_active) {
-        CHK(ensure(P, dEp, sizeof(double) * (P.Epat.nnz + 1)));
-        CHK(scatter_map(P, dE, (const int64_t *)P.emap.p, P.Epat.nnz, (double *)dEp.p));
-        dEu = (const double *)dEp.p;
-    }
-    CsrView Ev = CsrView{n, (const int64_t *)P.Epat.rp.p, (const int32_t *)P.Epat.ci.p, dEu};
     CHK(ensure(P, g, sizeof(double) * (P.TN.nnz + 1)));
     MaskTerm none{empty_view(), empty_view(), 0.0};
-    HIPCHK(values_at_t((const int64_t *)P.TN.rp.p, (const int32_t *)P.TN.ci.p, Ev.rp, Ev.v, n,
-                       (double *)g.p, st));
+    if (P.perm_active) {
+        // each entry of T'_N reads its entry of E through tmap (a diagonal
+        // that I + T_N left out reads 0)
+        CHK(gather_map(P, dE, (const int64_t *)P.tmap.p, P.TN.nnz, (double *)g.p));
+    } else {
+        HIPCHK(values_at_t((const int64_t *)P.TN.rp.p, (const int32_t *)P.TN.ci.p,
+                           (const int64_t *)P.Epat.rp.p, dE, n, (double *)g.p, st));
+    }
     // iterates of the current segment: seg[j] = T^_{base + j} (buffers kept
     // by the plan from call to call)
     std::vector<DCsr> &seg = P.seg_pool;
@@ -1504,7 +1505,6 @@ int backward(expm_plan_s &P, const double *dE, double *dH) {
     release(P, acc2);
     release(P, g);
     release(P, gn);
-    release(P, dEp);
     release(P, dHp);
     release(P, Tt);
     release(P, H0t);
@@ -2008,7 +2008,7 @@ void expm_free(expm_plan_t p) {
                     &P.p_words, &P.p_woff, &P.p_cnt, &P.p_ofs, &P.p_gcnt, &P.p_gofs,
                     &P.p_owner, &P.g_owner, &P.p_cols, &P.c_sq, &P.c_nz, &P.c_mn, &P.c_mx, &P.c_rc, &P.c_kc, &P.b_dg};
     for (Buf *b : tbufs) release(P, *b);
-    Buf *rbufs[] = {&P.order, &P.newidx, &P.hmap, &P.emap, &P.ro_rb, &P.ro_d0, &P.ro_d1,
+    Buf *rbufs[] = {&P.order, &P.newidx, &P.hmap, &P.tmap, &P.ro_rb, &P.ro_d0, &P.ro_d1,
                     &P.ro_d3, &P.ro_q0, &P.ro_q1, &P.ro_ell, &P.ro_cell, &P.ro_cnt, &P.ro_off,
                     &P.ro_pcnt, &P.ro_pw, &P.ro_pofs, &P.ro_gbits};
     for (Buf *b : rbufs) release(P, *b);

@@ -95,7 +95,7 @@ struct expm_plan_s {
     std::vector<xpm::host::TileSet> cts;
     std::vector<char> cts_ok;
     size_t dev_mem = 0;   // device memory in bytes (0: not queried yet)
-    xpm::host::DCsr Epat;                       // pattern of the returned E
+    xpm::host::DCsr Epat;   // the returned E's size (its row pointers without reordering)
     std::vector<double> theta;       // squaring thresholds, 1..N
     bool zero_h = false;
     // stats / outputs
@@ -142,10 +142,11 @@ struct expm_plan_s {
     xpm::host::Buf tc_cnt, tc_ptr, tc_fill, tc_k, tc_t, adj_tiles, adj_tilesA;
     std::vector<char> sq_path;       // per squaring step: 1 = tiles, 0 = scalar rows
     // locality reordering: order (new -> old), newidx (old -> new); H' = P H P^T
-    // replaces H0 and E = P^T E' P; hmap / emap give, for each entry of H' / of
-    // the returned E, the index of the matching entry of H / of E'
+    // replaces H0 and E = P^T (I + T'_N) P; hmap gives, for each entry of H',
+    // the index of the matching entry of H; tmap, for each entry of T'_N, the
+    // index of the matching entry of the returned E (-1: none)
     bool perm_active = false;
-    xpm::host::Buf order, newidx, hmap, emap, ro_rb, ro_d0, ro_d1, ro_d3, ro_q0, ro_q1, ro_ell,
+    xpm::host::Buf order, newidx, hmap, tmap, ro_rb, ro_d0, ro_d1, ro_d3, ro_q0, ro_q1, ro_ell,
         ro_cell,
         ro_cnt, ro_off, ro_pcnt, ro_pw, ro_pofs, ro_gbits;
     xpm::host::DCsr Hp, Eperm;
@@ -299,7 +300,14 @@ int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *acti
 int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
                 const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap,
                 bool cplx = false);
+int permute_count(expm_plan_s &P, CsrView X, const int32_t *src_row, const int32_t *colmap,
+                  int64_t *orp, bool ident, int64_t *total, int64_t *gwords);
+int permute_write(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
+                  const int32_t *colmap, const int64_t *orp, int32_t *oci, double *ov,
+                  int64_t *emap, int64_t *tmap, int64_t gwords, bool cplx, bool ident);
 int scatter_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst);
+// dst[i] = src[map[i]], or 0 where map[i] < 0
+int gather_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst);
 
 }  // namespace host
 }  // namespace xpm

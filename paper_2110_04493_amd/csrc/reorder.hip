@@ -334,22 +334,43 @@ __global__ void k_cell_sort(int64_t ncell, const int64_t *coff, const int32_t *t
 // Permuted rows: output row r is input row src_row[r] with its columns
 // mapped through colmap.  Per output row: its length and, when its column
 // window is wider than the LDS bit map, the number of global words.
+//
+// ident: the rows of I + X instead (X square, colmap the inverse of src_row,
+// so that input row s = src_row[r] keeps its diagonal at column s, mapped to
+// r).  The diagonal takes 1 + x, is inserted as 1 where X has none, and is
+// left out where 1 + x is exactly zero; the other entries stay as they are.
 __global__ void k_perm_words(CsrView X, const int32_t *src_row, const int32_t *colmap,
-                             int64_t *cnt, int64_t *gwords) {
+                             int64_t *cnt, int64_t *gwords, int ident) {
     const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (r >= X.n) return;
     const int32_t s = src_row[r];
     const int64_t b = X.rp[s], e = X.rp[s + 1];
     int mn = INT32_MAX, mx = -1;
+    bool hasd = false, zerod = false;
     for (int64_t p = b + lane_id(); p < e; p += kWave) {
-        const int c = colmap[X.ci[p]];
+        const int32_t sc = X.ci[p];
+        const int c = colmap[sc];
         mn = min(mn, c);
         mx = max(mx, c);
+        if (ident && sc == s) {
+            hasd = true;
+            zerod = 1.0 + X.v[p] == 0.0;
+        }
+    }
+    int64_t len = e - b;
+    if (ident) {   // every lane is back from the loop
+        if (__ballot(hasd) == 0) {
+            mn = min(mn, (int)r);
+            mx = max(mx, (int)r);
+            ++len;
+        } else if (__ballot(zerod) != 0) {
+            --len;
+        }
     }
     mn = wave_min(mn);
     mx = wave_max(mx);
     if (lane_id() == 0) {
-        cnt[r] = e - b;
+        cnt[r] = len;
         const int64_t W = mx < 0 ? 0 : (((int64_t)mx - (mn & ~31)) >> 5) + 1;
         gwords[r] = W > kPermLdsWords ? W : 0;
     }
@@ -360,20 +381,33 @@ __global__ void k_perm_words(CsrView X, const int32_t *src_row, const int32_t *c
 // column (prefix count + bits below it) is its position in the sorted output
 // row.  Rows of up to kWave * kPermCache entries keep their mapped columns
 // in registers between the passes.  emap (optional) receives, for every
-// output entry, the index of its input entry.
+// output entry, the index of its input entry (-1 for an inserted diagonal),
+// tmap (optional), for every input entry, the index of its output entry (-1
+// for a diagonal left out).  ident: the rows of I + X, as in k_perm_words.
 __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
     CsrView X, const int32_t *src_row, const int32_t *colmap, const int64_t *orp, int32_t *oci,
-    double *ov, int64_t *emap, const int64_t *gofs, uint2 *gbits, int cplx) {
+    double *ov, int64_t *emap, int64_t *tmap, const int64_t *gofs, uint2 *gbits, int cplx,
+    int ident) {
     __shared__ uint2 lbits[kPermWaves][kPermLdsWords];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     const int64_t r = (int64_t)blockIdx.x * kPermWaves + wv;
     if (r >= X.n) return;
     const int32_t s = src_row[r];
     const int64_t b = X.rp[s], e = X.rp[s + 1];
-    if (e == b) return;
+    if (e == b) {
+        if (ident && lane == 0) {   // the row of I alone
+            const int64_t q = orp[r];
+            oci[q] = (int32_t)r;
+            ov[q] = 1.0;
+            if (emap) emap[q] = -1;
+        }
+        return;
+    }
     const bool cached = e - b <= (int64_t)kWave * kPermCache;
     int cc[kPermCache];
     int mn = INT32_MAX, mx = -1;
+    bool hasd = false, zerod = false;
+    const int rd = (int)r;   // the diagonal's column in the output
     if (cached) {
 #pragma unroll
         for (int j = 0; j < kPermCache; ++j) {
@@ -382,6 +416,10 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
             if (cc[j] >= 0) {
                 mn = min(mn, cc[j]);
                 mx = max(mx, cc[j]);
+                if (ident && cc[j] == rd) {
+                    hasd = true;
+                    zerod = 1.0 + X.v[p] == 0.0;
+                }
             }
         }
     } else {
@@ -389,6 +427,23 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
             const int c = colmap[X.ci[p]];
             mn = min(mn, c);
             mx = max(mx, c);
+            if (ident && c == rd) {
+                hasd = true;
+                zerod = 1.0 + X.v[p] == 0.0;
+            }
+        }
+    }
+    // ident: insert the diagonal (addd) or leave it out (a column no entry
+    // takes otherwise: dskip); the window then spans r as k_perm_words's does
+    bool addd = false;
+    int dskip = -1;
+    if (ident) {   // every lane is back from the loops
+        addd = __ballot(hasd) == 0;
+        if (addd) {
+            mn = min(mn, rd);
+            mx = max(mx, rd);
+        } else if (__ballot(zerod) != 0) {
+            dskip = rd;
         }
     }
     mn = wave_min(mn);
@@ -417,6 +472,7 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
     }
     pass_end();
     auto mark = [&](int c) {
+        if (c == dskip) return;
         const int d = c - lo;
         atomicOr(&bits[2 * (d >> 5)], 1u << (d & 31));
     };
@@ -427,6 +483,7 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
     } else {
         for (int64_t p = b + lane; p < e; p += kWave) mark(colmap[X.ci[p]]);
     }
+    if (addd && lane == 0) mark(rd);
     pass_end();
     unsigned carry = 0;
     for (int64_t w0 = 0; w0 < W; w0 += kWave) {
@@ -438,17 +495,31 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
     }
     pass_end();
     const int64_t ob = orp[r];
-    auto place = [&](int c, int64_t p) {
+    auto slot = [&](int c) {
         const int d = c - lo;
         const uint32_t wx = ld(&bits[2 * (d >> 5)]), wy = ld(&bits[2 * (d >> 5) + 1]);
-        const int64_t q = ob + wy + __popc(wx & ((1u << (d & 31)) - 1u));
+        return ob + wy + __popc(wx & ((1u << (d & 31)) - 1u));
+    };
+    auto place = [&](int c, int64_t p) {
+        if (c == dskip) {
+            if (tmap) tmap[p] = -1;
+            return;
+        }
+        const int64_t q = slot(c);
         oci[q] = c;
         if (cplx)   // complex values: pairs of doubles
             ((double2 *)ov)[q] = ((const double2 *)X.v)[p];
         else
-            ov[q] = X.v[p];
+            ov[q] = ident && c == rd ? 1.0 + X.v[p] : X.v[p];
         if (emap) emap[q] = p;
+        if (tmap) tmap[p] = q;
     };
+    if (addd && lane == 0) {
+        const int64_t q = slot(rd);
+        oci[q] = rd;
+        ov[q] = 1.0;
+        if (emap) emap[q] = -1;
+    }
     if (cached) {
 #pragma unroll
         for (int j = 0; j < kPermCache; ++j)
@@ -461,6 +532,14 @@ __global__ __launch_bounds__(kWave * kPermWaves) void k_perm_rows(
 __global__ void k_scatter_map(const double *src, const int64_t *map, int64_t m, double *dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) dst[map[i]] = src[i];
+}
+
+__global__ void k_gather_map(const double *src, const int64_t *map, int64_t m, double *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) {
+        const int64_t j = map[i];
+        dst[i] = j >= 0 ? src[j] : 0.0;
+    }
 }
 
 static unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -599,11 +678,11 @@ int compute_reorder(expm_plan_s &P, CsrView G, int64_t nnz, int mode, bool *acti
     return EXPM_OK;
 }
 
-// Output CSR (orp, oci, ov; caller-allocated, nnz entries) whose row r is
-// row src_row[r] of X with columns mapped by colmap, sorted.
-int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
-                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap,
-                bool cplx) {
+// The row pointers of the permuted X (of I + X with ident) into orp (n + 1
+// entries), the global bit-map words of the widest rows, and both totals
+// read back (one wait): *total output entries, *gwords words.
+int permute_count(expm_plan_s &P, CsrView X, const int32_t *src_row, const int32_t *colmap,
+                  int64_t *orp, bool ident, int64_t *total, int64_t *gwords) {
     hipStream_t st = P.st;
     const int64_t n = X.n;
     CHK(ensure(P, P.ro_pcnt, sizeof(int64_t) * (n + 1)));
@@ -612,21 +691,53 @@ int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
     int64_t *pc = (int64_t *)P.ro_pcnt.p, *pw = (int64_t *)P.ro_pw.p,
             *pofs = (int64_t *)P.ro_pofs.p;
     hipLaunchKernelGGL(k_perm_words, dim3(blocks_for(n, 4)), dim3(256), 0, st, X, src_row, colmap,
-                       pc, pw);
+                       pc, pw, ident ? 1 : 0);
     HIPCHK(hipGetLastError());
     CHK(scan(P, pc, orp, n));
     CHK(scan(P, pw, pofs, n));
     int64_t *hl = (int64_t *)P.host;
-    HIPCHK(hipMemcpyAsync(hl, pofs + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hl, orp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hl + 1, pofs + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     CHK(sync(P));
-    const int64_t gw = hl[0];
-    CHK(ensure(P, P.ro_gbits, sizeof(uint2) * (gw + 1)));
-    if (nnz > 0) {
+    *total = hl[0];
+    *gwords = hl[1];
+    return EXPM_OK;
+}
+
+// The entries of the permuted X (of I + X with ident) into oci, ov on the
+// row pointers orp that permute_count gave (gwords from the same call).
+int permute_write(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
+                  const int32_t *colmap, const int64_t *orp, int32_t *oci, double *ov,
+                  int64_t *emap, int64_t *tmap, int64_t gwords, bool cplx, bool ident) {
+    if (ident && cplx) return fail(EXPM_ENOTIMPL, "permute_write: I + X is real only");
+    const int64_t n = X.n;
+    CHK(ensure(P, P.ro_gbits, sizeof(uint2) * (gwords + 1)));
+    if (nnz > 0 || (ident && n > 0)) {
         hipLaunchKernelGGL(k_perm_rows, dim3((unsigned)((n + kPermWaves - 1) / kPermWaves)),
-                           dim3(kWave * kPermWaves), 0, st, X, src_row, colmap, orp, oci, ov,
-                           emap, pofs, (uint2 *)P.ro_gbits.p, cplx ? 1 : 0);
+                           dim3(kWave * kPermWaves), 0, P.st, X, src_row, colmap, orp, oci, ov,
+                           emap, tmap, (const int64_t *)P.ro_pofs.p, (uint2 *)P.ro_gbits.p,
+                           cplx ? 1 : 0, ident ? 1 : 0);
         HIPCHK(hipGetLastError());
     }
+    return EXPM_OK;
+}
+
+// Output CSR (orp, oci, ov; caller-allocated, nnz entries) whose row r is
+// row src_row[r] of X with columns mapped by colmap, sorted.
+int permute_csr(expm_plan_s &P, CsrView X, int64_t nnz, const int32_t *src_row,
+                const int32_t *colmap, int64_t *orp, int32_t *oci, double *ov, int64_t *emap,
+                bool cplx) {
+    int64_t total = 0, gw = 0;
+    CHK(permute_count(P, X, src_row, colmap, orp, false, &total, &gw));
+    return permute_write(P, X, nnz, src_row, colmap, orp, oci, ov, emap, nullptr, gw, cplx,
+                         false);
+}
+
+int gather_map(expm_plan_s &P, const double *src, const int64_t *map, int64_t m, double *dst) {
+    if (m <= 0) return EXPM_OK;
+    hipLaunchKernelGGL(k_gather_map, dim3(blocks_for(m, 256)), dim3(256), 0, P.st, src, map, m,
+                       dst);
+    HIPCHK(hipGetLastError());
     return EXPM_OK;
 }
 

@@ -270,3 +270,58 @@ def test_work_order_does_not_change_bits(tmp_path):
     assert np.array_equal(z["col"], E.col)
     assert np.array_equal(z["val"].view(np.uint64), E.val.view(np.uint64))
     assert np.array_equal(z["dH"].view(np.uint64), dH.view(np.uint64))
+
+
+def grid_plus(extra):
+    """A 24 x 24 grid, H = -0.5 L, plus one more node m whose entries extra(m)
+    lists as (row, column, value)."""
+    rng = np.random.default_rng(21)
+    A = W.grid_laplacian(24, 24, rng).scaled(-0.5)
+    m = A.n
+    r, c, v = [A.rows()], [A.col.astype(np.int64)], [A.val]
+    for i, j, x in extra(m):
+        r.append([i])
+        c.append([j])
+        v.append([x])
+    return W.csr_from_coo(m + 1, np.concatenate(r), np.concatenate(c), np.concatenate(v)), m
+
+
+def diagonal_cases():
+    # a node joined to the grid by 1e-7: T_N's diagonal there (about 5e-15)
+    # falls under the last threshold (6.4e-15), so E takes the diagonal 1 of
+    # I alone in a row that has other entries
+    yield "pendant", *grid_plus(lambda m: [(m, 100, 1e-7), (100, m, 1e-7)])
+    # an isolated node with h = -800: its t = e^h - 1 rounds to -1 exactly,
+    # so E's diagonal there is exactly 0 and not stored
+    yield "vanishing", *grid_plus(lambda m: [(m, m, -800.0)])
+
+
+@pytest.mark.parametrize("reorder", [0, 1, 2])
+@pytest.mark.parametrize("name,H,m", list(diagonal_cases()),
+                         ids=[c[0] for c in diagonal_cases()])
+def test_identity_at_the_diagonal(name, H, m, reorder):
+    """E = I + T_N where T_N's diagonal is absent from a nonempty row, or
+    where 1 + t is exactly zero: in the natural order, and with the
+    permutation back from the locality order adding the identity on its way
+    (reorder 2 forces an ordering); forward and adjoint against the oracle."""
+    eps = 1e-12
+    print(f"[{name} reorder={reorder}] n={H.n}", flush=True)
+    Eg, sg = run_gpu(H, eps, reorder=reorder)
+    Eo, so = run_oracle(H, eps)
+    if reorder == 2:
+        assert sg["ordering"] != 0
+    rel, ok, og, oo = compare(Eg, Eo, final_theta(so))
+    print(f"[{name} reorder={reorder}] relF={rel:.2e} only={og},{oo}", flush=True)
+    assert rel <= TOL and ok, (rel, og, oo)
+    row = lambda E: slice(E.rowptr[m], E.rowptr[m + 1])
+    if name == "pendant":
+        assert Eo.col[row(Eo)][-1] == m and Eo.val[row(Eo)][-1] == 1.0
+        assert Eg.col[row(Eg)][-1] == m and Eg.val[row(Eg)][-1] == 1.0
+        assert Eg.rowptr[m + 1] - Eg.rowptr[m] > 1
+    else:
+        assert Eo.rowptr[m + 1] == Eo.rowptr[m] and Eg.rowptr[m + 1] == Eg.rowptr[m]
+    dg, _ = gpu_grad(H, eps, density=0.3, reorder=reorder)
+    do, _ = oracle_grad(H, eps, density=0.3)
+    rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+    print(f"[{name} reorder={reorder}] adjoint rel={rel:.2e}", flush=True)
+    assert rel <= TOL
