@@ -5,7 +5,7 @@ form e^{-tL} = e^{-tL_path} (x) e^{-tL_path} and unit row sums, which hold
 at any size.  The comparison of the whole E with the oracle's takes the
 oracle about 2 minutes on 16 host threads and tens of GB of host memory, so
 it is an opt-in test (EXPM_FULL_ORACLE=1); run on MI355X it gave a relative
-Frobenius error of 9.3e-15 with identical supports (793,765,472 entries)."""
+Frobenius error of 9.2e-15 with identical supports (793,765,472 entries)."""
 import time
 
 import numpy as np
